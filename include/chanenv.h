@@ -1,0 +1,183 @@
+/*
+ * chanenv.h -- C ABI of the MI355X channel-flow DNS environment.
+ *
+ * The library advances an incompressible channel flow with a Fourier (x, z) x
+ * Chebyshev (y) pseudo-spectral method in velocity--vorticity form, RK3 for the
+ * non-linear terms and Crank--Nicolson for the viscous terms (paper §3.1), with
+ * wall-normal blowing/suction at the lower wall as the control (§3.2),
+ * opposition control as the in-library controller (§4.1) and a wall-parallel
+ * velocity plane as the observation (§3.2).  Every numerical stage runs in
+ * FP64 HIP kernels on the device; the host only sequences launches.
+ *
+ * The calls map onto the request protocol of the paper's solver interface
+ * (§3.3): STATE -> the observation output of chan_env_step (and
+ * chan_env_get_state), CNTRL -> its action argument, EVOLVE -> its n_substeps
+ * argument with the wall shear and drag outputs, TERMN -> chan_env_destroy
+ * (chan_env_reset covers the restart of an episode).
+ *
+ * Units: lengths in the channel half-height h, velocities in the nominal
+ * friction velocity u_tau, so nu = 1/Re_tau and t+ = t Re_tau.  The channel is
+ * closed: walls at y = +1 and y = -1; the actuated wall is y = -1.
+ *
+ * Layouts.  Wall planes are row-major [z][x] with x fastest, on the grid
+ * x_i = i Lx/nx, z_k = k Lz/nz.  Spectral arrays are [q][p] with
+ * p = 0 .. nx/2-1 and the signed spanwise index q stored at q mod nz.
+ *
+ * Errors.  Every int-returning call returns CHAN_OK (0) or a negative code;
+ * no exception or abort crosses the ABI.  chan_strerror names a code.
+ * Threading: one env per thread; calls on one env must not overlap.
+ */
+#ifndef CHANENV_H
+#define CHANENV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CHAN_OK = 0,
+  CHAN_EINVAL = -1,      /* bad argument or unsupported option; nothing changed   */
+  CHAN_ENOMEM = -2,      /* device or host allocation failed                      */
+  CHAN_EDEVICE = -3,     /* a HIP runtime call failed                             */
+  CHAN_ENONFINITE = -4,  /* non-finite action (state untouched) or state (poisoned) */
+  CHAN_ESTATE = -5       /* step or get_state before reset/set_state, or poisoned */
+};
+
+/* Opaque environment handle, owned by the library. */
+typedef struct chan_env chan_env;
+
+enum { CHAN_TOP_WALL = 0, CHAN_TOP_FREESLIP = 1 };
+enum { CHAN_CFR = 0, CHAN_CPG = 1 };
+enum { CHAN_CTRL_EXTERNAL = 0, CHAN_CTRL_OPPOSITION = 1 };
+enum { CHAN_RAMP = 0, CHAN_HOLD = 1 };
+enum { CHAN_IC_LAMINAR = 0, CHAN_IC_REICHARDT = 1 };
+enum { CHAN_OBS_U = 1, CHAN_OBS_V = 2, CHAN_OBS_W = 4 };
+
+/* Grid and physical parameters (§3.1: N_x x N_y x N_z modes, Re_tau; §3.2:
+ * sensing height).  Supported: nx, nz in {4, 8, 16, 32, 64, 128};
+ * ny in {17, 33, 65, 97, 129}; re_tau > 0; dt_plus > 0; obs_y_plus > 0 and
+ * below the node next to the upper wall. */
+typedef struct {
+  int32_t nx, ny, nz;   /* Fourier modes in x, Chebyshev modes in y, Fourier modes in z */
+  double lx, lz;        /* box lengths in h (minimal channel 2.67 x 0.8, larger 2 pi x pi) */
+  double re_tau;        /* nominal friction Reynolds number; nu = 1/re_tau unless overridden */
+  double dt_plus;       /* one substep = one full RK3/CN time step of dt = dt_plus/re_tau */
+  double obs_y_plus;    /* sensing height above y = -1 in viscous units; rounded UP to a
+                           Chebyshev node (§3.2); chan_env_query reports the node used */
+} chan_grid_t;
+
+/* Options; passing NULL to chan_env_create selects the defaults in brackets. */
+typedef struct {
+  int32_t top_bc;       /* [CHAN_TOP_WALL]; CHAN_TOP_FREESLIP (the paper's open channel)
+                           is not implemented and returns CHAN_EINVAL */
+  int32_t forcing;      /* [CHAN_CFR] constant flow rate | CHAN_CPG constant pressure gradient */
+  double ub_plus;       /* [<= 0: 15.66 (re_tau/180)^(1/7)] bulk velocity held by CFR */
+  double px;            /* [0] pressure gradient for CPG */
+  double nu_override;   /* [<= 0: unused] > 0 replaces nu = 1/re_tau */
+  double dt_override;   /* [<= 0: unused] > 0 replaces dt = dt_plus/re_tau */
+  int32_t controller;   /* [CHAN_CTRL_EXTERNAL] caller's actions | CHAN_CTRL_OPPOSITION */
+  double opp_alpha;     /* [1.0] opposition gain alpha (§4.1) */
+  int32_t action_mode;  /* [CHAN_RAMP] linear old->new over the env step (§3.2) | CHAN_HOLD */
+  double clip;          /* [1.0] |action| bound in u_tau (§3.2); <= 0 disables clipping */
+  uint32_t obs_mask;    /* [CHAN_OBS_U | CHAN_OBS_V] observed components (§3.2, §4.2) */
+  int32_t ic_profile;   /* [CHAN_IC_LAMINAR] mean profile of chan_env_reset | CHAN_IC_REICHARDT */
+  double ic_amp;        /* [0.1] rms of the reset perturbation as a fraction of U_cl = 1.5 U_b */
+} chan_opts_t;
+
+/* Derived quantities, filled by chan_env_query. */
+typedef struct {
+  int32_t nx, ny, nz, js;      /* js: index of the sensing node, y_js = cos(pi js/(ny-1)) */
+  double y_plus_node;          /* (1 + y_js) / nu: the sensing height actually used */
+  double nu, dt, ub;           /* viscosity, time step, bulk velocity */
+  double t;                    /* simulated time since reset (units h/u_tau) */
+  int64_t nstep;               /* time steps since reset */
+  size_t state_doubles;        /* length of the get/set_state buffer */
+  size_t obs_doubles;          /* popcount(obs_mask) * nz * nx */
+  size_t footprint_bytes;      /* device memory held by the env */
+} chan_info_t;
+
+/* Fill *opts with the defaults listed above. */
+void chan_opts_default(chan_opts_t* opts);
+
+/* Create an env: validate, precompute the operators in FP64 on the host (tau
+ * factors, homogeneous solutions and 2x2 influence matrices per wavenumber
+ * pair and stage, Chebyshev and FFT tables), allocate the device state.
+ * hip_stream: the hipStream_t all work is queued on (NULL = default stream).
+ * *out owns the device memory until chan_env_destroy.  The env has no flow
+ * until chan_env_reset or chan_env_set_state.
+ * Errors: CHAN_EINVAL (*out untouched), CHAN_ENOMEM, CHAN_EDEVICE. */
+int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_stream,
+                    struct chan_env** out);
+
+/* Seeded initial condition (the paper's stored initial fields, §4.2, are
+ * replaced by a synthetic one): the selected mean profile plus a random
+ * divergence-free perturbation drawn from SplitMix64(seed), with v = dv/dy =
+ * omega_y = 0 at the walls and rms velocity ic_amp * U_cl.  Also sets the old
+ * action to zero, t = 0 and the step counter to 0, and clears a poisoned state.
+ * Errors: CHAN_EDEVICE. */
+int chan_env_reset(struct chan_env* env, uint64_t seed);
+
+/* One environment step (§3.2, §3.3): ingest the action, advance n_substeps
+ * time steps, and write the outputs.
+ *   action  DEVICE pointer to nz*nx doubles [z][x], the wall-normal velocity at
+ *           y = -1 requested by the agents.  Clipped to [-clip, clip], the
+ *           plane mean and the Nyquist modes are removed (zero net mass flux,
+ *           §4.1), and the wall velocity ramps linearly from the previous
+ *           action to this one over the env step (CHAN_RAMP) or jumps to it
+ *           (CHAN_HOLD).  NULL means an all-zero action.  Ignored under
+ *           CHAN_CTRL_OPPOSITION, where v_w = -alpha (v(y_s) - <v(y_s)>) is
+ *           evaluated at the start of every time step.
+ *   n_substeps  number of RK3/CN time steps, >= 1.
+ *   obs     DEVICE pointer, popcount(obs_mask)*nz*nx doubles: u, v, w (in that
+ *           order, selected by obs_mask) at the sensing node, end of the step.
+ *           May be NULL.
+ *   tau_w   DEVICE pointer, nz*nx doubles: nu du/dy at y = -1, end of step.  May be NULL.
+ *   drag    DEVICE pointer, 1 double: mean over the n_substeps time steps of the
+ *           plane-averaged lower-wall shear stress, sampled after each step
+ *           (the reward's input, §3.2).  May be NULL.
+ * All device pointers must be valid on the env's stream; the call returns
+ * after the stream has finished the step.
+ * Errors: CHAN_ESTATE (no flow yet, or poisoned), CHAN_EINVAL (n_substeps < 1),
+ * CHAN_ENONFINITE (non-finite action: nothing changed; or non-finite state
+ * after the step: the env is poisoned until reset/set_state), CHAN_EDEVICE. */
+int chan_env_step(struct chan_env* env, const double* action, int32_t n_substeps,
+                  double* obs, double* tau_w, double* drag);
+
+/* Copy the flow state to / from HOST memory, n_doubles = state_doubles:
+ *   v-hat [q][p][n] (re, im) | omega_y-hat [q][p][n] (re, im) | U [n] | W [n] |
+ *   v_w,old [q][p] (re, im) | t | step counter (as a double)
+ * with n the Chebyshev index.  set_state zeroes the Nyquist row and the (0,0)
+ * entries of v and omega_y, enforces the p = 0 Hermitian symmetry (the q > 0
+ * half wins) and clears a poisoned state.
+ * Errors: CHAN_EINVAL (wrong n_doubles or NULL), CHAN_ESTATE (get before any
+ * flow), CHAN_ENONFINITE (set with a non-finite value; nothing changed),
+ * CHAN_EDEVICE. */
+int chan_env_get_state(const struct chan_env* env, double* host, size_t n_doubles);
+int chan_env_set_state(struct chan_env* env, const double* host, size_t n_doubles);
+
+/* Sizes, sensing node, constants and counters.  Errors: CHAN_EINVAL (NULL). */
+int chan_env_query(const struct chan_env* env, chan_info_t* out);
+
+/* Device bytes an env of this shape holds (for admission by HBM footprint);
+ * 0 if the grid is invalid. */
+size_t chan_env_footprint_bytes(const chan_grid_t* grid, const chan_opts_t* opts);
+
+/* Free the env and its device memory.  NULL is a no-op. */
+void chan_env_destroy(struct chan_env* env);
+
+/* Static string naming an error code. */
+const char* chan_strerror(int code);
+
+/* Detail of the last failure on the calling thread (the HIP call and its error
+ * string, or the argument that was rejected); "" if none.  Valid until the next
+ * call into the library on this thread. */
+const char* chan_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHANENV_H */

@@ -168,7 +168,8 @@ def state_to_flat(S: Setup, st: State):
     """The library's state exchange format (host doubles):
     v [q][p][n] (re, im), omega_y [q][p][n] (re, im), U [n], W [n],
     v_w,old [q][p] (re, im), t, step counter."""
-    parts = [st.v.view(float).ravel(), st.om.view(float).ravel(), st.ubar, st.wbar,
+    parts = [np.ascontiguousarray(st.v).view(float).ravel(),
+             np.ascontiguousarray(st.om).view(float).ravel(), st.ubar, st.wbar,
              np.ascontiguousarray(st.vw_old).view(float).ravel(),
              np.array([st.t, float(st.nstep)])]
     return np.concatenate([np.ascontiguousarray(p, dtype=float).ravel() for p in parts])

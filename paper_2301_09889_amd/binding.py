@@ -1,0 +1,238 @@
+"""ctypes binding of include/chanenv.h: argument marshalling only.
+
+Every function here has the name of the C entry point it calls.  Device
+buffers are passed as raw pointers (``tensor.data_ptr()``) on the stream the env
+was created with; PyTorch serves only as the allocator of device memory and the
+owner of the stream.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+CHAN_OK, CHAN_EINVAL, CHAN_ENOMEM, CHAN_EDEVICE, CHAN_ENONFINITE, CHAN_ESTATE = 0, -1, -2, -3, -4, -5
+CHAN_TOP_WALL, CHAN_TOP_FREESLIP = 0, 1
+CHAN_CFR, CHAN_CPG = 0, 1
+CHAN_CTRL_EXTERNAL, CHAN_CTRL_OPPOSITION = 0, 1
+CHAN_RAMP, CHAN_HOLD = 0, 1
+CHAN_IC_LAMINAR, CHAN_IC_REICHARDT = 0, 1
+CHAN_OBS_U, CHAN_OBS_V, CHAN_OBS_W = 1, 2, 4
+
+EXPORTED = ["chan_opts_default", "chan_env_create", "chan_env_reset", "chan_env_step",
+            "chan_env_get_state", "chan_env_set_state", "chan_env_query",
+            "chan_env_footprint_bytes", "chan_env_destroy", "chan_strerror", "chan_last_error"]
+
+
+class ChanGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("lx", ctypes.c_double), ("lz", ctypes.c_double), ("re_tau", ctypes.c_double),
+                ("dt_plus", ctypes.c_double), ("obs_y_plus", ctypes.c_double)]
+
+
+class ChanOpts(ctypes.Structure):
+    _fields_ = [("top_bc", ctypes.c_int32), ("forcing", ctypes.c_int32),
+                ("ub_plus", ctypes.c_double), ("px", ctypes.c_double),
+                ("nu_override", ctypes.c_double), ("dt_override", ctypes.c_double),
+                ("controller", ctypes.c_int32), ("opp_alpha", ctypes.c_double),
+                ("action_mode", ctypes.c_int32), ("clip", ctypes.c_double),
+                ("obs_mask", ctypes.c_uint32), ("ic_profile", ctypes.c_int32),
+                ("ic_amp", ctypes.c_double)]
+
+
+class ChanInfo(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("js", ctypes.c_int32), ("y_plus_node", ctypes.c_double), ("nu", ctypes.c_double),
+                ("dt", ctypes.c_double), ("ub", ctypes.c_double), ("t", ctypes.c_double),
+                ("nstep", ctypes.c_int64), ("state_doubles", ctypes.c_size_t),
+                ("obs_doubles", ctypes.c_size_t), ("footprint_bytes", ctypes.c_size_t)]
+
+
+class ChanError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        detail = chan_last_error()
+        super().__init__(f"{where}: {chan_strerror(code)} ({code})" + (f" [{detail}]" if detail else ""))
+
+
+_LIB = None
+
+
+def library_path():
+    return os.path.join(HERE, "libchanenv.so")
+
+
+def load_library():
+    """Load libchanenv.so; raises if it has not been built (there is no fallback)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2301_09889_amd/build.py")
+    # PyTorch ships its own HIP runtime.  Load it first, so that the library's
+    # libamdhip64.so.7 dependency resolves to the same runtime (one device
+    # context; streams and device pointers from torch are valid in the library).
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    lib.chan_opts_default.argtypes = [P(ChanOpts)]
+    lib.chan_opts_default.restype = None
+    lib.chan_env_create.argtypes = [P(ChanGrid), P(ChanOpts), vp, P(vp)]
+    lib.chan_env_create.restype = ctypes.c_int
+    lib.chan_env_reset.argtypes = [vp, ctypes.c_uint64]
+    lib.chan_env_reset.restype = ctypes.c_int
+    lib.chan_env_step.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp]
+    lib.chan_env_step.restype = ctypes.c_int
+    lib.chan_env_get_state.argtypes = [vp, P(ctypes.c_double), ctypes.c_size_t]
+    lib.chan_env_get_state.restype = ctypes.c_int
+    lib.chan_env_set_state.argtypes = [vp, P(ctypes.c_double), ctypes.c_size_t]
+    lib.chan_env_set_state.restype = ctypes.c_int
+    lib.chan_env_query.argtypes = [vp, P(ChanInfo)]
+    lib.chan_env_query.restype = ctypes.c_int
+    lib.chan_env_footprint_bytes.argtypes = [P(ChanGrid), P(ChanOpts)]
+    lib.chan_env_footprint_bytes.restype = ctypes.c_size_t
+    lib.chan_env_destroy.argtypes = [vp]
+    lib.chan_env_destroy.restype = None
+    lib.chan_strerror.argtypes = [ctypes.c_int]
+    lib.chan_strerror.restype = ctypes.c_char_p
+    lib.chan_last_error.argtypes = []
+    lib.chan_last_error.restype = ctypes.c_char_p
+    _LIB = lib
+    return lib
+
+
+def chan_strerror(code):
+    return load_library().chan_strerror(int(code)).decode()
+
+
+def chan_last_error():
+    return load_library().chan_last_error().decode()
+
+
+def chan_opts_default():
+    o = ChanOpts()
+    load_library().chan_opts_default(ctypes.byref(o))
+    return o
+
+
+def chan_env_create(grid, opts=None, stream=0):
+    h = ctypes.c_void_p()
+    rc = load_library().chan_env_create(ctypes.byref(grid), ctypes.byref(opts) if opts is not None else None,
+                                        ctypes.c_void_p(stream), ctypes.byref(h))
+    if rc != CHAN_OK:
+        raise ChanError(rc, "chan_env_create")
+    return h
+
+
+def chan_env_reset(h, seed):
+    return load_library().chan_env_reset(h, ctypes.c_uint64(seed))
+
+
+def chan_env_step(h, action_ptr, n_substeps, obs_ptr, tau_ptr, drag_ptr):
+    return load_library().chan_env_step(h, ctypes.c_void_p(action_ptr or None), int(n_substeps),
+                                        ctypes.c_void_p(obs_ptr or None), ctypes.c_void_p(tau_ptr or None),
+                                        ctypes.c_void_p(drag_ptr or None))
+
+
+def chan_env_get_state(h, buf):
+    buf = np.ascontiguousarray(buf, dtype=np.float64)
+    return load_library().chan_env_get_state(h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), buf.size)
+
+
+def chan_env_set_state(h, buf):
+    buf = np.ascontiguousarray(buf, dtype=np.float64)
+    return load_library().chan_env_set_state(h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), buf.size)
+
+
+def chan_env_query(h):
+    info = ChanInfo()
+    rc = load_library().chan_env_query(h, ctypes.byref(info))
+    if rc != CHAN_OK:
+        raise ChanError(rc, "chan_env_query")
+    return info
+
+
+def chan_env_footprint_bytes(grid, opts=None):
+    return load_library().chan_env_footprint_bytes(ctypes.byref(grid),
+                                                   ctypes.byref(opts) if opts is not None else None)
+
+
+def chan_env_destroy(h):
+    load_library().chan_env_destroy(h)
+
+
+def make_grid(nx, ny, nz, lx, lz, re_tau, dt_plus, obs_y_plus):
+    return ChanGrid(nx, ny, nz, lx, lz, re_tau, dt_plus, obs_y_plus)
+
+
+def make_opts(**kw):
+    o = chan_opts_default()
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class ChanEnv:
+    """One channel on the current HIP device; tensors come from PyTorch."""
+
+    def __init__(self, grid, opts=None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("ChanEnv needs a HIP device")
+        self.torch = torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.grid = grid
+        self.opts = opts if opts is not None else chan_opts_default()
+        self.handle = chan_env_create(grid, self.opts, self.stream.cuda_stream)
+        self.info = chan_env_query(self.handle)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        nobs = bin(self.opts.obs_mask).count("1")
+        self.obs = torch.zeros((nobs, grid.nz, grid.nx), dtype=torch.float64, device=dev)
+        self.tau_w = torch.zeros((grid.nz, grid.nx), dtype=torch.float64, device=dev)
+        self.drag = torch.zeros(1, dtype=torch.float64, device=dev)
+
+    def _check(self, rc, where):
+        if rc != CHAN_OK:
+            raise ChanError(rc, where)
+
+    def reset(self, seed):
+        self._check(chan_env_reset(self.handle, seed), "chan_env_reset")
+
+    def set_state(self, flat):
+        self._check(chan_env_set_state(self.handle, flat), "chan_env_set_state")
+
+    def get_state(self):
+        buf = np.zeros(self.info.state_doubles)
+        self._check(chan_env_get_state(self.handle, buf), "chan_env_get_state")
+        return buf
+
+    def step(self, action, n_substeps):
+        """action: float64 device tensor (nz, nx) or None.  Returns (obs, tau_w, drag) tensors."""
+        ptr = 0
+        if action is not None:
+            assert action.dtype == self.torch.float64 and action.is_contiguous()
+            assert tuple(action.shape) == (self.grid.nz, self.grid.nx)
+            ptr = action.data_ptr()
+        rc = chan_env_step(self.handle, ptr, n_substeps, self.obs.data_ptr(), self.tau_w.data_ptr(),
+                           self.drag.data_ptr())
+        self._check(rc, "chan_env_step")
+        return self.obs, self.tau_w, self.drag
+
+    def query(self):
+        return chan_env_query(self.handle)
+
+    def close(self):
+        if self.handle:
+            chan_env_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,89 @@
+// Internal declarations shared by the host driver and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+namespace chanenv {
+
+typedef double2 cplx;
+
+// Status bits written by the kernels (device word, read back after a step).
+enum : int {
+  STATUS_BAD_ACTION = 1,   // non-finite action: every state-changing kernel skips
+  STATUS_NONFINITE = 2     // non-finite state produced by a stage
+};
+
+enum WallMode : int { WALL_RAMP = 0, WALL_OPP = 1 };
+
+// Number of per-column tau operators: the three stage operators D^2 - (k^2 + 1/(b_r nu dt))
+// and the velocity operator D^2 - k^2.
+constexpr int NOPS = 4;
+
+// Host-side geometry and the layout of the packed operator tables.
+struct Dims {
+  int nx, ny, nz, N, nkx, mx, mz, ncol;
+  int ml;        // unknowns per parity, N/2 + 1
+  int opsz;      // doubles per (column, operator, parity) record: w, u, f, F (ml each), 1/sum F, pad
+};
+
+// Offsets (in doubles) of each table inside the single device table buffer.
+struct TableLayout {
+  size_t cosk, rc, optab, vt, minv, up, inv_int_up, twz, twx, twnx, twnz, alpha, beta, total;
+};
+
+// Host precompute of every operator table, in FP64.
+struct HostTables {
+  std::vector<double> data;
+  TableLayout L;
+};
+
+struct PhysParams {
+  double nu, dt, ub;
+  int forcing;
+  double px;
+  double lx, lz;
+};
+
+void precompute_tables(const Dims& d, const PhysParams& ph, HostTables* out);
+
+// Host initial condition in the state exchange layout ([q][p][n] complex v, omega_y,
+// U, W, zero old action, t = 0, step 0).
+void initial_condition(const Dims& d, const PhysParams& ph, int profile, double amp,
+                       uint64_t seed, std::vector<double>* flat);
+
+// Device buffers of one env.
+struct DeviceState {
+  cplx *vS, *oS, *hist;         // [c][n] state, [2][c][n] previous-stage h_v, h_g
+  double *meanS, *meanH;        // [2][n] U, W ; [2][n] previous-stage h_u, h_w
+  cplx *F6, *Z6, *W3, *H3;      // plane-pass fields
+  cplx *vw_old, *vw_new, *vw_opp, *tauw;  // [c]
+  cplx *tmp2d;                  // [3][nz][nkx] small 2-D transform scratch
+  double *tab;                  // operator tables (one allocation, see TableLayout)
+  double *drag_acc;             // [1]
+  int *status;                  // [1]
+  // views into tab
+  const double *cosk, *rc, *optab, *vt, *minv, *up, *inv_int_up, *alpha, *beta;
+  const cplx *twz, *twx, *twnx, *twnz;
+};
+
+struct StageConsts {
+  double lam0, ab, gb, zb;      // 1/(b nu dt), a/b, g/(b nu), z/(b nu)
+};
+
+// Kernel launchers (kernels.hip).
+int launch_begin_step(const Dims& d, DeviceState& s, bool zero_vw_new, hipStream_t st);
+int launch_ingest(const Dims& d, DeviceState& s, const double* action, double clip, hipStream_t st);
+int launch_plane_pass(const Dims& d, DeviceState& s, hipStream_t st);
+int launch_column_pass(const Dims& d, DeviceState& s, const PhysParams& ph, int stage,
+                       const StageConsts& sc, int wall_mode, double s_ramp, int js,
+                       double opp_alpha, bool accumulate_drag, hipStream_t st);
+int launch_finish_step(const Dims& d, DeviceState& s, bool copy_vw, double* drag, int nsub,
+                       hipStream_t st);
+int launch_outputs(const Dims& d, DeviceState& s, int js, uint32_t obs_mask, double* obs,
+                   double* tau_w, hipStream_t st);
+
+}  // namespace chanenv

@@ -1,0 +1,1173 @@
+// FP64 HIP kernels of the channel-flow DNS step, written for gfx950 (CDNA4).
+//
+// One time step is three RK3/CN stages; each stage is a plane pass followed by a
+// column pass:
+//
+//   plane pass   the six velocity/vorticity fields at every Chebyshev node go to the
+//                3/2-padded (x, z) grid, u x omega is formed pointwise and the three
+//                products come back to the stored Fourier modes.  Three kernels:
+//                k_zinv  (inverse FFT along z per (node, p) pencil, with padding),
+//                k_xrow  (inverse real FFT along x, product, forward real FFT, per
+//                         pair of padded z rows),
+//                k_zfwd  (forward FFT along z, truncation, 1/(M_x M_z), Hermitian fix).
+//   column pass  one wavefront per wavenumber pair (alpha, beta) owns the whole
+//                wall-normal column: forward DCT-I of H, the explicit terms h_v, h_g,
+//                the RK3/CN right-hand sides, the Chebyshev-tau solves (quasi-
+//                tridiagonal even/odd recurrences on a few lanes), the 2x2
+//                influence-matrix correction, and then the reconstruction of
+//                (u, v, w, omega_x, omega_y, omega_z) and their inverse DCT-I for the
+//                next stage.  The (0, 0) pair carries the mean flow and the constant-
+//                flow-rate pressure gradient.
+//
+// Small kernels ingest the action (clip, 2-D FFT, zero net flux) and produce the
+// observation plane and the wall-shear field (inverse 2-D FFTs).
+//
+// Everything is FP64 (the method is chaotic and the tau systems are stiff); nothing is
+// a dense contraction, so there is no MFMA here.
+
+#include "chanenv_internal.h"
+
+namespace chanenv {
+
+// ----------------------------------------------------------------------------
+// Complex helpers (double2 as re, im).  Named functions only: HIP's vector
+// operators on double2 are component-wise, not complex.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ cplx cz() { return make_double2(0.0, 0.0); }
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ cplx csub(cplx a, cplx b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ cplx cscale(cplx a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ cplx cconj(cplx a) { return make_double2(a.x, -a.y); }
+// i * a
+__device__ __forceinline__ cplx cmuli(cplx a) { return make_double2(-a.y, a.x); }
+// acc + s * a
+__device__ __forceinline__ cplx caxpy(cplx acc, double s, cplx a) {
+  return make_double2(fma(s, a.x, acc.x), fma(s, a.y, acc.y));
+}
+
+// Wave-scope barrier for LDS data exchanged between lanes of one wavefront.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Butterfly sum over the 64 lanes; every lane receives the bitwise-same total.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ cplx wave_sum(cplx v) {
+  return make_double2(wave_sum(v.x), wave_sum(v.y));
+}
+
+// ----------------------------------------------------------------------------
+// Batched Stockham FFT in LDS (radix 3, 4, 2), used by all (x, z) transforms.
+// Sequence b of the batch lives at src + b*ld, length L (L = 2^a or 3*2^a).
+// tw[k] = exp(-2 pi i k / L).  inv selects the +i sign (no 1/L scaling).
+// Must be called by every thread of the block.  Returns the buffer holding the
+// result (src or dst).
+// ----------------------------------------------------------------------------
+__device__ cplx* fft_batch(cplx* src, cplx* dst, int L, int nb_seq, int ld,
+                           const cplx* __restrict__ tw, bool inv) {
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const double sg = inv ? 1.0 : -1.0;
+  int Ns = 1;
+  while (Ns < L) {
+    const int rem = L / Ns;
+    const int R = (rem % 3 == 0) ? 3 : ((rem % 4 == 0) ? 4 : 2);
+    const int nb = L / R;
+    const int tstep = L / (Ns * R);
+    for (int t = tid; t < nb_seq * nb; t += nthr) {
+      const int b = t / nb;
+      const int j = t - b * nb;
+      const int k = j % Ns;
+      const cplx* s = src + b * ld;
+      cplx x0 = s[j], x1 = s[j + nb], x2 = cz(), x3 = cz();
+      if (R >= 3) x2 = s[j + 2 * nb];
+      if (R == 4) x3 = s[j + 3 * nb];
+      if (k != 0) {
+        cplx w1 = tw[k * tstep];
+        if (inv) w1.y = -w1.y;
+        x1 = cmul(x1, w1);
+        if (R >= 3) {
+          cplx w2 = tw[2 * k * tstep];
+          if (inv) w2.y = -w2.y;
+          x2 = cmul(x2, w2);
+        }
+        if (R == 4) {
+          cplx w3 = tw[3 * k * tstep];
+          if (inv) w3.y = -w3.y;
+          x3 = cmul(x3, w3);
+        }
+      }
+      cplx y0, y1, y2, y3;
+      if (R == 2) {
+        y0 = cadd(x0, x1);
+        y1 = csub(x0, x1);
+      } else if (R == 4) {
+        const cplx a = cadd(x0, x2), b2 = csub(x0, x2);
+        const cplx c = cadd(x1, x3), d = csub(x1, x3);
+        // sg * i * d
+        const cplx id = make_double2(-sg * d.y, sg * d.x);
+        y0 = cadd(a, c);
+        y2 = csub(a, c);
+        y1 = cadd(b2, id);
+        y3 = csub(b2, id);
+      } else {  // R == 3
+        const double h = 0.86602540378443864676;  // sqrt(3)/2
+        const cplx t1 = cadd(x1, x2), t2 = csub(x1, x2);
+        y0 = cadd(x0, t1);
+        const cplx m = make_double2(x0.x - 0.5 * t1.x, x0.y - 0.5 * t1.y);
+        // sg * i * h * t2
+        const cplx r = make_double2(-sg * h * t2.y, sg * h * t2.x);
+        y1 = cadd(m, r);
+        y2 = csub(m, r);
+      }
+      cplx* dd = dst + b * ld + (j / Ns) * Ns * R + k;
+      dd[0] = y0;
+      dd[Ns] = y1;
+      if (R >= 3) dd[2 * Ns] = y2;
+      if (R == 4) dd[3 * Ns] = y3;
+    }
+    __syncthreads();
+    cplx* tmp = src;
+    src = dst;
+    dst = tmp;
+    Ns *= R;
+  }
+  return src;
+}
+
+// ----------------------------------------------------------------------------
+// Plane pass.
+// Layouts (complex):  F6[f][j][p][q], Z6[f][j][zz][p], W3[g][j][zz][p], H3[g][j][p][q]
+// with f in (u, v, w, omega_x, omega_y, omega_z), g in (H1, H2, H3), j the node,
+// zz < M_z the padded physical z index, p < N_x/2, q < N_z.
+// ----------------------------------------------------------------------------
+struct PlaneArgs {
+  int ny, nkx, nz, mx, mz;
+  const cplx* F6;
+  cplx* Z6;
+  cplx* W3;
+  cplx* H3;
+  const cplx* twz;
+  const cplx* twx;
+  const int* status;
+};
+
+constexpr int PLANE_THREADS = 256;
+
+// Inverse FFT along z of PB consecutive p pencils of one field at one node.
+__global__ __launch_bounds__(PLANE_THREADS) void k_zinv(PlaneArgs A, int PB) {
+  extern __shared__ double dyn_lds[];
+  cplx* sh = reinterpret_cast<cplx*>(dyn_lds);
+  if (*A.status & STATUS_BAD_ACTION) return;
+  const int p0 = blockIdx.x * PB, f = blockIdx.y, j = blockIdx.z;
+  const int np = min(PB, A.nkx - p0);
+  const int LP = A.mz + 1;
+  cplx* a = sh;
+  cplx* b = sh + PB * LP;
+  for (int t = threadIdx.x; t < np * LP; t += blockDim.x) a[t] = cz();
+  __syncthreads();
+  const size_t fj = (size_t)f * A.ny + j;
+  const cplx* src = A.F6 + fj * A.nkx * A.nz + (size_t)p0 * A.nz;
+  const int h = A.nz / 2;
+  for (int t = threadIdx.x; t < np * A.nz; t += blockDim.x) {
+    const int pp = t / A.nz, q = t - pp * A.nz;
+    if (q == h) continue;
+    const int zz = (q < h) ? q : q - A.nz + A.mz;
+    a[pp * LP + zz] = src[t];
+  }
+  __syncthreads();
+  cplx* r = fft_batch(a, b, A.mz, np, LP, A.twz, true);
+  cplx* dst = A.Z6 + fj * A.mz * A.nkx + p0;
+  for (int t = threadIdx.x; t < A.mz * np; t += blockDim.x) {
+    const int zz = t / np, pp = t - zz * np;
+    dst[(size_t)zz * A.nkx + pp] = r[pp * LP + zz];
+  }
+}
+
+// Rows of the padded plane, RB rows (RB/2 packed pairs) per block: inverse real FFTs
+// of the six fields along x, H = u x omega, forward real FFTs of the three products.
+__global__ __launch_bounds__(PLANE_THREADS) void k_xrow(PlaneArgs A, int RB) {
+  extern __shared__ double dyn_lds[];
+  cplx* sh = reinterpret_cast<cplx*>(dyn_lds);
+  if (*A.status & STATUS_BAD_ACTION) return;
+  const int z0 = blockIdx.x * RB, j = blockIdx.y;
+  const int npair = RB / 2;
+  const int LX = A.mx + 1;
+  const int nseq = 6 * npair;
+  cplx* a = sh;
+  cplx* b = sh + nseq * LX;
+  const int nkx = A.nkx, mx = A.mx;
+  // Packed spectra Y = X(row 2pr) + i X(row 2pr+1) with the Hermitian extension along x.
+  for (int t = threadIdx.x; t < nseq * mx; t += blockDim.x) {
+    const int sidx = t / mx, k = t - sidx * mx;
+    const int f = sidx / npair, pr = sidx - f * npair;
+    const size_t rowa = (((size_t)f * A.ny + j) * A.mz + (z0 + 2 * pr)) * nkx;
+    const size_t rowb = rowa + nkx;
+    cplx xa = cz(), xb = cz();
+    if (k < nkx) {
+      xa = A.Z6[rowa + k];
+      xb = A.Z6[rowb + k];
+      if (k == 0) {
+        xa.y = 0.0;
+        xb.y = 0.0;
+      }
+    } else if (k > mx - nkx) {
+      xa = cconj(A.Z6[rowa + (mx - k)]);
+      xb = cconj(A.Z6[rowb + (mx - k)]);
+    }
+    a[sidx * LX + k] = make_double2(xa.x - xb.y, xa.y + xb.x);
+  }
+  __syncthreads();
+  cplx* phys = fft_batch(a, b, mx, nseq, LX, A.twx, true);
+  cplx* out = (phys == a) ? b : a;
+  // Products on the padded grid; the three products of a row pair packed the same way.
+  for (int t = threadIdx.x; t < npair * mx; t += blockDim.x) {
+    const int pr = t / mx, x = t - pr * mx;
+    const cplx U = phys[(0 * npair + pr) * LX + x];
+    const cplx V = phys[(1 * npair + pr) * LX + x];
+    const cplx W = phys[(2 * npair + pr) * LX + x];
+    const cplx OX = phys[(3 * npair + pr) * LX + x];
+    const cplx OY = phys[(4 * npair + pr) * LX + x];
+    const cplx OZ = phys[(5 * npair + pr) * LX + x];
+    // .x = row 2pr, .y = row 2pr+1
+    const cplx H1 = make_double2(V.x * OZ.x - W.x * OY.x, V.y * OZ.y - W.y * OY.y);
+    const cplx H2 = make_double2(W.x * OX.x - U.x * OZ.x, W.y * OX.y - U.y * OZ.y);
+    const cplx H3 = make_double2(U.x * OY.x - V.x * OX.x, U.y * OY.y - V.y * OX.y);
+    out[(0 * npair + pr) * LX + x] = H1;
+    out[(1 * npair + pr) * LX + x] = H2;
+    out[(2 * npair + pr) * LX + x] = H3;
+  }
+  __syncthreads();
+  cplx* spec = fft_batch(out, phys, mx, 3 * npair, LX, A.twx, false);
+  for (int t = threadIdx.x; t < 3 * npair * nkx; t += blockDim.x) {
+    const int sidx = t / nkx, k = t - sidx * nkx;
+    const int g = sidx / npair, pr = sidx - g * npair;
+    const cplx Yk = spec[sidx * LX + k];
+    const cplx Ym = cconj(spec[sidx * LX + ((mx - k) % mx)]);
+    const cplx Xa = make_double2(0.5 * (Yk.x + Ym.x), 0.5 * (Yk.y + Ym.y));
+    // (Yk - Ym) / (2 i)
+    const cplx Xb = make_double2(0.5 * (Yk.y - Ym.y), -0.5 * (Yk.x - Ym.x));
+    const size_t rowa = (((size_t)g * A.ny + j) * A.mz + (z0 + 2 * pr)) * nkx;
+    A.W3[rowa + k] = Xa;
+    A.W3[rowa + nkx + k] = Xb;
+  }
+}
+
+// Forward FFT along z, truncation to the stored q, 1/(M_x M_z), Hermitian fix of p = 0.
+__global__ __launch_bounds__(PLANE_THREADS) void k_zfwd(PlaneArgs A, int PB) {
+  extern __shared__ double dyn_lds[];
+  cplx* sh = reinterpret_cast<cplx*>(dyn_lds);
+  if (*A.status & STATUS_BAD_ACTION) return;
+  const int p0 = blockIdx.x * PB, g = blockIdx.y, j = blockIdx.z;
+  const int np = min(PB, A.nkx - p0);
+  const int LP = A.mz + 1;
+  cplx* a = sh;
+  cplx* b = sh + PB * LP;
+  const size_t gj = (size_t)g * A.ny + j;
+  const cplx* src = A.W3 + gj * A.mz * A.nkx + p0;
+  for (int t = threadIdx.x; t < A.mz * np; t += blockDim.x) {
+    const int zz = t / np, pp = t - zz * np;
+    a[pp * LP + zz] = src[(size_t)zz * A.nkx + pp];
+  }
+  __syncthreads();
+  cplx* r = fft_batch(a, b, A.mz, np, LP, A.twz, false);
+  const double scale = 1.0 / ((double)A.mx * (double)A.mz);
+  const int h = A.nz / 2;
+  cplx* dst = A.H3 + gj * A.nkx * A.nz + (size_t)p0 * A.nz;
+  for (int t = threadIdx.x; t < np * A.nz; t += blockDim.x) {
+    const int pp = t / A.nz, q = t - pp * A.nz;
+    cplx v = cz();
+    if (q != h) {
+      if (p0 + pp == 0 && q > h) {
+        v = cconj(r[pp * LP + (A.nz - q)]);
+      } else {
+        const int zz = (q < h) ? q : q - A.nz + A.mz;
+        v = r[pp * LP + zz];
+      }
+      v = cscale(v, scale);
+      if (p0 + pp == 0 && q == 0) v.y = 0.0;
+    }
+    dst[t] = v;
+  }
+}
+
+int launch_plane_pass(const Dims& d, DeviceState& s, hipStream_t st) {
+  PlaneArgs A;
+  A.ny = d.ny;
+  A.nkx = d.nkx;
+  A.nz = d.nz;
+  A.mx = d.mx;
+  A.mz = d.mz;
+  A.F6 = s.F6;
+  A.Z6 = s.Z6;
+  A.W3 = s.W3;
+  A.H3 = s.H3;
+  A.twz = s.twz;
+  A.twx = s.twx;
+  A.status = s.status;
+  const int PB = d.nkx < 8 ? d.nkx : 8;
+  const int nblk = (d.nkx + PB - 1) / PB;
+  const size_t shz = (size_t)2 * PB * (d.mz + 1) * sizeof(cplx);
+  hipLaunchKernelGGL(k_zinv, dim3(nblk, 6, d.ny), dim3(PLANE_THREADS), shz, st, A, PB);
+  const int RB = (d.mz % 4 == 0 && d.mx <= 96) ? 4 : 2;
+  const size_t shx = (size_t)2 * 6 * (RB / 2) * (d.mx + 1) * sizeof(cplx);
+  hipLaunchKernelGGL(k_xrow, dim3(d.mz / RB, d.ny), dim3(PLANE_THREADS), shx, st, A, RB);
+  hipLaunchKernelGGL(k_zfwd, dim3(nblk, 3, d.ny), dim3(PLANE_THREADS), shz, st, A, PB);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ----------------------------------------------------------------------------
+// Column pass.
+// ----------------------------------------------------------------------------
+template <int N>
+struct CP {
+  static constexpr int NY = N + 1;
+  static constexpr int NS = (NY + 63) / 64;  // element slots per lane
+  static constexpr int ML = N / 2 + 1;
+  static constexpr int OPSZ = 4 * ML + 2;
+  static constexpr int NB = 8;               // complex work vectors per wave
+  static constexpr int NYP = NY + 1;
+  static constexpr int WAVE_DOUBLES = NB * NYP * 2 + 2 * OPSZ + 32;
+};
+
+// wavefronts (columns) per block: four for N <= 64, two above (LDS per block < 64 KiB)
+template <int N>
+constexpr int wpb() { return N <= 64 ? 4 : 2; }
+
+struct ColArgs {
+  int nkx, nz, ncol;
+  int stage;            // 0, 1, 2; -1: reconstruct only (after reset / set_state)
+  int wall_mode;
+  double s_ramp;
+  double lam0, ab, gb, zb;
+  double nu, opp_alpha, ub2, px;
+  int forcing, js, accumulate_drag;
+  size_t plane;         // elements per field in F6 / H3 (ny * nkx * nz)
+  cplx *vS, *oS, *hist;
+  double *meanS, *meanH;
+  const cplx* H3;
+  cplx* F6;
+  const cplx *vw_old, *vw_new;
+  cplx *vw_opp, *tauw;
+  const double *cosk, *rc, *optab, *vt, *minv, *up, *inv_int_up, *alpha, *beta;
+  double* drag_acc;
+  int* status;
+};
+
+// D on coefficients, output element e < N:  (2/c_e) sum_{p > e, p+e odd} p X_p.
+template <int N>
+__device__ __forceinline__ cplx cheb_d1(const cplx* X, int e) {
+  cplx acc = cz();
+#pragma unroll
+  for (int k = 0; k < (N + 1) / 2; ++k) {
+    const int pp = e + 1 + 2 * k;
+    if (pp <= N) acc = caxpy(acc, (double)pp, X[pp]);
+  }
+  return cscale(acc, e == 0 ? 1.0 : 2.0);
+}
+
+// D^2 on coefficients, output element e <= N:  (1/c_e) sum_{p >= e+2, p+e even} p (p^2 - e^2) X_p.
+template <int N>
+__device__ __forceinline__ cplx cheb_d2(const cplx* X, int e) {
+  cplx acc = cz();
+  const double e2 = (double)e * (double)e;
+#pragma unroll
+  for (int k = 0; k < N / 2; ++k) {
+    const int pp = e + 2 + 2 * k;
+    if (pp <= N) {
+      const double dp = (double)pp;
+      acc = caxpy(acc, dp * (dp * dp - e2), X[pp]);
+    }
+  }
+  return cscale(acc, e == 0 ? 0.5 : 1.0);
+}
+
+// Forward DCT-I of F nodal vectors X[f][0..N] (overwritten by the even/odd fold):
+// a_n = 2/(N cb_n) sum_j f_j cos(pi n j/N)/cb_j.  Result in out[f][slot].
+template <int N, int F>
+__device__ __forceinline__ void dct_forward(cplx* const* X, const double* __restrict__ cosk, int lane,
+                                            cplx (*out)[CP<N>::NS]) {
+  constexpr int H = N / 2;
+  for (int j = lane; j < H; j += 64) {
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      cplx a = X[f][j], b = X[f][N - j];
+      if (j == 0) {
+        a = cscale(a, 0.5);
+        b = cscale(b, 0.5);
+      }
+      X[f][j] = cadd(a, b);
+      X[f][N - j] = csub(a, b);
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int s = 0; s < CP<N>::NS; ++s) {
+    const int e = lane + 64 * s;
+    cplx acc[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) acc[f] = cz();
+    if (e < N) {
+      const bool odd = e & 1;
+#pragma unroll 4
+      for (int jj = 0; jj <= H; ++jj) {
+        const double cs = cosk[jj * (N + 1) + e];
+        const int idx = odd ? (jj < H ? N - jj : H) : jj;
+#pragma unroll
+        for (int f = 0; f < F; ++f) acc[f] = caxpy(acc[f], cs, X[f][idx]);
+      }
+    }
+    const double sc = (e == 0) ? (1.0 / N) : (2.0 / N);
+#pragma unroll
+    for (int f = 0; f < F; ++f) out[f][s] = cscale(acc[f], sc);
+  }
+  // a_N = (1/N) sum_{j <= N/2} (-1)^j S_j
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    cplx part = cz();
+    for (int j = lane; j <= H; j += 64) part = caxpy(part, (j & 1) ? -1.0 : 1.0, X[f][j]);
+    const cplx tot = wave_sum(part);
+    if (lane == (N % 64)) out[f][N / 64] = cscale(tot, 1.0 / N);
+  }
+}
+
+// Inverse DCT-I of F coefficient vectors X[f][0..N] (overwritten by the fold):
+// f_j = sum_n a_n cos(pi n j / N).  Result in out[f][slot] for node e = lane + 64 slot.
+template <int N, int F>
+__device__ __forceinline__ void dct_inverse(cplx* const* X, const double* __restrict__ cosk, int lane,
+                                            cplx (*out)[CP<N>::NS]) {
+  constexpr int H = N / 2;
+  for (int n = lane; n < H; n += 64) {
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      const cplx a = X[f][n], b = X[f][N - n];
+      X[f][n] = cadd(a, b);
+      X[f][N - n] = csub(a, b);
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int s = 0; s < CP<N>::NS; ++s) {
+    const int e = lane + 64 * s;
+    cplx acc[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) acc[f] = cz();
+    if (e < N) {
+      const bool odd = e & 1;
+#pragma unroll 4
+      for (int n = 0; n <= H; ++n) {
+        const double cs = cosk[n * (N + 1) + e];
+        const int idx = odd ? (n < H ? N - n : H) : n;
+#pragma unroll
+        for (int f = 0; f < F; ++f) acc[f] = caxpy(acc[f], cs, X[f][idx]);
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < F; ++f) out[f][s] = acc[f];
+  }
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    cplx part = cz();
+    for (int n = lane; n <= H; n += 64) part = caxpy(part, (n & 1) ? -1.0 : 1.0, X[f][n]);
+    const cplx tot = wave_sum(part);
+    if (lane == (N % 64)) out[f][N / 64] = tot;
+  }
+}
+
+// Right-hand side rows of the quasi-tridiagonal tau system (n = 2..N):
+// R_n = rc1_n f_{n-2} - rc2_n f_n + rc3_n f_{n+2}.
+template <int N>
+__device__ __forceinline__ cplx tau_rows(const cplx* f, const double* __restrict__ rc, int n) {
+  constexpr int NY = N + 1;
+  if (n < 2) return cz();
+  cplx r = cscale(f[n - 2], rc[n]);
+  r = caxpy(r, -rc[NY + n], f[n]);
+  if (n + 2 <= N) r = caxpy(r, rc[2 * NY + n], f[n + 2]);
+  return r;
+}
+
+// Serial even/odd elimination of one parity s of a tau system (run on one lane).
+// tab: the (operator, parity) record {w, u, f, F, 1/sum F}.  Writes E_i to E[2i+s]
+// (i >= 1) and returns x_0 = (g - sum E_i) / sum F_i.
+template <int N>
+__device__ __forceinline__ cplx tau_chain(const cplx* R, const double* tab, int s, cplx g, cplx* E) {
+  constexpr int ML = N / 2 + 1;
+  const int m = (N - s) / 2;
+  const double* w = tab;
+  const double* u = tab + ML;
+  const double* fr = tab + 2 * ML;
+  cplx e = cz();
+#pragma unroll
+  for (int i = N / 2; i >= 1; --i) {
+    if (i <= m) {
+      const cplx r = R[2 * i + s];
+      e = make_double2(fma(w[i], r.x, -u[i] * e.x), fma(w[i], r.y, -u[i] * e.y));
+      E[2 * i + s] = e;
+    }
+  }
+  cplx Ei = cz(), sum = cz();
+#pragma unroll
+  for (int i = 1; i <= N / 2; ++i) {
+    if (i <= m) {
+      Ei = caxpy(E[2 * i + s], fr[i], Ei);
+      E[2 * i + s] = Ei;
+      sum = cadd(sum, Ei);
+    }
+  }
+  return cscale(csub(g, sum), tab[4 * ML]);
+}
+
+// Value of element e of a tau solution: x_e = E_e + F_{e/2} x0_{parity(e)}.
+template <int N>
+__device__ __forceinline__ cplx tau_value(const cplx* E, const double* TAB, const cplx* x0, int e) {
+  constexpr int ML = N / 2 + 1;
+  constexpr int OPSZ = 4 * ML + 2;
+  const int i = e >> 1, s = e & 1;
+  const cplx base = (i == 0) ? cz() : E[e];
+  return caxpy(base, TAB[s * OPSZ + 3 * ML + i], x0[s]);
+}
+
+template <int N>
+__global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
+  constexpr int WPB = wpb<N>();
+  using P = CP<N>;
+  constexpr int NY = P::NY;
+  constexpr int NS = P::NS;
+  constexpr int H = N / 2;
+  extern __shared__ double dyn_lds[];
+  double* smem = dyn_lds;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c = blockIdx.x * WPB + wave;
+  if (c >= A.ncol) return;
+  if (*A.status & STATUS_BAD_ACTION) return;
+  const int nz = A.nz;
+  const int p = c / nz, q = c - p * nz;
+  if (q == nz / 2) return;            // Nyquist: never stored
+  if (p == 0 && q > nz / 2) return;   // written by its Hermitian partner (0, -q)
+  const bool mean = (c == 0);
+  const int partner = (p == 0 && q > 0) ? (nz - q) : -1;
+
+  double* wb = smem + (size_t)wave * P::WAVE_DOUBLES;
+  cplx* B[P::NB];
+#pragma unroll
+  for (int k = 0; k < P::NB; ++k) B[k] = reinterpret_cast<cplx*>(wb + (size_t)k * P::NYP * 2);
+  double* TAB = wb + (size_t)P::NB * P::NYP * 2;
+  cplx* SC = reinterpret_cast<cplx*>(TAB + 2 * P::OPSZ);  // small scalars
+
+  const double al = A.alpha[p], be = A.beta[q];
+  const double k2 = al * al + be * be;
+  const size_t col = (size_t)c * NY;
+
+  cplx vv[NS], oo[NS];  // state after this call (v, omega_y) or (U + iW, 0) for the mean
+
+  if (A.stage >= 0) {
+    // ---------------- solve part ----------------
+    const int r = A.stage;
+    // (a) H1, H2, H3 at the nodes
+    for (int e = lane; e < NY; e += 64) {
+      const size_t o = ((size_t)e * A.nkx + p) * nz + q;
+      cplx h0 = A.H3[o], h1 = A.H3[A.plane + o], h2 = A.H3[2 * A.plane + o];
+      if (mean) {  // the mean flow sees the real parts of H1, H3 only
+        h0.y = 0.0;
+        h2.y = 0.0;
+      }
+      B[0][e] = h0;
+      B[1][e] = h1;
+      B[2][e] = h2;
+    }
+    wave_sync();
+    cplx hc[3][NS];
+    dct_forward<N, 3>(B, A.cosk, lane, hc);
+    wave_sync();
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int e = lane + 64 * s;
+      if (e <= N) {
+        B[0][e] = hc[0][s];
+        B[1][e] = hc[1][s];
+        B[2][e] = hc[2][s];
+      }
+    }
+    wave_sync();
+    if (!mean) {
+      // (b) explicit terms h_v = -k^2 H2 - D(i al H1 + i be H3), h_g = i be H1 - i al H3
+      for (int e = lane; e <= N; e += 64) {
+        const cplx h1 = B[0][e], h3 = B[2][e];
+        B[3][e] = cmuli(make_double2(al * h1.x + be * h3.x, al * h1.y + be * h3.y));
+      }
+      wave_sync();
+      cplx hv[NS], hg[NS], hvp[NS], hgp[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int e = lane + 64 * s;
+        hv[s] = hg[s] = hvp[s] = hgp[s] = cz();
+        if (e <= N) {
+          const cplx dT = (e < N) ? cheb_d1<N>(B[3], e) : cz();
+          const cplx h1 = B[0][e], h2 = B[1][e], h3 = B[2][e];
+          hv[s] = csub(cscale(h2, -k2), dT);
+          hg[s] = cmuli(make_double2(be * h1.x - al * h3.x, be * h1.y - al * h3.y));
+          if (r > 0) {
+            hvp[s] = A.hist[col + e];
+            hgp[s] = A.hist[(size_t)A.ncol * NY + col + e];
+          }
+          if (r < 2) {
+            A.hist[col + e] = hv[s];
+            A.hist[(size_t)A.ncol * NY + col + e] = hg[s];
+          }
+        }
+      }
+      // (c) phi0 = (D^2 - k^2) v, psi = (D^2 - k^2) phi0, chi = (D^2 - k^2) omega_y
+      for (int e = lane; e <= N; e += 64) {
+        B[4][e] = A.vS[col + e];
+        B[5][e] = A.oS[col + e];
+      }
+      wave_sync();
+      cplx phi0[NS], chi[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int e = lane + 64 * s;
+        phi0[s] = chi[s] = cz();
+        if (e <= N) {
+          phi0[s] = caxpy(cheb_d2<N>(B[4], e), -k2, B[4][e]);
+          chi[s] = caxpy(cheb_d2<N>(B[5], e), -k2, B[5][e]);
+          B[6][e] = phi0[s];
+        }
+      }
+      wave_sync();
+      // (d) right-hand sides of the two Helmholtz problems with lam = k^2 + lam0
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int e = lane + 64 * s;
+        if (e <= N) {
+          const cplx psi = caxpy(cheb_d2<N>(B[6], e), -k2, phi0[s]);
+          cplx rp = cscale(phi0[s], -A.lam0);
+          rp = caxpy(rp, -A.ab, psi);
+          rp = caxpy(rp, -A.gb, hv[s]);
+          rp = caxpy(rp, -A.zb, hvp[s]);
+          const cplx om = B[5][e];
+          cplx ro = cscale(om, -A.lam0);
+          ro = caxpy(ro, -A.ab, chi[s]);
+          ro = caxpy(ro, -A.gb, hg[s]);
+          ro = caxpy(ro, -A.zb, hgp[s]);
+          B[0][e] = rp;
+          B[1][e] = ro;
+        }
+      }
+      // operator record of D^2 - lam for this column and stage -> LDS
+      {
+        const double* src = A.optab + ((size_t)c * NOPS + r) * 2 * P::OPSZ;
+        for (int t = lane; t < 2 * P::OPSZ; t += 64) TAB[t] = src[t];
+      }
+      wave_sync();
+      for (int e = lane; e <= N; e += 64) {
+        B[2][e] = tau_rows<N>(B[0], A.rc, e);
+        B[3][e] = tau_rows<N>(B[1], A.rc, e);
+      }
+      wave_sync();
+      // (e) phi_p and omega_y: four serial recurrences on lanes 0..3
+      if (lane < 4) {
+        const int s = lane & 1;
+        const bool isom = lane >= 2;
+        const cplx x0 = tau_chain<N>(isom ? B[3] : B[2], TAB + s * P::OPSZ, s, cz(), isom ? B[5] : B[4]);
+        SC[lane] = x0;
+      }
+      wave_sync();
+      for (int e = lane; e <= N; e += 64) {
+        const cplx phip = tau_value<N>(B[4], TAB, SC, e);
+        const cplx om = tau_value<N>(B[5], TAB, SC + 2, e);
+        B[6][e] = phip;
+        B[7][e] = om;
+      }
+      wave_sync();
+      // (f) v_p: (D^2 - k^2) v_p = phi_p, v_p(+1) = 0, v_p(-1) = v_w
+      cplx vw;
+      if (A.wall_mode == WALL_OPP) {
+        vw = A.vw_opp[c];
+      } else {
+        const cplx o = A.vw_old[c], nn = A.vw_new[c];
+        vw = caxpy(o, A.s_ramp, csub(nn, o));
+      }
+      {
+        const double* src = A.optab + ((size_t)c * NOPS + 3) * 2 * P::OPSZ;
+        for (int t = lane; t < 2 * P::OPSZ; t += 64) TAB[t] = src[t];
+      }
+      for (int e = lane; e <= N; e += 64) B[2][e] = tau_rows<N>(B[6], A.rc, e);
+      wave_sync();
+      if (lane < 2) {
+        const int s = lane;
+        // even part (g_top + g_bot)/2, odd part (g_top - g_bot)/2 with g_top = 0, g_bot = v_w
+        const cplx g = cscale(vw, s == 0 ? 0.5 : -0.5);
+        SC[4 + s] = tau_chain<N>(B[2], TAB + s * P::OPSZ, s, g, B[3]);
+      }
+      wave_sync();
+      // (g) influence-matrix correction: Dv(+1) = Dv(-1) = 0
+      cplx vp[NS];
+      cplx dtop = cz(), dbot = cz();
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int e = lane + 64 * s;
+        vp[s] = cz();
+        if (e <= N) {
+          vp[s] = tau_value<N>(B[3], TAB, SC + 4, e);
+          const double n2 = (double)e * (double)e;
+          dtop = caxpy(dtop, n2, vp[s]);
+          dbot = caxpy(dbot, (e & 1) ? n2 : -n2, vp[s]);
+        }
+      }
+      dtop = wave_sum(dtop);
+      dbot = wave_sum(dbot);
+      const double* mi = A.minv + ((size_t)c * 3 + r) * 4;
+      const cplx c0 = make_double2(-(mi[0] * dtop.x + mi[1] * dbot.x), -(mi[0] * dtop.y + mi[1] * dbot.y));
+      const cplx c1 = make_double2(-(mi[2] * dtop.x + mi[3] * dbot.x), -(mi[2] * dtop.y + mi[3] * dbot.y));
+      const double* vt = A.vt + ((size_t)c * 3 + r) * NY;
+      bool ok = true;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int e = lane + 64 * s;
+        vv[s] = oo[s] = cz();
+        if (e <= N) {
+          const double t = vt[e];
+          const double b = (e & 1) ? -t : t;
+          vv[s] = caxpy(caxpy(vp[s], t, c0), b, c1);
+          oo[s] = B[7][e];
+          A.vS[col + e] = vv[s];
+          A.oS[col + e] = oo[s];
+          if (partner >= 0) {
+            A.vS[(size_t)partner * NY + e] = cconj(vv[s]);
+            A.oS[(size_t)partner * NY + e] = cconj(oo[s]);
+          }
+          ok = ok && isfinite(vv[s].x) && isfinite(vv[s].y) && isfinite(oo[s].x) && isfinite(oo[s].y);
+        }
+      }
+      if (r == 2 && __any(!ok) && lane == 0) atomicOr(A.status, STATUS_NONFINITE);
+    } else {
+      // ---------------- mean flow (0, 0), packed as X = U + i W ----------------
+      cplx hm[NS], hmp[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int e = lane + 64 * s;
+        hm[s] = hmp[s] = cz();
+        if (e <= N) {
+          hm[s] = make_double2(B[0][e].x, B[2][e].x);  // h_u + i h_w
+          if (r > 0) hmp[s] = make_double2(A.meanH[e], A.meanH[NY + e]);
+          if (r < 2) {
+            A.meanH[e] = hm[s].x;
+            A.meanH[NY + e] = hm[s].y;
+          }
+        }
+      }
+      for (int e = lane; e <= N; e += 64) B[4][e] = make_double2(A.meanS[e], A.meanS[NY + e]);
+      {
+        const double* src = A.optab + ((size_t)c * NOPS + r) * 2 * P::OPSZ;
+        for (int t = lane; t < 2 * P::OPSZ; t += 64) TAB[t] = src[t];
+      }
+      wave_sync();
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int e = lane + 64 * s;
+        if (e <= N) {
+          const cplx X = B[4][e];
+          cplx rr = cscale(X, -A.lam0);
+          rr = caxpy(rr, -A.ab, cheb_d2<N>(B[4], e));
+          rr = caxpy(rr, -A.gb, hm[s]);
+          rr = caxpy(rr, -A.zb, hmp[s]);
+          B[0][e] = rr;
+        }
+      }
+      wave_sync();
+      for (int e = lane; e <= N; e += 64) B[2][e] = tau_rows<N>(B[0], A.rc, e);
+      wave_sync();
+      if (lane < 2) SC[lane] = tau_chain<N>(B[2], TAB + lane * P::OPSZ, lane, cz(), B[3]);
+      wave_sync();
+      cplx xs[NS];
+      double flux = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int e = lane + 64 * s;
+        xs[s] = cz();
+        if (e <= N) {
+          xs[s] = tau_value<N>(B[3], TAB, SC, e);
+          if (!(e & 1)) flux = fma(2.0 / (1.0 - (double)e * (double)e), xs[s].x, flux);
+        }
+      }
+      flux = wave_sum(flux);
+      const double P_r = (A.forcing == 0) ? (A.ub2 - flux) * A.inv_int_up[r] : A.px;
+      const double* up = A.up + (size_t)r * NY;
+      double slope = 0.0;
+      bool ok = true;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int e = lane + 64 * s;
+        vv[s] = oo[s] = cz();
+        if (e <= N) {
+          const double U = fma(P_r, up[e], xs[s].x);
+          vv[s] = make_double2(U, xs[s].y);  // U + i W
+          A.meanS[e] = U;
+          A.meanS[NY + e] = xs[s].y;
+          const double n2 = (double)e * (double)e;
+          slope = fma((e & 1) ? n2 : -n2, U, slope);
+          ok = ok && isfinite(U) && isfinite(xs[s].y);
+        }
+      }
+      slope = wave_sum(slope);
+      if (A.accumulate_drag && lane == 0) A.drag_acc[0] += A.nu * slope;
+      if (r == 2 && __any(!ok) && lane == 0) atomicOr(A.status, STATUS_NONFINITE);
+    }
+    wave_sync();
+  } else {
+    // ---------------- reconstruct-only: load the state ----------------
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int e = lane + 64 * s;
+      vv[s] = oo[s] = cz();
+      if (e <= N) {
+        if (mean) {
+          vv[s] = make_double2(A.meanS[e], A.meanS[NY + e]);
+        } else {
+          vv[s] = A.vS[col + e];
+          oo[s] = A.oS[col + e];
+        }
+      }
+    }
+  }
+
+  // ---------------- reconstruction and inverse DCT for the next stage ----------------
+  const bool want_end = (A.stage == 2 || A.stage < 0);
+  cplx tau_hat = cz();
+  if (!mean) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int e = lane + 64 * s;
+      if (e <= N) B[0][e] = vv[s];
+    }
+    wave_sync();
+    // u = (i al Dv - i be om)/k^2, w = (i be Dv + i al om)/k^2
+    const double ik2 = 1.0 / k2;
+    cplx uu[NS], ww[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int e = lane + 64 * s;
+      uu[s] = ww[s] = cz();
+      if (e <= N) {
+        const cplx dv = (e < N) ? cheb_d1<N>(B[0], e) : cz();
+        const cplx om = oo[s];
+        uu[s] = cscale(cmuli(make_double2(al * dv.x - be * om.x, al * dv.y - be * om.y)), ik2);
+        ww[s] = cscale(cmuli(make_double2(be * dv.x + al * om.x, be * dv.y + al * om.y)), ik2);
+        const double n2 = (double)e * (double)e;
+        tau_hat = caxpy(tau_hat, (e & 1) ? n2 : -n2, uu[s]);
+      }
+    }
+    tau_hat = cscale(wave_sum(tau_hat), A.nu);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int e = lane + 64 * s;
+      if (e <= N) {
+        B[2][e] = uu[s];
+        B[3][e] = ww[s];
+      }
+    }
+    wave_sync();
+    // omega_x = Dw - i be v, omega_z = i al v - Du
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int e = lane + 64 * s;
+      if (e <= N) {
+        const cplx du = (e < N) ? cheb_d1<N>(B[2], e) : cz();
+        const cplx dw = (e < N) ? cheb_d1<N>(B[3], e) : cz();
+        const cplx v = vv[s];
+        B[4][e] = csub(dw, cmuli(cscale(v, be)));
+        B[5][e] = csub(cmuli(cscale(v, al)), du);
+        B[6][e] = oo[s];
+      }
+    }
+    wave_sync();
+  } else {
+    // mean: u = U, w = W, omega_x = DW, omega_z = -DU, v = omega_y = 0
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int e = lane + 64 * s;
+      if (e <= N) B[0][e] = vv[s];
+    }
+    wave_sync();
+    double slope = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int e = lane + 64 * s;
+      if (e <= N) {
+        const cplx X = vv[s];
+        const cplx dX = (e < N) ? cheb_d1<N>(B[0], e) : cz();
+        const double n2 = (double)e * (double)e;
+        slope = fma((e & 1) ? n2 : -n2, X.x, slope);
+        B[2][e] = make_double2(X.x, 0.0);
+        B[3][e] = make_double2(X.y, 0.0);
+        B[4][e] = make_double2(dX.y, 0.0);
+        B[5][e] = make_double2(-dX.x, 0.0);
+        B[6][e] = cz();
+      }
+    }
+    tau_hat = make_double2(A.nu * wave_sum(slope), 0.0);
+    wave_sync();
+    for (int e = lane; e <= N; e += 64) B[0][e] = cz();
+    wave_sync();
+  }
+  // fields in order (u, v, w, omega_x, omega_y, omega_z)
+  cplx* X6[6] = {B[2], B[0], B[3], B[4], B[6], B[5]};
+  cplx ph[6][NS];
+  dct_inverse<N, 6>(X6, A.cosk, lane, ph);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int e = lane + 64 * s;
+    if (e <= N) {
+      const size_t o = ((size_t)e * A.nkx + p) * nz + q;
+      const size_t o2 = ((size_t)e * A.nkx + p) * nz + (partner >= 0 ? partner : 0);
+#pragma unroll
+      for (int f = 0; f < 6; ++f) {
+        cplx val = ph[f][s];
+        if (mean) val.y = 0.0;
+        A.F6[(size_t)f * A.plane + o] = val;
+        if (partner >= 0) A.F6[(size_t)f * A.plane + o2] = cconj(val);
+      }
+      if (want_end && e == A.js) {
+        const cplx opp = mean ? cz() : cscale(ph[1][s], -A.opp_alpha);
+        A.vw_opp[c] = opp;
+        if (partner >= 0) A.vw_opp[partner] = cconj(opp);
+      }
+    }
+  }
+  if (want_end && lane == 0) {
+    A.tauw[c] = tau_hat;
+    if (partner >= 0) A.tauw[partner] = cconj(tau_hat);
+  }
+}
+
+template <int N>
+static int launch_col(const ColArgs& A, hipStream_t st) {
+  constexpr int WPB = wpb<N>();
+  const int blocks = (A.ncol + WPB - 1) / WPB;
+  const size_t shm = (size_t)WPB * CP<N>::WAVE_DOUBLES * sizeof(double);
+  hipLaunchKernelGGL(k_column<N>, dim3(blocks), dim3(64 * WPB), shm, st, A);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+
+int launch_column_pass(const Dims& d, DeviceState& s, const PhysParams& ph, int stage,
+                       const StageConsts& sc, int wall_mode, double s_ramp, int js,
+                       double opp_alpha, bool accumulate_drag, hipStream_t st) {
+  ColArgs A;
+  A.nkx = d.nkx;
+  A.nz = d.nz;
+  A.ncol = d.ncol;
+  A.stage = stage;
+  A.wall_mode = wall_mode;
+  A.s_ramp = s_ramp;
+  A.lam0 = sc.lam0;
+  A.ab = sc.ab;
+  A.gb = sc.gb;
+  A.zb = sc.zb;
+  A.nu = ph.nu;
+  A.opp_alpha = opp_alpha;
+  A.ub2 = 2.0 * ph.ub;
+  A.px = ph.px;
+  A.forcing = ph.forcing;
+  A.js = js;
+  A.accumulate_drag = accumulate_drag ? 1 : 0;
+  A.plane = (size_t)d.ny * d.nkx * d.nz;
+  A.vS = s.vS;
+  A.oS = s.oS;
+  A.hist = s.hist;
+  A.meanS = s.meanS;
+  A.meanH = s.meanH;
+  A.H3 = s.H3;
+  A.F6 = s.F6;
+  A.vw_old = s.vw_old;
+  A.vw_new = s.vw_new;
+  A.vw_opp = s.vw_opp;
+  A.tauw = s.tauw;
+  A.cosk = s.cosk;
+  A.rc = s.rc;
+  A.optab = s.optab;
+  A.vt = s.vt;
+  A.minv = s.minv;
+  A.up = s.up;
+  A.inv_int_up = s.inv_int_up;
+  A.alpha = s.alpha;
+  A.beta = s.beta;
+  A.drag_acc = s.drag_acc;
+  A.status = s.status;
+  switch (d.N) {
+    case 16: return launch_col<16>(A, st);
+    case 32: return launch_col<32>(A, st);
+    case 64: return launch_col<64>(A, st);
+    case 96: return launch_col<96>(A, st);
+    case 128: return launch_col<128>(A, st);
+    default: return -1;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Small kernels: step bookkeeping, action ingest, observation and wall shear.
+// ----------------------------------------------------------------------------
+__global__ void k_begin_step(int* status, double* drag_acc, cplx* vw_new, int ncol, int zero_vw) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) {
+    status[0] = 0;
+    drag_acc[0] = 0.0;
+  }
+  if (zero_vw) {
+    for (int i = t; i < ncol; i += gridDim.x * blockDim.x) vw_new[i] = cz();
+  }
+}
+
+int launch_begin_step(const Dims& d, DeviceState& s, bool zero_vw_new, hipStream_t st) {
+  hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(256), 0, st, s.status, s.drag_acc, s.vw_new, d.ncol,
+                     zero_vw_new ? 1 : 0);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// Rows of the action: finiteness check, clip, forward FFT along x; keeps p < nx/2.
+__global__ void k_ingest_rows(const double* __restrict__ act, int nx, int nkx, double clip,
+                              const cplx* __restrict__ twnx, cplx* tmp, int* status) {
+  extern __shared__ double dyn_lds[];
+  cplx* a = reinterpret_cast<cplx*>(dyn_lds);
+  cplx* b = a + nx;
+  const int k = blockIdx.x;
+  int bad = 0;
+  for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+    double v = act[(size_t)k * nx + i];
+    if (!isfinite(v)) bad = 1;
+    if (clip > 0.0) v = fmin(fmax(v, -clip), clip);
+    a[i] = make_double2(v, 0.0);
+  }
+  if (__syncthreads_or(bad)) {
+    if (threadIdx.x == 0) atomicOr(status, STATUS_BAD_ACTION);
+    return;
+  }
+  cplx* r = fft_batch(a, b, nx, 1, nx, twnx, false);
+  for (int pidx = threadIdx.x; pidx < nkx; pidx += blockDim.x) tmp[(size_t)k * nkx + pidx] = r[pidx];
+}
+
+// Columns: forward FFT along z, 1/(nx nz), Nyquist and mean removed, Hermitian fix.
+__global__ void k_ingest_cols(const cplx* __restrict__ tmp, int nx, int nz, int nkx,
+                              const cplx* __restrict__ twnz, cplx* vw_new, const int* status) {
+  extern __shared__ double dyn_lds[];
+  cplx* a = reinterpret_cast<cplx*>(dyn_lds);
+  cplx* b = a + nz;
+  if (*status & STATUS_BAD_ACTION) return;
+  const int p = blockIdx.x;
+  for (int k = threadIdx.x; k < nz; k += blockDim.x) a[k] = tmp[(size_t)k * nkx + p];
+  __syncthreads();
+  cplx* r = fft_batch(a, b, nz, 1, nz, twnz, false);
+  const double sc = 1.0 / ((double)nx * (double)nz);
+  const int h = nz / 2;
+  for (int q = threadIdx.x; q < nz; q += blockDim.x) {
+    cplx v = cz();
+    if (q != h && !(p == 0 && q == 0)) {
+      v = (p == 0 && q > h) ? cconj(r[nz - q]) : r[q];
+      v = cscale(v, sc);
+    }
+    vw_new[(size_t)p * nz + q] = v;
+  }
+}
+
+int launch_ingest(const Dims& d, DeviceState& s, const double* action, double clip, hipStream_t st) {
+  hipLaunchKernelGGL(k_ingest_rows, dim3(d.nz), dim3(64), (size_t)2 * d.nx * sizeof(cplx), st, action,
+                     d.nx, d.nkx, clip, s.twnx, s.tmp2d, s.status);
+  hipLaunchKernelGGL(k_ingest_cols, dim3(d.nkx), dim3(64), (size_t)2 * d.nz * sizeof(cplx), st, s.tmp2d,
+                     d.nx, d.nz, d.nkx, s.twnz, s.vw_new, s.status);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// Output transforms.  Source spectra are [p][q] with p-stride src_pstride; field f of
+// the batch starts at src + f * src_fstride.  Columns: inverse FFT along z.
+__global__ void k_out_cols(const cplx* __restrict__ src, size_t src_fstride, int nz, int nkx,
+                           const cplx* __restrict__ twnz, cplx* tmp) {
+  extern __shared__ double dyn_lds[];
+  cplx* a = reinterpret_cast<cplx*>(dyn_lds);
+  cplx* b = a + nz;
+  const int p = blockIdx.x, f = blockIdx.y;
+  const cplx* s = src + (size_t)f * src_fstride + (size_t)p * nz;
+  const int h = nz / 2;
+  for (int q = threadIdx.x; q < nz; q += blockDim.x) a[q] = (q == h) ? cz() : s[q];
+  __syncthreads();
+  cplx* r = fft_batch(a, b, nz, 1, nz, twnz, true);
+  for (int k = threadIdx.x; k < nz; k += blockDim.x) tmp[((size_t)f * nz + k) * nkx + p] = r[k];
+}
+
+// Rows: Hermitian extension along x (real part of p = 0), inverse FFT, real part out.
+__global__ void k_out_rows(const cplx* __restrict__ tmp, int nx, int nz, int nkx,
+                           const cplx* __restrict__ twnx, double* out, size_t out_fstride) {
+  extern __shared__ double dyn_lds[];
+  cplx* a = reinterpret_cast<cplx*>(dyn_lds);
+  cplx* b = a + nx;
+  const int k = blockIdx.x, f = blockIdx.y;
+  const cplx* row = tmp + ((size_t)f * nz + k) * nkx;
+  for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+    cplx v = cz();
+    if (i == 0) {
+      v = make_double2(row[0].x, 0.0);
+    } else if (i < nkx) {
+      v = row[i];
+    } else if (i > nx - nkx) {
+      v = cconj(row[nx - i]);
+    }
+    a[i] = v;
+  }
+  __syncthreads();
+  cplx* r = fft_batch(a, b, nx, 1, nx, twnx, true);
+  for (int i = threadIdx.x; i < nx; i += blockDim.x) out[(size_t)f * out_fstride + (size_t)k * nx + i] = r[i].x;
+}
+
+int launch_outputs(const Dims& d, DeviceState& s, int js, uint32_t obs_mask, double* obs,
+                   double* tau_w, hipStream_t st) {
+  const size_t plane = (size_t)d.ny * d.nkx * d.nz;
+  const size_t shz = (size_t)2 * d.nz * sizeof(cplx), shx = (size_t)2 * d.nx * sizeof(cplx);
+  if (obs) {
+    int slot = 0;
+    for (int f = 0; f < 3; ++f) {
+      if (!(obs_mask & (1u << f))) continue;
+      const cplx* src = s.F6 + (size_t)f * plane + (size_t)js * d.nkx * d.nz;
+      hipLaunchKernelGGL(k_out_cols, dim3(d.nkx, 1), dim3(64), shz, st, src, (size_t)0, d.nz, d.nkx, s.twnz,
+                         s.tmp2d);
+      hipLaunchKernelGGL(k_out_rows, dim3(d.nz, 1), dim3(64), shx, st, s.tmp2d, d.nx, d.nz, d.nkx, s.twnx,
+                         obs + (size_t)slot * d.nz * d.nx, (size_t)0);
+      ++slot;
+    }
+  }
+  if (tau_w) {
+    hipLaunchKernelGGL(k_out_cols, dim3(d.nkx, 1), dim3(64), shz, st, s.tauw, (size_t)0, d.nz, d.nkx, s.twnz,
+                       s.tmp2d);
+    hipLaunchKernelGGL(k_out_rows, dim3(d.nz, 1), dim3(64), shx, st, s.tmp2d, d.nx, d.nz, d.nkx, s.twnx, tau_w,
+                       (size_t)0);
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// End of an env step: drag = accumulated / n, and v_w,old := v_w,new (unless the
+// action was rejected).
+__global__ void k_finish_step(const int* status, const double* drag_acc, double* drag, int nsub,
+                              const cplx* vw_new, cplx* vw_old, int ncol, int copy_vw) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool bad = (*status & STATUS_BAD_ACTION) != 0;
+  if (bad) return;
+  if (t == 0 && drag) drag[0] = drag_acc[0] / (double)nsub;
+  if (copy_vw) {
+    for (int i = t; i < ncol; i += gridDim.x * blockDim.x) vw_old[i] = vw_new[i];
+  }
+}
+
+int launch_finish_step(const Dims& d, DeviceState& s, bool copy_vw, double* drag, int nsub,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_finish_step, dim3(1), dim3(256), 0, st, s.status, s.drag_acc, drag, nsub, s.vw_new,
+                     s.vw_old, d.ncol, copy_vw ? 1 : 0);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace chanenv

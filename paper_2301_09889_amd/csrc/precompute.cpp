@@ -1,0 +1,204 @@
+// Host precompute of the operator tables, FP64 (done once per env).
+//
+// * cos(pi a b / N) for the folded DCT-I, a <= N/2, b <= N.
+// * The three-term rows of the quasi-tridiagonal tau form (Gottlieb & Orszag 1977;
+//   Canuto et al.): for a polynomial X of degree N with b = D^2 X,
+//     X_n = c_{n-2} b_{n-2} / (4n(n-1)) - b_n / (2(n^2-1)) + b_{n+2} / (4n(n+1)),
+//   n = 2..N, b_m = 0 for m >= N-1.  With the tau equations b_m = lam X_m + f_m
+//   (m <= N-2) this is, for each parity of n, a tridiagonal system closed by the
+//   boundary row sum_i X_{2i+s} = g_s.
+// * For every wavenumber pair and each of the operators D^2 - lam (the three RK
+//   stages' lam = k^2 + 1/(b_r nu dt), and lam = k^2 for v) and each parity: the
+//   bottom-up elimination coefficients w_i = 1/den_i, u_i = U_i/den_i,
+//   f_i = -L_i/den_i with den_i = D_i + U_i f_{i+1}, the products F_i = f_1..f_i and
+//   1/sum F_i.  The device then solves any right-hand side with two first-order
+//   recurrences.
+// * Per pair and stage, the homogeneous solution v_+ of the influence-matrix method
+//   (Kim, Moin & Moser 1987): (D^2 - lam) phi_+ = 0, phi_+(+1) = 1, phi_+(-1) = 0;
+//   (D^2 - k^2) v_+ = phi_+, v_+(+-1) = 0; v_- is its mirror image
+//   (v_-)_n = (-1)^n (v_+)_n, and the inverse of the 2x2 matrix of dv_+-/dy at
+//   the walls.
+// * Mean flow: the unit-pressure-gradient response U_P of each stage and 1/int U_P.
+// * FFT twiddles exp(-2 pi i k / L) for the padded and unpadded lengths, and the
+//   wavenumbers.
+#include <cmath>
+
+#include "chanenv_internal.h"
+
+namespace chanenv {
+
+namespace {
+
+// Solve (D^2 - lam) X = f (tau rows 0..N-2) with X(+1) = gt, X(-1) = gb, real data,
+// using the packed elimination records rec (two parities).
+void host_tau_solve(const Dims& d, const double* rec, const double* rc, const double* f, double gt,
+                    double gb, double* x) {
+  const int N = d.N, NY = d.ny, ML = d.ml;
+  std::vector<double> R(NY, 0.0), E(NY, 0.0);
+  for (int n = 2; n <= N; ++n) {
+    double r = rc[n] * f[n - 2] - rc[NY + n] * f[n];
+    if (n + 2 <= N) r += rc[2 * NY + n] * f[n + 2];
+    R[n] = r;
+  }
+  for (int s = 0; s < 2; ++s) {
+    const double* t = rec + (size_t)s * d.opsz;
+    const double *w = t, *u = t + ML, *fr = t + 2 * ML, *F = t + 3 * ML;
+    const int m = (N - s) / 2;
+    const double g = (s == 0) ? 0.5 * (gt + gb) : 0.5 * (gt - gb);
+    double e = 0.0;
+    for (int i = m; i >= 1; --i) {
+      e = w[i] * R[2 * i + s] - u[i] * e;
+      E[2 * i + s] = e;
+    }
+    double Ei = 0.0, sum = 0.0;
+    for (int i = 1; i <= m; ++i) {
+      Ei = E[2 * i + s] + fr[i] * Ei;
+      E[2 * i + s] = Ei;
+      sum += Ei;
+    }
+    const double x0 = (g - sum) * t[4 * ML];
+    for (int i = 0; i <= m; ++i) x[2 * i + s] = (i == 0 ? 0.0 : E[2 * i + s]) + F[i] * x0;
+  }
+}
+
+void fill_record(const Dims& d, double lam, double* rec) {
+  const int N = d.N, ML = d.ml;
+  for (int s = 0; s < 2; ++s) {
+    double* t = rec + (size_t)s * d.opsz;
+    double *w = t, *u = t + ML, *f = t + 2 * ML, *F = t + 3 * ML;
+    for (int k = 0; k < d.opsz; ++k) t[k] = 0.0;
+    const int m = (N - s) / 2;
+    double fnext = 0.0;
+    for (int i = m; i >= 1; --i) {
+      const int n = 2 * i + s;
+      const double cm2 = (n == 2) ? 2.0 : 1.0;
+      const double en = (n <= N - 2) ? 1.0 : 0.0;
+      const double en2 = (n + 2 <= N - 2) ? 1.0 : 0.0;
+      const double Li = -cm2 * lam / (4.0 * n * (n - 1.0));
+      const double Di = 1.0 + en * lam / (2.0 * ((double)n * n - 1.0));
+      const double Ui = -en2 * lam / (4.0 * n * (n + 1.0));
+      const double den = Di + Ui * fnext;
+      w[i] = 1.0 / den;
+      u[i] = Ui / den;
+      f[i] = -Li / den;
+      fnext = f[i];
+    }
+    F[0] = 1.0;
+    double sum = 1.0;
+    for (int i = 1; i <= m; ++i) {
+      F[i] = f[i] * F[i - 1];
+      sum += F[i];
+    }
+    t[4 * ML] = 1.0 / sum;
+  }
+}
+
+}  // namespace
+
+static const double RK_ALPHA[3] = {4.0 / 15.0, 1.0 / 15.0, 1.0 / 6.0};
+static const double RK_BETA[3] = {4.0 / 15.0, 1.0 / 15.0, 1.0 / 6.0};
+
+void precompute_tables(const Dims& d, const PhysParams& ph, HostTables* out) {
+  const int N = d.N, NY = d.ny, H = N / 2;
+  TableLayout& L = out->L;
+  size_t o = 0;
+  auto take = [&](size_t n) {
+    size_t r = o;
+    o += (n + 1) & ~size_t(1);  // keep every table 16-byte aligned
+    return r;
+  };
+  L.cosk = take((size_t)(H + 1) * NY);
+  L.rc = take((size_t)3 * NY);
+  L.optab = take((size_t)d.ncol * NOPS * 2 * d.opsz);
+  L.vt = take((size_t)d.ncol * 3 * NY);
+  L.minv = take((size_t)d.ncol * 3 * 4);
+  L.up = take((size_t)3 * NY);
+  L.inv_int_up = take(4);
+  L.twz = take((size_t)2 * d.mz);
+  L.twx = take((size_t)2 * d.mx);
+  L.twnx = take((size_t)2 * d.nx);
+  L.twnz = take((size_t)2 * d.nz);
+  L.alpha = take(d.nkx);
+  L.beta = take(d.nz);
+  L.total = o;
+  std::vector<double>& T = out->data;
+  T.assign(L.total, 0.0);
+
+  const long double PI = 3.141592653589793238462643383279502884L;
+  for (int a = 0; a <= H; ++a)
+    for (int b = 0; b <= N; ++b) {
+      const int k = (a * b) % (2 * N);
+      T[L.cosk + (size_t)a * NY + b] = (double)cosl(PI * (long double)k / (long double)N);
+    }
+  double* rc = &T[L.rc];
+  for (int n = 2; n <= N; ++n) {
+    const double cm2 = (n == 2) ? 2.0 : 1.0;
+    rc[n] = cm2 / (4.0 * n * (n - 1.0));
+    rc[NY + n] = (n <= N - 2) ? 1.0 / (2.0 * ((double)n * n - 1.0)) : 0.0;
+    rc[2 * NY + n] = (n + 2 <= N - 2) ? 1.0 / (4.0 * n * (n + 1.0)) : 0.0;
+  }
+  double* alpha = &T[L.alpha];
+  double* beta = &T[L.beta];
+  for (int p = 0; p < d.nkx; ++p) alpha[p] = 2.0 * M_PI * p / ph.lx;
+  for (int q = 0; q < d.nz; ++q) {
+    const int qs = (q < d.nz / 2) ? q : q - d.nz;
+    beta[q] = (q == d.nz / 2) ? 0.0 : 2.0 * M_PI * qs / ph.lz;
+  }
+  double lam0[3];
+  for (int r = 0; r < 3; ++r) lam0[r] = 1.0 / (RK_BETA[r] * ph.nu * ph.dt);
+
+  std::vector<double> phi(NY), v(NY), zero(NY, 0.0);
+  for (int c = 0; c < d.ncol; ++c) {
+    const int p = c / d.nz, q = c % d.nz;
+    if (q == d.nz / 2) continue;
+    if (p == 0 && q > d.nz / 2) continue;
+    const double k2 = alpha[p] * alpha[p] + beta[q] * beta[q];
+    double* base = &T[L.optab + (size_t)c * NOPS * 2 * d.opsz];
+    for (int r = 0; r < 3; ++r) fill_record(d, k2 + lam0[r], base + (size_t)r * 2 * d.opsz);
+    fill_record(d, k2, base + (size_t)3 * 2 * d.opsz);
+    if (c == 0) continue;
+    for (int r = 0; r < 3; ++r) {
+      host_tau_solve(d, base + (size_t)r * 2 * d.opsz, rc, zero.data(), 1.0, 0.0, phi.data());
+      host_tau_solve(d, base + (size_t)3 * 2 * d.opsz, rc, phi.data(), 0.0, 0.0, v.data());
+      double a = 0.0, b = 0.0;  // dv_+/dy at +1 and -1
+      for (int n = 0; n <= N; ++n) {
+        const double n2 = (double)n * n;
+        a += n2 * v[n];
+        b += ((n & 1) ? n2 : -n2) * v[n];
+      }
+      const double det = b * b - a * a;
+      double* mi = &T[L.minv + ((size_t)c * 3 + r) * 4];
+      mi[0] = -a / det;
+      mi[1] = b / det;
+      mi[2] = -b / det;
+      mi[3] = a / det;
+      for (int n = 0; n <= N; ++n) T[L.vt + ((size_t)c * 3 + r) * NY + n] = v[n];
+    }
+  }
+  // mean flow: (D^2 - lam0_r) U_P = -(a_r + b_r)/(b_r nu), U_P(+-1) = 0
+  {
+    const double* base = &T[L.optab];
+    std::vector<double> f(NY, 0.0);
+    for (int r = 0; r < 3; ++r) {
+      f[0] = -(RK_ALPHA[r] + RK_BETA[r]) / (RK_BETA[r] * ph.nu);
+      double* up = &T[L.up + (size_t)r * NY];
+      host_tau_solve(d, base + (size_t)r * 2 * d.opsz, rc, f.data(), 0.0, 0.0, up);
+      double integ = 0.0;
+      for (int n = 0; n <= N; n += 2) integ += 2.0 / (1.0 - (double)n * n) * up[n];
+      T[L.inv_int_up + r] = 1.0 / integ;
+    }
+  }
+  auto twiddles = [&](size_t off, int len) {
+    for (int k = 0; k < len; ++k) {
+      const long double ang = -2.0L * PI * (long double)k / (long double)len;
+      T[off + 2 * k] = (double)cosl(ang);
+      T[off + 2 * k + 1] = (double)sinl(ang);
+    }
+  };
+  twiddles(L.twz, d.mz);
+  twiddles(L.twx, d.mx);
+  twiddles(L.twnx, d.nx);
+  twiddles(L.twnz, d.nz);
+}
+
+}  // namespace chanenv

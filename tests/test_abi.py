@@ -1,0 +1,86 @@
+"""Host-side checks of the C ABI library (no GPU needed): it loads, exports every
+entry point declared in include/chanenv.h, and validates grids."""
+import os
+import re
+import subprocess
+
+import pytest
+
+from tests.conftest import ROOT
+
+
+def ensure_built():
+    import paper_2301_09889_amd.binding as b
+    if not os.path.exists(b.library_path()):
+        from paper_2301_09889_amd.build import build
+        build()
+    return b
+
+
+def declared_functions():
+    with open(os.path.join(ROOT, "include", "chanenv.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:int|void|size_t|const char\*)\s+(chan_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_documented_calls():
+    names = declared_functions()
+    for n in ["chan_env_create", "chan_env_reset", "chan_env_step", "chan_env_get_state",
+              "chan_env_set_state", "chan_env_query", "chan_env_destroy", "chan_strerror",
+              "chan_env_footprint_bytes", "chan_opts_default"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    b = ensure_built()
+    out = subprocess.run(["nm", "-D", "--defined-only", b.library_path()], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT\s+(chan_\w+)", out))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    lib = b.load_library()
+    for n in declared_functions():
+        assert hasattr(lib, n)
+
+
+def test_binding_names_match_header():
+    b = ensure_built()
+    for n in declared_functions():
+        assert callable(getattr(b, n)), n
+
+
+def test_grid_validation_and_footprint():
+    b = ensure_built()
+    good = b.ChanGrid(16, 65, 16, 2.67, 0.8, 180.0, 0.05, 15.0)
+    fp = b.chan_env_footprint_bytes(good)
+    assert fp > 0
+    big = b.ChanGrid(64, 65, 64, 6.283, 3.1416, 180.0, 0.05, 15.0)
+    assert b.chan_env_footprint_bytes(big) > 10 * fp
+    for bad in [b.ChanGrid(12, 65, 16, 2.67, 0.8, 180.0, 0.05, 15.0),   # nx not a power of 2
+                b.ChanGrid(16, 64, 16, 2.67, 0.8, 180.0, 0.05, 15.0),   # even ny
+                b.ChanGrid(16, 49, 16, 2.67, 0.8, 180.0, 0.05, 15.0),   # unsupported ny
+                b.ChanGrid(16, 65, 16, 2.67, 0.8, -1.0, 0.05, 15.0),    # re_tau
+                b.ChanGrid(16, 65, 16, 2.67, 0.8, 180.0, 0.0, 15.0),    # dt
+                b.ChanGrid(16, 65, 16, 0.0, 0.8, 180.0, 0.05, 15.0)]:   # lx
+        assert b.chan_env_footprint_bytes(bad) == 0
+    o = b.chan_opts_default()
+    assert o.clip == 1.0 and o.opp_alpha == 1.0 and o.obs_mask == 3
+    o.top_bc = b.CHAN_TOP_FREESLIP
+    assert b.chan_env_footprint_bytes(good, o) == 0
+
+
+def test_create_rejects_invalid_grid_without_device():
+    b = ensure_built()
+    bad = b.ChanGrid(12, 65, 16, 2.67, 0.8, 180.0, 0.05, 15.0)
+    with pytest.raises(b.ChanError) as ei:
+        b.chan_env_create(bad)
+    assert ei.value.code == b.CHAN_EINVAL
+
+
+def test_strerror():
+    b = ensure_built()
+    assert b.chan_strerror(0) == "ok"
+    assert "non-finite" in b.chan_strerror(-4)
+    assert b.chan_strerror(-99) == "unknown error"
