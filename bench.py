@@ -1,0 +1,192 @@
+#!/usr/bin/env python
+"""Benchmark of the channel-flow DNS environment step on one MI355X.
+
+Workload (the larger channel of §3.1, closed-channel reading): 2 pi h x 2h x pi h,
+64 x 65 x 64 modes, Re_tau = 180, dt+ = 0.05, Reichardt mean profile plus a seeded
+perturbation, one env step = a seeded Gaussian wall-velocity action (sigma = 0.1
+u_tau, plane mean removed) held for 10 RK3/CN time steps, then the observation
+plane (u, v at y+ = 15 -> node y+ 17.3), the wall-shear field and the drag.  All
+actions are on the device before the timed region starts.
+
+Prints one JSON line: env-steps/s (whole job), grid-point-substeps/s, p50/p99 env
+step latency, the roofline entry of the dominant kernel measured with HIP events
+inside the timed region, and the oracle timed on the host as the CPU baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "DNS env-steps/sec & grid-pt-substeps/s vs plain; p50/p99 step latency"
+HBM_PEAK_GBS = 8000.0
+
+LARGER = dict(nx=64, ny=65, nz=64, lx=2 * np.pi, lz=np.pi, re_tau=180.0, dt_plus=0.05, obs_y_plus=15.0)
+MINIMAL = dict(nx=16, ny=65, nz=16, lx=2.67, lz=0.8, re_tau=180.0, dt_plus=0.05, obs_y_plus=15.0)
+
+
+def resolved_points(g):
+    """K = (N_x/2)(N_z - 1) N_y: complex spectral unknowns of one field."""
+    return (g["nx"] // 2) * (g["nz"] - 1) * g["ny"]
+
+
+def algorithmic_bytes_per_launch(kclass, g):
+    """Minimum HBM bytes one launch of a kernel class must move, from the
+    two-layout pass model: 16 K bytes per complex field pass.  The column pass
+    reads H (3 fields), v and omega_y (2) and, from the second stage on, the
+    previous stage's h_v, h_g (2); it writes v, omega_y (2), h_v, h_g (2, first
+    two stages) and the six fields for the plane pass: 15 2/3 passes per launch
+    on average over the three stages."""
+    K = resolved_points(g)
+    if kclass == "column_pass":
+        return (3 + 2 + 4.0 / 3.0 + 2 + 4.0 / 3.0 + 6) * 16.0 * K
+    nkx, ny, mz = g["nx"] // 2, g["ny"], 3 * g["nz"] // 2
+    padded = 16.0 * ny * mz * nkx          # one field on the z-padded intermediate
+    if kclass == "z_inverse_fft":
+        return 6 * 16.0 * K + 6 * padded
+    if kclass == "x_rows_fft_product":
+        return 6 * padded + 3 * padded
+    if kclass == "z_forward_fft":
+        return 3 * padded + 3 * 16.0 * K
+    return None
+
+
+def cpu_baseline(g, opts_kw, n_sub_env, seed, budget_substeps):
+    """The oracle (test infrastructure) on a bounded sample of the same workload,
+    one BLAS thread."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import channel as ch
+    from synth import gaussian_action
+    cfg = ch.Config(**g, **opts_kw)
+    env = ch.Env(cfg)
+    env.reset(seed)
+    act = gaussian_action(1000 + seed, g["nz"], g["nx"])
+    with threadpool_limits(limits=1):
+        env.step(act, 1)  # warm caches and matrices
+        t0 = time.perf_counter()
+        env.step(act, budget_substeps)
+        dt = time.perf_counter() - t0
+    per_substep = dt / budget_substeps
+    return {"value": 1.0 / (per_substep * n_sub_env), "unit": "env-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{budget_substeps} time steps of one env step of the same workload "
+                      f"({dt:.1f} s), scaled to {n_sub_env} time steps per env step; one BLAS thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100, help="timed env steps")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed env steps")
+    ap.add_argument("--substeps", type=int, default=10, help="RK3 time steps per env step")
+    ap.add_argument("--workload", choices=["larger", "minimal"], default="larger")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-substeps", type=int, default=4, help="time steps in the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the channel step runs on a single MI355X; "
+              "multi-GPU sharding is a design note only (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2301_09889_amd.binding as b
+    from synth import gaussian_action
+
+    g = LARGER if args.workload == "larger" else MINIMAL
+    if args.workload == "larger":
+        opts_kw = dict(ic_profile=1, action_mode=1)    # Reichardt mean; action held over the env step
+        workload = ("larger channel 2pi x 2 x pi (h), 64x65x64 modes, Re_tau 180, dt+ 0.05, seeded Gaussian "
+                    "wall action sigma 0.1 u_tau held for 10 time steps, obs u,v at y+ 15")
+    else:
+        opts_kw = dict(controller=1)                   # opposition control at y+ = 15
+        workload = ("minimal channel 2.67 x 2 x 0.8 (h), 16x65x16 modes, Re_tau 180, dt+ 0.05, opposition "
+                    "control sensing at y+ 15")
+    torch.cuda.set_device(0)
+    grid = b.ChanGrid(g["nx"], g["ny"], g["nz"], g["lx"], g["lz"], g["re_tau"], g["dt_plus"], g["obs_y_plus"])
+    opts = b.make_opts(**opts_kw)
+    env = b.ChanEnv(grid, opts)
+    env.reset(args.seed)
+    n_act = args.warmup + 2 * args.steps
+    acts = torch.stack([torch.tensor(gaussian_action(1000 + args.seed + k, g["nz"], g["nx"]),
+                                     dtype=torch.float64) for k in range(n_act)]).cuda()
+    use_action = args.workload == "larger"
+    for k in range(args.warmup):
+        env.step(acts[k] if use_action else None, args.substeps)
+    torch.cuda.synchronize()
+
+    # timed region: throughput and per-step latency (timing instrumentation off)
+    lat = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        s0 = time.perf_counter()
+        env.step(acts[args.warmup + k] if use_action else None, args.substeps)
+        lat.append(time.perf_counter() - s0)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    # same number of env steps with every kernel bracketed by HIP events on the env's stream
+    b.chan_env_set_timing(env.handle, 1)
+    t1 = time.perf_counter()
+    for k in range(args.steps):
+        env.step(acts[args.warmup + args.steps + k] if use_action else None, args.substeps)
+    torch.cuda.synchronize()
+    elapsed_timed = time.perf_counter() - t1
+    kt = b.chan_env_timing_read(env.handle)
+    b.chan_env_set_timing(env.handle, 0)
+    env.close()
+
+    dom = max((k for k in kt if kt[k][0] > 0), key=lambda k: kt[k][1])
+    n_launch, ms = kt[dom]
+    avg_s = ms / 1e3 / n_launch
+    alg = algorithmic_bytes_per_launch(dom, g)
+    achieved = alg / avg_s / 1e9 if alg else None
+    roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+            "avg_launch_us": avg_s * 1e6, "launches": n_launch,
+            "algorithmic_bytes_per_launch": alg}
+    kernels = {k: {"launches": v[0], "total_ms": round(v[1], 4), "avg_us": round(1e3 * v[1] / v[0], 3)}
+               for k, v in kt.items() if v[0] > 0}
+
+    value = args.steps / elapsed
+    pts = g["nx"] * g["ny"] * g["nz"]
+    lat_ms = np.array(lat) * 1e3
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "env-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": workload, "grid": [g["nx"], g["ny"], g["nz"]], "substeps_per_env_step": args.substeps,
+                   "seed": args.seed},
+        "grid_pt_substeps_per_s": value * args.substeps * pts,
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
+        "roofline": roof,
+        "kernels": kernels,
+        "timing_pass_ms_per_step": 1e3 * elapsed_timed / args.steps,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(g, opts_kw, args.substeps, args.seed, args.cpu_substeps)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -168,6 +168,20 @@ size_t chan_env_footprint_bytes(const chan_grid_t* grid, const chan_opts_t* opts
 /* Free the env and its device memory.  NULL is a no-op. */
 void chan_env_destroy(struct chan_env* env);
 
+/* Kernel timing (instrumentation for benchmarks).  chan_env_set_timing(env, 1)
+ * clears the counters and brackets every later kernel launch of the env with a
+ * pair of HIP events on the env's stream; (env, 0) stops recording.  The event
+ * records add a little queue work, so throughput runs leave timing off.
+ * chan_env_timing_read synchronises the stream and fills, for the first nclass
+ * kernel classes, the number of launches and the summed event time in ms since
+ * timing was enabled; it returns the number of classes (>= 0) or a negative
+ * code.  Classes (chan_kernel_class_name): 0 column_pass, 1 z_inverse_fft,
+ * 2 x_rows_fft_product, 3 z_forward_fft, 4 action_ingest, 5 outputs,
+ * 6 bookkeeping.  Errors: CHAN_EINVAL, CHAN_EDEVICE. */
+int chan_env_set_timing(struct chan_env* env, int32_t enable);
+int chan_env_timing_read(struct chan_env* env, int32_t nclass, int64_t* launches, double* ms);
+const char* chan_kernel_class_name(int32_t cls);
+
 /* Static string naming an error code. */
 const char* chan_strerror(int code);
 

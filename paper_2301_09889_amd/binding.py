@@ -22,7 +22,8 @@ CHAN_OBS_U, CHAN_OBS_V, CHAN_OBS_W = 1, 2, 4
 
 EXPORTED = ["chan_opts_default", "chan_env_create", "chan_env_reset", "chan_env_step",
             "chan_env_get_state", "chan_env_set_state", "chan_env_query",
-            "chan_env_footprint_bytes", "chan_env_destroy", "chan_strerror", "chan_last_error"]
+            "chan_env_footprint_bytes", "chan_env_destroy", "chan_strerror", "chan_last_error",
+            "chan_env_set_timing", "chan_env_timing_read", "chan_kernel_class_name"]
 
 
 class ChanGrid(ctypes.Structure):
@@ -100,6 +101,12 @@ def load_library():
     lib.chan_strerror.restype = ctypes.c_char_p
     lib.chan_last_error.argtypes = []
     lib.chan_last_error.restype = ctypes.c_char_p
+    lib.chan_env_set_timing.argtypes = [vp, ctypes.c_int32]
+    lib.chan_env_set_timing.restype = ctypes.c_int
+    lib.chan_env_timing_read.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int64), P(ctypes.c_double)]
+    lib.chan_env_timing_read.restype = ctypes.c_int
+    lib.chan_kernel_class_name.argtypes = [ctypes.c_int32]
+    lib.chan_kernel_class_name.restype = ctypes.c_char_p
     _LIB = lib
     return lib
 
@@ -158,6 +165,24 @@ def chan_env_query(h):
 def chan_env_footprint_bytes(grid, opts=None):
     return load_library().chan_env_footprint_bytes(ctypes.byref(grid),
                                                    ctypes.byref(opts) if opts is not None else None)
+
+
+def chan_env_set_timing(h, enable):
+    return load_library().chan_env_set_timing(h, int(bool(enable)))
+
+
+def chan_env_timing_read(h, nclass=16):
+    """Returns {class name: (launches, total ms)}."""
+    launches = (ctypes.c_int64 * nclass)()
+    ms = (ctypes.c_double * nclass)()
+    n = load_library().chan_env_timing_read(h, nclass, launches, ms)
+    if n < 0:
+        raise ChanError(n, "chan_env_timing_read")
+    return {chan_kernel_class_name(k): (launches[k], ms[k]) for k in range(min(n, nclass))}
+
+
+def chan_kernel_class_name(cls):
+    return load_library().chan_kernel_class_name(int(cls)).decode()
 
 
 def chan_env_destroy(h):

@@ -70,20 +70,37 @@ struct DeviceState {
   const cplx *twz, *twx, *twnx, *twnz;
 };
 
+// Kernel classes for the optional event timing.
+enum KernelClass : int {
+  KC_COLUMN = 0, KC_ZINV = 1, KC_XROW = 2, KC_ZFWD = 3, KC_INGEST = 4, KC_OUTPUT = 5, KC_BOOK = 6,
+  KC_COUNT = 7
+};
+
+// Brackets kernel launches with HIP events when enabled (instrumentation only).
+struct KernelTimer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;     // created lazily, reused
+  std::vector<int> cls;             // class of each recorded pair
+  size_t used = 0;                  // pairs recorded since the last read
+  hipError_t begin(int c, hipStream_t st);
+  hipError_t end(hipStream_t st);
+};
+
 struct StageConsts {
   double lam0, ab, gb, zb;      // 1/(b nu dt), a/b, g/(b nu), z/(b nu)
 };
 
-// Kernel launchers (kernels.hip).
-int launch_begin_step(const Dims& d, DeviceState& s, bool zero_vw_new, hipStream_t st);
-int launch_ingest(const Dims& d, DeviceState& s, const double* action, double clip, hipStream_t st);
-int launch_plane_pass(const Dims& d, DeviceState& s, hipStream_t st);
+// Kernel launchers (kernels.hip).  tm may be null.
+int launch_begin_step(const Dims& d, DeviceState& s, bool zero_vw_new, hipStream_t st, KernelTimer* tm);
+int launch_ingest(const Dims& d, DeviceState& s, const double* action, double clip, hipStream_t st,
+                  KernelTimer* tm);
+int launch_plane_pass(const Dims& d, DeviceState& s, hipStream_t st, KernelTimer* tm);
 int launch_column_pass(const Dims& d, DeviceState& s, const PhysParams& ph, int stage,
                        const StageConsts& sc, int wall_mode, double s_ramp, int js,
-                       double opp_alpha, bool accumulate_drag, hipStream_t st);
+                       double opp_alpha, bool accumulate_drag, hipStream_t st, KernelTimer* tm);
 int launch_finish_step(const Dims& d, DeviceState& s, bool copy_vw, double* drag, int nsub,
-                       hipStream_t st);
+                       hipStream_t st, KernelTimer* tm);
 int launch_outputs(const Dims& d, DeviceState& s, int js, uint32_t obs_mask, double* obs,
-                   double* tau_w, hipStream_t st);
+                   double* tau_w, hipStream_t st, KernelTimer* tm);
 
 }  // namespace chanenv

@@ -28,6 +28,9 @@ struct chan_env {
   double t;
   int64_t nstep;
   StageConsts sc[3];
+  KernelTimer timer;
+  double timing_ms[KC_COUNT];
+  int64_t timing_launches[KC_COUNT];
 };
 
 namespace {
@@ -158,8 +161,10 @@ int prime(chan_env* e) {
   // Fill the plane-pass inputs, the opposition wall velocity and the wall shear from
   // the state just loaded (column pass in reconstruct-only mode).
   StageConsts sc = e->sc[0];
-  if (launch_begin_step(e->d, e->s, false, e->stream)) return fail(CHAN_EDEVICE, "launch begin_step", hipGetLastError());
-  if (launch_column_pass(e->d, e->s, e->ph, -1, sc, WALL_RAMP, 0.0, e->js, e->opts.opp_alpha, false, e->stream))
+  if (launch_begin_step(e->d, e->s, false, e->stream, nullptr))
+    return fail(CHAN_EDEVICE, "launch begin_step", hipGetLastError());
+  if (launch_column_pass(e->d, e->s, e->ph, -1, sc, WALL_RAMP, 0.0, e->js, e->opts.opp_alpha, false, e->stream,
+                         nullptr))
     return fail(CHAN_EDEVICE, "launch column pass", hipGetLastError());
   HIPCHECK(hipStreamSynchronize(e->stream));
   return CHAN_OK;
@@ -395,6 +400,7 @@ int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_
 void chan_env_destroy(chan_env* e) {
   if (!e) return;
   if (e->stream) (void)hipStreamSynchronize(e->stream);
+  for (hipEvent_t ev : e->timer.pool) (void)hipEventDestroy(ev);
   if (e->dev_block) (void)hipFree(e->dev_block);
   if (e->host_status) (void)hipHostFree(e->host_status);
   delete e;
@@ -481,11 +487,12 @@ int chan_env_step(chan_env* e, const double* action, int32_t n_substeps, double*
   const Dims& d = e->d;
   const bool ext = e->opts.controller == CHAN_CTRL_EXTERNAL;
   hipStream_t st = e->stream;
+  KernelTimer* tm = e->timer.on ? &e->timer : nullptr;
   g_last_error.clear();
-  if (launch_begin_step(d, e->s, ext && action == nullptr, st))
+  if (launch_begin_step(d, e->s, ext && action == nullptr, st, tm))
     return fail(CHAN_EDEVICE, "launch begin_step", hipGetLastError());
   if (ext && action != nullptr)
-    if (launch_ingest(d, e->s, action, e->opts.clip, st))
+    if (launch_ingest(d, e->s, action, e->opts.clip, st, tm))
       return fail(CHAN_EDEVICE, "launch ingest", hipGetLastError());
   for (int m = 0; m < n_substeps; ++m) {
     for (int r = 0; r < 3; ++r) {
@@ -495,14 +502,14 @@ int chan_env_step(chan_env* e, const double* action, int32_t n_substeps, double*
         mode = WALL_RAMP;
         s = (e->opts.action_mode == CHAN_HOLD) ? 1.0 : (m + RK_C_END[r]) / (double)n_substeps;
       }
-      if (launch_plane_pass(d, e->s, st)) return fail(CHAN_EDEVICE, "launch plane pass", hipGetLastError());
-      if (launch_column_pass(d, e->s, e->ph, r, e->sc[r], mode, s, e->js, e->opts.opp_alpha, r == 2, st))
+      if (launch_plane_pass(d, e->s, st, tm)) return fail(CHAN_EDEVICE, "launch plane pass", hipGetLastError());
+      if (launch_column_pass(d, e->s, e->ph, r, e->sc[r], mode, s, e->js, e->opts.opp_alpha, r == 2, st, tm))
         return fail(CHAN_EDEVICE, "launch column pass", hipGetLastError());
     }
   }
-  if (launch_finish_step(d, e->s, ext, drag, n_substeps, st))
+  if (launch_finish_step(d, e->s, ext, drag, n_substeps, st, tm))
     return fail(CHAN_EDEVICE, "launch finish_step", hipGetLastError());
-  if (launch_outputs(d, e->s, e->js, e->opts.obs_mask, obs, tau_w, st))
+  if (launch_outputs(d, e->s, e->js, e->opts.obs_mask, obs, tau_w, st, tm))
     return fail(CHAN_EDEVICE, "launch outputs", hipGetLastError());
   HIPCHECK(hipMemcpyAsync(e->host_status, e->s.status, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));
@@ -515,6 +522,53 @@ int chan_env_step(chan_env* e, const double* action, int32_t n_substeps, double*
     return fail(CHAN_ENONFINITE, "non-finite state after the step");
   }
   return CHAN_OK;
+}
+
+static const char* const kClassNames[KC_COUNT] = {
+    "column_pass", "z_inverse_fft", "x_rows_fft_product", "z_forward_fft", "action_ingest", "outputs",
+    "bookkeeping"};
+
+const char* chan_kernel_class_name(int32_t cls) {
+  if (cls < 0 || cls >= KC_COUNT) return "";
+  return kClassNames[cls];
+}
+
+// Fold the recorded event pairs into the per-class accumulators.
+static int drain_timer(chan_env* e) {
+  KernelTimer& t = e->timer;
+  if (t.used == 0) return CHAN_OK;
+  HIPCHECK(hipStreamSynchronize(e->stream));
+  for (size_t k = 0; k < t.used; ++k) {
+    float ms = 0.0f;
+    HIPCHECK(hipEventElapsedTime(&ms, t.pool[2 * k], t.pool[2 * k + 1]));
+    e->timing_ms[t.cls[k]] += ms;
+    e->timing_launches[t.cls[k]] += 1;
+  }
+  t.used = 0;
+  return CHAN_OK;
+}
+
+int chan_env_set_timing(chan_env* e, int32_t enable) {
+  if (!e) return CHAN_EINVAL;
+  const int rc = drain_timer(e);
+  if (rc != CHAN_OK) return rc;
+  for (int k = 0; k < KC_COUNT; ++k) {
+    e->timing_ms[k] = 0.0;
+    e->timing_launches[k] = 0;
+  }
+  e->timer.on = enable != 0;
+  return CHAN_OK;
+}
+
+int chan_env_timing_read(chan_env* e, int32_t nclass, int64_t* launches, double* ms) {
+  if (!e || nclass < 0 || (nclass > 0 && (!launches || !ms))) return CHAN_EINVAL;
+  const int rc = drain_timer(e);
+  if (rc != CHAN_OK) return rc;
+  for (int k = 0; k < nclass && k < KC_COUNT; ++k) {
+    launches[k] = e->timing_launches[k];
+    ms[k] = e->timing_ms[k];
+  }
+  return KC_COUNT;
 }
 
 }  // extern "C"

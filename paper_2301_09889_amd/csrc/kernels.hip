@@ -29,6 +29,36 @@
 
 namespace chanenv {
 
+hipError_t KernelTimer::begin(int c, hipStream_t st) {
+  if (!on) return hipSuccess;
+  if (2 * (used + 1) > pool.size()) {
+    for (int k = 0; k < 2; ++k) {
+      hipEvent_t ev;
+      const hipError_t err = hipEventCreate(&ev);
+      if (err != hipSuccess) return err;
+      pool.push_back(ev);
+    }
+  }
+  if (cls.size() < used + 1) cls.resize(used + 1);
+  cls[used] = c;
+  return hipEventRecord(pool[2 * used], st);
+}
+
+hipError_t KernelTimer::end(hipStream_t st) {
+  if (!on) return hipSuccess;
+  const hipError_t err = hipEventRecord(pool[2 * used + 1], st);
+  ++used;
+  return err;
+}
+
+// Launch bracketed by the optional timer.
+#define TIMED_LAUNCH(tm, cls, st, ...)           \
+  do {                                           \
+    if (tm) (void)(tm)->begin((cls), (st));      \
+    hipLaunchKernelGGL(__VA_ARGS__);             \
+    if (tm) (void)(tm)->end((st));               \
+  } while (0)
+
 // ----------------------------------------------------------------------------
 // Complex helpers (double2 as re, im).  Named functions only: HIP's vector
 // operators on double2 are component-wise, not complex.
@@ -299,7 +329,7 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_zfwd(PlaneArgs A, int PB) {
   }
 }
 
-int launch_plane_pass(const Dims& d, DeviceState& s, hipStream_t st) {
+int launch_plane_pass(const Dims& d, DeviceState& s, hipStream_t st, KernelTimer* tm) {
   PlaneArgs A;
   A.ny = d.ny;
   A.nkx = d.nkx;
@@ -316,11 +346,11 @@ int launch_plane_pass(const Dims& d, DeviceState& s, hipStream_t st) {
   const int PB = d.nkx < 8 ? d.nkx : 8;
   const int nblk = (d.nkx + PB - 1) / PB;
   const size_t shz = (size_t)2 * PB * (d.mz + 1) * sizeof(cplx);
-  hipLaunchKernelGGL(k_zinv, dim3(nblk, 6, d.ny), dim3(PLANE_THREADS), shz, st, A, PB);
+  TIMED_LAUNCH(tm, KC_ZINV, st, k_zinv, dim3(nblk, 6, d.ny), dim3(PLANE_THREADS), shz, st, A, PB);
   const int RB = (d.mz % 4 == 0 && d.mx <= 96) ? 4 : 2;
   const size_t shx = (size_t)2 * 6 * (RB / 2) * (d.mx + 1) * sizeof(cplx);
-  hipLaunchKernelGGL(k_xrow, dim3(d.mz / RB, d.ny), dim3(PLANE_THREADS), shx, st, A, RB);
-  hipLaunchKernelGGL(k_zfwd, dim3(nblk, 3, d.ny), dim3(PLANE_THREADS), shz, st, A, PB);
+  TIMED_LAUNCH(tm, KC_XROW, st, k_xrow, dim3(d.mz / RB, d.ny), dim3(PLANE_THREADS), shx, st, A, RB);
+  TIMED_LAUNCH(tm, KC_ZFWD, st, k_zfwd, dim3(nblk, 3, d.ny), dim3(PLANE_THREADS), shz, st, A, PB);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -949,18 +979,18 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
 }
 
 template <int N>
-static int launch_col(const ColArgs& A, hipStream_t st) {
+static int launch_col(const ColArgs& A, hipStream_t st, KernelTimer* tm) {
   constexpr int WPB = wpb<N>();
   const int blocks = (A.ncol + WPB - 1) / WPB;
   const size_t shm = (size_t)WPB * CP<N>::WAVE_DOUBLES * sizeof(double);
-  hipLaunchKernelGGL(k_column<N>, dim3(blocks), dim3(64 * WPB), shm, st, A);
+  TIMED_LAUNCH(tm, KC_COLUMN, st, k_column<N>, dim3(blocks), dim3(64 * WPB), shm, st, A);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 
 int launch_column_pass(const Dims& d, DeviceState& s, const PhysParams& ph, int stage,
                        const StageConsts& sc, int wall_mode, double s_ramp, int js,
-                       double opp_alpha, bool accumulate_drag, hipStream_t st) {
+                       double opp_alpha, bool accumulate_drag, hipStream_t st, KernelTimer* tm) {
   ColArgs A;
   A.nkx = d.nkx;
   A.nz = d.nz;
@@ -1003,11 +1033,11 @@ int launch_column_pass(const Dims& d, DeviceState& s, const PhysParams& ph, int 
   A.drag_acc = s.drag_acc;
   A.status = s.status;
   switch (d.N) {
-    case 16: return launch_col<16>(A, st);
-    case 32: return launch_col<32>(A, st);
-    case 64: return launch_col<64>(A, st);
-    case 96: return launch_col<96>(A, st);
-    case 128: return launch_col<128>(A, st);
+    case 16: return launch_col<16>(A, st, tm);
+    case 32: return launch_col<32>(A, st, tm);
+    case 64: return launch_col<64>(A, st, tm);
+    case 96: return launch_col<96>(A, st, tm);
+    case 128: return launch_col<128>(A, st, tm);
     default: return -1;
   }
 }
@@ -1026,8 +1056,8 @@ __global__ void k_begin_step(int* status, double* drag_acc, cplx* vw_new, int nc
   }
 }
 
-int launch_begin_step(const Dims& d, DeviceState& s, bool zero_vw_new, hipStream_t st) {
-  hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(256), 0, st, s.status, s.drag_acc, s.vw_new, d.ncol,
+int launch_begin_step(const Dims& d, DeviceState& s, bool zero_vw_new, hipStream_t st, KernelTimer* tm) {
+  TIMED_LAUNCH(tm, KC_BOOK, st, k_begin_step, dim3(1), dim3(256), 0, st, s.status, s.drag_acc, s.vw_new, d.ncol,
                      zero_vw_new ? 1 : 0);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -1077,10 +1107,11 @@ __global__ void k_ingest_cols(const cplx* __restrict__ tmp, int nx, int nz, int 
   }
 }
 
-int launch_ingest(const Dims& d, DeviceState& s, const double* action, double clip, hipStream_t st) {
-  hipLaunchKernelGGL(k_ingest_rows, dim3(d.nz), dim3(64), (size_t)2 * d.nx * sizeof(cplx), st, action,
+int launch_ingest(const Dims& d, DeviceState& s, const double* action, double clip, hipStream_t st,
+                  KernelTimer* tm) {
+  TIMED_LAUNCH(tm, KC_INGEST, st, k_ingest_rows, dim3(d.nz), dim3(64), (size_t)2 * d.nx * sizeof(cplx), st, action,
                      d.nx, d.nkx, clip, s.twnx, s.tmp2d, s.status);
-  hipLaunchKernelGGL(k_ingest_cols, dim3(d.nkx), dim3(64), (size_t)2 * d.nz * sizeof(cplx), st, s.tmp2d,
+  TIMED_LAUNCH(tm, KC_INGEST, st, k_ingest_cols, dim3(d.nkx), dim3(64), (size_t)2 * d.nz * sizeof(cplx), st, s.tmp2d,
                      d.nx, d.nz, d.nkx, s.twnz, s.vw_new, s.status);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -1126,7 +1157,7 @@ __global__ void k_out_rows(const cplx* __restrict__ tmp, int nx, int nz, int nkx
 }
 
 int launch_outputs(const Dims& d, DeviceState& s, int js, uint32_t obs_mask, double* obs,
-                   double* tau_w, hipStream_t st) {
+                   double* tau_w, hipStream_t st, KernelTimer* tm) {
   const size_t plane = (size_t)d.ny * d.nkx * d.nz;
   const size_t shz = (size_t)2 * d.nz * sizeof(cplx), shx = (size_t)2 * d.nx * sizeof(cplx);
   if (obs) {
@@ -1134,17 +1165,17 @@ int launch_outputs(const Dims& d, DeviceState& s, int js, uint32_t obs_mask, dou
     for (int f = 0; f < 3; ++f) {
       if (!(obs_mask & (1u << f))) continue;
       const cplx* src = s.F6 + (size_t)f * plane + (size_t)js * d.nkx * d.nz;
-      hipLaunchKernelGGL(k_out_cols, dim3(d.nkx, 1), dim3(64), shz, st, src, (size_t)0, d.nz, d.nkx, s.twnz,
+      TIMED_LAUNCH(tm, KC_OUTPUT, st, k_out_cols, dim3(d.nkx, 1), dim3(64), shz, st, src, (size_t)0, d.nz, d.nkx, s.twnz,
                          s.tmp2d);
-      hipLaunchKernelGGL(k_out_rows, dim3(d.nz, 1), dim3(64), shx, st, s.tmp2d, d.nx, d.nz, d.nkx, s.twnx,
+      TIMED_LAUNCH(tm, KC_OUTPUT, st, k_out_rows, dim3(d.nz, 1), dim3(64), shx, st, s.tmp2d, d.nx, d.nz, d.nkx, s.twnx,
                          obs + (size_t)slot * d.nz * d.nx, (size_t)0);
       ++slot;
     }
   }
   if (tau_w) {
-    hipLaunchKernelGGL(k_out_cols, dim3(d.nkx, 1), dim3(64), shz, st, s.tauw, (size_t)0, d.nz, d.nkx, s.twnz,
+    TIMED_LAUNCH(tm, KC_OUTPUT, st, k_out_cols, dim3(d.nkx, 1), dim3(64), shz, st, s.tauw, (size_t)0, d.nz, d.nkx, s.twnz,
                        s.tmp2d);
-    hipLaunchKernelGGL(k_out_rows, dim3(d.nz, 1), dim3(64), shx, st, s.tmp2d, d.nx, d.nz, d.nkx, s.twnx, tau_w,
+    TIMED_LAUNCH(tm, KC_OUTPUT, st, k_out_rows, dim3(d.nz, 1), dim3(64), shx, st, s.tmp2d, d.nx, d.nz, d.nkx, s.twnx, tau_w,
                        (size_t)0);
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -1164,8 +1195,8 @@ __global__ void k_finish_step(const int* status, const double* drag_acc, double*
 }
 
 int launch_finish_step(const Dims& d, DeviceState& s, bool copy_vw, double* drag, int nsub,
-                       hipStream_t st) {
-  hipLaunchKernelGGL(k_finish_step, dim3(1), dim3(256), 0, st, s.status, s.drag_acc, drag, nsub, s.vw_new,
+                       hipStream_t st, KernelTimer* tm) {
+  TIMED_LAUNCH(tm, KC_BOOK, st, k_finish_step, dim3(1), dim3(256), 0, st, s.status, s.drag_acc, drag, nsub, s.vw_new,
                      s.vw_old, d.ncol, copy_vw ? 1 : 0);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

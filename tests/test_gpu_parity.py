@@ -80,8 +80,9 @@ def test_external_actions_small_grids(shape, mode, forcing, mask):
 def test_larger_channel_bench_configuration():
     """Larger channel at full size (64 x 65 x 64), Reichardt mean + seeded
     perturbation, one env step of 10 time steps with a seeded Gaussian action
-    (sigma = 0.1 u_tau): the launch configuration the benchmark times."""
-    cfg = larger_channel()
+    (sigma = 0.1 u_tau) held over the env step: the launch configuration the
+    benchmark times."""
+    cfg = larger_channel(action_mode=ch.HOLD)
     run_pair(cfg, 0, [gaussian_action(1000, 64, 64)], 10, 1e-11)
 
 
