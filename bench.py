@@ -89,6 +89,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-substeps", type=int, default=4, help="time steps in the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the benchmark, run a plain 256 MiB device copy (for scaling the HBM "
+                         "byte counters of a profiler run)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -181,6 +184,13 @@ def main():
         "kernels": kernels,
         "timing_pass_ms_per_step": 1e3 * elapsed_timed / args.steps,
     }
+    if args.copy_probe:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes_each_way"] = src.numel() * 8
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, opts_kw, args.substeps, args.seed, args.cpu_substeps)
     else:

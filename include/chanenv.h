@@ -177,7 +177,8 @@ void chan_env_destroy(struct chan_env* env);
  * timing was enabled; it returns the number of classes (>= 0) or a negative
  * code.  Classes (chan_kernel_class_name): 0 column_pass, 1 z_inverse_fft,
  * 2 x_rows_fft_product, 3 z_forward_fft, 4 action_ingest, 5 outputs,
- * 6 bookkeeping.  Errors: CHAN_EINVAL, CHAN_EDEVICE. */
+ * 6 bookkeeping, 7 column_reconstruct (the reconstruct-only column pass that ends
+ * every env step).  Errors: CHAN_EINVAL, CHAN_EDEVICE. */
 int chan_env_set_timing(struct chan_env* env, int32_t enable);
 int chan_env_timing_read(struct chan_env* env, int32_t nclass, int64_t* launches, double* ms);
 const char* chan_kernel_class_name(int32_t cls);

@@ -12,7 +12,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I" + os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function"]
-SOURCES = [("kernels.hip", []), ("env.cpp", []), ("precompute.cpp", []),
+SOURCES = [("kernels.hip", []), ("plane_pass.hip", []), ("column_pass.hip", []), ("env.cpp", []), ("precompute.cpp", []),
            ("initial.cpp", ["-ffp-contract=off"])]
 
 

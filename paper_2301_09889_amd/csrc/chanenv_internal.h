@@ -32,8 +32,17 @@ struct Dims {
 
 // Offsets (in doubles) of each table inside the single device table buffer.
 struct TableLayout {
-  size_t cosk, rc, optab, vt, minv, up, inv_int_up, twz, twx, twnx, twnz, alpha, beta, total;
+  size_t cosk, rc, optab, vt, minv, up, inv_int_up, twz, twx, twnx, twnz, alpha, beta;
+  // parity-major copies for the column kernel with N <= 64 (one lane per coefficient:
+  // even n = 2l in lanes l < 32, odd n = 2i + 1 in lanes 32 + i, n = N as a 65th "tail" entry)
+  size_t kfwd, kinv, rc_pm, intw_pm, op_pm, vt_pm, up_pm;
+  size_t total;
 };
+
+// Parity-major record of one tau operator: w, u, f, F (65 entries each: 64 lanes + tail),
+// then 1/sum F for the even and the odd system.
+constexpr int PM_ENTRIES = 65;
+constexpr int PM_OPSZ = 4 * PM_ENTRIES + 4;
 
 // Host precompute of every operator table, in FP64.
 struct HostTables {
@@ -67,13 +76,14 @@ struct DeviceState {
   int *status;                  // [1]
   // views into tab
   const double *cosk, *rc, *optab, *vt, *minv, *up, *inv_int_up, *alpha, *beta;
+  const double *kfwd, *kinv, *rc_pm, *intw_pm, *op_pm, *vt_pm, *up_pm;
   const cplx *twz, *twx, *twnx, *twnz;
 };
 
 // Kernel classes for the optional event timing.
 enum KernelClass : int {
   KC_COLUMN = 0, KC_ZINV = 1, KC_XROW = 2, KC_ZFWD = 3, KC_INGEST = 4, KC_OUTPUT = 5, KC_BOOK = 6,
-  KC_COUNT = 7
+  KC_RECON = 7, KC_COUNT = 8
 };
 
 // Brackets kernel launches with HIP events when enabled (instrumentation only).
@@ -95,9 +105,16 @@ int launch_begin_step(const Dims& d, DeviceState& s, bool zero_vw_new, hipStream
 int launch_ingest(const Dims& d, DeviceState& s, const double* action, double clip, hipStream_t st,
                   KernelTimer* tm);
 int launch_plane_pass(const Dims& d, DeviceState& s, hipStream_t st, KernelTimer* tm);
+// Column pass; stage -1 only reconstructs the plane-pass input from the state.  With
+// recon false the pass stops after the solve (the caller reconstructs separately).
+int launch_column_pass_pm(const Dims& d, DeviceState& s, const PhysParams& ph, int stage,
+                          const StageConsts& sc, int wall_mode, double s_ramp, int js,
+                          double opp_alpha, bool accumulate_drag, bool recon, hipStream_t st,
+                          KernelTimer* tm);
 int launch_column_pass(const Dims& d, DeviceState& s, const PhysParams& ph, int stage,
                        const StageConsts& sc, int wall_mode, double s_ramp, int js,
-                       double opp_alpha, bool accumulate_drag, hipStream_t st, KernelTimer* tm);
+                       double opp_alpha, bool accumulate_drag, bool recon, hipStream_t st,
+                       KernelTimer* tm);
 int launch_finish_step(const Dims& d, DeviceState& s, bool copy_vw, double* drag, int nsub,
                        hipStream_t st, KernelTimer* tm);
 int launch_outputs(const Dims& d, DeviceState& s, int js, uint32_t obs_mask, double* obs,

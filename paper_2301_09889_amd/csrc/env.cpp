@@ -2,6 +2,7 @@
 // loop and the state exchange.  All numerical work of a step is queued as HIP
 // kernels (kernels.hip); the host only sequences launches.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -29,6 +30,7 @@ struct chan_env {
   int64_t nstep;
   StageConsts sc[3];
   KernelTimer timer;
+  bool force_generic;   // CHANENV_GENERIC_COLUMN=1: use the general column kernel for every N
   double timing_ms[KC_COUNT];
   int64_t timing_launches[KC_COUNT];
 };
@@ -135,9 +137,14 @@ size_t table_doubles(const Dims& d) {
   // mirrors precompute_tables' layout (with per-table rounding to even counts)
   auto r2 = [](size_t n) { return (n + 1) & ~size_t(1); };
   const int NY = d.ny, H = d.N / 2;
-  return r2((size_t)(H + 1) * NY) + r2((size_t)3 * NY) + r2((size_t)d.ncol * NOPS * 2 * d.opsz) +
-         r2((size_t)d.ncol * 3 * NY) + r2((size_t)d.ncol * 12) + r2((size_t)3 * NY) + r2(4) + r2(2 * d.mz) +
-         r2(2 * d.mx) + r2(2 * d.nx) + r2(2 * d.nz) + r2(d.nkx) + r2(d.nz);
+  const bool pm = d.N <= 64;
+  size_t t = r2((size_t)(H + 1) * NY) + r2((size_t)3 * NY) + r2((size_t)d.ncol * NOPS * 2 * d.opsz) +
+             r2((size_t)d.ncol * 3 * NY) + r2((size_t)d.ncol * 12) + r2((size_t)3 * NY) + r2(4) + r2(2 * d.mz) +
+             r2(2 * d.mx) + r2(2 * d.nx) + r2(2 * d.nz) + r2(d.nkx) + r2(d.nz);
+  if (pm)
+    t += 2 * r2((size_t)(H + 1) * 64) + r2((size_t)3 * PM_ENTRIES) + r2(PM_ENTRIES) +
+         r2((size_t)d.ncol * NOPS * PM_OPSZ) + r2((size_t)d.ncol * 3 * PM_ENTRIES) + r2((size_t)3 * PM_ENTRIES);
+  return t;
 }
 
 thread_local std::string g_last_error;
@@ -157,14 +164,23 @@ int fail(int code, const char* what, hipError_t err = hipSuccess) {
     if (err_ != hipSuccess) return fail(CHAN_EDEVICE, #x, err_); \
   } while (0)
 
+// The column pass: the parity-major kernel for N <= 64, the general one above.
+int column_pass(chan_env* e, int stage, const StageConsts& sc, int mode, double s_ramp, bool drag, bool recon,
+                KernelTimer* tm) {
+  if (e->d.N <= 64 && !e->force_generic)
+    return launch_column_pass_pm(e->d, e->s, e->ph, stage, sc, mode, s_ramp, e->js, e->opts.opp_alpha, drag,
+                                 recon, e->stream, tm);
+  return launch_column_pass(e->d, e->s, e->ph, stage, sc, mode, s_ramp, e->js, e->opts.opp_alpha, drag, recon,
+                            e->stream, tm);
+}
+
 int prime(chan_env* e) {
   // Fill the plane-pass inputs, the opposition wall velocity and the wall shear from
   // the state just loaded (column pass in reconstruct-only mode).
   StageConsts sc = e->sc[0];
   if (launch_begin_step(e->d, e->s, false, e->stream, nullptr))
     return fail(CHAN_EDEVICE, "launch begin_step", hipGetLastError());
-  if (launch_column_pass(e->d, e->s, e->ph, -1, sc, WALL_RAMP, 0.0, e->js, e->opts.opp_alpha, false, e->stream,
-                         nullptr))
+  if (column_pass(e, -1, sc, WALL_RAMP, 0.0, false, true, nullptr))
     return fail(CHAN_EDEVICE, "launch column pass", hipGetLastError());
   HIPCHECK(hipStreamSynchronize(e->stream));
   return CHAN_OK;
@@ -310,6 +326,10 @@ int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_
   e->stream = (hipStream_t)hip_stream;
   e->have_flow = false;
   e->poisoned = false;
+  {
+    const char* g = std::getenv("CHANENV_GENERIC_COLUMN");
+    e->force_generic = g && g[0] == '1';
+  }
   e->t = 0.0;
   e->nstep = 0;
   for (int r = 0; r < 3; ++r) {
@@ -377,6 +397,13 @@ int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_
   s.twx = (const cplx*)(s.tab + L.twx);
   s.twnx = (const cplx*)(s.tab + L.twnx);
   s.twnz = (const cplx*)(s.tab + L.twnz);
+  s.kfwd = s.tab + L.kfwd;
+  s.kinv = s.tab + L.kinv;
+  s.rc_pm = s.tab + L.rc_pm;
+  s.intw_pm = s.tab + L.intw_pm;
+  s.op_pm = s.tab + L.op_pm;
+  s.vt_pm = s.tab + L.vt_pm;
+  s.up_pm = s.tab + L.up_pm;
   {
     hipError_t err = hipMemsetAsync(e->dev_block, 0, z.total, e->stream);
     const char* what = "hipMemsetAsync";
@@ -503,10 +530,16 @@ int chan_env_step(chan_env* e, const double* action, int32_t n_substeps, double*
         s = (e->opts.action_mode == CHAN_HOLD) ? 1.0 : (m + RK_C_END[r]) / (double)n_substeps;
       }
       if (launch_plane_pass(d, e->s, st, tm)) return fail(CHAN_EDEVICE, "launch plane pass", hipGetLastError());
-      if (launch_column_pass(d, e->s, e->ph, r, e->sc[r], mode, s, e->js, e->opts.opp_alpha, r == 2, st, tm))
+      // The last stage of the env step leaves the reconstruction to the reconstruct-only
+      // pass below, so that the plane-pass input at an env-step boundary is always made
+      // by the same code path as after set_state (bitwise-identical resume).
+      const bool last = (m == n_substeps - 1) && (r == 2);
+      if (column_pass(e, r, e->sc[r], mode, s, r == 2, !last, tm))
         return fail(CHAN_EDEVICE, "launch column pass", hipGetLastError());
     }
   }
+  if (column_pass(e, -1, e->sc[0], WALL_RAMP, 0.0, false, true, tm))
+    return fail(CHAN_EDEVICE, "launch column pass", hipGetLastError());
   if (launch_finish_step(d, e->s, ext, drag, n_substeps, st, tm))
     return fail(CHAN_EDEVICE, "launch finish_step", hipGetLastError());
   if (launch_outputs(d, e->s, e->js, e->opts.obs_mask, obs, tau_w, st, tm))
@@ -526,7 +559,7 @@ int chan_env_step(chan_env* e, const double* action, int32_t n_substeps, double*
 
 static const char* const kClassNames[KC_COUNT] = {
     "column_pass", "z_inverse_fft", "x_rows_fft_product", "z_forward_fft", "action_ingest", "outputs",
-    "bookkeeping"};
+    "bookkeeping", "column_reconstruct"};
 
 const char* chan_kernel_class_name(int32_t cls) {
   if (cls < 0 || cls >= KC_COUNT) return "";

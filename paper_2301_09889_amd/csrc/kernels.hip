@@ -1,15 +1,8 @@
 // FP64 HIP kernels of the channel-flow DNS step, written for gfx950 (CDNA4).
 //
-// One time step is three RK3/CN stages; each stage is a plane pass followed by a
-// column pass:
+// One time step is three RK3/CN stages; each stage is a plane pass (plane_pass.hip)
+// followed by a column pass:
 //
-//   plane pass   the six velocity/vorticity fields at every Chebyshev node go to the
-//                3/2-padded (x, z) grid, u x omega is formed pointwise and the three
-//                products come back to the stored Fourier modes.  Three kernels:
-//                k_zinv  (inverse FFT along z per (node, p) pencil, with padding),
-//                k_xrow  (inverse real FFT along x, product, forward real FFT, per
-//                         pair of padded z rows),
-//                k_zfwd  (forward FFT along z, truncation, 1/(M_x M_z), Hermitian fix).
 //   column pass  one wavefront per wavenumber pair (alpha, beta) owns the whole
 //                wall-normal column: forward DCT-I of H, the explicit terms h_v, h_g,
 //                the RK3/CN right-hand sides, the Chebyshev-tau solves (quasi-
@@ -25,7 +18,7 @@
 // Everything is FP64 (the method is chaotic and the tau systems are stiff); nothing is
 // a dense contraction, so there is no MFMA here.
 
-#include "chanenv_internal.h"
+#include "device_common.h"
 
 namespace chanenv {
 
@@ -58,42 +51,6 @@ hipError_t KernelTimer::end(hipStream_t st) {
     hipLaunchKernelGGL(__VA_ARGS__);             \
     if (tm) (void)(tm)->end((st));               \
   } while (0)
-
-// ----------------------------------------------------------------------------
-// Complex helpers (double2 as re, im).  Named functions only: HIP's vector
-// operators on double2 are component-wise, not complex.
-// ----------------------------------------------------------------------------
-__device__ __forceinline__ cplx cz() { return make_double2(0.0, 0.0); }
-__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ cplx csub(cplx a, cplx b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ cplx cscale(cplx a, double s) { return make_double2(a.x * s, a.y * s); }
-__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ cplx cconj(cplx a) { return make_double2(a.x, -a.y); }
-// i * a
-__device__ __forceinline__ cplx cmuli(cplx a) { return make_double2(-a.y, a.x); }
-// acc + s * a
-__device__ __forceinline__ cplx caxpy(cplx acc, double s, cplx a) {
-  return make_double2(fma(s, a.x, acc.x), fma(s, a.y, acc.y));
-}
-
-// Wave-scope barrier for LDS data exchanged between lanes of one wavefront.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Butterfly sum over the 64 lanes; every lane receives the bitwise-same total.
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-__device__ __forceinline__ cplx wave_sum(cplx v) {
-  return make_double2(wave_sum(v.x), wave_sum(v.y));
-}
 
 // ----------------------------------------------------------------------------
 // Batched Stockham FFT in LDS (radix 3, 4, 2), used by all (x, z) transforms.
@@ -174,187 +131,6 @@ __device__ cplx* fft_batch(cplx* src, cplx* dst, int L, int nb_seq, int ld,
 }
 
 // ----------------------------------------------------------------------------
-// Plane pass.
-// Layouts (complex):  F6[f][j][p][q], Z6[f][j][zz][p], W3[g][j][zz][p], H3[g][j][p][q]
-// with f in (u, v, w, omega_x, omega_y, omega_z), g in (H1, H2, H3), j the node,
-// zz < M_z the padded physical z index, p < N_x/2, q < N_z.
-// ----------------------------------------------------------------------------
-struct PlaneArgs {
-  int ny, nkx, nz, mx, mz;
-  const cplx* F6;
-  cplx* Z6;
-  cplx* W3;
-  cplx* H3;
-  const cplx* twz;
-  const cplx* twx;
-  const int* status;
-};
-
-constexpr int PLANE_THREADS = 256;
-
-// Inverse FFT along z of PB consecutive p pencils of one field at one node.
-__global__ __launch_bounds__(PLANE_THREADS) void k_zinv(PlaneArgs A, int PB) {
-  extern __shared__ double dyn_lds[];
-  cplx* sh = reinterpret_cast<cplx*>(dyn_lds);
-  if (*A.status & STATUS_BAD_ACTION) return;
-  const int p0 = blockIdx.x * PB, f = blockIdx.y, j = blockIdx.z;
-  const int np = min(PB, A.nkx - p0);
-  const int LP = A.mz + 1;
-  cplx* a = sh;
-  cplx* b = sh + PB * LP;
-  for (int t = threadIdx.x; t < np * LP; t += blockDim.x) a[t] = cz();
-  __syncthreads();
-  const size_t fj = (size_t)f * A.ny + j;
-  const cplx* src = A.F6 + fj * A.nkx * A.nz + (size_t)p0 * A.nz;
-  const int h = A.nz / 2;
-  for (int t = threadIdx.x; t < np * A.nz; t += blockDim.x) {
-    const int pp = t / A.nz, q = t - pp * A.nz;
-    if (q == h) continue;
-    const int zz = (q < h) ? q : q - A.nz + A.mz;
-    a[pp * LP + zz] = src[t];
-  }
-  __syncthreads();
-  cplx* r = fft_batch(a, b, A.mz, np, LP, A.twz, true);
-  cplx* dst = A.Z6 + fj * A.mz * A.nkx + p0;
-  for (int t = threadIdx.x; t < A.mz * np; t += blockDim.x) {
-    const int zz = t / np, pp = t - zz * np;
-    dst[(size_t)zz * A.nkx + pp] = r[pp * LP + zz];
-  }
-}
-
-// Rows of the padded plane, RB rows (RB/2 packed pairs) per block: inverse real FFTs
-// of the six fields along x, H = u x omega, forward real FFTs of the three products.
-__global__ __launch_bounds__(PLANE_THREADS) void k_xrow(PlaneArgs A, int RB) {
-  extern __shared__ double dyn_lds[];
-  cplx* sh = reinterpret_cast<cplx*>(dyn_lds);
-  if (*A.status & STATUS_BAD_ACTION) return;
-  const int z0 = blockIdx.x * RB, j = blockIdx.y;
-  const int npair = RB / 2;
-  const int LX = A.mx + 1;
-  const int nseq = 6 * npair;
-  cplx* a = sh;
-  cplx* b = sh + nseq * LX;
-  const int nkx = A.nkx, mx = A.mx;
-  // Packed spectra Y = X(row 2pr) + i X(row 2pr+1) with the Hermitian extension along x.
-  for (int t = threadIdx.x; t < nseq * mx; t += blockDim.x) {
-    const int sidx = t / mx, k = t - sidx * mx;
-    const int f = sidx / npair, pr = sidx - f * npair;
-    const size_t rowa = (((size_t)f * A.ny + j) * A.mz + (z0 + 2 * pr)) * nkx;
-    const size_t rowb = rowa + nkx;
-    cplx xa = cz(), xb = cz();
-    if (k < nkx) {
-      xa = A.Z6[rowa + k];
-      xb = A.Z6[rowb + k];
-      if (k == 0) {
-        xa.y = 0.0;
-        xb.y = 0.0;
-      }
-    } else if (k > mx - nkx) {
-      xa = cconj(A.Z6[rowa + (mx - k)]);
-      xb = cconj(A.Z6[rowb + (mx - k)]);
-    }
-    a[sidx * LX + k] = make_double2(xa.x - xb.y, xa.y + xb.x);
-  }
-  __syncthreads();
-  cplx* phys = fft_batch(a, b, mx, nseq, LX, A.twx, true);
-  cplx* out = (phys == a) ? b : a;
-  // Products on the padded grid; the three products of a row pair packed the same way.
-  for (int t = threadIdx.x; t < npair * mx; t += blockDim.x) {
-    const int pr = t / mx, x = t - pr * mx;
-    const cplx U = phys[(0 * npair + pr) * LX + x];
-    const cplx V = phys[(1 * npair + pr) * LX + x];
-    const cplx W = phys[(2 * npair + pr) * LX + x];
-    const cplx OX = phys[(3 * npair + pr) * LX + x];
-    const cplx OY = phys[(4 * npair + pr) * LX + x];
-    const cplx OZ = phys[(5 * npair + pr) * LX + x];
-    // .x = row 2pr, .y = row 2pr+1
-    const cplx H1 = make_double2(V.x * OZ.x - W.x * OY.x, V.y * OZ.y - W.y * OY.y);
-    const cplx H2 = make_double2(W.x * OX.x - U.x * OZ.x, W.y * OX.y - U.y * OZ.y);
-    const cplx H3 = make_double2(U.x * OY.x - V.x * OX.x, U.y * OY.y - V.y * OX.y);
-    out[(0 * npair + pr) * LX + x] = H1;
-    out[(1 * npair + pr) * LX + x] = H2;
-    out[(2 * npair + pr) * LX + x] = H3;
-  }
-  __syncthreads();
-  cplx* spec = fft_batch(out, phys, mx, 3 * npair, LX, A.twx, false);
-  for (int t = threadIdx.x; t < 3 * npair * nkx; t += blockDim.x) {
-    const int sidx = t / nkx, k = t - sidx * nkx;
-    const int g = sidx / npair, pr = sidx - g * npair;
-    const cplx Yk = spec[sidx * LX + k];
-    const cplx Ym = cconj(spec[sidx * LX + ((mx - k) % mx)]);
-    const cplx Xa = make_double2(0.5 * (Yk.x + Ym.x), 0.5 * (Yk.y + Ym.y));
-    // (Yk - Ym) / (2 i)
-    const cplx Xb = make_double2(0.5 * (Yk.y - Ym.y), -0.5 * (Yk.x - Ym.x));
-    const size_t rowa = (((size_t)g * A.ny + j) * A.mz + (z0 + 2 * pr)) * nkx;
-    A.W3[rowa + k] = Xa;
-    A.W3[rowa + nkx + k] = Xb;
-  }
-}
-
-// Forward FFT along z, truncation to the stored q, 1/(M_x M_z), Hermitian fix of p = 0.
-__global__ __launch_bounds__(PLANE_THREADS) void k_zfwd(PlaneArgs A, int PB) {
-  extern __shared__ double dyn_lds[];
-  cplx* sh = reinterpret_cast<cplx*>(dyn_lds);
-  if (*A.status & STATUS_BAD_ACTION) return;
-  const int p0 = blockIdx.x * PB, g = blockIdx.y, j = blockIdx.z;
-  const int np = min(PB, A.nkx - p0);
-  const int LP = A.mz + 1;
-  cplx* a = sh;
-  cplx* b = sh + PB * LP;
-  const size_t gj = (size_t)g * A.ny + j;
-  const cplx* src = A.W3 + gj * A.mz * A.nkx + p0;
-  for (int t = threadIdx.x; t < A.mz * np; t += blockDim.x) {
-    const int zz = t / np, pp = t - zz * np;
-    a[pp * LP + zz] = src[(size_t)zz * A.nkx + pp];
-  }
-  __syncthreads();
-  cplx* r = fft_batch(a, b, A.mz, np, LP, A.twz, false);
-  const double scale = 1.0 / ((double)A.mx * (double)A.mz);
-  const int h = A.nz / 2;
-  cplx* dst = A.H3 + gj * A.nkx * A.nz + (size_t)p0 * A.nz;
-  for (int t = threadIdx.x; t < np * A.nz; t += blockDim.x) {
-    const int pp = t / A.nz, q = t - pp * A.nz;
-    cplx v = cz();
-    if (q != h) {
-      if (p0 + pp == 0 && q > h) {
-        v = cconj(r[pp * LP + (A.nz - q)]);
-      } else {
-        const int zz = (q < h) ? q : q - A.nz + A.mz;
-        v = r[pp * LP + zz];
-      }
-      v = cscale(v, scale);
-      if (p0 + pp == 0 && q == 0) v.y = 0.0;
-    }
-    dst[t] = v;
-  }
-}
-
-int launch_plane_pass(const Dims& d, DeviceState& s, hipStream_t st, KernelTimer* tm) {
-  PlaneArgs A;
-  A.ny = d.ny;
-  A.nkx = d.nkx;
-  A.nz = d.nz;
-  A.mx = d.mx;
-  A.mz = d.mz;
-  A.F6 = s.F6;
-  A.Z6 = s.Z6;
-  A.W3 = s.W3;
-  A.H3 = s.H3;
-  A.twz = s.twz;
-  A.twx = s.twx;
-  A.status = s.status;
-  const int PB = d.nkx < 8 ? d.nkx : 8;
-  const int nblk = (d.nkx + PB - 1) / PB;
-  const size_t shz = (size_t)2 * PB * (d.mz + 1) * sizeof(cplx);
-  TIMED_LAUNCH(tm, KC_ZINV, st, k_zinv, dim3(nblk, 6, d.ny), dim3(PLANE_THREADS), shz, st, A, PB);
-  const int RB = (d.mz % 4 == 0 && d.mx <= 96) ? 4 : 2;
-  const size_t shx = (size_t)2 * 6 * (RB / 2) * (d.mx + 1) * sizeof(cplx);
-  TIMED_LAUNCH(tm, KC_XROW, st, k_xrow, dim3(d.mz / RB, d.ny), dim3(PLANE_THREADS), shx, st, A, RB);
-  TIMED_LAUNCH(tm, KC_ZFWD, st, k_zfwd, dim3(nblk, 3, d.ny), dim3(PLANE_THREADS), shz, st, A, PB);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
-}
-
-// ----------------------------------------------------------------------------
 // Column pass.
 // ----------------------------------------------------------------------------
 template <int N>
@@ -380,6 +156,7 @@ struct ColArgs {
   double lam0, ab, gb, zb;
   double nu, opp_alpha, ub2, px;
   int forcing, js, accumulate_drag;
+  int recon;            // 0: skip the reconstruction for the next stage
   size_t plane;         // elements per field in F6 / H3 (ny * nkx * nz)
   cplx *vS, *oS, *hist;
   double *meanS, *meanH;
@@ -870,6 +647,7 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
   }
 
   // ---------------- reconstruction and inverse DCT for the next stage ----------------
+  if (!A.recon) return;
   const bool want_end = (A.stage == 2 || A.stage < 0);
   cplx tau_hat = cz();
   if (!mean) {
@@ -983,15 +761,16 @@ static int launch_col(const ColArgs& A, hipStream_t st, KernelTimer* tm) {
   constexpr int WPB = wpb<N>();
   const int blocks = (A.ncol + WPB - 1) / WPB;
   const size_t shm = (size_t)WPB * CP<N>::WAVE_DOUBLES * sizeof(double);
-  TIMED_LAUNCH(tm, KC_COLUMN, st, k_column<N>, dim3(blocks), dim3(64 * WPB), shm, st, A);
+  TIMED_LAUNCH(tm, A.stage < 0 ? KC_RECON : KC_COLUMN, st, k_column<N>, dim3(blocks), dim3(64 * WPB), shm, st, A);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 
 int launch_column_pass(const Dims& d, DeviceState& s, const PhysParams& ph, int stage,
                        const StageConsts& sc, int wall_mode, double s_ramp, int js,
-                       double opp_alpha, bool accumulate_drag, hipStream_t st, KernelTimer* tm) {
+                       double opp_alpha, bool accumulate_drag, bool recon, hipStream_t st, KernelTimer* tm) {
   ColArgs A;
+  A.recon = recon ? 1 : 0;
   A.nkx = d.nkx;
   A.nz = d.nz;
   A.ncol = d.ncol;

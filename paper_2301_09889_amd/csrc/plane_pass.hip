@@ -1,0 +1,370 @@
+// Plane pass of one RK3 stage: the six velocity/vorticity fields at every Chebyshev node
+// go to the 3/2-padded (x, z) grid, H = u x omega is formed pointwise, and the three
+// products come back to the stored Fourier modes (§3.1; 3/2-rule dealiasing in x and z).
+//
+// Every FFT has a compile-time length L = A B and runs as two register passes with one
+// LDS exchange (Cooley--Tukey, n = B n1 + n2, k = k1 + A k2):
+//   pass 1, task n2:  DFT_A over n1 of x[B n1 + n2], then the twiddle w_L^(n2 k1);
+//   pass 2, task k1:  DFT_B over n2, giving X[k1 + A k2].
+// Three kernels per stage:
+//   k_zinv<M_z>  inverse FFT along z of every (field, node, p) pencil, zero padding;
+//   k_xrow<M_x>  per pair of padded z rows: six inverse real FFTs along x (the two rows
+//                packed as real and imaginary part), the products, three forward FFTs,
+//                all on one block's LDS with one task per thread in every phase;
+//   k_zfwd<M_z>  forward FFT along z, truncation to |q| < N_z/2, 1/(M_x M_z), Hermitian fix.
+//
+// Layouts (complex):  F6[f][j][p][q], Z6[f][j][zz][p], W3[g][j][zz][p], H3[g][j][p][q].
+#include "device_common.h"
+
+namespace chanenv {
+
+template <int L>
+struct FftPlan;
+template <> struct FftPlan<6> { static constexpr int A = 3, B = 2; };
+template <> struct FftPlan<12> { static constexpr int A = 4, B = 3; };
+template <> struct FftPlan<24> { static constexpr int A = 6, B = 4; };
+template <> struct FftPlan<48> { static constexpr int A = 8, B = 6; };
+template <> struct FftPlan<96> { static constexpr int A = 12, B = 8; };
+template <> struct FftPlan<192> { static constexpr int A = 16, B = 12; };
+
+struct PlaneArgs2 {
+  int ny, nkx, nz;
+  double scale;        // 1 / (M_x M_z)
+  const cplx* F6;
+  cplx* Z6;
+  cplx* W3;
+  cplx* H3;
+  const cplx* twz;     // exp(-2 pi i k / M_z)
+  const cplx* twx;     // exp(-2 pi i k / M_x)
+  const int* status;
+};
+
+// a * w_L^(SG m) from a table tw[k] = exp(-2 pi i k / L) held in LDS.
+template <int L, int SG>
+__device__ __forceinline__ cplx twiddle(cplx a, const cplx* tw, int m) {
+  if (m == 0) return a;
+  cplx w = tw[m % L];
+  if (SG > 0) w.y = -w.y;
+  return cmul(a, w);
+}
+
+
+// ---------------------------------------------------------------------------
+// z inverse: block (p chunk, field, node); F6 -> Z6.
+// ---------------------------------------------------------------------------
+template <int L>
+__global__ __launch_bounds__(1024) void k_zinv2(PlaneArgs2 A, int PB) {
+  constexpr int FA = FftPlan<L>::A, FB = FftPlan<L>::B;
+  constexpr int LP = L + 1;
+  extern __shared__ double dyn_lds[];
+  cplx* tw = reinterpret_cast<cplx*>(dyn_lds);
+  cplx* Y = tw + L;
+  if (*A.status & STATUS_BAD_ACTION) return;
+  const int p0 = blockIdx.x * PB, f = blockIdx.y, j = blockIdx.z;
+  const int np = min(PB, A.nkx - p0);
+  const int nz = A.nz, h = nz / 2;
+  for (int t = threadIdx.x; t < L; t += blockDim.x) tw[t] = A.twz[t];
+  __syncthreads();
+  const size_t fj = (size_t)f * A.ny + j;
+  const cplx* src = A.F6 + (fj * A.nkx + p0) * nz;
+  for (int task = threadIdx.x; task < np * FB; task += blockDim.x) {
+    const int p = task / FB, n2 = task - p * FB;
+    cplx t[FA];
+#pragma unroll
+    for (int n1 = 0; n1 < FA; ++n1) {
+      const int zz = FB * n1 + n2;
+      const int q = (zz < h) ? zz : ((zz > L - h) ? zz - L + nz : -1);
+      t[n1] = (q >= 0) ? src[(size_t)p * nz + q] : cz();
+    }
+    Dft<FA, 1>::run(t);
+    cplx* y = Y + p * LP + n2 * FA;
+#pragma unroll
+    for (int k1 = 0; k1 < FA; ++k1) y[k1] = twiddle<L, 1>(t[k1], tw, n2 * k1);
+  }
+  __syncthreads();
+  cplx* dst = A.Z6 + fj * L * A.nkx + p0;
+  for (int task = threadIdx.x; task < FA * np; task += blockDim.x) {
+    const int k1 = task / np, p = task - k1 * np;
+    cplx u[FB];
+#pragma unroll
+    for (int n2 = 0; n2 < FB; ++n2) u[n2] = Y[p * LP + n2 * FA + k1];
+    Dft<FB, 1>::run(u);
+#pragma unroll
+    for (int k2 = 0; k2 < FB; ++k2) dst[(size_t)(k1 + FA * k2) * A.nkx + p] = u[k2];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// z forward: block (p chunk, product, node); W3 -> H3.
+// ---------------------------------------------------------------------------
+template <int L>
+__global__ __launch_bounds__(1024) void k_zfwd2(PlaneArgs2 A, int PB) {
+  constexpr int FA = FftPlan<L>::A, FB = FftPlan<L>::B;
+  constexpr int LP = L + 1;
+  extern __shared__ double dyn_lds[];
+  cplx* tw = reinterpret_cast<cplx*>(dyn_lds);
+  cplx* X0 = tw + L;       // the p = 0 pencil, for the Hermitian fix
+  cplx* Y = X0 + L;
+  if (*A.status & STATUS_BAD_ACTION) return;
+  const int p0 = blockIdx.x * PB, g = blockIdx.y, j = blockIdx.z;
+  const int np = min(PB, A.nkx - p0);
+  const int nz = A.nz, h = nz / 2;
+  for (int t = threadIdx.x; t < L; t += blockDim.x) tw[t] = A.twz[t];
+  __syncthreads();
+  const size_t gj = (size_t)g * A.ny + j;
+  const cplx* src = A.W3 + gj * L * A.nkx + p0;
+  for (int task = threadIdx.x; task < FB * np; task += blockDim.x) {
+    const int n2 = task / np, p = task - n2 * np;
+    cplx t[FA];
+#pragma unroll
+    for (int n1 = 0; n1 < FA; ++n1) t[n1] = src[(size_t)(FB * n1 + n2) * A.nkx + p];
+    Dft<FA, -1>::run(t);
+    cplx* y = Y + p * LP + n2 * FA;
+#pragma unroll
+    for (int k1 = 0; k1 < FA; ++k1) y[k1] = twiddle<L, -1>(t[k1], tw, n2 * k1);
+  }
+  __syncthreads();
+  cplx* dst = A.H3 + (gj * A.nkx + p0) * nz;
+  const double sc = A.scale;
+  for (int task = threadIdx.x; task < np * FA; task += blockDim.x) {
+    const int p = task / FA, k1 = task - p * FA;
+    cplx u[FB];
+#pragma unroll
+    for (int n2 = 0; n2 < FB; ++n2) u[n2] = Y[p * LP + n2 * FA + k1];
+    Dft<FB, -1>::run(u);
+#pragma unroll
+    for (int k2 = 0; k2 < FB; ++k2) {
+      const int zz = k1 + FA * k2;
+      const int q = (zz < h) ? zz : ((zz > L - h) ? zz - L + nz : -1);
+      if (q < 0) continue;
+      const cplx v = cscale(u[k2], sc);
+      if (p0 + p == 0) {
+        X0[q] = v;
+      } else {
+        dst[(size_t)p * nz + q] = v;
+      }
+    }
+  }
+  if (p0 == 0) {
+    __syncthreads();
+    for (int q = threadIdx.x; q < nz; q += blockDim.x) {
+      cplx v = cz();
+      if (q == 0) {
+        v = make_double2(X0[0].x, 0.0);
+      } else if (q < h) {
+        v = X0[q];
+      } else if (q > h) {
+        v = cconj(X0[nz - q]);
+      }
+      dst[q] = v;
+    }
+  }
+  // Nyquist row q = N_z/2 stays zero (written once when the buffers are cleared).
+}
+
+// ---------------------------------------------------------------------------
+// x rows: block (pair chunk, node); Z6 -> W3.  Each phase gives one task per thread so
+// that the six inverse transforms, the products and the three forward transforms of a
+// block are all in flight together; S holds 6 sequences per pair, transformed in place.
+// ---------------------------------------------------------------------------
+template <int L>
+__global__ __launch_bounds__(1024) void k_xrow2(PlaneArgs2 A, int P) {
+  constexpr int FA = FftPlan<L>::A, FB = FftPlan<L>::B;
+  constexpr int LP = L + 1;
+  extern __shared__ double dyn_lds[];
+  cplx* tw = reinterpret_cast<cplx*>(dyn_lds);
+  cplx* S = tw + L;         // [field][pair][LP]
+  if (*A.status & STATUS_BAD_ACTION) return;
+  const int pair0 = blockIdx.x * P, j = blockIdx.y;
+  const int nkx = A.nkx, ny = A.ny;
+  const int mz = 3 * A.nz / 2;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  for (int t = tid; t < L; t += nthr) tw[t] = A.twx[t];
+  __syncthreads();
+  // 1. inverse pass 1, tasks (f, pair, n2): packed spectrum of rows 2 pair, 2 pair + 1
+  for (int task = tid; task < 6 * P * FB; task += nthr) {
+    const int f = task / (P * FB);
+    const int rem = task - f * P * FB;
+    const int pr = rem / FB, n2 = rem - pr * FB;
+    const int za = 2 * (pair0 + pr);
+    const cplx* ra = A.Z6 + (((size_t)f * ny + j) * mz + za) * nkx;
+    const cplx* rb = ra + nkx;
+    cplx t[FA];
+#pragma unroll
+    for (int n1 = 0; n1 < FA; ++n1) {
+      const int k = FB * n1 + n2;
+      cplx xa = cz(), xb = cz();
+      if (k < nkx) {
+        xa = ra[k];
+        xb = rb[k];
+        if (k == 0) {
+          xa.y = 0.0;
+          xb.y = 0.0;
+        }
+      } else if (k > L - nkx) {
+        xa = cconj(ra[L - k]);
+        xb = cconj(rb[L - k]);
+      }
+      t[n1] = make_double2(xa.x - xb.y, xa.y + xb.x);  // xa + i xb
+    }
+    Dft<FA, 1>::run(t);
+    cplx* y = S + (f * P + pr) * LP + n2 * FA;
+#pragma unroll
+    for (int k1 = 0; k1 < FA; ++k1) y[k1] = twiddle<L, 1>(t[k1], tw, n2 * k1);
+  }
+  __syncthreads();
+  // 2. inverse pass 2, tasks (f, pair, k1): values at x = k1 + A k2, back into S in order
+  {
+    const int ntask = 6 * P * FA;
+    cplx X[FB];
+    int base = 0, k1 = 0;
+    const bool have = tid < ntask;
+    if (have) {
+      const int seq = tid / FA;
+      k1 = tid - seq * FA;
+      base = seq * LP;
+#pragma unroll
+      for (int n2 = 0; n2 < FB; ++n2) X[n2] = S[base + n2 * FA + k1];
+      Dft<FB, 1>::run(X);
+    }
+    __syncthreads();
+    if (have) {
+#pragma unroll
+      for (int k2 = 0; k2 < FB; ++k2) S[base + k1 + FA * k2] = X[k2];
+    }
+  }
+  __syncthreads();
+  // 3. products at every (pair, x); re = row 2 pair, im = row 2 pair + 1
+  for (int task = tid; task < P * L; task += nthr) {
+    const int pr = task / L, x = task - pr * L;
+    const cplx U = S[(0 * P + pr) * LP + x], V = S[(1 * P + pr) * LP + x], W = S[(2 * P + pr) * LP + x];
+    const cplx OX = S[(3 * P + pr) * LP + x], OY = S[(4 * P + pr) * LP + x], OZ = S[(5 * P + pr) * LP + x];
+    S[(0 * P + pr) * LP + x] = make_double2(V.x * OZ.x - W.x * OY.x, V.y * OZ.y - W.y * OY.y);
+    S[(1 * P + pr) * LP + x] = make_double2(W.x * OX.x - U.x * OZ.x, W.y * OX.y - U.y * OZ.y);
+    S[(2 * P + pr) * LP + x] = make_double2(U.x * OY.x - V.x * OX.x, U.y * OY.y - V.y * OX.y);
+  }
+  __syncthreads();
+  // 4. forward pass 1, tasks (g, pair, n2)
+  {
+    const int ntask = 3 * P * FB;
+    cplx t[FA];
+    int base = 0, n2 = 0;
+    const bool have = tid < ntask;
+    if (have) {
+      const int seq = tid / FB;
+      n2 = tid - seq * FB;
+      base = seq * LP;
+#pragma unroll
+      for (int n1 = 0; n1 < FA; ++n1) t[n1] = S[base + FB * n1 + n2];
+      Dft<FA, -1>::run(t);
+    }
+    __syncthreads();
+    if (have) {
+#pragma unroll
+      for (int k1 = 0; k1 < FA; ++k1) S[base + n2 * FA + k1] = twiddle<L, -1>(t[k1], tw, n2 * k1);
+    }
+  }
+  __syncthreads();
+  // 5. forward pass 2, tasks (g, pair, k1): spectrum k = k1 + A k2 back into S in order
+  {
+    const int ntask = 3 * P * FA;
+    cplx X[FB];
+    int base = 0, k1 = 0;
+    const bool have = tid < ntask;
+    if (have) {
+      const int seq = tid / FA;
+      k1 = tid - seq * FA;
+      base = seq * LP;
+#pragma unroll
+      for (int n2 = 0; n2 < FB; ++n2) X[n2] = S[base + n2 * FA + k1];
+      Dft<FB, -1>::run(X);
+    }
+    __syncthreads();
+    if (have) {
+#pragma unroll
+      for (int k2 = 0; k2 < FB; ++k2) S[base + k1 + FA * k2] = X[k2];
+    }
+  }
+  __syncthreads();
+  // 6. unpack the two rows of each pair: a = (Y_k + conj Y_{L-k})/2, b = (Y_k - conj Y_{L-k})/(2i)
+  for (int task = tid; task < 3 * P * nkx; task += nthr) {
+    const int seq = task / nkx, k = task - seq * nkx;
+    const int g = seq / P, pr = seq - g * P;
+    const cplx Yk = S[seq * LP + k];
+    const cplx Ym = cconj(S[seq * LP + ((L - k) % L)]);
+    const cplx Xa = make_double2(0.5 * (Yk.x + Ym.x), 0.5 * (Yk.y + Ym.y));
+    const cplx Xb = make_double2(0.5 * (Yk.y - Ym.y), -0.5 * (Yk.x - Ym.x));
+    const int za = 2 * (pair0 + pr);
+    cplx* wa = A.W3 + (((size_t)g * ny + j) * mz + za) * nkx;
+    wa[k] = Xa;
+    wa[nkx + k] = Xb;
+  }
+}
+
+template <int MZ, int MX>
+static int launch_plane2(const Dims& d, DeviceState& s, hipStream_t st, KernelTimer* tm) {
+  PlaneArgs2 A;
+  A.ny = d.ny;
+  A.nkx = d.nkx;
+  A.nz = d.nz;
+  A.scale = 1.0 / ((double)d.mx * (double)d.mz);
+  A.F6 = s.F6;
+  A.Z6 = s.Z6;
+  A.W3 = s.W3;
+  A.H3 = s.H3;
+  A.twz = s.twz;
+  A.twx = s.twx;
+  A.status = s.status;
+  const int PB = d.nkx < 32 ? d.nkx : 32;
+  const int nblk = (d.nkx + PB - 1) / PB;
+  const size_t shz = (size_t)(MZ + (size_t)PB * (MZ + 1)) * sizeof(cplx);
+  const size_t shf = (size_t)(2 * MZ + (size_t)PB * (MZ + 1)) * sizeof(cplx);
+  constexpr int ZA = FftPlan<MZ>::A;
+  const int zthr = ((PB * ZA + 63) / 64) * 64;
+  // pairs per x-row block: the largest divisor of M_z/2 with 6 P A <= 1024 threads and
+  // 6 P (M_x + 1) complex in LDS <= 80 KiB
+  constexpr int FA = FftPlan<MX>::A;
+  const int pairs = MZ / 2;
+  int P = 1;
+  for (int c = 1; c <= pairs; ++c)
+    if (pairs % c == 0 && 6 * c * FA <= 1024 && (size_t)6 * c * (MX + 1) * sizeof(cplx) <= 80 * 1024) P = c;
+  const int thr = ((6 * P * FA + 63) / 64) * 64;
+  const size_t shx = (size_t)(MX + (size_t)6 * P * (MX + 1)) * sizeof(cplx);
+  if (tm) (void)tm->begin(KC_ZINV, st);
+  hipLaunchKernelGGL(k_zinv2<MZ>, dim3(nblk, 6, d.ny), dim3(zthr), shz, st, A, PB);
+  if (tm) (void)tm->end(st);
+  if (tm) (void)tm->begin(KC_XROW, st);
+  hipLaunchKernelGGL(k_xrow2<MX>, dim3(pairs / P, d.ny), dim3(thr), shx, st, A, P);
+  if (tm) (void)tm->end(st);
+  if (tm) (void)tm->begin(KC_ZFWD, st);
+  hipLaunchKernelGGL(k_zfwd2<MZ>, dim3(nblk, 3, d.ny), dim3(zthr), shf, st, A, PB);
+  if (tm) (void)tm->end(st);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int MZ>
+static int dispatch_mx(const Dims& d, DeviceState& s, hipStream_t st, KernelTimer* tm) {
+  switch (d.mx) {
+    case 6: return launch_plane2<MZ, 6>(d, s, st, tm);
+    case 12: return launch_plane2<MZ, 12>(d, s, st, tm);
+    case 24: return launch_plane2<MZ, 24>(d, s, st, tm);
+    case 48: return launch_plane2<MZ, 48>(d, s, st, tm);
+    case 96: return launch_plane2<MZ, 96>(d, s, st, tm);
+    case 192: return launch_plane2<MZ, 192>(d, s, st, tm);
+    default: return -1;
+  }
+}
+
+int launch_plane_pass(const Dims& d, DeviceState& s, hipStream_t st, KernelTimer* tm) {
+  switch (d.mz) {
+    case 6: return dispatch_mx<6>(d, s, st, tm);
+    case 12: return dispatch_mx<12>(d, s, st, tm);
+    case 24: return dispatch_mx<24>(d, s, st, tm);
+    case 48: return dispatch_mx<48>(d, s, st, tm);
+    case 96: return dispatch_mx<96>(d, s, st, tm);
+    case 192: return dispatch_mx<192>(d, s, st, tm);
+    default: return -1;
+  }
+}
+
+}  // namespace chanenv

@@ -98,6 +98,51 @@ void fill_record(const Dims& d, double lam, double* rec) {
 static const double RK_ALPHA[3] = {4.0 / 15.0, 1.0 / 15.0, 1.0 / 6.0};
 static const double RK_BETA[3] = {4.0 / 15.0, 1.0 / 15.0, 1.0 / 6.0};
 
+// Position of Chebyshev index n in the parity-major order (lane, or 64 for n = N), or -1.
+static int pm_slot(int N, int n) {
+  if (n == N) return 64;
+  if (n % 2 == 0) return n / 2;
+  return 32 + (n - 1) / 2;
+}
+
+// Copies of the natural-order tables in parity-major order for the N <= 64 column kernel.
+static void fill_parity_major(const Dims& d, std::vector<double>& T, const TableLayout& L) {
+  const int N = d.N, NY = d.ny, H = N / 2, ML = d.ml;
+  const long double PI = 3.141592653589793238462643383279502884L;
+  auto lane_n = [&](int l) { return l < 32 ? 2 * l : 2 * (l - 32) + 1; };
+  auto lane_ok = [&](int l) { return (l < 32 ? l : l - 32) < H; };
+  for (int jj = 0; jj <= H; ++jj)
+    for (int l = 0; l < 64; ++l) {
+      const int n = lane_n(l);
+      T[L.kfwd + (size_t)jj * 64 + l] = lane_ok(l) ? (double)cosl(PI * (long double)((jj * n) % (2 * N)) / N) : 0.0;
+      T[L.kinv + (size_t)jj * 64 + l] = (l < N) ? (double)cosl(PI * (long double)((jj * l) % (2 * N)) / N) : 0.0;
+    }
+  for (int n = 0; n <= N; ++n) {
+    const int sl = pm_slot(N, n);
+    for (int k = 0; k < 3; ++k) T[L.rc_pm + (size_t)k * PM_ENTRIES + sl] = T[L.rc + (size_t)k * NY + n];
+    T[L.intw_pm + sl] = (n % 2 == 0) ? 2.0 / (1.0 - (double)n * n) : 0.0;
+    for (int r = 0; r < 3; ++r) T[L.up_pm + (size_t)r * PM_ENTRIES + sl] = T[L.up + (size_t)r * NY + n];
+  }
+  for (int c = 0; c < d.ncol; ++c) {
+    for (int op = 0; op < NOPS; ++op) {
+      const double* src = &T[L.optab + ((size_t)c * NOPS + op) * 2 * d.opsz];
+      double* dst = &T[L.op_pm + ((size_t)c * NOPS + op) * PM_OPSZ];
+      for (int s = 0; s < 2; ++s) {
+        const double* rec = src + (size_t)s * d.opsz;
+        const int m = (N - s) / 2;
+        for (int i = 0; i <= m; ++i) {
+          const int sl = pm_slot(N, 2 * i + s);
+          for (int a = 0; a < 4; ++a) dst[(size_t)a * PM_ENTRIES + sl] = rec[(size_t)a * ML + i];
+        }
+        dst[4 * PM_ENTRIES + s] = rec[4 * ML];
+      }
+    }
+    for (int r = 0; r < 3; ++r)
+      for (int n = 0; n <= N; ++n)
+        T[L.vt_pm + ((size_t)c * 3 + r) * PM_ENTRIES + pm_slot(N, n)] = T[L.vt + ((size_t)c * 3 + r) * NY + n];
+  }
+}
+
 void precompute_tables(const Dims& d, const PhysParams& ph, HostTables* out) {
   const int N = d.N, NY = d.ny, H = N / 2;
   TableLayout& L = out->L;
@@ -120,6 +165,14 @@ void precompute_tables(const Dims& d, const PhysParams& ph, HostTables* out) {
   L.twnz = take((size_t)2 * d.nz);
   L.alpha = take(d.nkx);
   L.beta = take(d.nz);
+  const bool pm = d.N <= 64;
+  L.kfwd = take(pm ? (size_t)(H + 1) * 64 : 0);
+  L.kinv = take(pm ? (size_t)(H + 1) * 64 : 0);
+  L.rc_pm = take(pm ? (size_t)3 * PM_ENTRIES : 0);
+  L.intw_pm = take(pm ? (size_t)PM_ENTRIES : 0);
+  L.op_pm = take(pm ? (size_t)d.ncol * NOPS * PM_OPSZ : 0);
+  L.vt_pm = take(pm ? (size_t)d.ncol * 3 * PM_ENTRIES : 0);
+  L.up_pm = take(pm ? (size_t)3 * PM_ENTRIES : 0);
   L.total = o;
   std::vector<double>& T = out->data;
   T.assign(L.total, 0.0);
@@ -188,6 +241,7 @@ void precompute_tables(const Dims& d, const PhysParams& ph, HostTables* out) {
       T[L.inv_int_up + r] = 1.0 / integ;
     }
   }
+  if (pm) fill_parity_major(d, T, L);
   auto twiddles = [&](size_t off, int len) {
     for (int k = 0; k < len; ++k) {
       const long double ang = -2.0L * PI * (long double)k / (long double)len;

@@ -79,6 +79,7 @@ def test_bitwise_repeatable_and_resumable():
             g.step(to_device(a), 3)
         runs.append(g.get_state())
         g.close()
+    print(f"  two straight runs: max |diff| {np.abs(runs[0] - runs[1]).max():.3e}", flush=True)
     assert np.array_equal(runs[0], runs[1])
     g1 = gpu_env(cfg)
     g1.set_state(st0)
@@ -90,8 +91,11 @@ def test_bitwise_repeatable_and_resumable():
     g2.set_state(mid)
     for a in acts[2:]:
         g2.step(to_device(a), 3)
-    assert np.array_equal(g2.get_state(), runs[0])
+    res = g2.get_state()
     g2.close()
+    diff = np.abs(res - runs[0])
+    print(f"  resumed vs straight: max |diff| {diff.max():.3e} at {int(np.argmax(diff))}", flush=True)
+    assert np.array_equal(res, runs[0])
 
 
 def test_laminar_poiseuille_steady_on_device():
