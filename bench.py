@@ -38,14 +38,17 @@ def resolved_points(g):
 
 def algorithmic_bytes_per_launch(kclass, g):
     """Minimum HBM bytes one launch of a kernel class must move, from the
-    two-layout pass model: 16 K bytes per complex field pass.  The column pass
+    two-layout pass model: 16 K bytes per complex field pass.  The column solve
     reads H (3 fields), v and omega_y (2) and, from the second stage on, the
-    previous stage's h_v, h_g (2); it writes v, omega_y (2), h_v, h_g (2, first
-    two stages) and the six fields for the plane pass: 15 2/3 passes per launch
-    on average over the three stages."""
+    previous stage's h_v, h_g (2); it writes v, omega_y (2) and h_v, h_g (2, first
+    two stages): 9 2/3 passes per launch on average over the three stages.  The
+    column reconstruction reads v, omega_y (2) and writes the six node fields for
+    the plane pass (6).  Precomputed operator tables are not counted."""
     K = resolved_points(g)
     if kclass == "column_pass":
-        return (3 + 2 + 4.0 / 3.0 + 2 + 4.0 / 3.0 + 6) * 16.0 * K
+        return (3 + 2 + 2.0 / 3.0 * 2 + 2 + 2.0 / 3.0 * 2) * 16.0 * K
+    if kclass == "column_reconstruct":
+        return (2 + 6) * 16.0 * K
     nkx, ny, mz = g["nx"] // 2, g["ny"], 3 * g["nz"] // 2
     padded = 16.0 * ny * mz * nkx          # one field on the z-padded intermediate
     if kclass == "z_inverse_fft":

@@ -11,14 +11,22 @@
 //         e_i = w_i R_i - u_i e_{i+1}   (bottom-up),   E_i = e_i + f_i E_{i-1}   (top-down),
 //     with w, u, f, F precomputed per pair and operator; both are affine scans across
 //     the 32 lanes of a half, five steps each, instead of 33 serial steps.
-// Node values (for the DCT-I and the plane pass) are in plain lane order: lane j holds
-// node j < N and node N is the tail.
+// Node values are in the same parity-major order (lane l < 32: node 2l, lane 32 + i: node
+// 2i + 1, node N the tail).  Every cross-lane exchange is a DPP move, a row broadcast or a
+// permlane swap, except the gather that folds the coefficients for the inverse DCT.
+//
+// The tau rows T (rows n >= 2 of the quasi-tridiagonal form) invert D^2 exactly on
+// polynomials of degree <= N: (T D^2 a)_n = a_n.  The right-hand side of each implicit
+// stage, T[-lam0 X - ab (D^2 - k^2) X - gb h - zb h'], is therefore formed as
+// T[(ab k^2 - lam0) X - gb h - zb h'] - ab X, which never forms D^2 phi or D^2 omega_y.
 //
 // Per stage the kernel takes the plane pass output H = u x omega at the nodes, forms
 // h_v, h_g, the RK3/CN right-hand sides, solves for phi_p, omega_y and v_p, applies the
 // 2x2 influence correction, and then prepares the next stage: reconstruction of
 // (u, v, w, omega_x, omega_y, omega_z) and their inverse DCT-I.  The (0, 0) pair solves
 // the mean flow with the constant-flow-rate pressure gradient.
+#include <utility>
+
 #include "device_common.h"
 
 namespace chanenv {
@@ -35,7 +43,8 @@ struct ColArgsPm {
   double lam0, ab, gb, zb;
   double nu, opp_alpha, ub2, px;
   int forcing, js, accumulate_drag;
-  int recon;            // 0: skip the reconstruction for the next stage
+  int want_end;         // reconstruction that ends an env step: also the opposition target
+                        // and the wall shear
   size_t plane;         // elements per field in F6 / H3 (ny nkx nz)
   cplx *vS, *oS, *hist;
   double *meanS, *meanH;
@@ -48,92 +57,218 @@ struct ColArgsPm {
   int* status;
 };
 
+// ---- cross-lane moves without LDS (gfx950 DPP and permlane swaps) ----
+// A row is 16 lanes.  DPP controls used here:
+constexpr int DPP_ROW_SHL = 0x100;        // + d: lane k of a row reads lane k + d of that row
+constexpr int DPP_ROW_SHR = 0x110;        // + d: lane k reads lane k - d
+constexpr int DPP_WAVE_SHL1 = 0x130;      // lane l reads lane l + 1
+constexpr int DPP_WAVE_SHR1 = 0x138;      // lane l reads lane l - 1
+constexpr int DPP_ROW_MIRROR = 0x140;     // lane k reads lane 15 - k
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;  // within 8 lanes: k reads 7 - k
+constexpr int DPP_ROW_BCAST = 0x150;      // + k: every lane of a row reads lane k of the row
+constexpr int DPP_QUAD_XOR1 = 0xB1;       // quad_perm [1, 0, 3, 2]
+constexpr int DPP_QUAD_XOR2 = 0x4E;       // quad_perm [2, 3, 0, 1]
+
+// Compile-time loops: fn(integral_constant<int, D>) for D = 1, 2, 4, 8 below LIMIT, and for
+// K = 0 .. 15.
+template <int LIMIT, class Fn>
+__device__ __forceinline__ void for_pow2(Fn&& fn) {
+  if constexpr (LIMIT > 1) fn(std::integral_constant<int, 1>{});
+  if constexpr (LIMIT > 2) fn(std::integral_constant<int, 2>{});
+  if constexpr (LIMIT > 4) fn(std::integral_constant<int, 4>{});
+  if constexpr (LIMIT > 8) fn(std::integral_constant<int, 8>{});
+}
+template <class Fn, int... K>
+__device__ __forceinline__ void for_each_k(Fn&& fn, std::integer_sequence<int, K...>) {
+  (fn(std::integral_constant<int, K>{}), ...);
+}
+template <class Fn>
+__device__ __forceinline__ void for_16(Fn&& fn) {
+  for_each_k(fn, std::make_integer_sequence<int, 16>{});
+}
+
+// x moved by the DPP pattern CTRL; a lane whose source lies outside the row (or the wave)
+// reads 0.
+template <int CTRL>
+__device__ __forceinline__ double dmov(double x) {
+  return __builtin_amdgcn_update_dpp(0.0, x, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL>
+__device__ __forceinline__ cplx cmov(cplx v) {
+  return make_double2(dmov<CTRL>(v.x), dmov<CTRL>(v.y));
+}
+__device__ __forceinline__ unsigned lo32(double x) { return (unsigned)(unsigned long long)__double_as_longlong(x); }
+__device__ __forceinline__ unsigned hi32(double x) {
+  return (unsigned)((unsigned long long)__double_as_longlong(x) >> 32);
+}
+__device__ __forceinline__ double join32(unsigned l, unsigned h) {
+  return __longlong_as_double((long long)(((unsigned long long)h << 32) | l));
+}
+// The value at the same position of the partner row (rows 0 <-> 1, 2 <-> 3).
+__device__ __forceinline__ double swap_rows(double x, bool even_row) {
+  const auto a = __builtin_amdgcn_permlane16_swap(lo32(x), lo32(x), false, false);
+  const auto b = __builtin_amdgcn_permlane16_swap(hi32(x), hi32(x), false, false);
+  return even_row ? join32(a[1], b[1]) : join32(a[0], b[0]);
+}
+__device__ __forceinline__ cplx swap_rows(cplx v, bool even_row) {
+  return make_double2(swap_rows(v.x, even_row), swap_rows(v.y, even_row));
+}
+// The value of lane l ^ 32.
+__device__ __forceinline__ double swap_halves(double x, bool low) {
+  const auto a = __builtin_amdgcn_permlane32_swap(lo32(x), lo32(x), false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap(hi32(x), hi32(x), false, false);
+  return low ? join32(a[1], b[1]) : join32(a[0], b[0]);
+}
+// Lanes l < 32 receive lo's lane l + 32, lanes l >= 32 receive hi's lane l - 32.
+__device__ __forceinline__ double cross_halves(double lo, double hi, bool low) {
+  const auto a = __builtin_amdgcn_permlane32_swap(lo32(lo), lo32(hi), false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap(hi32(lo), hi32(hi), false, false);
+  return low ? join32(a[1], b[1]) : join32(a[0], b[0]);
+}
+__device__ __forceinline__ double readlane_d(double x, int l) {
+  return join32(__builtin_amdgcn_readlane(lo32(x), l), __builtin_amdgcn_readlane(hi32(x), l));
+}
+__device__ __forceinline__ cplx readlane_c(cplx v, int l) { return make_double2(readlane_d(v.x, l), readlane_d(v.y, l)); }
 __device__ __forceinline__ cplx shfl_c(cplx v, int src) {
   return make_double2(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
 }
-__device__ __forceinline__ cplx shfl_down32(cplx v, int d) {
-  return make_double2(__shfl_down(v.x, d, 32), __shfl_down(v.y, d, 32));
+// Sums whose every step adds two values that are already identical within their groups, so
+// that every lane of the group receives the bitwise-same result.
+__device__ __forceinline__ double row_sum(double x) {
+  x += dmov<DPP_QUAD_XOR1>(x);
+  x += dmov<DPP_QUAD_XOR2>(x);
+  x += dmov<DPP_ROW_HALF_MIRROR>(x);
+  x += dmov<DPP_ROW_MIRROR>(x);
+  return x;
 }
-__device__ __forceinline__ cplx shfl_up32(cplx v, int d) {
-  return make_double2(__shfl_up(v.x, d, 32), __shfl_up(v.y, d, 32));
+__device__ __forceinline__ double half_sum(double x, bool even_row) {
+  x = row_sum(x);
+  return x + swap_rows(x, even_row);
 }
-// Sum over the 32 lanes of this lane's half (every lane of the half gets the same value).
-__device__ __forceinline__ cplx half_sum(cplx v) {
-#pragma unroll
-  for (int off = 16; off > 0; off >>= 1) {
-    v.x += __shfl_xor(v.x, off, 64);
-    v.y += __shfl_xor(v.y, off, 64);
-  }
-  return v;
+__device__ __forceinline__ cplx half_sum(cplx v, bool even_row) {
+  return make_double2(half_sum(v.x, even_row), half_sum(v.y, even_row));
+}
+__device__ __forceinline__ double lane_sum(double x, bool even_row, bool low) {
+  x = half_sum(x, even_row);
+  return x + swap_halves(x, low);
+}
+__device__ __forceinline__ cplx lane_sum(cplx v, bool even_row, bool low) {
+  return make_double2(lane_sum(v.x, even_row, low), lane_sum(v.y, even_row, low));
 }
 
 // Parity-major bookkeeping of one lane.
 template <int N>
 struct Lane {
   static constexpr int H = N / 2;
-  int l, i, odd, n;
-  bool ok;
+  int l, i, odd, n, rk;
+  bool ok, even_row, low;
   __device__ explicit Lane(int lane) {
     l = lane;
     odd = lane >= 32;
     i = lane & 31;
     n = odd ? 2 * i + 1 : 2 * i;
     ok = i < H;
+    rk = lane & 15;
+    even_row = ((lane >> 4) & 1) == 0;
+    low = !odd;
   }
 };
+
+// Suffix sum over this lane's half: lane i receives sum_{i' >= i} x_{i'} (lanes beyond the
+// valid range hold zeros).
+template <int H>
+__device__ __forceinline__ cplx half_suffix(const cplx x0, bool even_row) {
+  cplx x = x0;
+  for_pow2<(H < 16 ? H : 16)>([&](auto dc) { x = cadd(x, cmov<DPP_ROW_SHL + decltype(dc)::value>(x)); });
+  if constexpr (H > 16) {  // add the second row's total to the first row
+    const cplx t = swap_rows(cmov<DPP_ROW_BCAST + 0>(x), even_row);
+    if (even_row) x = cadd(x, t);
+  }
+  return x;
+}
 
 // D: b_n = (2/c_n) sum_{p > n, p + n odd} p a_p.  x: this lane's coefficient, xt: a_N.
 // Returns b (b_N = 0).
 template <int N>
 __device__ __forceinline__ cplx cheb_d(const Lane<N>& L, cplx x, cplx xt) {
   constexpr int H = N / 2;
-  cplx S = L.ok ? cscale(x, (double)L.n) : cz();
-#pragma unroll
-  for (int d = 1; d < 32; d <<= 1) {
-    const cplx o = shfl_down32(S, d);
-    if (L.i + d < 32) S = cadd(S, o);
-  }
+  const cplx S = half_suffix<H>(L.ok ? cscale(x, (double)L.n) : cz(), L.even_row);
   // even n = 2l: odd p >= 2l + 1  -> S at lane 32 + l
   // odd n = 2i + 1: even p >= 2i + 2 -> S at lane i + 1, plus the tail p = N
-  const cplx from_odd = shfl_c(S, (L.l + 32) & 63);
-  cplx from_even = shfl_c(S, (L.i + 1) & 31);
-  if (L.i + 1 >= H) from_even = cz();
-  cplx b = L.odd ? cadd(from_even, cscale(xt, (double)N)) : from_odd;
+  const cplx Sn = cmov<DPP_WAVE_SHL1>(S);
+  cplx g = make_double2(cross_halves(S.x, Sn.x, L.low), cross_halves(S.y, Sn.y, L.low));
+  if (L.odd && L.i + 1 >= H) g = cz();
+  const cplx b = L.odd ? cadd(g, cscale(xt, (double)N)) : g;
   const double c = (L.n == 0) ? 1.0 : 2.0;
   return L.ok ? cscale(b, c) : cz();
 }
 
-// Tau right-hand side rows R_n = rc1 f_{n-2} - rc2 f_n + rc3 f_{n+2} (n >= 2); returns the
-// lane's row, and the tail row R_N through rt.
+// This lane's tau-row coefficients (rc1, rc2, rc3 and rc1 of the tail row N).
+struct RowCoef {
+  double r1, r2, r3, rt;
+};
 template <int N>
-__device__ __forceinline__ cplx tau_rows_pm(const Lane<N>& L, cplx f, cplx ft, const double* __restrict__ rc,
-                                            cplx& rt) {
+__device__ __forceinline__ RowCoef load_rc(const Lane<N>& L, const double* __restrict__ rc) {
+  RowCoef t;
+  t.r1 = rc[L.l];
+  t.r2 = rc[PM_ENTRIES + L.l];
+  t.r3 = rc[2 * PM_ENTRIES + L.l];
+  t.rt = rc[64];
+  return t;
+}
+
+// Tau right-hand side rows R_n = rc1 f_{n-2} - rc2 f_n + rc3 f_{n+2} + cx x_n (n >= 2);
+// returns the lane's row, and the tail row R_N through rt.
+template <int N>
+__device__ __forceinline__ cplx tau_rows_pm(const Lane<N>& L, cplx f, cplx ft, const RowCoef& rc, double cx,
+                                            cplx x, cplx xt, cplx& rt) {
   constexpr int H = N / 2;
-  const cplx fm2 = shfl_up32(f, 1);
-  cplx fp2 = shfl_down32(f, 1);
+  cplx fm2 = cmov<DPP_WAVE_SHR1>(f);
+  if (L.i == 0) fm2 = cz();
+  cplx fp2 = cmov<DPP_WAVE_SHL1>(f);
+  if (L.i == 31) fp2 = cz();
   if (!L.odd && L.i == H - 1) fp2 = ft;  // n + 2 = N
-  const double r1 = rc[L.l], r2 = rc[PM_ENTRIES + L.l], r3 = rc[2 * PM_ENTRIES + L.l];
-  cplx r = cscale(fm2, r1);
-  r = caxpy(r, -r2, f);
-  r = caxpy(r, r3, fp2);
-  // R_N = rc1_N f_{N-2}: f_{N-2} is the even lane H - 1
-  const cplx fN2 = shfl_c(f, H - 1);
-  rt = cscale(fN2, rc[64]);
+  cplx r = cscale(fm2, rc.r1);
+  r = caxpy(r, -rc.r2, f);
+  r = caxpy(r, rc.r3, fp2);
+  r = caxpy(r, cx, x);
+  // R_N = rc1_N f_{N-2} + cx x_N: f_{N-2} is the even lane H - 1
+  const cplx fN2 = readlane_c(f, H - 1);
+  rt = caxpy(cscale(fN2, rc.rt), cx, xt);
   return (L.ok && L.n >= 2) ? r : cz();
+}
+
+// One operator's elimination record as this lane needs it (w, u, f, F at its index, the
+// even tail's w, f, F and the two 1/sum F).
+struct TauRec {
+  double w, u, fr, F, wt, frt, Ft, isf, isf_even;
+};
+template <int N>
+__device__ __forceinline__ TauRec load_rec(const Lane<N>& L, const double* __restrict__ rec) {
+  constexpr int P = PM_ENTRIES;
+  TauRec t;
+  t.w = rec[L.l];
+  t.u = rec[P + L.l];
+  t.fr = rec[2 * P + L.l];
+  t.F = rec[3 * P + L.l];
+  t.wt = rec[64];
+  t.frt = rec[2 * P + 64];
+  t.Ft = rec[3 * P + 64];
+  t.isf = rec[4 * P + L.odd];
+  t.isf_even = rec[4 * P];
+  return t;
 }
 
 // Solve (D^2 - lam) X = f for NR right-hand sides sharing one operator record (w, u, f,
 // F, 1/sum F, parity-major), with X(+1) = gt, X(-1) = gb per right-hand side.
 template <int N, int NR>
-__device__ __forceinline__ void tau_solve_pm(const Lane<N>& L, const cplx* R, const cplx* Rt,
-                                             const double* __restrict__ rec, const cplx* gt, const cplx* gb,
-                                             cplx* X, cplx* Xt) {
+__device__ __forceinline__ void tau_solve_pm(const Lane<N>& L, const cplx* R, const cplx* Rt, const TauRec& tr,
+                                             const cplx* gt, const cplx* gb, cplx* X, cplx* Xt) {
   constexpr int H = N / 2;
-  constexpr int P = PM_ENTRIES;
-  const double w = rec[L.l], u = rec[P + L.l], fr = rec[2 * P + L.l], F = rec[3 * P + L.l];
-  const double wt = rec[64], frt = rec[2 * P + 64], Ft = rec[3 * P + 64];
-  const double isf = rec[4 * P + L.odd];
-  const double isf_even = rec[4 * P];
+  const double w = tr.w, u = tr.u, fr = tr.fr, F = tr.F;
+  const double wt = tr.wt, frt = tr.frt, Ft = tr.Ft;
+  const double isf = tr.isf;
+  const double isf_even = tr.isf_even;
   // bottom-up: e_i = A_i + B_i e_{i+1}
   cplx A[NR], et[NR];
   double B = -u;
@@ -154,39 +289,53 @@ __device__ __forceinline__ void tau_solve_pm(const Lane<N>& L, const cplx* R, co
     for (int k = 0; k < NR; ++k) A[k] = cz();
     B = 0.0;
   }
-#pragma unroll
-  for (int d = 1; d < 32; d <<= 1) {
-    const double oB = __shfl_down(B, d, 32);
+  for_pow2<(H < 16 ? H : 16)>([&](auto dc) {
+    constexpr int d = decltype(dc)::value;
+    const double oB = dmov<DPP_ROW_SHL + d>(B);
     cplx oA[NR];
 #pragma unroll
-    for (int k = 0; k < NR; ++k) oA[k] = shfl_down32(A[k], d);
-    if (L.i + d < 32) {
+    for (int k = 0; k < NR; ++k) oA[k] = cmov<DPP_ROW_SHL + d>(A[k]);
+    if (L.rk + d < 16) {
 #pragma unroll
       for (int k = 0; k < NR; ++k) A[k] = caxpy(A[k], B, oA[k]);
       B = B * oB;
     }
+  });
+  if constexpr (H > 16) {  // first row: e_i = A_i + B_i e_16
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const cplx e16 = swap_rows(cmov<DPP_ROW_BCAST + 0>(A[k]), L.even_row);
+      if (L.even_row) A[k] = caxpy(A[k], B, e16);
+    }
   }
   // top-down: E_i = e_i + f_i E_{i-1}, E_0 = 0
   double C = (L.ok && L.i > 0) ? fr : 0.0;
-#pragma unroll
-  for (int d = 1; d < 32; d <<= 1) {
-    const double oC = __shfl_up(C, d, 32);
+  for_pow2<(H < 16 ? H : 16)>([&](auto dc) {
+    constexpr int d = decltype(dc)::value;
+    const double oC = dmov<DPP_ROW_SHR + d>(C);
     cplx oA[NR];
 #pragma unroll
-    for (int k = 0; k < NR; ++k) oA[k] = shfl_up32(A[k], d);
-    if (L.i >= d) {
+    for (int k = 0; k < NR; ++k) oA[k] = cmov<DPP_ROW_SHR + d>(A[k]);
+    if (L.rk >= d) {
 #pragma unroll
       for (int k = 0; k < NR; ++k) A[k] = caxpy(A[k], C, oA[k]);
       C = C * oC;
+    }
+  });
+  if constexpr (H > 16) {  // second row: E_i = A_i + C_i E_15
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const cplx e15 = swap_rows(cmov<DPP_ROW_BCAST + 15>(A[k]), L.even_row);
+      if (!L.even_row) A[k] = caxpy(A[k], C, e15);
     }
   }
 #pragma unroll
   for (int k = 0; k < NR; ++k) {
     // even tail E_{N/2} = e_{N/2} + f_{N/2} E_{N/2-1}
-    const cplx Elast = shfl_c(A[k], H - 1);
+    const cplx Elast = readlane_c(A[k], H - 1);
     const cplx Et = caxpy(et[k], frt, Elast);
-    cplx sum = half_sum(A[k]);
-    const cplx sum_even = shfl_c(sum, 0);
+    cplx sum = half_sum(A[k], L.even_row);
+    const cplx sum_even = readlane_c(sum, 0);
     if (!L.odd) sum = cadd(sum, Et);
     const cplx g = L.odd ? cscale(csub(gt[k], gb[k]), 0.5) : cscale(cadd(gt[k], gb[k]), 0.5);
     const cplx x0 = cscale(csub(g, sum), isf);
@@ -197,94 +346,160 @@ __device__ __forceinline__ void tau_solve_pm(const Lane<N>& L, const cplx* R, co
   }
 }
 
-// Forward DCT-I of F node vectors (this lane's node j = lane < N, tail = node N), giving
-// parity-major coefficients a (this lane) and the tail a_N.
-template <int N, int F>
-__device__ __forceinline__ void dct_fwd_pm(const Lane<N>& L, const cplx* f, const cplx* ft,
-                                           const double* __restrict__ kfwd, cplx* Sb, cplx* a, cplx* at) {
-  constexpr int H = N / 2;
-  constexpr int HP = H + 1;
-  const int lane = L.l;
-  // fold: g_j = f_j / cb_j; S_j = g_j + g_{N-j}, D_j = g_j - g_{N-j} (j < N/2), S = D = g at N/2
-  const int partner = (N - lane) & 63;
-#pragma unroll
-  for (int k = 0; k < F; ++k) {
-    cplx g = f[k];
-    if (lane == 0) g = cscale(g, 0.5);
-    cplx pg = shfl_c(f[k], partner);
-    if (lane == 0) pg = cscale(ft[k], 0.5);
-    if (lane < H) {
-      Sb[(2 * k) * HP + lane] = cadd(g, pg);
-      Sb[(2 * k + 1) * HP + lane] = csub(g, pg);
-    } else if (lane == H) {
-      Sb[(2 * k) * HP + H] = g;
-      Sb[(2 * k + 1) * HP + H] = g;
-    }
-  }
-  wave_sync();
-  cplx acc[F];
-#pragma unroll
-  for (int k = 0; k < F; ++k) acc[k] = cz();
-  const int sel = L.odd;  // even coefficients use S, odd ones D
-#pragma unroll 3
-  for (int jj = 0; jj <= H; ++jj) {
-    const double c = kfwd[jj * 64 + lane];
-#pragma unroll
-    for (int k = 0; k < F; ++k) acc[k] = caxpy(acc[k], c, Sb[(2 * k + sel) * HP + jj]);
-  }
-  const double sc = (L.n == 0) ? (1.0 / N) : (2.0 / N);
-#pragma unroll
-  for (int k = 0; k < F; ++k) {
-    a[k] = L.ok ? cscale(acc[k], sc) : cz();
-    // a_N = (1/N) sum_{j <= N/2} (-1)^j S_j
-    cplx part = cz();
-    if (lane <= H) part = cscale(Sb[(2 * k) * HP + lane], (lane & 1) ? -1.0 : 1.0);
-    at[k] = cscale(wave_sum(part), 1.0 / N);
+// acc[g] += c * (lane KK of this lane's row of q[g]) for G = 6 or 12 real vectors, as fused DPP
+// FMAs (src0 broadcast from a row lane; the only DPP pattern the FP64 ALU takes).  The leading
+// s_nop 4 covers the DPP read-after-VALU-write (2) and EXEC-write (5) wait states, whatever
+// the compiler places before the block.
+template <int KK, int G>
+__device__ __forceinline__ void fmac_row(double (&acc)[G], const double (&q)[G], double c) {
+  static_assert(G == 6 || G == 12, "row FMA blocks take 6 or 12 vectors");
+  if constexpr (G == 12) {
+    asm volatile(
+      "s_nop 4\n\t"
+      "v_fmac_f64_dpp %0, %12, %24 row_newbcast:%c25 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %1, %13, %24 row_newbcast:%c25 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %2, %14, %24 row_newbcast:%c25 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %3, %15, %24 row_newbcast:%c25 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %4, %16, %24 row_newbcast:%c25 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %5, %17, %24 row_newbcast:%c25 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %6, %18, %24 row_newbcast:%c25 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %7, %19, %24 row_newbcast:%c25 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %8, %20, %24 row_newbcast:%c25 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %9, %21, %24 row_newbcast:%c25 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %10, %22, %24 row_newbcast:%c25 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %11, %23, %24 row_newbcast:%c25 row_mask:0xf bank_mask:0xf"
+      : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]), "+v"(acc[5]), "+v"(acc[6]),
+        "+v"(acc[7]), "+v"(acc[8]), "+v"(acc[9]), "+v"(acc[10]), "+v"(acc[11])
+      : "v"(q[0]), "v"(q[1]), "v"(q[2]), "v"(q[3]), "v"(q[4]), "v"(q[5]), "v"(q[6]), "v"(q[7]), "v"(q[8]),
+        "v"(q[9]), "v"(q[10]), "v"(q[11]), "v"(c), "n"(KK));
+  } else {
+    asm volatile(
+      "s_nop 4\n\t"
+      "v_fmac_f64_dpp %0, %6, %12 row_newbcast:%c13 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %1, %7, %12 row_newbcast:%c13 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %2, %8, %12 row_newbcast:%c13 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %3, %9, %12 row_newbcast:%c13 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %4, %10, %12 row_newbcast:%c13 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %5, %11, %12 row_newbcast:%c13 row_mask:0xf bank_mask:0xf"
+      : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]), "+v"(acc[5])
+      : "v"(q[0]), "v"(q[1]), "v"(q[2]), "v"(q[3]), "v"(q[4]), "v"(q[5]), "v"(c), "n"(KK));
   }
 }
 
-// Inverse DCT-I: parity-major coefficients (this lane, tail) -> node values (node = lane < N,
-// tail node N).  f_j = sum_n a_n cos(pi n j / N), folded with P_n = a_n + a_{N-n},
-// M_n = a_n - a_{N-n} (n < N/2), P = M = a_{N/2} at n = N/2.
-template <int N, int F>
-__device__ __forceinline__ void dct_inv_pm(const Lane<N>& L, const cplx* a, const cplx* at,
-                                           const double* __restrict__ kinv, cplx* Sb, cplx* f, cplx* ft) {
+// Forward DCT-I of F fields, a_n = (2 / (N cb_n)) sum_j f_j cos(pi j n / N) / cb_j, read straight
+// from memory (load(g, j): node j of field g).  Folded: g_j = f_j / cb_j, S_j = g_j + g_{N-j},
+// D_j = g_j - g_{N-j} (j < N/2); even n need S, odd n need D, and g_{N/2} enters both.  Rows
+// 0, 1 (even coefficients) hold S_{16m+k}, rows 2, 3 (odd) hold D_{16m+k} in register group m
+// at row position k, so each term of the matvec is a row broadcast (no LDS).  Returns
+// parity-major coefficients a (this lane) and the tail a_N.
+template <int N, int F, class Load>
+__device__ __forceinline__ void dct_fwd_pm(const Lane<N>& L, Load load, const double* __restrict__ kfwd, cplx* a,
+                                           cplx* at) {
   constexpr int H = N / 2;
-  constexpr int HP = H + 1;
+  constexpr int NQ = (H + 15) / 16;
   const int lane = L.l;
-  // partner lane of N - n in the same half (n = 0 pairs with the tail)
-  int partner = 0;
-  if (!L.odd) partner = (H - L.i) & 63;
-  else partner = 32 + ((H - 1 - L.i) & 31);
+  const bool srow = L.l < 32;
+  // this lane's cosines, all requested before the first use (the FMA blocks below are
+  // ordering points for memory operations)
+  double cf[H + 1];
 #pragma unroll
-  for (int k = 0; k < F; ++k) {
-    cplx pa = shfl_c(a[k], partner);
-    if (!L.odd && L.i == 0) pa = at[k];
-    if (L.ok && L.n < H) {
-      Sb[(2 * k) * HP + L.n] = cadd(a[k], pa);
-      Sb[(2 * k + 1) * HP + L.n] = csub(a[k], pa);
-    } else if (L.ok && L.n == H) {
-      Sb[(2 * k) * HP + H] = a[k];
-      Sb[(2 * k + 1) * HP + H] = a[k];
+  for (int j = 0; j <= H; ++j) cf[j] = kfwd[j * 64 + lane];
+  double Q[NQ][2 * F];  // (re, im) of each field
+  cplx gh[F];
+#pragma unroll
+  for (int g = 0; g < F; ++g) {
+    gh[g] = load(g, H);
+#pragma unroll
+    for (int m = 0; m < NQ; ++m) {
+      const int j = 16 * m + L.rk;
+      cplx q = cz();
+      if (j < H) {
+        cplx x = load(g, j), y = load(g, N - j);
+        if (j == 0) {
+          x = cscale(x, 0.5);
+          y = cscale(y, 0.5);
+        }
+        q = srow ? cadd(x, y) : csub(x, y);
+      }
+      Q[m][2 * g] = q.x;
+      Q[m][2 * g + 1] = q.y;
     }
   }
-  wave_sync();
-  cplx acc[F];
+  double acc[2 * F];
 #pragma unroll
-  for (int k = 0; k < F; ++k) acc[k] = cz();
-  const int sel = lane & 1;  // even nodes use P, odd nodes M
-#pragma unroll 3
-  for (int n = 0; n <= H; ++n) {
-    const double c = kinv[n * 64 + lane];
+  for (int g = 0; g < 2 * F; ++g) acc[g] = 0.0;
+  auto term = [&](auto kk_c, auto m_c) {
+    constexpr int kk = decltype(kk_c)::value;
+    constexpr int m = decltype(m_c)::value;
+    if constexpr (16 * m + kk < H) fmac_row<kk, 2 * F>(acc, Q[m], cf[16 * m + kk]);
+  };
+  for_each_k([&](auto m_c) { for_16([&](auto kk_c) { term(kk_c, m_c); }); }, std::make_integer_sequence<int, NQ>{});
+  const double ch = cf[H];
+  const double sc = (L.n == 0) ? (1.0 / N) : (2.0 / N);
 #pragma unroll
-    for (int k = 0; k < F; ++k) acc[k] = caxpy(acc[k], c, Sb[(2 * k + sel) * HP + n]);
+  for (int g = 0; g < F; ++g) {
+    a[g] = L.ok ? cscale(caxpy(make_double2(acc[2 * g], acc[2 * g + 1]), ch, gh[g]), sc) : cz();
+    // a_N = (1/N) [sum_{j < N/2} (-1)^j S_j + (-1)^{N/2} g_{N/2}]; row 0 holds the S_j
+    cplx part = cz();
+#pragma unroll
+    for (int m = 0; m < NQ; ++m) part = cadd(part, make_double2(Q[m][2 * g], Q[m][2 * g + 1]));
+    if (L.rk & 1) part = cscale(part, -1.0);
+    const cplx rs = readlane_c(make_double2(row_sum(part.x), row_sum(part.y)), 0);
+    at[g] = cscale(caxpy(rs, (H & 1) ? -1.0 : 1.0, gh[g]), 1.0 / N);
+  }
+}
+
+// Inverse DCT-I: parity-major coefficients (this lane, tail) -> node values in parity-major
+// node order (lane l < 32: node 2l, lane 32 + i: node 2i + 1; tail: node N).
+// f_j = sum_n a_n cos(pi n j / N), folded with P_n = a_n + a_{N-n}, M_n = a_n - a_{N-n}
+// (n < N/2; even nodes need P, odd nodes M) and a_{N/2} in both; the node-N tail is
+// sum_n (-1)^n a_n.
+template <int N, int F>
+__device__ __forceinline__ void dct_inv_pm(const Lane<N>& L, const cplx* a, const cplx* at,
+                                           const double* __restrict__ kinv, cplx* f, cplx* ft) {
+  constexpr int H = N / 2;
+  constexpr int NQ = (H + 15) / 16;
+  constexpr int SH = (H & 1) ? 32 + (H >> 1) : (H >> 1);  // lane of a_{N/2}
+  const int lane = L.l;
+  const bool prow = L.l < 32;
+  double cf[H + 1];  // this lane's cosines, requested up front
+#pragma unroll
+  for (int n = 0; n <= H; ++n) cf[n] = kinv[n * 64 + lane];
+  double Q[NQ][2 * F];  // (re, im) of each field
+  cplx ah[F];
+#pragma unroll
+  for (int m = 0; m < NQ; ++m) {
+    const int n = 16 * m + L.rk;
+    const int n2 = N - n;
+    const int s1 = (n & 1) ? 32 + (n >> 1) : (n >> 1);
+    const int s2 = (n2 & 1) ? 32 + (n2 >> 1) : (n2 >> 1);
+#pragma unroll
+    for (int g = 0; g < F; ++g) {
+      const cplx x = shfl_c(a[g], s1 & 63);
+      cplx y = shfl_c(a[g], s2 & 63);
+      if (n == 0) y = at[g];
+      const cplx qv = (n < H) ? (prow ? cadd(x, y) : csub(x, y)) : cz();
+      Q[m][2 * g] = qv.x;
+      Q[m][2 * g + 1] = qv.y;
+    }
   }
 #pragma unroll
-  for (int k = 0; k < F; ++k) {
-    f[k] = (lane < N) ? acc[k] : cz();
-    cplx part = cz();
-    if (lane <= H) part = cscale(Sb[(2 * k) * HP + lane], (lane & 1) ? -1.0 : 1.0);
-    ft[k] = wave_sum(part);
+  for (int g = 0; g < F; ++g) ah[g] = readlane_c(a[g], SH);
+  double acc[2 * F];
+#pragma unroll
+  for (int g = 0; g < 2 * F; ++g) acc[g] = 0.0;
+  auto term = [&](auto kk_c, auto m_c) {
+    constexpr int kk = decltype(kk_c)::value;
+    constexpr int m = decltype(m_c)::value;
+    if constexpr (16 * m + kk < H) fmac_row<kk, 2 * F>(acc, Q[m], cf[16 * m + kk]);
+  };
+  for_each_k([&](auto m_c) { for_16([&](auto kk_c) { term(kk_c, m_c); }); }, std::make_integer_sequence<int, NQ>{});
+  const double ch = cf[H];
+#pragma unroll
+  for (int g = 0; g < F; ++g) {
+    f[g] = L.ok ? caxpy(make_double2(acc[2 * g], acc[2 * g + 1]), ch, ah[g]) : cz();
+    const cplx part = L.ok ? (L.odd ? cscale(a[g], -1.0) : a[g]) : cz();
+    ft[g] = cadd(lane_sum(part, L.even_row, L.low), at[g]);
   }
 }
 
@@ -292,18 +507,19 @@ __device__ __forceinline__ void dct_inv_pm(const Lane<N>& L, const cplx* a, cons
 template <int N>
 __device__ __forceinline__ cplx coef_sum(const Lane<N>& L, cplx x, cplx xt, double w_lane, double w_tail) {
   cplx part = L.ok ? cscale(x, w_lane) : cz();
-  return caxpy(wave_sum(part), w_tail, xt);
+  return caxpy(lane_sum(part, L.even_row, L.low), w_tail, xt);
 }
 
-template <int N>
-__global__ __launch_bounds__(64 * CWAVES) void k_column_pm(ColArgsPm A) {
+// The two parts of the column pass run as separate launches: the implicit solve of a stage,
+// and the reconstruction with the inverse DCT that feeds the next plane pass (which also
+// follows the last stage of an env step, from the stored state).
+constexpr int PART_SOLVE = 0, PART_RECON = 1;
+
+template <int N, int PART>
+__global__ __launch_bounds__(64 * CWAVES, 2) void k_column_pm(ColArgsPm A) {
   constexpr int NY = N + 1;
-  constexpr int H = N / 2;
-  constexpr int HP = H + 1;
-  constexpr int SB = 12 * HP;  // complex scratch per wave: 6 fields x (P, M)
-  extern __shared__ double dyn_lds[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int c = blockIdx.x * CWAVES + wave;
+  const int c = __builtin_amdgcn_readfirstlane(blockIdx.x * CWAVES + wave);  // wave-uniform column
   if (c >= A.ncol) return;
   if (*A.status & STATUS_BAD_ACTION) return;
   const int nz = A.nz;
@@ -312,7 +528,6 @@ __global__ __launch_bounds__(64 * CWAVES) void k_column_pm(ColArgsPm A) {
   if (p == 0 && q > nz / 2) return;   // written by its Hermitian partner (0, -q)
   const bool mean = (c == 0);
   const int partner = (p == 0 && q > 0) ? (nz - q) : -1;
-  cplx* Sb = reinterpret_cast<cplx*>(dyn_lds) + (size_t)wave * SB;
   const Lane<N> L(lane);
   const double al = A.alpha[p], be = A.beta[q];
   const double k2 = al * al + be * be;
@@ -322,42 +537,90 @@ __global__ __launch_bounds__(64 * CWAVES) void k_column_pm(ColArgsPm A) {
 
   cplx v, om, vt, omt;  // state after this call (mean: v = U + i W, om = 0)
 
-  if (A.stage >= 0) {
+  if constexpr (PART == PART_SOLVE) {
     const int r = A.stage;
-    // H1, H2, H3 at the nodes (lane j < N, tail N)
-    cplx hn[3], hnt[3];
-#pragma unroll
-    for (int g = 0; g < 3; ++g) {
-      const size_t o = ((size_t)(lane < N ? lane : 0) * A.nkx + p) * nz + q;
-      const size_t ot = ((size_t)N * A.nkx + p) * nz + q;
-      hn[g] = (lane < N) ? A.H3[g * A.plane + o] : cz();
-      hnt[g] = A.H3[g * A.plane + ot];
-      if (mean && g != 1) {  // the mean flow sees the real parts of H1, H3 only
-        hn[g].y = 0.0;
-        hnt[g].y = 0.0;
+    // H1, H2, H3 at node j of this column; the mean flow sees the real parts of H1, H3 only
+    const cplx* h3 = A.H3 + (size_t)p * nz + q;
+    const size_t jstride = (size_t)A.nkx * nz;
+    auto loadH = [&](int g, int j) {
+      cplx x = h3[g * A.plane + (size_t)j * jstride];
+      if (mean && g != 1) x.y = 0.0;
+      return x;
+    };
+    cplx hc[3], hct[3];
+    dct_fwd_pm<N, 3>(L, loadH, A.kfwd, hc, hct);
+    // state (v, omega_y; mean: X = U + i W) and the previous stage's explicit terms
+    // (h_v, h_g; mean: h_u + i h_w)
+    cplx x0, x0t, y0 = cz(), y0t = cz();
+    cplx hp0 = cz(), hp0t = cz(), hp1 = cz(), hp1t = cz();
+    cplx* hist_v = A.hist + col;
+    cplx* hist_g = A.hist + (size_t)A.ncol * NY + col;
+    if (!mean) {
+      x0 = L.ok ? A.vS[col + nl] : cz();
+      x0t = A.vS[col + N];
+      y0 = L.ok ? A.oS[col + nl] : cz();
+      y0t = A.oS[col + N];
+      if (r > 0) {
+        hp0 = L.ok ? hist_v[nl] : cz();
+        hp1 = L.ok ? hist_g[nl] : cz();
+        hp0t = hist_v[N];
+        hp1t = hist_g[N];
+      }
+    } else {
+      x0 = L.ok ? make_double2(A.meanS[nl], A.meanS[NY + nl]) : cz();
+      x0t = make_double2(A.meanS[N], A.meanS[NY + N]);
+      if (r > 0) {
+        if (L.ok) hp0 = make_double2(A.meanH[nl], A.meanH[NY + nl]);
+        hp0t = make_double2(A.meanH[N], A.meanH[NY + N]);
       }
     }
-    cplx hc[3], hct[3];
-    dct_fwd_pm<N, 3>(L, hn, hnt, A.kfwd, Sb, hc, hct);
-    wave_sync();
+    const RowCoef rcf = load_rc<N>(L, A.rc_pm);
+    const TauRec rs = load_rec<N>(L, A.op_pm + ((size_t)c * NOPS + r) * PM_OPSZ);
+    TauRec rv = rs;
+    cplx vw = cz();
+    double mi0 = 0.0, mi1 = 0.0, mi2 = 0.0, mi3 = 0.0, tv = 0.0, tvt = 0.0;
+    double iw = 0.0, iwt = 0.0, upl = 0.0, upt = 0.0, iiu = 0.0;
+    if (!mean) {
+      rv = load_rec<N>(L, A.op_pm + ((size_t)c * NOPS + 3) * PM_OPSZ);
+      if (A.wall_mode == WALL_OPP) {
+        vw = A.vw_opp[c];
+      } else {
+        const cplx o = A.vw_old[c], nn = A.vw_new[c];
+        vw = caxpy(o, A.s_ramp, csub(nn, o));
+      }
+      const double* mi = A.minv + ((size_t)c * 3 + r) * 4;
+      mi0 = mi[0];
+      mi1 = mi[1];
+      mi2 = mi[2];
+      mi3 = mi[3];
+      const double* vtab = A.vt_pm + ((size_t)c * 3 + r) * PM_ENTRIES;
+      tv = vtab[lane];
+      tvt = vtab[64];
+    } else {
+      iw = L.ok ? A.intw_pm[lane] : 0.0;
+      iwt = A.intw_pm[64];
+      const double* up = A.up_pm + (size_t)r * PM_ENTRIES;
+      upl = L.ok ? up[lane] : 0.0;
+      upt = up[64];
+      iiu = A.inv_int_up[r];
+    }
+
+    // tau rows of the implicit stage: T[cx X - gb h - zb h'] - ab X, cx = ab k^2 - lam0
+    const double cx = A.ab * k2 - A.lam0;
+    auto comb = [&](cplx x, cplx h, cplx hp) { return caxpy(caxpy(cscale(x, cx), -A.gb, h), -A.zb, hp); };
     if (!mean) {
       // explicit terms: h_v = -k^2 H2 - D(i al H1 + i be H3), h_g = i be H1 - i al H3
       const cplx T = cmuli(make_double2(al * hc[0].x + be * hc[2].x, al * hc[0].y + be * hc[2].y));
       const cplx Tt = cmuli(make_double2(al * hct[0].x + be * hct[2].x, al * hct[0].y + be * hct[2].y));
+      // phi0 = (D^2 - k^2) v, independent of the explicit terms
+      const cplx dv = cheb_d<N>(L, x0, x0t);
       const cplx dT = cheb_d<N>(L, T, Tt);
+      const cplx d2v = cheb_d<N>(L, dv, cz());
+      const cplx phi0 = caxpy(d2v, -k2, x0), phi0t = cscale(x0t, -k2);
       const cplx hv = csub(cscale(hc[1], -k2), dT);
       const cplx hvt = cscale(hct[1], -k2);
       const cplx hg = cmuli(make_double2(be * hc[0].x - al * hc[2].x, be * hc[0].y - al * hc[2].y));
       const cplx hgt = cmuli(make_double2(be * hct[0].x - al * hct[2].x, be * hct[0].y - al * hct[2].y));
-      cplx hvp = cz(), hgp = cz(), hvpt = cz(), hgpt = cz();
-      cplx* hist_v = A.hist + col;
-      cplx* hist_g = A.hist + (size_t)A.ncol * NY + col;
-      if (r > 0) {
-        hvp = L.ok ? hist_v[nl] : cz();
-        hgp = L.ok ? hist_g[nl] : cz();
-        hvpt = hist_v[N];
-        hgpt = hist_g[N];
-      }
       if (r < 2) {
         if (L.ok) {
           hist_v[nl] = hv;
@@ -368,57 +631,24 @@ __global__ __launch_bounds__(64 * CWAVES) void k_column_pm(ColArgsPm A) {
           hist_g[N] = hgt;
         }
       }
-      // phi0 = (D^2 - k^2) v, psi = (D^2 - k^2) phi0, chi = (D^2 - k^2) omega_y
-      const cplx v0 = L.ok ? A.vS[col + nl] : cz(), v0t = A.vS[col + N];
-      const cplx o0 = L.ok ? A.oS[col + nl] : cz(), o0t = A.oS[col + N];
-      const cplx dv = cheb_d<N>(L, v0, v0t);
-      const cplx d2v = cheb_d<N>(L, dv, cz());
-      const cplx phi0 = caxpy(d2v, -k2, v0), phi0t = cscale(v0t, -k2);
-      const cplx dphi = cheb_d<N>(L, phi0, phi0t);
-      const cplx d2phi = cheb_d<N>(L, dphi, cz());
-      const cplx psi = caxpy(d2phi, -k2, phi0), psit = cscale(phi0t, -k2);
-      const cplx dom = cheb_d<N>(L, o0, o0t);
-      const cplx d2om = cheb_d<N>(L, dom, cz());
-      const cplx chi = caxpy(d2om, -k2, o0), chit = cscale(o0t, -k2);
-      // right-hand sides of (D^2 - lam) X = rhs with lam = k^2 + lam0
-      auto rhs = [&](cplx x, cplx y, cplx h, cplx hp) {
-        cplx t = cscale(x, -A.lam0);
-        t = caxpy(t, -A.ab, y);
-        t = caxpy(t, -A.gb, h);
-        return caxpy(t, -A.zb, hp);
-      };
-      const cplx rp = rhs(phi0, psi, hv, hvp), rpt = rhs(phi0t, psit, hvt, hvpt);
-      const cplx ro = rhs(o0, chi, hg, hgp), rot = rhs(o0t, chit, hgt, hgpt);
       cplx R[2], Rt[2];
-      R[0] = tau_rows_pm<N>(L, rp, rpt, A.rc_pm, Rt[0]);
-      R[1] = tau_rows_pm<N>(L, ro, rot, A.rc_pm, Rt[1]);
-      const double* rec = A.op_pm + ((size_t)c * NOPS + r) * PM_OPSZ;
+      R[0] = tau_rows_pm<N>(L, comb(phi0, hv, hp0), comb(phi0t, hvt, hp0t), rcf, -A.ab, phi0, phi0t, Rt[0]);
+      R[1] = tau_rows_pm<N>(L, comb(y0, hg, hp1), comb(y0t, hgt, hp1t), rcf, -A.ab, y0, y0t, Rt[1]);
       const cplx zero2[2] = {cz(), cz()};
       cplx X[2], Xt[2];
-      tau_solve_pm<N, 2>(L, R, Rt, rec, zero2, zero2, X, Xt);
+      tau_solve_pm<N, 2>(L, R, Rt, rs, zero2, zero2, X, Xt);
       // v_p: (D^2 - k^2) v_p = phi_p, v_p(+1) = 0, v_p(-1) = v_w
-      cplx vw;
-      if (A.wall_mode == WALL_OPP) {
-        vw = A.vw_opp[c];
-      } else {
-        const cplx o = A.vw_old[c], nn = A.vw_new[c];
-        vw = caxpy(o, A.s_ramp, csub(nn, o));
-      }
       cplx Rv[1], Rvt[1];
-      Rv[0] = tau_rows_pm<N>(L, X[0], Xt[0], A.rc_pm, Rvt[0]);
-      const double* recv = A.op_pm + ((size_t)c * NOPS + 3) * PM_OPSZ;
+      Rv[0] = tau_rows_pm<N>(L, X[0], Xt[0], rcf, 0.0, cz(), cz(), Rvt[0]);
       const cplx gtop[1] = {cz()}, gbot[1] = {vw};
       cplx vp[1], vpt[1];
-      tau_solve_pm<N, 1>(L, Rv, Rvt, recv, gtop, gbot, vp, vpt);
+      tau_solve_pm<N, 1>(L, Rv, Rvt, rv, gtop, gbot, vp, vpt);
       // influence correction: dv/dy(+-1) = 0 with v = v_p + c0 v_+ + c1 v_-
       const double n2 = dn * dn;
       const cplx dtop = coef_sum<N>(L, vp[0], vpt[0], n2, dN * dN);
       const cplx dbot = coef_sum<N>(L, vp[0], vpt[0], L.odd ? n2 : -n2, -dN * dN);
-      const double* mi = A.minv + ((size_t)c * 3 + r) * 4;
-      const cplx c0 = make_double2(-(mi[0] * dtop.x + mi[1] * dbot.x), -(mi[0] * dtop.y + mi[1] * dbot.y));
-      const cplx c1 = make_double2(-(mi[2] * dtop.x + mi[3] * dbot.x), -(mi[2] * dtop.y + mi[3] * dbot.y));
-      const double* vtab = A.vt_pm + ((size_t)c * 3 + r) * PM_ENTRIES;
-      const double tv = vtab[lane], tvt = vtab[64];
+      const cplx c0 = make_double2(-(mi0 * dtop.x + mi1 * dbot.x), -(mi0 * dtop.y + mi1 * dbot.y));
+      const cplx c1 = make_double2(-(mi2 * dtop.x + mi3 * dbot.x), -(mi2 * dtop.y + mi3 * dbot.y));
       v = caxpy(caxpy(vp[0], tv, c0), L.odd ? -tv : tv, c1);
       vt = caxpy(caxpy(vpt[0], tvt, c0), tvt, c1);
       if (!L.ok) v = cz();
@@ -450,13 +680,8 @@ __global__ __launch_bounds__(64 * CWAVES) void k_column_pm(ColArgsPm A) {
                 isfinite(vt.y) && isfinite(omt.x) && isfinite(omt.y);
       if (r == 2 && __any(!ok) && lane == 0) atomicOr(A.status, STATUS_NONFINITE);
     } else {
-      // mean flow, packed X = U + i W; h = h_u + i h_w
+      // mean flow, packed X = U + i W; h = h_u + i h_w (k = 0)
       const cplx hm = make_double2(hc[0].x, hc[2].x), hmt = make_double2(hct[0].x, hct[2].x);
-      cplx hmp = cz(), hmpt = cz();
-      if (r > 0) {
-        if (L.ok) hmp = make_double2(A.meanH[nl], A.meanH[NY + nl]);
-        hmpt = make_double2(A.meanH[N], A.meanH[NY + N]);
-      }
       if (r < 2) {
         if (L.ok) {
           A.meanH[nl] = hm.x;
@@ -467,27 +692,15 @@ __global__ __launch_bounds__(64 * CWAVES) void k_column_pm(ColArgsPm A) {
           A.meanH[NY + N] = hmt.y;
         }
       }
-      const cplx X0 = L.ok ? make_double2(A.meanS[nl], A.meanS[NY + nl]) : cz();
-      const cplx X0t = make_double2(A.meanS[N], A.meanS[NY + N]);
-      const cplx d2X = cheb_d<N>(L, cheb_d<N>(L, X0, X0t), cz());
-      auto rhs = [&](cplx x, cplx y, cplx h, cplx hp) {
-        cplx t = cscale(x, -A.lam0);
-        t = caxpy(t, -A.ab, y);
-        t = caxpy(t, -A.gb, h);
-        return caxpy(t, -A.zb, hp);
-      };
-      const cplx rr = rhs(X0, d2X, hm, hmp), rrt = rhs(X0t, cz(), hmt, hmpt);
       cplx R[1], Rt[1];
-      R[0] = tau_rows_pm<N>(L, rr, rrt, A.rc_pm, Rt[0]);
-      const double* rec = A.op_pm + ((size_t)0 * NOPS + r) * PM_OPSZ;
+      R[0] = tau_rows_pm<N>(L, comb(x0, hm, hp0), comb(x0t, hmt, hp0t), rcf, -A.ab, x0, x0t, Rt[0]);
       const cplx z1[1] = {cz()};
       cplx Xs[1], Xst[1];
-      tau_solve_pm<N, 1>(L, R, Rt, rec, z1, z1, Xs, Xst);
-      double flux = wave_sum(L.ok ? A.intw_pm[lane] * Xs[0].x : 0.0) + A.intw_pm[64] * Xst[0].x;
-      const double P_r = (A.forcing == 0) ? (A.ub2 - flux) * A.inv_int_up[r] : A.px;
-      const double* up = A.up_pm + (size_t)r * PM_ENTRIES;
-      const double U = fma(P_r, L.ok ? up[lane] : 0.0, Xs[0].x);
-      const double Ut = fma(P_r, up[64], Xst[0].x);
+      tau_solve_pm<N, 1>(L, R, Rt, rs, z1, z1, Xs, Xst);
+      double flux = lane_sum(iw * Xs[0].x, L.even_row, L.low) + iwt * Xst[0].x;
+      const double P_r = (A.forcing == 0) ? (A.ub2 - flux) * iiu : A.px;
+      const double U = fma(P_r, upl, Xs[0].x);
+      const double Ut = fma(P_r, upt, Xst[0].x);
       v = L.ok ? make_double2(U, Xs[0].y) : cz();
       vt = make_double2(Ut, Xst[0].y);
       om = omt = cz();
@@ -500,13 +713,13 @@ __global__ __launch_bounds__(64 * CWAVES) void k_column_pm(ColArgsPm A) {
         A.meanS[NY + N] = vt.y;
       }
       const double n2 = dn * dn;
-      const double slope = wave_sum(L.ok ? (L.odd ? n2 : -n2) * v.x : 0.0) - dN * dN * vt.x;
+      const double slope = lane_sum(L.ok ? (L.odd ? n2 : -n2) * v.x : 0.0, L.even_row, L.low) - dN * dN * vt.x;
       if (A.accumulate_drag && lane == 0) A.drag_acc[0] += A.nu * slope;
       const bool ok = isfinite(v.x) && isfinite(v.y) && isfinite(vt.x) && isfinite(vt.y);
       if (r == 2 && __any(!ok) && lane == 0) atomicOr(A.status, STATUS_NONFINITE);
     }
   } else {
-    // reconstruct only: load the state
+    // load the state
     if (mean) {
       v = L.ok ? make_double2(A.meanS[nl], A.meanS[NY + nl]) : cz();
       vt = make_double2(A.meanS[N], A.meanS[NY + N]);
@@ -520,8 +733,8 @@ __global__ __launch_bounds__(64 * CWAVES) void k_column_pm(ColArgsPm A) {
   }
 
   // ---------------- reconstruction and inverse DCT for the next stage ----------------
-  if (!A.recon) return;
-  const bool want_end = (A.stage == 2 || A.stage < 0);
+  if constexpr (PART == PART_SOLVE) return;
+  const bool want_end = A.want_end != 0;
   cplx fld[6], fldt[6];  // (u, v, w, omega_x, omega_y, omega_z) coefficients
   cplx tau_hat;
   if (!mean) {
@@ -560,15 +773,16 @@ __global__ __launch_bounds__(64 * CWAVES) void k_column_pm(ColArgsPm A) {
     fld[5] = make_double2(-dX.x, 0.0);
     fldt[5] = cz();
     const double n2 = dn * dn;
-    const double slope = wave_sum(L.ok ? (L.odd ? n2 : -n2) * v.x : 0.0) - dN * dN * vt.x;
+    const double slope = lane_sum(L.ok ? (L.odd ? n2 : -n2) * v.x : 0.0, L.even_row, L.low) - dN * dN * vt.x;
     tau_hat = make_double2(A.nu * slope, 0.0);
   }
   cplx ph[6], pht[6];
-  dct_inv_pm<N, 6>(L, fld, fldt, A.kinv, Sb, ph, pht);
-  // write the six fields at the nodes (and the Hermitian partner column)
-  const size_t o = ((size_t)(lane < N ? lane : 0) * A.nkx + p) * nz + q;
+  dct_inv_pm<N, 6>(L, fld, fldt, A.kinv, ph, pht);
+  // write the six fields at the nodes (this lane: node n; lane 0 also node N) and the
+  // Hermitian partner column
+  const size_t o = ((size_t)nl * A.nkx + p) * nz + q;
   const size_t ot = ((size_t)N * A.nkx + p) * nz + q;
-  const size_t o2 = ((size_t)(lane < N ? lane : 0) * A.nkx + p) * nz + (partner >= 0 ? partner : 0);
+  const size_t o2 = ((size_t)nl * A.nkx + p) * nz + (partner >= 0 ? partner : 0);
   const size_t ot2 = ((size_t)N * A.nkx + p) * nz + (partner >= 0 ? partner : 0);
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
@@ -577,7 +791,7 @@ __global__ __launch_bounds__(64 * CWAVES) void k_column_pm(ColArgsPm A) {
       val.y = 0.0;
       valt.y = 0.0;
     }
-    if (lane < N) {
+    if (L.ok) {
       A.F6[(size_t)f * A.plane + o] = val;
       if (partner >= 0) A.F6[(size_t)f * A.plane + o2] = cconj(val);
     }
@@ -588,7 +802,7 @@ __global__ __launch_bounds__(64 * CWAVES) void k_column_pm(ColArgsPm A) {
   }
   if (want_end) {
     // opposition target from v at the sensing node (js < N), Hermitian partner too
-    if (lane == A.js) {
+    if (L.ok && L.n == A.js) {
       const cplx opp = mean ? cz() : cscale(ph[1], -A.opp_alpha);
       A.vw_opp[c] = opp;
       if (partner >= 0) A.vw_opp[partner] = cconj(opp);
@@ -601,13 +815,21 @@ __global__ __launch_bounds__(64 * CWAVES) void k_column_pm(ColArgsPm A) {
 }
 
 template <int N>
-int launch_pm(const ColArgsPm& A, hipStream_t st, KernelTimer* tm) {
+int launch_pm(const ColArgsPm& A, bool solve, bool recon, hipStream_t st, KernelTimer* tm) {
   const int blocks = (A.ncol + CWAVES - 1) / CWAVES;
-  const size_t shm = (size_t)CWAVES * 12 * (N / 2 + 1) * sizeof(cplx);
-  if (tm) (void)tm->begin(A.stage < 0 ? KC_RECON : KC_COLUMN, st);
-  hipLaunchKernelGGL(k_column_pm<N>, dim3(blocks), dim3(64 * CWAVES), shm, st, A);
-  if (tm) (void)tm->end(st);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
+  if (solve) {
+    if (tm) (void)tm->begin(KC_COLUMN, st);
+    hipLaunchKernelGGL((k_column_pm<N, PART_SOLVE>), dim3(blocks), dim3(64 * CWAVES), 0, st, A);
+    if (tm) (void)tm->end(st);
+    if (hipGetLastError() != hipSuccess) return -1;
+  }
+  if (recon) {
+    if (tm) (void)tm->begin(KC_RECON, st);
+    hipLaunchKernelGGL((k_column_pm<N, PART_RECON>), dim3(blocks), dim3(64 * CWAVES), 0, st, A);
+    if (tm) (void)tm->end(st);
+    if (hipGetLastError() != hipSuccess) return -1;
+  }
+  return 0;
 }
 
 }  // namespace
@@ -616,7 +838,9 @@ int launch_column_pass_pm(const Dims& d, DeviceState& s, const PhysParams& ph, i
                           int wall_mode, double s_ramp, int js, double opp_alpha, bool accumulate_drag,
                           bool recon, hipStream_t st, KernelTimer* tm) {
   ColArgsPm A;
-  A.recon = recon ? 1 : 0;
+  A.want_end = (stage == 2 || stage < 0) ? 1 : 0;
+  const bool solve = stage >= 0;
+  recon = recon || stage < 0;
   A.nkx = d.nkx;
   A.nz = d.nz;
   A.ncol = d.ncol;
@@ -660,9 +884,9 @@ int launch_column_pass_pm(const Dims& d, DeviceState& s, const PhysParams& ph, i
   A.drag_acc = s.drag_acc;
   A.status = s.status;
   switch (d.N) {
-    case 16: return launch_pm<16>(A, st, tm);
-    case 32: return launch_pm<32>(A, st, tm);
-    case 64: return launch_pm<64>(A, st, tm);
+    case 16: return launch_pm<16>(A, solve, recon, st, tm);
+    case 32: return launch_pm<32>(A, solve, recon, st, tm);
+    case 64: return launch_pm<64>(A, solve, recon, st, tm);
     default: return -1;
   }
 }

@@ -115,7 +115,7 @@ static void fill_parity_major(const Dims& d, std::vector<double>& T, const Table
     for (int l = 0; l < 64; ++l) {
       const int n = lane_n(l);
       T[L.kfwd + (size_t)jj * 64 + l] = lane_ok(l) ? (double)cosl(PI * (long double)((jj * n) % (2 * N)) / N) : 0.0;
-      T[L.kinv + (size_t)jj * 64 + l] = (l < N) ? (double)cosl(PI * (long double)((jj * l) % (2 * N)) / N) : 0.0;
+      T[L.kinv + (size_t)jj * 64 + l] = lane_ok(l) ? (double)cosl(PI * (long double)((jj * n) % (2 * N)) / N) : 0.0;
     }
   for (int n = 0; n <= N; ++n) {
     const int sl = pm_slot(N, n);
