@@ -13,6 +13,7 @@ step latency, the roofline entry of the dominant kernel measured with HIP events
 inside the timed region, and the oracle timed on the host as the CPU baseline.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,6 +30,36 @@ HBM_PEAK_GBS = 8000.0
 
 LARGER = dict(nx=64, ny=65, nz=64, lx=2 * np.pi, lz=np.pi, re_tau=180.0, dt_plus=0.05, obs_y_plus=15.0)
 MINIMAL = dict(nx=16, ny=65, nz=16, lx=2.67, lz=0.8, re_tau=180.0, dt_plus=0.05, obs_y_plus=15.0)
+
+
+# HBM bytes per launch on the larger channel, from two rocprofv3 --pmc runs of
+# "bench.py --steps 3 --warmup 1 --no-cpu-baseline --copy-probe" (FETCH_SIZE, then WRITE_SIZE,
+# KiB per dispatch; profiles/hbm_traffic_larger_channel.md).  FETCH_SIZE is scaled by 2.0 and
+# WRITE_SIZE by 1.0: what the two counters read for the 256 MiB device copy of --copy-probe
+# (131084 and 262144 KiB).  Each figure holds for the kernel source with the listed SHA-256
+# and is reported as null for any other source.
+TRAFFIC = {
+    "x_rows_fft_product": (2.8961e7, "plane_pass.hip", "6fdb128687b448a64b428d057242634abdcfe1413225da7354529975f39ccab6"),
+    "z_inverse_fft": (3.2054e7, "plane_pass.hip", "6fdb128687b448a64b428d057242634abdcfe1413225da7354529975f39ccab6"),
+    "z_forward_fft": (1.6092e7, "plane_pass.hip", "6fdb128687b448a64b428d057242634abdcfe1413225da7354529975f39ccab6"),
+    "column_pass": (3.7410e7, "column_pass.hip", "98d26b42ae1e6bd0dbb60aa652957fe16cb5e522e9e0d6f94ec5114583d5a5b2"),
+    "column_reconstruct": (1.8384e7, "column_pass.hip", "98d26b42ae1e6bd0dbb60aa652957fe16cb5e522e9e0d6f94ec5114583d5a5b2"),
+}
+
+
+def measured_traffic(kclass, workload):
+    """Profiled HBM bytes per launch of a kernel class on the larger channel, or None (other
+    workload, or the kernel source changed since the counters were taken)."""
+    if workload != "larger" or kclass not in TRAFFIC:
+        return None
+    nbytes, src, sha = TRAFFIC[kclass]
+    path = os.path.join(ROOT, "paper_2301_09889_amd", "csrc", src)
+    try:
+        with open(path, "rb") as fh:
+            ok = hashlib.sha256(fh.read()).hexdigest() == sha
+    except OSError:
+        ok = False
+    return nbytes if ok else None
 
 
 def resolved_points(g):
@@ -157,7 +188,7 @@ def main():
     alg = algorithmic_bytes_per_launch(dom, g)
     achieved = alg / avg_s / 1e9 if alg else None
     roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": measured_traffic(dom, args.workload),
             "avg_launch_us": avg_s * 1e6, "launches": n_launch,
             "algorithmic_bytes_per_launch": alg}
     kernels = {k: {"launches": v[0], "total_ms": round(v[1], 4), "avg_us": round(1e3 * v[1] / v[0], 3)}

@@ -1,6 +1,7 @@
 // Internal declarations shared by the host driver and the HIP kernels.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -92,9 +93,19 @@ struct KernelTimer {
   std::vector<hipEvent_t> pool;     // created lazily, reused
   std::vector<int> cls;             // class of each recorded pair
   size_t used = 0;                  // pairs recorded since the last read
-  hipError_t begin(int c, hipStream_t st);
-  hipError_t end(hipStream_t st);
+  // Event pair for the next launch of class c; hipExtLaunchKernel stamps them with that
+  // kernel's own start and end (no marker commands of their own in the stream).
+  hipError_t next(int c, hipEvent_t* start, hipEvent_t* stop);
 };
+
+// Launch, timed when tm is non-null.
+template <typename... KArgs, typename... Args>
+inline void timed_launch(KernelTimer* tm, int c, void (*kernel)(KArgs...), dim3 grid, dim3 block, size_t shm,
+                         hipStream_t st, Args... args) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (tm && tm->next(c, &a, &b) != hipSuccess) a = b = nullptr;
+  hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)shm, st, a, b, 0u, static_cast<KArgs>(args)...);
+}
 
 struct StageConsts {
   double lam0, ab, gb, zb;      // 1/(b nu dt), a/b, g/(b nu), z/(b nu)

@@ -818,15 +818,11 @@ template <int N>
 int launch_pm(const ColArgsPm& A, bool solve, bool recon, hipStream_t st, KernelTimer* tm) {
   const int blocks = (A.ncol + CWAVES - 1) / CWAVES;
   if (solve) {
-    if (tm) (void)tm->begin(KC_COLUMN, st);
-    hipLaunchKernelGGL((k_column_pm<N, PART_SOLVE>), dim3(blocks), dim3(64 * CWAVES), 0, st, A);
-    if (tm) (void)tm->end(st);
+    timed_launch(tm, KC_COLUMN, k_column_pm<N, PART_SOLVE>, dim3(blocks), dim3(64 * CWAVES), 0, st, A);
     if (hipGetLastError() != hipSuccess) return -1;
   }
   if (recon) {
-    if (tm) (void)tm->begin(KC_RECON, st);
-    hipLaunchKernelGGL((k_column_pm<N, PART_RECON>), dim3(blocks), dim3(64 * CWAVES), 0, st, A);
-    if (tm) (void)tm->end(st);
+    timed_launch(tm, KC_RECON, k_column_pm<N, PART_RECON>, dim3(blocks), dim3(64 * CWAVES), 0, st, A);
     if (hipGetLastError() != hipSuccess) return -1;
   }
   return 0;

@@ -22,7 +22,8 @@
 
 namespace chanenv {
 
-hipError_t KernelTimer::begin(int c, hipStream_t st) {
+hipError_t KernelTimer::next(int c, hipEvent_t* start, hipEvent_t* stop) {
+  *start = *stop = nullptr;
   if (!on) return hipSuccess;
   if (2 * (used + 1) > pool.size()) {
     for (int k = 0; k < 2; ++k) {
@@ -34,23 +35,15 @@ hipError_t KernelTimer::begin(int c, hipStream_t st) {
   }
   if (cls.size() < used + 1) cls.resize(used + 1);
   cls[used] = c;
-  return hipEventRecord(pool[2 * used], st);
-}
-
-hipError_t KernelTimer::end(hipStream_t st) {
-  if (!on) return hipSuccess;
-  const hipError_t err = hipEventRecord(pool[2 * used + 1], st);
+  *start = pool[2 * used];
+  *stop = pool[2 * used + 1];
   ++used;
-  return err;
+  return hipSuccess;
 }
 
-// Launch bracketed by the optional timer.
-#define TIMED_LAUNCH(tm, cls, st, ...)           \
-  do {                                           \
-    if (tm) (void)(tm)->begin((cls), (st));      \
-    hipLaunchKernelGGL(__VA_ARGS__);             \
-    if (tm) (void)(tm)->end((st));               \
-  } while (0)
+// Launch timed by the optional timer (argument order of hipLaunchKernelGGL after the class).
+#define TIMED_LAUNCH(tm, cls, st, kernel, grid, block, shm, st2, ...) \
+  timed_launch((tm), (cls), kernel, grid, block, shm, st2, __VA_ARGS__)
 
 // ----------------------------------------------------------------------------
 // Batched Stockham FFT in LDS (radix 3, 4, 2), used by all (x, z) transforms.

@@ -330,15 +330,9 @@ static int launch_plane2(const Dims& d, DeviceState& s, hipStream_t st, KernelTi
     if (pairs % c == 0 && 6 * c * FA <= 1024 && (size_t)6 * c * (MX + 1) * sizeof(cplx) <= 80 * 1024) P = c;
   const int thr = ((6 * P * FA + 63) / 64) * 64;
   const size_t shx = (size_t)(MX + (size_t)6 * P * (MX + 1)) * sizeof(cplx);
-  if (tm) (void)tm->begin(KC_ZINV, st);
-  hipLaunchKernelGGL(k_zinv2<MZ>, dim3(nblk, 6, d.ny), dim3(zthr), shz, st, A, PB);
-  if (tm) (void)tm->end(st);
-  if (tm) (void)tm->begin(KC_XROW, st);
-  hipLaunchKernelGGL(k_xrow2<MX>, dim3(pairs / P, d.ny), dim3(thr), shx, st, A, P);
-  if (tm) (void)tm->end(st);
-  if (tm) (void)tm->begin(KC_ZFWD, st);
-  hipLaunchKernelGGL(k_zfwd2<MZ>, dim3(nblk, 3, d.ny), dim3(zthr), shf, st, A, PB);
-  if (tm) (void)tm->end(st);
+  timed_launch(tm, KC_ZINV, k_zinv2<MZ>, dim3(nblk, 6, d.ny), dim3(zthr), shz, st, A, PB);
+  timed_launch(tm, KC_XROW, k_xrow2<MX>, dim3(pairs / P, d.ny), dim3(thr), shx, st, A, P);
+  timed_launch(tm, KC_ZFWD, k_zfwd2<MZ>, dim3(nblk, 3, d.ny), dim3(zthr), shf, st, A, PB);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
