@@ -27,6 +27,7 @@ if ROOT not in sys.path:
 
 METRIC = "DNS env-steps/sec & grid-pt-substeps/s vs plain; p50/p99 step latency"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
 
 LARGER = dict(nx=64, ny=65, nz=64, lx=2 * np.pi, lz=np.pi, re_tau=180.0, dt_plus=0.05, obs_y_plus=15.0)
 MINIMAL = dict(nx=16, ny=65, nz=16, lx=2.67, lz=0.8, re_tau=180.0, dt_plus=0.05, obs_y_plus=15.0)
@@ -91,6 +92,53 @@ def algorithmic_bytes_per_launch(kclass, g):
     return None
 
 
+def path_bytes_per_substep(g):
+    """Algorithmic bytes of one RK3/CN time step over the whole path: 74 complex-field passes
+    of 16 K bytes (13 per stage in the column pass, 9 per stage in the plane pass, 8 of
+    history per step)."""
+    return 74 * 16.0 * resolved_points(g)
+
+
+def path_flops_per_substep(g):
+    """Algorithmic FP64 flops of one time step: per stage the 9 padded 2D FFTs at every node
+    (2.5 M log2 M each), the 9 Chebyshev transforms of every column (as real FFTs of 2N),
+    the products and ~120 flops per unknown for the solves."""
+    nx, ny, nz = g["nx"], g["ny"], g["nz"]
+    mx, mz = 3 * nx // 2, 3 * nz // 2
+    n = ny - 1
+    m = mx * mz
+    fft = 9 * ny * 2.5 * m * np.log2(m)
+    dct = 9 * (nx // 2) * (nz - 1) * 2 * 2.5 * 2 * n * np.log2(2 * n)
+    return 3 * (fft + dct + 9 * m * ny + 120 * resolved_points(g))
+
+
+def copy_bandwidth_gbs(torch, nbytes=256 * 1024 * 1024, reps=10):
+    """Achievable device copy bandwidth (read + write bytes per second) of a plain copy."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    return 2.0 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+
+
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(g, opts_kw, n_sub_env, seed, budget_substeps):
     """The oracle (test infrastructure) on a bounded sample of the same workload,
     one BLAS thread."""
@@ -109,6 +157,7 @@ def cpu_baseline(g, opts_kw, n_sub_env, seed, budget_substeps):
         dt = time.perf_counter() - t0
     per_substep = dt / budget_substeps
     return {"value": 1.0 / (per_substep * n_sub_env), "unit": "env-steps/s", "cores": 1, "kind": "oracle",
+            "host_cpu": host_cpu_model(),
             "sample": f"{budget_substeps} time steps of one env step of the same workload "
                       f"({dt:.1f} s), scaled to {n_sub_env} time steps per env step; one BLAS thread"}
 
@@ -121,7 +170,7 @@ def main():
     ap.add_argument("--substeps", type=int, default=10, help="RK3 time steps per env step")
     ap.add_argument("--workload", choices=["larger", "minimal"], default="larger")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-substeps", type=int, default=4, help="time steps in the oracle sample")
+    ap.add_argument("--cpu-substeps", type=int, default=8, help="time steps in the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the benchmark, run a plain 256 MiB device copy (for scaling the HBM "
@@ -197,6 +246,15 @@ def main():
     value = args.steps / elapsed
     pts = g["nx"] * g["ny"] * g["nz"]
     lat_ms = np.array(lat) * 1e3
+    copy_gbs = copy_bandwidth_gbs(torch)
+    sub_s = elapsed / (args.steps * args.substeps)
+    path_gbs = path_bytes_per_substep(g) / sub_s / 1e9
+    path = {"alg_bytes_per_substep": path_bytes_per_substep(g), "achieved_GBs": path_gbs,
+            "frac_hbm_peak": path_gbs / HBM_PEAK_GBS, "frac_copy": path_gbs / copy_gbs,
+            "alg_flops_per_substep": path_flops_per_substep(g),
+            "achieved_TFs_fp64": path_flops_per_substep(g) / sub_s / 1e12,
+            "frac_fp64_peak": path_flops_per_substep(g) / sub_s / 1e12 / FP64_PEAK_TFS}
+    roof["frac_copy"] = (achieved / copy_gbs) if achieved else None
     out = {
         "metric": METRIC,
         "value": value,
@@ -215,6 +273,8 @@ def main():
         "grid_pt_substeps_per_s": value * args.substeps * pts,
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "roofline": roof,
+        "path_roofline": path,
+        "copy_bandwidth_GBs": copy_gbs,
         "kernels": kernels,
         "timing_pass_ms_per_step": 1e3 * elapsed_timed / args.steps,
     }
