@@ -162,13 +162,108 @@ def cpu_baseline(g, opts_kw, n_sub_env, seed, budget_substeps):
                       f"({dt:.1f} s), scaled to {n_sub_env} time steps per env step; one BLAS thread"}
 
 
+def batched_specs(n):
+    """Uneven mix: 16x65x16 and 32x65x32 minimal-box channels alternating, Re_tau 180 / 100 in
+    pairs, opposition control and Gaussian actions in fours; seed = channel index."""
+    specs = []
+    for i in range(n):
+        m = 16 if i % 2 == 0 else 32
+        specs.append(dict(nx=m, ny=65, nz=m, lx=2.67, lz=0.8, re_tau=180.0 if (i // 2) % 2 == 0 else 100.0,
+                          dt_plus=0.05, obs_y_plus=15.0, external=(i // 4) % 2 == 1, seed=i))
+    return specs
+
+
+def run_batched(args, torch, b, gaussian_action):
+    """Many channels advanced together (one launch per kernel and grid shape), against the same
+    channels advanced one per launch."""
+    specs = batched_specs(args.channels)
+    torch.cuda.set_device(0)
+    envs, acts = [], []
+    for sp in specs:
+        grid = b.ChanGrid(sp["nx"], sp["ny"], sp["nz"], sp["lx"], sp["lz"], sp["re_tau"], sp["dt_plus"],
+                          sp["obs_y_plus"])
+        e = b.ChanEnv(grid, b.make_opts(controller=0 if sp["external"] else 1))
+        e.reset(sp["seed"])
+        envs.append(e)
+        acts.append(torch.tensor(gaussian_action(1000 + sp["seed"], sp["nz"], sp["nx"]), dtype=torch.float64,
+                                 device="cuda") if sp["external"] else None)
+    batch = b.ChanBatch(envs)
+    for _ in range(args.warmup):
+        batch.step(acts, args.substeps)
+    torch.cuda.synchronize()
+    lat, codes = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        codes = batch.step(acts, args.substeps)
+        lat.append(time.perf_counter() - s0)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    active = sum(1 for c in codes if c == 0)
+    value = active * args.steps / elapsed
+    b.chan_batch_set_timing(batch.handle, 1)
+    batch.step(acts, args.substeps)
+    kt = b.chan_batch_timing_read(batch.handle)
+    b.chan_batch_set_timing(batch.handle, 0)
+    # the plain form: the same kind of channels, one channel per launch
+    sub = list(range(min(16, len(envs))))
+    for i in sub:
+        envs[i].step(acts[i], args.substeps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        for i in sub:
+            envs[i].step(acts[i], args.substeps)
+    torch.cuda.synchronize()
+    plain = len(sub) * reps / (time.perf_counter() - t1)
+    batch.close()
+    path_bytes = sum(path_bytes_per_substep(sp) for k, sp in enumerate(specs) if codes[k] == 0)
+    sub_s = elapsed / (args.steps * args.substeps)
+    copy_gbs = copy_bandwidth_gbs(torch)
+    lat_ms = np.array(lat) * 1e3
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "env-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"batched: {len(specs)} minimal-box channels (2.67 x 2 x 0.8 h), 16x65x16 and "
+                               f"32x65x32 alternating, Re_tau 180/100, opposition or Gaussian wall actions, "
+                               f"10 time steps per env step, one batch step advances every channel",
+                   "channels": len(specs), "active_channels": active, "substeps_per_env_step": args.substeps},
+        "grid_pt_substeps_per_s": sum(sp["nx"] * sp["ny"] * sp["nz"] for k, sp in enumerate(specs) if codes[k] == 0)
+        * args.steps * args.substeps / elapsed,
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
+        "plain_one_channel_per_launch": {"value": plain, "unit": "env-steps/s",
+                                         "sample": f"channels 0-{len(sub) - 1} of the mix, each stepped alone"},
+        "batched_over_plain": value / plain,
+        "roofline": None,
+        "path_roofline": {"alg_bytes_per_substep": path_bytes, "achieved_GBs": path_bytes / sub_s / 1e9,
+                          "frac_hbm_peak": path_bytes / sub_s / 1e9 / HBM_PEAK_GBS,
+                          "frac_copy": path_bytes / sub_s / 1e9 / copy_gbs},
+        "copy_bandwidth_GBs": copy_gbs,
+        "kernels_ms_per_env_step": {k: round(v[1], 3) for k, v in kt.items() if v[0] > 0},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100, help="timed env steps")
     ap.add_argument("--warmup", type=int, default=5, help="untimed env steps")
     ap.add_argument("--substeps", type=int, default=10, help="RK3 time steps per env step")
-    ap.add_argument("--workload", choices=["larger", "minimal"], default="larger")
+    ap.add_argument("--workload", choices=["larger", "minimal", "batched"], default="larger")
+    ap.add_argument("--channels", type=int, default=256, help="channels of the batched workload")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-substeps", type=int, default=8, help="time steps in the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -188,6 +283,9 @@ def main():
     import paper_2301_09889_amd.binding as b
     from synth import gaussian_action
 
+    if args.workload == "batched":
+        run_batched(args, torch, b, gaussian_action)
+        return
     g = LARGER if args.workload == "larger" else MINIMAL
     if args.workload == "larger":
         opts_kw = dict(ic_profile=1, action_mode=1)    # Reichardt mean; action held over the env step

@@ -169,19 +169,59 @@ size_t chan_env_footprint_bytes(const chan_grid_t* grid, const chan_opts_t* opts
 void chan_env_destroy(struct chan_env* env);
 
 /* Kernel timing (instrumentation for benchmarks).  chan_env_set_timing(env, 1)
- * clears the counters and brackets every later kernel launch of the env with a
- * pair of HIP events on the env's stream; (env, 0) stops recording.  The event
- * records add a little queue work, so throughput runs leave timing off.
+ * clears the counters and times every later kernel launch of the env's own steps
+ * with a pair of HIP events that hipExtLaunchKernel stamps with the kernel's start
+ * and end on the env's stream; (env, 0) stops recording.  Timed launches are
+ * serialised by the runtime, so throughput runs leave timing off.
  * chan_env_timing_read synchronises the stream and fills, for the first nclass
- * kernel classes, the number of launches and the summed event time in ms since
+ * kernel classes, the number of launches and the summed kernel time in ms since
  * timing was enabled; it returns the number of classes (>= 0) or a negative
- * code.  Classes (chan_kernel_class_name): 0 column_pass, 1 z_inverse_fft,
- * 2 x_rows_fft_product, 3 z_forward_fft, 4 action_ingest, 5 outputs,
- * 6 bookkeeping, 7 column_reconstruct (the reconstruct-only column pass that ends
- * every env step).  Errors: CHAN_EINVAL, CHAN_EDEVICE. */
+ * code.  Classes (chan_kernel_class_name): 0 column_pass (the implicit solve of a
+ * stage), 1 z_inverse_fft, 2 x_rows_fft_product, 3 z_forward_fft, 4 action_ingest,
+ * 5 outputs, 6 bookkeeping, 7 column_reconstruct (velocity/vorticity reconstruction
+ * and inverse Chebyshev transform after each stage, and from the stored state at
+ * the end of every env step).  Errors: CHAN_EINVAL, CHAN_EDEVICE. */
 int chan_env_set_timing(struct chan_env* env, int32_t enable);
 int chan_env_timing_read(struct chan_env* env, int32_t nclass, int64_t* launches, double* ms);
 const char* chan_kernel_class_name(int32_t cls);
+
+/* ---- Batches: many channels advanced together ----
+ * Serving many RL workers means stepping many independent channels at once (they
+ * may differ in grid, Re_tau, dt, controller and options).  A batch advances a
+ * fixed set of existing
+ * envs with one launch per kernel and grid shape instead of one per env, so that
+ * small channels fill the GPU.  Each channel computes exactly what chan_env_step
+ * would (the same kernels on the same per-channel data): results are bitwise the
+ * same alone and in the batch.
+ *
+ * chan_batch_create: n envs (n >= 1), each listed once, all created on the same
+ * HIP stream and device; the batch refers to them and does not own them (destroy
+ * the batch first).  Errors: CHAN_EINVAL (empty, null, duplicate, mixed streams,
+ * more than 65535 / N_y channels of one shape), CHAN_ENOMEM, CHAN_EDEVICE.
+ *
+ * chan_batch_step: one env step (n_substeps time steps) of every env, in the
+ * order given at creation.  actions, obs, tau_w and drag are host arrays of n
+ * device pointers with the meaning of chan_env_step's arguments (any entry may be
+ * NULL; a NULL array means all NULL).  results, if non-NULL, receives n codes:
+ * CHAN_OK; CHAN_ENONFINITE for a rejected action (that env untouched) or a
+ * non-finite state (that env poisoned); CHAN_ESTATE for an env without a flow
+ * state or poisoned, which is skipped (untouched, outputs not written) while the
+ * others advance.  Returns CHAN_OK if every env succeeded, else the first failing
+ * env's code; CHAN_ESTATE (nothing run) if no env has a valid state; CHAN_EINVAL
+ * for n_substeps < 1; CHAN_EDEVICE.
+ * Synchronises the stream before returning.  Calls on one batch, or on batches
+ * sharing an env, must not overlap.
+ *
+ * chan_batch_set_timing / chan_batch_timing_read: as for an env, for the batch's
+ * launches.  chan_batch_size: number of envs (0 for NULL). */
+typedef struct chan_batch chan_batch;
+int chan_batch_create(int32_t n, struct chan_env* const* envs, struct chan_batch** out);
+int chan_batch_step(struct chan_batch* batch, const double* const* actions, int32_t n_substeps,
+                    double* const* obs, double* const* tau_w, double* const* drag, int32_t* results);
+void chan_batch_destroy(struct chan_batch* batch);
+int32_t chan_batch_size(const struct chan_batch* batch);
+int chan_batch_set_timing(struct chan_batch* batch, int32_t enable);
+int chan_batch_timing_read(struct chan_batch* batch, int32_t nclass, int64_t* launches, double* ms);
 
 /* Static string naming an error code. */
 const char* chan_strerror(int code);

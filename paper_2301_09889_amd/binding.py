@@ -107,6 +107,18 @@ def load_library():
     lib.chan_env_timing_read.restype = ctypes.c_int
     lib.chan_kernel_class_name.argtypes = [ctypes.c_int32]
     lib.chan_kernel_class_name.restype = ctypes.c_char_p
+    lib.chan_batch_create.argtypes = [ctypes.c_int32, P(vp), P(vp)]
+    lib.chan_batch_create.restype = ctypes.c_int
+    lib.chan_batch_step.argtypes = [vp, P(vp), ctypes.c_int32, P(vp), P(vp), P(vp), P(ctypes.c_int32)]
+    lib.chan_batch_step.restype = ctypes.c_int
+    lib.chan_batch_destroy.argtypes = [vp]
+    lib.chan_batch_destroy.restype = None
+    lib.chan_batch_size.argtypes = [vp]
+    lib.chan_batch_size.restype = ctypes.c_int32
+    lib.chan_batch_set_timing.argtypes = [vp, ctypes.c_int32]
+    lib.chan_batch_set_timing.restype = ctypes.c_int
+    lib.chan_batch_timing_read.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int64), P(ctypes.c_double)]
+    lib.chan_batch_timing_read.restype = ctypes.c_int
     _LIB = lib
     return lib
 
@@ -189,6 +201,51 @@ def chan_env_destroy(h):
     load_library().chan_env_destroy(h)
 
 
+def _ptr_array(ptrs):
+    """ctypes array of device pointers (0 / None -> NULL), or None for an absent list."""
+    if ptrs is None:
+        return None
+    return (ctypes.c_void_p * len(ptrs))(*[ctypes.c_void_p(p or None) for p in ptrs])
+
+
+def chan_batch_create(env_handles):
+    hs = (ctypes.c_void_p * len(env_handles))(*env_handles)
+    h = ctypes.c_void_p()
+    rc = load_library().chan_batch_create(len(env_handles), hs, ctypes.byref(h))
+    if rc != CHAN_OK:
+        raise ChanError(rc, "chan_batch_create")
+    return h
+
+
+def chan_batch_step(h, action_ptrs, n_substeps, obs_ptrs, tau_ptrs, drag_ptrs, results=None):
+    """Pointer lists hold one device address (or 0) per env; results, if given, is a ctypes
+    int32 array of the batch size."""
+    return load_library().chan_batch_step(h, _ptr_array(action_ptrs), int(n_substeps), _ptr_array(obs_ptrs),
+                                          _ptr_array(tau_ptrs), _ptr_array(drag_ptrs), results)
+
+
+def chan_batch_destroy(h):
+    load_library().chan_batch_destroy(h)
+
+
+def chan_batch_size(h):
+    return load_library().chan_batch_size(h)
+
+
+def chan_batch_set_timing(h, enable):
+    return load_library().chan_batch_set_timing(h, int(bool(enable)))
+
+
+def chan_batch_timing_read(h, nclass=16):
+    """Returns {class name: (launches, total ms)}."""
+    launches = (ctypes.c_int64 * nclass)()
+    ms = (ctypes.c_double * nclass)()
+    n = load_library().chan_batch_timing_read(h, nclass, launches, ms)
+    if n < 0:
+        raise ChanError(n, "chan_batch_timing_read")
+    return {chan_kernel_class_name(k): (launches[k], ms[k]) for k in range(min(n, nclass))}
+
+
 def make_grid(nx, ny, nz, lx, lz, re_tau, dt_plus, obs_y_plus):
     return ChanGrid(nx, ny, nz, lx, lz, re_tau, dt_plus, obs_y_plus)
 
@@ -254,6 +311,47 @@ class ChanEnv:
     def close(self):
         if self.handle:
             chan_env_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ChanBatch:
+    """Several ChanEnv (same stream) advanced together; each env's step outputs land in that
+    env's own obs / tau_w / drag tensors, exactly as ChanEnv.step would write them."""
+
+    def __init__(self, envs):
+        self.envs = list(envs)
+        self.handle = chan_batch_create([e.handle for e in self.envs])
+        self.results = (ctypes.c_int32 * len(self.envs))()
+
+    def step(self, actions, n_substeps):
+        """actions: list of float64 device tensors (nz, nx) or None per env (or None for all).
+        Returns the per-env result codes; raises if the call itself failed before running."""
+        aptrs = []
+        for k, e in enumerate(self.envs):
+            a = actions[k] if actions is not None else None
+            if a is not None:
+                assert a.dtype == e.torch.float64 and a.is_contiguous()
+                assert tuple(a.shape) == (e.grid.nz, e.grid.nx)
+            aptrs.append(a.data_ptr() if a is not None else 0)
+        for k in range(len(self.envs)):
+            self.results[k] = CHAN_OK
+        rc = chan_batch_step(self.handle, aptrs, n_substeps, [e.obs.data_ptr() for e in self.envs],
+                             [e.tau_w.data_ptr() for e in self.envs], [e.drag.data_ptr() for e in self.envs],
+                             self.results)
+        codes = list(self.results)
+        if rc != CHAN_OK and all(c == CHAN_OK for c in codes):
+            raise ChanError(rc, "chan_batch_step")
+        return codes
+
+    def close(self):
+        if self.handle:
+            chan_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

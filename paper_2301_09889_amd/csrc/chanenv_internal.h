@@ -71,7 +71,7 @@ struct DeviceState {
   double *meanS, *meanH;        // [2][n] U, W ; [2][n] previous-stage h_u, h_w
   cplx *F6, *Z6, *W3, *H3;      // plane-pass fields
   cplx *vw_old, *vw_new, *vw_opp, *tauw;  // [c]
-  cplx *tmp2d;                  // [3][nz][nkx] small 2-D transform scratch
+  cplx *tmp2d;                  // [OUT_SLOTS][nz][nkx] small 2-D transform scratch
   double *tab;                  // operator tables (one allocation, see TableLayout)
   double *drag_acc;             // [1]
   int *status;                  // [1]
@@ -79,6 +79,72 @@ struct DeviceState {
   const double *cosk, *rc, *optab, *vt, *minv, *up, *inv_int_up, *alpha, *beta;
   const double *kfwd, *kinv, *rc_pm, *intw_pm, *op_pm, *vt_pm, *up_pm;
   const cplx *twz, *twx, *twnx, *twnz;
+};
+
+// ---- per-channel launch arguments (device-resident arrays, one entry per channel) ----
+// A launch covers every channel of one grid shape (column and plane kernels) or of the whole
+// batch (the per-env-step kernels); a single env is a batch of one, so a channel runs the
+// same code alone and in a mix.
+
+// N <= 64 column kernels: everything of one channel that does not change between launches.
+struct ColChan {
+  int nkx, nz, ncol;
+  int ext;                      // 1: external action (ramped or held wall velocity); 0: opposition
+  int hold;                     // external action held for the whole env step
+  int forcing, js;
+  double lam0[3], ab[3], gb[3], zb[3];  // per RK stage: 1/(b nu dt), a/b, g/(b nu), z/(b nu)
+  double nu, opp_alpha, ub2, px;
+  size_t plane;                 // elements per field in F6 / H3 (ny nkx nz)
+  cplx *vS, *oS, *hist;
+  double *meanS, *meanH;
+  const cplx* H3;
+  cplx* F6;
+  const cplx *vw_old, *vw_new;
+  cplx *vw_opp, *tauw;
+  const double *kfwd, *kinv, *rc_pm, *intw_pm, *op_pm, *vt_pm, *up_pm, *minv, *inv_int_up, *alpha, *beta;
+  double* drag_acc;
+  int* status;
+};
+
+// The launch-wide part: RK stage (-1: reconstruction from the stored state, which ends an env
+// step), time step m of n_sub in the env step.
+struct ColStage {
+  int stage, m, n_sub;
+};
+
+// Plane-pass kernels of one channel.
+struct PlaneChan {
+  int ny, nkx, nz;
+  double scale;        // 1 / (M_x M_z)
+  const cplx* F6;
+  cplx* Z6;
+  cplx* W3;
+  cplx* H3;
+  const cplx* twz;     // exp(-2 pi i k / M_z)
+  const cplx* twx;     // exp(-2 pi i k / M_x)
+  const int* status;
+};
+
+// Per-env-step kernels (begin, action ingest, end, outputs) of one channel; rebuilt for
+// every step call (action and output pointers).
+constexpr int OUT_SLOTS = 4;   // u, v, w at the sensing node, and tau_w
+struct StepChan {
+  int nx, nz, nkx, ncol, n_sub;
+  int skip;                     // not advanced this call (no valid state): marked like a
+                                // rejected action, so every kernel leaves it untouched
+  int zero_vw;                  // external action and none given: v_w,new := 0
+  int copy_vw;                  // external action: v_w,old := v_w,new at the end
+  double clip;
+  const double* action;         // [nz][nx] device, or null
+  double* drag_out;             // or null
+  const cplx* out_src[OUT_SLOTS];  // spectra [p][q] (obs: the F6 plane at the sensing node)
+  double* out_dst[OUT_SLOTS];      // [nz][nx] device, or null
+  cplx *vw_new, *vw_old;
+  cplx* tmp2d;                  // [OUT_SLOTS][nz][nkx]
+  const cplx *twnx, *twnz;
+  double* drag_acc;
+  int* status;
+  int* status_out;              // batch-wide status array entry (read back once per call)
 };
 
 // Kernel classes for the optional event timing.
@@ -112,23 +178,26 @@ struct StageConsts {
 };
 
 // Kernel launchers (kernels.hip).  tm may be null.
-int launch_begin_step(const Dims& d, DeviceState& s, bool zero_vw_new, hipStream_t st, KernelTimer* tm);
-int launch_ingest(const Dims& d, DeviceState& s, const double* action, double clip, hipStream_t st,
+// Per-env-step kernels over nch channels of any shapes (max_* size the LDS and the grid).
+int launch_begin_step(const StepChan* d_step, int nch, hipStream_t st, KernelTimer* tm);
+int launch_ingest(const StepChan* d_step, int nch, int max_nx, int max_nz, int max_nkx, hipStream_t st,
                   KernelTimer* tm);
-int launch_plane_pass(const Dims& d, DeviceState& s, hipStream_t st, KernelTimer* tm);
-// Column pass; stage -1 only reconstructs the plane-pass input from the state.  With
-// recon false the pass stops after the solve (the caller reconstructs separately).
-int launch_column_pass_pm(const Dims& d, DeviceState& s, const PhysParams& ph, int stage,
-                          const StageConsts& sc, int wall_mode, double s_ramp, int js,
-                          double opp_alpha, bool accumulate_drag, bool recon, hipStream_t st,
-                          KernelTimer* tm);
+int launch_finish_step(const StepChan* d_step, int nch, hipStream_t st, KernelTimer* tm);
+int launch_outputs(const StepChan* d_step, int nch, int max_nx, int max_nz, int max_nkx, hipStream_t st,
+                   KernelTimer* tm);
+// Plane pass over nch channels of one shape (M_x, M_z from nx, nz).
+int launch_plane_pass(const Dims& d, const PlaneChan* d_plane, int nch, hipStream_t st, KernelTimer* tm);
+// N <= 64 column pass over nch channels of one shape: the solve of stage S.stage (if solve)
+// and/or the reconstruction that follows it (if recon; S.stage -1: reconstruction only).
+// d_col: the channels' arguments on the device; h_col (optional): the same on the host, used
+// to pass a single channel's arguments by value.
+int launch_column_pm(const Dims& d, const ColChan* d_col, const ColChan* h_col, int nch, const ColStage& S,
+                     bool solve, bool recon, hipStream_t st, KernelTimer* tm);
+// General column pass (any N, one channel per launch); stage -1 only reconstructs the
+// plane-pass input from the state; with recon false the pass stops after the solve.
 int launch_column_pass(const Dims& d, DeviceState& s, const PhysParams& ph, int stage,
                        const StageConsts& sc, int wall_mode, double s_ramp, int js,
                        double opp_alpha, bool accumulate_drag, bool recon, hipStream_t st,
                        KernelTimer* tm);
-int launch_finish_step(const Dims& d, DeviceState& s, bool copy_vw, double* drag, int nsub,
-                       hipStream_t st, KernelTimer* tm);
-int launch_outputs(const Dims& d, DeviceState& s, int js, uint32_t obs_mask, double* obs,
-                   double* tau_w, hipStream_t st, KernelTimer* tm);
 
 }  // namespace chanenv

@@ -35,27 +35,6 @@ namespace {
 
 constexpr int CWAVES = 4;  // columns (wavefronts) per block
 
-struct ColArgsPm {
-  int nkx, nz, ncol;
-  int stage;            // 0, 1, 2; -1: reconstruct only
-  int wall_mode;
-  double s_ramp;
-  double lam0, ab, gb, zb;
-  double nu, opp_alpha, ub2, px;
-  int forcing, js, accumulate_drag;
-  int want_end;         // reconstruction that ends an env step: also the opposition target
-                        // and the wall shear
-  size_t plane;         // elements per field in F6 / H3 (ny nkx nz)
-  cplx *vS, *oS, *hist;
-  double *meanS, *meanH;
-  const cplx* H3;
-  cplx* F6;
-  const cplx *vw_old, *vw_new;
-  cplx *vw_opp, *tauw;
-  const double *kfwd, *kinv, *rc_pm, *intw_pm, *op_pm, *vt_pm, *up_pm, *minv, *inv_int_up, *alpha, *beta;
-  double* drag_acc;
-  int* status;
-};
 
 // ---- cross-lane moves without LDS (gfx950 DPP and permlane swaps) ----
 // A row is 16 lanes.  DPP controls used here:
@@ -515,13 +494,20 @@ __device__ __forceinline__ cplx coef_sum(const Lane<N>& L, cplx x, cplx xt, doub
 // follows the last stage of an env step, from the stored state).
 constexpr int PART_SOLVE = 0, PART_RECON = 1;
 
+// Time fraction at the end of RK stage r (c_end of the stage).
+__device__ __forceinline__ double stage_end(int r) { return r == 0 ? 8.0 / 15.0 : (r == 1 ? 2.0 / 3.0 : 1.0); }
+
+// One block of CWAVES columns (block cb of the channel's columns).
 template <int N, int PART>
-__global__ __launch_bounds__(64 * CWAVES, 2) void k_column_pm(ColArgsPm A) {
+__device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S, int cb) {
   constexpr int NY = N + 1;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int c = __builtin_amdgcn_readfirstlane(blockIdx.x * CWAVES + wave);  // wave-uniform column
+  // wave-uniform column
+  const int c = __builtin_amdgcn_readfirstlane(cb * CWAVES + wave);
   if (c >= A.ncol) return;
-  if (*A.status & STATUS_BAD_ACTION) return;
+  // a rejected action skips the step: tested before the first store, loaded here so that
+  // its latency overlaps the loads below
+  const int status0 = *A.status;
   const int nz = A.nz;
   const int p = c / nz, q = c - p * nz;
   if (q == nz / 2) return;            // Nyquist: never stored
@@ -538,7 +524,8 @@ __global__ __launch_bounds__(64 * CWAVES, 2) void k_column_pm(ColArgsPm A) {
   cplx v, om, vt, omt;  // state after this call (mean: v = U + i W, om = 0)
 
   if constexpr (PART == PART_SOLVE) {
-    const int r = A.stage;
+    const int r = S.stage;
+    const double lam0 = A.lam0[r], ab = A.ab[r], gb = A.gb[r], zb = A.zb[r];
     // H1, H2, H3 at node j of this column; the mean flow sees the real parts of H1, H3 only
     const cplx* h3 = A.H3 + (size_t)p * nz + q;
     const size_t jstride = (size_t)A.nkx * nz;
@@ -549,6 +536,7 @@ __global__ __launch_bounds__(64 * CWAVES, 2) void k_column_pm(ColArgsPm A) {
     };
     cplx hc[3], hct[3];
     dct_fwd_pm<N, 3>(L, loadH, A.kfwd, hc, hct);
+    if (status0 & STATUS_BAD_ACTION) return;
     // state (v, omega_y; mean: X = U + i W) and the previous stage's explicit terms
     // (h_v, h_g; mean: h_u + i h_w)
     cplx x0, x0t, y0 = cz(), y0t = cz();
@@ -582,11 +570,12 @@ __global__ __launch_bounds__(64 * CWAVES, 2) void k_column_pm(ColArgsPm A) {
     double iw = 0.0, iwt = 0.0, upl = 0.0, upt = 0.0, iiu = 0.0;
     if (!mean) {
       rv = load_rec<N>(L, A.op_pm + ((size_t)c * NOPS + 3) * PM_OPSZ);
-      if (A.wall_mode == WALL_OPP) {
+      if (!A.ext) {
         vw = A.vw_opp[c];
-      } else {
+      } else {  // wall velocity ramped from the old to the new action (or the new one held)
+        const double s_ramp = A.hold ? 1.0 : (S.m + stage_end(r)) / (double)S.n_sub;
         const cplx o = A.vw_old[c], nn = A.vw_new[c];
-        vw = caxpy(o, A.s_ramp, csub(nn, o));
+        vw = caxpy(o, s_ramp, csub(nn, o));
       }
       const double* mi = A.minv + ((size_t)c * 3 + r) * 4;
       mi0 = mi[0];
@@ -606,8 +595,8 @@ __global__ __launch_bounds__(64 * CWAVES, 2) void k_column_pm(ColArgsPm A) {
     }
 
     // tau rows of the implicit stage: T[cx X - gb h - zb h'] - ab X, cx = ab k^2 - lam0
-    const double cx = A.ab * k2 - A.lam0;
-    auto comb = [&](cplx x, cplx h, cplx hp) { return caxpy(caxpy(cscale(x, cx), -A.gb, h), -A.zb, hp); };
+    const double cx = ab * k2 - lam0;
+    auto comb = [&](cplx x, cplx h, cplx hp) { return caxpy(caxpy(cscale(x, cx), -gb, h), -zb, hp); };
     if (!mean) {
       // explicit terms: h_v = -k^2 H2 - D(i al H1 + i be H3), h_g = i be H1 - i al H3
       const cplx T = cmuli(make_double2(al * hc[0].x + be * hc[2].x, al * hc[0].y + be * hc[2].y));
@@ -632,8 +621,8 @@ __global__ __launch_bounds__(64 * CWAVES, 2) void k_column_pm(ColArgsPm A) {
         }
       }
       cplx R[2], Rt[2];
-      R[0] = tau_rows_pm<N>(L, comb(phi0, hv, hp0), comb(phi0t, hvt, hp0t), rcf, -A.ab, phi0, phi0t, Rt[0]);
-      R[1] = tau_rows_pm<N>(L, comb(y0, hg, hp1), comb(y0t, hgt, hp1t), rcf, -A.ab, y0, y0t, Rt[1]);
+      R[0] = tau_rows_pm<N>(L, comb(phi0, hv, hp0), comb(phi0t, hvt, hp0t), rcf, -ab, phi0, phi0t, Rt[0]);
+      R[1] = tau_rows_pm<N>(L, comb(y0, hg, hp1), comb(y0t, hgt, hp1t), rcf, -ab, y0, y0t, Rt[1]);
       const cplx zero2[2] = {cz(), cz()};
       cplx X[2], Xt[2];
       tau_solve_pm<N, 2>(L, R, Rt, rs, zero2, zero2, X, Xt);
@@ -693,7 +682,7 @@ __global__ __launch_bounds__(64 * CWAVES, 2) void k_column_pm(ColArgsPm A) {
         }
       }
       cplx R[1], Rt[1];
-      R[0] = tau_rows_pm<N>(L, comb(x0, hm, hp0), comb(x0t, hmt, hp0t), rcf, -A.ab, x0, x0t, Rt[0]);
+      R[0] = tau_rows_pm<N>(L, comb(x0, hm, hp0), comb(x0t, hmt, hp0t), rcf, -ab, x0, x0t, Rt[0]);
       const cplx z1[1] = {cz()};
       cplx Xs[1], Xst[1];
       tau_solve_pm<N, 1>(L, R, Rt, rs, z1, z1, Xs, Xst);
@@ -714,7 +703,7 @@ __global__ __launch_bounds__(64 * CWAVES, 2) void k_column_pm(ColArgsPm A) {
       }
       const double n2 = dn * dn;
       const double slope = lane_sum(L.ok ? (L.odd ? n2 : -n2) * v.x : 0.0, L.even_row, L.low) - dN * dN * vt.x;
-      if (A.accumulate_drag && lane == 0) A.drag_acc[0] += A.nu * slope;
+      if (r == 2 && lane == 0) A.drag_acc[0] += A.nu * slope;  // drag: end of every time step
       const bool ok = isfinite(v.x) && isfinite(v.y) && isfinite(vt.x) && isfinite(vt.y);
       if (r == 2 && __any(!ok) && lane == 0) atomicOr(A.status, STATUS_NONFINITE);
     }
@@ -734,7 +723,7 @@ __global__ __launch_bounds__(64 * CWAVES, 2) void k_column_pm(ColArgsPm A) {
 
   // ---------------- reconstruction and inverse DCT for the next stage ----------------
   if constexpr (PART == PART_SOLVE) return;
-  const bool want_end = A.want_end != 0;
+  const bool want_end = (S.stage == 2 || S.stage < 0);  // end of a time step
   cplx fld[6], fldt[6];  // (u, v, w, omega_x, omega_y, omega_z) coefficients
   cplx tau_hat;
   if (!mean) {
@@ -778,6 +767,7 @@ __global__ __launch_bounds__(64 * CWAVES, 2) void k_column_pm(ColArgsPm A) {
   }
   cplx ph[6], pht[6];
   dct_inv_pm<N, 6>(L, fld, fldt, A.kinv, ph, pht);
+  if (status0 & STATUS_BAD_ACTION) return;
   // write the six fields at the nodes (this lane: node n; lane 0 also node N) and the
   // Hermitian partner column
   const size_t o = ((size_t)nl * A.nkx + p) * nz + q;
@@ -814,15 +804,39 @@ __global__ __launch_bounds__(64 * CWAVES, 2) void k_column_pm(ColArgsPm A) {
   }
 }
 
+// Many channels: channel blockIdx.x / bpc of the device array.
+template <int N, int PART>
+__global__ __launch_bounds__(64 * CWAVES, 2) void k_column_pm(const ColChan* __restrict__ chans, ColStage S,
+                                                               int bpc) {
+  const int ch = blockIdx.x / bpc;
+  column_block<N, PART>(chans[ch], S, blockIdx.x - ch * bpc);
+}
+
+// One channel, its arguments by value (preloaded with the kernel arguments instead of read
+// through a pointer); the same column code as the batched kernel.
+template <int N, int PART>
+__global__ __launch_bounds__(64 * CWAVES, 2) void k_column_pm1(ColChan A, ColStage S) {
+  column_block<N, PART>(A, S, blockIdx.x);
+}
+
 template <int N>
-int launch_pm(const ColArgsPm& A, bool solve, bool recon, hipStream_t st, KernelTimer* tm) {
-  const int blocks = (A.ncol + CWAVES - 1) / CWAVES;
+int launch_pm(const ColChan* d_col, const ColChan* h_col, int nch, int ncol, const ColStage& S, bool solve,
+              bool recon, hipStream_t st, KernelTimer* tm) {
+  const int bpc = (ncol + CWAVES - 1) / CWAVES;
+  const dim3 grid(bpc * nch), block(64 * CWAVES);
+  const bool one = nch == 1 && h_col != nullptr;
   if (solve) {
-    timed_launch(tm, KC_COLUMN, k_column_pm<N, PART_SOLVE>, dim3(blocks), dim3(64 * CWAVES), 0, st, A);
+    if (one)
+      timed_launch(tm, KC_COLUMN, k_column_pm1<N, PART_SOLVE>, grid, block, 0, st, h_col[0], S);
+    else
+      timed_launch(tm, KC_COLUMN, k_column_pm<N, PART_SOLVE>, grid, block, 0, st, d_col, S, bpc);
     if (hipGetLastError() != hipSuccess) return -1;
   }
   if (recon) {
-    timed_launch(tm, KC_RECON, k_column_pm<N, PART_RECON>, dim3(blocks), dim3(64 * CWAVES), 0, st, A);
+    if (one)
+      timed_launch(tm, KC_RECON, k_column_pm1<N, PART_RECON>, grid, block, 0, st, h_col[0], S);
+    else
+      timed_launch(tm, KC_RECON, k_column_pm<N, PART_RECON>, grid, block, 0, st, d_col, S, bpc);
     if (hipGetLastError() != hipSuccess) return -1;
   }
   return 0;
@@ -830,59 +844,13 @@ int launch_pm(const ColArgsPm& A, bool solve, bool recon, hipStream_t st, Kernel
 
 }  // namespace
 
-int launch_column_pass_pm(const Dims& d, DeviceState& s, const PhysParams& ph, int stage, const StageConsts& sc,
-                          int wall_mode, double s_ramp, int js, double opp_alpha, bool accumulate_drag,
-                          bool recon, hipStream_t st, KernelTimer* tm) {
-  ColArgsPm A;
-  A.want_end = (stage == 2 || stage < 0) ? 1 : 0;
-  const bool solve = stage >= 0;
-  recon = recon || stage < 0;
-  A.nkx = d.nkx;
-  A.nz = d.nz;
-  A.ncol = d.ncol;
-  A.stage = stage;
-  A.wall_mode = wall_mode;
-  A.s_ramp = s_ramp;
-  A.lam0 = sc.lam0;
-  A.ab = sc.ab;
-  A.gb = sc.gb;
-  A.zb = sc.zb;
-  A.nu = ph.nu;
-  A.opp_alpha = opp_alpha;
-  A.ub2 = 2.0 * ph.ub;
-  A.px = ph.px;
-  A.forcing = ph.forcing;
-  A.js = js;
-  A.accumulate_drag = accumulate_drag ? 1 : 0;
-  A.plane = (size_t)d.ny * d.nkx * d.nz;
-  A.vS = s.vS;
-  A.oS = s.oS;
-  A.hist = s.hist;
-  A.meanS = s.meanS;
-  A.meanH = s.meanH;
-  A.H3 = s.H3;
-  A.F6 = s.F6;
-  A.vw_old = s.vw_old;
-  A.vw_new = s.vw_new;
-  A.vw_opp = s.vw_opp;
-  A.tauw = s.tauw;
-  A.kfwd = s.kfwd;
-  A.kinv = s.kinv;
-  A.rc_pm = s.rc_pm;
-  A.intw_pm = s.intw_pm;
-  A.op_pm = s.op_pm;
-  A.vt_pm = s.vt_pm;
-  A.up_pm = s.up_pm;
-  A.minv = s.minv;
-  A.inv_int_up = s.inv_int_up;
-  A.alpha = s.alpha;
-  A.beta = s.beta;
-  A.drag_acc = s.drag_acc;
-  A.status = s.status;
+int launch_column_pm(const Dims& d, const ColChan* d_col, const ColChan* h_col, int nch, const ColStage& S,
+                     bool solve, bool recon, hipStream_t st, KernelTimer* tm) {
+  if (nch < 1) return 0;
   switch (d.N) {
-    case 16: return launch_pm<16>(A, solve, recon, st, tm);
-    case 32: return launch_pm<32>(A, solve, recon, st, tm);
-    case 64: return launch_pm<64>(A, solve, recon, st, tm);
+    case 16: return launch_pm<16>(d_col, h_col, nch, d.ncol, S, solve, recon, st, tm);
+    case 32: return launch_pm<32>(d_col, h_col, nch, d.ncol, S, solve, recon, st, tm);
+    case 64: return launch_pm<64>(d_col, h_col, nch, d.ncol, S, solve, recon, st, tm);
     default: return -1;
   }
 }

@@ -1,6 +1,7 @@
 // C ABI of the channel-flow environment: validation, device allocation, the stage
 // loop and the state exchange.  All numerical work of a step is queued as HIP
 // kernels (kernels.hip); the host only sequences launches.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -11,6 +12,33 @@
 #include "chanenv_internal.h"
 
 using namespace chanenv;
+
+// Channels of one grid shape inside a batch: one launch per kernel covers all of them.
+struct ShapeGroup {
+  Dims d;
+  bool pm;                        // N <= 64: the parity-major column kernels
+  std::vector<int> members;       // indices into chan_batch::envs
+  ColChan* d_col = nullptr;       // [members] (pm groups)
+  std::vector<ColChan> h_col;     // host copy of d_col
+  PlaneChan* d_plane = nullptr;   // [members]
+};
+
+// Envs stepped together: per-channel launch arguments resident on the device, the per-call
+// ones staged through pinned memory.  Every env owns a batch of one for its own steps.
+struct chan_batch {
+  std::vector<chan_env*> envs;
+  std::vector<ShapeGroup> groups;
+  hipStream_t stream = nullptr;
+  void* dev = nullptr;            // ColChan[n], PlaneChan[n], StepChan[n], int status[n]
+  StepChan* d_step = nullptr;
+  int* d_status = nullptr;
+  StepChan* h_step = nullptr;     // pinned
+  int* h_status = nullptr;        // pinned
+  int max_nx = 0, max_nz = 0, max_nkx = 0;
+  KernelTimer timer;
+  double timing_ms[KC_COUNT];
+  int64_t timing_launches[KC_COUNT];
+};
 
 struct chan_env {
   chan_grid_t grid;
@@ -29,10 +57,8 @@ struct chan_env {
   double t;
   int64_t nstep;
   StageConsts sc[3];
-  KernelTimer timer;
   bool force_generic;   // CHANENV_GENERIC_COLUMN=1: use the general column kernel for every N
-  double timing_ms[KC_COUNT];
-  int64_t timing_launches[KC_COUNT];
+  chan_batch* self;     // batch of one for chan_env_step
 };
 
 namespace {
@@ -126,7 +152,7 @@ Sizes buffer_sizes(const Dims& d, size_t tab_doubles) {
   z.w3 = align256((size_t)3 * d.ny * d.mz * d.nkx * C);
   z.h3 = align256((size_t)3 * d.ny * d.nkx * d.nz * C);
   z.wall = align256((size_t)d.ncol * C);
-  z.tmp2d = align256((size_t)3 * d.nz * d.nkx * C);
+  z.tmp2d = align256((size_t)OUT_SLOTS * d.nz * d.nkx * C);
   z.tab = align256(tab_doubles * sizeof(double));
   z.total = 4 * z.spec + align256((size_t)4 * d.ny * sizeof(double)) + z.plane6 + z.z6 + z.w3 + z.h3 +
             4 * z.wall + z.tmp2d + z.tab + 256 + 256;
@@ -164,26 +190,350 @@ int fail(int code, const char* what, hipError_t err = hipSuccess) {
     if (err_ != hipSuccess) return fail(CHAN_EDEVICE, #x, err_); \
   } while (0)
 
-// The column pass: the parity-major kernel for N <= 64, the general one above.
-int column_pass(chan_env* e, int stage, const StageConsts& sc, int mode, double s_ramp, bool drag, bool recon,
-                KernelTimer* tm) {
-  if (e->d.N <= 64 && !e->force_generic)
-    return launch_column_pass_pm(e->d, e->s, e->ph, stage, sc, mode, s_ramp, e->js, e->opts.opp_alpha, drag,
-                                 recon, e->stream, tm);
-  return launch_column_pass(e->d, e->s, e->ph, stage, sc, mode, s_ramp, e->js, e->opts.opp_alpha, drag, recon,
-                            e->stream, tm);
+ColChan make_col_chan(const chan_env* e) {
+  ColChan c;
+  std::memset(&c, 0, sizeof(c));
+  const Dims& d = e->d;
+  const DeviceState& s = e->s;
+  c.nkx = d.nkx;
+  c.nz = d.nz;
+  c.ncol = d.ncol;
+  c.ext = e->opts.controller == CHAN_CTRL_EXTERNAL ? 1 : 0;
+  c.hold = e->opts.action_mode == CHAN_HOLD ? 1 : 0;
+  c.forcing = e->ph.forcing;
+  c.js = e->js;
+  for (int r = 0; r < 3; ++r) {
+    c.lam0[r] = e->sc[r].lam0;
+    c.ab[r] = e->sc[r].ab;
+    c.gb[r] = e->sc[r].gb;
+    c.zb[r] = e->sc[r].zb;
+  }
+  c.nu = e->ph.nu;
+  c.opp_alpha = e->opts.opp_alpha;
+  c.ub2 = 2.0 * e->ph.ub;
+  c.px = e->ph.px;
+  c.plane = (size_t)d.ny * d.nkx * d.nz;
+  c.vS = s.vS;
+  c.oS = s.oS;
+  c.hist = s.hist;
+  c.meanS = s.meanS;
+  c.meanH = s.meanH;
+  c.H3 = s.H3;
+  c.F6 = s.F6;
+  c.vw_old = s.vw_old;
+  c.vw_new = s.vw_new;
+  c.vw_opp = s.vw_opp;
+  c.tauw = s.tauw;
+  c.kfwd = s.kfwd;
+  c.kinv = s.kinv;
+  c.rc_pm = s.rc_pm;
+  c.intw_pm = s.intw_pm;
+  c.op_pm = s.op_pm;
+  c.vt_pm = s.vt_pm;
+  c.up_pm = s.up_pm;
+  c.minv = s.minv;
+  c.inv_int_up = s.inv_int_up;
+  c.alpha = s.alpha;
+  c.beta = s.beta;
+  c.drag_acc = s.drag_acc;
+  c.status = s.status;
+  return c;
 }
 
-int prime(chan_env* e) {
-  // Fill the plane-pass inputs, the opposition wall velocity and the wall shear from
-  // the state just loaded (column pass in reconstruct-only mode).
-  StageConsts sc = e->sc[0];
-  if (launch_begin_step(e->d, e->s, false, e->stream, nullptr))
-    return fail(CHAN_EDEVICE, "launch begin_step", hipGetLastError());
-  if (column_pass(e, -1, sc, WALL_RAMP, 0.0, false, true, nullptr))
-    return fail(CHAN_EDEVICE, "launch column pass", hipGetLastError());
-  HIPCHECK(hipStreamSynchronize(e->stream));
+PlaneChan make_plane_chan(const chan_env* e) {
+  PlaneChan c;
+  std::memset(&c, 0, sizeof(c));
+  const Dims& d = e->d;
+  c.ny = d.ny;
+  c.nkx = d.nkx;
+  c.nz = d.nz;
+  c.scale = 1.0 / ((double)d.mx * (double)d.mz);
+  c.F6 = e->s.F6;
+  c.Z6 = e->s.Z6;
+  c.W3 = e->s.W3;
+  c.H3 = e->s.H3;
+  c.twz = e->s.twz;
+  c.twx = e->s.twx;
+  c.status = e->s.status;
+  return c;
+}
+
+bool uses_pm(const chan_env* e) { return e->d.N <= 64 && !e->force_generic; }
+
+void batch_free(chan_batch* b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  for (hipEvent_t ev : b->timer.pool) (void)hipEventDestroy(ev);
+  if (b->dev) (void)hipFree(b->dev);
+  if (b->h_step) (void)hipHostFree(b->h_step);
+  if (b->h_status) (void)hipHostFree(b->h_status);
+  delete b;
+}
+
+// Groups the envs by grid shape and uploads their launch arguments.  The envs must share
+// one stream and one device and appear once each.
+int batch_build(chan_env* const* envs, int n, chan_batch** out) {
+  if (n < 1 || !envs) return fail(CHAN_EINVAL, "batch: no envs");
+  for (int i = 0; i < n; ++i) {
+    if (!envs[i]) return fail(CHAN_EINVAL, "batch: null env");
+    if (envs[i]->stream != envs[0]->stream || envs[i]->device != envs[0]->device)
+      return fail(CHAN_EINVAL, "batch: envs on different streams or devices");
+    for (int k = 0; k < i; ++k)
+      if (envs[k] == envs[i]) return fail(CHAN_EINVAL, "batch: env listed twice");
+  }
+  chan_batch* b = new (std::nothrow) chan_batch();
+  if (!b) return CHAN_ENOMEM;
+  b->envs.assign(envs, envs + n);
+  b->stream = envs[0]->stream;
+  for (int k = 0; k < KC_COUNT; ++k) {
+    b->timing_ms[k] = 0.0;
+    b->timing_launches[k] = 0;
+  }
+  for (int i = 0; i < n; ++i) {
+    const chan_env* e = envs[i];
+    const bool pm = uses_pm(e);
+    int gi = -1;
+    for (size_t g = 0; g < b->groups.size(); ++g) {
+      const Dims& d = b->groups[g].d;
+      if (d.nx == e->d.nx && d.ny == e->d.ny && d.nz == e->d.nz && b->groups[g].pm == pm) gi = (int)g;
+    }
+    if (gi < 0) {
+      b->groups.push_back(ShapeGroup());
+      gi = (int)b->groups.size() - 1;
+      b->groups[gi].d = e->d;
+      b->groups[gi].pm = pm;
+    }
+    b->groups[gi].members.push_back(i);
+    if (e->d.ny * (int)b->groups[gi].members.size() > 65535) {
+      batch_free(b);
+      return fail(CHAN_EINVAL, "batch: too many channels of one shape (N_y x count > 65535)");
+    }
+    b->max_nx = std::max(b->max_nx, e->d.nx);
+    b->max_nz = std::max(b->max_nz, e->d.nz);
+    b->max_nkx = std::max(b->max_nkx, e->d.nkx);
+  }
+  const size_t col_b = align256(n * sizeof(ColChan)), plane_b = align256(n * sizeof(PlaneChan));
+  const size_t step_b = align256(n * sizeof(StepChan)), stat_b = align256(n * sizeof(int));
+  hipError_t err = hipMalloc(&b->dev, col_b + plane_b + step_b + stat_b);
+  if (err != hipSuccess) {
+    batch_free(b);
+    return fail(CHAN_ENOMEM, "hipMalloc(batch)", err);
+  }
+  if (hipHostMalloc((void**)&b->h_step, n * sizeof(StepChan)) != hipSuccess ||
+      hipHostMalloc((void**)&b->h_status, n * sizeof(int)) != hipSuccess) {
+    batch_free(b);
+    return fail(CHAN_ENOMEM, "hipHostMalloc(batch)");
+  }
+  char* base = (char*)b->dev;
+  ColChan* d_col = (ColChan*)base;
+  PlaneChan* d_plane = (PlaneChan*)(base + col_b);
+  b->d_step = (StepChan*)(base + col_b + plane_b);
+  b->d_status = (int*)(base + col_b + plane_b + step_b);
+  std::vector<ColChan> hc;
+  std::vector<PlaneChan> hp;
+  for (ShapeGroup& g : b->groups) {
+    g.d_col = d_col + hc.size();
+    g.d_plane = d_plane + hp.size();
+    for (int i : g.members) {
+      hc.push_back(make_col_chan(b->envs[i]));
+      hp.push_back(make_plane_chan(b->envs[i]));
+      g.h_col.push_back(hc.back());
+    }
+  }
+  err = hipMemcpyAsync(d_col, hc.data(), hc.size() * sizeof(ColChan), hipMemcpyHostToDevice, b->stream);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(d_plane, hp.data(), hp.size() * sizeof(PlaneChan), hipMemcpyHostToDevice, b->stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(b->stream);
+  if (err != hipSuccess) {
+    batch_free(b);
+    return fail(CHAN_EDEVICE, "batch argument upload", err);
+  }
+  *out = b;
   return CHAN_OK;
+}
+
+// The per-call launch arguments of env i.
+StepChan make_step_chan(const chan_batch* b, int i, const double* action, int n_sub, double* obs, double* tau_w,
+                        double* drag) {
+  const chan_env* e = b->envs[i];
+  const Dims& d = e->d;
+  const bool ext = e->opts.controller == CHAN_CTRL_EXTERNAL;
+  StepChan c;
+  std::memset(&c, 0, sizeof(c));
+  c.nx = d.nx;
+  c.nz = d.nz;
+  c.nkx = d.nkx;
+  c.ncol = d.ncol;
+  c.n_sub = n_sub;
+  c.zero_vw = (ext && action == nullptr) ? 1 : 0;
+  c.copy_vw = ext ? 1 : 0;
+  c.clip = e->opts.clip;
+  c.action = ext ? action : nullptr;
+  c.drag_out = drag;
+  const size_t plane = (size_t)d.ny * d.nkx * d.nz;
+  if (obs) {
+    int slot = 0;
+    for (int f = 0; f < 3; ++f) {
+      if (!(e->opts.obs_mask & (1u << f))) continue;
+      c.out_src[f] = e->s.F6 + (size_t)f * plane + (size_t)e->js * d.nkx * d.nz;
+      c.out_dst[f] = obs + (size_t)slot * d.nz * d.nx;
+      ++slot;
+    }
+  }
+  if (tau_w) {
+    c.out_src[3] = e->s.tauw;
+    c.out_dst[3] = tau_w;
+  }
+  c.vw_new = e->s.vw_new;
+  c.vw_old = e->s.vw_old;
+  c.tmp2d = e->s.tmp2d;
+  c.twnx = e->s.twnx;
+  c.twnz = e->s.twnz;
+  c.drag_acc = e->s.drag_acc;
+  c.status = e->s.status;
+  c.status_out = b->d_status + i;
+  return c;
+}
+
+// Column pass of one group after the plane pass of stage S.stage (or, S.stage = -1, the
+// reconstruction alone).
+int group_column(chan_batch* b, const ShapeGroup& g, const ColStage& S, bool solve, bool recon, KernelTimer* tm) {
+  if (g.pm) return launch_column_pm(g.d, g.d_col, g.h_col.data(), (int)g.members.size(), S, solve, recon, b->stream, tm);
+  for (int i : g.members) {
+    chan_env* e = b->envs[i];
+    const int r = S.stage;
+    int mode = WALL_OPP;
+    double s = 0.0;
+    if (e->opts.controller == CHAN_CTRL_EXTERNAL) {
+      mode = WALL_RAMP;
+      if (r >= 0) s = (e->opts.action_mode == CHAN_HOLD) ? 1.0 : (S.m + RK_C_END[r]) / (double)S.n_sub;
+    }
+    if (launch_column_pass(e->d, e->s, e->ph, r, e->sc[r < 0 ? 0 : r], mode, s, e->js, e->opts.opp_alpha, r == 2,
+                           recon, b->stream, tm))
+      return -1;
+  }
+  return 0;
+}
+
+// Plane-pass input, opposition target and wall shear from the stored state of every env of
+// the batch (after reset or set_state).
+int batch_prime(chan_batch* b) {
+  const int n = (int)b->envs.size();
+  for (int i = 0; i < n; ++i) b->h_step[i] = make_step_chan(b, i, nullptr, 1, nullptr, nullptr, nullptr);
+  for (int i = 0; i < n; ++i) b->h_step[i].zero_vw = 0;
+  HIPCHECK(hipMemcpyAsync(b->d_step, b->h_step, n * sizeof(StepChan), hipMemcpyHostToDevice, b->stream));
+  if (launch_begin_step(b->d_step, n, b->stream, nullptr)) return fail(CHAN_EDEVICE, "launch begin_step", hipGetLastError());
+  const ColStage S = {-1, 0, 1};
+  for (const ShapeGroup& g : b->groups)
+    if (group_column(b, g, S, false, true, nullptr))
+      return fail(CHAN_EDEVICE, "launch column pass", hipGetLastError());
+  HIPCHECK(hipStreamSynchronize(b->stream));
+  return CHAN_OK;
+}
+
+// One env step of every env of the batch.  Per-env pointer arrays may be null (all null).
+int batch_step(chan_batch* b, const double* const* actions, int32_t n_substeps, double* const* obs,
+               double* const* tau_w, double* const* drag, int32_t* results) {
+  if (n_substeps < 1) return fail(CHAN_EINVAL, "n_substeps < 1");
+  const int n = (int)b->envs.size();
+  int n_ready = 0;
+  for (int i = 0; i < n; ++i) n_ready += (b->envs[i]->have_flow && !b->envs[i]->poisoned) ? 1 : 0;
+  if (n_ready == 0) return fail(CHAN_ESTATE, "no env with a valid flow state");
+  g_last_error.clear();
+  bool any_action = false;
+  for (int i = 0; i < n; ++i) {
+    b->h_step[i] = make_step_chan(b, i, actions ? actions[i] : nullptr, n_substeps, obs ? obs[i] : nullptr,
+                                  tau_w ? tau_w[i] : nullptr, drag ? drag[i] : nullptr);
+    b->h_step[i].skip = (b->envs[i]->have_flow && !b->envs[i]->poisoned) ? 0 : 1;
+    any_action = any_action || (b->h_step[i].action != nullptr && !b->h_step[i].skip);
+  }
+  hipStream_t st = b->stream;
+  KernelTimer* tm = b->timer.on ? &b->timer : nullptr;
+  HIPCHECK(hipMemcpyAsync(b->d_step, b->h_step, n * sizeof(StepChan), hipMemcpyHostToDevice, st));
+  if (launch_begin_step(b->d_step, n, st, tm)) return fail(CHAN_EDEVICE, "launch begin_step", hipGetLastError());
+  if (any_action && launch_ingest(b->d_step, n, b->max_nx, b->max_nz, b->max_nkx, st, tm))
+    return fail(CHAN_EDEVICE, "launch ingest", hipGetLastError());
+  for (int m = 0; m < n_substeps; ++m) {
+    for (int r = 0; r < 3; ++r) {
+      // The last stage of the env step leaves its reconstruction to the reconstruction
+      // below, which also serves set_state (bitwise-identical resume).
+      const bool last = (m == n_substeps - 1) && (r == 2);
+      const ColStage S = {r, m, n_substeps};
+      for (const ShapeGroup& g : b->groups) {
+        if (launch_plane_pass(g.d, g.d_plane, (int)g.members.size(), st, tm))
+          return fail(CHAN_EDEVICE, "launch plane pass", hipGetLastError());
+        if (group_column(b, g, S, true, !last, tm)) return fail(CHAN_EDEVICE, "launch column pass", hipGetLastError());
+      }
+    }
+  }
+  const ColStage S_end = {-1, 0, n_substeps};
+  for (const ShapeGroup& g : b->groups)
+    if (group_column(b, g, S_end, false, true, tm)) return fail(CHAN_EDEVICE, "launch column pass", hipGetLastError());
+  if (launch_finish_step(b->d_step, n, st, tm)) return fail(CHAN_EDEVICE, "launch finish_step", hipGetLastError());
+  if (launch_outputs(b->d_step, n, b->max_nx, b->max_nz, b->max_nkx, st, tm))
+    return fail(CHAN_EDEVICE, "launch outputs", hipGetLastError());
+  HIPCHECK(hipMemcpyAsync(b->h_status, b->d_status, n * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  int rc = CHAN_OK;
+  for (int i = 0; i < n; ++i) {
+    chan_env* e = b->envs[i];
+    const int status = b->h_status[i];
+    int ri = CHAN_OK;
+    if (b->h_step[i].skip) {
+      ri = CHAN_ESTATE;
+      if (rc == CHAN_OK) fail(CHAN_ESTATE, "env without a valid flow state (skipped)");
+    } else if (status & STATUS_BAD_ACTION) {
+      ri = CHAN_ENONFINITE;
+      if (rc == CHAN_OK) fail(CHAN_ENONFINITE, "non-finite action");
+    } else {
+      e->t += n_substeps * e->ph.dt;
+      e->nstep += n_substeps;
+      if (status & STATUS_NONFINITE) {
+        e->poisoned = true;
+        ri = CHAN_ENONFINITE;
+        if (rc == CHAN_OK) fail(CHAN_ENONFINITE, "non-finite state after the step");
+      }
+    }
+    if (results) results[i] = ri;
+    if (rc == CHAN_OK) rc = ri;
+  }
+  return rc;
+}
+
+int batch_drain_timer(chan_batch* b) {
+  KernelTimer& t = b->timer;
+  if (t.used == 0) return CHAN_OK;
+  HIPCHECK(hipStreamSynchronize(b->stream));
+  for (size_t k = 0; k < t.used; ++k) {
+    float ms = 0.0f;
+    HIPCHECK(hipEventElapsedTime(&ms, t.pool[2 * k], t.pool[2 * k + 1]));
+    b->timing_ms[t.cls[k]] += ms;
+    b->timing_launches[t.cls[k]] += 1;
+  }
+  t.used = 0;
+  return CHAN_OK;
+}
+
+int batch_set_timing(chan_batch* b, int32_t enable) {
+  const int rc = batch_drain_timer(b);
+  if (rc != CHAN_OK) return rc;
+  for (int k = 0; k < KC_COUNT; ++k) {
+    b->timing_ms[k] = 0.0;
+    b->timing_launches[k] = 0;
+  }
+  b->timer.on = enable != 0;
+  return CHAN_OK;
+}
+
+int batch_timing_read(chan_batch* b, int32_t nclass, int64_t* launches, double* ms) {
+  if (nclass < 0 || (nclass > 0 && (!launches || !ms))) return CHAN_EINVAL;
+  const int rc = batch_drain_timer(b);
+  if (rc != CHAN_OK) return rc;
+  for (int k = 0; k < nclass && k < KC_COUNT; ++k) {
+    launches[k] = b->timing_launches[k];
+    ms[k] = b->timing_ms[k];
+  }
+  return KC_COUNT;
 }
 
 // Host-side canonicalisation of a state in the exchange layout: zero Nyquist rows and
@@ -249,7 +599,7 @@ int upload_state(chan_env* e, const double* flat_in) {
   e->nstep = (int64_t)flat[n - 1];
   e->have_flow = true;
   e->poisoned = false;
-  return prime(e);
+  return batch_prime(e->self);
 }
 
 }  // namespace
@@ -326,6 +676,7 @@ int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_
   e->stream = (hipStream_t)hip_stream;
   e->have_flow = false;
   e->poisoned = false;
+  e->self = nullptr;
   {
     const char* g = std::getenv("CHANENV_GENERIC_COLUMN");
     e->force_generic = g && g[0] == '1';
@@ -420,6 +771,16 @@ int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_
       return fail(CHAN_EDEVICE, what, err);
     }
   }
+  {
+    chan_env* one[1] = {e};
+    const int rc = batch_build(one, 1, &e->self);
+    if (rc != CHAN_OK) {
+      const std::string why = g_last_error;
+      chan_env_destroy(e);
+      g_last_error = why;
+      return rc;
+    }
+  }
   *out = e;
   return CHAN_OK;
 }
@@ -427,7 +788,7 @@ int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_
 void chan_env_destroy(chan_env* e) {
   if (!e) return;
   if (e->stream) (void)hipStreamSynchronize(e->stream);
-  for (hipEvent_t ev : e->timer.pool) (void)hipEventDestroy(ev);
+  batch_free(e->self);
   if (e->dev_block) (void)hipFree(e->dev_block);
   if (e->host_status) (void)hipHostFree(e->host_status);
   delete e;
@@ -509,52 +870,34 @@ int chan_env_query(const chan_env* e, chan_info_t* out) {
 int chan_env_step(chan_env* e, const double* action, int32_t n_substeps, double* obs, double* tau_w,
                   double* drag) {
   if (!e) return CHAN_EINVAL;
-  if (n_substeps < 1) return CHAN_EINVAL;
-  if (!e->have_flow || e->poisoned) return CHAN_ESTATE;
-  const Dims& d = e->d;
-  const bool ext = e->opts.controller == CHAN_CTRL_EXTERNAL;
-  hipStream_t st = e->stream;
-  KernelTimer* tm = e->timer.on ? &e->timer : nullptr;
+  return batch_step(e->self, &action, n_substeps, &obs, &tau_w, &drag, nullptr);
+}
+
+int chan_batch_create(int32_t n, chan_env* const* envs, chan_batch** out) {
   g_last_error.clear();
-  if (launch_begin_step(d, e->s, ext && action == nullptr, st, tm))
-    return fail(CHAN_EDEVICE, "launch begin_step", hipGetLastError());
-  if (ext && action != nullptr)
-    if (launch_ingest(d, e->s, action, e->opts.clip, st, tm))
-      return fail(CHAN_EDEVICE, "launch ingest", hipGetLastError());
-  for (int m = 0; m < n_substeps; ++m) {
-    for (int r = 0; r < 3; ++r) {
-      int mode = WALL_OPP;
-      double s = 0.0;
-      if (ext) {
-        mode = WALL_RAMP;
-        s = (e->opts.action_mode == CHAN_HOLD) ? 1.0 : (m + RK_C_END[r]) / (double)n_substeps;
-      }
-      if (launch_plane_pass(d, e->s, st, tm)) return fail(CHAN_EDEVICE, "launch plane pass", hipGetLastError());
-      // The last stage of the env step leaves the reconstruction to the reconstruct-only
-      // pass below, so that the plane-pass input at an env-step boundary is always made
-      // by the same code path as after set_state (bitwise-identical resume).
-      const bool last = (m == n_substeps - 1) && (r == 2);
-      if (column_pass(e, r, e->sc[r], mode, s, r == 2, !last, tm))
-        return fail(CHAN_EDEVICE, "launch column pass", hipGetLastError());
-    }
-  }
-  if (column_pass(e, -1, e->sc[0], WALL_RAMP, 0.0, false, true, tm))
-    return fail(CHAN_EDEVICE, "launch column pass", hipGetLastError());
-  if (launch_finish_step(d, e->s, ext, drag, n_substeps, st, tm))
-    return fail(CHAN_EDEVICE, "launch finish_step", hipGetLastError());
-  if (launch_outputs(d, e->s, e->js, e->opts.obs_mask, obs, tau_w, st, tm))
-    return fail(CHAN_EDEVICE, "launch outputs", hipGetLastError());
-  HIPCHECK(hipMemcpyAsync(e->host_status, e->s.status, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCHECK(hipStreamSynchronize(st));
-  const int status = *e->host_status;
-  if (status & STATUS_BAD_ACTION) return fail(CHAN_ENONFINITE, "non-finite action");
-  e->t += n_substeps * e->ph.dt;
-  e->nstep += n_substeps;
-  if (status & STATUS_NONFINITE) {
-    e->poisoned = true;
-    return fail(CHAN_ENONFINITE, "non-finite state after the step");
-  }
-  return CHAN_OK;
+  if (!out) return CHAN_EINVAL;
+  *out = nullptr;
+  return batch_build(envs, n, out);
+}
+
+int chan_batch_step(chan_batch* b, const double* const* actions, int32_t n_substeps, double* const* obs,
+                    double* const* tau_w, double* const* drag, int32_t* results) {
+  if (!b) return CHAN_EINVAL;
+  return batch_step(b, actions, n_substeps, obs, tau_w, drag, results);
+}
+
+void chan_batch_destroy(chan_batch* b) { batch_free(b); }
+
+int32_t chan_batch_size(const chan_batch* b) { return b ? (int32_t)b->envs.size() : 0; }
+
+int chan_batch_set_timing(chan_batch* b, int32_t enable) {
+  if (!b) return CHAN_EINVAL;
+  return batch_set_timing(b, enable);
+}
+
+int chan_batch_timing_read(chan_batch* b, int32_t nclass, int64_t* launches, double* ms) {
+  if (!b) return CHAN_EINVAL;
+  return batch_timing_read(b, nclass, launches, ms);
 }
 
 static const char* const kClassNames[KC_COUNT] = {
@@ -566,42 +909,14 @@ const char* chan_kernel_class_name(int32_t cls) {
   return kClassNames[cls];
 }
 
-// Fold the recorded event pairs into the per-class accumulators.
-static int drain_timer(chan_env* e) {
-  KernelTimer& t = e->timer;
-  if (t.used == 0) return CHAN_OK;
-  HIPCHECK(hipStreamSynchronize(e->stream));
-  for (size_t k = 0; k < t.used; ++k) {
-    float ms = 0.0f;
-    HIPCHECK(hipEventElapsedTime(&ms, t.pool[2 * k], t.pool[2 * k + 1]));
-    e->timing_ms[t.cls[k]] += ms;
-    e->timing_launches[t.cls[k]] += 1;
-  }
-  t.used = 0;
-  return CHAN_OK;
-}
-
 int chan_env_set_timing(chan_env* e, int32_t enable) {
   if (!e) return CHAN_EINVAL;
-  const int rc = drain_timer(e);
-  if (rc != CHAN_OK) return rc;
-  for (int k = 0; k < KC_COUNT; ++k) {
-    e->timing_ms[k] = 0.0;
-    e->timing_launches[k] = 0;
-  }
-  e->timer.on = enable != 0;
-  return CHAN_OK;
+  return batch_set_timing(e->self, enable);
 }
 
 int chan_env_timing_read(chan_env* e, int32_t nclass, int64_t* launches, double* ms) {
-  if (!e || nclass < 0 || (nclass > 0 && (!launches || !ms))) return CHAN_EINVAL;
-  const int rc = drain_timer(e);
-  if (rc != CHAN_OK) return rc;
-  for (int k = 0; k < nclass && k < KC_COUNT; ++k) {
-    launches[k] = e->timing_launches[k];
-    ms[k] = e->timing_ms[k];
-  }
-  return KC_COUNT;
+  if (!e) return CHAN_EINVAL;
+  return batch_timing_read(e->self, nclass, launches, ms);
 }
 
 }  // extern "C"

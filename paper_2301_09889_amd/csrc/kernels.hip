@@ -817,56 +817,69 @@ int launch_column_pass(const Dims& d, DeviceState& s, const PhysParams& ph, int 
 // ----------------------------------------------------------------------------
 // Small kernels: step bookkeeping, action ingest, observation and wall shear.
 // ----------------------------------------------------------------------------
-__global__ void k_begin_step(int* status, double* drag_acc, cplx* vw_new, int ncol, int zero_vw) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+// ----------------------------------------------------------------------------
+// Per-env-step kernels.  Each covers every channel of a step call (blockIdx.y = channel),
+// whatever its grid: sizes come from the channel's StepChan, LDS is sized by the launcher
+// for the largest channel, and blocks beyond a channel's own extent return at once.
+// ----------------------------------------------------------------------------
+
+// Start of an env step: clear the status word and the drag accumulator; v_w,new := 0 when
+// an external-action channel gets no action.
+__global__ void k_begin_step(const StepChan* __restrict__ chans) {
+  const StepChan& C = chans[blockIdx.y];
+  const int t = threadIdx.x;
   if (t == 0) {
-    status[0] = 0;
-    drag_acc[0] = 0.0;
+    C.status[0] = C.skip ? STATUS_BAD_ACTION : 0;
+    C.drag_acc[0] = 0.0;
   }
-  if (zero_vw) {
-    for (int i = t; i < ncol; i += gridDim.x * blockDim.x) vw_new[i] = cz();
+  if (C.zero_vw && !C.skip) {
+    for (int i = t; i < C.ncol; i += blockDim.x) C.vw_new[i] = cz();
   }
 }
 
-int launch_begin_step(const Dims& d, DeviceState& s, bool zero_vw_new, hipStream_t st, KernelTimer* tm) {
-  TIMED_LAUNCH(tm, KC_BOOK, st, k_begin_step, dim3(1), dim3(256), 0, st, s.status, s.drag_acc, s.vw_new, d.ncol,
-                     zero_vw_new ? 1 : 0);
+int launch_begin_step(const StepChan* d_step, int nch, hipStream_t st, KernelTimer* tm) {
+  if (nch < 1) return 0;
+  timed_launch(tm, KC_BOOK, k_begin_step, dim3(1, nch), dim3(256), 0, st, d_step);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 // Rows of the action: finiteness check, clip, forward FFT along x; keeps p < nx/2.
-__global__ void k_ingest_rows(const double* __restrict__ act, int nx, int nkx, double clip,
-                              const cplx* __restrict__ twnx, cplx* tmp, int* status) {
+__global__ void k_ingest_rows(const StepChan* __restrict__ chans) {
   extern __shared__ double dyn_lds[];
+  const StepChan& C = chans[blockIdx.y];
+  const int k = blockIdx.x;
+  if (C.action == nullptr || C.skip || k >= C.nz) return;
+  const int nx = C.nx, nkx = C.nkx;
   cplx* a = reinterpret_cast<cplx*>(dyn_lds);
   cplx* b = a + nx;
-  const int k = blockIdx.x;
   int bad = 0;
   for (int i = threadIdx.x; i < nx; i += blockDim.x) {
-    double v = act[(size_t)k * nx + i];
+    double v = C.action[(size_t)k * nx + i];
     if (!isfinite(v)) bad = 1;
-    if (clip > 0.0) v = fmin(fmax(v, -clip), clip);
+    if (C.clip > 0.0) v = fmin(fmax(v, -C.clip), C.clip);
     a[i] = make_double2(v, 0.0);
   }
   if (__syncthreads_or(bad)) {
-    if (threadIdx.x == 0) atomicOr(status, STATUS_BAD_ACTION);
+    if (threadIdx.x == 0) atomicOr(C.status, STATUS_BAD_ACTION);
     return;
   }
-  cplx* r = fft_batch(a, b, nx, 1, nx, twnx, false);
-  for (int pidx = threadIdx.x; pidx < nkx; pidx += blockDim.x) tmp[(size_t)k * nkx + pidx] = r[pidx];
+  cplx* r = fft_batch(a, b, nx, 1, nx, C.twnx, false);
+  for (int pidx = threadIdx.x; pidx < nkx; pidx += blockDim.x) C.tmp2d[(size_t)k * nkx + pidx] = r[pidx];
 }
 
 // Columns: forward FFT along z, 1/(nx nz), Nyquist and mean removed, Hermitian fix.
-__global__ void k_ingest_cols(const cplx* __restrict__ tmp, int nx, int nz, int nkx,
-                              const cplx* __restrict__ twnz, cplx* vw_new, const int* status) {
+__global__ void k_ingest_cols(const StepChan* __restrict__ chans) {
   extern __shared__ double dyn_lds[];
+  const StepChan& C = chans[blockIdx.y];
+  const int p = blockIdx.x;
+  if (C.action == nullptr || p >= C.nkx) return;
+  if (*C.status & STATUS_BAD_ACTION) return;
+  const int nx = C.nx, nz = C.nz, nkx = C.nkx;
   cplx* a = reinterpret_cast<cplx*>(dyn_lds);
   cplx* b = a + nz;
-  if (*status & STATUS_BAD_ACTION) return;
-  const int p = blockIdx.x;
-  for (int k = threadIdx.x; k < nz; k += blockDim.x) a[k] = tmp[(size_t)k * nkx + p];
+  for (int k = threadIdx.x; k < nz; k += blockDim.x) a[k] = C.tmp2d[(size_t)k * nkx + p];
   __syncthreads();
-  cplx* r = fft_batch(a, b, nz, 1, nz, twnz, false);
+  cplx* r = fft_batch(a, b, nz, 1, nz, C.twnz, false);
   const double sc = 1.0 / ((double)nx * (double)nz);
   const int h = nz / 2;
   for (int q = threadIdx.x; q < nz; q += blockDim.x) {
@@ -875,43 +888,50 @@ __global__ void k_ingest_cols(const cplx* __restrict__ tmp, int nx, int nz, int 
       v = (p == 0 && q > h) ? cconj(r[nz - q]) : r[q];
       v = cscale(v, sc);
     }
-    vw_new[(size_t)p * nz + q] = v;
+    C.vw_new[(size_t)p * nz + q] = v;
   }
 }
 
-int launch_ingest(const Dims& d, DeviceState& s, const double* action, double clip, hipStream_t st,
+int launch_ingest(const StepChan* d_step, int nch, int max_nx, int max_nz, int max_nkx, hipStream_t st,
                   KernelTimer* tm) {
-  TIMED_LAUNCH(tm, KC_INGEST, st, k_ingest_rows, dim3(d.nz), dim3(64), (size_t)2 * d.nx * sizeof(cplx), st, action,
-                     d.nx, d.nkx, clip, s.twnx, s.tmp2d, s.status);
-  TIMED_LAUNCH(tm, KC_INGEST, st, k_ingest_cols, dim3(d.nkx), dim3(64), (size_t)2 * d.nz * sizeof(cplx), st, s.tmp2d,
-                     d.nx, d.nz, d.nkx, s.twnz, s.vw_new, s.status);
+  if (nch < 1) return 0;
+  timed_launch(tm, KC_INGEST, k_ingest_rows, dim3(max_nz, nch), dim3(64), (size_t)2 * max_nx * sizeof(cplx), st,
+               d_step);
+  timed_launch(tm, KC_INGEST, k_ingest_cols, dim3(max_nkx, nch), dim3(64), (size_t)2 * max_nz * sizeof(cplx), st,
+               d_step);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-// Output transforms.  Source spectra are [p][q] with p-stride src_pstride; field f of
-// the batch starts at src + f * src_fstride.  Columns: inverse FFT along z.
-__global__ void k_out_cols(const cplx* __restrict__ src, size_t src_fstride, int nz, int nkx,
-                           const cplx* __restrict__ twnz, cplx* tmp) {
+// Output transforms, slot = blockIdx.z (u, v, w at the sensing node, tau_w).  Source spectra
+// are [p][q].  Columns: inverse FFT along z.
+__global__ void k_out_cols(const StepChan* __restrict__ chans) {
   extern __shared__ double dyn_lds[];
+  const StepChan& C = chans[blockIdx.y];
+  const int p = blockIdx.x, f = blockIdx.z;
+  const cplx* src = C.out_src[f];
+  if (src == nullptr || C.out_dst[f] == nullptr || C.skip || p >= C.nkx) return;
+  const int nz = C.nz, nkx = C.nkx;
   cplx* a = reinterpret_cast<cplx*>(dyn_lds);
   cplx* b = a + nz;
-  const int p = blockIdx.x, f = blockIdx.y;
-  const cplx* s = src + (size_t)f * src_fstride + (size_t)p * nz;
+  const cplx* s = src + (size_t)p * nz;
   const int h = nz / 2;
   for (int q = threadIdx.x; q < nz; q += blockDim.x) a[q] = (q == h) ? cz() : s[q];
   __syncthreads();
-  cplx* r = fft_batch(a, b, nz, 1, nz, twnz, true);
-  for (int k = threadIdx.x; k < nz; k += blockDim.x) tmp[((size_t)f * nz + k) * nkx + p] = r[k];
+  cplx* r = fft_batch(a, b, nz, 1, nz, C.twnz, true);
+  for (int k = threadIdx.x; k < nz; k += blockDim.x) C.tmp2d[((size_t)f * nz + k) * nkx + p] = r[k];
 }
 
 // Rows: Hermitian extension along x (real part of p = 0), inverse FFT, real part out.
-__global__ void k_out_rows(const cplx* __restrict__ tmp, int nx, int nz, int nkx,
-                           const cplx* __restrict__ twnx, double* out, size_t out_fstride) {
+__global__ void k_out_rows(const StepChan* __restrict__ chans) {
   extern __shared__ double dyn_lds[];
+  const StepChan& C = chans[blockIdx.y];
+  const int k = blockIdx.x, f = blockIdx.z;
+  double* out = C.out_dst[f];
+  if (C.out_src[f] == nullptr || out == nullptr || C.skip || k >= C.nz) return;
+  const int nx = C.nx, nz = C.nz, nkx = C.nkx;
   cplx* a = reinterpret_cast<cplx*>(dyn_lds);
   cplx* b = a + nx;
-  const int k = blockIdx.x, f = blockIdx.y;
-  const cplx* row = tmp + ((size_t)f * nz + k) * nkx;
+  const cplx* row = C.tmp2d + ((size_t)f * nz + k) * nkx;
   for (int i = threadIdx.x; i < nx; i += blockDim.x) {
     cplx v = cz();
     if (i == 0) {
@@ -924,52 +944,36 @@ __global__ void k_out_rows(const cplx* __restrict__ tmp, int nx, int nz, int nkx
     a[i] = v;
   }
   __syncthreads();
-  cplx* r = fft_batch(a, b, nx, 1, nx, twnx, true);
-  for (int i = threadIdx.x; i < nx; i += blockDim.x) out[(size_t)f * out_fstride + (size_t)k * nx + i] = r[i].x;
+  cplx* r = fft_batch(a, b, nx, 1, nx, C.twnx, true);
+  for (int i = threadIdx.x; i < nx; i += blockDim.x) out[(size_t)k * nx + i] = r[i].x;
 }
 
-int launch_outputs(const Dims& d, DeviceState& s, int js, uint32_t obs_mask, double* obs,
-                   double* tau_w, hipStream_t st, KernelTimer* tm) {
-  const size_t plane = (size_t)d.ny * d.nkx * d.nz;
-  const size_t shz = (size_t)2 * d.nz * sizeof(cplx), shx = (size_t)2 * d.nx * sizeof(cplx);
-  if (obs) {
-    int slot = 0;
-    for (int f = 0; f < 3; ++f) {
-      if (!(obs_mask & (1u << f))) continue;
-      const cplx* src = s.F6 + (size_t)f * plane + (size_t)js * d.nkx * d.nz;
-      TIMED_LAUNCH(tm, KC_OUTPUT, st, k_out_cols, dim3(d.nkx, 1), dim3(64), shz, st, src, (size_t)0, d.nz, d.nkx, s.twnz,
-                         s.tmp2d);
-      TIMED_LAUNCH(tm, KC_OUTPUT, st, k_out_rows, dim3(d.nz, 1), dim3(64), shx, st, s.tmp2d, d.nx, d.nz, d.nkx, s.twnx,
-                         obs + (size_t)slot * d.nz * d.nx, (size_t)0);
-      ++slot;
-    }
-  }
-  if (tau_w) {
-    TIMED_LAUNCH(tm, KC_OUTPUT, st, k_out_cols, dim3(d.nkx, 1), dim3(64), shz, st, s.tauw, (size_t)0, d.nz, d.nkx, s.twnz,
-                       s.tmp2d);
-    TIMED_LAUNCH(tm, KC_OUTPUT, st, k_out_rows, dim3(d.nz, 1), dim3(64), shx, st, s.tmp2d, d.nx, d.nz, d.nkx, s.twnx, tau_w,
-                       (size_t)0);
-  }
+int launch_outputs(const StepChan* d_step, int nch, int max_nx, int max_nz, int max_nkx, hipStream_t st,
+                   KernelTimer* tm) {
+  if (nch < 1) return 0;
+  const size_t shz = (size_t)2 * max_nz * sizeof(cplx), shx = (size_t)2 * max_nx * sizeof(cplx);
+  timed_launch(tm, KC_OUTPUT, k_out_cols, dim3(max_nkx, nch, OUT_SLOTS), dim3(64), shz, st, d_step);
+  timed_launch(tm, KC_OUTPUT, k_out_rows, dim3(max_nz, nch, OUT_SLOTS), dim3(64), shx, st, d_step);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-// End of an env step: drag = accumulated / n, and v_w,old := v_w,new (unless the
-// action was rejected).
-__global__ void k_finish_step(const int* status, const double* drag_acc, double* drag, int nsub,
-                              const cplx* vw_new, cplx* vw_old, int ncol, int copy_vw) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool bad = (*status & STATUS_BAD_ACTION) != 0;
-  if (bad) return;
-  if (t == 0 && drag) drag[0] = drag_acc[0] / (double)nsub;
-  if (copy_vw) {
-    for (int i = t; i < ncol; i += gridDim.x * blockDim.x) vw_old[i] = vw_new[i];
+// End of an env step: drag = accumulated / n, v_w,old := v_w,new (unless the action was
+// rejected), and the channel's status into the batch-wide status array.
+__global__ void k_finish_step(const StepChan* __restrict__ chans) {
+  const StepChan& C = chans[blockIdx.y];
+  const int t = threadIdx.x;
+  const int status = *C.status;
+  if (t == 0) C.status_out[0] = status;
+  if (status & STATUS_BAD_ACTION) return;
+  if (t == 0 && C.drag_out) C.drag_out[0] = C.drag_acc[0] / (double)C.n_sub;
+  if (C.copy_vw) {
+    for (int i = t; i < C.ncol; i += blockDim.x) C.vw_old[i] = C.vw_new[i];
   }
 }
 
-int launch_finish_step(const Dims& d, DeviceState& s, bool copy_vw, double* drag, int nsub,
-                       hipStream_t st, KernelTimer* tm) {
-  TIMED_LAUNCH(tm, KC_BOOK, st, k_finish_step, dim3(1), dim3(256), 0, st, s.status, s.drag_acc, drag, nsub, s.vw_new,
-                     s.vw_old, d.ncol, copy_vw ? 1 : 0);
+int launch_finish_step(const StepChan* d_step, int nch, hipStream_t st, KernelTimer* tm) {
+  if (nch < 1) return 0;
+  timed_launch(tm, KC_BOOK, k_finish_step, dim3(1, nch), dim3(256), 0, st, d_step);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

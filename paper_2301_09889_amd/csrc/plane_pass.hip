@@ -14,6 +14,7 @@
 //   k_zfwd<M_z>  forward FFT along z, truncation to |q| < N_z/2, 1/(M_x M_z), Hermitian fix.
 //
 // Layouts (complex):  F6[f][j][p][q], Z6[f][j][zz][p], W3[g][j][zz][p], H3[g][j][p][q].
+// A launch covers nch channels of one shape: blockIdx.z = channel * N_y + node.
 #include "device_common.h"
 
 namespace chanenv {
@@ -27,17 +28,6 @@ template <> struct FftPlan<48> { static constexpr int A = 8, B = 6; };
 template <> struct FftPlan<96> { static constexpr int A = 12, B = 8; };
 template <> struct FftPlan<192> { static constexpr int A = 16, B = 12; };
 
-struct PlaneArgs2 {
-  int ny, nkx, nz;
-  double scale;        // 1 / (M_x M_z)
-  const cplx* F6;
-  cplx* Z6;
-  cplx* W3;
-  cplx* H3;
-  const cplx* twz;     // exp(-2 pi i k / M_z)
-  const cplx* twx;     // exp(-2 pi i k / M_x)
-  const int* status;
-};
 
 // a * w_L^(SG m) from a table tw[k] = exp(-2 pi i k / L) held in LDS.
 template <int L, int SG>
@@ -53,14 +43,17 @@ __device__ __forceinline__ cplx twiddle(cplx a, const cplx* tw, int m) {
 // z inverse: block (p chunk, field, node); F6 -> Z6.
 // ---------------------------------------------------------------------------
 template <int L>
-__global__ __launch_bounds__(1024) void k_zinv2(PlaneArgs2 A, int PB) {
+__global__ __launch_bounds__(1024) void k_zinv2(const PlaneChan* __restrict__ chans, int ny, int PB) {
   constexpr int FA = FftPlan<L>::A, FB = FftPlan<L>::B;
   constexpr int LP = L + 1;
   extern __shared__ double dyn_lds[];
   cplx* tw = reinterpret_cast<cplx*>(dyn_lds);
   cplx* Y = tw + L;
-  if (*A.status & STATUS_BAD_ACTION) return;
-  const int p0 = blockIdx.x * PB, f = blockIdx.y, j = blockIdx.z;
+  const PlaneChan& A = chans[blockIdx.z / ny];
+  // a rejected action leaves every buffer untouched (tested at the stores, so that the
+  // status load overlaps the data loads)
+  const bool skip = (*A.status & STATUS_BAD_ACTION) != 0;
+  const int p0 = blockIdx.x * PB, f = blockIdx.y, j = blockIdx.z % ny;
   const int np = min(PB, A.nkx - p0);
   const int nz = A.nz, h = nz / 2;
   for (int t = threadIdx.x; t < L; t += blockDim.x) tw[t] = A.twz[t];
@@ -89,6 +82,7 @@ __global__ __launch_bounds__(1024) void k_zinv2(PlaneArgs2 A, int PB) {
 #pragma unroll
     for (int n2 = 0; n2 < FB; ++n2) u[n2] = Y[p * LP + n2 * FA + k1];
     Dft<FB, 1>::run(u);
+    if (skip) continue;
 #pragma unroll
     for (int k2 = 0; k2 < FB; ++k2) dst[(size_t)(k1 + FA * k2) * A.nkx + p] = u[k2];
   }
@@ -98,15 +92,16 @@ __global__ __launch_bounds__(1024) void k_zinv2(PlaneArgs2 A, int PB) {
 // z forward: block (p chunk, product, node); W3 -> H3.
 // ---------------------------------------------------------------------------
 template <int L>
-__global__ __launch_bounds__(1024) void k_zfwd2(PlaneArgs2 A, int PB) {
+__global__ __launch_bounds__(1024) void k_zfwd2(const PlaneChan* __restrict__ chans, int ny, int PB) {
   constexpr int FA = FftPlan<L>::A, FB = FftPlan<L>::B;
   constexpr int LP = L + 1;
   extern __shared__ double dyn_lds[];
   cplx* tw = reinterpret_cast<cplx*>(dyn_lds);
   cplx* X0 = tw + L;       // the p = 0 pencil, for the Hermitian fix
   cplx* Y = X0 + L;
-  if (*A.status & STATUS_BAD_ACTION) return;
-  const int p0 = blockIdx.x * PB, g = blockIdx.y, j = blockIdx.z;
+  const PlaneChan& A = chans[blockIdx.z / ny];
+  const bool skip = (*A.status & STATUS_BAD_ACTION) != 0;  // tested at the stores
+  const int p0 = blockIdx.x * PB, g = blockIdx.y, j = blockIdx.z % ny;
   const int np = min(PB, A.nkx - p0);
   const int nz = A.nz, h = nz / 2;
   for (int t = threadIdx.x; t < L; t += blockDim.x) tw[t] = A.twz[t];
@@ -140,12 +135,12 @@ __global__ __launch_bounds__(1024) void k_zfwd2(PlaneArgs2 A, int PB) {
       const cplx v = cscale(u[k2], sc);
       if (p0 + p == 0) {
         X0[q] = v;
-      } else {
+      } else if (!skip) {
         dst[(size_t)p * nz + q] = v;
       }
     }
   }
-  if (p0 == 0) {
+  if (p0 == 0 && !skip) {
     __syncthreads();
     for (int q = threadIdx.x; q < nz; q += blockDim.x) {
       cplx v = cz();
@@ -168,14 +163,15 @@ __global__ __launch_bounds__(1024) void k_zfwd2(PlaneArgs2 A, int PB) {
 // block are all in flight together; S holds 6 sequences per pair, transformed in place.
 // ---------------------------------------------------------------------------
 template <int L>
-__global__ __launch_bounds__(1024) void k_xrow2(PlaneArgs2 A, int P) {
+__global__ __launch_bounds__(1024) void k_xrow2(const PlaneChan* __restrict__ chans, int nyc, int P) {
   constexpr int FA = FftPlan<L>::A, FB = FftPlan<L>::B;
   constexpr int LP = L + 1;
   extern __shared__ double dyn_lds[];
   cplx* tw = reinterpret_cast<cplx*>(dyn_lds);
   cplx* S = tw + L;         // [field][pair][LP]
-  if (*A.status & STATUS_BAD_ACTION) return;
-  const int pair0 = blockIdx.x * P, j = blockIdx.y;
+  const PlaneChan& A = chans[blockIdx.y / nyc];
+  const bool skip = (*A.status & STATUS_BAD_ACTION) != 0;  // tested at the stores
+  const int pair0 = blockIdx.x * P, j = blockIdx.y % nyc;
   const int nkx = A.nkx, ny = A.ny;
   const int mz = 3 * A.nz / 2;
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -287,7 +283,7 @@ __global__ __launch_bounds__(1024) void k_xrow2(PlaneArgs2 A, int P) {
   }
   __syncthreads();
   // 6. unpack the two rows of each pair: a = (Y_k + conj Y_{L-k})/2, b = (Y_k - conj Y_{L-k})/(2i)
-  for (int task = tid; task < 3 * P * nkx; task += nthr) {
+  for (int task = tid; task < 3 * P * nkx && !skip; task += nthr) {
     const int seq = task / nkx, k = task - seq * nkx;
     const int g = seq / P, pr = seq - g * P;
     const cplx Yk = S[seq * LP + k];
@@ -302,19 +298,7 @@ __global__ __launch_bounds__(1024) void k_xrow2(PlaneArgs2 A, int P) {
 }
 
 template <int MZ, int MX>
-static int launch_plane2(const Dims& d, DeviceState& s, hipStream_t st, KernelTimer* tm) {
-  PlaneArgs2 A;
-  A.ny = d.ny;
-  A.nkx = d.nkx;
-  A.nz = d.nz;
-  A.scale = 1.0 / ((double)d.mx * (double)d.mz);
-  A.F6 = s.F6;
-  A.Z6 = s.Z6;
-  A.W3 = s.W3;
-  A.H3 = s.H3;
-  A.twz = s.twz;
-  A.twx = s.twx;
-  A.status = s.status;
+static int launch_plane2(const Dims& d, const PlaneChan* chans, int nch, hipStream_t st, KernelTimer* tm) {
   const int PB = d.nkx < 32 ? d.nkx : 32;
   const int nblk = (d.nkx + PB - 1) / PB;
   const size_t shz = (size_t)(MZ + (size_t)PB * (MZ + 1)) * sizeof(cplx);
@@ -330,33 +314,36 @@ static int launch_plane2(const Dims& d, DeviceState& s, hipStream_t st, KernelTi
     if (pairs % c == 0 && 6 * c * FA <= 1024 && (size_t)6 * c * (MX + 1) * sizeof(cplx) <= 80 * 1024) P = c;
   const int thr = ((6 * P * FA + 63) / 64) * 64;
   const size_t shx = (size_t)(MX + (size_t)6 * P * (MX + 1)) * sizeof(cplx);
-  timed_launch(tm, KC_ZINV, k_zinv2<MZ>, dim3(nblk, 6, d.ny), dim3(zthr), shz, st, A, PB);
-  timed_launch(tm, KC_XROW, k_xrow2<MX>, dim3(pairs / P, d.ny), dim3(thr), shx, st, A, P);
-  timed_launch(tm, KC_ZFWD, k_zfwd2<MZ>, dim3(nblk, 3, d.ny), dim3(zthr), shf, st, A, PB);
+  const unsigned nyz = (unsigned)(d.ny * nch);
+  timed_launch(tm, KC_ZINV, k_zinv2<MZ>, dim3(nblk, 6, nyz), dim3(zthr), shz, st, chans, d.ny, PB);
+  timed_launch(tm, KC_XROW, k_xrow2<MX>, dim3(pairs / P, nyz), dim3(thr), shx, st, chans, d.ny, P);
+  timed_launch(tm, KC_ZFWD, k_zfwd2<MZ>, dim3(nblk, 3, nyz), dim3(zthr), shf, st, chans, d.ny, PB);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <int MZ>
-static int dispatch_mx(const Dims& d, DeviceState& s, hipStream_t st, KernelTimer* tm) {
+static int dispatch_mx(const Dims& d, const PlaneChan* chans, int nch, hipStream_t st, KernelTimer* tm) {
   switch (d.mx) {
-    case 6: return launch_plane2<MZ, 6>(d, s, st, tm);
-    case 12: return launch_plane2<MZ, 12>(d, s, st, tm);
-    case 24: return launch_plane2<MZ, 24>(d, s, st, tm);
-    case 48: return launch_plane2<MZ, 48>(d, s, st, tm);
-    case 96: return launch_plane2<MZ, 96>(d, s, st, tm);
-    case 192: return launch_plane2<MZ, 192>(d, s, st, tm);
+    case 6: return launch_plane2<MZ, 6>(d, chans, nch, st, tm);
+    case 12: return launch_plane2<MZ, 12>(d, chans, nch, st, tm);
+    case 24: return launch_plane2<MZ, 24>(d, chans, nch, st, tm);
+    case 48: return launch_plane2<MZ, 48>(d, chans, nch, st, tm);
+    case 96: return launch_plane2<MZ, 96>(d, chans, nch, st, tm);
+    case 192: return launch_plane2<MZ, 192>(d, chans, nch, st, tm);
     default: return -1;
   }
 }
 
-int launch_plane_pass(const Dims& d, DeviceState& s, hipStream_t st, KernelTimer* tm) {
+int launch_plane_pass(const Dims& d, const PlaneChan* chans, int nch, hipStream_t st, KernelTimer* tm) {
+  if (nch < 1) return 0;
+  if ((size_t)d.ny * nch > 65535) return -1;   // grid z limit
   switch (d.mz) {
-    case 6: return dispatch_mx<6>(d, s, st, tm);
-    case 12: return dispatch_mx<12>(d, s, st, tm);
-    case 24: return dispatch_mx<24>(d, s, st, tm);
-    case 48: return dispatch_mx<48>(d, s, st, tm);
-    case 96: return dispatch_mx<96>(d, s, st, tm);
-    case 192: return dispatch_mx<192>(d, s, st, tm);
+    case 6: return dispatch_mx<6>(d, chans, nch, st, tm);
+    case 12: return dispatch_mx<12>(d, chans, nch, st, tm);
+    case 24: return dispatch_mx<24>(d, chans, nch, st, tm);
+    case 48: return dispatch_mx<48>(d, chans, nch, st, tm);
+    case 96: return dispatch_mx<96>(d, chans, nch, st, tm);
+    case 192: return dispatch_mx<192>(d, chans, nch, st, tm);
     default: return -1;
   }
 }
