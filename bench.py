@@ -164,12 +164,15 @@ def cpu_baseline(g, opts_kw, n_sub_env, seed, budget_substeps):
 
 def batched_specs(n):
     """Uneven mix: 16x65x16 and 32x65x32 minimal-box channels alternating, Re_tau 180 / 100 in
-    pairs, opposition control and Gaussian actions in fours; seed = channel index."""
+    pairs, seed = channel index; opposition control on the 16x65x16 channels at Re_tau 180,
+    Gaussian wall actions on the others (opposition control with alpha = 1 from the seeded
+    initial fields diverges for some seeds at Re_tau 100 and on 32x65x32, in the oracle too)."""
     specs = []
     for i in range(n):
         m = 16 if i % 2 == 0 else 32
-        specs.append(dict(nx=m, ny=65, nz=m, lx=2.67, lz=0.8, re_tau=180.0 if (i // 2) % 2 == 0 else 100.0,
-                          dt_plus=0.05, obs_y_plus=15.0, external=(i // 4) % 2 == 1, seed=i))
+        re = 180.0 if (i // 2) % 2 == 0 else 100.0
+        specs.append(dict(nx=m, ny=65, nz=m, lx=2.67, lz=0.8, re_tau=re, dt_plus=0.05, obs_y_plus=15.0,
+                          external=not (m == 16 and re == 180.0), seed=i))
     return specs
 
 
@@ -192,15 +195,17 @@ def run_batched(args, torch, b, gaussian_action):
         batch.step(acts, args.substeps)
     torch.cuda.synchronize()
     lat, codes = [], []
+    done = 0                                  # env steps completed (a diverged channel stops)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         s0 = time.perf_counter()
         codes = batch.step(acts, args.substeps)
         lat.append(time.perf_counter() - s0)
+        done += sum(1 for c in codes if c == 0)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     active = sum(1 for c in codes if c == 0)
-    value = active * args.steps / elapsed
+    value = done / elapsed
     b.chan_batch_set_timing(batch.handle, 1)
     batch.step(acts, args.substeps)
     kt = b.chan_batch_timing_read(batch.handle)
@@ -236,11 +241,13 @@ def run_batched(args, torch, b, gaussian_action):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"batched: {len(specs)} minimal-box channels (2.67 x 2 x 0.8 h), 16x65x16 and "
-                               f"32x65x32 alternating, Re_tau 180/100, opposition or Gaussian wall actions, "
-                               f"10 time steps per env step, one batch step advances every channel",
+                               f"32x65x32 alternating, Re_tau 180/100, opposition control (16x65x16 at Re_tau "
+                               f"180) or Gaussian wall actions sigma 0.1 u_tau, 10 time steps per env step, "
+                               f"one batch step advances every channel",
                    "channels": len(specs), "active_channels": active, "substeps_per_env_step": args.substeps},
         "grid_pt_substeps_per_s": sum(sp["nx"] * sp["ny"] * sp["nz"] for k, sp in enumerate(specs) if codes[k] == 0)
         * args.steps * args.substeps / elapsed,
+        "env_steps_completed": done,
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "plain_one_channel_per_launch": {"value": plain, "unit": "env-steps/s",
                                          "sample": f"channels 0-{len(sub) - 1} of the mix, each stepped alone"},

@@ -185,8 +185,16 @@ int launch_ingest(const StepChan* d_step, int nch, int max_nx, int max_nz, int m
 int launch_finish_step(const StepChan* d_step, int nch, hipStream_t st, KernelTimer* tm);
 int launch_outputs(const StepChan* d_step, int nch, int max_nx, int max_nz, int max_nkx, hipStream_t st,
                    KernelTimer* tm);
-// Plane pass over nch channels of one shape (M_x, M_z from nx, nz).
-int launch_plane_pass(const Dims& d, const PlaneChan* d_plane, int nch, hipStream_t st, KernelTimer* tm);
+// Plane pass over nch channels of one shape (M_x, M_z from nx, nz), with a tiling: PB pencils
+// per z-kernel block, P pairs of padded z rows per x-row block.  The tiling distributes
+// independent transforms over blocks and does not change any result.
+struct PlaneTiles {
+  int PB, P;
+};
+int launch_plane_pass(const Dims& d, const PlaneChan* d_plane, int nch, const PlaneTiles& t, hipStream_t st,
+                      KernelTimer* tm);
+// Every valid tiling for the shape (for the tuner); -1 if the shape has none.
+int plane_tile_candidates(const Dims& d, std::vector<PlaneTiles>* out);
 // N <= 64 column pass over nch channels of one shape: the solve of stage S.stage (if solve)
 // and/or the reconstruction that follows it (if recon; S.stage -1: reconstruction only).
 // d_col: the channels' arguments on the device; h_col (optional): the same on the host, used

@@ -21,6 +21,7 @@ struct ShapeGroup {
   ColChan* d_col = nullptr;       // [members] (pm groups)
   std::vector<ColChan> h_col;     // host copy of d_col
   PlaneChan* d_plane = nullptr;   // [members]
+  PlaneTiles tiles = {0, 0};      // plane-pass tiling chosen by tune_plane
 };
 
 // Envs stepped together: per-channel launch arguments resident on the device, the per-call
@@ -270,6 +271,8 @@ void batch_free(chan_batch* b) {
   delete b;
 }
 
+int tune_plane(chan_batch* b, ShapeGroup& g);
+
 // Groups the envs by grid shape and uploads their launch arguments.  The envs must share
 // one stream and one device and appear once each.
 int batch_build(chan_env* const* envs, int n, chan_batch** out) {
@@ -348,8 +351,56 @@ int batch_build(chan_env* const* envs, int n, chan_batch** out) {
     batch_free(b);
     return fail(CHAN_EDEVICE, "batch argument upload", err);
   }
+  for (ShapeGroup& g : b->groups) {
+    const int rc = tune_plane(b, g);
+    if (rc != CHAN_OK) {
+      batch_free(b);
+      return rc;
+    }
+  }
   *out = b;
   return CHAN_OK;
+}
+
+// Plane-pass tiling of a group: every valid tiling is timed on the group's own buffers and
+// the fastest kept (the plane pass rewrites only its intermediates and H3, with the values
+// the next plane pass writes anyway, and no tiling changes a result).
+int tune_plane(chan_batch* b, ShapeGroup& g) {
+  std::vector<PlaneTiles> cands;
+  if (plane_tile_candidates(g.d, &cands)) return fail(CHAN_EINVAL, "no plane-pass tiling for this grid");
+  g.tiles = cands.back();
+  if (cands.size() == 1) return CHAN_OK;
+  const int nm = (int)g.members.size();
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHECK(hipEventCreate(&e0));
+  hipError_t err = hipEventCreate(&e1);
+  if (err != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(CHAN_EDEVICE, "hipEventCreate", err);
+  }
+  float best = 0.0f;
+  bool have = false;
+  constexpr int REPS = 3;
+  for (const PlaneTiles& t : cands) {
+    if (launch_plane_pass(g.d, g.d_plane, nm, t, b->stream, nullptr)) continue;  // warm-up
+    err = hipEventRecord(e0, b->stream);
+    for (int k = 0; k < REPS && err == hipSuccess; ++k)
+      if (launch_plane_pass(g.d, g.d_plane, nm, t, b->stream, nullptr)) err = hipErrorLaunchFailure;
+    if (err == hipSuccess) err = hipEventRecord(e1, b->stream);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err != hipSuccess) break;
+    if (!have || ms < best) {
+      best = ms;
+      g.tiles = t;
+      have = true;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(CHAN_EDEVICE, "plane-pass tiling", err);
+  return have ? CHAN_OK : fail(CHAN_EDEVICE, "plane-pass tiling: no candidate ran", hipGetLastError());
 }
 
 // The per-call launch arguments of env i.
@@ -460,7 +511,7 @@ int batch_step(chan_batch* b, const double* const* actions, int32_t n_substeps, 
       const bool last = (m == n_substeps - 1) && (r == 2);
       const ColStage S = {r, m, n_substeps};
       for (const ShapeGroup& g : b->groups) {
-        if (launch_plane_pass(g.d, g.d_plane, (int)g.members.size(), st, tm))
+        if (launch_plane_pass(g.d, g.d_plane, (int)g.members.size(), g.tiles, st, tm))
           return fail(CHAN_EDEVICE, "launch plane pass", hipGetLastError());
         if (group_column(b, g, S, true, !last, tm)) return fail(CHAN_EDEVICE, "launch column pass", hipGetLastError());
       }

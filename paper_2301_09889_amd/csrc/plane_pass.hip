@@ -297,55 +297,92 @@ __global__ __launch_bounds__(1024) void k_xrow2(const PlaneChan* __restrict__ ch
   }
 }
 
+// LDS of the x-row kernel with P pairs of rows per block, and its thread count.
+template <int MX>
+static size_t xrow_lds(int P) { return (size_t)(MX + (size_t)6 * P * (MX + 1)) * sizeof(cplx); }
+template <int MX>
+static int xrow_threads(int P) { return ((6 * P * FftPlan<MX>::A + 63) / 64) * 64; }
+
 template <int MZ, int MX>
-static int launch_plane2(const Dims& d, const PlaneChan* chans, int nch, hipStream_t st, KernelTimer* tm) {
-  const int PB = d.nkx < 32 ? d.nkx : 32;
+static int launch_plane2(const Dims& d, const PlaneChan* chans, int nch, const PlaneTiles& t, hipStream_t st,
+                         KernelTimer* tm) {
+  const int PB = t.PB, P = t.P;
+  const int pairs = MZ / 2;
+  if (PB < 1 || PB > d.nkx || P < 1 || pairs % P != 0 || xrow_threads<MX>(P) > 1024) return -1;
   const int nblk = (d.nkx + PB - 1) / PB;
   const size_t shz = (size_t)(MZ + (size_t)PB * (MZ + 1)) * sizeof(cplx);
   const size_t shf = (size_t)(2 * MZ + (size_t)PB * (MZ + 1)) * sizeof(cplx);
   constexpr int ZA = FftPlan<MZ>::A;
   const int zthr = ((PB * ZA + 63) / 64) * 64;
-  // pairs per x-row block: the largest divisor of M_z/2 with 6 P A <= 1024 threads and
-  // 6 P (M_x + 1) complex in LDS <= 80 KiB
-  constexpr int FA = FftPlan<MX>::A;
-  const int pairs = MZ / 2;
-  int P = 1;
-  for (int c = 1; c <= pairs; ++c)
-    if (pairs % c == 0 && 6 * c * FA <= 1024 && (size_t)6 * c * (MX + 1) * sizeof(cplx) <= 80 * 1024) P = c;
-  const int thr = ((6 * P * FA + 63) / 64) * 64;
-  const size_t shx = (size_t)(MX + (size_t)6 * P * (MX + 1)) * sizeof(cplx);
   const unsigned nyz = (unsigned)(d.ny * nch);
   timed_launch(tm, KC_ZINV, k_zinv2<MZ>, dim3(nblk, 6, nyz), dim3(zthr), shz, st, chans, d.ny, PB);
-  timed_launch(tm, KC_XROW, k_xrow2<MX>, dim3(pairs / P, nyz), dim3(thr), shx, st, chans, d.ny, P);
+  timed_launch(tm, KC_XROW, k_xrow2<MX>, dim3(pairs / P, nyz), dim3(xrow_threads<MX>(P)), xrow_lds<MX>(P), st,
+               chans, d.ny, P);
   timed_launch(tm, KC_ZFWD, k_zfwd2<MZ>, dim3(nblk, 3, nyz), dim3(zthr), shf, st, chans, d.ny, PB);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// Valid tilings: z-kernel blocks of 8, 16 or 32 pencils (at most N_x/2); x-row blocks of P
+// pairs of rows with P dividing M_z/2, at most 1024 threads and 80 KiB of LDS.
+template <int MZ, int MX>
+static void tiles2(const Dims& d, std::vector<PlaneTiles>* out) {
+  const int pairs = MZ / 2;
+  std::vector<int> pbs;
+  for (int pb : {8, 16, 32})
+    if (pb <= d.nkx) pbs.push_back(pb);
+  if (pbs.empty()) pbs.push_back(d.nkx);
+  for (int P = 1; P <= pairs; ++P) {
+    if (pairs % P != 0 || xrow_threads<MX>(P) > 1024 || xrow_lds<MX>(P) > 80 * 1024) continue;
+    for (int pb : pbs) out->push_back(PlaneTiles{pb, P});
+  }
+}
+
 template <int MZ>
-static int dispatch_mx(const Dims& d, const PlaneChan* chans, int nch, hipStream_t st, KernelTimer* tm) {
+static int dispatch_mx(const Dims& d, const PlaneChan* chans, int nch, const PlaneTiles& t, hipStream_t st,
+                       KernelTimer* tm, std::vector<PlaneTiles>* tiles) {
   switch (d.mx) {
-    case 6: return launch_plane2<MZ, 6>(d, chans, nch, st, tm);
-    case 12: return launch_plane2<MZ, 12>(d, chans, nch, st, tm);
-    case 24: return launch_plane2<MZ, 24>(d, chans, nch, st, tm);
-    case 48: return launch_plane2<MZ, 48>(d, chans, nch, st, tm);
-    case 96: return launch_plane2<MZ, 96>(d, chans, nch, st, tm);
-    case 192: return launch_plane2<MZ, 192>(d, chans, nch, st, tm);
+#define CHANENV_MX(M)                                              \
+    case M:                                                       \
+      if (tiles) {                                                \
+        tiles2<MZ, M>(d, tiles);                                  \
+        return 0;                                                 \
+      }                                                           \
+      return launch_plane2<MZ, M>(d, chans, nch, t, st, tm);
+    CHANENV_MX(6)
+    CHANENV_MX(12)
+    CHANENV_MX(24)
+    CHANENV_MX(48)
+    CHANENV_MX(96)
+    CHANENV_MX(192)
+#undef CHANENV_MX
     default: return -1;
   }
 }
 
-int launch_plane_pass(const Dims& d, const PlaneChan* chans, int nch, hipStream_t st, KernelTimer* tm) {
-  if (nch < 1) return 0;
-  if ((size_t)d.ny * nch > 65535) return -1;   // grid z limit
+static int dispatch_mz(const Dims& d, const PlaneChan* chans, int nch, const PlaneTiles& t, hipStream_t st,
+                       KernelTimer* tm, std::vector<PlaneTiles>* tiles) {
   switch (d.mz) {
-    case 6: return dispatch_mx<6>(d, chans, nch, st, tm);
-    case 12: return dispatch_mx<12>(d, chans, nch, st, tm);
-    case 24: return dispatch_mx<24>(d, chans, nch, st, tm);
-    case 48: return dispatch_mx<48>(d, chans, nch, st, tm);
-    case 96: return dispatch_mx<96>(d, chans, nch, st, tm);
-    case 192: return dispatch_mx<192>(d, chans, nch, st, tm);
+    case 6: return dispatch_mx<6>(d, chans, nch, t, st, tm, tiles);
+    case 12: return dispatch_mx<12>(d, chans, nch, t, st, tm, tiles);
+    case 24: return dispatch_mx<24>(d, chans, nch, t, st, tm, tiles);
+    case 48: return dispatch_mx<48>(d, chans, nch, t, st, tm, tiles);
+    case 96: return dispatch_mx<96>(d, chans, nch, t, st, tm, tiles);
+    case 192: return dispatch_mx<192>(d, chans, nch, t, st, tm, tiles);
     default: return -1;
   }
+}
+
+int launch_plane_pass(const Dims& d, const PlaneChan* chans, int nch, const PlaneTiles& t, hipStream_t st,
+                      KernelTimer* tm) {
+  if (nch < 1) return 0;
+  if ((size_t)d.ny * nch > 65535) return -1;   // grid z limit
+  return dispatch_mz(d, chans, nch, t, st, tm, nullptr);
+}
+
+int plane_tile_candidates(const Dims& d, std::vector<PlaneTiles>* out) {
+  out->clear();
+  const int rc = dispatch_mz(d, nullptr, 0, PlaneTiles{0, 0}, nullptr, nullptr, out);
+  return (rc == 0 && !out->empty()) ? 0 : -1;
 }
 
 }  // namespace chanenv
