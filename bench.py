@@ -263,13 +263,97 @@ def run_batched(args, torch, b, gaussian_action):
     print(json.dumps(out), flush=True)
 
 
+def run_served(args, torch, b, gaussian_action):
+    """Request loop: Poisson arrivals from many workers, one channel each on mixed grids, served
+    with continuous batching (paper_2301_09889_amd.serve)."""
+    from paper_2301_09889_amd.serve import ChannelServer, run_open_loop
+    torch.cuda.set_device(0)
+    free, _ = torch.cuda.mem_get_info()
+    server = ChannelServer(hbm_budget=free // 2)
+    sizes = (16, 32, 64)
+    lx = {16: 2.67, 32: 2.67, 64: 2 * np.pi}
+    lz = {16: 0.8, 32: 0.8, 64: np.pi}
+    ids, grid_of = [], []
+    t_setup = time.perf_counter()
+    for w in range(args.workers):
+        m = sizes[w % 3]
+        grid = b.ChanGrid(m, 65, m, lx[m], lz[m], 180.0, 0.05, 15.0)
+        cid = server.admit(grid, b.make_opts(controller=0, ic_profile=1), w)
+        if cid is not None:
+            ids.append(cid)
+            grid_of.append(m)
+    t_setup = time.perf_counter() - t_setup
+    rng = np.random.default_rng(args.seed)
+    acts = {}
+
+    def make_action(cid, k):
+        key = (cid, k % 4)
+        if key not in acts:
+            m = grid_of[cid]
+            acts[key] = torch.tensor(gaussian_action(1000 + 7 * cid + k % 4, m, m), dtype=torch.float64, device="cuda")
+        return acts[key]
+
+    # warm-up: every channel once (also builds the batch and tunes the tilings)
+    for cid in ids:
+        server.submit(cid, make_action(cid, 0), args.substeps)
+    while server.has_pending():
+        server.step_once()
+    torch.cuda.synchronize()
+    # closed loop: every channel always has a request pending (saturation)
+    t0 = time.perf_counter()
+    n_done = 0
+    for _ in range(3):
+        for cid in ids:
+            server.submit(cid, make_action(cid, 1), args.substeps)
+        while server.has_pending():
+            n_done += sum(1 for r in server.step_once() if r.code == 0)
+    sat = n_done / (time.perf_counter() - t0)
+    sweep = []
+    for rate in [float(x) for x in args.rates.split(",")]:
+        gaps = rng.exponential(1.0 / rate, size=args.requests)
+        arrivals = list(zip(np.cumsum(gaps), rng.integers(0, len(ids), size=args.requests)))
+        done, wall = run_open_loop(server, [(float(t), int(c)) for t, c in arrivals], make_action, args.substeps)
+        lat = np.array([(r.t_done - r.t_arrival) * 1e3 for r in done if r.code == 0])
+        sweep.append({"offered_per_s": rate, "served_per_s": len(lat) / wall, "p50_ms": float(np.percentile(lat, 50)),
+                      "p99_ms": float(np.percentile(lat, 99)), "requests": len(done)})
+    server.close()
+    out = {
+        "metric": METRIC,
+        "value": sat,
+        "unit": "env-steps/s",
+        "n_gpus": 1,
+        "steps": 3,
+        "warmup": 1,
+        "ms_per_step": 1e3 * len(ids) / sat,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"served: {args.workers} workers, one channel each, grids 16x65x16 / 32x65x32 / "
+                               f"64x65x64 in thirds (minimal box for 16 and 32, 2pi x 2 x pi for 64), Re_tau 180, "
+                               f"Gaussian wall actions, {args.substeps} time steps per request, admission by HBM "
+                               f"footprint against half the free HBM",
+                   "admitted": len(ids), "rejected": server.rejected_channels, "hbm_budget_bytes": server.budget,
+                   "hbm_admitted_bytes": server.used, "setup_s": t_setup},
+        "saturation": {"value": sat, "note": "closed loop: every channel always has one request pending"},
+        "sweep": sweep,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100, help="timed env steps")
     ap.add_argument("--warmup", type=int, default=5, help="untimed env steps")
     ap.add_argument("--substeps", type=int, default=10, help="RK3 time steps per env step")
-    ap.add_argument("--workload", choices=["larger", "minimal", "batched"], default="larger")
+    ap.add_argument("--workload", choices=["larger", "minimal", "batched", "served"], default="larger")
+    ap.add_argument("--workers", type=int, default=512, help="workers (one channel each) of the served workload")
+    ap.add_argument("--rates", default="200,1000,4000", help="offered request rates (1/s) of the served sweep")
+    ap.add_argument("--requests", type=int, default=600, help="requests per rate of the served sweep")
     ap.add_argument("--channels", type=int, default=256, help="channels of the batched workload")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-substeps", type=int, default=8, help="time steps in the oracle sample")
@@ -292,6 +376,9 @@ def main():
 
     if args.workload == "batched":
         run_batched(args, torch, b, gaussian_action)
+        return
+    if args.workload == "served":
+        run_served(args, torch, b, gaussian_action)
         return
     g = LARGER if args.workload == "larger" else MINIMAL
     if args.workload == "larger":

@@ -212,12 +212,20 @@ const char* chan_kernel_class_name(int32_t cls);
  * Synchronises the stream before returning.  Calls on one batch, or on batches
  * sharing an env, must not overlap.
  *
+ * chan_batch_step_subset: the same for the n envs idx[0..n) of the batch (indices
+ * as at creation, each at most once), the others untouched; the per-env arrays are
+ * indexed like idx.  This is how a request loop advances whichever channels have a
+ * pending request.  Extra errors: CHAN_EINVAL for a bad, repeated or missing index.
+ *
  * chan_batch_set_timing / chan_batch_timing_read: as for an env, for the batch's
  * launches.  chan_batch_size: number of envs (0 for NULL). */
 typedef struct chan_batch chan_batch;
 int chan_batch_create(int32_t n, struct chan_env* const* envs, struct chan_batch** out);
 int chan_batch_step(struct chan_batch* batch, const double* const* actions, int32_t n_substeps,
                     double* const* obs, double* const* tau_w, double* const* drag, int32_t* results);
+int chan_batch_step_subset(struct chan_batch* batch, int32_t n, const int32_t* idx,
+                           const double* const* actions, int32_t n_substeps, double* const* obs,
+                           double* const* tau_w, double* const* drag, int32_t* results);
 void chan_batch_destroy(struct chan_batch* batch);
 int32_t chan_batch_size(const struct chan_batch* batch);
 int chan_batch_set_timing(struct chan_batch* batch, int32_t enable);

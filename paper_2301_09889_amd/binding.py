@@ -111,6 +111,9 @@ def load_library():
     lib.chan_batch_create.restype = ctypes.c_int
     lib.chan_batch_step.argtypes = [vp, P(vp), ctypes.c_int32, P(vp), P(vp), P(vp), P(ctypes.c_int32)]
     lib.chan_batch_step.restype = ctypes.c_int
+    lib.chan_batch_step_subset.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int32), P(vp), ctypes.c_int32, P(vp),
+                                           P(vp), P(vp), P(ctypes.c_int32)]
+    lib.chan_batch_step_subset.restype = ctypes.c_int
     lib.chan_batch_destroy.argtypes = [vp]
     lib.chan_batch_destroy.restype = None
     lib.chan_batch_size.argtypes = [vp]
@@ -222,6 +225,15 @@ def chan_batch_step(h, action_ptrs, n_substeps, obs_ptrs, tau_ptrs, drag_ptrs, r
     int32 array of the batch size."""
     return load_library().chan_batch_step(h, _ptr_array(action_ptrs), int(n_substeps), _ptr_array(obs_ptrs),
                                           _ptr_array(tau_ptrs), _ptr_array(drag_ptrs), results)
+
+
+def chan_batch_step_subset(h, idx, action_ptrs, n_substeps, obs_ptrs, tau_ptrs, drag_ptrs, results=None):
+    """Like chan_batch_step for the envs idx (positions at creation); pointer lists are indexed
+    like idx."""
+    ia = (ctypes.c_int32 * len(idx))(*[int(i) for i in idx])
+    return load_library().chan_batch_step_subset(h, len(idx), ia, _ptr_array(action_ptrs), int(n_substeps),
+                                                 _ptr_array(obs_ptrs), _ptr_array(tau_ptrs), _ptr_array(drag_ptrs),
+                                                 results)
 
 
 def chan_batch_destroy(h):
@@ -347,6 +359,26 @@ class ChanBatch:
         codes = list(self.results)
         if rc != CHAN_OK and all(c == CHAN_OK for c in codes):
             raise ChanError(rc, "chan_batch_step")
+        return codes
+
+    def step_subset(self, idx, actions, n_substeps):
+        """Advance only the envs idx (positions in this batch); actions indexed like idx (or None).
+        Returns the result codes, indexed like idx."""
+        aptrs = []
+        for k, i in enumerate(idx):
+            e = self.envs[i]
+            a = actions[k] if actions is not None else None
+            if a is not None:
+                assert a.dtype == e.torch.float64 and a.is_contiguous()
+                assert tuple(a.shape) == (e.grid.nz, e.grid.nx)
+            aptrs.append(a.data_ptr() if a is not None else 0)
+        res = (ctypes.c_int32 * len(idx))()
+        sel = [self.envs[i] for i in idx]
+        rc = chan_batch_step_subset(self.handle, idx, aptrs, n_substeps, [e.obs.data_ptr() for e in sel],
+                                    [e.tau_w.data_ptr() for e in sel], [e.drag.data_ptr() for e in sel], res)
+        codes = list(res)
+        if rc != CHAN_OK and all(c == CHAN_OK for c in codes):
+            raise ChanError(rc, "chan_batch_step_subset")
         return codes
 
     def close(self):

@@ -13,28 +13,36 @@
 
 using namespace chanenv;
 
-// Channels of one grid shape inside a batch: one launch per kernel covers all of them.
+// Channels of one grid shape inside a batch: one launch per kernel covers the active ones.
 struct ShapeGroup {
   Dims d;
   bool pm;                        // N <= 64: the parity-major column kernels
   std::vector<int> members;       // indices into chan_batch::envs
-  ColChan* d_col = nullptr;       // [members] (pm groups)
-  std::vector<ColChan> h_col;     // host copy of d_col
-  PlaneChan* d_plane = nullptr;   // [members]
   PlaneTiles tiles = {0, 0};      // plane-pass tiling chosen by tune_plane
+  // this call's active members, their arguments in the staging buffers
+  int nact = 0;
+  ColChan* d_col = nullptr;
+  const ColChan* h_col = nullptr;
+  PlaneChan* d_plane = nullptr;
 };
 
-// Envs stepped together: per-channel launch arguments resident on the device, the per-call
-// ones staged through pinned memory.  Every env owns a batch of one for its own steps.
+// Envs stepped together.  Each call copies the launch arguments of its active channels
+// (per-step StepChan, and the fixed ColChan / PlaneChan, grouped by shape) into one pinned
+// staging buffer and uploads it with one copy.  Every env owns a batch of one for its own
+// steps.
 struct chan_batch {
   std::vector<chan_env*> envs;
   std::vector<ShapeGroup> groups;
+  std::vector<int> group_of;      // env index -> group
+  std::vector<ColChan> col;       // per env
+  std::vector<PlaneChan> plane;   // per env
   hipStream_t stream = nullptr;
-  void* dev = nullptr;            // ColChan[n], PlaneChan[n], StepChan[n], int status[n]
-  StepChan* d_step = nullptr;
+  void* dev = nullptr;            // staging copy on the device + int status[n]
+  char* h_stage = nullptr;        // pinned: StepChan[n] | ColChan[n] | PlaneChan[n]
+  size_t stage_bytes = 0, off_col = 0, off_plane = 0;
   int* d_status = nullptr;
-  StepChan* h_step = nullptr;     // pinned
   int* h_status = nullptr;        // pinned
+  std::vector<int> active;        // this call's env indices, in call order
   int max_nx = 0, max_nz = 0, max_nkx = 0;
   KernelTimer timer;
   double timing_ms[KC_COUNT];
@@ -266,15 +274,96 @@ void batch_free(chan_batch* b) {
   if (b->stream) (void)hipStreamSynchronize(b->stream);
   for (hipEvent_t ev : b->timer.pool) (void)hipEventDestroy(ev);
   if (b->dev) (void)hipFree(b->dev);
-  if (b->h_step) (void)hipHostFree(b->h_step);
+  if (b->h_stage) (void)hipHostFree(b->h_stage);
   if (b->h_status) (void)hipHostFree(b->h_status);
   delete b;
 }
 
+StepChan* stage_step(const chan_batch* b) { return (StepChan*)b->h_stage; }
+StepChan* dev_step(const chan_batch* b) { return (StepChan*)b->dev; }
+
+// The per-call launch arguments of env i (k: its position among this call's active envs).
+StepChan make_step_chan(const chan_batch* b, int i, int k, const double* action, int n_sub, double* obs,
+                        double* tau_w, double* drag) {
+  const chan_env* e = b->envs[i];
+  const Dims& d = e->d;
+  const bool ext = e->opts.controller == CHAN_CTRL_EXTERNAL;
+  StepChan c;
+  std::memset(&c, 0, sizeof(c));
+  c.nx = d.nx;
+  c.nz = d.nz;
+  c.nkx = d.nkx;
+  c.ncol = d.ncol;
+  c.n_sub = n_sub;
+  c.skip = (e->have_flow && !e->poisoned) ? 0 : 1;
+  c.zero_vw = (ext && action == nullptr) ? 1 : 0;
+  c.copy_vw = ext ? 1 : 0;
+  c.clip = e->opts.clip;
+  c.action = ext ? action : nullptr;
+  c.drag_out = drag;
+  const size_t plane = (size_t)d.ny * d.nkx * d.nz;
+  if (obs) {
+    int slot = 0;
+    for (int f = 0; f < 3; ++f) {
+      if (!(e->opts.obs_mask & (1u << f))) continue;
+      c.out_src[f] = e->s.F6 + (size_t)f * plane + (size_t)e->js * d.nkx * d.nz;
+      c.out_dst[f] = obs + (size_t)slot * d.nz * d.nx;
+      ++slot;
+    }
+  }
+  if (tau_w) {
+    c.out_src[3] = e->s.tauw;
+    c.out_dst[3] = tau_w;
+  }
+  c.vw_new = e->s.vw_new;
+  c.vw_old = e->s.vw_old;
+  c.tmp2d = e->s.tmp2d;
+  c.twnx = e->s.twnx;
+  c.twnz = e->s.twnz;
+  c.drag_acc = e->s.drag_acc;
+  c.status = e->s.status;
+  c.status_out = b->d_status + k;
+  return c;
+}
+
+// Stages the arguments of the active envs (b->active) and uploads them; StepChan entries
+// come from step(i, k).
+template <class StepFn>
+int stage_call(chan_batch* b, StepFn step) {
+  const int na = (int)b->active.size();
+  StepChan* hs = stage_step(b);
+  ColChan* hc = (ColChan*)(b->h_stage + b->off_col);
+  PlaneChan* hp = (PlaneChan*)(b->h_stage + b->off_plane);
+  char* dbase = (char*)b->dev;
+  for (ShapeGroup& g : b->groups) g.nact = 0;
+  for (int k = 0; k < na; ++k) {
+    hs[k] = step(b->active[k], k);
+    b->groups[b->group_of[b->active[k]]].nact++;
+  }
+  size_t pos = 0;
+  for (ShapeGroup& g : b->groups) {
+    g.d_col = (ColChan*)(dbase + b->off_col) + pos;
+    g.h_col = hc + pos;
+    g.d_plane = (PlaneChan*)(dbase + b->off_plane) + pos;
+    for (int k = 0; k < na; ++k) {
+      const int i = b->active[k];
+      if (&b->groups[b->group_of[i]] != &g) continue;
+      hc[pos] = b->col[i];
+      hp[pos] = b->plane[i];
+      ++pos;
+    }
+  }
+  // the three arrays, each as far as it is used
+  HIPCHECK(hipMemcpyAsync(dbase, b->h_stage, na * sizeof(StepChan), hipMemcpyHostToDevice, b->stream));
+  HIPCHECK(hipMemcpyAsync(dbase + b->off_col, hc, pos * sizeof(ColChan), hipMemcpyHostToDevice, b->stream));
+  HIPCHECK(hipMemcpyAsync(dbase + b->off_plane, hp, pos * sizeof(PlaneChan), hipMemcpyHostToDevice, b->stream));
+  return CHAN_OK;
+}
+
 int tune_plane(chan_batch* b, ShapeGroup& g);
 
-// Groups the envs by grid shape and uploads their launch arguments.  The envs must share
-// one stream and one device and appear once each.
+// Groups the envs by grid shape and allocates the staging buffers.  The envs must share one
+// stream and one device and appear once each.
 int batch_build(chan_env* const* envs, int n, chan_batch** out) {
   if (n < 1 || !envs) return fail(CHAN_EINVAL, "batch: no envs");
   for (int i = 0; i < n; ++i) {
@@ -307,6 +396,9 @@ int batch_build(chan_env* const* envs, int n, chan_batch** out) {
       b->groups[gi].pm = pm;
     }
     b->groups[gi].members.push_back(i);
+    b->group_of.push_back(gi);
+    b->col.push_back(make_col_chan(e));
+    b->plane.push_back(make_plane_chan(e));
     if (e->d.ny * (int)b->groups[gi].members.size() > 65535) {
       batch_free(b);
       return fail(CHAN_EINVAL, "batch: too many channels of one shape (N_y x count > 65535)");
@@ -315,48 +407,28 @@ int batch_build(chan_env* const* envs, int n, chan_batch** out) {
     b->max_nz = std::max(b->max_nz, e->d.nz);
     b->max_nkx = std::max(b->max_nkx, e->d.nkx);
   }
-  const size_t col_b = align256(n * sizeof(ColChan)), plane_b = align256(n * sizeof(PlaneChan));
-  const size_t step_b = align256(n * sizeof(StepChan)), stat_b = align256(n * sizeof(int));
-  hipError_t err = hipMalloc(&b->dev, col_b + plane_b + step_b + stat_b);
+  b->off_col = align256(n * sizeof(StepChan));
+  b->off_plane = b->off_col + align256(n * sizeof(ColChan));
+  b->stage_bytes = b->off_plane + align256(n * sizeof(PlaneChan));
+  hipError_t err = hipMalloc(&b->dev, b->stage_bytes + align256(n * sizeof(int)));
   if (err != hipSuccess) {
     batch_free(b);
     return fail(CHAN_ENOMEM, "hipMalloc(batch)", err);
   }
-  if (hipHostMalloc((void**)&b->h_step, n * sizeof(StepChan)) != hipSuccess ||
+  b->d_status = (int*)((char*)b->dev + b->stage_bytes);
+  if (hipHostMalloc((void**)&b->h_stage, b->stage_bytes) != hipSuccess ||
       hipHostMalloc((void**)&b->h_status, n * sizeof(int)) != hipSuccess) {
     batch_free(b);
     return fail(CHAN_ENOMEM, "hipHostMalloc(batch)");
   }
-  char* base = (char*)b->dev;
-  ColChan* d_col = (ColChan*)base;
-  PlaneChan* d_plane = (PlaneChan*)(base + col_b);
-  b->d_step = (StepChan*)(base + col_b + plane_b);
-  b->d_status = (int*)(base + col_b + plane_b + step_b);
-  std::vector<ColChan> hc;
-  std::vector<PlaneChan> hp;
-  for (ShapeGroup& g : b->groups) {
-    g.d_col = d_col + hc.size();
-    g.d_plane = d_plane + hp.size();
-    for (int i : g.members) {
-      hc.push_back(make_col_chan(b->envs[i]));
-      hp.push_back(make_plane_chan(b->envs[i]));
-      g.h_col.push_back(hc.back());
-    }
-  }
-  err = hipMemcpyAsync(d_col, hc.data(), hc.size() * sizeof(ColChan), hipMemcpyHostToDevice, b->stream);
-  if (err == hipSuccess)
-    err = hipMemcpyAsync(d_plane, hp.data(), hp.size() * sizeof(PlaneChan), hipMemcpyHostToDevice, b->stream);
-  if (err == hipSuccess) err = hipStreamSynchronize(b->stream);
-  if (err != hipSuccess) {
+  // tune with every env staged (no step arguments are used by the plane pass)
+  b->active.resize(n);
+  for (int i = 0; i < n; ++i) b->active[i] = i;
+  int rc = stage_call(b, [&](int i, int k) { return make_step_chan(b, i, k, nullptr, 1, nullptr, nullptr, nullptr); });
+  for (size_t g = 0; g < b->groups.size() && rc == CHAN_OK; ++g) rc = tune_plane(b, b->groups[g]);
+  if (rc != CHAN_OK) {
     batch_free(b);
-    return fail(CHAN_EDEVICE, "batch argument upload", err);
-  }
-  for (ShapeGroup& g : b->groups) {
-    const int rc = tune_plane(b, g);
-    if (rc != CHAN_OK) {
-      batch_free(b);
-      return rc;
-    }
+    return rc;
   }
   *out = b;
   return CHAN_OK;
@@ -370,7 +442,7 @@ int tune_plane(chan_batch* b, ShapeGroup& g) {
   if (plane_tile_candidates(g.d, &cands)) return fail(CHAN_EINVAL, "no plane-pass tiling for this grid");
   g.tiles = cands.back();
   if (cands.size() == 1) return CHAN_OK;
-  const int nm = (int)g.members.size();
+  const int nm = g.nact;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHECK(hipEventCreate(&e0));
   hipError_t err = hipEventCreate(&e1);
@@ -403,55 +475,16 @@ int tune_plane(chan_batch* b, ShapeGroup& g) {
   return have ? CHAN_OK : fail(CHAN_EDEVICE, "plane-pass tiling: no candidate ran", hipGetLastError());
 }
 
-// The per-call launch arguments of env i.
-StepChan make_step_chan(const chan_batch* b, int i, const double* action, int n_sub, double* obs, double* tau_w,
-                        double* drag) {
-  const chan_env* e = b->envs[i];
-  const Dims& d = e->d;
-  const bool ext = e->opts.controller == CHAN_CTRL_EXTERNAL;
-  StepChan c;
-  std::memset(&c, 0, sizeof(c));
-  c.nx = d.nx;
-  c.nz = d.nz;
-  c.nkx = d.nkx;
-  c.ncol = d.ncol;
-  c.n_sub = n_sub;
-  c.zero_vw = (ext && action == nullptr) ? 1 : 0;
-  c.copy_vw = ext ? 1 : 0;
-  c.clip = e->opts.clip;
-  c.action = ext ? action : nullptr;
-  c.drag_out = drag;
-  const size_t plane = (size_t)d.ny * d.nkx * d.nz;
-  if (obs) {
-    int slot = 0;
-    for (int f = 0; f < 3; ++f) {
-      if (!(e->opts.obs_mask & (1u << f))) continue;
-      c.out_src[f] = e->s.F6 + (size_t)f * plane + (size_t)e->js * d.nkx * d.nz;
-      c.out_dst[f] = obs + (size_t)slot * d.nz * d.nx;
-      ++slot;
-    }
-  }
-  if (tau_w) {
-    c.out_src[3] = e->s.tauw;
-    c.out_dst[3] = tau_w;
-  }
-  c.vw_new = e->s.vw_new;
-  c.vw_old = e->s.vw_old;
-  c.tmp2d = e->s.tmp2d;
-  c.twnx = e->s.twnx;
-  c.twnz = e->s.twnz;
-  c.drag_acc = e->s.drag_acc;
-  c.status = e->s.status;
-  c.status_out = b->d_status + i;
-  return c;
-}
-
-// Column pass of one group after the plane pass of stage S.stage (or, S.stage = -1, the
-// reconstruction alone).
+// Column pass of one group's active channels after the plane pass of stage S.stage (or,
+// S.stage = -1, the reconstruction alone).
 int group_column(chan_batch* b, const ShapeGroup& g, const ColStage& S, bool solve, bool recon, KernelTimer* tm) {
-  if (g.pm) return launch_column_pm(g.d, g.d_col, g.h_col.data(), (int)g.members.size(), S, solve, recon, b->stream, tm);
-  for (int i : g.members) {
-    chan_env* e = b->envs[i];
+  if (g.nact == 0) return 0;
+  if (g.pm) return launch_column_pm(g.d, g.d_col, g.h_col, g.nact, S, solve, recon, b->stream, tm);
+  for (int k = 0; k < g.nact; ++k) {
+    const ColChan& c = g.h_col[k];
+    chan_env* e = nullptr;
+    for (int i : g.members)
+      if (b->col[i].vS == c.vS) e = b->envs[i];
     const int r = S.stage;
     int mode = WALL_OPP;
     double s = 0.0;
@@ -470,10 +503,17 @@ int group_column(chan_batch* b, const ShapeGroup& g, const ColStage& S, bool sol
 // the batch (after reset or set_state).
 int batch_prime(chan_batch* b) {
   const int n = (int)b->envs.size();
-  for (int i = 0; i < n; ++i) b->h_step[i] = make_step_chan(b, i, nullptr, 1, nullptr, nullptr, nullptr);
-  for (int i = 0; i < n; ++i) b->h_step[i].zero_vw = 0;
-  HIPCHECK(hipMemcpyAsync(b->d_step, b->h_step, n * sizeof(StepChan), hipMemcpyHostToDevice, b->stream));
-  if (launch_begin_step(b->d_step, n, b->stream, nullptr)) return fail(CHAN_EDEVICE, "launch begin_step", hipGetLastError());
+  b->active.resize(n);
+  for (int i = 0; i < n; ++i) b->active[i] = i;
+  int rc = stage_call(b, [&](int i, int k) {
+    StepChan c = make_step_chan(b, i, k, nullptr, 1, nullptr, nullptr, nullptr);
+    c.zero_vw = 0;
+    c.skip = 0;
+    return c;
+  });
+  if (rc != CHAN_OK) return rc;
+  if (launch_begin_step(dev_step(b), n, b->stream, nullptr))
+    return fail(CHAN_EDEVICE, "launch begin_step", hipGetLastError());
   const ColStage S = {-1, 0, 1};
   for (const ShapeGroup& g : b->groups)
     if (group_column(b, g, S, false, true, nullptr))
@@ -482,27 +522,40 @@ int batch_prime(chan_batch* b) {
   return CHAN_OK;
 }
 
-// One env step of every env of the batch.  Per-env pointer arrays may be null (all null).
-int batch_step(chan_batch* b, const double* const* actions, int32_t n_substeps, double* const* obs,
-               double* const* tau_w, double* const* drag, int32_t* results) {
+// One env step of the envs idx[0..na) of the batch (per-call arrays indexed like idx; any
+// array may be null = all null).
+int batch_step(chan_batch* b, int32_t na, const int32_t* idx, const double* const* actions, int32_t n_substeps,
+               double* const* obs, double* const* tau_w, double* const* drag, int32_t* results) {
   if (n_substeps < 1) return fail(CHAN_EINVAL, "n_substeps < 1");
   const int n = (int)b->envs.size();
+  if (na < 1 || na > n) return fail(CHAN_EINVAL, "batch step: bad number of envs");
+  b->active.resize(na);
+  {
+    std::vector<char> seen(n, 0);
+    for (int k = 0; k < na; ++k) {
+      const int i = idx ? idx[k] : k;
+      if (i < 0 || i >= n || seen[i]) return fail(CHAN_EINVAL, "batch step: env index out of range or repeated");
+      seen[i] = 1;
+      b->active[k] = i;
+    }
+  }
   int n_ready = 0;
-  for (int i = 0; i < n; ++i) n_ready += (b->envs[i]->have_flow && !b->envs[i]->poisoned) ? 1 : 0;
+  for (int k = 0; k < na; ++k) n_ready += (b->envs[b->active[k]]->have_flow && !b->envs[b->active[k]]->poisoned) ? 1 : 0;
   if (n_ready == 0) return fail(CHAN_ESTATE, "no env with a valid flow state");
   g_last_error.clear();
   bool any_action = false;
-  for (int i = 0; i < n; ++i) {
-    b->h_step[i] = make_step_chan(b, i, actions ? actions[i] : nullptr, n_substeps, obs ? obs[i] : nullptr,
-                                  tau_w ? tau_w[i] : nullptr, drag ? drag[i] : nullptr);
-    b->h_step[i].skip = (b->envs[i]->have_flow && !b->envs[i]->poisoned) ? 0 : 1;
-    any_action = any_action || (b->h_step[i].action != nullptr && !b->h_step[i].skip);
-  }
+  int rc = stage_call(b, [&](int i, int k) {
+    StepChan c = make_step_chan(b, i, k, actions ? actions[k] : nullptr, n_substeps, obs ? obs[k] : nullptr,
+                                tau_w ? tau_w[k] : nullptr, drag ? drag[k] : nullptr);
+    any_action = any_action || (c.action != nullptr && !c.skip);
+    return c;
+  });
+  if (rc != CHAN_OK) return rc;
   hipStream_t st = b->stream;
   KernelTimer* tm = b->timer.on ? &b->timer : nullptr;
-  HIPCHECK(hipMemcpyAsync(b->d_step, b->h_step, n * sizeof(StepChan), hipMemcpyHostToDevice, st));
-  if (launch_begin_step(b->d_step, n, st, tm)) return fail(CHAN_EDEVICE, "launch begin_step", hipGetLastError());
-  if (any_action && launch_ingest(b->d_step, n, b->max_nx, b->max_nz, b->max_nkx, st, tm))
+  StepChan* ds = dev_step(b);
+  if (launch_begin_step(ds, na, st, tm)) return fail(CHAN_EDEVICE, "launch begin_step", hipGetLastError());
+  if (any_action && launch_ingest(ds, na, b->max_nx, b->max_nz, b->max_nkx, st, tm))
     return fail(CHAN_EDEVICE, "launch ingest", hipGetLastError());
   for (int m = 0; m < n_substeps; ++m) {
     for (int r = 0; r < 3; ++r) {
@@ -511,7 +564,8 @@ int batch_step(chan_batch* b, const double* const* actions, int32_t n_substeps, 
       const bool last = (m == n_substeps - 1) && (r == 2);
       const ColStage S = {r, m, n_substeps};
       for (const ShapeGroup& g : b->groups) {
-        if (launch_plane_pass(g.d, g.d_plane, (int)g.members.size(), g.tiles, st, tm))
+        if (g.nact == 0) continue;
+        if (launch_plane_pass(g.d, g.d_plane, g.nact, g.tiles, st, tm))
           return fail(CHAN_EDEVICE, "launch plane pass", hipGetLastError());
         if (group_column(b, g, S, true, !last, tm)) return fail(CHAN_EDEVICE, "launch column pass", hipGetLastError());
       }
@@ -520,17 +574,18 @@ int batch_step(chan_batch* b, const double* const* actions, int32_t n_substeps, 
   const ColStage S_end = {-1, 0, n_substeps};
   for (const ShapeGroup& g : b->groups)
     if (group_column(b, g, S_end, false, true, tm)) return fail(CHAN_EDEVICE, "launch column pass", hipGetLastError());
-  if (launch_finish_step(b->d_step, n, st, tm)) return fail(CHAN_EDEVICE, "launch finish_step", hipGetLastError());
-  if (launch_outputs(b->d_step, n, b->max_nx, b->max_nz, b->max_nkx, st, tm))
+  if (launch_finish_step(ds, na, st, tm)) return fail(CHAN_EDEVICE, "launch finish_step", hipGetLastError());
+  if (launch_outputs(ds, na, b->max_nx, b->max_nz, b->max_nkx, st, tm))
     return fail(CHAN_EDEVICE, "launch outputs", hipGetLastError());
-  HIPCHECK(hipMemcpyAsync(b->h_status, b->d_status, n * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipMemcpyAsync(b->h_status, b->d_status, na * sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));
-  int rc = CHAN_OK;
-  for (int i = 0; i < n; ++i) {
-    chan_env* e = b->envs[i];
-    const int status = b->h_status[i];
+  rc = CHAN_OK;
+  const StepChan* hs = stage_step(b);
+  for (int k = 0; k < na; ++k) {
+    chan_env* e = b->envs[b->active[k]];
+    const int status = b->h_status[k];
     int ri = CHAN_OK;
-    if (b->h_step[i].skip) {
+    if (hs[k].skip) {
       ri = CHAN_ESTATE;
       if (rc == CHAN_OK) fail(CHAN_ESTATE, "env without a valid flow state (skipped)");
     } else if (status & STATUS_BAD_ACTION) {
@@ -545,7 +600,7 @@ int batch_step(chan_batch* b, const double* const* actions, int32_t n_substeps, 
         if (rc == CHAN_OK) fail(CHAN_ENONFINITE, "non-finite state after the step");
       }
     }
-    if (results) results[i] = ri;
+    if (results) results[k] = ri;
     if (rc == CHAN_OK) rc = ri;
   }
   return rc;
@@ -921,7 +976,7 @@ int chan_env_query(const chan_env* e, chan_info_t* out) {
 int chan_env_step(chan_env* e, const double* action, int32_t n_substeps, double* obs, double* tau_w,
                   double* drag) {
   if (!e) return CHAN_EINVAL;
-  return batch_step(e->self, &action, n_substeps, &obs, &tau_w, &drag, nullptr);
+  return batch_step(e->self, 1, nullptr, &action, n_substeps, &obs, &tau_w, &drag, nullptr);
 }
 
 int chan_batch_create(int32_t n, chan_env* const* envs, chan_batch** out) {
@@ -934,7 +989,14 @@ int chan_batch_create(int32_t n, chan_env* const* envs, chan_batch** out) {
 int chan_batch_step(chan_batch* b, const double* const* actions, int32_t n_substeps, double* const* obs,
                     double* const* tau_w, double* const* drag, int32_t* results) {
   if (!b) return CHAN_EINVAL;
-  return batch_step(b, actions, n_substeps, obs, tau_w, drag, results);
+  return batch_step(b, (int32_t)b->envs.size(), nullptr, actions, n_substeps, obs, tau_w, drag, results);
+}
+
+int chan_batch_step_subset(chan_batch* b, int32_t n, const int32_t* idx, const double* const* actions,
+                           int32_t n_substeps, double* const* obs, double* const* tau_w, double* const* drag,
+                           int32_t* results) {
+  if (!b || !idx) return CHAN_EINVAL;
+  return batch_step(b, n, idx, actions, n_substeps, obs, tau_w, drag, results);
 }
 
 void chan_batch_destroy(chan_batch* b) { batch_free(b); }

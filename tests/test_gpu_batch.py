@@ -161,3 +161,33 @@ def test_invalid_channel_is_skipped():
     only.close()
     for e in alone + mixed:
         e.close()
+
+
+def test_subsets_match_alone_bitwise():
+    """Different subsets of a mixed batch advanced over several calls (what a request loop
+    does): every channel ends bitwise where its twin, advanced alone by the same calls, ends;
+    channels outside a call's subset are untouched by it."""
+    import paper_2301_09889_amd.binding as b
+    alone, mixed = make_envs(MIX), make_envs(MIX)
+    batch = b.ChanBatch(mixed)
+    plan = [[0, 1, 2, 3, 4, 5, 6], [1, 3, 5], [6, 0], [2], [4, 5, 6, 1]]
+    for k, idx in enumerate(plan):
+        acts = actions_for(MIX, k)
+        before = {i: mixed[i].get_state() for i in range(len(MIX)) if i not in idx}
+        codes = batch.step_subset(idx, [acts[i] for i in idx], 2)
+        assert codes == [0] * len(idx), (k, codes)
+        for i in idx:
+            alone[i].step(acts[i], 2)
+        for i in range(len(MIX)):
+            if i in idx:
+                assert np.array_equal(alone[i].get_state(), mixed[i].get_state()), (k, i)
+                oa, om = outputs(alone[i]), outputs(mixed[i])
+                assert np.array_equal(oa[0], om[0]) and np.array_equal(oa[1], om[1]) and oa[2] == om[2], (k, i)
+            else:
+                assert np.array_equal(before[i], mixed[i].get_state()), (k, i)
+    with pytest.raises(b.ChanError) as ei:
+        batch.step_subset([1, 1], None, 2)
+    assert ei.value.code == b.CHAN_EINVAL
+    batch.close()
+    for e in alone + mixed:
+        e.close()
