@@ -162,14 +162,14 @@ def cpu_baseline(g, opts_kw, n_sub_env, seed, budget_substeps):
                       f"({dt:.1f} s), scaled to {n_sub_env} time steps per env step; one BLAS thread"}
 
 
-def batched_specs(n):
+def batched_specs(n, mix="uneven"):
     """Uneven mix: 16x65x16 and 32x65x32 minimal-box channels alternating, Re_tau 180 / 100 in
     pairs, seed = channel index; opposition control on the 16x65x16 channels at Re_tau 180,
     Gaussian wall actions on the others (opposition control with alpha = 1 from the seeded
     initial fields diverges for some seeds at Re_tau 100 and on 32x65x32, in the oracle too)."""
     specs = []
     for i in range(n):
-        m = 16 if i % 2 == 0 else 32
+        m = 16 if (i % 2 == 0 or mix == "minimal") else 32
         re = 180.0 if (i // 2) % 2 == 0 else 100.0
         specs.append(dict(nx=m, ny=65, nz=m, lx=2.67, lz=0.8, re_tau=re, dt_plus=0.05, obs_y_plus=15.0,
                           external=not (m == 16 and re == 180.0), seed=i))
@@ -179,7 +179,7 @@ def batched_specs(n):
 def run_batched(args, torch, b, gaussian_action):
     """Many channels advanced together (one launch per kernel and grid shape), against the same
     channels advanced one per launch."""
-    specs = batched_specs(args.channels)
+    specs = batched_specs(args.channels, args.mix)
     torch.cuda.set_device(0)
     envs, acts = [], []
     for sp in specs:
@@ -240,10 +240,11 @@ def run_batched(args, torch, b, gaussian_action):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"batched: {len(specs)} minimal-box channels (2.67 x 2 x 0.8 h), 16x65x16 and "
-                               f"32x65x32 alternating, Re_tau 180/100, opposition control (16x65x16 at Re_tau "
-                               f"180) or Gaussian wall actions sigma 0.1 u_tau, 10 time steps per env step, "
-                               f"one batch step advances every channel",
+        "config": {"workload": f"batched: {len(specs)} minimal-box channels (2.67 x 2 x 0.8 h), "
+                               + ("16x65x16 and 32x65x32 alternating" if args.mix == "uneven" else "all 16x65x16")
+                               + ", Re_tau 180/100, opposition control (16x65x16 at Re_tau 180) or Gaussian wall "
+                               "actions sigma 0.1 u_tau, 10 time steps per env step, one batch step advances "
+                               "every channel",
                    "channels": len(specs), "active_channels": active, "substeps_per_env_step": args.substeps},
         "grid_pt_substeps_per_s": sum(sp["nx"] * sp["ny"] * sp["nz"] for k, sp in enumerate(specs) if codes[k] == 0)
         * args.steps * args.substeps / elapsed,
@@ -355,6 +356,8 @@ def main():
     ap.add_argument("--rates", default="200,1000,4000", help="offered request rates (1/s) of the served sweep")
     ap.add_argument("--requests", type=int, default=600, help="requests per rate of the served sweep")
     ap.add_argument("--channels", type=int, default=256, help="channels of the batched workload")
+    ap.add_argument("--mix", choices=["uneven", "minimal"], default="uneven",
+                    help="batched workload: 16x65x16 / 32x65x32 alternating, or 16x65x16 only")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-substeps", type=int, default=8, help="time steps in the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")

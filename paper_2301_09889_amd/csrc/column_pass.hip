@@ -371,7 +371,9 @@ __device__ __forceinline__ void fmac_row(double (&acc)[G], const double (&q)[G],
 // 0, 1 (even coefficients) hold S_{16m+k}, rows 2, 3 (odd) hold D_{16m+k} in register group m
 // at row position k, so each term of the matvec is a row broadcast (no LDS).  Returns
 // parity-major coefficients a (this lane) and the tail a_N.
-template <int N, int F, class Load>
+// CHUNK: request the cosines of each group of 16 terms just before its FMA blocks instead of
+// all at once (fewer live registers; the same arithmetic in the same order).
+template <int N, int F, bool CHUNK, class Load>
 __device__ __forceinline__ void dct_fwd_pm(const Lane<N>& L, Load load, const double* __restrict__ kfwd, cplx* a,
                                            cplx* at) {
   constexpr int H = N / 2;
@@ -381,8 +383,10 @@ __device__ __forceinline__ void dct_fwd_pm(const Lane<N>& L, Load load, const do
   // this lane's cosines, all requested before the first use (the FMA blocks below are
   // ordering points for memory operations)
   double cf[H + 1];
+  if constexpr (!CHUNK) {
 #pragma unroll
-  for (int j = 0; j <= H; ++j) cf[j] = kfwd[j * 64 + lane];
+    for (int j = 0; j <= H; ++j) cf[j] = kfwd[j * 64 + lane];
+  }
   double Q[NQ][2 * F];  // (re, im) of each field
   cplx gh[F];
 #pragma unroll
@@ -412,7 +416,18 @@ __device__ __forceinline__ void dct_fwd_pm(const Lane<N>& L, Load load, const do
     constexpr int m = decltype(m_c)::value;
     if constexpr (16 * m + kk < H) fmac_row<kk, 2 * F>(acc, Q[m], cf[16 * m + kk]);
   };
-  for_each_k([&](auto m_c) { for_16([&](auto kk_c) { term(kk_c, m_c); }); }, std::make_integer_sequence<int, NQ>{});
+  for_each_k(
+      [&](auto m_c) {
+        constexpr int m = decltype(m_c)::value;
+        if constexpr (CHUNK) {
+#pragma unroll
+          for (int kk = 0; kk < 16; ++kk)
+            if (16 * m + kk < H) cf[16 * m + kk] = kfwd[(16 * m + kk) * 64 + lane];
+        }
+        for_16([&](auto kk_c) { term(kk_c, m_c); });
+      },
+      std::make_integer_sequence<int, NQ>{});
+  if constexpr (CHUNK) cf[H] = kfwd[H * 64 + lane];
   const double ch = cf[H];
   const double sc = (L.n == 0) ? (1.0 / N) : (2.0 / N);
 #pragma unroll
@@ -433,7 +448,7 @@ __device__ __forceinline__ void dct_fwd_pm(const Lane<N>& L, Load load, const do
 // f_j = sum_n a_n cos(pi n j / N), folded with P_n = a_n + a_{N-n}, M_n = a_n - a_{N-n}
 // (n < N/2; even nodes need P, odd nodes M) and a_{N/2} in both; the node-N tail is
 // sum_n (-1)^n a_n.
-template <int N, int F>
+template <int N, int F, bool CHUNK>
 __device__ __forceinline__ void dct_inv_pm(const Lane<N>& L, const cplx* a, const cplx* at,
                                            const double* __restrict__ kinv, cplx* f, cplx* ft) {
   constexpr int H = N / 2;
@@ -441,9 +456,11 @@ __device__ __forceinline__ void dct_inv_pm(const Lane<N>& L, const cplx* a, cons
   constexpr int SH = (H & 1) ? 32 + (H >> 1) : (H >> 1);  // lane of a_{N/2}
   const int lane = L.l;
   const bool prow = L.l < 32;
-  double cf[H + 1];  // this lane's cosines, requested up front
+  double cf[H + 1];  // this lane's cosines, requested up front (or per group of 16, CHUNK)
+  if constexpr (!CHUNK) {
 #pragma unroll
-  for (int n = 0; n <= H; ++n) cf[n] = kinv[n * 64 + lane];
+    for (int n = 0; n <= H; ++n) cf[n] = kinv[n * 64 + lane];
+  }
   double Q[NQ][2 * F];  // (re, im) of each field
   cplx ah[F];
 #pragma unroll
@@ -472,7 +489,18 @@ __device__ __forceinline__ void dct_inv_pm(const Lane<N>& L, const cplx* a, cons
     constexpr int m = decltype(m_c)::value;
     if constexpr (16 * m + kk < H) fmac_row<kk, 2 * F>(acc, Q[m], cf[16 * m + kk]);
   };
-  for_each_k([&](auto m_c) { for_16([&](auto kk_c) { term(kk_c, m_c); }); }, std::make_integer_sequence<int, NQ>{});
+  for_each_k(
+      [&](auto m_c) {
+        constexpr int m = decltype(m_c)::value;
+        if constexpr (CHUNK) {
+#pragma unroll
+          for (int kk = 0; kk < 16; ++kk)
+            if (16 * m + kk < H) cf[16 * m + kk] = kinv[(16 * m + kk) * 64 + lane];
+        }
+        for_16([&](auto kk_c) { term(kk_c, m_c); });
+      },
+      std::make_integer_sequence<int, NQ>{});
+  if constexpr (CHUNK) cf[H] = kinv[H * 64 + lane];
   const double ch = cf[H];
 #pragma unroll
   for (int g = 0; g < F; ++g) {
@@ -498,7 +526,7 @@ constexpr int PART_SOLVE = 0, PART_RECON = 1;
 __device__ __forceinline__ double stage_end(int r) { return r == 0 ? 8.0 / 15.0 : (r == 1 ? 2.0 / 3.0 : 1.0); }
 
 // One block of CWAVES columns (block cb of the channel's columns).
-template <int N, int PART>
+template <int N, int PART, bool CHUNK>
 __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S, int cb) {
   constexpr int NY = N + 1;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -535,7 +563,7 @@ __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S
       return x;
     };
     cplx hc[3], hct[3];
-    dct_fwd_pm<N, 3>(L, loadH, A.kfwd, hc, hct);
+    dct_fwd_pm<N, 3, CHUNK>(L, loadH, A.kfwd, hc, hct);
     if (status0 & STATUS_BAD_ACTION) return;
     // state (v, omega_y; mean: X = U + i W) and the previous stage's explicit terms
     // (h_v, h_g; mean: h_u + i h_w)
@@ -766,7 +794,7 @@ __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S
     tau_hat = make_double2(A.nu * slope, 0.0);
   }
   cplx ph[6], pht[6];
-  dct_inv_pm<N, 6>(L, fld, fldt, A.kinv, ph, pht);
+  dct_inv_pm<N, 6, CHUNK>(L, fld, fldt, A.kinv, ph, pht);
   if (status0 & STATUS_BAD_ACTION) return;
   // write the six fields at the nodes (this lane: node n; lane 0 also node N) and the
   // Hermitian partner column
@@ -804,19 +832,21 @@ __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S
   }
 }
 
-// Many channels: channel blockIdx.x / bpc of the device array.
+// Many channels: channel blockIdx.x / bpc of the device array.  With many columns resident,
+// occupancy hides load latency: the reconstruction requests its cosines per group of 16
+// terms, which takes it from 172 to 143 registers (three waves per SIMD instead of two).
 template <int N, int PART>
-__global__ __launch_bounds__(64 * CWAVES, 2) void k_column_pm(const ColChan* __restrict__ chans, ColStage S,
+__global__ __launch_bounds__(64 * CWAVES, 3) void k_column_pm(const ColChan* __restrict__ chans, ColStage S,
                                                                int bpc) {
   const int ch = blockIdx.x / bpc;
-  column_block<N, PART>(chans[ch], S, blockIdx.x - ch * bpc);
+  column_block<N, PART, PART == PART_RECON>(chans[ch], S, blockIdx.x - ch * bpc);
 }
 
 // One channel, its arguments by value (preloaded with the kernel arguments instead of read
 // through a pointer); the same column code as the batched kernel.
 template <int N, int PART>
 __global__ __launch_bounds__(64 * CWAVES, 2) void k_column_pm1(ColChan A, ColStage S) {
-  column_block<N, PART>(A, S, blockIdx.x);
+  column_block<N, PART, false>(A, S, blockIdx.x);
 }
 
 template <int N>
