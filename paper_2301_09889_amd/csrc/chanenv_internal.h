@@ -81,6 +81,19 @@ struct DeviceState {
   const cplx *twz, *twx, *twnx, *twnz;
 };
 
+// Device memory pointers held in the per-channel argument structs.  In the device pass they are
+// typed as global-address-space pointers: read from memory, an untyped pointer would make the
+// compiler use flat memory instructions, whose completion shares the LDS counter (so every
+// LDS wait would also wait for them).  In the host pass they are plain pointers (same size and
+// layout); host code assigns them with a cast.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+#else
+template <class T>
+using gptr = T*;
+#endif
+
 // ---- per-channel launch arguments (device-resident arrays, one entry per channel) ----
 // A launch covers every channel of one grid shape (column and plane kernels) or of the whole
 // batch (the per-env-step kernels); a single env is a batch of one, so a channel runs the
@@ -95,15 +108,15 @@ struct ColChan {
   double lam0[3], ab[3], gb[3], zb[3];  // per RK stage: 1/(b nu dt), a/b, g/(b nu), z/(b nu)
   double nu, opp_alpha, ub2, px;
   size_t plane;                 // elements per field in F6 / H3 (ny nkx nz)
-  cplx *vS, *oS, *hist;
-  double *meanS, *meanH;
-  const cplx* H3;
-  cplx* F6;
-  const cplx *vw_old, *vw_new;
-  cplx *vw_opp, *tauw;
-  const double *kfwd, *kinv, *rc_pm, *intw_pm, *op_pm, *vt_pm, *up_pm, *minv, *inv_int_up, *alpha, *beta;
-  double* drag_acc;
-  int* status;
+  gptr<cplx> vS, oS, hist;
+  gptr<double> meanS, meanH;
+  gptr<const cplx> H3;
+  gptr<cplx> F6;
+  gptr<const cplx> vw_old, vw_new;
+  gptr<cplx> vw_opp, tauw;
+  gptr<const double> kfwd, kinv, rc_pm, intw_pm, op_pm, vt_pm, up_pm, minv, inv_int_up, alpha, beta;
+  gptr<double> drag_acc;
+  gptr<int> status;
 };
 
 // The launch-wide part: RK stage (-1: reconstruction from the stored state, which ends an env
@@ -116,13 +129,13 @@ struct ColStage {
 struct PlaneChan {
   int ny, nkx, nz;
   double scale;        // 1 / (M_x M_z)
-  const cplx* F6;
-  cplx* Z6;
-  cplx* W3;
-  cplx* H3;
-  const cplx* twz;     // exp(-2 pi i k / M_z)
-  const cplx* twx;     // exp(-2 pi i k / M_x)
-  const int* status;
+  gptr<const cplx> F6;
+  gptr<cplx> Z6;
+  gptr<cplx> W3;
+  gptr<cplx> H3;
+  gptr<const cplx> twz;   // exp(-2 pi i k / M_z)
+  gptr<const cplx> twx;   // exp(-2 pi i k / M_x)
+  gptr<const int> status;
 };
 
 // Per-env-step kernels (begin, action ingest, end, outputs) of one channel; rebuilt for
@@ -135,16 +148,16 @@ struct StepChan {
   int zero_vw;                  // external action and none given: v_w,new := 0
   int copy_vw;                  // external action: v_w,old := v_w,new at the end
   double clip;
-  const double* action;         // [nz][nx] device, or null
-  double* drag_out;             // or null
-  const cplx* out_src[OUT_SLOTS];  // spectra [p][q] (obs: the F6 plane at the sensing node)
-  double* out_dst[OUT_SLOTS];      // [nz][nx] device, or null
-  cplx *vw_new, *vw_old;
-  cplx* tmp2d;                  // [OUT_SLOTS][nz][nkx]
-  const cplx *twnx, *twnz;
-  double* drag_acc;
-  int* status;
-  int* status_out;              // batch-wide status array entry (read back once per call)
+  gptr<const double> action;         // [nz][nx] device, or null
+  gptr<double> drag_out;             // or null
+  gptr<const cplx> out_src[OUT_SLOTS];  // spectra [p][q] (obs: the F6 plane at the sensing node)
+  gptr<double> out_dst[OUT_SLOTS];      // [nz][nx] device, or null
+  gptr<cplx> vw_new, vw_old;
+  gptr<cplx> tmp2d;                  // [OUT_SLOTS][nz][nkx]
+  gptr<const cplx> twnx, twnz;
+  gptr<double> drag_acc;
+  gptr<int> status;
+  gptr<int> status_out;         // batch-wide status array entry (read back once per call)
 };
 
 // Kernel classes for the optional event timing.

@@ -222,30 +222,30 @@ ColChan make_col_chan(const chan_env* e) {
   c.ub2 = 2.0 * e->ph.ub;
   c.px = e->ph.px;
   c.plane = (size_t)d.ny * d.nkx * d.nz;
-  c.vS = s.vS;
-  c.oS = s.oS;
-  c.hist = s.hist;
-  c.meanS = s.meanS;
-  c.meanH = s.meanH;
-  c.H3 = s.H3;
-  c.F6 = s.F6;
-  c.vw_old = s.vw_old;
-  c.vw_new = s.vw_new;
-  c.vw_opp = s.vw_opp;
-  c.tauw = s.tauw;
-  c.kfwd = s.kfwd;
-  c.kinv = s.kinv;
-  c.rc_pm = s.rc_pm;
-  c.intw_pm = s.intw_pm;
-  c.op_pm = s.op_pm;
-  c.vt_pm = s.vt_pm;
-  c.up_pm = s.up_pm;
-  c.minv = s.minv;
-  c.inv_int_up = s.inv_int_up;
-  c.alpha = s.alpha;
-  c.beta = s.beta;
-  c.drag_acc = s.drag_acc;
-  c.status = s.status;
+  c.vS = (decltype(c.vS))(s.vS);
+  c.oS = (decltype(c.oS))(s.oS);
+  c.hist = (decltype(c.hist))(s.hist);
+  c.meanS = (decltype(c.meanS))(s.meanS);
+  c.meanH = (decltype(c.meanH))(s.meanH);
+  c.H3 = (decltype(c.H3))(s.H3);
+  c.F6 = (decltype(c.F6))(s.F6);
+  c.vw_old = (decltype(c.vw_old))(s.vw_old);
+  c.vw_new = (decltype(c.vw_new))(s.vw_new);
+  c.vw_opp = (decltype(c.vw_opp))(s.vw_opp);
+  c.tauw = (decltype(c.tauw))(s.tauw);
+  c.kfwd = (decltype(c.kfwd))(s.kfwd);
+  c.kinv = (decltype(c.kinv))(s.kinv);
+  c.rc_pm = (decltype(c.rc_pm))(s.rc_pm);
+  c.intw_pm = (decltype(c.intw_pm))(s.intw_pm);
+  c.op_pm = (decltype(c.op_pm))(s.op_pm);
+  c.vt_pm = (decltype(c.vt_pm))(s.vt_pm);
+  c.up_pm = (decltype(c.up_pm))(s.up_pm);
+  c.minv = (decltype(c.minv))(s.minv);
+  c.inv_int_up = (decltype(c.inv_int_up))(s.inv_int_up);
+  c.alpha = (decltype(c.alpha))(s.alpha);
+  c.beta = (decltype(c.beta))(s.beta);
+  c.drag_acc = (decltype(c.drag_acc))(s.drag_acc);
+  c.status = (decltype(c.status))(s.status);
   return c;
 }
 
@@ -257,13 +257,13 @@ PlaneChan make_plane_chan(const chan_env* e) {
   c.nkx = d.nkx;
   c.nz = d.nz;
   c.scale = 1.0 / ((double)d.mx * (double)d.mz);
-  c.F6 = e->s.F6;
-  c.Z6 = e->s.Z6;
-  c.W3 = e->s.W3;
-  c.H3 = e->s.H3;
-  c.twz = e->s.twz;
-  c.twx = e->s.twx;
-  c.status = e->s.status;
+  c.F6 = (decltype(c.F6))(e->s.F6);
+  c.Z6 = (decltype(c.Z6))(e->s.Z6);
+  c.W3 = (decltype(c.W3))(e->s.W3);
+  c.H3 = (decltype(c.H3))(e->s.H3);
+  c.twz = (decltype(c.twz))(e->s.twz);
+  c.twx = (decltype(c.twx))(e->s.twx);
+  c.status = (decltype(c.status))(e->s.status);
   return c;
 }
 
@@ -299,30 +299,30 @@ StepChan make_step_chan(const chan_batch* b, int i, int k, const double* action,
   c.zero_vw = (ext && action == nullptr) ? 1 : 0;
   c.copy_vw = ext ? 1 : 0;
   c.clip = e->opts.clip;
-  c.action = ext ? action : nullptr;
-  c.drag_out = drag;
+  c.action = (decltype(c.action))(ext ? action : nullptr);
+  c.drag_out = (decltype(c.drag_out))(drag);
   const size_t plane = (size_t)d.ny * d.nkx * d.nz;
   if (obs) {
     int slot = 0;
     for (int f = 0; f < 3; ++f) {
       if (!(e->opts.obs_mask & (1u << f))) continue;
-      c.out_src[f] = e->s.F6 + (size_t)f * plane + (size_t)e->js * d.nkx * d.nz;
-      c.out_dst[f] = obs + (size_t)slot * d.nz * d.nx;
+      c.out_src[f] = (gptr<const cplx>)(e->s.F6 + (size_t)f * plane + (size_t)e->js * d.nkx * d.nz);
+      c.out_dst[f] = (gptr<double>)(obs + (size_t)slot * d.nz * d.nx);
       ++slot;
     }
   }
   if (tau_w) {
-    c.out_src[3] = e->s.tauw;
-    c.out_dst[3] = tau_w;
+    c.out_src[3] = (gptr<const cplx>)(e->s.tauw);
+    c.out_dst[3] = (gptr<double>)(tau_w);
   }
-  c.vw_new = e->s.vw_new;
-  c.vw_old = e->s.vw_old;
-  c.tmp2d = e->s.tmp2d;
-  c.twnx = e->s.twnx;
-  c.twnz = e->s.twnz;
-  c.drag_acc = e->s.drag_acc;
-  c.status = e->s.status;
-  c.status_out = b->d_status + k;
+  c.vw_new = (decltype(c.vw_new))(e->s.vw_new);
+  c.vw_old = (decltype(c.vw_old))(e->s.vw_old);
+  c.tmp2d = (decltype(c.tmp2d))(e->s.tmp2d);
+  c.twnx = (decltype(c.twnx))(e->s.twnx);
+  c.twnz = (decltype(c.twnz))(e->s.twnz);
+  c.drag_acc = (decltype(c.drag_acc))(e->s.drag_acc);
+  c.status = (decltype(c.status))(e->s.status);
+  c.status_out = (decltype(c.status_out))(b->d_status + k);
   return c;
 }
 

@@ -826,7 +826,7 @@ int launch_column_pass(const Dims& d, DeviceState& s, const PhysParams& ph, int 
 // Start of an env step: clear the status word and the drag accumulator; v_w,new := 0 when
 // an external-action channel gets no action.
 __global__ void k_begin_step(const StepChan* __restrict__ chans) {
-  const StepChan& C = chans[blockIdx.y];
+  const StepChan C = chans[blockIdx.y];
   const int t = threadIdx.x;
   if (t == 0) {
     C.status[0] = C.skip ? STATUS_BAD_ACTION : 0;
@@ -846,7 +846,7 @@ int launch_begin_step(const StepChan* d_step, int nch, hipStream_t st, KernelTim
 // Rows of the action: finiteness check, clip, forward FFT along x; keeps p < nx/2.
 __global__ void k_ingest_rows(const StepChan* __restrict__ chans) {
   extern __shared__ double dyn_lds[];
-  const StepChan& C = chans[blockIdx.y];
+  const StepChan C = chans[blockIdx.y];
   const int k = blockIdx.x;
   if (C.action == nullptr || C.skip || k >= C.nz) return;
   const int nx = C.nx, nkx = C.nkx;
@@ -870,7 +870,7 @@ __global__ void k_ingest_rows(const StepChan* __restrict__ chans) {
 // Columns: forward FFT along z, 1/(nx nz), Nyquist and mean removed, Hermitian fix.
 __global__ void k_ingest_cols(const StepChan* __restrict__ chans) {
   extern __shared__ double dyn_lds[];
-  const StepChan& C = chans[blockIdx.y];
+  const StepChan C = chans[blockIdx.y];
   const int p = blockIdx.x;
   if (C.action == nullptr || p >= C.nkx) return;
   if (*C.status & STATUS_BAD_ACTION) return;
@@ -906,7 +906,7 @@ int launch_ingest(const StepChan* d_step, int nch, int max_nx, int max_nz, int m
 // are [p][q].  Columns: inverse FFT along z.
 __global__ void k_out_cols(const StepChan* __restrict__ chans) {
   extern __shared__ double dyn_lds[];
-  const StepChan& C = chans[blockIdx.y];
+  const StepChan C = chans[blockIdx.y];
   const int p = blockIdx.x, f = blockIdx.z;
   const cplx* src = C.out_src[f];
   if (src == nullptr || C.out_dst[f] == nullptr || C.skip || p >= C.nkx) return;
@@ -924,7 +924,7 @@ __global__ void k_out_cols(const StepChan* __restrict__ chans) {
 // Rows: Hermitian extension along x (real part of p = 0), inverse FFT, real part out.
 __global__ void k_out_rows(const StepChan* __restrict__ chans) {
   extern __shared__ double dyn_lds[];
-  const StepChan& C = chans[blockIdx.y];
+  const StepChan C = chans[blockIdx.y];
   const int k = blockIdx.x, f = blockIdx.z;
   double* out = C.out_dst[f];
   if (C.out_src[f] == nullptr || out == nullptr || C.skip || k >= C.nz) return;
@@ -960,7 +960,7 @@ int launch_outputs(const StepChan* d_step, int nch, int max_nx, int max_nz, int 
 // End of an env step: drag = accumulated / n, v_w,old := v_w,new (unless the action was
 // rejected), and the channel's status into the batch-wide status array.
 __global__ void k_finish_step(const StepChan* __restrict__ chans) {
-  const StepChan& C = chans[blockIdx.y];
+  const StepChan C = chans[blockIdx.y];
   const int t = threadIdx.x;
   const int status = *C.status;
   if (t == 0) C.status_out[0] = status;

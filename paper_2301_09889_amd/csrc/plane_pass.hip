@@ -49,7 +49,7 @@ __global__ __launch_bounds__(1024) void k_zinv2(const PlaneChan* __restrict__ ch
   extern __shared__ double dyn_lds[];
   cplx* tw = reinterpret_cast<cplx*>(dyn_lds);
   cplx* Y = tw + L;
-  const PlaneChan& A = chans[blockIdx.z / ny];
+  const PlaneChan A = chans[blockIdx.z / ny];
   // a rejected action leaves every buffer untouched (tested at the stores, so that the
   // status load overlaps the data loads)
   const bool skip = (*A.status & STATUS_BAD_ACTION) != 0;
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(1024) void k_zfwd2(const PlaneChan* __restrict__ ch
   cplx* tw = reinterpret_cast<cplx*>(dyn_lds);
   cplx* X0 = tw + L;       // the p = 0 pencil, for the Hermitian fix
   cplx* Y = X0 + L;
-  const PlaneChan& A = chans[blockIdx.z / ny];
+  const PlaneChan A = chans[blockIdx.z / ny];
   const bool skip = (*A.status & STATUS_BAD_ACTION) != 0;  // tested at the stores
   const int p0 = blockIdx.x * PB, g = blockIdx.y, j = blockIdx.z % ny;
   const int np = min(PB, A.nkx - p0);
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(1024) void k_xrow2(const PlaneChan* __restrict__ ch
   extern __shared__ double dyn_lds[];
   cplx* tw = reinterpret_cast<cplx*>(dyn_lds);
   cplx* S = tw + L;         // [field][pair][LP]
-  const PlaneChan& A = chans[blockIdx.y / nyc];
+  const PlaneChan A = chans[blockIdx.y / nyc];
   const bool skip = (*A.status & STATUS_BAD_ACTION) != 0;  // tested at the stores
   const int pair0 = blockIdx.x * P, j = blockIdx.y % nyc;
   const int nkx = A.nkx, ny = A.ny;
