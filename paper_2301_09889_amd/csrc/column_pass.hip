@@ -83,20 +83,29 @@ __device__ __forceinline__ unsigned hi32(double x) {
 __device__ __forceinline__ double join32(unsigned l, unsigned h) {
   return __longlong_as_double((long long)(((unsigned long long)h << 32) | l));
 }
-// The value at the same position of the partner row (rows 0 <-> 1, 2 <-> 3).
-__device__ __forceinline__ double swap_rows(double x, bool even_row) {
-  const auto a = __builtin_amdgcn_permlane16_swap(lo32(x), lo32(x), false, false);
-  const auto b = __builtin_amdgcn_permlane16_swap(hi32(x), hi32(x), false, false);
-  return even_row ? join32(a[1], b[1]) : join32(a[0], b[0]);
+// Both results of v_permlane16_swap on (x, y): a holds rows (x0, y0, x2, y2), b holds rows
+// (x1, y1, x3, y3).  Using both (instead of selecting one per row) costs no VALU merge.
+struct Pair {
+  double a, b;
+};
+__device__ __forceinline__ Pair row_swap(double x, double y) {
+  const auto l = __builtin_amdgcn_permlane16_swap(lo32(x), lo32(y), false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap(hi32(x), hi32(y), false, false);
+  return {join32(l[0], h[0]), join32(l[1], h[1])};
 }
-__device__ __forceinline__ cplx swap_rows(cplx v, bool even_row) {
-  return make_double2(swap_rows(v.x, even_row), swap_rows(v.y, even_row));
+// Both results of v_permlane32_swap on (x, y): a holds halves (x_lo, y_lo), b (x_hi, y_hi).
+__device__ __forceinline__ Pair half_swap(double x, double y) {
+  const auto l = __builtin_amdgcn_permlane32_swap(lo32(x), lo32(y), false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap(hi32(x), hi32(y), false, false);
+  return {join32(l[0], h[0]), join32(l[1], h[1])};
 }
-// The value of lane l ^ 32.
-__device__ __forceinline__ double swap_halves(double x, bool low) {
-  const auto a = __builtin_amdgcn_permlane32_swap(lo32(x), lo32(x), false, false);
-  const auto b = __builtin_amdgcn_permlane32_swap(hi32(x), hi32(x), false, false);
-  return low ? join32(a[1], b[1]) : join32(a[0], b[0]);
+// Rows 0 and 2 receive x's rows 1 and 3; rows 1 and 3 read 0.
+__device__ __forceinline__ double from_odd_rows(double x) { return row_swap(x, 0.0).b; }
+__device__ __forceinline__ cplx from_odd_rows(cplx v) { return make_double2(from_odd_rows(v.x), from_odd_rows(v.y)); }
+// Rows 1 and 3 receive x's rows 0 and 2; rows 0 and 2 read 0.
+__device__ __forceinline__ double from_even_rows(double x) { return row_swap(0.0, x).a; }
+__device__ __forceinline__ cplx from_even_rows(cplx v) {
+  return make_double2(from_even_rows(v.x), from_even_rows(v.y));
 }
 // Lanes l < 32 receive lo's lane l + 32, lanes l >= 32 receive hi's lane l - 32.
 __device__ __forceinline__ double cross_halves(double lo, double hi, bool low) {
@@ -120,20 +129,17 @@ __device__ __forceinline__ double row_sum(double x) {
   x += dmov<DPP_ROW_MIRROR>(x);
   return x;
 }
-__device__ __forceinline__ double half_sum(double x, bool even_row) {
-  x = row_sum(x);
-  return x + swap_rows(x, even_row);
+__device__ __forceinline__ double half_sum(double x) {
+  const Pair r = row_swap(row_sum(x), row_sum(x));
+  return r.a + r.b;  // (row 0 + row 1) or (row 2 + row 3), in that order on every lane
 }
-__device__ __forceinline__ cplx half_sum(cplx v, bool even_row) {
-  return make_double2(half_sum(v.x, even_row), half_sum(v.y, even_row));
+__device__ __forceinline__ cplx half_sum(cplx v) { return make_double2(half_sum(v.x), half_sum(v.y)); }
+__device__ __forceinline__ double lane_sum(double x) {
+  const double h = half_sum(x);
+  const Pair r = half_swap(h, h);
+  return r.a + r.b;  // low half + high half on every lane
 }
-__device__ __forceinline__ double lane_sum(double x, bool even_row, bool low) {
-  x = half_sum(x, even_row);
-  return x + swap_halves(x, low);
-}
-__device__ __forceinline__ cplx lane_sum(cplx v, bool even_row, bool low) {
-  return make_double2(lane_sum(v.x, even_row, low), lane_sum(v.y, even_row, low));
-}
+__device__ __forceinline__ cplx lane_sum(cplx v) { return make_double2(lane_sum(v.x), lane_sum(v.y)); }
 
 // Parity-major bookkeeping of one lane.
 template <int N>
@@ -156,12 +162,11 @@ struct Lane {
 // Suffix sum over this lane's half: lane i receives sum_{i' >= i} x_{i'} (lanes beyond the
 // valid range hold zeros).
 template <int H>
-__device__ __forceinline__ cplx half_suffix(const cplx x0, bool even_row) {
+__device__ __forceinline__ cplx half_suffix(const cplx x0) {
   cplx x = x0;
   for_pow2<(H < 16 ? H : 16)>([&](auto dc) { x = cadd(x, cmov<DPP_ROW_SHL + decltype(dc)::value>(x)); });
   if constexpr (H > 16) {  // add the second row's total to the first row
-    const cplx t = swap_rows(cmov<DPP_ROW_BCAST + 0>(x), even_row);
-    if (even_row) x = cadd(x, t);
+    x = cadd(x, from_odd_rows(cmov<DPP_ROW_BCAST + 0>(x)));  // odd rows add 0
   }
   return x;
 }
@@ -171,7 +176,7 @@ __device__ __forceinline__ cplx half_suffix(const cplx x0, bool even_row) {
 template <int N>
 __device__ __forceinline__ cplx cheb_d(const Lane<N>& L, cplx x, cplx xt) {
   constexpr int H = N / 2;
-  const cplx S = half_suffix<H>(L.ok ? cscale(x, (double)L.n) : cz(), L.even_row);
+  const cplx S = half_suffix<H>(L.ok ? cscale(x, (double)L.n) : cz());
   // even n = 2l: odd p >= 2l + 1  -> S at lane 32 + l
   // odd n = 2i + 1: even p >= 2i + 2 -> S at lane i + 1, plus the tail p = N
   const cplx Sn = cmov<DPP_WAVE_SHL1>(S);
@@ -283,8 +288,8 @@ __device__ __forceinline__ void tau_solve_pm(const Lane<N>& L, const cplx* R, co
   if constexpr (H > 16) {  // first row: e_i = A_i + B_i e_16
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
-      const cplx e16 = swap_rows(cmov<DPP_ROW_BCAST + 0>(A[k]), L.even_row);
-      if (L.even_row) A[k] = caxpy(A[k], B, e16);
+      const cplx e16 = from_odd_rows(cmov<DPP_ROW_BCAST + 0>(A[k]));  // 0 on the second row
+      A[k] = caxpy(A[k], B, e16);
     }
   }
   // top-down: E_i = e_i + f_i E_{i-1}, E_0 = 0
@@ -304,8 +309,8 @@ __device__ __forceinline__ void tau_solve_pm(const Lane<N>& L, const cplx* R, co
   if constexpr (H > 16) {  // second row: E_i = A_i + C_i E_15
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
-      const cplx e15 = swap_rows(cmov<DPP_ROW_BCAST + 15>(A[k]), L.even_row);
-      if (!L.even_row) A[k] = caxpy(A[k], C, e15);
+      const cplx e15 = from_even_rows(cmov<DPP_ROW_BCAST + 15>(A[k]));  // 0 on the first row
+      A[k] = caxpy(A[k], C, e15);
     }
   }
 #pragma unroll
@@ -313,7 +318,7 @@ __device__ __forceinline__ void tau_solve_pm(const Lane<N>& L, const cplx* R, co
     // even tail E_{N/2} = e_{N/2} + f_{N/2} E_{N/2-1}
     const cplx Elast = readlane_c(A[k], H - 1);
     const cplx Et = caxpy(et[k], frt, Elast);
-    cplx sum = half_sum(A[k], L.even_row);
+    cplx sum = half_sum(A[k]);
     const cplx sum_even = readlane_c(sum, 0);
     if (!L.odd) sum = cadd(sum, Et);
     const cplx g = L.odd ? cscale(csub(gt[k], gb[k]), 0.5) : cscale(cadd(gt[k], gb[k]), 0.5);
@@ -506,7 +511,7 @@ __device__ __forceinline__ void dct_inv_pm(const Lane<N>& L, const cplx* a, cons
   for (int g = 0; g < F; ++g) {
     f[g] = L.ok ? caxpy(make_double2(acc[2 * g], acc[2 * g + 1]), ch, ah[g]) : cz();
     const cplx part = L.ok ? (L.odd ? cscale(a[g], -1.0) : a[g]) : cz();
-    ft[g] = cadd(lane_sum(part, L.even_row, L.low), at[g]);
+    ft[g] = cadd(lane_sum(part), at[g]);
   }
 }
 
@@ -514,7 +519,7 @@ __device__ __forceinline__ void dct_inv_pm(const Lane<N>& L, const cplx* a, cons
 template <int N>
 __device__ __forceinline__ cplx coef_sum(const Lane<N>& L, cplx x, cplx xt, double w_lane, double w_tail) {
   cplx part = L.ok ? cscale(x, w_lane) : cz();
-  return caxpy(lane_sum(part, L.even_row, L.low), w_tail, xt);
+  return caxpy(lane_sum(part), w_tail, xt);
 }
 
 // The two parts of the column pass run as separate launches: the implicit solve of a stage,
@@ -714,7 +719,7 @@ __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S
       const cplx z1[1] = {cz()};
       cplx Xs[1], Xst[1];
       tau_solve_pm<N, 1>(L, R, Rt, rs, z1, z1, Xs, Xst);
-      double flux = lane_sum(iw * Xs[0].x, L.even_row, L.low) + iwt * Xst[0].x;
+      double flux = lane_sum(iw * Xs[0].x) + iwt * Xst[0].x;
       const double P_r = (A.forcing == 0) ? (A.ub2 - flux) * iiu : A.px;
       const double U = fma(P_r, upl, Xs[0].x);
       const double Ut = fma(P_r, upt, Xst[0].x);
@@ -730,7 +735,7 @@ __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S
         A.meanS[NY + N] = vt.y;
       }
       const double n2 = dn * dn;
-      const double slope = lane_sum(L.ok ? (L.odd ? n2 : -n2) * v.x : 0.0, L.even_row, L.low) - dN * dN * vt.x;
+      const double slope = lane_sum(L.ok ? (L.odd ? n2 : -n2) * v.x : 0.0) - dN * dN * vt.x;
       if (r == 2 && lane == 0) A.drag_acc[0] += A.nu * slope;  // drag: end of every time step
       const bool ok = isfinite(v.x) && isfinite(v.y) && isfinite(vt.x) && isfinite(vt.y);
       if (r == 2 && __any(!ok) && lane == 0) atomicOr(A.status, STATUS_NONFINITE);
@@ -790,7 +795,7 @@ __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S
     fld[5] = make_double2(-dX.x, 0.0);
     fldt[5] = cz();
     const double n2 = dn * dn;
-    const double slope = lane_sum(L.ok ? (L.odd ? n2 : -n2) * v.x : 0.0, L.even_row, L.low) - dN * dN * vt.x;
+    const double slope = lane_sum(L.ok ? (L.odd ? n2 : -n2) * v.x : 0.0) - dN * dN * vt.x;
     tau_hat = make_double2(A.nu * slope, 0.0);
   }
   cplx ph[6], pht[6];
