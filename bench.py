@@ -75,12 +75,15 @@ def algorithmic_bytes_per_launch(kclass, g):
     previous stage's h_v, h_g (2); it writes v, omega_y (2) and h_v, h_g (2, first
     two stages): 9 2/3 passes per launch on average over the three stages.  The
     column reconstruction reads v, omega_y (2) and writes the six node fields for
-    the plane pass (6).  Precomputed operator tables are not counted."""
+    the plane pass (6); run in the same launch as the solve it reads nothing more
+    (15 2/3 passes for both).  Precomputed operator tables are not counted."""
     K = resolved_points(g)
     if kclass == "column_pass":
         return (3 + 2 + 2.0 / 3.0 * 2 + 2 + 2.0 / 3.0 * 2) * 16.0 * K
     if kclass == "column_reconstruct":
         return (2 + 6) * 16.0 * K
+    if kclass == "column_solve_reconstruct":     # both parts in one launch: no state reload
+        return (3 + 2 + 2.0 / 3.0 * 2 + 2 + 2.0 / 3.0 * 2 + 6) * 16.0 * K
     nkx, ny, mz = g["nx"] // 2, g["ny"], 3 * g["nz"] // 2
     padded = 16.0 * ny * mz * nkx          # one field on the z-padded intermediate
     if kclass == "z_inverse_fft":

@@ -177,10 +177,12 @@ void chan_env_destroy(struct chan_env* env);
  * kernel classes, the number of launches and the summed kernel time in ms since
  * timing was enabled; it returns the number of classes (>= 0) or a negative
  * code.  Classes (chan_kernel_class_name): 0 column_pass (the implicit solve of a
- * stage), 1 z_inverse_fft, 2 x_rows_fft_product, 3 z_forward_fft, 4 action_ingest,
+ * stage alone), 1 z_inverse_fft, 2 x_rows_fft_product, 3 z_forward_fft, 4 action_ingest,
  * 5 outputs, 6 bookkeeping, 7 column_reconstruct (velocity/vorticity reconstruction
  * and inverse Chebyshev transform after each stage, and from the stored state at
- * the end of every env step).  Errors: CHAN_EINVAL, CHAN_EDEVICE. */
+ * the end of every env step), 8 column_solve_reconstruct (both parts in one launch:
+ * every stage but the last of an env step, whose solve counts under 0).  Errors:
+ * CHAN_EINVAL, CHAN_EDEVICE. */
 int chan_env_set_timing(struct chan_env* env, int32_t enable);
 int chan_env_timing_read(struct chan_env* env, int32_t nclass, int64_t* launches, double* ms);
 const char* chan_kernel_class_name(int32_t cls);

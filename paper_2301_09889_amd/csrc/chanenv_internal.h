@@ -163,7 +163,7 @@ struct StepChan {
 // Kernel classes for the optional event timing.
 enum KernelClass : int {
   KC_COLUMN = 0, KC_ZINV = 1, KC_XROW = 2, KC_ZFWD = 3, KC_INGEST = 4, KC_OUTPUT = 5, KC_BOOK = 6,
-  KC_RECON = 7, KC_COUNT = 8
+  KC_RECON = 7, KC_FUSED = 8, KC_COUNT = 9
 };
 
 // Brackets kernel launches with HIP events when enabled (instrumentation only).

@@ -522,10 +522,11 @@ __device__ __forceinline__ cplx coef_sum(const Lane<N>& L, cplx x, cplx xt, doub
   return caxpy(lane_sum(part), w_tail, xt);
 }
 
-// The two parts of the column pass run as separate launches: the implicit solve of a stage,
-// and the reconstruction with the inverse DCT that feeds the next plane pass (which also
-// follows the last stage of an env step, from the stored state).
-constexpr int PART_SOLVE = 0, PART_RECON = 1;
+// Parts of the column pass: the implicit solve of a stage, the reconstruction with the
+// inverse DCT that feeds the next plane pass (from the stored state: after the last stage of
+// an env step and for set_state), or both in one launch with the solved state kept in
+// registers (every other stage).
+constexpr int PART_SOLVE = 0, PART_RECON = 1, PART_BOTH = 2;
 
 // Time fraction at the end of RK stage r (c_end of the stage).
 __device__ __forceinline__ double stage_end(int r) { return r == 0 ? 8.0 / 15.0 : (r == 1 ? 2.0 / 3.0 : 1.0); }
@@ -556,7 +557,7 @@ __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S
 
   cplx v, om, vt, omt;  // state after this call (mean: v = U + i W, om = 0)
 
-  if constexpr (PART == PART_SOLVE) {
+  if constexpr (PART != PART_RECON) {
     const int r = S.stage;
     const double lam0 = A.lam0[r], ab = A.ab[r], gb = A.gb[r], zb = A.zb[r];
     // H1, H2, H3 at node j of this column; the mean flow sees the real parts of H1, H3 only
@@ -568,7 +569,7 @@ __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S
       return x;
     };
     cplx hc[3], hct[3];
-    dct_fwd_pm<N, 3, CHUNK>(L, loadH, A.kfwd, hc, hct);
+    dct_fwd_pm<N, 3, false>(L, loadH, A.kfwd, hc, hct);
     if (status0 & STATUS_BAD_ACTION) return;
     // state (v, omega_y; mean: X = U + i W) and the previous stage's explicit terms
     // (h_v, h_g; mean: h_u + i h_w)
@@ -844,7 +845,7 @@ template <int N, int PART>
 __global__ __launch_bounds__(64 * CWAVES, 3) void k_column_pm(const ColChan* __restrict__ chans, ColStage S,
                                                                int bpc) {
   const int ch = blockIdx.x / bpc;
-  column_block<N, PART, PART == PART_RECON>(chans[ch], S, blockIdx.x - ch * bpc);
+  column_block<N, PART, PART != PART_SOLVE>(chans[ch], S, blockIdx.x - ch * bpc);
 }
 
 // One channel, its arguments by value (preloaded with the kernel arguments instead of read
@@ -860,6 +861,16 @@ int launch_pm(const ColChan* d_col, const ColChan* h_col, int nch, int ncol, con
   const int bpc = (ncol + CWAVES - 1) / CWAVES;
   const dim3 grid(bpc * nch), block(64 * CWAVES);
   const bool one = nch == 1 && h_col != nullptr;
+  // Both parts in one launch: the solved state stays in registers for the reconstruction,
+  // which saves a kernel boundary and the state's reload.  (Every stage of every batch takes
+  // this path, so a channel's arithmetic does not depend on the batch it is in.)
+  if (solve && recon) {
+    if (one)
+      timed_launch(tm, KC_FUSED, k_column_pm1<N, PART_BOTH>, grid, block, 0, st, h_col[0], S);
+    else
+      timed_launch(tm, KC_FUSED, k_column_pm<N, PART_BOTH>, grid, block, 0, st, d_col, S, bpc);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+  }
   if (solve) {
     if (one)
       timed_launch(tm, KC_COLUMN, k_column_pm1<N, PART_SOLVE>, grid, block, 0, st, h_col[0], S);

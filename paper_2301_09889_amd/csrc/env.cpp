@@ -1033,7 +1033,7 @@ int chan_batch_timing_read(chan_batch* b, int32_t nclass, int64_t* launches, dou
 
 static const char* const kClassNames[KC_COUNT] = {
     "column_pass", "z_inverse_fft", "x_rows_fft_product", "z_forward_fft", "action_ingest", "outputs",
-    "bookkeeping", "column_reconstruct"};
+    "bookkeeping", "column_reconstruct", "column_solve_reconstruct"};
 
 const char* chan_kernel_class_name(int32_t cls) {
   if (cls < 0 || cls >= KC_COUNT) return "";

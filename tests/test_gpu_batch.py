@@ -191,3 +191,24 @@ def test_subsets_match_alone_bitwise():
     batch.close()
     for e in alone + mixed:
         e.close()
+
+
+def test_large_batch_matches_alone_bitwise():
+    """17 channels of 32x65x32 (8432 columns per column launch) stepped as one batch end
+    bitwise where each ends alone."""
+    import paper_2301_09889_amd.binding as b
+    specs = [(32, 65, 32, 180.0, ch.CTRL_EXTERNAL, ch.RAMP, ch.IC_REICHARDT, 20 + i) for i in range(17)]
+    alone, mixed = make_envs(specs), make_envs(specs)
+    batch = b.ChanBatch(mixed)
+    for k in range(2):
+        acts = actions_for(specs, k)
+        for e, a in zip(alone, acts):
+            e.step(a, 2)
+        assert batch.step(acts, 2) == [0] * len(specs)
+    for i, (ea, em) in enumerate(zip(alone, mixed)):
+        assert np.array_equal(ea.get_state(), em.get_state()), i
+        oa, om = outputs(ea), outputs(em)
+        assert np.array_equal(oa[0], om[0]) and np.array_equal(oa[1], om[1]) and oa[2] == om[2], i
+    batch.close()
+    for e in alone + mixed:
+        e.close()
