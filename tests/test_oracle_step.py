@@ -313,3 +313,22 @@ def test_flow_rate_is_constant_and_state_stays_real():
     for q in range(1, S.nz // 2):
         assert np.all(st.v[S.nz - q, 0] == np.conj(st.v[q, 0]))
     assert np.all(st.om[0, 0] == 0) and np.all(st.v[S.nz // 2] == 0)
+
+
+def test_turbulent_drag_golden_is_consistent():
+    """The stored oracle drag statistics (tests/golden/make_turbulent_drag.py) agree with
+    themselves: window means are the means of their blocks, the ensemble mean is the mean of
+    the seeds', and the drag of the controlled turbulent flow lies between the laminar value
+    (3 U_b / Re_tau) and the uncontrolled turbulent level (about 1 in wall units)."""
+    g = golden("turbulent_drag_minimal.json")
+    a, b = g["window"]
+    blk = g["block"]
+    assert g["n_env_steps"] % blk == 0 and a % blk == 0 and b % blk == 0
+    laminar = 3.0 * 15.66 / 180.0
+    for s in g["seeds"]:
+        bm = np.asarray(g["block_means"][str(s)])
+        assert bm.size == g["n_env_steps"] // blk
+        assert abs(bm[a // blk:b // blk].mean() - g["window_mean"][str(s)]) <= 1e-12
+        assert laminar < g["window_mean"][str(s)] < 1.2
+    ens = np.mean([g["window_mean"][str(s)] for s in g["seeds"]])
+    assert abs(ens - g["ensemble_window_mean"]) <= 1e-12
