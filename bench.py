@@ -37,14 +37,15 @@ MINIMAL = dict(nx=16, ny=65, nz=16, lx=2.67, lz=0.8, re_tau=180.0, dt_plus=0.05,
 # "bench.py --steps 3 --warmup 1 --no-cpu-baseline --copy-probe" (FETCH_SIZE, then WRITE_SIZE,
 # KiB per dispatch; profiles/hbm_traffic_larger_channel.md).  FETCH_SIZE is scaled by 2.0 and
 # WRITE_SIZE by 1.0: what the two counters read for the 256 MiB device copy of --copy-probe
-# (131084 and 262144 KiB).  Each figure holds for the kernel source with the listed SHA-256
+# (131089 and 262144 KiB).  Each figure holds for the kernel source with the listed SHA-256
 # and is reported as null for any other source.
 TRAFFIC = {
-    "x_rows_fft_product": (2.8961e7, "plane_pass.hip", "6fdb128687b448a64b428d057242634abdcfe1413225da7354529975f39ccab6"),
-    "z_inverse_fft": (3.2054e7, "plane_pass.hip", "6fdb128687b448a64b428d057242634abdcfe1413225da7354529975f39ccab6"),
-    "z_forward_fft": (1.6092e7, "plane_pass.hip", "6fdb128687b448a64b428d057242634abdcfe1413225da7354529975f39ccab6"),
-    "column_pass": (3.7410e7, "column_pass.hip", "98d26b42ae1e6bd0dbb60aa652957fe16cb5e522e9e0d6f94ec5114583d5a5b2"),
-    "column_reconstruct": (1.8384e7, "column_pass.hip", "98d26b42ae1e6bd0dbb60aa652957fe16cb5e522e9e0d6f94ec5114583d5a5b2"),
+    "column_solve_reconstruct": (5.1233e7, "column_pass.hip", "5f931bec72dfe606a93edc43c3646f2a17356bd5dbfbeb05244e6d7db4c8cfb2"),
+    "x_rows_fft_product": (2.8973e7, "plane_pass.hip", "441bf8230c2d8038429ffa3aef7848cbd1370d27e40ec0b96bef6434f6d1b0ae"),
+    "z_inverse_fft": (3.2055e7, "plane_pass.hip", "441bf8230c2d8038429ffa3aef7848cbd1370d27e40ec0b96bef6434f6d1b0ae"),
+    "z_forward_fft": (1.6094e7, "plane_pass.hip", "441bf8230c2d8038429ffa3aef7848cbd1370d27e40ec0b96bef6434f6d1b0ae"),
+    "column_pass": (3.5880e7, "column_pass.hip", "5f931bec72dfe606a93edc43c3646f2a17356bd5dbfbeb05244e6d7db4c8cfb2"),
+    "column_reconstruct": (1.7980e7, "column_pass.hip", "5f931bec72dfe606a93edc43c3646f2a17356bd5dbfbeb05244e6d7db4c8cfb2"),
 }
 
 
