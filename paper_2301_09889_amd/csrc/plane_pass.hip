@@ -166,6 +166,7 @@ template <int L>
 __global__ __launch_bounds__(1024) void k_xrow2(const PlaneChan* __restrict__ chans, int nyc, int P) {
   constexpr int FA = FftPlan<L>::A, FB = FftPlan<L>::B;
   constexpr int LP = L + 1;
+  static_assert(FA >= FB, "pass 1 has at most one task per thread");
   extern __shared__ double dyn_lds[];
   cplx* tw = reinterpret_cast<cplx*>(dyn_lds);
   cplx* S = tw + L;         // [field][pair][LP]
@@ -176,37 +177,47 @@ __global__ __launch_bounds__(1024) void k_xrow2(const PlaneChan* __restrict__ ch
   const int mz = 3 * A.nz / 2;
   const int tid = threadIdx.x, nthr = blockDim.x;
   for (int t = tid; t < L; t += nthr) tw[t] = A.twx[t];
-  __syncthreads();
-  // 1. inverse pass 1, tasks (f, pair, n2): packed spectrum of rows 2 pair, 2 pair + 1
-  for (int task = tid; task < 6 * P * FB; task += nthr) {
-    const int f = task / (P * FB);
-    const int rem = task - f * P * FB;
-    const int pr = rem / FB, n2 = rem - pr * FB;
+  // 0. stage the rows: for every (field, pair) sequence and stored mode m < N_x/2, the packed
+  // spectrum P_m = a_m + i b_m of the two rows (a_0, b_0 real) at S[seq][m] and the packed
+  // conjugates Q_m = conj(a_m) + i conj(b_m), which give modes L - m, at S[seq][nkx + m]
+  // (2 nkx <= L + 1 slots).  Each stored mode is loaded once, coalesced.
+  for (int it = tid; it < 6 * P * nkx; it += nthr) {
+    const int seq = it / nkx, m = it - seq * nkx;
+    const int f = seq / P, pr = seq - f * P;
     const int za = 2 * (pair0 + pr);
     const cplx* ra = A.Z6 + (((size_t)f * ny + j) * mz + za) * nkx;
-    const cplx* rb = ra + nkx;
-    cplx t[FA];
-#pragma unroll
-    for (int n1 = 0; n1 < FA; ++n1) {
-      const int k = FB * n1 + n2;
-      cplx xa = cz(), xb = cz();
-      if (k < nkx) {
-        xa = ra[k];
-        xb = rb[k];
-        if (k == 0) {
-          xa.y = 0.0;
-          xb.y = 0.0;
-        }
-      } else if (k > L - nkx) {
-        xa = cconj(ra[L - k]);
-        xb = cconj(rb[L - k]);
-      }
-      t[n1] = make_double2(xa.x - xb.y, xa.y + xb.x);  // xa + i xb
+    cplx xa = ra[m], xb = ra[nkx + m];
+    if (m == 0) {
+      xa.y = 0.0;
+      xb.y = 0.0;
     }
-    Dft<FA, 1>::run(t);
-    cplx* y = S + (f * P + pr) * LP + n2 * FA;
+    S[seq * LP + m] = make_double2(xa.x - xb.y, xa.y + xb.x);
+    S[seq * LP + nkx + m] = make_double2(xa.x + xb.y, xb.x - xa.y);
+  }
+  __syncthreads();
+  // 1. inverse pass 1, one task (f, pair, n2) per thread (the block has 6 P A >= 6 P B
+  // threads): the packed spectrum k = B n1 + n2 is read into registers, then (after every
+  // task has read its inputs) transformed and written back over the staged rows
+  {
+    const int task = tid;
+    const bool have = task < 6 * P * FB;
+    const int seq = task / FB, n2 = task - seq * FB;
+    cplx t[FA];
+    if (have) {
+      const cplx* z = S + seq * LP;
 #pragma unroll
-    for (int k1 = 0; k1 < FA; ++k1) y[k1] = twiddle<L, 1>(t[k1], tw, n2 * k1);
+      for (int n1 = 0; n1 < FA; ++n1) {
+        const int k = FB * n1 + n2;
+        t[n1] = (k < nkx) ? z[k] : ((k > L - nkx) ? z[nkx + (L - k)] : cz());
+      }
+    }
+    __syncthreads();
+    if (have) {
+      Dft<FA, 1>::run(t);
+      cplx* y = S + seq * LP + n2 * FA;
+#pragma unroll
+      for (int k1 = 0; k1 < FA; ++k1) y[k1] = twiddle<L, 1>(t[k1], tw, n2 * k1);
+    }
   }
   __syncthreads();
   // 2. inverse pass 2, tasks (f, pair, k1): values at x = k1 + A k2, back into S in order
