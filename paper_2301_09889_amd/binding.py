@@ -271,6 +271,20 @@ def make_opts(**kw):
     return o
 
 
+def _action_ptr(env, a):
+    """Device pointer of an action tensor for env (0 for None), after checking that the kernels
+    can read it: float64, contiguous, (nz, nx), on the env's device."""
+    if a is None:
+        return 0
+    if a.dtype != env.torch.float64 or not a.is_contiguous():
+        raise ValueError("action must be a contiguous float64 tensor")
+    if tuple(a.shape) != (env.grid.nz, env.grid.nx):
+        raise ValueError(f"action shape {tuple(a.shape)} != (nz, nx) = {(env.grid.nz, env.grid.nx)}")
+    if a.device != env.obs.device:
+        raise ValueError(f"action on {a.device}, env on {env.obs.device}")
+    return a.data_ptr()
+
+
 class ChanEnv:
     """One channel on the current HIP device; tensors come from PyTorch."""
 
@@ -307,11 +321,7 @@ class ChanEnv:
 
     def step(self, action, n_substeps):
         """action: float64 device tensor (nz, nx) or None.  Returns (obs, tau_w, drag) tensors."""
-        ptr = 0
-        if action is not None:
-            assert action.dtype == self.torch.float64 and action.is_contiguous()
-            assert tuple(action.shape) == (self.grid.nz, self.grid.nx)
-            ptr = action.data_ptr()
+        ptr = _action_ptr(self, action)
         rc = chan_env_step(self.handle, ptr, n_substeps, self.obs.data_ptr(), self.tau_w.data_ptr(),
                            self.drag.data_ptr())
         self._check(rc, "chan_env_step")
@@ -344,13 +354,7 @@ class ChanBatch:
     def step(self, actions, n_substeps):
         """actions: list of float64 device tensors (nz, nx) or None per env (or None for all).
         Returns the per-env result codes; raises if the call itself failed before running."""
-        aptrs = []
-        for k, e in enumerate(self.envs):
-            a = actions[k] if actions is not None else None
-            if a is not None:
-                assert a.dtype == e.torch.float64 and a.is_contiguous()
-                assert tuple(a.shape) == (e.grid.nz, e.grid.nx)
-            aptrs.append(a.data_ptr() if a is not None else 0)
+        aptrs = [_action_ptr(e, actions[k] if actions is not None else None) for k, e in enumerate(self.envs)]
         for k in range(len(self.envs)):
             self.results[k] = CHAN_OK
         rc = chan_batch_step(self.handle, aptrs, n_substeps, [e.obs.data_ptr() for e in self.envs],
@@ -364,14 +368,9 @@ class ChanBatch:
     def step_subset(self, idx, actions, n_substeps):
         """Advance only the envs idx (positions in this batch); actions indexed like idx (or None).
         Returns the result codes, indexed like idx."""
-        aptrs = []
-        for k, i in enumerate(idx):
-            e = self.envs[i]
-            a = actions[k] if actions is not None else None
-            if a is not None:
-                assert a.dtype == e.torch.float64 and a.is_contiguous()
-                assert tuple(a.shape) == (e.grid.nz, e.grid.nx)
-            aptrs.append(a.data_ptr() if a is not None else 0)
+        if any(not 0 <= i < len(self.envs) for i in idx):
+            raise ValueError("env index out of range")
+        aptrs = [_action_ptr(self.envs[i], actions[k] if actions is not None else None) for k, i in enumerate(idx)]
         res = (ctypes.c_int32 * len(idx))()
         sel = [self.envs[i] for i in idx]
         rc = chan_batch_step_subset(self.handle, idx, aptrs, n_substeps, [e.obs.data_ptr() for e in sel],

@@ -840,7 +840,8 @@ __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S
 
 // Many channels: channel blockIdx.x / bpc of the device array.  With many columns resident,
 // occupancy hides load latency: the reconstruction requests its cosines per group of 16
-// terms, which takes it from 172 to 143 registers (three waves per SIMD instead of two).
+// terms, which keeps the reconstruction and the fused launch within three waves per SIMD
+// (138 and 164 VGPRs at N = 64; all cosines up front needs more than 170).
 template <int N, int PART>
 __global__ __launch_bounds__(64 * CWAVES, 3) void k_column_pm(const ColChan* __restrict__ chans, ColStage S,
                                                                int bpc) {

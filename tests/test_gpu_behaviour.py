@@ -29,6 +29,23 @@ def test_error_codes():
     genv.close()
 
 
+def test_binding_rejects_unreadable_actions():
+    """A host tensor, a wrong shape or dtype is refused before anything is launched."""
+    import torch
+    cfg = minimal_channel()
+    genv = gpu_env(cfg)
+    genv.reset(2)
+    before = genv.get_state()
+    good = to_device(gaussian_action(5, 16, 16))
+    for bad in (good.cpu(), good[:, :8].contiguous(), good.float(), good.t()):
+        with pytest.raises(ValueError):
+            genv.step(bad, 1)
+    assert np.array_equal(genv.get_state(), before)
+    genv.step(good, 1)
+    genv.close()
+    assert torch.cuda.is_available()
+
+
 def test_nonfinite_action_leaves_state_untouched():
     import paper_2301_09889_amd.binding as b
     cfg = minimal_channel()
