@@ -157,6 +157,10 @@ struct Lane {
     even_row = ((lane >> 4) & 1) == 0;
     low = !odd;
   }
+  // (-1)^odd and [even]: parity choices as exact multiplications instead of per-lane selects
+  // (recomputed where used rather than held in registers)
+  __device__ double sgn() const { return odd ? -1.0 : 1.0; }
+  __device__ double evenf() const { return odd ? 0.0 : 1.0; }
 };
 
 // Suffix sum over this lane's half: lane i receives sum_{i' >= i} x_{i'} (lanes beyond the
@@ -182,7 +186,7 @@ __device__ __forceinline__ cplx cheb_d(const Lane<N>& L, cplx x, cplx xt) {
   const cplx Sn = cmov<DPP_WAVE_SHL1>(S);
   cplx g = make_double2(cross_halves(S.x, Sn.x, L.low), cross_halves(S.y, Sn.y, L.low));
   if (L.odd && L.i + 1 >= H) g = cz();
-  const cplx b = L.odd ? cadd(g, cscale(xt, (double)N)) : g;
+  const cplx b = caxpy(g, 1.0 - L.evenf(), cscale(xt, (double)N));  // odd lanes add the tail
   const double c = (L.n == 0) ? 1.0 : 2.0;
   return L.ok ? cscale(b, c) : cz();
 }
@@ -320,8 +324,8 @@ __device__ __forceinline__ void tau_solve_pm(const Lane<N>& L, const cplx* R, co
     const cplx Et = caxpy(et[k], frt, Elast);
     cplx sum = half_sum(A[k]);
     const cplx sum_even = readlane_c(sum, 0);
-    if (!L.odd) sum = cadd(sum, Et);
-    const cplx g = L.odd ? cscale(csub(gt[k], gb[k]), 0.5) : cscale(cadd(gt[k], gb[k]), 0.5);
+    sum = caxpy(sum, L.evenf(), Et);                            // even lanes: + E_{N/2}
+    const cplx g = cscale(caxpy(gt[k], L.sgn(), gb[k]), 0.5);   // (g_t +- g_b) / 2
     const cplx x0 = cscale(csub(g, sum), isf);
     X[k] = L.ok ? caxpy(A[k], F, x0) : cz();
     const cplx ge = cscale(cadd(gt[k], gb[k]), 0.5);
@@ -460,7 +464,6 @@ __device__ __forceinline__ void dct_inv_pm(const Lane<N>& L, const cplx* a, cons
   constexpr int NQ = (H + 15) / 16;
   constexpr int SH = (H & 1) ? 32 + (H >> 1) : (H >> 1);  // lane of a_{N/2}
   const int lane = L.l;
-  const bool prow = L.l < 32;
   double cf[H + 1];  // this lane's cosines, requested up front (or per group of 16, CHUNK)
   if constexpr (!CHUNK) {
 #pragma unroll
@@ -479,7 +482,7 @@ __device__ __forceinline__ void dct_inv_pm(const Lane<N>& L, const cplx* a, cons
       const cplx x = shfl_c(a[g], s1 & 63);
       cplx y = shfl_c(a[g], s2 & 63);
       if (n == 0) y = at[g];
-      const cplx qv = (n < H) ? (prow ? cadd(x, y) : csub(x, y)) : cz();
+      const cplx qv = (n < H) ? caxpy(x, L.sgn(), y) : cz();  // P_n (rows 0-1) or M_n (rows 2-3)
       Q[m][2 * g] = qv.x;
       Q[m][2 * g + 1] = qv.y;
     }
@@ -510,7 +513,7 @@ __device__ __forceinline__ void dct_inv_pm(const Lane<N>& L, const cplx* a, cons
 #pragma unroll
   for (int g = 0; g < F; ++g) {
     f[g] = L.ok ? caxpy(make_double2(acc[2 * g], acc[2 * g + 1]), ch, ah[g]) : cz();
-    const cplx part = L.ok ? (L.odd ? cscale(a[g], -1.0) : a[g]) : cz();
+    const cplx part = L.ok ? cscale(a[g], L.sgn()) : cz();
     ft[g] = cadd(lane_sum(part), at[g]);
   }
 }
@@ -669,10 +672,10 @@ __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S
       // influence correction: dv/dy(+-1) = 0 with v = v_p + c0 v_+ + c1 v_-
       const double n2 = dn * dn;
       const cplx dtop = coef_sum<N>(L, vp[0], vpt[0], n2, dN * dN);
-      const cplx dbot = coef_sum<N>(L, vp[0], vpt[0], L.odd ? n2 : -n2, -dN * dN);
+      const cplx dbot = coef_sum<N>(L, vp[0], vpt[0], -L.sgn() * n2, -dN * dN);
       const cplx c0 = make_double2(-(mi0 * dtop.x + mi1 * dbot.x), -(mi0 * dtop.y + mi1 * dbot.y));
       const cplx c1 = make_double2(-(mi2 * dtop.x + mi3 * dbot.x), -(mi2 * dtop.y + mi3 * dbot.y));
-      v = caxpy(caxpy(vp[0], tv, c0), L.odd ? -tv : tv, c1);
+      v = caxpy(caxpy(vp[0], tv, c0), L.sgn() * tv, c1);
       vt = caxpy(caxpy(vpt[0], tvt, c0), tvt, c1);
       if (!L.ok) v = cz();
       om = X[1];
@@ -736,7 +739,7 @@ __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S
         A.meanS[NY + N] = vt.y;
       }
       const double n2 = dn * dn;
-      const double slope = lane_sum(L.ok ? (L.odd ? n2 : -n2) * v.x : 0.0) - dN * dN * vt.x;
+      const double slope = lane_sum(L.ok ? (-L.sgn() * n2) * v.x : 0.0) - dN * dN * vt.x;
       if (r == 2 && lane == 0) A.drag_acc[0] += A.nu * slope;  // drag: end of every time step
       const bool ok = isfinite(v.x) && isfinite(v.y) && isfinite(vt.x) && isfinite(vt.y);
       if (r == 2 && __any(!ok) && lane == 0) atomicOr(A.status, STATUS_NONFINITE);
@@ -782,7 +785,7 @@ __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S
     fld[5] = csub(cmuli(cscale(v, al)), du);
     fldt[5] = cscale(cmuli(vt), al);
     const double n2 = dn * dn;
-    tau_hat = cscale(coef_sum<N>(L, u, ut, L.odd ? n2 : -n2, -dN * dN), A.nu);
+    tau_hat = cscale(coef_sum<N>(L, u, ut, -L.sgn() * n2, -dN * dN), A.nu);
   } else {
     const cplx dX = cheb_d<N>(L, v, vt);
     fld[0] = make_double2(v.x, 0.0);
@@ -796,7 +799,7 @@ __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S
     fld[5] = make_double2(-dX.x, 0.0);
     fldt[5] = cz();
     const double n2 = dn * dn;
-    const double slope = lane_sum(L.ok ? (L.odd ? n2 : -n2) * v.x : 0.0) - dN * dN * vt.x;
+    const double slope = lane_sum(L.ok ? (-L.sgn() * n2) * v.x : 0.0) - dN * dN * vt.x;
     tau_hat = make_double2(A.nu * slope, 0.0);
   }
   cplx ph[6], pht[6];
