@@ -212,3 +212,43 @@ def test_large_batch_matches_alone_bitwise():
     batch.close()
     for e in alone + mixed:
         e.close()
+
+
+def test_bench_batch_members_match_oracle():
+    """The benchmark's 256-channel uneven batch (bench.py --workload batched), one env step of
+    10 time steps in that launch configuration; sampled members (both shapes, both Re_tau,
+    opposition and external actions) against the oracle from the same state."""
+    import torch
+    import paper_2301_09889_amd.binding as b
+    import bench
+    specs = bench.batched_specs(256, "uneven")
+    envs, acts = [], []
+    for sp in specs:
+        grid = b.ChanGrid(sp["nx"], sp["ny"], sp["nz"], sp["lx"], sp["lz"], sp["re_tau"], sp["dt_plus"],
+                          sp["obs_y_plus"])
+        e = b.ChanEnv(grid, b.make_opts(controller=0 if sp["external"] else 1))
+        e.reset(sp["seed"])
+        envs.append(e)
+        acts.append(torch.tensor(gaussian_action(1000 + sp["seed"], sp["nz"], sp["nx"]), dtype=torch.float64,
+                                 device="cuda") if sp["external"] else None)
+    sample = [0, 1, 3, 254]
+    start = {i: envs[i].get_state() for i in sample}
+    batch = b.ChanBatch(envs)
+    assert batch.step(acts, 10) == [0] * len(specs)
+    for i in sample:
+        sp = specs[i]
+        cfg = ch.Config(nx=sp["nx"], ny=sp["ny"], nz=sp["nz"], lx=sp["lx"], lz=sp["lz"], re_tau=sp["re_tau"],
+                        dt_plus=sp["dt_plus"], obs_y_plus=sp["obs_y_plus"],
+                        controller=ch.CTRL_EXTERNAL if sp["external"] else ch.CTRL_OPPOSITION)
+        oenv = ch.Env(cfg)
+        oenv.set_state(ch.state_from_flat(oenv.S, start[i]))
+        obs_o, tau_o, drag_o = oenv.step(acts[i].cpu().numpy() if acts[i] is not None else None, 10)
+        d = rel_state_diff(gpu_state(oenv.S, envs[i]), oenv.state)
+        print(f"  member {i} {sp['nx']}x65x{sp['nz']} Re_tau {sp['re_tau']:.0f} "
+              f"{'external' if sp['external'] else 'opposition'}: state rel diff {d:.3e}", flush=True)
+        assert d <= 1e-11, i
+        assert rel_field_diff(envs[i].obs.cpu().numpy(), obs_o) <= 1e-10
+        assert rel_field_diff(envs[i].tau_w.cpu().numpy(), tau_o) <= 64 ** 2 * 1e-11
+    batch.close()
+    for e in envs:
+        e.close()
