@@ -172,3 +172,61 @@ def test_stokes_mode_on_device(parity):
     gs = gpu_state(S, g)
     assert np.abs(gs.v[0, 1] - ref * G ** 50).max() / np.abs(ref).max() < 1e-10
     g.close()
+
+
+def test_closed_forms_at_full_size_re395():
+    """The 128 x 97 x 128 channel at Re_tau 395 (general column kernel, N = 96; 192-point plane
+    transforms), too large for the oracle to step in a test: closed-form solutions instead.
+    (1) the exact nonlinear decaying mode u = A sin(pi (1 + y)) cos(beta z) (CPG, P_x = 0)
+    scales by the RK3/CN factor G per time step; (2) a small even Stokes mode of v decays by
+    its own factor; (3) laminar Poiseuille under CPG is steady."""
+    base = dict(nx=128, ny=97, nz=128, lx=2 * np.pi, lz=np.pi, re_tau=395.0, dt_plus=0.05)
+    # (1) omega_y mode at (p, q) = (0, 1)
+    cfg = tiny(**base, forcing=ch.CPG, px=0.0)
+    S = ch.Setup(cfg)
+    st = ch.zero_state(S)
+    prof = S.C @ (1.5 * np.sin(2 * np.pi * (1 + S.y) / 2))
+    beta = S.beta[1]
+    st.om[1, 0] = 1j * beta * prof / 2
+    st.om[S.nz - 1, 0] = np.conj(st.om[1, 0])
+    ref0 = st.om.copy()
+    G = rk_amplification(S.dt, -S.nu * (beta ** 2 + np.pi ** 2))
+    g = gpu_env(cfg)
+    g.set_state(ch.state_to_flat(S, st))
+    g.step(None, 20)
+    gs = gpu_state(S, g)
+    err = np.abs(gs.om - ref0 * G ** 20).max() / np.abs(ref0).max()
+    print(f"  decaying mode: max rel error {err:.2e}", flush=True)
+    assert err < 1e-12
+    assert np.abs(gs.v).max() < 1e-12 * np.abs(ref0).max()
+    g.close()
+    # (2) even Stokes mode of v at (p, q) = (1, 0)
+    k = S.alpha[1]
+    pp = stokes_p(k, "even")
+    st = ch.zero_state(S)
+    st.v[0, 1] = S.C @ (0.5e-8 * stokes_profile(k, pp, "even", S.y))
+    ref = st.v[0, 1].copy()
+    G = rk_amplification(S.dt, -S.nu * (k * k + pp * pp))
+    g = gpu_env(cfg)
+    g.set_state(ch.state_to_flat(S, st))
+    g.step(None, 20)
+    gs = gpu_state(S, g)
+    err = np.abs(gs.v[0, 1] - ref * G ** 20).max() / np.abs(ref).max()
+    print(f"  Stokes mode: max rel error {err:.2e}", flush=True)
+    assert err < 1e-10
+    g.close()
+    # (3) laminar Poiseuille, P_x = 2 nu U_cl
+    ucl = 20.0
+    cfg = tiny(**base, forcing=ch.CPG, px=2 * (1 / 395.0) * ucl)
+    S = ch.Setup(cfg)
+    st = ch.zero_state(S)
+    st.ubar[0], st.ubar[2] = ucl / 2, -ucl / 2
+    g = gpu_env(cfg)
+    g.set_state(ch.state_to_flat(S, st))
+    g.step(None, 20)
+    gs = gpu_state(S, g)
+    err = np.abs(gs.ubar - st.ubar).max() / ucl
+    print(f"  Poiseuille: max rel drift {err:.2e}", flush=True)
+    assert err < 1e-13
+    assert np.abs(gs.v).max() == 0 and np.abs(gs.om).max() == 0
+    g.close()
