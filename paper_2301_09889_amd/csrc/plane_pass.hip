@@ -28,6 +28,16 @@ template <> struct FftPlan<48> { static constexpr int A = 8, B = 6; };
 template <> struct FftPlan<96> { static constexpr int A = 12, B = 8; };
 template <> struct FftPlan<192> { static constexpr int A = 16, B = 12; };
 
+// LDS layout of a transform: pass 1 writes each task's A outputs at stride AP (odd, so that
+// the tasks of a wavefront land in different banks) and sequences lie LS apart (odd, at least
+// L + 1 and B AP).  Pass 2 reads back at the same strides; the data stay bitwise the same.
+template <int L>
+struct FftLds {
+  static constexpr int A = FftPlan<L>::A, B = FftPlan<L>::B;
+  static constexpr int AP = A | 1;
+  static constexpr int LS = ((L + 1 > B * AP) ? L + 1 : B * AP) | 1;
+};
+
 
 // a * w_L^(SG m) from a table tw[k] = exp(-2 pi i k / L) held in LDS.
 template <int L, int SG>
@@ -45,7 +55,7 @@ __device__ __forceinline__ cplx twiddle(cplx a, const cplx* tw, int m) {
 template <int L>
 __global__ __launch_bounds__(1024) void k_zinv2(const PlaneChan* __restrict__ chans, int ny, int PB) {
   constexpr int FA = FftPlan<L>::A, FB = FftPlan<L>::B;
-  constexpr int LP = L + 1;
+  constexpr int LP = FftLds<L>::LS, AP = FftLds<L>::AP;
   extern __shared__ double dyn_lds[];
   cplx* tw = reinterpret_cast<cplx*>(dyn_lds);
   cplx* Y = tw + L;
@@ -70,7 +80,7 @@ __global__ __launch_bounds__(1024) void k_zinv2(const PlaneChan* __restrict__ ch
       t[n1] = (q >= 0) ? src[(size_t)p * nz + q] : cz();
     }
     Dft<FA, 1>::run(t);
-    cplx* y = Y + p * LP + n2 * FA;
+    cplx* y = Y + p * LP + n2 * AP;
 #pragma unroll
     for (int k1 = 0; k1 < FA; ++k1) y[k1] = twiddle<L, 1>(t[k1], tw, n2 * k1);
   }
@@ -80,7 +90,7 @@ __global__ __launch_bounds__(1024) void k_zinv2(const PlaneChan* __restrict__ ch
     const int k1 = task / np, p = task - k1 * np;
     cplx u[FB];
 #pragma unroll
-    for (int n2 = 0; n2 < FB; ++n2) u[n2] = Y[p * LP + n2 * FA + k1];
+    for (int n2 = 0; n2 < FB; ++n2) u[n2] = Y[p * LP + n2 * AP + k1];
     Dft<FB, 1>::run(u);
     if (skip) continue;
 #pragma unroll
@@ -94,7 +104,7 @@ __global__ __launch_bounds__(1024) void k_zinv2(const PlaneChan* __restrict__ ch
 template <int L>
 __global__ __launch_bounds__(1024) void k_zfwd2(const PlaneChan* __restrict__ chans, int ny, int PB) {
   constexpr int FA = FftPlan<L>::A, FB = FftPlan<L>::B;
-  constexpr int LP = L + 1;
+  constexpr int LP = FftLds<L>::LS, AP = FftLds<L>::AP;
   extern __shared__ double dyn_lds[];
   cplx* tw = reinterpret_cast<cplx*>(dyn_lds);
   cplx* X0 = tw + L;       // the p = 0 pencil, for the Hermitian fix
@@ -114,7 +124,7 @@ __global__ __launch_bounds__(1024) void k_zfwd2(const PlaneChan* __restrict__ ch
 #pragma unroll
     for (int n1 = 0; n1 < FA; ++n1) t[n1] = src[(size_t)(FB * n1 + n2) * A.nkx + p];
     Dft<FA, -1>::run(t);
-    cplx* y = Y + p * LP + n2 * FA;
+    cplx* y = Y + p * LP + n2 * AP;
 #pragma unroll
     for (int k1 = 0; k1 < FA; ++k1) y[k1] = twiddle<L, -1>(t[k1], tw, n2 * k1);
   }
@@ -125,7 +135,7 @@ __global__ __launch_bounds__(1024) void k_zfwd2(const PlaneChan* __restrict__ ch
     const int p = task / FA, k1 = task - p * FA;
     cplx u[FB];
 #pragma unroll
-    for (int n2 = 0; n2 < FB; ++n2) u[n2] = Y[p * LP + n2 * FA + k1];
+    for (int n2 = 0; n2 < FB; ++n2) u[n2] = Y[p * LP + n2 * AP + k1];
     Dft<FB, -1>::run(u);
 #pragma unroll
     for (int k2 = 0; k2 < FB; ++k2) {
@@ -165,7 +175,7 @@ __global__ __launch_bounds__(1024) void k_zfwd2(const PlaneChan* __restrict__ ch
 template <int L>
 __global__ __launch_bounds__(1024) void k_xrow2(const PlaneChan* __restrict__ chans, int nyc, int P) {
   constexpr int FA = FftPlan<L>::A, FB = FftPlan<L>::B;
-  constexpr int LP = L + 1;
+  constexpr int LP = FftLds<L>::LS, AP = FftLds<L>::AP;
   static_assert(FA >= FB, "pass 1 has at most one task per thread");
   extern __shared__ double dyn_lds[];
   cplx* tw = reinterpret_cast<cplx*>(dyn_lds);
@@ -214,7 +224,7 @@ __global__ __launch_bounds__(1024) void k_xrow2(const PlaneChan* __restrict__ ch
     __syncthreads();
     if (have) {
       Dft<FA, 1>::run(t);
-      cplx* y = S + seq * LP + n2 * FA;
+      cplx* y = S + seq * LP + n2 * AP;
 #pragma unroll
       for (int k1 = 0; k1 < FA; ++k1) y[k1] = twiddle<L, 1>(t[k1], tw, n2 * k1);
     }
@@ -231,7 +241,7 @@ __global__ __launch_bounds__(1024) void k_xrow2(const PlaneChan* __restrict__ ch
       k1 = tid - seq * FA;
       base = seq * LP;
 #pragma unroll
-      for (int n2 = 0; n2 < FB; ++n2) X[n2] = S[base + n2 * FA + k1];
+      for (int n2 = 0; n2 < FB; ++n2) X[n2] = S[base + n2 * AP + k1];
       Dft<FB, 1>::run(X);
     }
     __syncthreads();
@@ -268,7 +278,7 @@ __global__ __launch_bounds__(1024) void k_xrow2(const PlaneChan* __restrict__ ch
     __syncthreads();
     if (have) {
 #pragma unroll
-      for (int k1 = 0; k1 < FA; ++k1) S[base + n2 * FA + k1] = twiddle<L, -1>(t[k1], tw, n2 * k1);
+      for (int k1 = 0; k1 < FA; ++k1) S[base + n2 * AP + k1] = twiddle<L, -1>(t[k1], tw, n2 * k1);
     }
   }
   __syncthreads();
@@ -283,7 +293,7 @@ __global__ __launch_bounds__(1024) void k_xrow2(const PlaneChan* __restrict__ ch
       k1 = tid - seq * FA;
       base = seq * LP;
 #pragma unroll
-      for (int n2 = 0; n2 < FB; ++n2) X[n2] = S[base + n2 * FA + k1];
+      for (int n2 = 0; n2 < FB; ++n2) X[n2] = S[base + n2 * AP + k1];
       Dft<FB, -1>::run(X);
     }
     __syncthreads();
@@ -310,7 +320,7 @@ __global__ __launch_bounds__(1024) void k_xrow2(const PlaneChan* __restrict__ ch
 
 // LDS of the x-row kernel with P pairs of rows per block, and its thread count.
 template <int MX>
-static size_t xrow_lds(int P) { return (size_t)(MX + (size_t)6 * P * (MX + 1)) * sizeof(cplx); }
+static size_t xrow_lds(int P) { return (size_t)(MX + (size_t)6 * P * FftLds<MX>::LS) * sizeof(cplx); }
 template <int MX>
 static int xrow_threads(int P) { return ((6 * P * FftPlan<MX>::A + 63) / 64) * 64; }
 
@@ -321,8 +331,8 @@ static int launch_plane2(const Dims& d, const PlaneChan* chans, int nch, const P
   const int pairs = MZ / 2;
   if (PB < 1 || PB > d.nkx || P < 1 || pairs % P != 0 || xrow_threads<MX>(P) > 1024) return -1;
   const int nblk = (d.nkx + PB - 1) / PB;
-  const size_t shz = (size_t)(MZ + (size_t)PB * (MZ + 1)) * sizeof(cplx);
-  const size_t shf = (size_t)(2 * MZ + (size_t)PB * (MZ + 1)) * sizeof(cplx);
+  const size_t shz = (size_t)(MZ + (size_t)PB * FftLds<MZ>::LS) * sizeof(cplx);
+  const size_t shf = (size_t)(2 * MZ + (size_t)PB * FftLds<MZ>::LS) * sizeof(cplx);
   constexpr int ZA = FftPlan<MZ>::A;
   const int zthr = ((PB * ZA + 63) / 64) * 64;
   const unsigned nyz = (unsigned)(d.ny * nch);
