@@ -1,0 +1,90 @@
+"""Drag reduction by opposition control in the larger channel (§4.1: opposition control as the
+classical baseline, sensing plane at y+ 10 and 15).
+
+Every case runs as one channel per seed, all advanced together in one batch:
+* uncontrolled: zero wall velocity (external controller, no action);
+* opposition control with the sensing plane at each requested y+ (alpha = 1, zero net flux).
+All channels: 64x65x64 modes, 2 pi x 2 x pi (h), Re_tau 180, dt+ 0.05, constant flow rate,
+Reichardt mean profile with the seeded perturbation.  The drag (plane-mean wall shear in wall
+units) is averaged over a window after the initial transient; DR = 1 - D_controlled /
+D_uncontrolled with the means over the seeds.
+
+    python -m paper_2301_09889_amd.drag_reduction [--env-steps 6000] [--seeds 0 1 2] [--y-plus 10 15]
+"""
+import argparse
+import json
+import time
+
+import numpy as np
+
+from . import binding as b
+
+LARGER = dict(nx=64, ny=65, nz=64, lx=2 * np.pi, lz=np.pi, re_tau=180.0, dt_plus=0.05)
+
+
+def run(y_plus=(10.0, 15.0), seeds=(0, 1, 2), n_env=6000, n_sub=10, window_start=1000, grid=LARGER,
+        progress=None):
+    """Drag histories and drag reduction.  Returns a dict with, per case, the per-seed window
+    means, their mean, and DR against the uncontrolled case."""
+    import torch
+    cases = [("uncontrolled", 15.0, b.CHAN_CTRL_EXTERNAL)] + \
+            [(f"opposition y+{yp:g}", float(yp), b.CHAN_CTRL_OPPOSITION) for yp in y_plus]
+    envs, labels = [], []
+    for name, yp, ctrl in cases:
+        for s in seeds:
+            g = b.ChanGrid(grid["nx"], grid["ny"], grid["nz"], grid["lx"], grid["lz"], grid["re_tau"],
+                           grid["dt_plus"], yp)
+            e = b.ChanEnv(g, b.make_opts(controller=ctrl, ic_profile=1))
+            e.reset(s)
+            envs.append(e)
+            labels.append((name, s))
+    batch = b.ChanBatch(envs)
+    hist = torch.zeros((len(envs), n_env), dtype=torch.float64, device=envs[0].obs.device)
+    t0 = time.perf_counter()
+    try:
+        for k in range(n_env):
+            codes = batch.step(None, n_sub)
+            bad = [labels[i] for i, c in enumerate(codes) if c != 0]
+            if bad:
+                raise RuntimeError(f"env step {k}: channels {bad} failed")
+            for i, e in enumerate(envs):
+                hist[i, k] = e.drag[0]
+            if progress and (k + 1) % 1000 == 0:
+                progress(k + 1, time.perf_counter() - t0)
+        h = hist.cpu().numpy()
+    finally:
+        batch.close()
+        for e in envs:
+            e.close()
+    out = {"window_env_steps": [window_start, n_env], "t_plus_per_env_step": n_sub * grid["dt_plus"],
+           "seeds": list(seeds), "cases": {}}
+    for name, _, _ in cases:
+        w = [float(h[i, window_start:].mean()) for i, (nm, _) in enumerate(labels) if nm == name]
+        out["cases"][name] = {"window_mean_per_seed": w, "mean": float(np.mean(w))}
+    ref = out["cases"]["uncontrolled"]["mean"]
+    for c in out["cases"].values():
+        c["drag_reduction"] = 1.0 - c["mean"] / ref
+    out["elapsed_s"] = time.perf_counter() - t0
+    out["histories"] = {f"{nm} seed {s}": h[i].tolist() for i, (nm, s) in enumerate(labels)}
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--env-steps", type=int, default=6000)
+    ap.add_argument("--window-start", type=int, default=1000)
+    ap.add_argument("--seeds", type=int, nargs="+", default=[0, 1, 2])
+    ap.add_argument("--y-plus", type=float, nargs="+", default=[10.0, 15.0])
+    ap.add_argument("--histories", help="write the drag histories (JSON) to this file")
+    args = ap.parse_args()
+    res = run(args.y_plus, args.seeds, args.env_steps, window_start=args.window_start,
+              progress=lambda k, t: print(f"env step {k} ({t:.0f} s)", flush=True))
+    hist = res.pop("histories")
+    if args.histories:
+        with open(args.histories, "w") as fh:
+            json.dump(hist, fh)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()
