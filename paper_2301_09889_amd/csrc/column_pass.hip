@@ -33,7 +33,7 @@ namespace chanenv {
 
 namespace {
 
-constexpr int CWAVES = 4;  // columns (wavefronts) per block
+constexpr int CWAVES = 4;  // columns (wavefronts) per block of the batched kernel
 
 
 // ---- cross-lane moves without LDS (gfx950 DPP and permlane swaps) ----
@@ -534,13 +534,13 @@ constexpr int PART_SOLVE = 0, PART_RECON = 1, PART_BOTH = 2;
 // Time fraction at the end of RK stage r (c_end of the stage).
 __device__ __forceinline__ double stage_end(int r) { return r == 0 ? 8.0 / 15.0 : (r == 1 ? 2.0 / 3.0 : 1.0); }
 
-// One block of CWAVES columns (block cb of the channel's columns).
-template <int N, int PART, bool CHUNK>
+// One block of CW columns (block cb of the channel's columns).
+template <int N, int PART, bool CHUNK, int CW>
 __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S, int cb) {
   constexpr int NY = N + 1;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // wave-uniform column
-  const int c = __builtin_amdgcn_readfirstlane(cb * CWAVES + wave);
+  const int c = __builtin_amdgcn_readfirstlane(cb * CW + wave);
   if (c >= A.ncol) return;
   // a rejected action skips the step: tested before the first store, loaded here so that
   // its latency overlaps the loads below
@@ -849,44 +849,67 @@ template <int N, int PART>
 __global__ __launch_bounds__(64 * CWAVES, 3) void k_column_pm(const ColChan* __restrict__ chans, ColStage S,
                                                                int bpc) {
   const int ch = blockIdx.x / bpc;
-  column_block<N, PART, PART != PART_SOLVE>(chans[ch], S, blockIdx.x - ch * bpc);
+  column_block<N, PART, PART != PART_SOLVE, CWAVES>(chans[ch], S, blockIdx.x - ch * bpc);
 }
 
 // One channel, its arguments by value (preloaded with the kernel arguments instead of read
-// through a pointer); the same column code as the batched kernel.
-template <int N, int PART>
-__global__ __launch_bounds__(64 * CWAVES, 2) void k_column_pm1(ColChan A, ColStage S) {
-  column_block<N, PART, false>(A, S, blockIdx.x);
+// through a pointer); the same column code as the batched kernel.  CW columns per block: few
+// columns spread over more CUs in small blocks (the minimal channel, 120 columns, steps about
+// 5 % faster with one per block), many fill the CUs better in blocks of four (the larger
+// channel, 1984 columns, 8 % slower with one per block).
+template <int N, int PART, int CW>
+__global__ __launch_bounds__(64 * CW, 2) void k_column_pm1(ColChan A, ColStage S) {
+  column_block<N, PART, false, CW>(A, S, blockIdx.x);
+}
+
+// Columns per block of the single-channel launch for ncol columns.
+inline int single_channel_cw(int ncol) { return ncol <= 256 ? 1 : (ncol <= 1024 ? 2 : 4); }
+
+template <int N, int CW>
+int launch_pm1(const ColChan& A, int ncol, const ColStage& S, bool solve, bool recon, hipStream_t st,
+               KernelTimer* tm) {
+  const dim3 grid((ncol + CW - 1) / CW), block(64 * CW);
+  if (solve && recon) {
+    timed_launch(tm, KC_FUSED, k_column_pm1<N, PART_BOTH, CW>, grid, block, 0, st, A, S);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+  }
+  if (solve) {
+    timed_launch(tm, KC_COLUMN, k_column_pm1<N, PART_SOLVE, CW>, grid, block, 0, st, A, S);
+    if (hipGetLastError() != hipSuccess) return -1;
+  }
+  if (recon) {
+    timed_launch(tm, KC_RECON, k_column_pm1<N, PART_RECON, CW>, grid, block, 0, st, A, S);
+    if (hipGetLastError() != hipSuccess) return -1;
+  }
+  return 0;
 }
 
 template <int N>
 int launch_pm(const ColChan* d_col, const ColChan* h_col, int nch, int ncol, const ColStage& S, bool solve,
               bool recon, hipStream_t st, KernelTimer* tm) {
-  const int bpc = (ncol + CWAVES - 1) / CWAVES;
-  const dim3 grid(bpc * nch), block(64 * CWAVES);
-  const bool one = nch == 1 && h_col != nullptr;
   // Both parts in one launch: the solved state stays in registers for the reconstruction,
   // which saves a kernel boundary and the state's reload.  (Every stage of every batch takes
-  // this path, so a channel's arithmetic does not depend on the batch it is in.)
+  // this path, so a channel's arithmetic does not depend on the batch it is in; neither does
+  // it depend on the block shape.)
+  if (nch == 1 && h_col != nullptr) {
+    switch (single_channel_cw(ncol)) {
+      case 1: return launch_pm1<N, 1>(h_col[0], ncol, S, solve, recon, st, tm);
+      case 2: return launch_pm1<N, 2>(h_col[0], ncol, S, solve, recon, st, tm);
+      default: return launch_pm1<N, 4>(h_col[0], ncol, S, solve, recon, st, tm);
+    }
+  }
+  const int bpc = (ncol + CWAVES - 1) / CWAVES;
+  const dim3 grid(bpc * nch), block(64 * CWAVES);
   if (solve && recon) {
-    if (one)
-      timed_launch(tm, KC_FUSED, k_column_pm1<N, PART_BOTH>, grid, block, 0, st, h_col[0], S);
-    else
-      timed_launch(tm, KC_FUSED, k_column_pm<N, PART_BOTH>, grid, block, 0, st, d_col, S, bpc);
+    timed_launch(tm, KC_FUSED, k_column_pm<N, PART_BOTH>, grid, block, 0, st, d_col, S, bpc);
     return hipGetLastError() == hipSuccess ? 0 : -1;
   }
   if (solve) {
-    if (one)
-      timed_launch(tm, KC_COLUMN, k_column_pm1<N, PART_SOLVE>, grid, block, 0, st, h_col[0], S);
-    else
-      timed_launch(tm, KC_COLUMN, k_column_pm<N, PART_SOLVE>, grid, block, 0, st, d_col, S, bpc);
+    timed_launch(tm, KC_COLUMN, k_column_pm<N, PART_SOLVE>, grid, block, 0, st, d_col, S, bpc);
     if (hipGetLastError() != hipSuccess) return -1;
   }
   if (recon) {
-    if (one)
-      timed_launch(tm, KC_RECON, k_column_pm1<N, PART_RECON>, grid, block, 0, st, h_col[0], S);
-    else
-      timed_launch(tm, KC_RECON, k_column_pm<N, PART_RECON>, grid, block, 0, st, d_col, S, bpc);
+    timed_launch(tm, KC_RECON, k_column_pm<N, PART_RECON>, grid, block, 0, st, d_col, S, bpc);
     if (hipGetLastError() != hipSuccess) return -1;
   }
   return 0;
