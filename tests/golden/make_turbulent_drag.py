@@ -10,6 +10,8 @@ per seed and over the six seeds.
 Run one process per seed, then combine:
     python tests/golden/make_turbulent_drag.py --seed K --work DIR      (K = 0..5)
     python tests/golden/make_turbulent_drag.py --combine --work DIR
+The six seeds 0-5 give turbulent_drag_minimal.json; with --nseeds 12 (seeds 0-11, run the
+same way) the combination goes to turbulent_drag_minimal_12seeds.json.
 Each seed takes about three hours on one core; partial histories are saved in DIR every 100
 env steps and a restarted run continues from them.
 """
@@ -64,9 +66,9 @@ def run_seed(seed, work):
             print(f"seed {seed}: {len(drags)} env steps, {time.time() - t0:.0f} s", flush=True)
 
 
-def combine(work):
+def combine(work, seeds=SEEDS, out_path=OUT):
     series = {}
-    for s in SEEDS:
+    for s in seeds:
         z = np.load(os.path.join(work, f"seed{s}.npz"))
         d = z["drag"]
         if d.size < N_ENV:
@@ -77,14 +79,14 @@ def combine(work):
         "what": "oracle drag history, minimal channel 16x65x16, Re_tau 180, dt+ 0.05, CFR, opposition control "
                 "at y+ 15 (alpha 1), seeded initial fields; env step = 10 time steps",
         "written_by": "tests/golden/make_turbulent_drag.py (oracle only)",
-        "seeds": SEEDS, "n_env_steps": N_ENV, "n_substeps": N_SUB, "window": [a, b], "block": BLOCK,
-        "window_mean": {str(s): float(series[s][a:b].mean()) for s in SEEDS},
-        "block_means": {str(s): [float(x) for x in series[s].reshape(-1, BLOCK).mean(axis=1)] for s in SEEDS},
+        "seeds": list(seeds), "n_env_steps": N_ENV, "n_substeps": N_SUB, "window": [a, b], "block": BLOCK,
+        "window_mean": {str(s): float(series[s][a:b].mean()) for s in seeds},
+        "block_means": {str(s): [float(x) for x in series[s].reshape(-1, BLOCK).mean(axis=1)] for s in seeds},
     }
-    out["ensemble_window_mean"] = float(np.mean([out["window_mean"][str(s)] for s in SEEDS]))
-    with open(OUT, "w") as fh:
+    out["ensemble_window_mean"] = float(np.mean([out["window_mean"][str(s)] for s in seeds]))
+    with open(out_path, "w") as fh:
         json.dump(out, fh, indent=1)
-    print(f"wrote {OUT}: ensemble window mean {out['ensemble_window_mean']:.6f}")
+    print(f"wrote {out_path}: ensemble window mean {out['ensemble_window_mean']:.6f}")
 
 
 def main():
@@ -92,10 +94,15 @@ def main():
     ap.add_argument("--seed", type=int)
     ap.add_argument("--combine", action="store_true")
     ap.add_argument("--work", required=True)
+    ap.add_argument("--nseeds", type=int, default=len(SEEDS), help="combine seeds 0 .. nseeds-1")
     args = ap.parse_args()
     os.makedirs(args.work, exist_ok=True)
     if args.combine:
-        combine(args.work)
+        if args.nseeds == len(SEEDS):
+            combine(args.work)
+        else:
+            combine(args.work, list(range(args.nseeds)),
+                    os.path.join(HERE, f"turbulent_drag_minimal_{args.nseeds}seeds.json"))
     else:
         from threadpoolctl import threadpool_limits
         with threadpool_limits(limits=1):

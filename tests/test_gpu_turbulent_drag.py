@@ -87,3 +87,27 @@ def test_mean_drag_matches_oracle():
     print(f"  six-seed mean drag, t+ 500-2500: GPU {ens_g:.5f} oracle {ens_o:.5f} rel diff {rel:.4f} "
           f"(sampling error of the difference {sig:.4f})", flush=True)
     assert rel <= 0.01
+
+
+GOLDEN12 = os.path.join(os.path.dirname(__file__), "golden", "turbulent_drag_minimal_12seeds.json")
+
+
+def test_mean_drag_twelve_seeds_within_sampling_error():
+    """The same comparison over seeds 0-11 (six more oracle runs, made after the six-seed test
+    was fixed): the twelve-seed mean drags agree within three sampling errors of their
+    difference; whether they also agree within 1 % is printed, not asserted."""
+    if not os.path.exists(GOLDEN12):
+        pytest.skip("twelve-seed oracle statistics not written")
+    with open(GOLDEN12) as fh:
+        ref = json.load(fh)
+    seeds, n_env, n_sub = ref["seeds"], ref["n_env_steps"], ref["n_substeps"]
+    a, bnd = ref["window"]
+    g = gpu_histories(seeds, n_env, n_sub)
+    wg = np.array([g[i, a:bnd].mean() for i in range(len(seeds))])
+    wo = np.array([ref["window_mean"][str(s)] for s in seeds])
+    ens_g, ens_o = float(wg.mean()), ref["ensemble_window_mean"]
+    rel = abs(ens_g - ens_o) / ens_o
+    sig = np.sqrt(wg.var(ddof=1) / len(seeds) + wo.var(ddof=1) / len(seeds)) / ens_o
+    print(f"  twelve-seed mean drag, t+ 500-2500: GPU {ens_g:.5f} oracle {ens_o:.5f} rel diff {rel:.4f} "
+          f"(sampling error of the difference {sig:.4f}; within 1 %: {rel <= 0.01})", flush=True)
+    assert rel <= 3 * sig
