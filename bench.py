@@ -40,12 +40,12 @@ MINIMAL = dict(nx=16, ny=65, nz=16, lx=2.67, lz=0.8, re_tau=180.0, dt_plus=0.05,
 # (131089 and 262144 KiB).  Each figure holds for the kernel source with the listed SHA-256
 # and is reported as null for any other source.
 TRAFFIC = {
-    "column_solve_reconstruct": (5.1227e+07, "column_pass.hip", "ae27452585a3e3eac0ac969382621f394f40a9a37b8995b2472894c481c7651b"),
-    "x_rows_fft_product": (2.8928e+07, "plane_pass.hip", "b7afe031e40d9d93435ff7712c4b46d2ac3bceb1e4af67af166d454b117823f0"),
-    "z_inverse_fft": (3.2061e+07, "plane_pass.hip", "b7afe031e40d9d93435ff7712c4b46d2ac3bceb1e4af67af166d454b117823f0"),
-    "z_forward_fft": (1.6094e+07, "plane_pass.hip", "b7afe031e40d9d93435ff7712c4b46d2ac3bceb1e4af67af166d454b117823f0"),
-    "column_pass": (3.5884e+07, "column_pass.hip", "ae27452585a3e3eac0ac969382621f394f40a9a37b8995b2472894c481c7651b"),
-    "column_reconstruct": (1.8021e+07, "column_pass.hip", "ae27452585a3e3eac0ac969382621f394f40a9a37b8995b2472894c481c7651b"),
+    "column_solve_reconstruct": (5.1017e+07, "column_pass.hip", "83fc4599437f61f9f531833e32ec6cb4c7dcca9f19d2000d23ac019ff8a0ceb0"),
+    "x_rows_fft_product": (2.8928e+07, "plane_pass.hip", "e482b1f48e2a6f8d9e5db1ec2caed7bf6175f2d3da369d8adbf949a60b79ab53"),
+    "z_inverse_fft": (3.2061e+07, "plane_pass.hip", "e482b1f48e2a6f8d9e5db1ec2caed7bf6175f2d3da369d8adbf949a60b79ab53"),
+    "z_forward_fft": (1.6094e+07, "plane_pass.hip", "e482b1f48e2a6f8d9e5db1ec2caed7bf6175f2d3da369d8adbf949a60b79ab53"),
+    "column_pass": (3.5860e+07, "column_pass.hip", "83fc4599437f61f9f531833e32ec6cb4c7dcca9f19d2000d23ac019ff8a0ceb0"),
+    "column_reconstruct": (1.8260e+07, "column_pass.hip", "83fc4599437f61f9f531833e32ec6cb4c7dcca9f19d2000d23ac019ff8a0ceb0"),
 }
 
 
