@@ -763,6 +763,12 @@ size_t chan_env_footprint_bytes(const chan_grid_t* grid, const chan_opts_t* opts
   if (opts) o = *opts; else chan_opts_default(&o);
   if (!valid_grid(grid) || !valid_opts(&o)) return 0;
   const Dims d = make_dims(grid);
+  // the same checks as chan_env_create: a grid it would refuse has no footprint
+  const PhysParams ph = make_phys(grid, &o);
+  if (!(ph.nu > 0) || !(ph.dt > 0)) return 0;
+  double ypn = 0.0;
+  const int js = sensing_node(d, ph.nu, grid->obs_y_plus, &ypn);
+  if (js < 0 || js >= d.N) return 0;
   return buffer_sizes(d, table_doubles(d)).total;
 }
 
@@ -774,10 +780,10 @@ int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_
   if (!valid_opts(&o)) return fail(CHAN_EINVAL, "options");
   const Dims d = make_dims(grid);
   const PhysParams ph = make_phys(grid, &o);
-  if (!(ph.nu > 0) || !(ph.dt > 0)) return CHAN_EINVAL;
+  if (!(ph.nu > 0) || !(ph.dt > 0)) return fail(CHAN_EINVAL, "viscosity or time step");
   double ypn = 0.0;
   const int js = sensing_node(d, ph.nu, grid->obs_y_plus, &ypn);
-  if (js < 0 || js >= d.N) return CHAN_EINVAL;
+  if (js < 0 || js >= d.N) return fail(CHAN_EINVAL, "sensing plane not inside the channel");
 
   HostTables ht;
   try {

@@ -63,7 +63,10 @@ def test_grid_validation_and_footprint():
                 b.ChanGrid(16, 49, 16, 2.67, 0.8, 180.0, 0.05, 15.0),   # unsupported ny
                 b.ChanGrid(16, 65, 16, 2.67, 0.8, -1.0, 0.05, 15.0),    # re_tau
                 b.ChanGrid(16, 65, 16, 2.67, 0.8, 180.0, 0.0, 15.0),    # dt
-                b.ChanGrid(16, 65, 16, 0.0, 0.8, 180.0, 0.05, 15.0)]:   # lx
+                b.ChanGrid(16, 65, 16, 0.0, 0.8, 180.0, 0.05, 15.0),    # lx
+                b.ChanGrid(16, 65, 16, 2.67, 0.8, 180.0, 0.05, 500.0),  # sensing plane above the top wall
+                b.ChanGrid(256, 65, 16, 2.67, 0.8, 180.0, 0.05, 15.0),  # no plane-pass size for nx
+                b.ChanGrid(16, 65, 16, 2.67, 0.8, float("nan"), 0.05, 15.0)]:
         assert b.chan_env_footprint_bytes(bad) == 0
     o = b.chan_opts_default()
     assert o.clip == 1.0 and o.opp_alpha == 1.0 and o.obs_mask == 3
