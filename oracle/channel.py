@@ -22,6 +22,13 @@ paper's solver is built on, named where used):
   value at the lower wall (§3.2: control by a wall-normal velocity).
 * Constant flow rate: a pressure gradient chosen every stage so that the bulk
   velocity stays at U_b.
+* Geometry: the closed channel (walls at y = -1 and y = +1, half-height h = 1)
+  or the open channel of the paper's setup (§3.1: a wall at the bottom, a
+  free-slip surface at height h = 1 on top).  Both are discretised on the
+  Chebyshev variable xi in [-1, 1]; the physical wall-normal coordinate is
+  y = xi (closed) or y = (1 + xi)/2 (open), so d/dy = s d/dxi with s = 1 or 2.
+  At a free-slip surface du/dy = dw/dy = 0 and v = 0, hence (continuity)
+  d^2v/dy^2 = 0 and d omega_y / dy = 0.
 * Control boundary condition at the lower wall y = -1 (§3.2): clipped to
   [-clip, clip] u_tau, zero net mass flux (the (0, 0) mode of v_w is zero,
   §4.1), ramped linearly from the old action to the new one over the
@@ -103,8 +110,8 @@ class Setup:
             raise ValueError("nx, nz must be positive multiples of 4")
         if cfg.ny < 5 or cfg.ny % 2 == 0:
             raise ValueError("ny must be odd and >= 5")
-        if cfg.top_bc != TOP_WALL:
-            raise ValueError("only the closed channel (walls at y = +-1) is implemented")
+        if cfg.top_bc not in (TOP_WALL, TOP_FREESLIP):
+            raise ValueError("top_bc must be TOP_WALL or TOP_FREESLIP")
         self.cfg = cfg
         self.nx, self.ny, self.nz = cfg.nx, cfg.ny, cfg.nz
         self.N = cfg.ny - 1
@@ -118,25 +125,42 @@ class Setup:
         q = np.arange(cfg.nz)
         self.active = (self.k2 > 0) & (q[:, None] != cfg.nz // 2)
         N = self.N
-        self.y = cheb.nodes(N)
+        self.open = cfg.top_bc == TOP_FREESLIP
+        # d/dy = s d/dxi: y = xi (closed channel) or y = (1 + xi)/2 (open channel)
+        self.s = 2.0 if self.open else 1.0
+        self.y = cheb.nodes(N)  # the Chebyshev variable xi at the nodes
         self.C = cheb.forward_matrix(N)
         self.B = cheb.inverse_matrix(N)
-        self.D = cheb.derivative_matrix(N)
-        self.D2 = cheb.second_derivative_matrix(N)
+        # derivatives with respect to the physical y
+        self.D = self.s * cheb.derivative_matrix(N)
+        self.D2 = self.s ** 2 * cheb.second_derivative_matrix(N)
         self.top_val = cheb.value_row(N, +1)
         self.bot_val = cheb.value_row(N, -1)
-        self.top_slope = cheb.slope_row(N, +1)
-        self.bot_slope = cheb.slope_row(N, -1)
+        self.top_slope = self.s * cheb.slope_row(N, +1)
+        self.bot_slope = self.s * cheb.slope_row(N, -1)
+        self.top_curv = self.top_val @ self.D2  # d^2/dy^2 at the top
+        # integral over xi; the bulk velocity is its half in both geometries
+        # (closed: int_{-1}^{1} dy / 2; open: int_0^1 dy = int dxi / 2)
         self.intw = cheb.integral_weights(N)
-        self.js = observation_node(self.y, 1.0 / self.nu, cfg.obs_y_plus)
-        self.y_plus_node = (1.0 + self.y[self.js]) / self.nu
+        self.wall_dist = (1.0 + self.y) / self.s  # distance from the lower wall
+        self.js = observation_node(self.wall_dist, 1.0 / self.nu, cfg.obs_y_plus)
+        self.y_plus_node = self.wall_dist[self.js] / self.nu
+
+    def helmholtz(self, lam, f, g_top, g_bot, top="dirichlet"):
+        """Solve (d^2/dy^2 - lam) X = f with X(bottom) = g_bot and, at the top,
+        X = g_top (``top`` "dirichlet") or dX/dy = g_top ("neumann").  In xi this
+        is (D_xi^2 - lam/s^2) X = f/s^2 with dX/dxi = g_top/s."""
+        s2 = self.s ** 2
+        gt = g_top / self.s if top == "neumann" else g_top
+        return tau_solve(self.N, np.asarray(lam) / s2, np.asarray(f) / s2, gt, g_bot,
+                         bc=(top, "dirichlet"))
 
 
-def observation_node(y, inv_nu, y_plus):
+def observation_node(d, inv_nu, y_plus):
     """Index j of the sensing plane: the first node at or above y_s^+
-    measured from the lower wall, i.e. the smallest wall distance
-    d_j = 1 + y_j with d_j / nu >= y_s^+ (§3.2, "rounded up")."""
-    d = 1.0 + y
+    measured from the lower wall, i.e. the smallest wall distance d_j
+    (1 + xi_j closed, (1 + xi_j)/2 open) with d_j / nu >= y_s^+ (§3.2,
+    "rounded up")."""
     ok = np.nonzero(d * inv_nu >= y_plus)[0]
     if len(ok) == 0:
         raise ValueError("observation height above the channel")
@@ -301,26 +325,29 @@ def stage(S: Setup, st: State, r: int, hist, vw):
     rhs_om = (-om * lam0 - (a_r / b_r) * L(om, k2a)
               - (g_r * hg[act] + z_r * hg_p[act]) / (b_r * nu))
 
-    # Particular solutions: phi_p with phi_p(+-1) = 0, omega with omega(+-1) = 0,
-    # then v_p from (D^2 - k^2) v_p = phi_p, v_p(+1) = 0, v_p(-1) = v_w.
-    phi_p = tau_solve(N, lam, rhs_phi, 0.0, 0.0)
-    om_new = tau_solve(N, lam, rhs_om, 0.0, 0.0)
-    v_p = tau_solve(N, k2a, phi_p, 0.0, vw[act])
+    # Particular solutions: phi_p with phi_p(+-1) = 0, omega with omega(-1) = 0 and
+    # omega(+1) = 0 (wall) or d omega/dy (+1) = 0 (free slip), then v_p from
+    # (D^2 - k^2) v_p = phi_p, v_p(+1) = 0, v_p(-1) = v_w.
+    phi_p = S.helmholtz(lam, rhs_phi, 0.0, 0.0)
+    om_new = S.helmholtz(lam, rhs_om, 0.0, 0.0, top="neumann" if S.open else "dirichlet")
+    v_p = S.helmholtz(k2a, phi_p, 0.0, vw[act])
     # Homogeneous solutions (influence matrix, Kim, Moin & Moser 1987):
     # phi_+- solve (D^2 - lam) phi = 0 with phi(+-1) = 1, phi(-+1) = 0, and
     # v_+- solve (D^2 - k^2) v = phi_+- with v(+-1) = 0.
     zero = np.zeros((k2a.size, S.ny))
-    phi_t = tau_solve(N, lam, zero, 1.0, 0.0)
-    phi_b = tau_solve(N, lam, zero, 0.0, 1.0)
-    v_t = tau_solve(N, k2a, phi_t, 0.0, 0.0)
-    v_b = tau_solve(N, k2a, phi_b, 0.0, 0.0)
-    # 2x2 influence matrix: choose c so that Dv(+1) = Dv(-1) = 0.
+    phi_t = S.helmholtz(lam, zero, 1.0, 0.0)
+    phi_b = S.helmholtz(lam, zero, 0.0, 1.0)
+    v_t = S.helmholtz(k2a, phi_t, 0.0, 0.0)
+    v_b = S.helmholtz(k2a, phi_b, 0.0, 0.0)
+    # 2x2 influence matrix: choose c so that Dv(-1) = 0 and, at the top, Dv(+1) = 0
+    # (wall) or D^2 v(+1) = 0 (free slip).
+    top = S.top_curv if S.open else S.top_slope
     M = np.empty((k2a.size, 2, 2))
-    M[:, 0, 0] = v_t @ S.top_slope
-    M[:, 0, 1] = v_b @ S.top_slope
+    M[:, 0, 0] = v_t @ top
+    M[:, 0, 1] = v_b @ top
     M[:, 1, 0] = v_t @ S.bot_slope
     M[:, 1, 1] = v_b @ S.bot_slope
-    g = -np.stack([v_p @ S.top_slope, v_p @ S.bot_slope], axis=-1)
+    g = -np.stack([v_p @ top, v_p @ S.bot_slope], axis=-1)
     c = np.linalg.solve(M, np.stack([g.real, g.imag], axis=-1))
     c = c[..., 0] + 1j * c[..., 1]
     v_new = v_p + c[:, 0, None] * v_t + c[:, 1, None] * v_b
@@ -335,19 +362,21 @@ def stage(S: Setup, st: State, r: int, hist, vw):
 
     # Mean flow.  U^r = U* + P^r U_P where U_P carries the stage's share
     # (a_r + b_r) dt of a unit pressure gradient; constant flow rate picks P^r
-    # so that int U^r dy = 2 U_b, constant pressure gradient uses P^r = P_x.
+    # so that int U^r dxi = 2 U_b, constant pressure gradient uses P^r = P_x.
+    # U = W = 0 at the wall(s); dU/dy = dW/dy = 0 at a free-slip top.
+    top_mean = "neumann" if S.open else "dirichlet"
     rhs_u = -st.ubar * lam0 - (a_r / b_r) * (S.D2 @ st.ubar) - (g_r * hu + z_r * hu_p) / (b_r * nu)
     rhs_w = -st.wbar * lam0 - (a_r / b_r) * (S.D2 @ st.wbar) - (g_r * hw + z_r * hw_p) / (b_r * nu)
-    ustar = tau_solve(N, lam0, rhs_u, 0.0, 0.0)
+    ustar = S.helmholtz(lam0, rhs_u, 0.0, 0.0, top=top_mean)
     forcing = np.zeros(S.ny)
     forcing[0] = -(a_r + b_r) / (b_r * nu)
-    u_P = tau_solve(N, lam0, forcing, 0.0, 0.0)
+    u_P = S.helmholtz(lam0, forcing, 0.0, 0.0, top=top_mean)
     if S.cfg.forcing == CFR:
         P = (2.0 * S.ub - S.intw @ ustar) / (S.intw @ u_P)
     else:
         P = S.cfg.px
     out.ubar = ustar + P * u_P
-    out.wbar = tau_solve(N, lam0, rhs_w, 0.0, 0.0)
+    out.wbar = S.helmholtz(lam0, rhs_w, 0.0, 0.0, top=top_mean)
     return out, (hv, hg, hu, hw)
 
 
@@ -402,12 +431,12 @@ def opposition_wall(S: Setup, st: State):
 
 
 def mean_wall_shear(S: Setup, st: State):
-    """nu dU/dy at the lower wall y = -1: the plane mean of tau_w (units rho u_tau^2)."""
+    """nu dU/dy at the lower wall: the plane mean of tau_w (units rho u_tau^2)."""
     return S.nu * (S.bot_slope @ st.ubar)
 
 
 def wall_shear_field(S: Setup, st: State):
-    """tau_w(x, z) = nu du/dy at y = -1 on the N_z x N_x grid."""
+    """tau_w(x, z) = nu du/dy at the lower wall on the N_z x N_x grid."""
     u = reconstruct(S, st)[0]
     th = S.nu * (u @ S.bot_slope)
     return fr.to_physical(th, S.nx, S.nz)

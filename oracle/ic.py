@@ -7,11 +7,16 @@ The paper starts every episode from one of six stored turbulent fields
 paper's grid and Reynolds number stands in.  Recipe (a reading, stated in
 the design doc's input recipe):
 
-* mean profile: laminar U = 1.5 U_b (1 - y^2), or the Reichardt law of the
-  wall in d^+ = min(1 + y, 1 - y) / nu scaled to the bulk flow 2 U_b;
-* perturbation on 0 < k, p <= 3, |q| <= 6:
-  v-hat = (1 - y^2)^2 sum_{m<8} c_m T_m,  omega_y-hat = (1 - y^2) sum_{m<8} d_m T_m,
-  so that v = dv/dy = omega_y = 0 at both walls; the real and imaginary parts
+* mean profile: laminar U = 1.5 U_b (1 - r^2) with r the distance from the
+  centreline of the closed channel (r = xi) or from the surface of the open
+  one (r = 1 - y = (1 - xi)/2), or the Reichardt law of the wall in d^+ = d/nu, d the
+  distance from the nearest wall, scaled to int U dxi = 2 U_b;
+* perturbation on 0 < k, p <= 3, |q| <= 6, with the envelopes E_v, E_o:
+  v-hat = E_v sum_{m<8} c_m T_m(xi),  omega_y-hat = E_o sum_{m<8} d_m T_m(xi);
+  closed channel E_v = (1 - xi^2)^2, E_o = 1 - xi^2 (v = dv/dy = omega_y = 0 at
+  both walls); open channel E_v = (1 + xi)^2 (1 - xi)^3, E_o = (1 + xi)(1 - xi)^2
+  (the wall conditions at the bottom, v = d^2v/dy^2 = d omega_y/dy = 0 at the
+  free-slip top); the real and imaginary parts
   of c_m, d_m are 2U - 1 with U = (x >> 11) 2^-53 from SplitMix64(seed)
   (Steele, Lea & Flood 2014), drawn in the loop order q (from -6 up), p,
   field (v, then omega_y), m, real part then imaginary part;
@@ -58,12 +63,13 @@ def reichardt(dplus, kappa=0.41):
 
 
 def mean_profile(S):
-    y = S.y
+    xi = S.y
     if S.cfg.ic_profile == IC_REICHARDT:
-        dplus = np.minimum(1.0 + y, 1.0 - y) / S.nu
-        a = S.C @ reichardt(dplus)
+        d = S.wall_dist if S.open else np.minimum(1.0 + xi, 1.0 - xi)
+        a = S.C @ reichardt(d / S.nu)
         return a * (2.0 * S.ub / (S.intw @ a))
-    return S.C @ (1.5 * S.ub * (1.0 - y * y))
+    r = (1.0 - xi) / 2.0 if S.open else xi
+    return S.C @ (1.5 * S.ub * (1.0 - r * r))
 
 
 def volume_rms(S, st: State):
@@ -75,7 +81,7 @@ def volume_rms(S, st: State):
         f = f.copy()
         f[0, 0] = 0.0
         g = np.abs(f @ S.B.T) ** 2            # |f-hat|^2 at the nodes
-        integ = (g @ S.C.T) @ S.intw          # int_{-1}^{1} dy, per (q, p)
+        integ = (g @ S.C.T) @ S.intw          # int_{-1}^{1} dxi, per (q, p)
         total += np.sum(mult * integ)
     return np.sqrt(total / 2.0 / 3.0)
 
@@ -84,9 +90,13 @@ def initial_state(S, seed):
     st = zero_state(S)
     st.ubar = mean_profile(S)
     rng = SplitMix64(seed)
-    y = S.y
-    env_v = (1.0 - y * y) ** 2
-    env_o = 1.0 - y * y
+    xi = S.y
+    if S.open:
+        env_v = (1.0 + xi) ** 2 * (1.0 - xi) ** 3
+        env_o = (1.0 + xi) * (1.0 - xi) ** 2
+    else:
+        env_v = (1.0 - xi * xi) ** 2
+        env_o = 1.0 - xi * xi
     Tm = S.B[:, :8]                          # T_m(y_j), m < 8
     pmax = min(3, S.nkx - 1)
     qmax = min(6, S.nz // 2 - 1)
