@@ -15,9 +15,14 @@
  * argument with the wall shear and drag outputs, TERMN -> chan_env_destroy
  * (chan_env_reset covers the restart of an episode).
  *
- * Units: lengths in the channel half-height h, velocities in the nominal
- * friction velocity u_tau, so nu = 1/Re_tau and t+ = t Re_tau.  The channel is
- * closed: walls at y = +1 and y = -1; the actuated wall is y = -1.
+ * Units: lengths in h, velocities in the nominal friction velocity u_tau, so
+ * nu = 1/Re_tau and t+ = t Re_tau.  Two geometries (§3.1):
+ *   closed channel (default): walls at y = -1 and y = +1, h the half-height;
+ *   open channel (CHAN_TOP_FREESLIP): a wall at y = 0 and a free-slip surface at
+ *   y = h = 1 (u_y = w_y = v = 0 there).
+ * The actuated wall is always the lower one.  The Chebyshev variable xi in
+ * [-1, 1] is y (closed) or 2y - 1 (open); spectral state coefficients are those
+ * of T_n(xi), and node j is xi_j = cos(pi j / N) in both.
  *
  * Layouts.  Wall planes are row-major [z][x] with x fastest, on the grid
  * x_i = i Lx/nx, z_k = k Lz/nz.  Spectral arrays are [q][p] with
@@ -59,20 +64,21 @@ enum { CHAN_OBS_U = 1, CHAN_OBS_V = 2, CHAN_OBS_W = 4 };
 /* Grid and physical parameters (§3.1: N_x x N_y x N_z modes, Re_tau; §3.2:
  * sensing height).  Supported: nx, nz in {4, 8, 16, 32, 64, 128};
  * ny in {17, 33, 65, 97, 129}; re_tau > 0; dt_plus > 0; obs_y_plus > 0 and
- * below the node next to the upper wall. */
+ * below the node next to the top (wall or surface). */
 typedef struct {
   int32_t nx, ny, nz;   /* Fourier modes in x, Chebyshev modes in y, Fourier modes in z */
   double lx, lz;        /* box lengths in h (minimal channel 2.67 x 0.8, larger 2 pi x pi) */
   double re_tau;        /* nominal friction Reynolds number; nu = 1/re_tau unless overridden */
   double dt_plus;       /* one substep = one full RK3/CN time step of dt = dt_plus/re_tau */
-  double obs_y_plus;    /* sensing height above y = -1 in viscous units; rounded UP to a
+  double obs_y_plus;    /* sensing height above the lower wall in viscous units; rounded UP to a
                            Chebyshev node (§3.2); chan_env_query reports the node used */
 } chan_grid_t;
 
 /* Options; passing NULL to chan_env_create selects the defaults in brackets. */
 typedef struct {
-  int32_t top_bc;       /* [CHAN_TOP_WALL]; CHAN_TOP_FREESLIP (the paper's open channel)
-                           is not implemented and returns CHAN_EINVAL */
+  int32_t top_bc;       /* [CHAN_TOP_WALL] closed channel | CHAN_TOP_FREESLIP open channel
+                           (the paper's geometry); the open channel needs ny <= 65 and
+                           returns CHAN_EINVAL otherwise */
   int32_t forcing;      /* [CHAN_CFR] constant flow rate | CHAN_CPG constant pressure gradient */
   double ub_plus;       /* [<= 0: 15.66 (re_tau/180)^(1/7)] bulk velocity held by CFR */
   double px;            /* [0] pressure gradient for CPG */
@@ -90,7 +96,7 @@ typedef struct {
 /* Derived quantities, filled by chan_env_query. */
 typedef struct {
   int32_t nx, ny, nz, js;      /* js: index of the sensing node, y_js = cos(pi js/(ny-1)) */
-  double y_plus_node;          /* (1 + y_js) / nu: the sensing height actually used */
+  double y_plus_node;          /* wall distance of node js / nu: the sensing height used */
   double nu, dt, ub;           /* viscosity, time step, bulk velocity */
   double t;                    /* simulated time since reset (units h/u_tau) */
   int64_t nstep;               /* time steps since reset */

@@ -37,6 +37,8 @@ struct TableLayout {
   // parity-major copies for the column kernel with N <= 64 (one lane per coefficient:
   // even n = 2l in lanes l < 32, odd n = 2i + 1 in lanes 32 + i, n = N as a 65th "tail" entry)
   size_t kfwd, kinv, rc_pm, intw_pm, op_pm, vt_pm, up_pm;
+  // open channel only: phi_+ of every pair and stage (parity-major) and 1/(dphi_+/dxi)(+1)
+  size_t pt_pm, ptinv;
   size_t total;
 };
 
@@ -56,6 +58,12 @@ struct PhysParams {
   int forcing;
   double px;
   double lx, lz;
+  // geometry: closed channel (walls at y = +-1) or open channel (wall at y = 0, free-slip
+  // surface at y = 1); the Chebyshev variable is xi = y or xi = 2y - 1, d/dy = ys d/dxi
+  int open;
+  double ys;
+  // the viscosity seen in the Chebyshev variable: nu ys^2
+  double nu_xi() const { return nu * ys * ys; }
 };
 
 void precompute_tables(const Dims& d, const PhysParams& ph, HostTables* out);
@@ -77,7 +85,7 @@ struct DeviceState {
   int *status;                  // [1]
   // views into tab
   const double *cosk, *rc, *optab, *vt, *minv, *up, *inv_int_up, *alpha, *beta;
-  const double *kfwd, *kinv, *rc_pm, *intw_pm, *op_pm, *vt_pm, *up_pm;
+  const double *kfwd, *kinv, *rc_pm, *intw_pm, *op_pm, *vt_pm, *up_pm, *pt_pm, *ptinv;
   const cplx *twz, *twx, *twnx, *twnz;
 };
 
@@ -105,8 +113,13 @@ struct ColChan {
   int ext;                      // 1: external action (ramped or held wall velocity); 0: opposition
   int hold;                     // external action held for the whole env step
   int forcing, js;
-  double lam0[3], ab[3], gb[3], zb[3];  // per RK stage: 1/(b nu dt), a/b, g/(b nu), z/(b nu)
-  double nu, opp_alpha, ub2, px;
+  int open;                     // free-slip top (open channel)
+  // per RK stage: 1/(b nu' dt), a/b, g/(b nu'), z/(b nu') with nu' = nu ys^2, the viscosity
+  // in the Chebyshev variable
+  double lam0[3], ab[3], gb[3], zb[3];
+  double nu_wall;               // nu ys: wall shear = nu_wall d/dxi
+  double ys, ysi;               // d/dy = ys d/dxi; ysi = 1/ys (both powers of two)
+  double opp_alpha, ub2, px;
   size_t plane;                 // elements per field in F6 / H3 (ny nkx nz)
   gptr<cplx> vS, oS, hist;
   gptr<double> meanS, meanH;
@@ -115,6 +128,7 @@ struct ColChan {
   gptr<const cplx> vw_old, vw_new;
   gptr<cplx> vw_opp, tauw;
   gptr<const double> kfwd, kinv, rc_pm, intw_pm, op_pm, vt_pm, up_pm, minv, inv_int_up, alpha, beta;
+  gptr<const double> pt_pm, ptinv;
   gptr<double> drag_acc;
   gptr<int> status;
 };

@@ -25,6 +25,15 @@
 // 2x2 influence correction, and then prepares the next stage: reconstruction of
 // (u, v, w, omega_x, omega_y, omega_z) and their inverse DCT-I.  The (0, 0) pair solves
 // the mean flow with the constant-flow-rate pressure gradient.
+//
+// Geometry: every operator acts on the Chebyshev variable xi, with d/dy = ys d/dxi (closed
+// channel ys = 1, open channel ys = 2).  The solve works in xi throughout: wavenumbers scaled
+// by 1/ys, the explicit term h_v scaled by 1/ys^2 (phi is carried as (D_xi^2 - k^2/ys^2) v),
+// the stage constants built with the viscosity nu ys^2.  The reconstruction returns physical
+// y-derivatives.  ys is a power of two, so all these scalings are exact.  In the open channel
+// the influence correction imposes d^2v/dxi^2 = 0 at the surface instead of dv/dxi = 0, and
+// omega_y and the mean flow are corrected with the top-unit homogeneous solution phi_+ so
+// that their xi-derivative vanishes there.
 #include <utility>
 
 #include "device_common.h"
@@ -631,20 +640,24 @@ __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S
       iiu = A.inv_int_up[r];
     }
 
+    // wavenumbers in xi (k2s = k^2/ys^2)
+    const double als = al * A.ysi, bes = be * A.ysi;
+    const double k2s = als * als + bes * bes;
     // tau rows of the implicit stage: T[cx X - gb h - zb h'] - ab X, cx = ab k^2 - lam0
-    const double cx = ab * k2 - lam0;
+    const double cx = ab * k2s - lam0;
     auto comb = [&](cplx x, cplx h, cplx hp) { return caxpy(caxpy(cscale(x, cx), -gb, h), -zb, hp); };
     if (!mean) {
       // explicit terms: h_v = -k^2 H2 - D(i al H1 + i be H3), h_g = i be H1 - i al H3
-      const cplx T = cmuli(make_double2(al * hc[0].x + be * hc[2].x, al * hc[0].y + be * hc[2].y));
-      const cplx Tt = cmuli(make_double2(al * hct[0].x + be * hct[2].x, al * hct[0].y + be * hct[2].y));
+      // (h_v / ys^2 in xi: the wavenumbers of the D term and k^2 are the scaled ones)
+      const cplx T = cmuli(make_double2(als * hc[0].x + bes * hc[2].x, als * hc[0].y + bes * hc[2].y));
+      const cplx Tt = cmuli(make_double2(als * hct[0].x + bes * hct[2].x, als * hct[0].y + bes * hct[2].y));
       // phi0 = (D^2 - k^2) v, independent of the explicit terms
       const cplx dv = cheb_d<N>(L, x0, x0t);
       const cplx dT = cheb_d<N>(L, T, Tt);
       const cplx d2v = cheb_d<N>(L, dv, cz());
-      const cplx phi0 = caxpy(d2v, -k2, x0), phi0t = cscale(x0t, -k2);
-      const cplx hv = csub(cscale(hc[1], -k2), dT);
-      const cplx hvt = cscale(hct[1], -k2);
+      const cplx phi0 = caxpy(d2v, -k2s, x0), phi0t = cscale(x0t, -k2s);
+      const cplx hv = csub(cscale(hc[1], -k2s), dT);
+      const cplx hvt = cscale(hct[1], -k2s);
       const cplx hg = cmuli(make_double2(be * hc[0].x - al * hc[2].x, be * hc[0].y - al * hc[2].y));
       const cplx hgt = cmuli(make_double2(be * hct[0].x - al * hct[2].x, be * hct[0].y - al * hct[2].y));
       if (r < 2) {
@@ -669,9 +682,13 @@ __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S
       const cplx gtop[1] = {cz()}, gbot[1] = {vw};
       cplx vp[1], vpt[1];
       tau_solve_pm<N, 1>(L, Rv, Rvt, rv, gtop, gbot, vp, vpt);
-      // influence correction: dv/dy(+-1) = 0 with v = v_p + c0 v_+ + c1 v_-
-      const double n2 = dn * dn;
-      const cplx dtop = coef_sum<N>(L, vp[0], vpt[0], n2, dN * dN);
+      // influence correction: dv/dy(-1) = 0 and, at the top, dv/dy = 0 (wall) or
+      // d^2v/dy^2 = 0 (surface), with v = v_p + c0 v_+ + c1 v_-
+      // (T_n'(1) = n^2, T_n''(1) = n^2 (n^2 - 1)/3, an exact integer)
+      const double n2 = dn * dn, N2 = dN * dN;
+      const double wtop = A.open ? n2 * (n2 - 1.0) / 3.0 : n2;
+      const double wtopt = A.open ? N2 * (N2 - 1.0) / 3.0 : N2;
+      const cplx dtop = coef_sum<N>(L, vp[0], vpt[0], wtop, wtopt);
       const cplx dbot = coef_sum<N>(L, vp[0], vpt[0], -L.sgn() * n2, -dN * dN);
       const cplx c0 = make_double2(-(mi0 * dtop.x + mi1 * dbot.x), -(mi0 * dtop.y + mi1 * dbot.y));
       const cplx c1 = make_double2(-(mi2 * dtop.x + mi3 * dbot.x), -(mi2 * dtop.y + mi3 * dbot.y));
@@ -680,6 +697,15 @@ __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S
       if (!L.ok) v = cz();
       om = X[1];
       omt = Xt[1];
+      if (A.open) {  // d omega_y/dxi (+1) = 0: add c phi_+
+        const double* ptab = A.pt_pm + ((size_t)c * 3 + r) * PM_ENTRIES;
+        const double pl = ptab[lane], plt = ptab[64];
+        const cplx dw = coef_sum<N>(L, om, omt, n2, N2);
+        const double pinv = A.ptinv[(size_t)c * 3 + r];
+        const cplx cw = make_double2(-dw.x * pinv, -dw.y * pinv);
+        om = caxpy(om, pl, cw);
+        omt = caxpy(omt, plt, cw);
+      }
       cplx* vout = A.vS + col;
       cplx* oout = A.oS + col;
       if (L.ok) {
@@ -723,6 +749,15 @@ __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S
       const cplx z1[1] = {cz()};
       cplx Xs[1], Xst[1];
       tau_solve_pm<N, 1>(L, R, Rt, rs, z1, z1, Xs, Xst);
+      if (A.open) {  // dU/dxi (+1) = dW/dxi (+1) = 0: add c phi_+ (k = 0)
+        const double* ptab = A.pt_pm + (size_t)r * PM_ENTRIES;
+        const double pl = ptab[lane], plt = ptab[64];
+        const cplx ds = coef_sum<N>(L, Xs[0], Xst[0], dn * dn, dN * dN);
+        const double pinv = A.ptinv[r];
+        const cplx cu = make_double2(-ds.x * pinv, -ds.y * pinv);
+        Xs[0] = caxpy(Xs[0], pl, cu);
+        Xst[0] = caxpy(Xst[0], plt, cu);
+      }
       double flux = lane_sum(iw * Xs[0].x) + iwt * Xst[0].x;
       const double P_r = (A.forcing == 0) ? (A.ub2 - flux) * iiu : A.px;
       const double U = fma(P_r, upl, Xs[0].x);
@@ -740,7 +775,7 @@ __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S
       }
       const double n2 = dn * dn;
       const double slope = lane_sum(L.ok ? (-L.sgn() * n2) * v.x : 0.0) - dN * dN * vt.x;
-      if (r == 2 && lane == 0) A.drag_acc[0] += A.nu * slope;  // drag: end of every time step
+      if (r == 2 && lane == 0) A.drag_acc[0] += A.nu_wall * slope;  // drag: end of every time step
       const bool ok = isfinite(v.x) && isfinite(v.y) && isfinite(vt.x) && isfinite(vt.y);
       if (r == 2 && __any(!ok) && lane == 0) atomicOr(A.status, STATUS_NONFINITE);
     }
@@ -765,9 +800,10 @@ __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S
   cplx tau_hat;
   if (!mean) {
     const double ik2 = 1.0 / k2;
-    const cplx dv = cheb_d<N>(L, v, vt);
-    const cplx u = cscale(cmuli(make_double2(al * dv.x - be * om.x, al * dv.y - be * om.y)), ik2);
-    const cplx w = cscale(cmuli(make_double2(be * dv.x + al * om.x, be * dv.y + al * om.y)), ik2);
+    const cplx dv = cheb_d<N>(L, v, vt);  // dv/dxi; dv/dy = ys dv/dxi
+    const double aly = al * A.ys, bey = be * A.ys;
+    const cplx u = cscale(cmuli(make_double2(aly * dv.x - be * om.x, aly * dv.y - be * om.y)), ik2);
+    const cplx w = cscale(cmuli(make_double2(bey * dv.x + al * om.x, bey * dv.y + al * om.y)), ik2);
     const cplx ut = cscale(cmuli(make_double2(-be * omt.x, -be * omt.y)), ik2);
     const cplx wt = cscale(cmuli(make_double2(al * omt.x, al * omt.y)), ik2);
     const cplx du = cheb_d<N>(L, u, ut);
@@ -778,14 +814,14 @@ __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S
     fldt[1] = vt;
     fld[2] = w;
     fldt[2] = wt;
-    fld[3] = csub(dw, cmuli(cscale(v, be)));
+    fld[3] = csub(cscale(dw, A.ys), cmuli(cscale(v, be)));
     fldt[3] = cscale(cmuli(vt), -be);
     fld[4] = om;
     fldt[4] = omt;
-    fld[5] = csub(cmuli(cscale(v, al)), du);
+    fld[5] = csub(cmuli(cscale(v, al)), cscale(du, A.ys));
     fldt[5] = cscale(cmuli(vt), al);
     const double n2 = dn * dn;
-    tau_hat = cscale(coef_sum<N>(L, u, ut, -L.sgn() * n2, -dN * dN), A.nu);
+    tau_hat = cscale(coef_sum<N>(L, u, ut, -L.sgn() * n2, -dN * dN), A.nu_wall);
   } else {
     const cplx dX = cheb_d<N>(L, v, vt);
     fld[0] = make_double2(v.x, 0.0);
@@ -793,14 +829,14 @@ __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S
     fld[1] = fldt[1] = cz();
     fld[2] = make_double2(v.y, 0.0);
     fldt[2] = make_double2(vt.y, 0.0);
-    fld[3] = make_double2(dX.y, 0.0);
+    fld[3] = make_double2(A.ys * dX.y, 0.0);
     fldt[3] = cz();
     fld[4] = fldt[4] = cz();
-    fld[5] = make_double2(-dX.x, 0.0);
+    fld[5] = make_double2(-(A.ys * dX.x), 0.0);
     fldt[5] = cz();
     const double n2 = dn * dn;
     const double slope = lane_sum(L.ok ? (-L.sgn() * n2) * v.x : 0.0) - dN * dN * vt.x;
-    tau_hat = make_double2(A.nu * slope, 0.0);
+    tau_hat = make_double2(A.nu_wall * slope, 0.0);
   }
   cplx ph[6], pht[6];
   dct_inv_pm<N, 6, CHUNK>(L, fld, fldt, A.kinv, ph, pht);

@@ -96,7 +96,7 @@ bool valid_grid(const chan_grid_t* g) {
 }
 
 bool valid_opts(const chan_opts_t* o) {
-  if (o->top_bc != CHAN_TOP_WALL) return false;
+  if (o->top_bc != CHAN_TOP_WALL && o->top_bc != CHAN_TOP_FREESLIP) return false;
   if (o->forcing != CHAN_CFR && o->forcing != CHAN_CPG) return false;
   if (o->controller != CHAN_CTRL_EXTERNAL && o->controller != CHAN_CTRL_OPPOSITION) return false;
   if (o->action_mode != CHAN_RAMP && o->action_mode != CHAN_HOLD) return false;
@@ -132,18 +132,32 @@ PhysParams make_phys(const chan_grid_t* g, const chan_opts_t* o) {
   p.px = o->px;
   p.lx = g->lx;
   p.lz = g->lz;
+  p.open = o->top_bc == CHAN_TOP_FREESLIP ? 1 : 0;
+  p.ys = p.open ? 2.0 : 1.0;
   return p;
 }
 
 // Sensing node: the first Chebyshev node at or above obs_y_plus from the lower wall.
-int sensing_node(const Dims& d, double nu, double yplus, double* node_yplus) {
+// The sensing node: the first node at or above y+ from the lower wall.  The wall distance of
+// node j is 1 + xi_j (closed channel) or (1 + xi_j)/2 (open channel).
+int sensing_node(const Dims& d, const PhysParams& ph, double yplus, double* node_yplus) {
   int js = -1;
   for (int j = 0; j <= d.N; ++j) {
-    const double dist = 1.0 + std::cos(M_PI * j / d.N);
-    if (dist / nu >= yplus) js = j;
+    const double dist = (1.0 + std::cos(M_PI * j / d.N)) / ph.ys;
+    if (dist / ph.nu >= yplus) js = j;
   }
-  if (js >= 0) *node_yplus = (1.0 + std::cos(M_PI * js / d.N)) / nu;
+  if (js >= 0) *node_yplus = (1.0 + std::cos(M_PI * js / d.N)) / ph.ys / ph.nu;
   return js;
+}
+
+// The open channel runs on the N <= 64 column kernels only.
+bool geometry_supported(const Dims& d, const PhysParams& ph, bool force_generic) {
+  return !ph.open || (d.N <= 64 && !force_generic);
+}
+
+bool generic_forced() {
+  const char* g = std::getenv("CHANENV_GENERIC_COLUMN");
+  return g && g[0] == '1';
 }
 
 struct Sizes {
@@ -168,7 +182,7 @@ Sizes buffer_sizes(const Dims& d, size_t tab_doubles) {
   return z;
 }
 
-size_t table_doubles(const Dims& d) {
+size_t table_doubles(const Dims& d, bool open) {
   // mirrors precompute_tables' layout (with per-table rounding to even counts)
   auto r2 = [](size_t n) { return (n + 1) & ~size_t(1); };
   const int NY = d.ny, H = d.N / 2;
@@ -179,6 +193,7 @@ size_t table_doubles(const Dims& d) {
   if (pm)
     t += 2 * r2((size_t)(H + 1) * 64) + r2((size_t)3 * PM_ENTRIES) + r2(PM_ENTRIES) +
          r2((size_t)d.ncol * NOPS * PM_OPSZ) + r2((size_t)d.ncol * 3 * PM_ENTRIES) + r2((size_t)3 * PM_ENTRIES);
+  if (pm && open) t += r2((size_t)d.ncol * 3 * PM_ENTRIES) + r2((size_t)d.ncol * 3);
   return t;
 }
 
@@ -211,13 +226,16 @@ ColChan make_col_chan(const chan_env* e) {
   c.hold = e->opts.action_mode == CHAN_HOLD ? 1 : 0;
   c.forcing = e->ph.forcing;
   c.js = e->js;
+  c.open = e->ph.open;
   for (int r = 0; r < 3; ++r) {
     c.lam0[r] = e->sc[r].lam0;
     c.ab[r] = e->sc[r].ab;
     c.gb[r] = e->sc[r].gb;
     c.zb[r] = e->sc[r].zb;
   }
-  c.nu = e->ph.nu;
+  c.nu_wall = e->ph.nu * e->ph.ys;
+  c.ys = e->ph.ys;
+  c.ysi = 1.0 / e->ph.ys;
   c.opp_alpha = e->opts.opp_alpha;
   c.ub2 = 2.0 * e->ph.ub;
   c.px = e->ph.px;
@@ -240,6 +258,8 @@ ColChan make_col_chan(const chan_env* e) {
   c.op_pm = (decltype(c.op_pm))(s.op_pm);
   c.vt_pm = (decltype(c.vt_pm))(s.vt_pm);
   c.up_pm = (decltype(c.up_pm))(s.up_pm);
+  c.pt_pm = (decltype(c.pt_pm))(s.pt_pm);
+  c.ptinv = (decltype(c.ptinv))(s.ptinv);
   c.minv = (decltype(c.minv))(s.minv);
   c.inv_int_up = (decltype(c.inv_int_up))(s.inv_int_up);
   c.alpha = (decltype(c.alpha))(s.alpha);
@@ -767,9 +787,10 @@ size_t chan_env_footprint_bytes(const chan_grid_t* grid, const chan_opts_t* opts
   const PhysParams ph = make_phys(grid, &o);
   if (!(ph.nu > 0) || !(ph.dt > 0)) return 0;
   double ypn = 0.0;
-  const int js = sensing_node(d, ph.nu, grid->obs_y_plus, &ypn);
+  const int js = sensing_node(d, ph, grid->obs_y_plus, &ypn);
   if (js < 0 || js >= d.N) return 0;
-  return buffer_sizes(d, table_doubles(d)).total;
+  if (!geometry_supported(d, ph, generic_forced())) return 0;
+  return buffer_sizes(d, table_doubles(d, ph.open)).total;
 }
 
 int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_stream, chan_env** out) {
@@ -782,8 +803,10 @@ int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_
   const PhysParams ph = make_phys(grid, &o);
   if (!(ph.nu > 0) || !(ph.dt > 0)) return fail(CHAN_EINVAL, "viscosity or time step");
   double ypn = 0.0;
-  const int js = sensing_node(d, ph.nu, grid->obs_y_plus, &ypn);
+  const int js = sensing_node(d, ph, grid->obs_y_plus, &ypn);
   if (js < 0 || js >= d.N) return fail(CHAN_EINVAL, "sensing plane not inside the channel");
+  if (!geometry_supported(d, ph, generic_forced()))
+    return fail(CHAN_EINVAL, "the open channel (free-slip top) needs ny <= 65 and the parity-major column kernel");
 
   HostTables ht;
   try {
@@ -791,7 +814,7 @@ int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_
   } catch (const std::bad_alloc&) {
     return CHAN_ENOMEM;
   }
-  if (ht.L.total != table_doubles(d)) return CHAN_EINVAL;
+  if (ht.L.total != table_doubles(d, ph.open)) return CHAN_EINVAL;
   for (double v : ht.data)
     if (!std::isfinite(v)) return CHAN_EINVAL;  // e.g. a singular influence matrix
 
@@ -807,17 +830,16 @@ int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_
   e->have_flow = false;
   e->poisoned = false;
   e->self = nullptr;
-  {
-    const char* g = std::getenv("CHANENV_GENERIC_COLUMN");
-    e->force_generic = g && g[0] == '1';
-  }
+  e->force_generic = generic_forced();
   e->t = 0.0;
   e->nstep = 0;
   for (int r = 0; r < 3; ++r) {
-    e->sc[r].lam0 = 1.0 / (RK_BETA[r] * ph.nu * ph.dt);
+    // in the Chebyshev variable: nu' = nu ys^2 (closed channel: nu)
+    const double nux = ph.nu_xi();
+    e->sc[r].lam0 = 1.0 / (RK_BETA[r] * nux * ph.dt);
     e->sc[r].ab = RK_ALPHA[r] / RK_BETA[r];
-    e->sc[r].gb = RK_GAMMA[r] / (RK_BETA[r] * ph.nu);
-    e->sc[r].zb = RK_ZETA[r] / (RK_BETA[r] * ph.nu);
+    e->sc[r].gb = RK_GAMMA[r] / (RK_BETA[r] * nux);
+    e->sc[r].zb = RK_ZETA[r] / (RK_BETA[r] * nux);
   }
   {
     const hipError_t err = hipGetDevice(&e->device);
@@ -885,6 +907,8 @@ int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_
   s.op_pm = s.tab + L.op_pm;
   s.vt_pm = s.tab + L.vt_pm;
   s.up_pm = s.tab + L.up_pm;
+  s.pt_pm = s.tab + L.pt_pm;
+  s.ptinv = s.tab + L.ptinv;
   {
     hipError_t err = hipMemsetAsync(e->dev_block, 0, z.total, e->stream);
     const char* what = "hipMemsetAsync";

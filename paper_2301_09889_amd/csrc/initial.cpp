@@ -2,12 +2,16 @@
 //
 // The paper starts each episode from stored turbulent fields (§3.3, §4.2) that are not
 // part of this library; a reproducible synthetic field stands in:
-//   mean:   laminar U = 1.5 U_b (1 - y^2), or Reichardt's law of the wall in
-//           d+ = min(1 + y, 1 - y)/nu scaled to the bulk flow 2 U_b;
+//   mean:   laminar U = 1.5 U_b (1 - r^2), r the distance from the closed channel's
+//           centreline (r = xi) or from the open channel's surface (r = (1 - xi)/2), or
+//           Reichardt's law of the wall in d+ = d/nu, d the distance from the nearest wall,
+//           scaled so that the integral over xi is 2 U_b;
 //   perturbation on 0 < k, p <= 3, |q| <= 6 (inside the resolved modes):
-//           v = (1 - y^2)^2 sum_{m<8} c_m T_m,   omega_y = (1 - y^2) sum_{m<8} d_m T_m,
-//           so v = dv/dy = omega_y = 0 at both walls (divergence-free by
-//           construction of the v--omega_y form); Re and Im of c_m, d_m are 2U - 1
+//           v = E_v(xi) sum_{m<8} c_m T_m(xi),   omega_y = E_o(xi) sum_{m<8} d_m T_m(xi),
+//           closed channel E_v = (1 - xi^2)^2, E_o = 1 - xi^2 (v = dv/dy = omega_y = 0 at
+//           both walls); open channel E_v = (1 + xi)^2 (1 - xi)^3, E_o = (1 + xi)(1 - xi)^2
+//           (wall conditions at the bottom; v = v'' = omega_y' = 0 at the surface);
+//           divergence-free by construction of the v--omega_y form; Re and Im of c_m, d_m are 2U - 1
 //           with U = (x >> 11) 2^-53 from SplitMix64(seed) (Steele, Lea & Flood 2014),
 //           drawn in the order q = -6..6, p, field (v, omega_y), m, Re then Im;
 //   the p = 0 column is made Hermitian (the q > 0 half is kept), and the perturbation
@@ -82,16 +86,22 @@ void initial_condition(const Dims& d, const PhysParams& ph, int profile, double 
   std::vector<double> intw(NY, 0.0);
   for (int n = 0; n <= N; n += 2) intw[n] = 2.0 / (1.0 - (double)n * n);
 
-  // mean profile
+  // mean profile (y[] holds the Chebyshev variable xi)
   std::vector<double> U(NY), Uv(NY);
   if (profile == 1) {
-    for (int j = 0; j <= N; ++j) Uv[j] = reichardt(std::fmin(1.0 + y[j], 1.0 - y[j]) / ph.nu);
+    for (int j = 0; j <= N; ++j) {
+      const double dist = ph.open ? (1.0 + y[j]) / 2.0 : std::fmin(1.0 + y[j], 1.0 - y[j]);
+      Uv[j] = reichardt(dist / ph.nu);
+    }
     dct_fwd(N, Uv.data(), U.data());
     double q = 0.0;
     for (int n = 0; n <= N; ++n) q += intw[n] * U[n];
     for (int n = 0; n <= N; ++n) U[n] *= 2.0 * ph.ub / q;
   } else {
-    for (int j = 0; j <= N; ++j) Uv[j] = 1.5 * ph.ub * (1.0 - y[j] * y[j]);
+    for (int j = 0; j <= N; ++j) {
+      const double r = ph.open ? (1.0 - y[j]) / 2.0 : y[j];
+      Uv[j] = 1.5 * ph.ub * (1.0 - r * r);
+    }
     dct_fwd(N, Uv.data(), U.data());
   }
 
@@ -115,8 +125,15 @@ void initial_condition(const Dims& d, const PhysParams& ph, int profile, double 
         for (int j = 0; j <= N; ++j) {
           cd s = 0.0;
           for (int m = 0; m < 8; ++m) s += c[m] * std::cos(M_PI * (double)((m * j) % (2 * N)) / N);
-          const double e1 = 1.0 - y[j] * y[j];
-          vals[j] = s * (field == 0 ? e1 * e1 : e1);
+          double env;
+          if (ph.open) {
+            const double bp = 1.0 + y[j], bm = 1.0 - y[j];
+            env = field == 0 ? bp * bp * (bm * bm * bm) : bp * (bm * bm);
+          } else {
+            const double e1 = 1.0 - y[j] * y[j];
+            env = field == 0 ? e1 * e1 : e1;
+          }
+          vals[j] = s * env;
         }
         dct_fwd(N, vals.data(), coef.data());
         cd* dst = (field == 0 ? v.data() : om.data()) + ((size_t)qi * nkx + p) * NY;
@@ -144,6 +161,7 @@ void initial_condition(const Dims& d, const PhysParams& ph, int profile, double 
       const cd* vp = &v[((size_t)q * nkx + p) * NY];
       const cd* op = &om[((size_t)q * nkx + p) * NY];
       deriv(N, vp, Dv.data());
+      for (int n = 0; n <= N; ++n) Dv[n] *= ph.ys;  // d/dy = ys d/dxi
       const cd I(0.0, 1.0);
       for (int n = 0; n <= N; ++n) {
         uu[n] = (I * al * Dv[n] - I * be * op[n]) / k2;

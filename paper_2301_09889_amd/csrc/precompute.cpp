@@ -19,6 +19,13 @@
 //   (v_-)_n = (-1)^n (v_+)_n, and the inverse of the 2x2 matrix of dv_+-/dy at
 //   the walls.
 // * Mean flow: the unit-pressure-gradient response U_P of each stage and 1/int U_P.
+// * Geometry: every operator acts on the Chebyshev variable xi, d/dy = ys d/dxi (ys = 1 closed
+//   channel, 2 open channel), so the Helmholtz operators are built for k^2/ys^2 and the
+//   viscosity nu ys^2.  In the open channel the influence matrix imposes d^2v/dxi^2 = 0 at
+//   the surface instead of dv/dxi = 0, and omega_y and the mean flow take d/dxi = 0 there:
+//   their Dirichlet solutions are corrected with phi_+ (the top-unit homogeneous solution),
+//   which is stored with 1/(dphi_+/dxi)(+1) for every pair and stage (the mean flow's at
+//   k = 0).
 // * FFT twiddles exp(-2 pi i k / L) for the padded and unpadded lengths, and the
 //   wavenumbers.
 #include <cmath>
@@ -173,6 +180,9 @@ void precompute_tables(const Dims& d, const PhysParams& ph, HostTables* out) {
   L.op_pm = take(pm ? (size_t)d.ncol * NOPS * PM_OPSZ : 0);
   L.vt_pm = take(pm ? (size_t)d.ncol * 3 * PM_ENTRIES : 0);
   L.up_pm = take(pm ? (size_t)3 * PM_ENTRIES : 0);
+  const bool open = pm && ph.open;
+  L.pt_pm = take(open ? (size_t)d.ncol * 3 * PM_ENTRIES : 0);
+  L.ptinv = take(open ? (size_t)d.ncol * 3 : 0);
   L.total = o;
   std::vector<double>& T = out->data;
   T.assign(L.total, 0.0);
@@ -197,45 +207,70 @@ void precompute_tables(const Dims& d, const PhysParams& ph, HostTables* out) {
     const int qs = (q < d.nz / 2) ? q : q - d.nz;
     beta[q] = (q == d.nz / 2) ? 0.0 : 2.0 * M_PI * qs / ph.lz;
   }
+  // operators in xi: nu' = nu ys^2, k'^2 = k^2 / ys^2 (exact: ys is a power of two)
+  const double nux = ph.nu_xi(), iys2 = 1.0 / (ph.ys * ph.ys);
   double lam0[3];
-  for (int r = 0; r < 3; ++r) lam0[r] = 1.0 / (RK_BETA[r] * ph.nu * ph.dt);
+  for (int r = 0; r < 3; ++r) lam0[r] = 1.0 / (RK_BETA[r] * nux * ph.dt);
+  // dX/dxi (+1) of a coefficient vector
+  auto slope_top = [&](const double* x) {
+    double a = 0.0;
+    for (int n = 0; n <= N; ++n) a += (double)n * n * x[n];
+    return a;
+  };
 
   std::vector<double> phi(NY), v(NY), zero(NY, 0.0);
   for (int c = 0; c < d.ncol; ++c) {
     const int p = c / d.nz, q = c % d.nz;
     if (q == d.nz / 2) continue;
     if (p == 0 && q > d.nz / 2) continue;
-    const double k2 = alpha[p] * alpha[p] + beta[q] * beta[q];
+    const double k2 = (alpha[p] * alpha[p] + beta[q] * beta[q]) * iys2;
     double* base = &T[L.optab + (size_t)c * NOPS * 2 * d.opsz];
     for (int r = 0; r < 3; ++r) fill_record(d, k2 + lam0[r], base + (size_t)r * 2 * d.opsz);
     fill_record(d, k2, base + (size_t)3 * 2 * d.opsz);
-    if (c == 0) continue;
     for (int r = 0; r < 3; ++r) {
+      // phi_+: (D^2 - lam) phi = 0, phi(+1) = 1, phi(-1) = 0
       host_tau_solve(d, base + (size_t)r * 2 * d.opsz, rc, zero.data(), 1.0, 0.0, phi.data());
+      if (open) {
+        for (int n = 0; n <= N; ++n) T[L.pt_pm + ((size_t)c * 3 + r) * PM_ENTRIES + pm_slot(N, n)] = phi[n];
+        T[L.ptinv + (size_t)c * 3 + r] = 1.0 / slope_top(phi.data());
+      }
+      if (c == 0) continue;
       host_tau_solve(d, base + (size_t)3 * 2 * d.opsz, rc, phi.data(), 0.0, 0.0, v.data());
-      double a = 0.0, b = 0.0;  // dv_+/dy at +1 and -1
+      // influence matrix M = [top row of v_+, of v_-; dv/dxi(-1) of v_+, of v_-], with
+      // v_- the mirror image of v_+; top row dv/dxi(+1) (wall) or d^2v/dxi^2(+1) (surface)
+      double a11 = 0.0, a12 = 0.0, a21 = 0.0, a22 = 0.0;
       for (int n = 0; n <= N; ++n) {
         const double n2 = (double)n * n;
-        a += n2 * v[n];
-        b += ((n & 1) ? n2 : -n2) * v[n];
+        const double sgn = (n & 1) ? -1.0 : 1.0;
+        const double wt = ph.open ? n2 * (n2 - 1.0) / 3.0 : n2;
+        a11 += wt * v[n];
+        a12 += wt * sgn * v[n];
+        a21 += -sgn * n2 * v[n];
+        a22 += -n2 * v[n];
       }
-      const double det = b * b - a * a;
+      const double det = a11 * a22 - a12 * a21;
       double* mi = &T[L.minv + ((size_t)c * 3 + r) * 4];
-      mi[0] = -a / det;
-      mi[1] = b / det;
-      mi[2] = -b / det;
-      mi[3] = a / det;
+      mi[0] = a22 / det;
+      mi[1] = -a12 / det;
+      mi[2] = -a21 / det;
+      mi[3] = a11 / det;
       for (int n = 0; n <= N; ++n) T[L.vt + ((size_t)c * 3 + r) * NY + n] = v[n];
     }
   }
-  // mean flow: (D^2 - lam0_r) U_P = -(a_r + b_r)/(b_r nu), U_P(+-1) = 0
+  // mean flow: (D^2 - lam0_r) U_P = -(a_r + b_r)/(b_r nu'), U_P = 0 at the wall(s); at a
+  // free-slip top dU_P/dxi = 0 (the Dirichlet solution plus a multiple of phi_+ at k = 0)
   {
     const double* base = &T[L.optab];
     std::vector<double> f(NY, 0.0);
     for (int r = 0; r < 3; ++r) {
-      f[0] = -(RK_ALPHA[r] + RK_BETA[r]) / (RK_BETA[r] * ph.nu);
+      f[0] = -(RK_ALPHA[r] + RK_BETA[r]) / (RK_BETA[r] * nux);
       double* up = &T[L.up + (size_t)r * NY];
       host_tau_solve(d, base + (size_t)r * 2 * d.opsz, rc, f.data(), 0.0, 0.0, up);
+      if (open) {
+        host_tau_solve(d, base + (size_t)r * 2 * d.opsz, rc, zero.data(), 1.0, 0.0, phi.data());
+        const double cu = -slope_top(up) / slope_top(phi.data());
+        for (int n = 0; n <= N; ++n) up[n] += cu * phi[n];
+      }
       double integ = 0.0;
       for (int n = 0; n <= N; n += 2) integ += 2.0 / (1.0 - (double)n * n) * up[n];
       T[L.inv_int_up + r] = 1.0 / integ;

@@ -1,0 +1,97 @@
+"""Open channel (free-slip top, the geometry of §3.1) on the GPU, through the C ABI: parity
+with the oracle at the stated bars (relative state difference <= 1e-12 after one time step,
+<= 1e-9 after 100), the seeded initial condition and the sensing node, and bitwise equality
+of an open channel advanced alone and in a batch with closed channels."""
+import numpy as np
+import pytest
+
+from oracle import channel as ch
+from oracle.ic import initial_state
+from synth import gaussian_action
+from tests.gpu_helpers import grid_opts, gpu_env, gpu_state, rel_state_diff, to_device
+from tests.oracle_cases import larger_channel, minimal_channel
+from tests.test_gpu_parity import run_pair
+
+pytestmark = pytest.mark.gpu
+
+OPEN = ch.TOP_FREESLIP
+
+
+def test_open_minimal_channel_opposition_one_step():
+    run_pair(minimal_channel(top_bc=OPEN, controller=ch.CTRL_OPPOSITION), 0, [None], 1, 1e-12)
+
+
+def test_open_minimal_channel_opposition_100_steps():
+    """Minimal open channel, opposition control at y+ = 15, 10 env steps x 10 time steps."""
+    cfg = minimal_channel(top_bc=OPEN, controller=ch.CTRL_OPPOSITION)
+    run_pair(cfg, 0, [None] * 10, 10, 1e-9, check_each=False)
+
+
+@pytest.mark.parametrize("shape,mode,forcing,mask", [
+    ((8, 33, 4), ch.RAMP, ch.CFR, 3),
+    ((4, 17, 8), ch.HOLD, ch.CPG, 7),
+    ((32, 33, 16), ch.RAMP, ch.CFR, 5),
+    ((16, 65, 32), ch.RAMP, ch.CPG, 2),
+])
+def test_open_external_actions_small_grids(shape, mode, forcing, mask):
+    nx, ny, nz = shape
+    cfg = ch.Config(nx=nx, ny=ny, nz=nz, lx=2.67, lz=0.8, re_tau=180.0, dt_plus=0.05,
+                    obs_y_plus=15.0, action_mode=mode, forcing=forcing, px=0.02, obs_mask=mask,
+                    ic_profile=ch.IC_REICHARDT, top_bc=OPEN)
+    acts = [gaussian_action(1000 + k, nz, nx) * 4.0 for k in range(3)]  # some values clip
+    acts[1][0, 0] = 5.0
+    run_pair(cfg, 7, acts, 2, 1e-11)
+
+
+def test_open_larger_channel_one_step():
+    run_pair(larger_channel(top_bc=OPEN), 1, [gaussian_action(1001, 64, 64)], 1, 1e-12)
+
+
+def test_open_reset_and_sensing_node():
+    for cfg, seed in [(minimal_channel(top_bc=OPEN), 3),
+                      (larger_channel(top_bc=OPEN, ic_profile=ch.IC_LAMINAR), 2)]:
+        S = ch.Setup(cfg)
+        genv = gpu_env(cfg)
+        genv.reset(seed)
+        gs = gpu_state(S, genv)
+        assert rel_state_diff(gs, initial_state(S, seed)) < 1e-13
+        info = genv.query()
+        assert info.js == S.js
+        assert abs(info.y_plus_node - S.y_plus_node) < 1e-12 * S.y_plus_node
+        genv.close()
+
+
+def test_open_and_closed_channels_in_one_batch_match_alone_bitwise():
+    import paper_2301_09889_amd.binding as b
+    specs = [(minimal_channel(top_bc=OPEN, controller=ch.CTRL_OPPOSITION), 0),
+             (minimal_channel(), 1),
+             (minimal_channel(top_bc=OPEN, ic_profile=ch.IC_REICHARDT), 2),
+             (ch.Config(nx=8, ny=33, nz=8, lx=2.67, lz=0.8, re_tau=180.0, dt_plus=0.05,
+                        obs_y_plus=15.0, top_bc=OPEN), 3)]
+
+    def make():
+        envs = []
+        for cfg, seed in specs:
+            e = b.ChanEnv(*grid_opts(cfg))
+            e.reset(seed)
+            envs.append(e)
+        return envs
+
+    alone, mixed = make(), make()
+    batch = b.ChanBatch(mixed)
+    for k in range(3):
+        acts = [None if cfg.controller == ch.CTRL_OPPOSITION else
+                to_device(gaussian_action(2000 + 10 * i + k, cfg.nz, cfg.nx))
+                for i, (cfg, _) in enumerate(specs)]
+        for e, a in zip(alone, acts):
+            e.step(a, 2)
+        assert batch.step(acts, 2) == [0] * len(specs)
+        for i, (ea, em) in enumerate(zip(alone, mixed)):
+            nd = int(np.count_nonzero(ea.get_state() != em.get_state()))
+            print(f"  env step {k}, channel {i}: state entries differing {nd}", flush=True)
+            assert nd == 0, (k, i)
+            assert np.array_equal(ea.tau_w.cpu().numpy(), em.tau_w.cpu().numpy())
+            assert ea.drag.item() == em.drag.item()
+    batch.close()
+    for e in alone + mixed:
+        e.close()
