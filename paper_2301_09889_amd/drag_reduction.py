@@ -5,11 +5,14 @@ Every case runs as one channel per seed, all advanced together in one batch:
 * uncontrolled: zero wall velocity (external controller, no action);
 * opposition control with the sensing plane at each requested y+ (alpha = 1, zero net flux).
 All channels: 64x65x64 modes, 2 pi x 2 x pi (h), Re_tau 180, dt+ 0.05, constant flow rate,
-Reichardt mean profile with the seeded perturbation.  The drag (plane-mean wall shear in wall
-units) is averaged over a window after the initial transient; DR = 1 - D_controlled /
-D_uncontrolled with the means over the seeds.
+Reichardt mean profile with the seeded perturbation; or the minimal box (16x65x16,
+2.67 x 2 x 0.8); closed channel, or with --top freeslip the open channel of §3.1 (a wall and a
+free-slip surface at height h, the box 2 pi x 1 x pi or 2.67 x 1 x 0.8).  The drag (plane-mean
+wall shear in wall units) is averaged over a window after the initial transient;
+DR = 1 - D_controlled / D_uncontrolled with the means over the seeds.
 
     python -m paper_2301_09889_amd.drag_reduction [--env-steps 6000] [--seeds 0 1 2] [--y-plus 10 15]
+        [--grid larger|minimal] [--top wall|freeslip]
 """
 import argparse
 import json
@@ -20,10 +23,11 @@ import numpy as np
 from . import binding as b
 
 LARGER = dict(nx=64, ny=65, nz=64, lx=2 * np.pi, lz=np.pi, re_tau=180.0, dt_plus=0.05)
+MINIMAL = dict(nx=16, ny=65, nz=16, lx=2.67, lz=0.8, re_tau=180.0, dt_plus=0.05)
 
 
 def run(y_plus=(10.0, 15.0), seeds=(0, 1, 2), n_env=6000, n_sub=10, window_start=1000, grid=LARGER,
-        progress=None):
+        progress=None, top_bc=b.CHAN_TOP_WALL):
     """Drag histories and drag reduction.  Returns a dict with, per case, the per-seed window
     means, their mean, and DR against the uncontrolled case."""
     import torch
@@ -34,7 +38,7 @@ def run(y_plus=(10.0, 15.0), seeds=(0, 1, 2), n_env=6000, n_sub=10, window_start
         for s in seeds:
             g = b.ChanGrid(grid["nx"], grid["ny"], grid["nz"], grid["lx"], grid["lz"], grid["re_tau"],
                            grid["dt_plus"], yp)
-            e = b.ChanEnv(g, b.make_opts(controller=ctrl, ic_profile=1))
+            e = b.ChanEnv(g, b.make_opts(controller=ctrl, ic_profile=1, top_bc=top_bc))
             e.reset(s)
             envs.append(e)
             labels.append((name, s))
@@ -56,7 +60,8 @@ def run(y_plus=(10.0, 15.0), seeds=(0, 1, 2), n_env=6000, n_sub=10, window_start
         batch.close()
         for e in envs:
             e.close()
-    out = {"window_env_steps": [window_start, n_env], "t_plus_per_env_step": n_sub * grid["dt_plus"],
+    out = {"grid": [grid["nx"], grid["ny"], grid["nz"]], "top_bc": top_bc,
+           "window_env_steps": [window_start, n_env], "t_plus_per_env_step": n_sub * grid["dt_plus"],
            "seeds": list(seeds), "cases": {}}
     for name, _, _ in cases:
         w = [float(h[i, window_start:].mean()) for i, (nm, _) in enumerate(labels) if nm == name]
@@ -75,9 +80,13 @@ def main():
     ap.add_argument("--window-start", type=int, default=1000)
     ap.add_argument("--seeds", type=int, nargs="+", default=[0, 1, 2])
     ap.add_argument("--y-plus", type=float, nargs="+", default=[10.0, 15.0])
+    ap.add_argument("--grid", choices=["larger", "minimal"], default="larger")
+    ap.add_argument("--top", choices=["wall", "freeslip"], default="wall")
     ap.add_argument("--histories", help="write the drag histories (JSON) to this file")
     args = ap.parse_args()
     res = run(args.y_plus, args.seeds, args.env_steps, window_start=args.window_start,
+              grid=LARGER if args.grid == "larger" else MINIMAL,
+              top_bc=b.CHAN_TOP_FREESLIP if args.top == "freeslip" else b.CHAN_TOP_WALL,
               progress=lambda k, t: print(f"env step {k} ({t:.0f} s)", flush=True))
     hist = res.pop("histories")
     if args.histories:

@@ -3,19 +3,21 @@ uncontrolled drag is close to 1 in wall units (tau_w = rho u_tau^2 at the nomina
 opposition control with the sensing plane at y+ 10 and 15 reduces it by the amount the
 literature and the paper report (§4.1: about 18 % at y+ 10, 20-25 % at y+ 15).  Two seeds per
 case, t+ 2000, averaged over t+ 500-2000.  The bounds are physical, not round-off: they leave
-room for the statistical spread of two seeds."""
+room for the statistical spread of two seeds.  Both geometries: the closed channel, and the
+open channel of §3.1 (free-slip surface at height h), the paper's own setup."""
 import pytest
 
 pytestmark = pytest.mark.gpu
 
 
-def test_opposition_control_reduces_drag():
+@pytest.mark.parametrize("top_bc", [0, 1], ids=["closed", "open"])
+def test_opposition_control_reduces_drag(top_bc):
     from paper_2301_09889_amd.drag_reduction import run
-    res = run(y_plus=(10.0, 15.0), seeds=(0, 1), n_env=4000, window_start=1000)
+    res = run(y_plus=(10.0, 15.0), seeds=(0, 1), n_env=4000, window_start=1000, top_bc=top_bc)
     for name, c in res["cases"].items():
         print(f"  {name:18s} drag {c['mean']:.4f} per seed {[round(x, 4) for x in c['window_mean_per_seed']]} "
               f"DR {c['drag_reduction']:+.3f}", flush=True)
     cases = res["cases"]
     assert 0.93 < cases["uncontrolled"]["mean"] < 1.07
     assert 0.12 < cases["opposition y+10"]["drag_reduction"] < 0.25
-    assert 0.14 < cases["opposition y+15"]["drag_reduction"] < 0.28
+    assert 0.14 < cases["opposition y+15"]["drag_reduction"] < 0.30
