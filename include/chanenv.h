@@ -60,6 +60,9 @@ enum { CHAN_CTRL_EXTERNAL = 0, CHAN_CTRL_OPPOSITION = 1 };
 enum { CHAN_RAMP = 0, CHAN_HOLD = 1 };
 enum { CHAN_IC_LAMINAR = 0, CHAN_IC_REICHARDT = 1 };
 enum { CHAN_OBS_U = 1, CHAN_OBS_V = 2, CHAN_OBS_W = 4 };
+/* Observation planes: the sensing plane of chan_grid_t plus up to CHAN_MAX_EXTRA_PLANES more
+ * (§3.2: the observed state is one or more wall-parallel planes). */
+enum { CHAN_MAX_EXTRA_PLANES = 3 };
 
 /* Grid and physical parameters (§3.1: N_x x N_y x N_z modes, Re_tau; §3.2:
  * sensing height).  Supported: nx, nz in {4, 8, 16, 32, 64, 128};
@@ -91,6 +94,10 @@ typedef struct {
   uint32_t obs_mask;    /* [CHAN_OBS_U | CHAN_OBS_V] observed components (§3.2, §4.2) */
   int32_t ic_profile;   /* [CHAN_IC_LAMINAR] mean profile of chan_env_reset | CHAN_IC_REICHARDT */
   double ic_amp;        /* [0.1] rms of the reset perturbation as a fraction of U_cl = 1.5 U_b */
+  int32_t n_extra_planes;  /* [0] further observation planes, 0 .. CHAN_MAX_EXTRA_PLANES */
+  double extra_obs_y_plus[CHAN_MAX_EXTRA_PLANES];  /* their heights above the lower wall in
+                           viscous units, each rounded up to a node like obs_y_plus; observed
+                           with the same obs_mask components */
 } chan_opts_t;
 
 /* Derived quantities, filled by chan_env_query. */
@@ -101,8 +108,11 @@ typedef struct {
   double t;                    /* simulated time since reset (units h/u_tau) */
   int64_t nstep;               /* time steps since reset */
   size_t state_doubles;        /* length of the get/set_state buffer */
-  size_t obs_doubles;          /* popcount(obs_mask) * nz * nx */
+  size_t obs_doubles;          /* (1 + n_extra_planes) * popcount(obs_mask) * nz * nx */
   size_t footprint_bytes;      /* device memory held by the env */
+  int32_t n_planes;            /* observation planes: 1 + n_extra_planes */
+  int32_t js_planes[1 + CHAN_MAX_EXTRA_PLANES];      /* node of each plane (js first) */
+  double y_plus_planes[1 + CHAN_MAX_EXTRA_PLANES];   /* its wall distance / nu */
 } chan_info_t;
 
 /* Fill *opts with the defaults listed above. */
@@ -137,10 +147,11 @@ int chan_env_reset(struct chan_env* env, uint64_t seed);
  *           CHAN_CTRL_OPPOSITION, where v_w = -alpha (v(y_s) - <v(y_s)>) is
  *           evaluated at the start of every time step.
  *   n_substeps  number of RK3/CN time steps, >= 1.
- *   obs     DEVICE pointer, popcount(obs_mask)*nz*nx doubles: u, v, w (in that
- *           order, selected by obs_mask) at the sensing node, end of the step.
- *           May be NULL.
- *   tau_w   DEVICE pointer, nz*nx doubles: nu du/dy at y = -1, end of step.  May be NULL.
+ *   obs     DEVICE pointer, n_planes*popcount(obs_mask)*nz*nx doubles, layout
+ *           [plane][component][z][x]: u, v, w (in that order, selected by obs_mask)
+ *           at the sensing node, then at each extra observation plane, end of the
+ *           step.  May be NULL.
+ *   tau_w   DEVICE pointer, nz*nx doubles: nu du/dy at the lower wall, end of step.  May be NULL.
  *   drag    DEVICE pointer, 1 double: mean over the n_substeps time steps of the
  *           plane-averaged lower-wall shear stress, sampled after each step
  *           (the reward's input, §3.2).  May be NULL.

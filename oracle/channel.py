@@ -36,7 +36,8 @@ paper's solver is built on, named where used):
   controller: v_w = -alpha (v(y_s) - <v(y_s)>).
 * Observation: velocity components on the wall-parallel plane at the first
   Chebyshev node at or above y_s^+ (§3.2 "rounded up to the closest Chebyshev
-  colocation node").  Wall-shear stress at the lower wall, and the drag as
+  colocation node"), and on further planes chosen the same way (§3.2: one or
+  more wall-parallel planes).  Wall-shear stress at the lower wall, and the drag as
   its plane mean averaged over the time steps between two actions (§3.2).
 
 Readings where the paper is silent are listed in the design doc's table of
@@ -91,6 +92,7 @@ class Config:
     obs_mask: int = 3
     ic_profile: int = IC_LAMINAR
     ic_amp: float = 0.1
+    extra_obs_y_plus: tuple = ()
 
 
 def default_bulk_velocity(re_tau):
@@ -145,6 +147,9 @@ class Setup:
         self.wall_dist = (1.0 + self.y) / self.s  # distance from the lower wall
         self.js = observation_node(self.wall_dist, 1.0 / self.nu, cfg.obs_y_plus)
         self.y_plus_node = self.wall_dist[self.js] / self.nu
+        # observation planes: the sensing plane first, then the extra ones in order
+        self.js_planes = [self.js] + [observation_node(self.wall_dist, 1.0 / self.nu, yp)
+                                      for yp in cfg.extra_obs_y_plus]
 
     def helmholtz(self, lam, f, g_top, g_bot, top="dirichlet"):
         """Solve (d^2/dy^2 - lam) X = f with X(bottom) = g_bot and, at the top,
@@ -443,13 +448,15 @@ def wall_shear_field(S: Setup, st: State):
 
 
 def observation(S: Setup, st: State):
-    """Selected velocity components (bit 0 u, bit 1 v, bit 2 w) at node j_s,
-    each on the N_z x N_x grid, stacked in that order."""
+    """Selected velocity components (bit 0 u, bit 1 v, bit 2 w) on each
+    observation plane (node j_s first, then the extra planes), each on the
+    N_z x N_x grid, stacked plane by plane and in that order within a plane."""
     fields = reconstruct(S, st)
     comps = []
-    for bit, f in ((1, fields[0]), (2, fields[1]), (4, fields[2])):
-        if S.cfg.obs_mask & bit:
-            comps.append(fr.to_physical(values_at_node(S, f, S.js), S.nx, S.nz))
+    for j in S.js_planes:
+        for bit, f in ((1, fields[0]), (2, fields[1]), (4, fields[2])):
+            if S.cfg.obs_mask & bit:
+                comps.append(fr.to_physical(values_at_node(S, f, j), S.nx, S.nz))
     return np.stack(comps) if comps else np.zeros((0, S.nz, S.nx))
 
 

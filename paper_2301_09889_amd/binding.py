@@ -39,7 +39,8 @@ class ChanOpts(ctypes.Structure):
                 ("controller", ctypes.c_int32), ("opp_alpha", ctypes.c_double),
                 ("action_mode", ctypes.c_int32), ("clip", ctypes.c_double),
                 ("obs_mask", ctypes.c_uint32), ("ic_profile", ctypes.c_int32),
-                ("ic_amp", ctypes.c_double)]
+                ("ic_amp", ctypes.c_double), ("n_extra_planes", ctypes.c_int32),
+                ("extra_obs_y_plus", ctypes.c_double * 3)]
 
 
 class ChanInfo(ctypes.Structure):
@@ -47,7 +48,9 @@ class ChanInfo(ctypes.Structure):
                 ("js", ctypes.c_int32), ("y_plus_node", ctypes.c_double), ("nu", ctypes.c_double),
                 ("dt", ctypes.c_double), ("ub", ctypes.c_double), ("t", ctypes.c_double),
                 ("nstep", ctypes.c_int64), ("state_doubles", ctypes.c_size_t),
-                ("obs_doubles", ctypes.c_size_t), ("footprint_bytes", ctypes.c_size_t)]
+                ("obs_doubles", ctypes.c_size_t), ("footprint_bytes", ctypes.c_size_t),
+                ("n_planes", ctypes.c_int32), ("js_planes", ctypes.c_int32 * 4),
+                ("y_plus_planes", ctypes.c_double * 4)]
 
 
 class ChanError(RuntimeError):
@@ -263,10 +266,20 @@ def make_grid(nx, ny, nz, lx, lz, re_tau, dt_plus, obs_y_plus):
 
 
 def make_opts(**kw):
+    """chan_opts_t with the defaults, then the given fields; ``extra_obs_y_plus`` takes a sequence
+    of heights and sets ``n_extra_planes`` to its length."""
     o = chan_opts_default()
     for k, v in kw.items():
         if not hasattr(o, k):
             raise KeyError(k)
+        if k == "extra_obs_y_plus":
+            v = list(v)
+            if len(v) > len(o.extra_obs_y_plus):
+                raise ValueError(f"at most {len(o.extra_obs_y_plus)} extra observation planes")
+            for i, y in enumerate(v):
+                o.extra_obs_y_plus[i] = float(y)
+            o.n_extra_planes = len(v)
+            continue
         setattr(o, k, v)
     return o
 
@@ -299,7 +312,7 @@ class ChanEnv:
         self.handle = chan_env_create(grid, self.opts, self.stream.cuda_stream)
         self.info = chan_env_query(self.handle)
         dev = torch.device("cuda", torch.cuda.current_device())
-        nobs = bin(self.opts.obs_mask).count("1")
+        nobs = bin(self.opts.obs_mask).count("1") * self.info.n_planes   # [plane][component] flattened
         self.obs = torch.zeros((nobs, grid.nz, grid.nx), dtype=torch.float64, device=dev)
         self.tau_w = torch.zeros((grid.nz, grid.nx), dtype=torch.float64, device=dev)
         self.drag = torch.zeros(1, dtype=torch.float64, device=dev)

@@ -8,6 +8,8 @@
 #include <cstdint>
 #include <vector>
 
+#include "chanenv.h"
+
 namespace chanenv {
 
 typedef double2 cplx;
@@ -154,7 +156,10 @@ struct PlaneChan {
 
 // Per-env-step kernels (begin, action ingest, end, outputs) of one channel; rebuilt for
 // every step call (action and output pointers).
-constexpr int OUT_SLOTS = 4;   // u, v, w at the sensing node, and tau_w
+// Output transforms: slot 0 tau_w, slot 1 + 3 k + f component f (u, v, w) of observation
+// plane k (the sensing plane first, then up to CHAN_MAX_EXTRA_PLANES more).
+constexpr int MAX_PLANES = 1 + CHAN_MAX_EXTRA_PLANES;
+constexpr int OUT_SLOTS = 1 + 3 * MAX_PLANES;
 struct StepChan {
   int nx, nz, nkx, ncol, n_sub;
   int skip;                     // not advanced this call (no valid state): marked like a
@@ -164,7 +169,7 @@ struct StepChan {
   double clip;
   gptr<const double> action;         // [nz][nx] device, or null
   gptr<double> drag_out;             // or null
-  gptr<const cplx> out_src[OUT_SLOTS];  // spectra [p][q] (obs: the F6 plane at the sensing node)
+  gptr<const cplx> out_src[OUT_SLOTS];  // spectra [p][q] (obs: the F6 plane at an observation node)
   gptr<double> out_dst[OUT_SLOTS];      // [nz][nx] device, or null
   gptr<cplx> vw_new, vw_old;
   gptr<cplx> tmp2d;                  // [OUT_SLOTS][nz][nkx]
@@ -210,7 +215,7 @@ int launch_begin_step(const StepChan* d_step, int nch, hipStream_t st, KernelTim
 int launch_ingest(const StepChan* d_step, int nch, int max_nx, int max_nz, int max_nkx, hipStream_t st,
                   KernelTimer* tm);
 int launch_finish_step(const StepChan* d_step, int nch, hipStream_t st, KernelTimer* tm);
-int launch_outputs(const StepChan* d_step, int nch, int max_nx, int max_nz, int max_nkx, hipStream_t st,
+int launch_outputs(const StepChan* d_step, int nch, int max_nx, int max_nz, int max_nkx, int nslots, hipStream_t st,
                    KernelTimer* tm);
 // Plane pass over nch channels of one shape (M_x, M_z from nx, nz), with a tiling: PB pencils
 // per z-kernel block, P pairs of padded z rows per x-row block.  The tiling distributes

@@ -56,6 +56,9 @@ struct chan_env {
   PhysParams ph;
   int js;
   double y_plus_node;
+  int n_planes;                     // observation planes (the sensing plane first)
+  int js_planes[MAX_PLANES];
+  double y_plus_planes[MAX_PLANES];
   hipStream_t stream;
   int device;
   DeviceState s;
@@ -105,6 +108,9 @@ bool valid_opts(const chan_opts_t* o) {
   const double vals[] = {o->ub_plus, o->px, o->nu_override, o->dt_override, o->opp_alpha, o->clip, o->ic_amp};
   for (double v : vals)
     if (!std::isfinite(v)) return false;
+  if (o->n_extra_planes < 0 || o->n_extra_planes > CHAN_MAX_EXTRA_PLANES) return false;
+  for (int k = 0; k < o->n_extra_planes; ++k)
+    if (!(o->extra_obs_y_plus[k] > 0) || !std::isfinite(o->extra_obs_y_plus[k])) return false;
   return true;
 }
 
@@ -322,18 +328,20 @@ StepChan make_step_chan(const chan_batch* b, int i, int k, const double* action,
   c.action = (decltype(c.action))(ext ? action : nullptr);
   c.drag_out = (decltype(c.drag_out))(drag);
   const size_t plane = (size_t)d.ny * d.nkx * d.nz;
-  if (obs) {
+  if (obs) {  // [plane][component][z][x]
     int slot = 0;
-    for (int f = 0; f < 3; ++f) {
-      if (!(e->opts.obs_mask & (1u << f))) continue;
-      c.out_src[f] = (gptr<const cplx>)(e->s.F6 + (size_t)f * plane + (size_t)e->js * d.nkx * d.nz);
-      c.out_dst[f] = (gptr<double>)(obs + (size_t)slot * d.nz * d.nx);
-      ++slot;
-    }
+    for (int k = 0; k < e->n_planes; ++k)
+      for (int f = 0; f < 3; ++f) {
+        if (!(e->opts.obs_mask & (1u << f))) continue;
+        c.out_src[1 + 3 * k + f] =
+            (gptr<const cplx>)(e->s.F6 + (size_t)f * plane + (size_t)e->js_planes[k] * d.nkx * d.nz);
+        c.out_dst[1 + 3 * k + f] = (gptr<double>)(obs + (size_t)slot * d.nz * d.nx);
+        ++slot;
+      }
   }
   if (tau_w) {
-    c.out_src[3] = (gptr<const cplx>)(e->s.tauw);
-    c.out_dst[3] = (gptr<double>)(tau_w);
+    c.out_src[0] = (gptr<const cplx>)(e->s.tauw);
+    c.out_dst[0] = (gptr<double>)(tau_w);
   }
   c.vw_new = (decltype(c.vw_new))(e->s.vw_new);
   c.vw_old = (decltype(c.vw_old))(e->s.vw_old);
@@ -613,7 +621,9 @@ int batch_step(chan_batch* b, int32_t na, const int32_t* idx, const double* cons
   for (const ShapeGroup& g : b->groups)
     if (group_column(b, g, S_end, false, true, tm)) return fail(CHAN_EDEVICE, "launch column pass", hipGetLastError());
   if (launch_finish_step(ds, na, st, tm)) return fail(CHAN_EDEVICE, "launch finish_step", hipGetLastError());
-  if (launch_outputs(ds, na, b->max_nx, b->max_nz, b->max_nkx, st, tm))
+  int max_planes = 1;
+  for (int k = 0; k < na; ++k) max_planes = std::max(max_planes, b->envs[b->active[k]]->n_planes);
+  if (launch_outputs(ds, na, b->max_nx, b->max_nz, b->max_nkx, 1 + 3 * max_planes, st, tm))
     return fail(CHAN_EDEVICE, "launch outputs", hipGetLastError());
   HIPCHECK(hipMemcpyAsync(b->h_status, b->d_status, na * sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));
@@ -789,6 +799,10 @@ size_t chan_env_footprint_bytes(const chan_grid_t* grid, const chan_opts_t* opts
   double ypn = 0.0;
   const int js = sensing_node(d, ph, grid->obs_y_plus, &ypn);
   if (js < 0 || js >= d.N) return 0;
+  for (int k = 0; k < o.n_extra_planes; ++k) {
+    const int jk = sensing_node(d, ph, o.extra_obs_y_plus[k], &ypn);
+    if (jk < 0 || jk >= d.N) return 0;
+  }
   if (!geometry_supported(d, ph, generic_forced())) return 0;
   return buffer_sizes(d, table_doubles(d, ph.open)).total;
 }
@@ -805,6 +819,15 @@ int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_
   double ypn = 0.0;
   const int js = sensing_node(d, ph, grid->obs_y_plus, &ypn);
   if (js < 0 || js >= d.N) return fail(CHAN_EINVAL, "sensing plane not inside the channel");
+  int js_planes[MAX_PLANES];
+  double yp_planes[MAX_PLANES];
+  js_planes[0] = js;
+  yp_planes[0] = ypn;
+  for (int k = 0; k < o.n_extra_planes; ++k) {
+    js_planes[1 + k] = sensing_node(d, ph, o.extra_obs_y_plus[k], &yp_planes[1 + k]);
+    if (js_planes[1 + k] < 0 || js_planes[1 + k] >= d.N)
+      return fail(CHAN_EINVAL, "extra observation plane not inside the channel");
+  }
   if (!geometry_supported(d, ph, generic_forced()))
     return fail(CHAN_EINVAL, "the open channel (free-slip top) needs ny <= 65 and the parity-major column kernel");
 
@@ -826,6 +849,11 @@ int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_
   e->ph = ph;
   e->js = js;
   e->y_plus_node = ypn;
+  e->n_planes = 1 + o.n_extra_planes;
+  for (int k = 0; k < MAX_PLANES; ++k) {
+    e->js_planes[k] = k < e->n_planes ? js_planes[k] : -1;
+    e->y_plus_planes[k] = k < e->n_planes ? yp_planes[k] : 0.0;
+  }
   e->stream = (hipStream_t)hip_stream;
   e->have_flow = false;
   e->poisoned = false;
@@ -1016,7 +1044,12 @@ int chan_env_query(const chan_env* e, chan_info_t* out) {
   out->t = e->t;
   out->nstep = e->nstep;
   out->state_doubles = (size_t)4 * d.nz * d.nkx * d.ny + 2 * (size_t)d.ny + 2 * (size_t)d.nz * d.nkx + 2;
-  out->obs_doubles = (size_t)__builtin_popcount(e->opts.obs_mask) * d.nz * d.nx;
+  out->obs_doubles = (size_t)e->n_planes * __builtin_popcount(e->opts.obs_mask) * d.nz * d.nx;
+  out->n_planes = e->n_planes;
+  for (int k = 0; k < MAX_PLANES; ++k) {
+    out->js_planes[k] = e->js_planes[k];
+    out->y_plus_planes[k] = e->y_plus_planes[k];
+  }
   out->footprint_bytes = e->dev_bytes;
   return CHAN_OK;
 }

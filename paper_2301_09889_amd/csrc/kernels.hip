@@ -902,8 +902,8 @@ int launch_ingest(const StepChan* d_step, int nch, int max_nx, int max_nz, int m
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-// Output transforms, slot = blockIdx.z (u, v, w at the sensing node, tau_w).  Source spectra
-// are [p][q].  Columns: inverse FFT along z.
+// Output transforms, slot = blockIdx.z (tau_w, then u, v, w at each observation plane).
+// Source spectra are [p][q].  Columns: inverse FFT along z.
 __global__ void k_out_cols(const StepChan* __restrict__ chans) {
   extern __shared__ double dyn_lds[];
   const StepChan C = chans[blockIdx.y];
@@ -948,12 +948,13 @@ __global__ void k_out_rows(const StepChan* __restrict__ chans) {
   for (int i = threadIdx.x; i < nx; i += blockDim.x) out[(size_t)k * nx + i] = r[i].x;
 }
 
-int launch_outputs(const StepChan* d_step, int nch, int max_nx, int max_nz, int max_nkx, hipStream_t st,
+int launch_outputs(const StepChan* d_step, int nch, int max_nx, int max_nz, int max_nkx, int nslots, hipStream_t st,
                    KernelTimer* tm) {
   if (nch < 1) return 0;
+  if (nslots < 1 || nslots > OUT_SLOTS) return -1;
   const size_t shz = (size_t)2 * max_nz * sizeof(cplx), shx = (size_t)2 * max_nx * sizeof(cplx);
-  timed_launch(tm, KC_OUTPUT, k_out_cols, dim3(max_nkx, nch, OUT_SLOTS), dim3(64), shz, st, d_step);
-  timed_launch(tm, KC_OUTPUT, k_out_rows, dim3(max_nz, nch, OUT_SLOTS), dim3(64), shx, st, d_step);
+  timed_launch(tm, KC_OUTPUT, k_out_cols, dim3(max_nkx, nch, nslots), dim3(64), shz, st, d_step);
+  timed_launch(tm, KC_OUTPUT, k_out_rows, dim3(max_nz, nch, nslots), dim3(64), shx, st, d_step);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -11,7 +11,8 @@ def grid_opts(cfg):
                        nu_override=cfg.nu_override, dt_override=cfg.dt_override,
                        controller=cfg.controller, opp_alpha=cfg.opp_alpha,
                        action_mode=cfg.action_mode, clip=cfg.clip, obs_mask=cfg.obs_mask,
-                       ic_profile=cfg.ic_profile, ic_amp=cfg.ic_amp)
+                       ic_profile=cfg.ic_profile, ic_amp=cfg.ic_amp,
+                       extra_obs_y_plus=cfg.extra_obs_y_plus)
     return grid, opts
 
 

@@ -79,6 +79,16 @@ def test_grid_validation_and_footprint():
     assert b.chan_env_footprint_bytes(top) > 0 and b.chan_env_footprint_bytes(top, o) == 0
     o.top_bc = 2
     assert b.chan_env_footprint_bytes(good, o) == 0
+    # extra observation planes: at most three, each inside the channel
+    assert b.chan_env_footprint_bytes(good, b.make_opts(extra_obs_y_plus=[5.0, 30.0, 100.0])) > 0
+    for bad in ([-1.0], [float("nan")], [500.0], [5.0, 10.0, 20.0, 0.0]):
+        o = b.make_opts()
+        o.n_extra_planes = len(bad)
+        for i, y in enumerate(bad[:3]):
+            o.extra_obs_y_plus[i] = y
+        assert b.chan_env_footprint_bytes(good, o) == 0, bad
+    with pytest.raises(ValueError):
+        b.make_opts(extra_obs_y_plus=[1.0, 2.0, 3.0, 4.0])
 
 
 def test_open_channel_refused_on_the_general_kernel_without_device():

@@ -1,7 +1,8 @@
 """Open channel (free-slip top, the geometry of §3.1) on the GPU, through the C ABI: parity
 with the oracle at the stated bars (relative state difference <= 1e-12 after one time step,
 <= 1e-9 after 100), the seeded initial condition and the sensing node, and bitwise equality
-of an open channel advanced alone and in a batch with closed channels."""
+of an open channel advanced alone and in a batch with closed channels (one of them with
+extra observation planes)."""
 import numpy as np
 import pytest
 
@@ -64,7 +65,7 @@ def test_open_reset_and_sensing_node():
 def test_open_and_closed_channels_in_one_batch_match_alone_bitwise():
     import paper_2301_09889_amd.binding as b
     specs = [(minimal_channel(top_bc=OPEN, controller=ch.CTRL_OPPOSITION), 0),
-             (minimal_channel(), 1),
+             (minimal_channel(obs_mask=7, extra_obs_y_plus=(8.0, 60.0)), 1),
              (minimal_channel(top_bc=OPEN, ic_profile=ch.IC_REICHARDT), 2),
              (ch.Config(nx=8, ny=33, nz=8, lx=2.67, lz=0.8, re_tau=180.0, dt_plus=0.05,
                         obs_y_plus=15.0, top_bc=OPEN), 3)]
@@ -91,6 +92,7 @@ def test_open_and_closed_channels_in_one_batch_match_alone_bitwise():
             print(f"  env step {k}, channel {i}: state entries differing {nd}", flush=True)
             assert nd == 0, (k, i)
             assert np.array_equal(ea.tau_w.cpu().numpy(), em.tau_w.cpu().numpy())
+            assert np.array_equal(ea.obs.cpu().numpy(), em.obs.cpu().numpy())
             assert ea.drag.item() == em.drag.item()
     batch.close()
     for e in alone + mixed:

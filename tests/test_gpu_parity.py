@@ -111,3 +111,22 @@ def test_query_reports_sensing_node():
     assert abs(info.ub - 15.66) < 1e-12
     assert info.state_doubles == ch.state_size(ch.Setup(minimal_channel()))
     genv.close()
+
+
+@pytest.mark.parametrize("top_bc", [ch.TOP_WALL, ch.TOP_FREESLIP], ids=["closed", "open"])
+def test_extra_observation_planes(top_bc):
+    """Three extra observation planes (y+ 5, 40, 150) with all three components: the
+    observation is [plane][component] and matches the oracle plane by plane; query reports
+    each plane's node."""
+    cfg = minimal_channel(controller=ch.CTRL_OPPOSITION, obs_mask=7, top_bc=top_bc,
+                          extra_obs_y_plus=(5.0, 40.0, 150.0))
+    run_pair(cfg, 2, [None, None], 2, 1e-11)
+    S = ch.Setup(cfg)
+    genv = gpu_env(cfg)
+    info = genv.query()
+    assert info.n_planes == 4
+    assert list(info.js_planes) == S.js_planes
+    assert info.obs_doubles == 12 * cfg.nz * cfg.nx
+    for k, j in enumerate(S.js_planes):
+        assert abs(info.y_plus_planes[k] - S.wall_dist[j] / S.nu) < 1e-12 * info.y_plus_planes[k]
+    genv.close()

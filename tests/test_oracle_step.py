@@ -50,6 +50,28 @@ def test_observation_node_rounds_up():
     assert S2.js == 50
 
 
+def test_extra_observation_planes():
+    """Each extra plane is rounded up to a node like the sensing plane; the observation is the
+    sensing plane's block followed by one block per extra plane, each the components' values at
+    that node (checked against numpy's Chebyshev series and FFT, not the oracle's helpers)."""
+    cfg = minimal_channel(obs_mask=7, extra_obs_y_plus=(5.0, 40.0, 179.0))
+    S = ch.Setup(cfg)
+    d = 1 + S.y
+    for j, yp in zip(S.js_planes[1:], cfg.extra_obs_y_plus):
+        assert d[j] * 180 >= yp > d[j + 1] * 180
+    st = initial_state(S, 4)
+    obs = ch.observation(S, st)
+    assert obs.shape == (12, S.nz, S.nx)
+    one = ch.observation(ch.Setup(minimal_channel(obs_mask=7)), st)
+    assert np.array_equal(obs[:3], one)
+    u, v, w = ch.reconstruct(S, st)[:3]
+    for k, j in enumerate(S.js_planes):
+        for c, f in enumerate((u, v, w)):
+            spec = npc.chebval(S.y[j], np.moveaxis(f, -1, 0))     # (nz, nkx) at node j
+            phys = np.fft.irfft2(spec, s=(S.nz, S.nx)) * S.nx * S.nz  # Nyquist column zero
+            assert np.abs(obs[3 * k + c] - phys).max() < 1e-12 * max(1.0, np.abs(phys).max())
+
+
 def test_reconstruction_is_divergence_free():
     S = ch.Setup(minimal_channel())
     st = initial_state(S, 3)
