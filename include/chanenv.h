@@ -59,7 +59,7 @@ enum { CHAN_CFR = 0, CHAN_CPG = 1 };
 enum { CHAN_CTRL_EXTERNAL = 0, CHAN_CTRL_OPPOSITION = 1 };
 enum { CHAN_RAMP = 0, CHAN_HOLD = 1 };
 enum { CHAN_IC_LAMINAR = 0, CHAN_IC_REICHARDT = 1 };
-enum { CHAN_OBS_U = 1, CHAN_OBS_V = 2, CHAN_OBS_W = 4 };
+enum { CHAN_OBS_U = 1, CHAN_OBS_V = 2, CHAN_OBS_W = 4, CHAN_OBS_P = 8 };
 /* Observation planes: the sensing plane of chan_grid_t plus up to CHAN_MAX_EXTRA_PLANES more
  * (§3.2: the observed state is one or more wall-parallel planes). */
 enum { CHAN_MAX_EXTRA_PLANES = 3 };
@@ -91,7 +91,9 @@ typedef struct {
   double opp_alpha;     /* [1.0] opposition gain alpha (§4.1) */
   int32_t action_mode;  /* [CHAN_RAMP] linear old->new over the env step (§3.2) | CHAN_HOLD */
   double clip;          /* [1.0] |action| bound in u_tau (§3.2); <= 0 disables clipping */
-  uint32_t obs_mask;    /* [CHAN_OBS_U | CHAN_OBS_V] observed components (§3.2, §4.2) */
+  uint32_t obs_mask;    /* [CHAN_OBS_U | CHAN_OBS_V] observed components (§3.2, §4.2); with
+                           CHAN_OBS_P the static-pressure fluctuation p - <p>_plane (abstract:
+                           velocity and pressure observable), which needs ny <= 65 */
   int32_t ic_profile;   /* [CHAN_IC_LAMINAR] mean profile of chan_env_reset | CHAN_IC_REICHARDT */
   double ic_amp;        /* [0.1] rms of the reset perturbation as a fraction of U_cl = 1.5 U_b */
   int32_t n_extra_planes;  /* [0] further observation planes, 0 .. CHAN_MAX_EXTRA_PLANES */
@@ -148,9 +150,12 @@ int chan_env_reset(struct chan_env* env, uint64_t seed);
  *           evaluated at the start of every time step.
  *   n_substeps  number of RK3/CN time steps, >= 1.
  *   obs     DEVICE pointer, n_planes*popcount(obs_mask)*nz*nx doubles, layout
- *           [plane][component][z][x]: u, v, w (in that order, selected by obs_mask)
- *           at the sensing node, then at each extra observation plane, end of the
- *           step.  May be NULL.
+ *           [plane][component][z][x]: u, v, w, p (in that order, selected by
+ *           obs_mask) at the sensing node, then at each extra observation plane, end
+ *           of the step.  p: from lap P = div(u x omega), P = p + |u|^2/2, with
+ *           dP/dy = H_y + nu lap v - dv/dt at both boundaries (dv/dt: the slope of a
+ *           ramped external action at the lower wall, else 0), the plane mean removed.
+ *           May be NULL.
  *   tau_w   DEVICE pointer, nz*nx doubles: nu du/dy at the lower wall, end of step.  May be NULL.
  *   drag    DEVICE pointer, 1 double: mean over the n_substeps time steps of the
  *           plane-averaged lower-wall shear stress, sampled after each step

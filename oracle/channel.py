@@ -141,6 +141,7 @@ class Setup:
         self.top_slope = self.s * cheb.slope_row(N, +1)
         self.bot_slope = self.s * cheb.slope_row(N, -1)
         self.top_curv = self.top_val @ self.D2  # d^2/dy^2 at the top
+        self.bot_curv = self.bot_val @ self.D2
         # integral over xi; the bulk velocity is its half in both geometries
         # (closed: int_{-1}^{1} dy / 2; open: int_0^1 dy = int dxi / 2)
         self.intw = cheb.integral_weights(N)
@@ -151,14 +152,15 @@ class Setup:
         self.js_planes = [self.js] + [observation_node(self.wall_dist, 1.0 / self.nu, yp)
                                       for yp in cfg.extra_obs_y_plus]
 
-    def helmholtz(self, lam, f, g_top, g_bot, top="dirichlet"):
-        """Solve (d^2/dy^2 - lam) X = f with X(bottom) = g_bot and, at the top,
-        X = g_top (``top`` "dirichlet") or dX/dy = g_top ("neumann").  In xi this
-        is (D_xi^2 - lam/s^2) X = f/s^2 with dX/dxi = g_top/s."""
+    def helmholtz(self, lam, f, g_top, g_bot, top="dirichlet", bot="dirichlet"):
+        """Solve (d^2/dy^2 - lam) X = f with, at each end, X = g ("dirichlet") or
+        dX/dy = g ("neumann").  In xi this is (D_xi^2 - lam/s^2) X = f/s^2 with
+        dX/dxi = g/s."""
         s2 = self.s ** 2
         gt = g_top / self.s if top == "neumann" else g_top
-        return tau_solve(self.N, np.asarray(lam) / s2, np.asarray(f) / s2, gt, g_bot,
-                         bc=(top, "dirichlet"))
+        gb = g_bot / self.s if bot == "neumann" else g_bot
+        return tau_solve(self.N, np.asarray(lam) / s2, np.asarray(f) / s2, gt, gb,
+                         bc=(top, bot))
 
 
 def observation_node(d, inv_nu, y_plus):
@@ -447,16 +449,59 @@ def wall_shear_field(S: Setup, st: State):
     return fr.to_physical(th, S.nx, S.nz)
 
 
-def observation(S: Setup, st: State):
-    """Selected velocity components (bit 0 u, bit 1 v, bit 2 w) on each
+def pressure_coefficients(S: Setup, st: State, dvw_dt):
+    """Chebyshev coefficients of the total pressure P = p + |u|^2/2 for every
+    wavenumber pair except (0, 0), whose plane means the observable removes.
+
+    Rotational form of the momentum equation: du/dt = -grad P + H + nu lap u
+    with H = u x omega.  Its divergence gives lap P = div H, i.e. per pair
+      (D^2 - k^2) P = i alpha H_1 + D H_2 + i beta H_3,
+    and its wall-normal component at the two boundaries gives the Neumann
+    conditions
+      dP/dy = H_2 + nu (D^2 - k^2) v - dv/dt,
+    where dv/dt is the rate of the lower wall's velocity (``dvw_dt``, (N_z,
+    N_x/2)) and zero at the top.  H is the state's own non-linear term (the
+    plane pass of the next stage).  Tau method with both conditions as
+    boundary rows."""
+    H1, H2, H3 = nonlinear(S, st)
+    act = S.active
+    ia = 1j * S.alpha[None, :]
+    ib = 1j * S.beta[:, None]
+    k2 = S.k2[act]
+    rhs = (ia[..., None] * H1 + H2 @ S.D.T + ib[..., None] * H3)[act]
+    v = st.v[act]
+    lapv_top = S.nu * (v @ S.top_curv - k2 * (v @ S.top_val))
+    lapv_bot = S.nu * (v @ S.bot_curv - k2 * (v @ S.bot_val))
+    g_top = H2[act] @ S.top_val + lapv_top
+    g_bot = H2[act] @ S.bot_val + lapv_bot - dvw_dt[act]
+    P = np.zeros_like(st.v)
+    P[act] = S.helmholtz(k2, rhs, g_top, g_bot, top="neumann", bot="neumann")
+    return P
+
+
+def observation(S: Setup, st: State, dvw_dt=None):
+    """Selected components (bit 0 u, bit 1 v, bit 2 w, bit 3 p) on each
     observation plane (node j_s first, then the extra planes), each on the
-    N_z x N_x grid, stacked plane by plane and in that order within a plane."""
+    N_z x N_x grid, stacked plane by plane and in that order within a plane.
+
+    p is the static-pressure fluctuation p - <p> (the plane mean removed):
+    p = P - |u|^2/2 evaluated pointwise on the plane's grid, P from
+    ``pressure_coefficients``.  ``dvw_dt`` is the lower wall's velocity rate
+    (zero if None)."""
     fields = reconstruct(S, st)
+    want_p = bool(S.cfg.obs_mask & 8)
+    if want_p:
+        P = pressure_coefficients(S, st, np.zeros_like(st.vw_old) if dvw_dt is None else dvw_dt)
     comps = []
     for j in S.js_planes:
-        for bit, f in ((1, fields[0]), (2, fields[1]), (4, fields[2])):
+        phys = [fr.to_physical(values_at_node(S, f, j), S.nx, S.nz) for f in fields[:3]]
+        for bit, f in zip((1, 2, 4), phys):
             if S.cfg.obs_mask & bit:
-                comps.append(fr.to_physical(values_at_node(S, f, j), S.nx, S.nz))
+                comps.append(f)
+        if want_p:
+            Pj = fr.to_physical(values_at_node(S, P, j), S.nx, S.nz)   # (0, 0) pair is zero
+            b = 0.5 * (phys[0] ** 2 + phys[1] ** 2 + phys[2] ** 2)
+            comps.append(Pj - (b - b.mean()))
     return np.stack(comps) if comps else np.zeros((0, S.nz, S.nx))
 
 
@@ -520,4 +565,9 @@ class Env:
         for d in drags:
             drag += d
         drag /= n_substeps
-        return observation(S, st), wall_shear_field(S, st), drag
+        # rate of the lower wall's velocity at the end of the env step: the ramp's slope
+        # (held actions and opposition control are constant over the last time step)
+        dvw_dt = np.zeros_like(st.vw_old)
+        if ext and S.cfg.action_mode == RAMP:
+            dvw_dt = (vw_new - vw_old) / (n_substeps * S.dt)
+        return observation(S, st, dvw_dt), wall_shear_field(S, st), drag

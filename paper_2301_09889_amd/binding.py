@@ -18,7 +18,7 @@ CHAN_CFR, CHAN_CPG = 0, 1
 CHAN_CTRL_EXTERNAL, CHAN_CTRL_OPPOSITION = 0, 1
 CHAN_RAMP, CHAN_HOLD = 0, 1
 CHAN_IC_LAMINAR, CHAN_IC_REICHARDT = 0, 1
-CHAN_OBS_U, CHAN_OBS_V, CHAN_OBS_W = 1, 2, 4
+CHAN_OBS_U, CHAN_OBS_V, CHAN_OBS_W, CHAN_OBS_P = 1, 2, 4, 8
 
 EXPORTED = ["chan_opts_default", "chan_env_create", "chan_env_reset", "chan_env_step",
             "chan_env_get_state", "chan_env_set_state", "chan_env_query",

@@ -41,8 +41,14 @@ struct TableLayout {
   size_t kfwd, kinv, rc_pm, intw_pm, op_pm, vt_pm, up_pm;
   // open channel only: phi_+ of every pair and stage (parity-major) and 1/(dphi_+/dxi)(+1)
   size_t pt_pm, ptinv;
+  // pressure: phi_+ of (D^2 - k^2/ys^2) per pair (parity-major) and the inverse of the 2x2
+  // Neumann matrix (dphi_+-/dxi at +-1)
+  size_t pk_pm, pkinv;
   size_t total;
 };
+
+// Observation planes per env: the sensing plane and the extra ones.
+constexpr int MAX_PLANES = 1 + CHAN_MAX_EXTRA_PLANES;
 
 // Parity-major record of one tau operator: w, u, f, F (65 entries each: 64 lanes + tail),
 // then 1/sum F for the even and the odd system.
@@ -87,7 +93,9 @@ struct DeviceState {
   int *status;                  // [1]
   // views into tab
   const double *cosk, *rc, *optab, *vt, *minv, *up, *inv_int_up, *alpha, *beta;
-  const double *kfwd, *kinv, *rc_pm, *intw_pm, *op_pm, *vt_pm, *up_pm, *pt_pm, *ptinv;
+  const double *kfwd, *kinv, *rc_pm, *intw_pm, *op_pm, *vt_pm, *up_pm, *pt_pm, *ptinv, *pk_pm, *pkinv;
+  cplx *pbuf;                   // [MAX_PLANES][nkx][nz] pressure spectra on the observation planes
+  double *pscr;                 // [MAX_PLANES][3][nz][nx] u, v, w on the pressure planes
   const cplx *twz, *twx, *twnx, *twnz;
 };
 
@@ -120,6 +128,9 @@ struct ColChan {
   // in the Chebyshev variable
   double lam0[3], ab[3], gb[3], zb[3];
   double nu_wall;               // nu ys: wall shear = nu_wall d/dxi
+  double dt;                    // time step (the rate of a ramped wall velocity)
+  int n_pplanes;                // pressure planes (0: no pressure observed)
+  int pjs[MAX_PLANES];          // their nodes
   double ys, ysi;               // d/dy = ys d/dxi; ysi = 1/ys (both powers of two)
   double opp_alpha, ub2, px;
   size_t plane;                 // elements per field in F6 / H3 (ny nkx nz)
@@ -130,7 +141,8 @@ struct ColChan {
   gptr<const cplx> vw_old, vw_new;
   gptr<cplx> vw_opp, tauw;
   gptr<const double> kfwd, kinv, rc_pm, intw_pm, op_pm, vt_pm, up_pm, minv, inv_int_up, alpha, beta;
-  gptr<const double> pt_pm, ptinv;
+  gptr<const double> pt_pm, ptinv, pk_pm, pkinv;
+  gptr<cplx> pbuf;
   gptr<double> drag_acc;
   gptr<int> status;
 };
@@ -156,10 +168,11 @@ struct PlaneChan {
 
 // Per-env-step kernels (begin, action ingest, end, outputs) of one channel; rebuilt for
 // every step call (action and output pointers).
-// Output transforms: slot 0 tau_w, slot 1 + 3 k + f component f (u, v, w) of observation
-// plane k (the sensing plane first, then up to CHAN_MAX_EXTRA_PLANES more).
-constexpr int MAX_PLANES = 1 + CHAN_MAX_EXTRA_PLANES;
-constexpr int OUT_SLOTS = 1 + 3 * MAX_PLANES;
+// Output transforms: slot 0 tau_w; for observation plane k (the sensing plane first, then up
+// to CHAN_MAX_EXTRA_PLANES more) slot 1 + 7 k + f: component f of u, v, w, P into the
+// observation, and 1 + 7 k + 4 + f: u, v, w into the pressure scratch.
+constexpr int SLOTS_PER_PLANE = 7;
+constexpr int OUT_SLOTS = 1 + SLOTS_PER_PLANE * MAX_PLANES;
 struct StepChan {
   int nx, nz, nkx, ncol, n_sub;
   int skip;                     // not advanced this call (no valid state): marked like a
@@ -215,6 +228,11 @@ int launch_begin_step(const StepChan* d_step, int nch, hipStream_t st, KernelTim
 int launch_ingest(const StepChan* d_step, int nch, int max_nx, int max_nz, int max_nkx, hipStream_t st,
                   KernelTimer* tm);
 int launch_finish_step(const StepChan* d_step, int nch, hipStream_t st, KernelTimer* tm);
+// Pressure on the observation planes from the end-of-step state (H3 holds its non-linear term).
+int launch_pressure_pm(const Dims& d, const ColChan* d_col, int nch, const ColStage& S, hipStream_t st,
+                       KernelTimer* tm);
+// p = P - (|u|^2/2 - its plane mean) on every pressure plane, after the output transforms.
+int launch_pressure_finish(const StepChan* d_step, int nch, hipStream_t st, KernelTimer* tm);
 int launch_outputs(const StepChan* d_step, int nch, int max_nx, int max_nz, int max_nkx, int nslots, hipStream_t st,
                    KernelTimer* tm);
 // Plane pass over nch channels of one shape (M_x, M_z from nx, nz), with a tiling: PB pencils

@@ -951,6 +951,108 @@ int launch_pm(const ColChan* d_col, const ColChan* h_col, int nch, int ncol, con
   return 0;
 }
 
+// Pressure on the observation planes (the observable p - <p>_plane; end of an env step, after a
+// plane pass of the end-of-step state filled H3).  With P = p + |u|^2/2, per pair k != 0:
+//   (D^2 - k^2) P = i al H1 + D H2 + i be H3,   dP/dy = H2 + nu (D^2 - k^2) v - dv/dt at both
+// boundaries (dv/dt: the lower wall's velocity rate, a ramped external action's slope).  In xi:
+// (D_xi^2 - k^2/ys^2) P = (i (al H1 + be H3)/ys + D_xi H2)/ys, dP/dxi = (dP/dy)/ys.  Tau
+// solution with zero values, plus c_+ phi_+ + c_- phi_- for the two Neumann conditions; P is
+// then evaluated at each plane's node.  The (0, 0) pair (plane means) is set to zero.
+template <int N>
+__device__ __forceinline__ void pressure_block(const ColChan& A, const ColStage& S, int cb) {
+  constexpr int NY = N + 1;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c = __builtin_amdgcn_readfirstlane(cb * CWAVES + wave);
+  if (c >= A.ncol || A.n_pplanes <= 0) return;
+  const int nz = A.nz;
+  const int p = c / nz, q = c - p * nz;
+  if (q == nz / 2) return;
+  if (p == 0 && q > nz / 2) return;
+  const int partner = (p == 0 && q > 0) ? (nz - q) : -1;
+  const size_t pstride = (size_t)A.nkx * nz;
+  cplx* pout = A.pbuf;
+  if (c == 0) {
+    if (lane < A.n_pplanes) pout[(size_t)lane * pstride] = cz();
+    return;
+  }
+  const Lane<N> L(lane);
+  const double al = A.alpha[p], be = A.beta[q];
+  const double als = al * A.ysi, bes = be * A.ysi;
+  const double k2s = als * als + bes * bes;
+  const double dn = (double)L.n, dN = (double)N;
+  // H1, H2, H3 at the nodes of this column -> Chebyshev coefficients
+  const cplx* h3 = A.H3 + (size_t)p * nz + q;
+  const size_t jstride = (size_t)A.nkx * nz;
+  auto loadH = [&](int g, int j) { return h3[g * A.plane + (size_t)j * jstride]; };
+  cplx hc[3], hct[3];
+  dct_fwd_pm<N, 3, false>(L, loadH, A.kfwd, hc, hct);
+  const int nl = (L.ok ? L.n : 0);
+  const size_t col = (size_t)c * NY;
+  const cplx v = L.ok ? A.vS[col + nl] : cz();
+  const cplx vt = A.vS[col + N];
+  // right-hand side in xi
+  const cplx dH2 = cheb_d<N>(L, hc[1], hct[1]);
+  const cplx ab = cmuli(make_double2(als * hc[0].x + bes * hc[2].x, als * hc[0].y + bes * hc[2].y));
+  const cplx abt = cmuli(make_double2(als * hct[0].x + bes * hct[2].x, als * hct[0].y + bes * hct[2].y));
+  // ab = i (al H1 + be H3)/ys already carries one 1/ys
+  const cplx f = cscale(cadd(dH2, ab), A.ysi);
+  const cplx ft = cscale(abt, A.ysi);
+  const RowCoef rcf = load_rc<N>(L, A.rc_pm);
+  const TauRec rk = load_rec<N>(L, A.op_pm + ((size_t)c * NOPS + 3) * PM_OPSZ);
+  cplx R[1], Rt[1];
+  R[0] = tau_rows_pm<N>(L, f, ft, rcf, 0.0, cz(), cz(), Rt[0]);
+  const cplx z1[1] = {cz()};
+  cplx P[1], Pt[1];
+  tau_solve_pm<N, 1>(L, R, Rt, rk, z1, z1, P, Pt);
+  // Neumann data at +1 (top) and -1 (bottom), in xi
+  const double n2 = dn * dn, N2 = dN * dN;
+  const double w2 = n2 * (n2 - 1.0) / 3.0, w2t = N2 * (N2 - 1.0) / 3.0;  // T_n''(1)
+  const cplx d2v_top = coef_sum<N>(L, v, vt, w2, w2t);
+  const cplx d2v_bot = coef_sum<N>(L, v, vt, L.sgn() * w2, w2t);
+  const cplx v_top = coef_sum<N>(L, v, vt, 1.0, 1.0);
+  const cplx v_bot = coef_sum<N>(L, v, vt, L.sgn(), 1.0);
+  const double nux = A.nu_wall * A.ys;  // nu ys^2
+  const cplx H2_top = loadH(1, 0), H2_bot = loadH(1, N);
+  cplx rate = cz();
+  if (A.ext && !A.hold) {
+    const cplx o = A.vw_old[c], nn = A.vw_new[c];
+    rate = cscale(csub(nn, o), 1.0 / ((double)S.n_sub * A.dt));
+  }
+  // g = H2 + nu' (D_xi^2 - k'^2) v - dv/dt, then / ys
+  const cplx g_top = cscale(caxpy(H2_top, nux, caxpy(d2v_top, -k2s, v_top)), A.ysi);
+  const cplx g_bot = cscale(csub(caxpy(H2_bot, nux, caxpy(d2v_bot, -k2s, v_bot)), rate), A.ysi);
+  const cplx dP_top = coef_sum<N>(L, P[0], Pt[0], n2, N2);
+  const cplx dP_bot = coef_sum<N>(L, P[0], Pt[0], -L.sgn() * n2, -N2);
+  const cplx r_top = csub(g_top, dP_top), r_bot = csub(g_bot, dP_bot);
+  const double* mi = A.pkinv + (size_t)c * 4;
+  const cplx c0 = make_double2(mi[0] * r_top.x + mi[1] * r_bot.x, mi[0] * r_top.y + mi[1] * r_bot.y);
+  const cplx c1 = make_double2(mi[2] * r_top.x + mi[3] * r_bot.x, mi[2] * r_top.y + mi[3] * r_bot.y);
+  const double* ptab = A.pk_pm + (size_t)c * PM_ENTRIES;
+  const double pl = ptab[lane], plt = ptab[64];
+  cplx Pc = caxpy(caxpy(P[0], pl, c0), L.sgn() * pl, c1);
+  const cplx Pct = caxpy(caxpy(Pt[0], plt, c0), plt, c1);
+  if (!L.ok) Pc = cz();
+  // value at each plane's node j: sum_n P_n cos(pi n j/N); cos(pi n j/N) = (-1)^n cos(pi n (N-j)/N)
+  for (int k = 0; k < A.n_pplanes; ++k) {
+    const int j = A.pjs[k];
+    const bool flip = j > N / 2;
+    const int jj = flip ? N - j : j;
+    const double cw = A.kfwd[(size_t)jj * 64 + lane] * (flip ? L.sgn() : 1.0);
+    const double tail = (j & 1) ? -1.0 : 1.0;
+    const cplx val = make_double2(lane_sum(cw * Pc.x) + tail * Pct.x, lane_sum(cw * Pc.y) + tail * Pct.y);
+    if (lane == 0) {
+      pout[(size_t)k * pstride + (size_t)p * nz + q] = val;
+      if (partner >= 0) pout[(size_t)k * pstride + partner] = cconj(val);
+    }
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(64 * CWAVES, 2) void k_pressure_pm(const ColChan* __restrict__ chans, ColStage S, int bpc) {
+  const int ch = blockIdx.x / bpc;
+  pressure_block<N>(chans[ch], S, blockIdx.x - ch * bpc);
+}
+
 }  // namespace
 
 int launch_column_pm(const Dims& d, const ColChan* d_col, const ColChan* h_col, int nch, const ColStage& S,
@@ -962,6 +1064,20 @@ int launch_column_pm(const Dims& d, const ColChan* d_col, const ColChan* h_col, 
     case 64: return launch_pm<64>(d_col, h_col, nch, d.ncol, S, solve, recon, st, tm);
     default: return -1;
   }
+}
+
+int launch_pressure_pm(const Dims& d, const ColChan* d_col, int nch, const ColStage& S, hipStream_t st,
+                       KernelTimer* tm) {
+  if (nch < 1) return 0;
+  const int bpc = (d.ncol + CWAVES - 1) / CWAVES;
+  const dim3 grid(bpc * nch), block(64 * CWAVES);
+  switch (d.N) {
+    case 16: timed_launch(tm, KC_OUTPUT, k_pressure_pm<16>, grid, block, 0, st, d_col, S, bpc); break;
+    case 32: timed_launch(tm, KC_OUTPUT, k_pressure_pm<32>, grid, block, 0, st, d_col, S, bpc); break;
+    case 64: timed_launch(tm, KC_OUTPUT, k_pressure_pm<64>, grid, block, 0, st, d_col, S, bpc); break;
+    default: return -1;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 }  // namespace chanenv

@@ -104,7 +104,7 @@ bool valid_opts(const chan_opts_t* o) {
   if (o->controller != CHAN_CTRL_EXTERNAL && o->controller != CHAN_CTRL_OPPOSITION) return false;
   if (o->action_mode != CHAN_RAMP && o->action_mode != CHAN_HOLD) return false;
   if (o->ic_profile != CHAN_IC_LAMINAR && o->ic_profile != CHAN_IC_REICHARDT) return false;
-  if (o->obs_mask & ~7u) return false;
+  if (o->obs_mask & ~15u) return false;
   const double vals[] = {o->ub_plus, o->px, o->nu_override, o->dt_override, o->opp_alpha, o->clip, o->ic_amp};
   for (double v : vals)
     if (!std::isfinite(v)) return false;
@@ -156,9 +156,12 @@ int sensing_node(const Dims& d, const PhysParams& ph, double yplus, double* node
   return js;
 }
 
-// The open channel runs on the N <= 64 column kernels only.
+// The open channel and the pressure observable run on the N <= 64 column kernels only.
 bool geometry_supported(const Dims& d, const PhysParams& ph, bool force_generic) {
   return !ph.open || (d.N <= 64 && !force_generic);
+}
+bool pressure_supported(const Dims& d, const chan_opts_t& o, bool force_generic) {
+  return !(o.obs_mask & CHAN_OBS_P) || (d.N <= 64 && !force_generic);
 }
 
 bool generic_forced() {
@@ -167,7 +170,7 @@ bool generic_forced() {
 }
 
 struct Sizes {
-  size_t spec, plane6, z6, w3, h3, wall, tmp2d, tab, total;
+  size_t spec, plane6, z6, w3, h3, wall, tmp2d, tab, pbuf, pscr, total;
 };
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -183,8 +186,10 @@ Sizes buffer_sizes(const Dims& d, size_t tab_doubles) {
   z.wall = align256((size_t)d.ncol * C);
   z.tmp2d = align256((size_t)OUT_SLOTS * d.nz * d.nkx * C);
   z.tab = align256(tab_doubles * sizeof(double));
+  z.pbuf = align256((size_t)MAX_PLANES * d.nkx * d.nz * C);
+  z.pscr = align256((size_t)MAX_PLANES * 3 * d.nz * d.nx * sizeof(double));
   z.total = 4 * z.spec + align256((size_t)4 * d.ny * sizeof(double)) + z.plane6 + z.z6 + z.w3 + z.h3 +
-            4 * z.wall + z.tmp2d + z.tab + 256 + 256;
+            4 * z.wall + z.tmp2d + z.tab + z.pbuf + z.pscr + 256 + 256;
   return z;
 }
 
@@ -200,6 +205,7 @@ size_t table_doubles(const Dims& d, bool open) {
     t += 2 * r2((size_t)(H + 1) * 64) + r2((size_t)3 * PM_ENTRIES) + r2(PM_ENTRIES) +
          r2((size_t)d.ncol * NOPS * PM_OPSZ) + r2((size_t)d.ncol * 3 * PM_ENTRIES) + r2((size_t)3 * PM_ENTRIES);
   if (pm && open) t += r2((size_t)d.ncol * 3 * PM_ENTRIES) + r2((size_t)d.ncol * 3);
+  if (pm) t += r2((size_t)d.ncol * PM_ENTRIES) + r2((size_t)d.ncol * 4);
   return t;
 }
 
@@ -240,6 +246,9 @@ ColChan make_col_chan(const chan_env* e) {
     c.zb[r] = e->sc[r].zb;
   }
   c.nu_wall = e->ph.nu * e->ph.ys;
+  c.dt = e->ph.dt;
+  c.n_pplanes = (e->opts.obs_mask & CHAN_OBS_P) ? e->n_planes : 0;
+  for (int k = 0; k < MAX_PLANES; ++k) c.pjs[k] = k < e->n_planes ? e->js_planes[k] : 0;
   c.ys = e->ph.ys;
   c.ysi = 1.0 / e->ph.ys;
   c.opp_alpha = e->opts.opp_alpha;
@@ -266,6 +275,9 @@ ColChan make_col_chan(const chan_env* e) {
   c.up_pm = (decltype(c.up_pm))(s.up_pm);
   c.pt_pm = (decltype(c.pt_pm))(s.pt_pm);
   c.ptinv = (decltype(c.ptinv))(s.ptinv);
+  c.pk_pm = (decltype(c.pk_pm))(s.pk_pm);
+  c.pkinv = (decltype(c.pkinv))(s.pkinv);
+  c.pbuf = (decltype(c.pbuf))(s.pbuf);
   c.minv = (decltype(c.minv))(s.minv);
   c.inv_int_up = (decltype(c.inv_int_up))(s.inv_int_up);
   c.alpha = (decltype(c.alpha))(s.alpha);
@@ -329,15 +341,27 @@ StepChan make_step_chan(const chan_batch* b, int i, int k, const double* action,
   c.drag_out = (decltype(c.drag_out))(drag);
   const size_t plane = (size_t)d.ny * d.nkx * d.nz;
   if (obs) {  // [plane][component][z][x]
+    const bool pres = (e->opts.obs_mask & CHAN_OBS_P) != 0;
+    const size_t pl = (size_t)d.nz * d.nx;
     int slot = 0;
-    for (int k = 0; k < e->n_planes; ++k)
+    for (int k = 0; k < e->n_planes; ++k) {
+      const int base = 1 + SLOTS_PER_PLANE * k;
+      const size_t node = (size_t)e->js_planes[k] * d.nkx * d.nz;
       for (int f = 0; f < 3; ++f) {
+        if (pres)  // u, v, w on the plane for the Bernoulli term
+          c.out_src[base + 4 + f] = (gptr<const cplx>)(e->s.F6 + (size_t)f * plane + node),
+          c.out_dst[base + 4 + f] = (gptr<double>)(e->s.pscr + ((size_t)k * 3 + f) * pl);
         if (!(e->opts.obs_mask & (1u << f))) continue;
-        c.out_src[1 + 3 * k + f] =
-            (gptr<const cplx>)(e->s.F6 + (size_t)f * plane + (size_t)e->js_planes[k] * d.nkx * d.nz);
-        c.out_dst[1 + 3 * k + f] = (gptr<double>)(obs + (size_t)slot * d.nz * d.nx);
+        c.out_src[base + f] = (gptr<const cplx>)(e->s.F6 + (size_t)f * plane + node);
+        c.out_dst[base + f] = (gptr<double>)(obs + (size_t)slot * pl);
         ++slot;
       }
+      if (pres) {  // P on the plane, then p = P - |u|^2/2 + its mean in place
+        c.out_src[base + 3] = (gptr<const cplx>)(e->s.pbuf + (size_t)k * d.nkx * d.nz);
+        c.out_dst[base + 3] = (gptr<double>)(obs + (size_t)slot * pl);
+        ++slot;
+      }
+    }
   }
   if (tau_w) {
     c.out_src[0] = (gptr<const cplx>)(e->s.tauw);
@@ -620,11 +644,32 @@ int batch_step(chan_batch* b, int32_t na, const int32_t* idx, const double* cons
   const ColStage S_end = {-1, 0, n_substeps};
   for (const ShapeGroup& g : b->groups)
     if (group_column(b, g, S_end, false, true, tm)) return fail(CHAN_EDEVICE, "launch column pass", hipGetLastError());
-  if (launch_finish_step(ds, na, st, tm)) return fail(CHAN_EDEVICE, "launch finish_step", hipGetLastError());
+  // pressure observed: the end-of-step state's non-linear term (a plane pass; the next step's
+  // first stage recomputes the same H), then the Poisson solve per pair, before finish_step
+  // replaces the old wall velocity (its rate enters the wall condition)
   int max_planes = 1;
-  for (int k = 0; k < na; ++k) max_planes = std::max(max_planes, b->envs[b->active[k]]->n_planes);
-  if (launch_outputs(ds, na, b->max_nx, b->max_nz, b->max_nkx, 1 + 3 * max_planes, st, tm))
+  bool any_pressure = false;
+  for (int k = 0; k < na; ++k) {
+    const chan_env* e = b->envs[b->active[k]];
+    max_planes = std::max(max_planes, e->n_planes);
+    any_pressure = any_pressure || (obs != nullptr && obs[k] != nullptr && (e->opts.obs_mask & CHAN_OBS_P));
+  }
+  if (any_pressure)
+    for (const ShapeGroup& g : b->groups) {
+      bool has = false;
+      for (int k = 0; k < g.nact; ++k) has = has || g.h_col[k].n_pplanes > 0;
+      if (!has) continue;
+      if (launch_plane_pass(g.d, g.d_plane, g.nact, g.tiles, st, tm))
+        return fail(CHAN_EDEVICE, "launch plane pass (pressure)", hipGetLastError());
+      if (launch_pressure_pm(g.d, g.d_col, g.nact, S_end, st, tm))
+        return fail(CHAN_EDEVICE, "launch pressure", hipGetLastError());
+    }
+  if (launch_finish_step(ds, na, st, tm)) return fail(CHAN_EDEVICE, "launch finish_step", hipGetLastError());
+  const int nslots = any_pressure ? 1 + SLOTS_PER_PLANE * max_planes : SLOTS_PER_PLANE * max_planes - 3;
+  if (launch_outputs(ds, na, b->max_nx, b->max_nz, b->max_nkx, nslots, st, tm))
     return fail(CHAN_EDEVICE, "launch outputs", hipGetLastError());
+  if (any_pressure && launch_pressure_finish(ds, na, st, tm))
+    return fail(CHAN_EDEVICE, "launch pressure finish", hipGetLastError());
   HIPCHECK(hipMemcpyAsync(b->h_status, b->d_status, na * sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));
   rc = CHAN_OK;
@@ -804,6 +849,7 @@ size_t chan_env_footprint_bytes(const chan_grid_t* grid, const chan_opts_t* opts
     if (jk < 0 || jk >= d.N) return 0;
   }
   if (!geometry_supported(d, ph, generic_forced())) return 0;
+  if (!pressure_supported(d, o, generic_forced())) return 0;
   return buffer_sizes(d, table_doubles(d, ph.open)).total;
 }
 
@@ -830,6 +876,8 @@ int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_
   }
   if (!geometry_supported(d, ph, generic_forced()))
     return fail(CHAN_EINVAL, "the open channel (free-slip top) needs ny <= 65 and the parity-major column kernel");
+  if (!pressure_supported(d, o, generic_forced()))
+    return fail(CHAN_EINVAL, "the pressure observable needs ny <= 65 and the parity-major column kernel");
 
   HostTables ht;
   try {
@@ -912,6 +960,8 @@ int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_
   s.tauw = (cplx*)take(z.wall);
   s.tmp2d = (cplx*)take(z.tmp2d);
   s.tab = (double*)take(z.tab);
+  s.pbuf = (cplx*)take(z.pbuf);
+  s.pscr = (double*)take(z.pscr);
   s.drag_acc = (double*)take(256);
   s.status = (int*)take(256);
   const TableLayout& L = ht.L;
@@ -937,6 +987,8 @@ int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_
   s.up_pm = s.tab + L.up_pm;
   s.pt_pm = s.tab + L.pt_pm;
   s.ptinv = s.tab + L.ptinv;
+  s.pk_pm = s.tab + L.pk_pm;
+  s.pkinv = s.tab + L.pkinv;
   {
     hipError_t err = hipMemsetAsync(e->dev_block, 0, z.total, e->stream);
     const char* what = "hipMemsetAsync";

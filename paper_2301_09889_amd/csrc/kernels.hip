@@ -902,7 +902,8 @@ int launch_ingest(const StepChan* d_step, int nch, int max_nx, int max_nz, int m
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-// Output transforms, slot = blockIdx.z (tau_w, then u, v, w at each observation plane).
+// Output transforms, slot = blockIdx.z (tau_w, then per observation plane u, v, w and P into
+// the observation and u, v, w into the pressure scratch).
 // Source spectra are [p][q].  Columns: inverse FFT along z.
 __global__ void k_out_cols(const StepChan* __restrict__ chans) {
   extern __shared__ double dyn_lds[];
@@ -946,6 +947,38 @@ __global__ void k_out_rows(const StepChan* __restrict__ chans) {
   __syncthreads();
   cplx* r = fft_batch(a, b, nx, 1, nx, C.twnx, true);
   for (int i = threadIdx.x; i < nx; i += blockDim.x) out[(size_t)k * nx + i] = r[i].x;
+}
+
+// Static pressure on plane blockIdx.y of channel blockIdx.x: the output transforms left P (the
+// pair (0, 0) excluded) in the observation and u, v, w in the scratch; p = P - (|u|^2/2 minus
+// its plane mean), pointwise on the N_z x N_x grid, in place.  Fixed-order block reduction.
+__global__ __launch_bounds__(256) void k_pressure_finish(const StepChan* __restrict__ chans) {
+  __shared__ double red[256];
+  const StepChan C = chans[blockIdx.x];
+  const int base = 1 + SLOTS_PER_PLANE * (int)blockIdx.y;
+  auto pr = C.out_dst[base + 3];
+  if (C.skip || pr == nullptr || C.out_src[base + 3] == nullptr) return;  // uniform per block
+  auto u = C.out_dst[base + 4];
+  auto v = C.out_dst[base + 5];
+  auto w = C.out_dst[base + 6];
+  const int n = C.nx * C.nz;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) acc += 0.5 * (u[i] * u[i] + v[i] * v[i] + w[i] * w[i]);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  const double mean = red[0] / (double)n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    pr[i] = pr[i] - (0.5 * (u[i] * u[i] + v[i] * v[i] + w[i] * w[i]) - mean);
+}
+
+int launch_pressure_finish(const StepChan* d_step, int nch, hipStream_t st, KernelTimer* tm) {
+  if (nch < 1) return 0;
+  timed_launch(tm, KC_OUTPUT, k_pressure_finish, dim3(nch, MAX_PLANES), dim3(256), 0, st, d_step);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_outputs(const StepChan* d_step, int nch, int max_nx, int max_nz, int max_nkx, int nslots, hipStream_t st,

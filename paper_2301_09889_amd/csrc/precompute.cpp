@@ -183,6 +183,8 @@ void precompute_tables(const Dims& d, const PhysParams& ph, HostTables* out) {
   const bool open = pm && ph.open;
   L.pt_pm = take(open ? (size_t)d.ncol * 3 * PM_ENTRIES : 0);
   L.ptinv = take(open ? (size_t)d.ncol * 3 : 0);
+  L.pk_pm = take(pm ? (size_t)d.ncol * PM_ENTRIES : 0);
+  L.pkinv = take(pm ? (size_t)d.ncol * 4 : 0);
   L.total = o;
   std::vector<double>& T = out->data;
   T.assign(L.total, 0.0);
@@ -227,6 +229,24 @@ void precompute_tables(const Dims& d, const PhysParams& ph, HostTables* out) {
     double* base = &T[L.optab + (size_t)c * NOPS * 2 * d.opsz];
     for (int r = 0; r < 3; ++r) fill_record(d, k2 + lam0[r], base + (size_t)r * 2 * d.opsz);
     fill_record(d, k2, base + (size_t)3 * 2 * d.opsz);
+    if (pm && c > 0) {
+      // pressure: phi_+ of (D^2 - k'^2), phi_+(+1) = 1, phi_+(-1) = 0, and the inverse of the
+      // Neumann matrix [dphi_+(+1), dphi_-(+1); dphi_+(-1), dphi_-(-1)] (phi_- its mirror)
+      host_tau_solve(d, base + (size_t)3 * 2 * d.opsz, rc, zero.data(), 1.0, 0.0, phi.data());
+      double a = 0.0, b = 0.0;  // dphi_+/dxi at +1 and -1
+      for (int n = 0; n <= N; ++n) {
+        const double n2 = (double)n * n;
+        a += n2 * phi[n];
+        b += ((n & 1) ? n2 : -n2) * phi[n];
+      }
+      const double det = b * b - a * a;
+      double* mi = &T[L.pkinv + (size_t)c * 4];
+      mi[0] = -a / det;
+      mi[1] = b / det;
+      mi[2] = -b / det;
+      mi[3] = a / det;
+      for (int n = 0; n <= N; ++n) T[L.pk_pm + (size_t)c * PM_ENTRIES + pm_slot(N, n)] = phi[n];
+    }
     for (int r = 0; r < 3; ++r) {
       // phi_+: (D^2 - lam) phi = 0, phi(+1) = 1, phi(-1) = 0
       host_tau_solve(d, base + (size_t)r * 2 * d.opsz, rc, zero.data(), 1.0, 0.0, phi.data());

@@ -89,6 +89,12 @@ def test_grid_validation_and_footprint():
         assert b.chan_env_footprint_bytes(good, o) == 0, bad
     with pytest.raises(ValueError):
         b.make_opts(extra_obs_y_plus=[1.0, 2.0, 3.0, 4.0])
+    # pressure (bit 3): on the N_y <= 65 kernels only; no bits above it
+    assert b.chan_env_footprint_bytes(good, b.make_opts(obs_mask=15)) > 0
+    assert b.chan_env_footprint_bytes(good, b.make_opts(obs_mask=16)) == 0
+    g97 = b.ChanGrid(8, 97, 8, 2.67, 0.8, 180.0, 0.05, 15.0)
+    assert b.chan_env_footprint_bytes(g97) > 0
+    assert b.chan_env_footprint_bytes(g97, b.make_opts(obs_mask=11)) == 0
 
 
 def test_open_channel_refused_on_the_general_kernel_without_device():

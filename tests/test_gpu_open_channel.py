@@ -2,7 +2,7 @@
 with the oracle at the stated bars (relative state difference <= 1e-12 after one time step,
 <= 1e-9 after 100), the seeded initial condition and the sensing node, and bitwise equality
 of an open channel advanced alone and in a batch with closed channels (one of them with
-extra observation planes)."""
+extra observation planes and the pressure observable)."""
 import numpy as np
 import pytest
 
@@ -65,7 +65,7 @@ def test_open_reset_and_sensing_node():
 def test_open_and_closed_channels_in_one_batch_match_alone_bitwise():
     import paper_2301_09889_amd.binding as b
     specs = [(minimal_channel(top_bc=OPEN, controller=ch.CTRL_OPPOSITION), 0),
-             (minimal_channel(obs_mask=7, extra_obs_y_plus=(8.0, 60.0)), 1),
+             (minimal_channel(obs_mask=15, extra_obs_y_plus=(8.0, 60.0)), 1),
              (minimal_channel(top_bc=OPEN, ic_profile=ch.IC_REICHARDT), 2),
              (ch.Config(nx=8, ny=33, nz=8, lx=2.67, lz=0.8, re_tau=180.0, dt_plus=0.05,
                         obs_y_plus=15.0, top_bc=OPEN), 3)]
