@@ -80,8 +80,7 @@ typedef struct {
 /* Options; passing NULL to chan_env_create selects the defaults in brackets. */
 typedef struct {
   int32_t top_bc;       /* [CHAN_TOP_WALL] closed channel | CHAN_TOP_FREESLIP open channel
-                           (the paper's geometry); the open channel needs ny <= 65 and
-                           returns CHAN_EINVAL otherwise */
+                           (the paper's geometry) */
   int32_t forcing;      /* [CHAN_CFR] constant flow rate | CHAN_CPG constant pressure gradient */
   double ub_plus;       /* [<= 0: 15.66 (re_tau/180)^(1/7)] bulk velocity held by CFR */
   double px;            /* [0] pressure gradient for CPG */

@@ -39,8 +39,9 @@ struct TableLayout {
   // parity-major copies for the column kernel with N <= 64 (one lane per coefficient:
   // even n = 2l in lanes l < 32, odd n = 2i + 1 in lanes 32 + i, n = N as a 65th "tail" entry)
   size_t kfwd, kinv, rc_pm, intw_pm, op_pm, vt_pm, up_pm;
-  // open channel only: phi_+ of every pair and stage (parity-major) and 1/(dphi_+/dxi)(+1)
-  size_t pt_pm, ptinv;
+  // open channel only: phi_+ of every pair and stage (parity-major for N <= 64, natural order
+  // above) and 1/(dphi_+/dxi)(+1)
+  size_t pt_pm, ptinv, pt;
   // pressure: phi_+ of (D^2 - k^2/ys^2) per pair (parity-major) and the inverse of the 2x2
   // Neumann matrix (dphi_+-/dxi at +-1)
   size_t pk_pm, pkinv;
@@ -93,7 +94,7 @@ struct DeviceState {
   int *status;                  // [1]
   // views into tab
   const double *cosk, *rc, *optab, *vt, *minv, *up, *inv_int_up, *alpha, *beta;
-  const double *kfwd, *kinv, *rc_pm, *intw_pm, *op_pm, *vt_pm, *up_pm, *pt_pm, *ptinv, *pk_pm, *pkinv;
+  const double *kfwd, *kinv, *rc_pm, *intw_pm, *op_pm, *vt_pm, *up_pm, *pt_pm, *ptinv, *pt, *pk_pm, *pkinv;
   cplx *pbuf;                   // [MAX_PLANES][nkx][nz] pressure spectra on the observation planes
   double *pscr;                 // [MAX_PLANES][3][nz][nx] u, v, w on the pressure planes
   const cplx *twz, *twx, *twnx, *twnz;

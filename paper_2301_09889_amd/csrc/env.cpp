@@ -156,10 +156,8 @@ int sensing_node(const Dims& d, const PhysParams& ph, double yplus, double* node
   return js;
 }
 
-// The open channel and the pressure observable run on the N <= 64 column kernels only.
-bool geometry_supported(const Dims& d, const PhysParams& ph, bool force_generic) {
-  return !ph.open || (d.N <= 64 && !force_generic);
-}
+// The pressure observable runs on the N <= 64 column kernels only (both geometries run on both
+// column kernels).
 bool pressure_supported(const Dims& d, const chan_opts_t& o, bool force_generic) {
   return !(o.obs_mask & CHAN_OBS_P) || (d.N <= 64 && !force_generic);
 }
@@ -204,7 +202,7 @@ size_t table_doubles(const Dims& d, bool open) {
   if (pm)
     t += 2 * r2((size_t)(H + 1) * 64) + r2((size_t)3 * PM_ENTRIES) + r2(PM_ENTRIES) +
          r2((size_t)d.ncol * NOPS * PM_OPSZ) + r2((size_t)d.ncol * 3 * PM_ENTRIES) + r2((size_t)3 * PM_ENTRIES);
-  if (pm && open) t += r2((size_t)d.ncol * 3 * PM_ENTRIES) + r2((size_t)d.ncol * 3);
+  if (open) t += r2((size_t)d.ncol * 3) + r2((size_t)d.ncol * 3 * NY) + (pm ? r2((size_t)d.ncol * 3 * PM_ENTRIES) : 0);
   if (pm) t += r2((size_t)d.ncol * PM_ENTRIES) + r2((size_t)d.ncol * 4);
   return t;
 }
@@ -848,7 +846,6 @@ size_t chan_env_footprint_bytes(const chan_grid_t* grid, const chan_opts_t* opts
     const int jk = sensing_node(d, ph, o.extra_obs_y_plus[k], &ypn);
     if (jk < 0 || jk >= d.N) return 0;
   }
-  if (!geometry_supported(d, ph, generic_forced())) return 0;
   if (!pressure_supported(d, o, generic_forced())) return 0;
   return buffer_sizes(d, table_doubles(d, ph.open)).total;
 }
@@ -874,8 +871,6 @@ int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_
     if (js_planes[1 + k] < 0 || js_planes[1 + k] >= d.N)
       return fail(CHAN_EINVAL, "extra observation plane not inside the channel");
   }
-  if (!geometry_supported(d, ph, generic_forced()))
-    return fail(CHAN_EINVAL, "the open channel (free-slip top) needs ny <= 65 and the parity-major column kernel");
   if (!pressure_supported(d, o, generic_forced()))
     return fail(CHAN_EINVAL, "the pressure observable needs ny <= 65 and the parity-major column kernel");
 
@@ -987,6 +982,7 @@ int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_
   s.up_pm = s.tab + L.up_pm;
   s.pt_pm = s.tab + L.pt_pm;
   s.ptinv = s.tab + L.ptinv;
+  s.pt = s.tab + L.pt;
   s.pk_pm = s.tab + L.pk_pm;
   s.pkinv = s.tab + L.pkinv;
   {

@@ -146,9 +146,11 @@ struct ColArgs {
   int stage;            // 0, 1, 2; -1: reconstruct only (after reset / set_state)
   int wall_mode;
   double s_ramp;
-  double lam0, ab, gb, zb;
-  double nu, opp_alpha, ub2, px;
+  double lam0, ab, gb, zb;       // built with nu' = nu ys^2 (the Chebyshev variable's)
+  double nu, opp_alpha, ub2, px; // nu: nu ys, the wall-shear factor of d/dxi
   int forcing, js, accumulate_drag;
+  int open;                      // free-slip top: phi_+ corrections and the d^2v row
+  double ys, ysi;                // d/dy = ys d/dxi
   int recon;            // 0: skip the reconstruction for the next stage
   size_t plane;         // elements per field in F6 / H3 (ny * nkx * nz)
   cplx *vS, *oS, *hist;
@@ -158,6 +160,7 @@ struct ColArgs {
   const cplx *vw_old, *vw_new;
   cplx *vw_opp, *tauw;
   const double *cosk, *rc, *optab, *vt, *minv, *up, *inv_int_up, *alpha, *beta;
+  const double *pt, *ptinv;      // open channel: phi_+ per pair and stage [c][r][n], 1/dphi_+/dxi(+1)
   double* drag_acc;
   int* status;
 };
@@ -364,6 +367,9 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
 
   const double al = A.alpha[p], be = A.beta[q];
   const double k2 = al * al + be * be;
+  // the solve works in xi: wavenumbers / ys (exact, ys a power of two)
+  const double als = al * A.ysi, bes = be * A.ysi;
+  const double k2s = als * als + bes * bes;
   const size_t col = (size_t)c * NY;
 
   cplx vv[NS], oo[NS];  // state after this call (v, omega_y) or (U + iW, 0) for the mean
@@ -401,7 +407,7 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
       // (b) explicit terms h_v = -k^2 H2 - D(i al H1 + i be H3), h_g = i be H1 - i al H3
       for (int e = lane; e <= N; e += 64) {
         const cplx h1 = B[0][e], h3 = B[2][e];
-        B[3][e] = cmuli(make_double2(al * h1.x + be * h3.x, al * h1.y + be * h3.y));
+        B[3][e] = cmuli(make_double2(als * h1.x + bes * h3.x, als * h1.y + bes * h3.y));
       }
       wave_sync();
       cplx hv[NS], hg[NS], hvp[NS], hgp[NS];
@@ -412,7 +418,7 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
         if (e <= N) {
           const cplx dT = (e < N) ? cheb_d1<N>(B[3], e) : cz();
           const cplx h1 = B[0][e], h2 = B[1][e], h3 = B[2][e];
-          hv[s] = csub(cscale(h2, -k2), dT);
+          hv[s] = csub(cscale(h2, -k2s), dT);
           hg[s] = cmuli(make_double2(be * h1.x - al * h3.x, be * h1.y - al * h3.y));
           if (r > 0) {
             hvp[s] = A.hist[col + e];
@@ -436,8 +442,8 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
         const int e = lane + 64 * s;
         phi0[s] = chi[s] = cz();
         if (e <= N) {
-          phi0[s] = caxpy(cheb_d2<N>(B[4], e), -k2, B[4][e]);
-          chi[s] = caxpy(cheb_d2<N>(B[5], e), -k2, B[5][e]);
+          phi0[s] = caxpy(cheb_d2<N>(B[4], e), -k2s, B[4][e]);
+          chi[s] = caxpy(cheb_d2<N>(B[5], e), -k2s, B[5][e]);
           B[6][e] = phi0[s];
         }
       }
@@ -447,7 +453,7 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
       for (int s = 0; s < NS; ++s) {
         const int e = lane + 64 * s;
         if (e <= N) {
-          const cplx psi = caxpy(cheb_d2<N>(B[6], e), -k2, phi0[s]);
+          const cplx psi = caxpy(cheb_d2<N>(B[6], e), -k2s, phi0[s]);
           cplx rp = cscale(phi0[s], -A.lam0);
           rp = caxpy(rp, -A.ab, psi);
           rp = caxpy(rp, -A.gb, hv[s]);
@@ -518,7 +524,8 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
         if (e <= N) {
           vp[s] = tau_value<N>(B[3], TAB, SC + 4, e);
           const double n2 = (double)e * (double)e;
-          dtop = caxpy(dtop, n2, vp[s]);
+          // top row: dv/dxi(+1) (wall) or d^2v/dxi^2(+1) = sum n^2 (n^2 - 1)/3 v_n (surface)
+          dtop = caxpy(dtop, A.open ? n2 * (n2 - 1.0) / 3.0 : n2, vp[s]);
           dbot = caxpy(dbot, (e & 1) ? n2 : -n2, vp[s]);
         }
       }
@@ -528,6 +535,16 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
       const cplx c0 = make_double2(-(mi[0] * dtop.x + mi[1] * dbot.x), -(mi[0] * dtop.y + mi[1] * dbot.y));
       const cplx c1 = make_double2(-(mi[2] * dtop.x + mi[3] * dbot.x), -(mi[2] * dtop.y + mi[3] * dbot.y));
       const double* vt = A.vt + ((size_t)c * 3 + r) * NY;
+      // free-slip top: omega_y += c phi_+ with c = -(domega/dxi)(+1) / (dphi_+/dxi)(+1)
+      cplx cw = cz();
+      const double* ptc = A.open ? A.pt + ((size_t)c * 3 + r) * NY : nullptr;
+      if (A.open) {
+        cplx dw = cz();
+        for (int e = lane; e <= N; e += 64) dw = caxpy(dw, (double)e * (double)e, B[7][e]);
+        dw = wave_sum(dw);
+        const double pinv = A.ptinv[(size_t)c * 3 + r];
+        cw = make_double2(-dw.x * pinv, -dw.y * pinv);
+      }
       bool ok = true;
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
@@ -537,7 +554,7 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
           const double t = vt[e];
           const double b = (e & 1) ? -t : t;
           vv[s] = caxpy(caxpy(vp[s], t, c0), b, c1);
-          oo[s] = B[7][e];
+          oo[s] = A.open ? caxpy(B[7][e], ptc[e], cw) : B[7][e];
           A.vS[col + e] = vv[s];
           A.oS[col + e] = oo[s];
           if (partner >= 0) {
@@ -593,10 +610,29 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
       for (int s = 0; s < NS; ++s) {
         const int e = lane + 64 * s;
         xs[s] = cz();
-        if (e <= N) {
-          xs[s] = tau_value<N>(B[3], TAB, SC, e);
-          if (!(e & 1)) flux = fma(2.0 / (1.0 - (double)e * (double)e), xs[s].x, flux);
+        if (e <= N) xs[s] = tau_value<N>(B[3], TAB, SC, e);
+      }
+      if (A.open) {  // dU/dxi(+1) = dW/dxi(+1) = 0: add c phi_+ (k = 0)
+        cplx ds = cz();
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const int e = lane + 64 * s;
+          if (e <= N) ds = caxpy(ds, (double)e * (double)e, xs[s]);
         }
+        ds = wave_sum(ds);
+        const double pinv = A.ptinv[r];
+        const cplx cu = make_double2(-ds.x * pinv, -ds.y * pinv);
+        const double* pt0 = A.pt + (size_t)r * NY;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const int e = lane + 64 * s;
+          if (e <= N) xs[s] = caxpy(xs[s], pt0[e], cu);
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int e = lane + 64 * s;
+        if (e <= N && !(e & 1)) flux = fma(2.0 / (1.0 - (double)e * (double)e), xs[s].x, flux);
       }
       flux = wave_sum(flux);
       const double P_r = (A.forcing == 0) ? (A.ub2 - flux) * A.inv_int_up[r] : A.px;
@@ -658,10 +694,11 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
       const int e = lane + 64 * s;
       uu[s] = ww[s] = cz();
       if (e <= N) {
-        const cplx dv = (e < N) ? cheb_d1<N>(B[0], e) : cz();
+        const cplx dv = (e < N) ? cheb_d1<N>(B[0], e) : cz();  // dv/dxi; dv/dy = ys dv/dxi
         const cplx om = oo[s];
-        uu[s] = cscale(cmuli(make_double2(al * dv.x - be * om.x, al * dv.y - be * om.y)), ik2);
-        ww[s] = cscale(cmuli(make_double2(be * dv.x + al * om.x, be * dv.y + al * om.y)), ik2);
+        const double aly = al * A.ys, bey = be * A.ys;
+        uu[s] = cscale(cmuli(make_double2(aly * dv.x - be * om.x, aly * dv.y - be * om.y)), ik2);
+        ww[s] = cscale(cmuli(make_double2(bey * dv.x + al * om.x, bey * dv.y + al * om.y)), ik2);
         const double n2 = (double)e * (double)e;
         tau_hat = caxpy(tau_hat, (e & 1) ? n2 : -n2, uu[s]);
       }
@@ -684,8 +721,8 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
         const cplx du = (e < N) ? cheb_d1<N>(B[2], e) : cz();
         const cplx dw = (e < N) ? cheb_d1<N>(B[3], e) : cz();
         const cplx v = vv[s];
-        B[4][e] = csub(dw, cmuli(cscale(v, be)));
-        B[5][e] = csub(cmuli(cscale(v, al)), du);
+        B[4][e] = csub(cscale(dw, A.ys), cmuli(cscale(v, be)));
+        B[5][e] = csub(cmuli(cscale(v, al)), cscale(du, A.ys));
         B[6][e] = oo[s];
       }
     }
@@ -709,8 +746,8 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
         slope = fma((e & 1) ? n2 : -n2, X.x, slope);
         B[2][e] = make_double2(X.x, 0.0);
         B[3][e] = make_double2(X.y, 0.0);
-        B[4][e] = make_double2(dX.y, 0.0);
-        B[5][e] = make_double2(-dX.x, 0.0);
+        B[4][e] = make_double2(A.ys * dX.y, 0.0);
+        B[5][e] = make_double2(-(A.ys * dX.x), 0.0);
         B[6][e] = cz();
       }
     }
@@ -774,7 +811,10 @@ int launch_column_pass(const Dims& d, DeviceState& s, const PhysParams& ph, int 
   A.ab = sc.ab;
   A.gb = sc.gb;
   A.zb = sc.zb;
-  A.nu = ph.nu;
+  A.nu = ph.nu * ph.ys;
+  A.open = ph.open;
+  A.ys = ph.ys;
+  A.ysi = 1.0 / ph.ys;
   A.opp_alpha = opp_alpha;
   A.ub2 = 2.0 * ph.ub;
   A.px = ph.px;
@@ -798,6 +838,8 @@ int launch_column_pass(const Dims& d, DeviceState& s, const PhysParams& ph, int 
   A.optab = s.optab;
   A.vt = s.vt;
   A.minv = s.minv;
+  A.pt = s.pt;
+  A.ptinv = s.ptinv;
   A.up = s.up;
   A.inv_int_up = s.inv_int_up;
   A.alpha = s.alpha;

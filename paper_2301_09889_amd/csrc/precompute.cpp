@@ -180,9 +180,11 @@ void precompute_tables(const Dims& d, const PhysParams& ph, HostTables* out) {
   L.op_pm = take(pm ? (size_t)d.ncol * NOPS * PM_OPSZ : 0);
   L.vt_pm = take(pm ? (size_t)d.ncol * 3 * PM_ENTRIES : 0);
   L.up_pm = take(pm ? (size_t)3 * PM_ENTRIES : 0);
-  const bool open = pm && ph.open;
-  L.pt_pm = take(open ? (size_t)d.ncol * 3 * PM_ENTRIES : 0);
+  const bool open = ph.open;
+  L.pt_pm = take(open && pm ? (size_t)d.ncol * 3 * PM_ENTRIES : 0);
   L.ptinv = take(open ? (size_t)d.ncol * 3 : 0);
+  // natural order, for the general kernel (which CHANENV_GENERIC_COLUMN can select at any N)
+  L.pt = take(open ? (size_t)d.ncol * 3 * NY : 0);
   L.pk_pm = take(pm ? (size_t)d.ncol * PM_ENTRIES : 0);
   L.pkinv = take(pm ? (size_t)d.ncol * 4 : 0);
   L.total = o;
@@ -251,7 +253,10 @@ void precompute_tables(const Dims& d, const PhysParams& ph, HostTables* out) {
       // phi_+: (D^2 - lam) phi = 0, phi(+1) = 1, phi(-1) = 0
       host_tau_solve(d, base + (size_t)r * 2 * d.opsz, rc, zero.data(), 1.0, 0.0, phi.data());
       if (open) {
-        for (int n = 0; n <= N; ++n) T[L.pt_pm + ((size_t)c * 3 + r) * PM_ENTRIES + pm_slot(N, n)] = phi[n];
+        for (int n = 0; n <= N; ++n) {
+          if (pm) T[L.pt_pm + ((size_t)c * 3 + r) * PM_ENTRIES + pm_slot(N, n)] = phi[n];
+          T[L.pt + ((size_t)c * 3 + r) * NY + n] = phi[n];
+        }
         T[L.ptinv + (size_t)c * 3 + r] = 1.0 / slope_top(phi.data());
       }
       if (c == 0) continue;

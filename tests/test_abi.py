@@ -70,10 +70,11 @@ def test_grid_validation_and_footprint():
         assert b.chan_env_footprint_bytes(bad) == 0
     o = b.chan_opts_default()
     assert o.clip == 1.0 and o.opp_alpha == 1.0 and o.obs_mask == 3
-    # open channel: extra per-pair tables on the N <= 64 kernels; refused for ny > 65
+    # open channel: extra per-pair tables, on both column kernels
     o.top_bc = b.CHAN_TOP_FREESLIP
     assert b.chan_env_footprint_bytes(good, o) > fp
-    assert b.chan_env_footprint_bytes(b.ChanGrid(8, 97, 8, 2.67, 0.8, 180.0, 0.05, 15.0), o) == 0
+    g97 = b.ChanGrid(8, 97, 8, 2.67, 0.8, 180.0, 0.05, 15.0)
+    assert b.chan_env_footprint_bytes(g97, o) > b.chan_env_footprint_bytes(g97)
     # y+ 181 lies above the open channel's surface (y+ 180), inside the closed channel
     top = b.ChanGrid(16, 65, 16, 2.67, 0.8, 180.0, 0.05, 181.0)
     assert b.chan_env_footprint_bytes(top) > 0 and b.chan_env_footprint_bytes(top, o) == 0
@@ -97,14 +98,12 @@ def test_grid_validation_and_footprint():
     assert b.chan_env_footprint_bytes(g97, b.make_opts(obs_mask=11)) == 0
 
 
-def test_open_channel_refused_on_the_general_kernel_without_device():
+def test_pressure_refused_on_the_general_kernel_without_device():
     b = ensure_built()
-    o = b.chan_opts_default()
-    o.top_bc = b.CHAN_TOP_FREESLIP
     with pytest.raises(b.ChanError) as ei:
-        b.chan_env_create(b.ChanGrid(8, 97, 8, 2.67, 0.8, 180.0, 0.05, 15.0), o)
+        b.chan_env_create(b.ChanGrid(8, 97, 8, 2.67, 0.8, 180.0, 0.05, 15.0), b.make_opts(obs_mask=9))
     assert ei.value.code == b.CHAN_EINVAL
-    assert "open channel" in str(ei.value)
+    assert "pressure" in str(ei.value)
 
 
 def test_create_rejects_invalid_grid_without_device():

@@ -33,6 +33,7 @@ def test_open_minimal_channel_opposition_100_steps():
     ((4, 17, 8), ch.HOLD, ch.CPG, 7),
     ((32, 33, 16), ch.RAMP, ch.CFR, 5),
     ((16, 65, 32), ch.RAMP, ch.CPG, 2),
+    ((8, 97, 8), ch.HOLD, ch.CFR, 1),      # general column kernel (N = 96)
 ])
 def test_open_external_actions_small_grids(shape, mode, forcing, mask):
     nx, ny, nz = shape
@@ -42,6 +43,15 @@ def test_open_external_actions_small_grids(shape, mode, forcing, mask):
     acts = [gaussian_action(1000 + k, nz, nx) * 4.0 for k in range(3)]  # some values clip
     acts[1][0, 0] = 5.0
     run_pair(cfg, 7, acts, 2, 1e-11)
+
+
+def test_open_channel_on_the_general_kernel(monkeypatch):
+    """The general column kernel (forced for N = 64 by CHANENV_GENERIC_COLUMN=1, read at
+    creation) on the open minimal channel with opposition control, one and ten time steps."""
+    monkeypatch.setenv("CHANENV_GENERIC_COLUMN", "1")
+    cfg = minimal_channel(top_bc=OPEN, controller=ch.CTRL_OPPOSITION, obs_mask=7)
+    run_pair(cfg, 1, [None], 1, 1e-12)
+    run_pair(cfg, 1, [None], 10, 1e-11)
 
 
 def test_open_larger_channel_one_step():
