@@ -92,7 +92,7 @@ typedef struct {
   double clip;          /* [1.0] |action| bound in u_tau (§3.2); <= 0 disables clipping */
   uint32_t obs_mask;    /* [CHAN_OBS_U | CHAN_OBS_V] observed components (§3.2, §4.2); with
                            CHAN_OBS_P the static-pressure fluctuation p - <p>_plane (abstract:
-                           velocity and pressure observable), which needs ny <= 65 */
+                           velocity and pressure observable) */
   int32_t ic_profile;   /* [CHAN_IC_LAMINAR] mean profile of chan_env_reset | CHAN_IC_REICHARDT */
   double ic_amp;        /* [0.1] rms of the reset perturbation as a fraction of U_cl = 1.5 U_b */
   int32_t n_extra_planes;  /* [0] further observation planes, 0 .. CHAN_MAX_EXTRA_PLANES */

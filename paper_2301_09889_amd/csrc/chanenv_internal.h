@@ -42,9 +42,9 @@ struct TableLayout {
   // open channel only: phi_+ of every pair and stage (parity-major for N <= 64, natural order
   // above) and 1/(dphi_+/dxi)(+1)
   size_t pt_pm, ptinv, pt;
-  // pressure: phi_+ of (D^2 - k^2/ys^2) per pair (parity-major) and the inverse of the 2x2
-  // Neumann matrix (dphi_+-/dxi at +-1)
-  size_t pk_pm, pkinv;
+  // pressure: phi_+ of (D^2 - k^2/ys^2) per pair (parity-major for N <= 64, and natural
+  // order for the general kernel) and the inverse of the 2x2 Neumann matrix (dphi_+-/dxi at +-1)
+  size_t pk_pm, pkinv, pk;
   size_t total;
 };
 
@@ -94,7 +94,7 @@ struct DeviceState {
   int *status;                  // [1]
   // views into tab
   const double *cosk, *rc, *optab, *vt, *minv, *up, *inv_int_up, *alpha, *beta;
-  const double *kfwd, *kinv, *rc_pm, *intw_pm, *op_pm, *vt_pm, *up_pm, *pt_pm, *ptinv, *pt, *pk_pm, *pkinv;
+  const double *kfwd, *kinv, *rc_pm, *intw_pm, *op_pm, *vt_pm, *up_pm, *pt_pm, *ptinv, *pt, *pk_pm, *pkinv, *pk;
   cplx *pbuf;                   // [MAX_PLANES][nkx][nz] pressure spectra on the observation planes
   double *pscr;                 // [MAX_PLANES][3][nz][nx] u, v, w on the pressure planes
   const cplx *twz, *twx, *twnx, *twnz;
@@ -232,6 +232,9 @@ int launch_finish_step(const StepChan* d_step, int nch, hipStream_t st, KernelTi
 // Pressure on the observation planes from the end-of-step state (H3 holds its non-linear term).
 int launch_pressure_pm(const Dims& d, const ColChan* d_col, int nch, const ColStage& S, hipStream_t st,
                        KernelTimer* tm);
+// The same with the general column kernel, for one channel.
+int launch_pressure_generic(const Dims& d, const DeviceState& s, const PhysParams& ph, int n_planes,
+                            const int* js_planes, bool ramp, int n_sub, hipStream_t st, KernelTimer* tm);
 // p = P - (|u|^2/2 - its plane mean) on every pressure plane, after the output transforms.
 int launch_pressure_finish(const StepChan* d_step, int nch, hipStream_t st, KernelTimer* tm);
 int launch_outputs(const StepChan* d_step, int nch, int max_nx, int max_nz, int max_nkx, int nslots, hipStream_t st,

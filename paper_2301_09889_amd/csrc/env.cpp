@@ -156,11 +156,6 @@ int sensing_node(const Dims& d, const PhysParams& ph, double yplus, double* node
   return js;
 }
 
-// The pressure observable runs on the N <= 64 column kernels only (both geometries run on both
-// column kernels).
-bool pressure_supported(const Dims& d, const chan_opts_t& o, bool force_generic) {
-  return !(o.obs_mask & CHAN_OBS_P) || (d.N <= 64 && !force_generic);
-}
 
 bool generic_forced() {
   const char* g = std::getenv("CHANENV_GENERIC_COLUMN");
@@ -203,7 +198,7 @@ size_t table_doubles(const Dims& d, bool open) {
     t += 2 * r2((size_t)(H + 1) * 64) + r2((size_t)3 * PM_ENTRIES) + r2(PM_ENTRIES) +
          r2((size_t)d.ncol * NOPS * PM_OPSZ) + r2((size_t)d.ncol * 3 * PM_ENTRIES) + r2((size_t)3 * PM_ENTRIES);
   if (open) t += r2((size_t)d.ncol * 3) + r2((size_t)d.ncol * 3 * NY) + (pm ? r2((size_t)d.ncol * 3 * PM_ENTRIES) : 0);
-  if (pm) t += r2((size_t)d.ncol * PM_ENTRIES) + r2((size_t)d.ncol * 4);
+  t += r2((size_t)d.ncol * 4) + r2((size_t)d.ncol * NY) + (pm ? r2((size_t)d.ncol * PM_ENTRIES) : 0);
   return t;
 }
 
@@ -659,8 +654,21 @@ int batch_step(chan_batch* b, int32_t na, const int32_t* idx, const double* cons
       if (!has) continue;
       if (launch_plane_pass(g.d, g.d_plane, g.nact, g.tiles, st, tm))
         return fail(CHAN_EDEVICE, "launch plane pass (pressure)", hipGetLastError());
-      if (launch_pressure_pm(g.d, g.d_col, g.nact, S_end, st, tm))
-        return fail(CHAN_EDEVICE, "launch pressure", hipGetLastError());
+      if (g.pm) {
+        if (launch_pressure_pm(g.d, g.d_col, g.nact, S_end, st, tm))
+          return fail(CHAN_EDEVICE, "launch pressure", hipGetLastError());
+      } else {
+        for (int k = 0; k < g.nact; ++k) {
+          if (g.h_col[k].n_pplanes == 0) continue;
+          const chan_env* e = nullptr;
+          for (int i : g.members)
+            if (b->col[i].vS == g.h_col[k].vS) e = b->envs[i];
+          if (!e) continue;
+          const bool ramp = e->opts.controller == CHAN_CTRL_EXTERNAL && e->opts.action_mode == CHAN_RAMP;
+          if (launch_pressure_generic(e->d, e->s, e->ph, e->n_planes, e->js_planes, ramp, n_substeps, st, tm))
+            return fail(CHAN_EDEVICE, "launch pressure", hipGetLastError());
+        }
+      }
     }
   if (launch_finish_step(ds, na, st, tm)) return fail(CHAN_EDEVICE, "launch finish_step", hipGetLastError());
   const int nslots = any_pressure ? 1 + SLOTS_PER_PLANE * max_planes : SLOTS_PER_PLANE * max_planes - 3;
@@ -846,7 +854,6 @@ size_t chan_env_footprint_bytes(const chan_grid_t* grid, const chan_opts_t* opts
     const int jk = sensing_node(d, ph, o.extra_obs_y_plus[k], &ypn);
     if (jk < 0 || jk >= d.N) return 0;
   }
-  if (!pressure_supported(d, o, generic_forced())) return 0;
   return buffer_sizes(d, table_doubles(d, ph.open)).total;
 }
 
@@ -871,8 +878,6 @@ int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_
     if (js_planes[1 + k] < 0 || js_planes[1 + k] >= d.N)
       return fail(CHAN_EINVAL, "extra observation plane not inside the channel");
   }
-  if (!pressure_supported(d, o, generic_forced()))
-    return fail(CHAN_EINVAL, "the pressure observable needs ny <= 65 and the parity-major column kernel");
 
   HostTables ht;
   try {
@@ -985,6 +990,7 @@ int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_
   s.pt = s.tab + L.pt;
   s.pk_pm = s.tab + L.pk_pm;
   s.pkinv = s.tab + L.pkinv;
+  s.pk = s.tab + L.pk;
   {
     hipError_t err = hipMemsetAsync(e->dev_block, 0, z.total, e->stream);
     const char* what = "hipMemsetAsync";

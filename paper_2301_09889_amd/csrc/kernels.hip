@@ -18,6 +18,8 @@
 // Everything is FP64 (the method is chaotic and the tau systems are stiff); nothing is
 // a dense contraction, so there is no MFMA here.
 
+#include <cstring>
+
 #include "device_common.h"
 
 namespace chanenv {
@@ -783,6 +785,194 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
   if (want_end && lane == 0) {
     A.tauw[c] = tau_hat;
     if (partner >= 0) A.tauw[partner] = cconj(tau_hat);
+  }
+}
+
+// Pressure on the observation planes, general column kernel (one wavefront per pair, column
+// data in LDS): the same Poisson problem as the parity-major pressure kernel,
+//   (D_xi^2 - k^2/ys^2) P = (i (al H1 + be H3)/ys + D_xi H2)/ys,
+//   dP/dxi(+-1) = (H2 + nu ys^2 (D_xi^2 - k^2/ys^2) v - [lower wall] dv_w/dt)/ys,
+// solved as the zero-value tau solution plus c_+ phi_+ + c_- phi_-, then evaluated at each
+// plane's node.  The pair (0, 0) is set to zero.
+struct PressGenArgs {
+  int nkx, nz, ncol, n_pplanes;
+  int pjs[MAX_PLANES];
+  int ramp;                 // ramped external action: its slope enters the lower-wall condition
+  double rate_scale;        // 1 / (n_sub dt)
+  double ys, ysi, nu_xi;    // nu_xi = nu ys^2
+  size_t plane;
+  const cplx *H3, *vS, *vw_old, *vw_new;
+  cplx* pbuf;
+  const double *cosk, *rc, *optab, *alpha, *beta, *pk, *pkinv;
+};
+
+template <int N>
+__global__ __launch_bounds__(64 * wpb<N>()) void k_pressure_gen(PressGenArgs A) {
+  constexpr int WPB = wpb<N>();
+  using P = CP<N>;
+  constexpr int NY = P::NY;
+  constexpr int NS = P::NS;
+  constexpr int H = N / 2;
+  extern __shared__ double dyn_lds[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c = blockIdx.x * WPB + wave;
+  if (c >= A.ncol) return;
+  const int nz = A.nz;
+  const int p = c / nz, q = c - p * nz;
+  if (q == nz / 2) return;
+  if (p == 0 && q > nz / 2) return;
+  const int partner = (p == 0 && q > 0) ? (nz - q) : -1;
+  const size_t pstride = (size_t)A.nkx * nz;
+  if (c == 0) {
+    if (lane < A.n_pplanes) A.pbuf[(size_t)lane * pstride] = cz();
+    return;
+  }
+  double* wb = dyn_lds + (size_t)wave * P::WAVE_DOUBLES;
+  cplx* B[P::NB];
+#pragma unroll
+  for (int k = 0; k < P::NB; ++k) B[k] = reinterpret_cast<cplx*>(wb + (size_t)k * P::NYP * 2);
+  double* TAB = wb + (size_t)P::NB * P::NYP * 2;
+  cplx* SC = reinterpret_cast<cplx*>(TAB + 2 * P::OPSZ);
+  const double al = A.alpha[p], be = A.beta[q];
+  const double als = al * A.ysi, bes = be * A.ysi;
+  const double k2s = als * als + bes * bes;
+  for (int e = lane; e < NY; e += 64) {
+    const size_t o = ((size_t)e * A.nkx + p) * nz + q;
+    B[0][e] = A.H3[o];
+    B[1][e] = A.H3[A.plane + o];
+    B[2][e] = A.H3[2 * A.plane + o];
+  }
+  wave_sync();
+  const cplx H2_top = B[1][0], H2_bot = B[1][N];  // node values at y = +1 and -1
+  wave_sync();
+  cplx hc[3][NS];
+  dct_forward<N, 3>(B, A.cosk, lane, hc);
+  wave_sync();
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int e = lane + 64 * s;
+    if (e <= N) {
+      B[0][e] = hc[0][s];
+      B[1][e] = hc[1][s];
+      B[2][e] = hc[2][s];
+    }
+  }
+  wave_sync();
+  for (int e = lane; e <= N; e += 64) {
+    const cplx dH2 = (e < N) ? cheb_d1<N>(B[1], e) : cz();
+    const cplx h1 = B[0][e], h3 = B[2][e];
+    const cplx ab = cmuli(make_double2(als * h1.x + bes * h3.x, als * h1.y + bes * h3.y));
+    B[3][e] = cscale(cadd(dH2, ab), A.ysi);
+  }
+  {
+    const double* src = A.optab + ((size_t)c * NOPS + 3) * 2 * P::OPSZ;
+    for (int t = lane; t < 2 * P::OPSZ; t += 64) TAB[t] = src[t];
+  }
+  wave_sync();
+  for (int e = lane; e <= N; e += 64) B[4][e] = tau_rows<N>(B[3], A.rc, e);
+  wave_sync();
+  if (lane < 2) SC[lane] = tau_chain<N>(B[4], TAB + lane * P::OPSZ, lane, cz(), B[5]);
+  wave_sync();
+  cplx Pd[NS];
+  cplx dPt = cz(), dPb = cz(), d2vt = cz(), d2vb = cz(), vt0 = cz(), vb0 = cz();
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int e = lane + 64 * s;
+    Pd[s] = cz();
+    if (e <= N) {
+      Pd[s] = tau_value<N>(B[5], TAB, SC, e);
+      const double n2 = (double)e * (double)e;
+      const double sg = (e & 1) ? -1.0 : 1.0;
+      const double w2 = n2 * (n2 - 1.0) / 3.0;  // T_n''(1)
+      const cplx v = A.vS[(size_t)c * NY + e];
+      dPt = caxpy(dPt, n2, Pd[s]);
+      dPb = caxpy(dPb, -sg * n2, Pd[s]);
+      d2vt = caxpy(d2vt, w2, v);
+      d2vb = caxpy(d2vb, sg * w2, v);
+      vt0 = cadd(vt0, v);
+      vb0 = caxpy(vb0, sg, v);
+    }
+  }
+  dPt = wave_sum(dPt);
+  dPb = wave_sum(dPb);
+  d2vt = wave_sum(d2vt);
+  d2vb = wave_sum(d2vb);
+  vt0 = wave_sum(vt0);
+  vb0 = wave_sum(vb0);
+  cplx rate = cz();
+  if (A.ramp) rate = cscale(csub(A.vw_new[c], A.vw_old[c]), A.rate_scale);
+  const cplx g_top = cscale(caxpy(H2_top, A.nu_xi, caxpy(d2vt, -k2s, vt0)), A.ysi);
+  const cplx g_bot = cscale(csub(caxpy(H2_bot, A.nu_xi, caxpy(d2vb, -k2s, vb0)), rate), A.ysi);
+  const cplx r_top = csub(g_top, dPt), r_bot = csub(g_bot, dPb);
+  const double* mi = A.pkinv + (size_t)c * 4;
+  const cplx c0 = make_double2(mi[0] * r_top.x + mi[1] * r_bot.x, mi[0] * r_top.y + mi[1] * r_bot.y);
+  const cplx c1 = make_double2(mi[2] * r_top.x + mi[3] * r_bot.x, mi[2] * r_top.y + mi[3] * r_bot.y);
+  const double* pk = A.pk + (size_t)c * NY;
+  for (int k = 0; k < A.n_pplanes; ++k) {
+    const int j = A.pjs[k];
+    const bool flip = j > H;
+    const int jj = flip ? N - j : j;
+    cplx part = cz();
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int e = lane + 64 * s;
+      if (e <= N) {
+        const double sg = (e & 1) ? -1.0 : 1.0;
+        const cplx Pe = caxpy(caxpy(Pd[s], pk[e], c0), sg * pk[e], c1);
+        part = caxpy(part, A.cosk[(size_t)jj * (N + 1) + e] * (flip ? sg : 1.0), Pe);
+      }
+    }
+    const cplx val = wave_sum(part);
+    if (lane == 0) {
+      A.pbuf[(size_t)k * pstride + (size_t)p * nz + q] = val;
+      if (partner >= 0) A.pbuf[(size_t)k * pstride + partner] = cconj(val);
+    }
+  }
+}
+
+template <int N>
+static int launch_pgen(const PressGenArgs& A, hipStream_t st, KernelTimer* tm) {
+  constexpr int WPB = wpb<N>();
+  const int blocks = (A.ncol + WPB - 1) / WPB;
+  const size_t shm = (size_t)WPB * CP<N>::WAVE_DOUBLES * sizeof(double);
+  TIMED_LAUNCH(tm, KC_OUTPUT, st, k_pressure_gen<N>, dim3(blocks), dim3(64 * WPB), shm, st, A);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_pressure_generic(const Dims& d, const DeviceState& s, const PhysParams& ph, int n_planes,
+                            const int* js_planes, bool ramp, int n_sub, hipStream_t st, KernelTimer* tm) {
+  PressGenArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.nkx = d.nkx;
+  A.nz = d.nz;
+  A.ncol = d.ncol;
+  A.n_pplanes = n_planes;
+  for (int k = 0; k < n_planes && k < MAX_PLANES; ++k) A.pjs[k] = js_planes[k];
+  A.ramp = ramp ? 1 : 0;
+  A.rate_scale = 1.0 / ((double)n_sub * ph.dt);
+  A.ys = ph.ys;
+  A.ysi = 1.0 / ph.ys;
+  A.nu_xi = ph.nu_xi();
+  A.plane = (size_t)d.ny * d.nkx * d.nz;
+  A.H3 = s.H3;
+  A.vS = s.vS;
+  A.vw_old = s.vw_old;
+  A.vw_new = s.vw_new;
+  A.pbuf = s.pbuf;
+  A.cosk = s.cosk;
+  A.rc = s.rc;
+  A.optab = s.optab;
+  A.alpha = s.alpha;
+  A.beta = s.beta;
+  A.pk = s.pk;
+  A.pkinv = s.pkinv;
+  switch (d.N) {
+    case 16: return launch_pgen<16>(A, st, tm);
+    case 32: return launch_pgen<32>(A, st, tm);
+    case 64: return launch_pgen<64>(A, st, tm);
+    case 96: return launch_pgen<96>(A, st, tm);
+    case 128: return launch_pgen<128>(A, st, tm);
+    default: return -1;
   }
 }
 

@@ -186,7 +186,8 @@ void precompute_tables(const Dims& d, const PhysParams& ph, HostTables* out) {
   // natural order, for the general kernel (which CHANENV_GENERIC_COLUMN can select at any N)
   L.pt = take(open ? (size_t)d.ncol * 3 * NY : 0);
   L.pk_pm = take(pm ? (size_t)d.ncol * PM_ENTRIES : 0);
-  L.pkinv = take(pm ? (size_t)d.ncol * 4 : 0);
+  L.pkinv = take((size_t)d.ncol * 4);
+  L.pk = take((size_t)d.ncol * NY);
   L.total = o;
   std::vector<double>& T = out->data;
   T.assign(L.total, 0.0);
@@ -231,7 +232,7 @@ void precompute_tables(const Dims& d, const PhysParams& ph, HostTables* out) {
     double* base = &T[L.optab + (size_t)c * NOPS * 2 * d.opsz];
     for (int r = 0; r < 3; ++r) fill_record(d, k2 + lam0[r], base + (size_t)r * 2 * d.opsz);
     fill_record(d, k2, base + (size_t)3 * 2 * d.opsz);
-    if (pm && c > 0) {
+    if (c > 0) {
       // pressure: phi_+ of (D^2 - k'^2), phi_+(+1) = 1, phi_+(-1) = 0, and the inverse of the
       // Neumann matrix [dphi_+(+1), dphi_-(+1); dphi_+(-1), dphi_-(-1)] (phi_- its mirror)
       host_tau_solve(d, base + (size_t)3 * 2 * d.opsz, rc, zero.data(), 1.0, 0.0, phi.data());
@@ -247,7 +248,10 @@ void precompute_tables(const Dims& d, const PhysParams& ph, HostTables* out) {
       mi[1] = b / det;
       mi[2] = -b / det;
       mi[3] = a / det;
-      for (int n = 0; n <= N; ++n) T[L.pk_pm + (size_t)c * PM_ENTRIES + pm_slot(N, n)] = phi[n];
+      for (int n = 0; n <= N; ++n) {
+        if (pm) T[L.pk_pm + (size_t)c * PM_ENTRIES + pm_slot(N, n)] = phi[n];
+        T[L.pk + (size_t)c * NY + n] = phi[n];
+      }
     }
     for (int r = 0; r < 3; ++r) {
       // phi_+: (D^2 - lam) phi = 0, phi(+1) = 1, phi(-1) = 0

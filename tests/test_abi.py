@@ -90,20 +90,11 @@ def test_grid_validation_and_footprint():
         assert b.chan_env_footprint_bytes(good, o) == 0, bad
     with pytest.raises(ValueError):
         b.make_opts(extra_obs_y_plus=[1.0, 2.0, 3.0, 4.0])
-    # pressure (bit 3): on the N_y <= 65 kernels only; no bits above it
+    # pressure (bit 3), on both column kernels; no bits above it
     assert b.chan_env_footprint_bytes(good, b.make_opts(obs_mask=15)) > 0
     assert b.chan_env_footprint_bytes(good, b.make_opts(obs_mask=16)) == 0
     g97 = b.ChanGrid(8, 97, 8, 2.67, 0.8, 180.0, 0.05, 15.0)
-    assert b.chan_env_footprint_bytes(g97) > 0
-    assert b.chan_env_footprint_bytes(g97, b.make_opts(obs_mask=11)) == 0
-
-
-def test_pressure_refused_on_the_general_kernel_without_device():
-    b = ensure_built()
-    with pytest.raises(b.ChanError) as ei:
-        b.chan_env_create(b.ChanGrid(8, 97, 8, 2.67, 0.8, 180.0, 0.05, 15.0), b.make_opts(obs_mask=9))
-    assert ei.value.code == b.CHAN_EINVAL
-    assert "pressure" in str(ei.value)
+    assert b.chan_env_footprint_bytes(g97, b.make_opts(obs_mask=11)) > 0
 
 
 def test_create_rejects_invalid_grid_without_device():

@@ -60,3 +60,14 @@ def test_pressure_ramped_actions(top_bc):
 def test_pressure_larger_channel_one_step():
     cfg = larger_channel(obs_mask=15)
     run_pressure(cfg, 1, [gaussian_action(1001, 64, 64)], 1, 1e-12)
+
+
+def test_pressure_general_kernel(monkeypatch):
+    """The general column kernel's pressure step: N_y = 97 (open channel, ramped actions), and
+    forced at N_y = 65 (CHANENV_GENERIC_COLUMN=1, read at creation) with opposition control."""
+    cfg = ch.Config(nx=8, ny=97, nz=8, lx=2.67, lz=0.8, re_tau=180.0, dt_plus=0.05, obs_y_plus=15.0,
+                    obs_mask=15, top_bc=ch.TOP_FREESLIP, extra_obs_y_plus=(3.0, 60.0))
+    acts = [gaussian_action(4000 + k, cfg.nz, cfg.nx) * 3.0 for k in range(2)]
+    run_pressure(cfg, 6, acts, 2, 1e-11)
+    monkeypatch.setenv("CHANENV_GENERIC_COLUMN", "1")
+    run_pressure(minimal_channel(controller=ch.CTRL_OPPOSITION, obs_mask=15), 0, [None], 2, 1e-11)
