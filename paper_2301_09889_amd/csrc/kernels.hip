@@ -299,35 +299,74 @@ __device__ __forceinline__ cplx tau_rows(const cplx* f, const double* __restrict
   return r;
 }
 
-// Serial even/odd elimination of one parity s of a tau system (run on one lane).
-// tab: the (operator, parity) record {w, u, f, F, 1/sum F}.  Writes E_i to E[2i+s]
-// (i >= 1) and returns x_0 = (g - sum E_i) / sum F_i.
-template <int N>
-__device__ __forceinline__ cplx tau_chain(const cplx* R, const double* tab, int s, cplx g, cplx* E) {
+// Even/odd elimination of both parities of K tau systems that share one operator record
+// {w, u, f, F, 1/sum F} per parity, on the whole wavefront: lane l takes index i = l + 1
+// (i <= m = (N - s)/2 <= 64).  The bottom-up
+// recurrence e_i = w_i R_{2i+s} - u_i e_{i+1} (e_{m+1} = 0) is the affine suffix composition of
+// (a_i, b_i) = (w_i R_{2i+s}, -u_i), the top-down one E_i = e_i + f_i E_{i-1} (E_0 = 0) the
+// affine prefix composition of (e_i, f_i); each is a six-step Hillis-Steele scan over lanes.
+// Writes E_i to E[k][2i+s] and x0[2k+s] = (g[2k+s] - sum_i E_i) / sum F_i.
+template <int N, int K>
+__device__ __forceinline__ void tau_chain_wave(cplx* const* R, const double* TAB, const cplx* g, cplx* const* E,
+                                               cplx* x0, int lane) {
   constexpr int ML = N / 2 + 1;
-  const int m = (N - s) / 2;
-  const double* w = tab;
-  const double* u = tab + ML;
-  const double* fr = tab + 2 * ML;
-  cplx e = cz();
+  constexpr int OPSZ = 4 * ML + 2;
+  static_assert(N / 2 <= 64, "one lane per elimination index");
+  const int i = lane + 1;
 #pragma unroll
-  for (int i = N / 2; i >= 1; --i) {
-    if (i <= m) {
-      const cplx r = R[2 * i + s];
-      e = make_double2(fma(w[i], r.x, -u[i] * e.x), fma(w[i], r.y, -u[i] * e.y));
-      E[2 * i + s] = e;
+  for (int s = 0; s < 2; ++s) {
+    const double* tab = TAB + s * OPSZ;
+    const int m = (N - s) / 2;
+    const bool act = i <= m;
+    const double w = act ? tab[i] : 0.0, u = act ? tab[ML + i] : 0.0, f = act ? tab[2 * ML + i] : 0.0;
+    cplx a[K];
+    double b[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      a[k] = act ? cscale(R[k][2 * i + s], w) : cz();
+      b[k] = act ? -u : 0.0;
+    }
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const bool in = i + d <= m;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const double ax = __shfl_down(a[k].x, d, 64), ay = __shfl_down(a[k].y, d, 64);
+        const double bn = __shfl_down(b[k], d, 64);
+        if (in) {
+          a[k] = make_double2(fma(b[k], ax, a[k].x), fma(b[k], ay, a[k].y));
+          b[k] *= bn;
+        } else {
+          b[k] = 0.0;
+        }
+      }
+    }
+    // a[k] = e_i; now the prefix scan E_i = e_i + f_i E_{i-1}
+    double gg[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) gg[k] = act ? f : 0.0;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const bool in = i - d >= 1;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const double cx = __shfl_up(a[k].x, d, 64), cy = __shfl_up(a[k].y, d, 64);
+        const double gn = __shfl_up(gg[k], d, 64);
+        if (in) {
+          a[k] = make_double2(fma(gg[k], cx, a[k].x), fma(gg[k], cy, a[k].y));
+          gg[k] *= gn;
+        } else {
+          gg[k] = 0.0;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (act) E[k][2 * i + s] = a[k];
+      const cplx sum = wave_sum(act ? a[k] : cz());
+      x0[2 * k + s] = cscale(csub(g[2 * k + s], sum), tab[4 * ML]);
     }
   }
-  cplx Ei = cz(), sum = cz();
-#pragma unroll
-  for (int i = 1; i <= N / 2; ++i) {
-    if (i <= m) {
-      Ei = caxpy(E[2 * i + s], fr[i], Ei);
-      E[2 * i + s] = Ei;
-      sum = cadd(sum, Ei);
-    }
-  }
-  return cscale(csub(g, sum), tab[4 * ML]);
 }
 
 // Value of element e of a tau solution: x_e = E_e + F_{e/2} x0_{parity(e)}.
@@ -480,12 +519,15 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
         B[3][e] = tau_rows<N>(B[1], A.rc, e);
       }
       wave_sync();
-      // (e) phi_p and omega_y: four serial recurrences on lanes 0..3
-      if (lane < 4) {
-        const int s = lane & 1;
-        const bool isom = lane >= 2;
-        const cplx x0 = tau_chain<N>(isom ? B[3] : B[2], TAB + s * P::OPSZ, s, cz(), isom ? B[5] : B[4]);
-        SC[lane] = x0;
+      // (e) phi_p and omega_y: both parities of both systems as wave-wide scans
+      {
+        cplx* const Rs[2] = {B[2], B[3]};
+        cplx* const Es[2] = {B[4], B[5]};
+        const cplx g0[4] = {cz(), cz(), cz(), cz()};
+        cplx x0[4];
+        tau_chain_wave<N, 2>(Rs, TAB, g0, Es, x0, lane);
+        if (lane == 0)
+          for (int t = 0; t < 4; ++t) SC[t] = x0[t];
       }
       wave_sync();
       for (int e = lane; e <= N; e += 64) {
@@ -509,11 +551,17 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
       }
       for (int e = lane; e <= N; e += 64) B[2][e] = tau_rows<N>(B[6], A.rc, e);
       wave_sync();
-      if (lane < 2) {
-        const int s = lane;
+      {
         // even part (g_top + g_bot)/2, odd part (g_top - g_bot)/2 with g_top = 0, g_bot = v_w
-        const cplx g = cscale(vw, s == 0 ? 0.5 : -0.5);
-        SC[4 + s] = tau_chain<N>(B[2], TAB + s * P::OPSZ, s, g, B[3]);
+        cplx* const Rs[1] = {B[2]};
+        cplx* const Es[1] = {B[3]};
+        const cplx gv[2] = {cscale(vw, 0.5), cscale(vw, -0.5)};
+        cplx x0[2];
+        tau_chain_wave<N, 1>(Rs, TAB, gv, Es, x0, lane);
+        if (lane == 0) {
+          SC[4] = x0[0];
+          SC[5] = x0[1];
+        }
       }
       wave_sync();
       // (g) influence-matrix correction: Dv(+1) = Dv(-1) = 0
@@ -604,7 +652,17 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
       wave_sync();
       for (int e = lane; e <= N; e += 64) B[2][e] = tau_rows<N>(B[0], A.rc, e);
       wave_sync();
-      if (lane < 2) SC[lane] = tau_chain<N>(B[2], TAB + lane * P::OPSZ, lane, cz(), B[3]);
+      {
+        cplx* const Rs[1] = {B[2]};
+        cplx* const Es[1] = {B[3]};
+        const cplx g0[2] = {cz(), cz()};
+        cplx x0[2];
+        tau_chain_wave<N, 1>(Rs, TAB, g0, Es, x0, lane);
+        if (lane == 0) {
+          SC[0] = x0[0];
+          SC[1] = x0[1];
+        }
+      }
       wave_sync();
       cplx xs[NS];
       double flux = 0.0;
@@ -871,7 +929,17 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_pressure_gen(PressGenArgs A) 
   wave_sync();
   for (int e = lane; e <= N; e += 64) B[4][e] = tau_rows<N>(B[3], A.rc, e);
   wave_sync();
-  if (lane < 2) SC[lane] = tau_chain<N>(B[4], TAB + lane * P::OPSZ, lane, cz(), B[5]);
+  {
+    cplx* const Rs[1] = {B[4]};
+    cplx* const Es[1] = {B[5]};
+    const cplx g0[2] = {cz(), cz()};
+    cplx x0[2];
+    tau_chain_wave<N, 1>(Rs, TAB, g0, Es, x0, lane);
+    if (lane == 0) {
+      SC[0] = x0[0];
+      SC[1] = x0[1];
+    }
+  }
   wave_sync();
   cplx Pd[NS];
   cplx dPt = cz(), dPb = cz(), d2vt = cz(), d2vb = cz(), vt0 = cz(), vb0 = cz();
