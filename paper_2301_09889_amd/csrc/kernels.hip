@@ -167,32 +167,43 @@ struct ColArgs {
   int* status;
 };
 
-// D on coefficients, output element e < N:  (2/c_e) sum_{p > e, p+e odd} p X_p.
+// D on coefficients held in registers, element e = lane + 64 s in slot s (zero above N):
+//   b_e = (2/c_e) sum_{p > e, p + e odd} p a_p = (2/c_e) W(e + 1),  W(e) = sum_{k >= 0} y_{e+2k},
+// y_p = p a_p.  W is a stride-2 suffix sum: a five-step scan within each slot (offsets 2 .. 32
+// keep the parity), plus the same-parity totals of the higher slots; b_N = 0.  Wave-uniform.
 template <int N>
-__device__ __forceinline__ cplx cheb_d1(const cplx* X, int e) {
-  cplx acc = cz();
+__device__ __forceinline__ void cheb_d1_reg(const cplx* x, cplx* out, int lane) {
+  constexpr int NS = CP<N>::NS;
+  cplx w[NS];
 #pragma unroll
-  for (int k = 0; k < (N + 1) / 2; ++k) {
-    const int pp = e + 1 + 2 * k;
-    if (pp <= N) acc = caxpy(acc, (double)pp, X[pp]);
+  for (int s = 0; s < NS; ++s) {
+    const int e = lane + 64 * s;
+    w[s] = (e <= N) ? cscale(x[s], (double)e) : cz();
   }
-  return cscale(acc, e == 0 ? 1.0 : 2.0);
-}
-
-// D^2 on coefficients, output element e <= N:  (1/c_e) sum_{p >= e+2, p+e even} p (p^2 - e^2) X_p.
-template <int N>
-__device__ __forceinline__ cplx cheb_d2(const cplx* X, int e) {
-  cplx acc = cz();
-  const double e2 = (double)e * (double)e;
 #pragma unroll
-  for (int k = 0; k < N / 2; ++k) {
-    const int pp = e + 2 + 2 * k;
-    if (pp <= N) {
-      const double dp = (double)pp;
-      acc = caxpy(acc, dp * (dp * dp - e2), X[pp]);
+  for (int d = 2; d < 64; d <<= 1) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const double nx = __shfl_down(w[s].x, d, 64), ny = __shfl_down(w[s].y, d, 64);
+      if (lane + d < 64) w[s] = make_double2(w[s].x + nx, w[s].y + ny);
     }
   }
-  return cscale(acc, e == 0 ? 0.5 : 1.0);
+  cplx carry = cz();
+#pragma unroll
+  for (int s = NS - 1; s >= 0; --s) {
+    const cplx tot = make_double2(__shfl(w[s].x, lane & 1, 64), __shfl(w[s].y, lane & 1, 64));
+    w[s] = cadd(w[s], carry);
+    carry = cadd(carry, tot);
+  }
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const double zx = __shfl_down(w[s].x, 1, 64), zy = __shfl_down(w[s].y, 1, 64);
+    cplx next = cz();
+    if (s + 1 < NS) next = make_double2(__shfl(w[s + 1 < NS ? s + 1 : s].x, 0, 64), __shfl(w[s + 1 < NS ? s + 1 : s].y, 0, 64));
+    const cplx z = (lane < 63) ? make_double2(zx, zy) : next;
+    const int e = lane + 64 * s;
+    out[s] = (e < N) ? cscale(z, e == 0 ? 1.0 : 2.0) : cz();
+  }
 }
 
 // Forward DCT-I of F nodal vectors X[f][0..N] (overwritten by the even/odd fold):
@@ -451,13 +462,19 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
         B[3][e] = cmuli(make_double2(als * h1.x + bes * h3.x, als * h1.y + bes * h3.y));
       }
       wave_sync();
-      cplx hv[NS], hg[NS], hvp[NS], hgp[NS];
+      cplx hv[NS], hg[NS], hvp[NS], hgp[NS], tT[NS], dTs[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int e = lane + 64 * s;
+        tT[s] = (e <= N) ? B[3][e] : cz();
+      }
+      cheb_d1_reg<N>(tT, dTs, lane);
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         const int e = lane + 64 * s;
         hv[s] = hg[s] = hvp[s] = hgp[s] = cz();
         if (e <= N) {
-          const cplx dT = (e < N) ? cheb_d1<N>(B[3], e) : cz();
+          const cplx dT = dTs[s];
           const cplx h1 = B[0][e], h2 = B[1][e], h3 = B[2][e];
           hv[s] = csub(cscale(h2, -k2s), dT);
           hg[s] = cmuli(make_double2(be * h1.x - al * h3.x, be * h1.y - al * h3.y));
@@ -477,24 +494,35 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
         B[5][e] = A.oS[col + e];
       }
       wave_sync();
-      cplx phi0[NS], chi[NS];
+      cplx phi0[NS], chi[NS], xv[NS], xo[NS], d1[NS], d2v[NS], d2o[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int e = lane + 64 * s;
+        xv[s] = (e <= N) ? B[4][e] : cz();
+        xo[s] = (e <= N) ? B[5][e] : cz();
+      }
+      cheb_d1_reg<N>(xv, d1, lane);
+      cheb_d1_reg<N>(d1, d2v, lane);
+      cheb_d1_reg<N>(xo, d1, lane);
+      cheb_d1_reg<N>(d1, d2o, lane);
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         const int e = lane + 64 * s;
         phi0[s] = chi[s] = cz();
         if (e <= N) {
-          phi0[s] = caxpy(cheb_d2<N>(B[4], e), -k2s, B[4][e]);
-          chi[s] = caxpy(cheb_d2<N>(B[5], e), -k2s, B[5][e]);
-          B[6][e] = phi0[s];
+          phi0[s] = caxpy(d2v[s], -k2s, xv[s]);
+          chi[s] = caxpy(d2o[s], -k2s, xo[s]);
         }
       }
-      wave_sync();
+      cplx d2p[NS];
+      cheb_d1_reg<N>(phi0, d1, lane);
+      cheb_d1_reg<N>(d1, d2p, lane);
       // (d) right-hand sides of the two Helmholtz problems with lam = k^2 + lam0
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         const int e = lane + 64 * s;
         if (e <= N) {
-          const cplx psi = caxpy(cheb_d2<N>(B[6], e), -k2s, phi0[s]);
+          const cplx psi = caxpy(d2p[s], -k2s, phi0[s]);
           cplx rp = cscale(phi0[s], -A.lam0);
           rp = caxpy(rp, -A.ab, psi);
           rp = caxpy(rp, -A.gb, hv[s]);
@@ -637,13 +665,21 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
         for (int t = lane; t < 2 * P::OPSZ; t += 64) TAB[t] = src[t];
       }
       wave_sync();
+      cplx xm[NS], dm1[NS], dm2[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int e = lane + 64 * s;
+        xm[s] = (e <= N) ? B[4][e] : cz();
+      }
+      cheb_d1_reg<N>(xm, dm1, lane);
+      cheb_d1_reg<N>(dm1, dm2, lane);
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         const int e = lane + 64 * s;
         if (e <= N) {
-          const cplx X = B[4][e];
+          const cplx X = xm[s];
           cplx rr = cscale(X, -A.lam0);
-          rr = caxpy(rr, -A.ab, cheb_d2<N>(B[4], e));
+          rr = caxpy(rr, -A.ab, dm2[s]);
           rr = caxpy(rr, -A.gb, hm[s]);
           rr = caxpy(rr, -A.zb, hmp[s]);
           B[0][e] = rr;
@@ -748,13 +784,14 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
     wave_sync();
     // u = (i al Dv - i be om)/k^2, w = (i be Dv + i al om)/k^2
     const double ik2 = 1.0 / k2;
-    cplx uu[NS], ww[NS];
+    cplx uu[NS], ww[NS], dvs[NS];
+    cheb_d1_reg<N>(vv, dvs, lane);  // dv/dxi; dv/dy = ys dv/dxi
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const int e = lane + 64 * s;
       uu[s] = ww[s] = cz();
       if (e <= N) {
-        const cplx dv = (e < N) ? cheb_d1<N>(B[0], e) : cz();  // dv/dxi; dv/dy = ys dv/dxi
+        const cplx dv = dvs[s];
         const cplx om = oo[s];
         const double aly = al * A.ys, bey = be * A.ys;
         uu[s] = cscale(cmuli(make_double2(aly * dv.x - be * om.x, aly * dv.y - be * om.y)), ik2);
@@ -774,12 +811,15 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
     }
     wave_sync();
     // omega_x = Dw - i be v, omega_z = i al v - Du
+    cplx dus[NS], dws[NS];
+    cheb_d1_reg<N>(uu, dus, lane);
+    cheb_d1_reg<N>(ww, dws, lane);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const int e = lane + 64 * s;
       if (e <= N) {
-        const cplx du = (e < N) ? cheb_d1<N>(B[2], e) : cz();
-        const cplx dw = (e < N) ? cheb_d1<N>(B[3], e) : cz();
+        const cplx du = dus[s];
+        const cplx dw = dws[s];
         const cplx v = vv[s];
         B[4][e] = csub(cscale(dw, A.ys), cmuli(cscale(v, be)));
         B[5][e] = csub(cmuli(cscale(v, al)), cscale(du, A.ys));
@@ -796,12 +836,14 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
     }
     wave_sync();
     double slope = 0.0;
+    cplx dXs[NS];
+    cheb_d1_reg<N>(vv, dXs, lane);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const int e = lane + 64 * s;
       if (e <= N) {
         const cplx X = vv[s];
-        const cplx dX = (e < N) ? cheb_d1<N>(B[0], e) : cz();
+        const cplx dX = dXs[s];
         const double n2 = (double)e * (double)e;
         slope = fma((e & 1) ? n2 : -n2, X.x, slope);
         B[2][e] = make_double2(X.x, 0.0);
@@ -916,11 +958,16 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_pressure_gen(PressGenArgs A) 
     }
   }
   wave_sync();
-  for (int e = lane; e <= N; e += 64) {
-    const cplx dH2 = (e < N) ? cheb_d1<N>(B[1], e) : cz();
-    const cplx h1 = B[0][e], h3 = B[2][e];
-    const cplx ab = cmuli(make_double2(als * h1.x + bes * h3.x, als * h1.y + bes * h3.y));
-    B[3][e] = cscale(cadd(dH2, ab), A.ysi);
+  cplx dH2s[NS];
+  cheb_d1_reg<N>(hc[1], dH2s, lane);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int e = lane + 64 * s;
+    if (e <= N) {
+      const cplx h1 = hc[0][s], h3 = hc[2][s];
+      const cplx ab = cmuli(make_double2(als * h1.x + bes * h3.x, als * h1.y + bes * h3.y));
+      B[3][e] = cscale(cadd(dH2s[s], ab), A.ysi);
+    }
   }
   {
     const double* src = A.optab + ((size_t)c * NOPS + 3) * 2 * P::OPSZ;
