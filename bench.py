@@ -31,6 +31,7 @@ FP64_PEAK_TFS = 78.6
 
 LARGER = dict(nx=64, ny=65, nz=64, lx=2 * np.pi, lz=np.pi, re_tau=180.0, dt_plus=0.05, obs_y_plus=15.0)
 MINIMAL = dict(nx=16, ny=65, nz=16, lx=2.67, lz=0.8, re_tau=180.0, dt_plus=0.05, obs_y_plus=15.0)
+RE395 = dict(nx=128, ny=97, nz=128, lx=2 * np.pi, lz=np.pi, re_tau=395.0, dt_plus=0.05, obs_y_plus=15.0)
 
 
 # HBM bytes per launch on the larger channel, from two rocprofv3 --pmc runs of
@@ -69,7 +70,7 @@ def resolved_points(g):
     return (g["nx"] // 2) * (g["nz"] - 1) * g["ny"]
 
 
-def algorithmic_bytes_per_launch(kclass, g):
+def algorithmic_bytes_per_launch(kclass, g, n_sub=10):
     """Minimum HBM bytes one launch of a kernel class must move, from the
     two-layout pass model: 16 K bytes per complex field pass.  The column solve
     reads H (3 fields), v and omega_y (2) and, from the second stage on, the
@@ -77,8 +78,14 @@ def algorithmic_bytes_per_launch(kclass, g):
     two stages): 9 2/3 passes per launch on average over the three stages.  The
     column reconstruction reads v, omega_y (2) and writes the six node fields for
     the plane pass (6); run in the same launch as the solve it reads nothing more
-    (15 2/3 passes for both).  Precomputed operator tables are not counted."""
+    (15 2/3 passes for both).  Precomputed operator tables are not counted.  The general
+    column kernel (N_y > 65) runs solve and reconstruction in one launch of the column_pass
+    class except at the last stage of an env step: the mean over the 3 n_sub launches."""
     K = resolved_points(g)
+    if kclass == "column_pass" and g["ny"] > 65:
+        solve, both = 3 + 2 + 2.0 / 3.0 * 2 + 2 + 2.0 / 3.0 * 2, 3 + 2 + 2.0 / 3.0 * 2 + 2 + 2.0 / 3.0 * 2 + 6
+        n = 3 * n_sub
+        return ((n - 1) * both + solve) / n * 16.0 * K
     if kclass == "column_pass":
         return (3 + 2 + 2.0 / 3.0 * 2 + 2 + 2.0 / 3.0 * 2) * 16.0 * K
     if kclass == "column_reconstruct":
@@ -355,7 +362,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100, help="timed env steps")
     ap.add_argument("--warmup", type=int, default=5, help="untimed env steps")
     ap.add_argument("--substeps", type=int, default=10, help="RK3 time steps per env step")
-    ap.add_argument("--workload", choices=["larger", "minimal", "batched", "served"], default="larger")
+    ap.add_argument("--workload", choices=["larger", "minimal", "re395", "batched", "served"], default="larger")
     ap.add_argument("--workers", type=int, default=512, help="workers (one channel each) of the served workload")
     ap.add_argument("--rates", default="200,1000,4000", help="offered request rates (1/s) of the served sweep")
     ap.add_argument("--requests", type=int, default=600, help="requests per rate of the served sweep")
@@ -389,8 +396,12 @@ def main():
     if args.workload == "served":
         run_served(args, torch, b, gaussian_action)
         return
-    g = LARGER if args.workload == "larger" else MINIMAL
-    if args.workload == "larger":
+    g = {"larger": LARGER, "minimal": MINIMAL, "re395": RE395}[args.workload]
+    if args.workload == "re395":
+        opts_kw = dict(ic_profile=1, action_mode=1)
+        workload = ("channel at Re_tau 395, 2pi x 2 x pi (h), 128x97x128 modes (general column kernel), "
+                    "dt+ 0.05, seeded Gaussian wall action sigma 0.1 u_tau held for 10 time steps, obs u,v at y+ 15")
+    elif args.workload == "larger":
         opts_kw = dict(ic_profile=1, action_mode=1)    # Reichardt mean; action held over the env step
         workload = ("larger channel 2pi x 2 x pi (h), 64x65x64 modes, Re_tau 180, dt+ 0.05, seeded Gaussian "
                     "wall action sigma 0.1 u_tau held for 10 time steps, obs u,v at y+ 15")
@@ -409,7 +420,7 @@ def main():
     n_act = args.warmup + 2 * args.steps
     acts = torch.stack([torch.tensor(gaussian_action(1000 + args.seed + k, g["nz"], g["nx"]),
                                      dtype=torch.float64) for k in range(n_act)]).cuda()
-    use_action = args.workload == "larger"
+    use_action = args.workload in ("larger", "re395")
     for k in range(args.warmup):
         env.step(acts[k] if use_action else None, args.substeps)
     torch.cuda.synchronize()
@@ -438,7 +449,7 @@ def main():
     dom = max((k for k in kt if kt[k][0] > 0), key=lambda k: kt[k][1])
     n_launch, ms = kt[dom]
     avg_s = ms / 1e3 / n_launch
-    alg = algorithmic_bytes_per_launch(dom, g)
+    alg = algorithmic_bytes_per_launch(dom, g, args.substeps)
     achieved = alg / avg_s / 1e9 if alg else None
     roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
@@ -490,7 +501,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_probe_bytes_each_way"] = src.numel() * 8
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload != "re395":  # one oracle time step takes minutes there
         out["cpu_baseline"] = cpu_baseline(g, opts_kw, args.substeps, args.seed, args.cpu_substeps)
     else:
         out["cpu_baseline"] = None
