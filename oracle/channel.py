@@ -40,8 +40,8 @@ paper's solver is built on, named where used):
   more wall-parallel planes).  Wall-shear stress at the lower wall, and the drag as
   its plane mean averaged over the time steps between two actions (§3.2).
 
-Readings where the paper is silent are listed in the design doc's table of
-readings; the code states each where it is used.
+Where the paper is silent the code states the reading it takes where it is
+used.
 """
 from dataclasses import dataclass
 

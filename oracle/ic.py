@@ -4,8 +4,7 @@ TEST INFRASTRUCTURE: see ``oracle/__init__.py``.
 
 The paper starts every episode from one of six stored turbulent fields
 (§3.3, §4.2), which are not available here; a seeded synthetic field with the
-paper's grid and Reynolds number stands in.  Recipe (a reading, stated in
-the design doc's input recipe):
+paper's grid and Reynolds number stands in.  Recipe (a reading):
 
 * mean profile: laminar U = 1.5 U_b (1 - r^2) with r the distance from the
   centreline of the closed channel (r = xi) or from the surface of the open
