@@ -318,6 +318,253 @@ __global__ __launch_bounds__(1024) void k_xrow2(const PlaneChan* __restrict__ ch
   }
 }
 
+// ---------------------------------------------------------------------------
+// Small grids (M_z = M_x = 24): the whole plane pass of one node in one block, the z-inverse
+// output and the x-row products kept in LDS instead of Z6 / W3.  Every phase is the
+// corresponding phase of k_zinv2, k_xrow2 (all M_z/2 pairs of rows) and k_zfwd2 with the same
+// operations in the same order, so the results are bitwise those of the three launches; what
+// goes is two kernel boundaries and the Z6 / W3 round trips, which dominate these small planes.
+// Block: channel * N_y + node.
+// ---------------------------------------------------------------------------
+template <int MZ, int MX>
+struct SmallPlane {
+  static constexpr int NKX = MX / 3;
+  static constexpr int P = MZ / 2;                 // pairs of z rows
+  static constexpr int LPZ = FftLds<MZ>::LS, APZ = FftLds<MZ>::AP;
+  static constexpr int LPX = FftLds<MX>::LS;
+  static constexpr int SCR_A = 6 * NKX * LPZ, SCR_B = 6 * P * LPX, SCR_C = 3 * NKX * LPZ;
+  static constexpr int SCR = (SCR_A > SCR_B ? (SCR_A > SCR_C ? SCR_A : SCR_C) : (SCR_B > SCR_C ? SCR_B : SCR_C));
+  static constexpr int LDS_CPLX = MZ + MX + 6 * MZ * NKX + SCR + 3 * MZ;
+  static constexpr int THREADS = ((6 * P * FftPlan<MX>::A + 63) / 64) * 64;
+};
+
+template <int MZ, int MX>
+__global__ __launch_bounds__((SmallPlane<MZ, MX>::THREADS)) void k_plane_small(const PlaneChan* __restrict__ chans,
+                                                                             int ny) {
+  using SP = SmallPlane<MZ, MX>;
+  constexpr int NKX = SP::NKX, P = SP::P, LPZ = SP::LPZ, APZ = SP::APZ;
+  constexpr int ZA = FftPlan<MZ>::A, ZB = FftPlan<MZ>::B;
+  constexpr int XA = FftPlan<MX>::A, XB = FftPlan<MX>::B;
+  constexpr int LPX = FftLds<MX>::LS, APX = FftLds<MX>::AP;
+  static_assert(XA >= XB, "x pass 1 has at most one task per thread");
+  extern __shared__ double dyn_lds[];
+  cplx* twz = reinterpret_cast<cplx*>(dyn_lds);
+  cplx* twx = twz + MZ;
+  cplx* ZW = twx + MX;             // Z [f][zz][p] (z inverse), later W [g][zz][p] (x-row output)
+  cplx* SCR = ZW + 6 * MZ * NKX;   // pass scratch of each phase
+  cplx* X0 = SCR + SP::SCR;        // [g][q]: the p = 0 pencils, for the Hermitian fix
+  const PlaneChan A = chans[blockIdx.x / ny];
+  const bool skip = (*A.status & STATUS_BAD_ACTION) != 0;  // tested at the stores
+  const int j = blockIdx.x % ny;
+  const int nz = A.nz, h = nz / 2;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  for (int t = tid; t < MZ; t += nthr) twz[t] = A.twz[t];
+  for (int t = tid; t < MX; t += nthr) twx[t] = A.twx[t];
+  __syncthreads();
+
+  // A. z inverse of every (field, p) pencil (k_zinv2)
+  for (int task = tid; task < 6 * NKX * ZB; task += nthr) {
+    const int f = task / (NKX * ZB), rem = task - f * NKX * ZB;
+    const int p = rem / ZB, n2 = rem - p * ZB;
+    const cplx* src = A.F6 + (((size_t)f * A.ny + j) * NKX + p) * nz;
+    cplx t[ZA];
+#pragma unroll
+    for (int n1 = 0; n1 < ZA; ++n1) {
+      const int zz = ZB * n1 + n2;
+      const int q = (zz < h) ? zz : ((zz > MZ - h) ? zz - MZ + nz : -1);
+      t[n1] = (q >= 0) ? src[q] : cz();
+    }
+    Dft<ZA, 1>::run(t);
+    cplx* y = SCR + (f * NKX + p) * LPZ + n2 * APZ;
+#pragma unroll
+    for (int k1 = 0; k1 < ZA; ++k1) y[k1] = twiddle<MZ, 1>(t[k1], twz, n2 * k1);
+  }
+  __syncthreads();
+  for (int task = tid; task < 6 * ZA * NKX; task += nthr) {
+    const int f = task / (ZA * NKX), rem = task - f * ZA * NKX;
+    const int k1 = rem / NKX, p = rem - k1 * NKX;
+    cplx u[ZB];
+#pragma unroll
+    for (int n2 = 0; n2 < ZB; ++n2) u[n2] = SCR[(f * NKX + p) * LPZ + n2 * APZ + k1];
+    Dft<ZB, 1>::run(u);
+#pragma unroll
+    for (int k2 = 0; k2 < ZB; ++k2) ZW[(f * MZ + k1 + ZA * k2) * NKX + p] = u[k2];
+  }
+  __syncthreads();
+
+  // B. x rows, all pairs (k_xrow2 with pair0 = 0); S = SCR [field][pair][LPX]
+  cplx* S = SCR;
+  for (int it = tid; it < 6 * P * NKX; it += nthr) {
+    const int seq = it / NKX, m = it - seq * NKX;
+    const int f = seq / P, pr = seq - f * P;
+    const cplx* ra = ZW + (f * MZ + 2 * pr) * NKX;
+    cplx xa = ra[m], xb = ra[NKX + m];
+    if (m == 0) {
+      xa.y = 0.0;
+      xb.y = 0.0;
+    }
+    S[seq * LPX + m] = make_double2(xa.x - xb.y, xa.y + xb.x);
+    S[seq * LPX + NKX + m] = make_double2(xa.x + xb.y, xb.x - xa.y);
+  }
+  __syncthreads();
+  {
+    const int task = tid;
+    const bool have = task < 6 * P * XB;
+    const int seq = task / XB, n2 = task - seq * XB;
+    cplx t[XA];
+    if (have) {
+      const cplx* z = S + seq * LPX;
+#pragma unroll
+      for (int n1 = 0; n1 < XA; ++n1) {
+        const int k = XB * n1 + n2;
+        t[n1] = (k < NKX) ? z[k] : ((k > MX - NKX) ? z[NKX + (MX - k)] : cz());
+      }
+    }
+    __syncthreads();
+    if (have) {
+      Dft<XA, 1>::run(t);
+      cplx* y = S + seq * LPX + n2 * APX;
+#pragma unroll
+      for (int k1 = 0; k1 < XA; ++k1) y[k1] = twiddle<MX, 1>(t[k1], twx, n2 * k1);
+    }
+  }
+  __syncthreads();
+  {
+    const int ntask = 6 * P * XA;
+    cplx X[XB];
+    int base = 0, k1 = 0;
+    const bool have = tid < ntask;
+    if (have) {
+      const int seq = tid / XA;
+      k1 = tid - seq * XA;
+      base = seq * LPX;
+#pragma unroll
+      for (int n2 = 0; n2 < XB; ++n2) X[n2] = S[base + n2 * APX + k1];
+      Dft<XB, 1>::run(X);
+    }
+    __syncthreads();
+    if (have) {
+#pragma unroll
+      for (int k2 = 0; k2 < XB; ++k2) S[base + k1 + XA * k2] = X[k2];
+    }
+  }
+  __syncthreads();
+  for (int task = tid; task < P * MX; task += nthr) {
+    const int pr = task / MX, x = task - pr * MX;
+    const cplx U = S[(0 * P + pr) * LPX + x], V = S[(1 * P + pr) * LPX + x], W = S[(2 * P + pr) * LPX + x];
+    const cplx OX = S[(3 * P + pr) * LPX + x], OY = S[(4 * P + pr) * LPX + x], OZ = S[(5 * P + pr) * LPX + x];
+    S[(0 * P + pr) * LPX + x] = make_double2(V.x * OZ.x - W.x * OY.x, V.y * OZ.y - W.y * OY.y);
+    S[(1 * P + pr) * LPX + x] = make_double2(W.x * OX.x - U.x * OZ.x, W.y * OX.y - U.y * OZ.y);
+    S[(2 * P + pr) * LPX + x] = make_double2(U.x * OY.x - V.x * OX.x, U.y * OY.y - V.y * OX.y);
+  }
+  __syncthreads();
+  {
+    const int ntask = 3 * P * XB;
+    cplx t[XA];
+    int base = 0, n2 = 0;
+    const bool have = tid < ntask;
+    if (have) {
+      const int seq = tid / XB;
+      n2 = tid - seq * XB;
+      base = seq * LPX;
+#pragma unroll
+      for (int n1 = 0; n1 < XA; ++n1) t[n1] = S[base + XB * n1 + n2];
+      Dft<XA, -1>::run(t);
+    }
+    __syncthreads();
+    if (have) {
+#pragma unroll
+      for (int k1 = 0; k1 < XA; ++k1) S[base + n2 * APX + k1] = twiddle<MX, -1>(t[k1], twx, n2 * k1);
+    }
+  }
+  __syncthreads();
+  {
+    const int ntask = 3 * P * XA;
+    cplx X[XB];
+    int base = 0, k1 = 0;
+    const bool have = tid < ntask;
+    if (have) {
+      const int seq = tid / XA;
+      k1 = tid - seq * XA;
+      base = seq * LPX;
+#pragma unroll
+      for (int n2 = 0; n2 < XB; ++n2) X[n2] = S[base + n2 * APX + k1];
+      Dft<XB, -1>::run(X);
+    }
+    __syncthreads();
+    if (have) {
+#pragma unroll
+      for (int k2 = 0; k2 < XB; ++k2) S[base + k1 + XA * k2] = X[k2];
+    }
+  }
+  __syncthreads();
+  for (int task = tid; task < 3 * P * NKX; task += nthr) {
+    const int seq = task / NKX, k = task - seq * NKX;
+    const int g = seq / P, pr = seq - g * P;
+    const cplx Yk = S[seq * LPX + k];
+    const cplx Ym = cconj(S[seq * LPX + ((MX - k) % MX)]);
+    const cplx Xa = make_double2(0.5 * (Yk.x + Ym.x), 0.5 * (Yk.y + Ym.y));
+    const cplx Xb = make_double2(0.5 * (Yk.y - Ym.y), -0.5 * (Yk.x - Ym.x));
+    cplx* wa = ZW + (g * MZ + 2 * pr) * NKX;
+    wa[k] = Xa;
+    wa[NKX + k] = Xb;
+  }
+  __syncthreads();
+
+  // C. z forward of every (product, p) pencil, truncation, 1/(M_x M_z), Hermitian fix (k_zfwd2)
+  for (int task = tid; task < 3 * ZB * NKX; task += nthr) {
+    const int g = task / (ZB * NKX), rem = task - g * ZB * NKX;
+    const int n2 = rem / NKX, p = rem - n2 * NKX;
+    cplx t[ZA];
+#pragma unroll
+    for (int n1 = 0; n1 < ZA; ++n1) t[n1] = ZW[(g * MZ + ZB * n1 + n2) * NKX + p];
+    Dft<ZA, -1>::run(t);
+    cplx* y = SCR + (g * NKX + p) * LPZ + n2 * APZ;
+#pragma unroll
+    for (int k1 = 0; k1 < ZA; ++k1) y[k1] = twiddle<MZ, -1>(t[k1], twz, n2 * k1);
+  }
+  __syncthreads();
+  const double sc = A.scale;
+  for (int task = tid; task < 3 * NKX * ZA; task += nthr) {
+    const int g = task / (NKX * ZA), rem = task - g * NKX * ZA;
+    const int p = rem / ZA, k1 = rem - p * ZA;
+    cplx u[ZB];
+#pragma unroll
+    for (int n2 = 0; n2 < ZB; ++n2) u[n2] = SCR[(g * NKX + p) * LPZ + n2 * APZ + k1];
+    Dft<ZB, -1>::run(u);
+    cplx* dst = A.H3 + (((size_t)g * A.ny + j) * NKX + p) * nz;
+#pragma unroll
+    for (int k2 = 0; k2 < ZB; ++k2) {
+      const int zz = k1 + ZA * k2;
+      const int q = (zz < h) ? zz : ((zz > MZ - h) ? zz - MZ + nz : -1);
+      if (q < 0) continue;
+      const cplx v = cscale(u[k2], sc);
+      if (p == 0) {
+        X0[g * MZ + q] = v;
+      } else if (!skip) {
+        dst[q] = v;
+      }
+    }
+  }
+  __syncthreads();
+  if (!skip) {
+    for (int task = tid; task < 3 * nz; task += nthr) {
+      const int g = task / nz, q = task - g * nz;
+      const cplx* x0 = X0 + g * MZ;
+      cplx v = cz();
+      if (q == 0) {
+        v = make_double2(x0[0].x, 0.0);
+      } else if (q < h) {
+        v = x0[q];
+      } else if (q > h) {
+        v = cconj(x0[nz - q]);
+      }
+      A.H3[(((size_t)g * A.ny + j) * NKX) * nz + q] = v;
+    }
+  }
+  // Nyquist row q = N_z/2 stays zero (written once when the buffers are cleared).
+}
+
 // LDS of the x-row kernel with P pairs of rows per block, and its thread count.
 template <int MX>
 static size_t xrow_lds(int P) { return (size_t)(MX + (size_t)6 * P * FftLds<MX>::LS) * sizeof(cplx); }
@@ -327,6 +574,14 @@ static int xrow_threads(int P) { return ((6 * P * FftPlan<MX>::A + 63) / 64) * 6
 template <int MZ, int MX>
 static int launch_plane2(const Dims& d, const PlaneChan* chans, int nch, const PlaneTiles& t, hipStream_t st,
                          KernelTimer* tm) {
+  if constexpr (MZ == 24 && MX == 24) {  // one launch per stage for the small planes
+    using SP = SmallPlane<MZ, MX>;
+    if (d.nkx != SP::NKX) return -1;
+    const size_t shm = (size_t)SP::LDS_CPLX * sizeof(cplx);
+    timed_launch(tm, KC_XROW, k_plane_small<MZ, MX>, dim3((unsigned)(d.ny * nch)), dim3(SP::THREADS), shm, st,
+                 chans, d.ny);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+  }
   const int PB = t.PB, P = t.P;
   const int pairs = MZ / 2;
   if (PB < 1 || PB > d.nkx || P < 1 || pairs % P != 0 || xrow_threads<MX>(P) > 1024) return -1;
