@@ -42,9 +42,9 @@ RE395 = dict(nx=128, ny=97, nz=128, lx=2 * np.pi, lz=np.pi, re_tau=395.0, dt_plu
 # and is reported as null for any other source.
 TRAFFIC = {
     "column_solve_reconstruct": (5.0949e+07, "column_pass.hip", "588d9b7c0cd26dac0a9e2a9bdb6f14fb6987b4a4d9b3e5816f8e59a6fbc192e0"),
-    "x_rows_fft_product": (2.8928e+07, "plane_pass.hip", "e482b1f48e2a6f8d9e5db1ec2caed7bf6175f2d3da369d8adbf949a60b79ab53"),
-    "z_inverse_fft": (3.2061e+07, "plane_pass.hip", "e482b1f48e2a6f8d9e5db1ec2caed7bf6175f2d3da369d8adbf949a60b79ab53"),
-    "z_forward_fft": (1.6094e+07, "plane_pass.hip", "e482b1f48e2a6f8d9e5db1ec2caed7bf6175f2d3da369d8adbf949a60b79ab53"),
+    "x_rows_fft_product": (2.8928e+07, "plane_pass.hip", "568603a192e34b53e8317047b4929f10b9886cf4214356d0c7d1c83a21547e90"),
+    "z_inverse_fft": (3.2061e+07, "plane_pass.hip", "568603a192e34b53e8317047b4929f10b9886cf4214356d0c7d1c83a21547e90"),
+    "z_forward_fft": (1.6094e+07, "plane_pass.hip", "568603a192e34b53e8317047b4929f10b9886cf4214356d0c7d1c83a21547e90"),
     "column_pass": (3.5885e+07, "column_pass.hip", "588d9b7c0cd26dac0a9e2a9bdb6f14fb6987b4a4d9b3e5816f8e59a6fbc192e0"),
     "column_reconstruct": (1.8065e+07, "column_pass.hip", "588d9b7c0cd26dac0a9e2a9bdb6f14fb6987b4a4d9b3e5816f8e59a6fbc192e0"),
 }
