@@ -27,9 +27,12 @@ MINIMAL = dict(nx=16, ny=65, nz=16, lx=2.67, lz=0.8, re_tau=180.0, dt_plus=0.05)
 
 
 def run(y_plus=(10.0, 15.0), seeds=(0, 1, 2), n_env=6000, n_sub=10, window_start=1000, grid=LARGER,
-        progress=None, top_bc=b.CHAN_TOP_WALL):
+        progress=None, top_bc=b.CHAN_TOP_WALL, drop_failed=False):
     """Drag histories and drag reduction.  Returns a dict with, per case, the per-seed window
-    means, their mean, and DR against the uncontrolled case."""
+    means, their mean, and DR against the uncontrolled case.  A channel whose step fails (a
+    non-finite state: opposition control with alpha = 1 diverges from some initial fields)
+    raises, or with ``drop_failed`` is left out of its case's mean and listed under "failed"
+    (the batch advances the other channels)."""
     import torch
     cases = [("uncontrolled", 15.0, b.CHAN_CTRL_EXTERNAL)] + \
             [(f"opposition y+{yp:g}", float(yp), b.CHAN_CTRL_OPPOSITION) for yp in y_plus]
@@ -45,12 +48,15 @@ def run(y_plus=(10.0, 15.0), seeds=(0, 1, 2), n_env=6000, n_sub=10, window_start
     batch = b.ChanBatch(envs)
     hist = torch.zeros((len(envs), n_env), dtype=torch.float64, device=envs[0].obs.device)
     t0 = time.perf_counter()
+    failed = {}
     try:
         for k in range(n_env):
             codes = batch.step(None, n_sub)
-            bad = [labels[i] for i, c in enumerate(codes) if c != 0]
-            if bad:
-                raise RuntimeError(f"env step {k}: channels {bad} failed")
+            bad = [i for i, c in enumerate(codes) if c != 0 and labels[i] not in failed]
+            if bad and not drop_failed:
+                raise RuntimeError(f"env step {k}: channels {[labels[i] for i in bad]} failed")
+            for i in bad:
+                failed[labels[i]] = k
             for i, e in enumerate(envs):
                 hist[i, k] = e.drag[0]
             if progress and (k + 1) % 1000 == 0:
@@ -64,13 +70,15 @@ def run(y_plus=(10.0, 15.0), seeds=(0, 1, 2), n_env=6000, n_sub=10, window_start
            "window_env_steps": [window_start, n_env], "t_plus_per_env_step": n_sub * grid["dt_plus"],
            "seeds": list(seeds), "cases": {}}
     for name, _, _ in cases:
-        w = [float(h[i, window_start:].mean()) for i, (nm, _) in enumerate(labels) if nm == name]
-        out["cases"][name] = {"window_mean_per_seed": w, "mean": float(np.mean(w))}
+        w = [float(h[i, window_start:].mean()) for i, lab in enumerate(labels) if lab[0] == name and lab not in failed]
+        out["cases"][name] = {"window_mean_per_seed": w, "mean": float(np.mean(w)),
+                              "std_error": float(np.std(w, ddof=1) / np.sqrt(len(w))) if len(w) > 1 else None}
+    out["failed"] = [{"case": nm, "seed": sd, "env_step": k} for (nm, sd), k in failed.items()]
     ref = out["cases"]["uncontrolled"]["mean"]
     for c in out["cases"].values():
         c["drag_reduction"] = 1.0 - c["mean"] / ref
     out["elapsed_s"] = time.perf_counter() - t0
-    out["histories"] = {f"{nm} seed {s}": h[i].tolist() for i, (nm, s) in enumerate(labels)}
+    out["histories"] = {f"{nm} seed {s}": h[i].tolist() for i, (nm, s) in enumerate(labels) if (nm, s) not in failed}
     return out
 
 
@@ -83,11 +91,12 @@ def main():
     ap.add_argument("--grid", choices=["larger", "minimal"], default="larger")
     ap.add_argument("--top", choices=["wall", "freeslip"], default="wall")
     ap.add_argument("--histories", help="write the drag histories (JSON) to this file")
+    ap.add_argument("--drop-failed", action="store_true", help="leave diverged channels out instead of stopping")
     args = ap.parse_args()
     res = run(args.y_plus, args.seeds, args.env_steps, window_start=args.window_start,
               grid=LARGER if args.grid == "larger" else MINIMAL,
               top_bc=b.CHAN_TOP_FREESLIP if args.top == "freeslip" else b.CHAN_TOP_WALL,
-              progress=lambda k, t: print(f"env step {k} ({t:.0f} s)", flush=True))
+              progress=lambda k, t: print(f"env step {k} ({t:.0f} s)", flush=True), drop_failed=args.drop_failed)
     hist = res.pop("histories")
     if args.histories:
         with open(args.histories, "w") as fh:
