@@ -38,15 +38,15 @@ RE395 = dict(nx=128, ny=97, nz=128, lx=2 * np.pi, lz=np.pi, re_tau=395.0, dt_plu
 # "bench.py --steps 3 --warmup 1 --no-cpu-baseline --copy-probe" (FETCH_SIZE, then WRITE_SIZE,
 # KiB per dispatch; profiles/hbm_traffic_larger_channel.md).  FETCH_SIZE is scaled by 2.0 and
 # WRITE_SIZE by 1.0: what the two counters read for the 256 MiB device copy of --copy-probe
-# (131089 and 262144 KiB).  Each figure holds for the kernel source with the listed SHA-256
+# (131084 and 262144 KiB).  Each figure holds for the kernel source with the listed SHA-256
 # and is reported as null for any other source.
 TRAFFIC = {
-    "column_solve_reconstruct": (5.0949e+07, "column_pass.hip", "588d9b7c0cd26dac0a9e2a9bdb6f14fb6987b4a4d9b3e5816f8e59a6fbc192e0"),
+    "column_solve_reconstruct": (5.1015e+07, "column_pass.hip", "cf740114fb4c2f8c05006919f5bcde01668102fe97155613717bff17d30b1e93"),
     "x_rows_fft_product": (2.8928e+07, "plane_pass.hip", "568603a192e34b53e8317047b4929f10b9886cf4214356d0c7d1c83a21547e90"),
     "z_inverse_fft": (3.2061e+07, "plane_pass.hip", "568603a192e34b53e8317047b4929f10b9886cf4214356d0c7d1c83a21547e90"),
     "z_forward_fft": (1.6094e+07, "plane_pass.hip", "568603a192e34b53e8317047b4929f10b9886cf4214356d0c7d1c83a21547e90"),
-    "column_pass": (3.5885e+07, "column_pass.hip", "588d9b7c0cd26dac0a9e2a9bdb6f14fb6987b4a4d9b3e5816f8e59a6fbc192e0"),
-    "column_reconstruct": (1.8065e+07, "column_pass.hip", "588d9b7c0cd26dac0a9e2a9bdb6f14fb6987b4a4d9b3e5816f8e59a6fbc192e0"),
+    "column_pass": (3.5895e+07, "column_pass.hip", "cf740114fb4c2f8c05006919f5bcde01668102fe97155613717bff17d30b1e93"),
+    "column_reconstruct": (1.7936e+07, "column_pass.hip", "cf740114fb4c2f8c05006919f5bcde01668102fe97155613717bff17d30b1e93"),
 }
 
 
@@ -356,13 +356,96 @@ def run_served(args, torch, b, gaussian_action):
     print(json.dumps(out), flush=True)
 
 
+def run_scale(args, torch, b, gaussian_action):
+    """Batched and served at scale: 8 channels of 128x97x128 at Re_tau 395 and 64 minimal
+    channels in one request loop (continuous batching, admission by HBM footprint), every
+    channel advancing 2000 time steps in requests of args.substeps with Gaussian zero-net-flux
+    actions; closed loop (each channel submits its next request as soon as the last is done)."""
+    from paper_2301_09889_amd.serve import ChannelServer
+    torch.cuda.set_device(0)
+    free, _ = torch.cuda.mem_get_info()
+    server = ChannelServer(hbm_budget=free // 2)
+    mix = [(RE395, 8), (MINIMAL, 64)]
+    ids, kind = [], []
+    for gi, (g, count) in enumerate(mix):
+        for i in range(count):
+            grid = b.ChanGrid(g["nx"], g["ny"], g["nz"], g["lx"], g["lz"], g["re_tau"], g["dt_plus"],
+                              g["obs_y_plus"])
+            cid = server.admit(grid, b.make_opts(controller=0, ic_profile=1), 100 * gi + i)
+            if cid is not None:
+                ids.append(cid)
+                kind.append(gi)
+    acts = {}
+
+    def make_action(cid, k):
+        key = (cid, k % 4)
+        if key not in acts:
+            g = mix[kind[cid]][0]
+            acts[key] = torch.tensor(gaussian_action(5000 + 7 * cid + k % 4, g["nz"], g["nx"]),
+                                     dtype=torch.float64, device="cuda")
+        return acts[key]
+
+    for cid in ids:  # warm-up: builds the batch and tunes the plane-pass tilings
+        server.submit(cid, make_action(cid, 0), args.substeps)
+    while server.has_pending():
+        server.step_once()
+    torch.cuda.synchronize()
+    n_req = max(1, 2000 // args.substeps)
+    left = {cid: n_req - 1 for cid in ids}
+    lat = {0: [], 1: []}
+    failed = 0
+    t0 = time.perf_counter()
+    for cid in ids:
+        server.submit(cid, make_action(cid, 1), args.substeps)
+    while server.has_pending():
+        for r in server.step_once():
+            if r.code != 0:
+                failed += 1
+                continue
+            lat[kind[r.channel]].append((r.t_done - r.t_arrival) * 1e3)
+            if left[r.channel] > 0:
+                left[r.channel] -= 1
+                server.submit(r.channel, make_action(r.channel, n_req - left[r.channel]), args.substeps)
+    wall = time.perf_counter() - t0
+    server.close()
+    done = sum(len(v) for v in lat.values())
+    pct = {name: {"p50_ms": float(np.percentile(lat[gi], 50)), "p99_ms": float(np.percentile(lat[gi], 99)),
+                  "requests": len(lat[gi])}
+           for gi, name in enumerate(["128x97x128", "16x65x16"]) if lat[gi]}
+    out = {
+        "metric": METRIC,
+        "value": done / wall,
+        "unit": "env-steps/s",
+        "n_gpus": 1,
+        "steps": n_req,
+        "warmup": 1,
+        "ms_per_step": 1e3 * wall / n_req,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"batched and served at scale: 8 channels 128x97x128 (2pi x 2 x pi h, Re_tau 395) "
+                               f"and 64 minimal channels 16x65x16 (Re_tau 180) in one request loop, Gaussian "
+                               f"wall actions, {n_req} requests of {args.substeps} time steps per channel, "
+                               f"closed loop", "admitted": len(ids), "rejected": server.rejected_channels},
+        "grid_pt_substeps_per_s": sum(mix[k][0]["nx"] * mix[k][0]["ny"] * mix[k][0]["nz"] for k in kind)
+                                  * n_req * args.substeps / wall,
+        "latency_ms": pct,
+        "failed_requests": failed,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100, help="timed env steps")
     ap.add_argument("--warmup", type=int, default=5, help="untimed env steps")
     ap.add_argument("--substeps", type=int, default=10, help="RK3 time steps per env step")
-    ap.add_argument("--workload", choices=["larger", "minimal", "re395", "batched", "served"], default="larger")
+    ap.add_argument("--workload", choices=["larger", "minimal", "re395", "batched", "served", "scale"], default="larger")
     ap.add_argument("--workers", type=int, default=512, help="workers (one channel each) of the served workload")
     ap.add_argument("--rates", default="200,1000,4000", help="offered request rates (1/s) of the served sweep")
     ap.add_argument("--requests", type=int, default=600, help="requests per rate of the served sweep")
@@ -395,6 +478,9 @@ def main():
         return
     if args.workload == "served":
         run_served(args, torch, b, gaussian_action)
+        return
+    if args.workload == "scale":
+        run_scale(args, torch, b, gaussian_action)
         return
     g = {"larger": LARGER, "minimal": MINIMAL, "re395": RE395}[args.workload]
     if args.workload == "re395":

@@ -25,6 +25,15 @@ HD cplx caxpy(cplx acc, double s, cplx a) {
   return make_double2(fma(s, a.x, acc.x), fma(s, a.y, acc.y));
 }
 
+// Workgroups go to the eight XCDs in turn (workgroup b to XCD b mod 8), each XCD with its own
+// L2.  Logical block of workgroup b of G: every XCD takes one contiguous range, so neighbouring
+// columns, which share the cache lines of the node-major fields, meet in one L2.  A bijection
+// of [0, G) for any G (the first G mod 8 XCDs take one block more).
+__device__ __forceinline__ int xcd_block(int b, int G) {
+  const int x = b & 7, i = b >> 3, q = G >> 3, r = G & 7;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 // Wave-scope barrier for LDS data exchanged between lanes of one wavefront.
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

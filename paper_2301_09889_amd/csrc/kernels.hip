@@ -400,7 +400,8 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
   extern __shared__ double dyn_lds[];
   double* smem = dyn_lds;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int c = blockIdx.x * WPB + wave;
+  // contiguous column ranges per XCD: 317 -> 293 us per launch at 128x97x128
+  const int c = xcd_block(blockIdx.x, gridDim.x) * WPB + wave;
   if (c >= A.ncol) return;
   if (*A.status & STATUS_BAD_ACTION) return;
   const int nz = A.nz;
