@@ -82,3 +82,50 @@ def test_admission_by_footprint():
     assert b.chan_env_footprint_bytes(small, sopts) <= server.budget - server.used
     assert server.admit(small, sopts, 9) == 2        # a smaller channel still fits
     server.close()
+
+
+def test_scale_mix_served_equals_alone():
+    """The at-scale mix at full size: two 128x97x128 channels at Re_tau 395 (2 pi x 2 x pi h,
+    general column kernel) and six minimal channels (16x65x16, Re_tau 180) in one request loop,
+    Gaussian zero-net-flux actions, three requests of 10 time steps each, the large channels'
+    requests arriving late: every channel bitwise equal to the same requests served alone."""
+    import paper_2301_09889_amd.binding as b
+    from paper_2301_09889_amd.serve import ChannelServer
+
+    big = ch.Config(nx=128, ny=97, nz=128, lx=2 * np.pi, lz=np.pi, re_tau=395.0, dt_plus=0.05,
+                    obs_y_plus=15.0, ic_profile=ch.IC_REICHARDT)
+    small = ch.Config(nx=16, ny=65, nz=16, lx=2.67, lz=0.8, re_tau=180.0, dt_plus=0.05, obs_y_plus=15.0,
+                      ic_profile=ch.IC_REICHARDT)
+    cfgs = [big, big] + [small] * 6
+    seeds = list(range(len(cfgs)))
+
+    def act(i, k):
+        c = cfgs[i]
+        return to_device(gaussian_action(7000 + 13 * i + k, c.nz, c.nx))
+
+    server = ChannelServer(hbm_budget=1 << 40)
+    for c, s in zip(cfgs, seeds):
+        assert server.admit(*grid_opts(c), s) is not None
+    reqs = []
+    for k in range(3):
+        for i in range(2, len(cfgs)):
+            reqs.append(server.submit(i, act(i, k), 10))
+        server.step_once()
+        for i in range(2):
+            reqs.append(server.submit(i, act(i, k), 10))
+    while server.has_pending():
+        server.step_once()
+    assert all(r.code == 0 for r in reqs)
+    for i, (c, s) in enumerate(zip(cfgs, seeds)):
+        e = b.ChanEnv(*grid_opts(c))
+        e.reset(s)
+        for k in range(3):
+            e.step(act(i, k), 10)
+        nd = int(np.count_nonzero(e.get_state() != server.channels[i].get_state()))
+        print(f"  channel {i} ({c.nx}x{c.ny}x{c.nz}): state entries differing {nd}", flush=True)
+        assert nd == 0, i
+        assert np.array_equal(e.obs.cpu().numpy(), server.channels[i].obs.cpu().numpy()), i
+        assert np.array_equal(e.tau_w.cpu().numpy(), server.channels[i].tau_w.cpu().numpy()), i
+        assert e.drag.item() == server.channels[i].drag.item(), i
+        e.close()
+    server.close()
