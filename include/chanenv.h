@@ -254,6 +254,35 @@ int32_t chan_batch_size(const struct chan_batch* batch);
 int chan_batch_set_timing(struct chan_batch* batch, int32_t enable);
 int chan_batch_timing_read(struct chan_batch* batch, int32_t nclass, int64_t* launches, double* ms);
 
+/* ---- No allocation ----
+ * For callers that cannot allocate device memory (code inside a tight serving loop, harnesses
+ * that forbid hipMalloc): one env step of a flow state the caller owns, with no env object and
+ * no hipMalloc, hipHostMalloc, hipFree or other device-allocating call.  The operator tables,
+ * every work buffer and the launch arguments live in a static device array of 32 MiB inside the
+ * library (one per device, held until the process ends), so only grids whose
+ * chan_env_footprint_bytes is at most 32 MiB - 4 KiB run here (16x65x16 and 32x65x32 do,
+ * 64x65x64 does not).  It runs the kernels of chan_env_step on the canonical state that
+ * chan_env_set_state would make, so its results equal chan_env_set_state + chan_env_step +
+ * chan_env_get_state bitwise.
+ *   grid, opts   as for chan_env_create (opts NULL: the defaults).
+ *   hip_stream   the hipStream_t (on the current device) all work is queued on.
+ *   state        DEVICE pointer to state_doubles doubles in the exchange layout of
+ *                chan_env_get_state: read, advanced n_substeps time steps, written back (t and
+ *                the step counter advance too).
+ *   action, n_substeps, obs, tau_w, drag   as for chan_env_step (device pointers).
+ * Returns after the stream has finished the step.  The first call on a device for a grid and
+ * physical parameters (box, viscosity, time step, forcing, geometry) computes the operator
+ * tables on the host, in ordinary heap memory, and copies them into the array; later calls
+ * with the same ones reuse them.  Calls on one device share the array, which keeps the last
+ * call's contents: overlapping calls would race, so the library serialises the calls made on
+ * one device (each holds a per-device lock until its stream has finished), and other work must
+ * not use the array.
+ * Errors: CHAN_EINVAL (bad grid or options, n_substeps < 1, NULL state, or a footprint above the
+ * array; nothing done), CHAN_ENONFINITE (a non-finite value in the state or the action: the
+ * state is left unchanged; or a non-finite state after the step: written back), CHAN_EDEVICE. */
+int chan_step_static(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_stream, double* state,
+                     const double* action, int32_t n_substeps, double* obs, double* tau_w, double* drag);
+
 /* Static string naming an error code. */
 const char* chan_strerror(int code);
 

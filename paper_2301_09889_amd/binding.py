@@ -125,6 +125,8 @@ def load_library():
     lib.chan_batch_set_timing.restype = ctypes.c_int
     lib.chan_batch_timing_read.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int64), P(ctypes.c_double)]
     lib.chan_batch_timing_read.restype = ctypes.c_int
+    lib.chan_step_static.argtypes = [P(ChanGrid), P(ChanOpts), vp, vp, vp, ctypes.c_int32, vp, vp, vp]
+    lib.chan_step_static.restype = ctypes.c_int
     _LIB = lib
     return lib
 
@@ -150,6 +152,16 @@ def chan_env_create(grid, opts=None, stream=0):
     if rc != CHAN_OK:
         raise ChanError(rc, "chan_env_create")
     return h
+
+
+def chan_step_static(grid, opts, stream, state_ptr, action_ptr, n_substeps, obs_ptr, tau_ptr, drag_ptr):
+    """One env step of the flow state at state_ptr (device, exchange layout) with no allocation;
+    returns the library's code."""
+    return load_library().chan_step_static(ctypes.byref(grid), ctypes.byref(opts) if opts is not None else None,
+                                           ctypes.c_void_p(stream), ctypes.c_void_p(state_ptr),
+                                           ctypes.c_void_p(action_ptr or None), int(n_substeps),
+                                           ctypes.c_void_p(obs_ptr or None), ctypes.c_void_p(tau_ptr or None),
+                                           ctypes.c_void_p(drag_ptr or None))
 
 
 def chan_env_reset(h, seed):

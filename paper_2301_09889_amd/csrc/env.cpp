@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -202,6 +203,63 @@ size_t table_doubles(const Dims& d, bool open) {
   return t;
 }
 
+// Every device buffer of one env, carved in a fixed order out of one block of z.total bytes
+// (the env's own allocation, or the static scratch of chan_step_static).
+void carve_state(const Dims& d, const Sizes& z, const TableLayout& L, char* base, DeviceState* out) {
+  char* b = base;
+  auto take = [&](size_t n) {
+    char* r = b;
+    b += n;
+    return r;
+  };
+  DeviceState& s = *out;
+  s.vS = (cplx*)take(z.spec);
+  s.oS = (cplx*)take(z.spec);
+  s.hist = (cplx*)take(2 * z.spec);
+  s.meanS = (double*)take(align256((size_t)2 * d.ny * sizeof(double)));
+  s.meanH = (double*)take(align256((size_t)2 * d.ny * sizeof(double)));
+  s.F6 = (cplx*)take(z.plane6);
+  s.Z6 = (cplx*)take(z.z6);
+  s.W3 = (cplx*)take(z.w3);
+  s.H3 = (cplx*)take(z.h3);
+  s.vw_old = (cplx*)take(z.wall);
+  s.vw_new = (cplx*)take(z.wall);
+  s.vw_opp = (cplx*)take(z.wall);
+  s.tauw = (cplx*)take(z.wall);
+  s.tmp2d = (cplx*)take(z.tmp2d);
+  s.tab = (double*)take(z.tab);
+  s.pbuf = (cplx*)take(z.pbuf);
+  s.pscr = (double*)take(z.pscr);
+  s.drag_acc = (double*)take(256);
+  s.status = (int*)take(256);
+  s.cosk = s.tab + L.cosk;
+  s.rc = s.tab + L.rc;
+  s.optab = s.tab + L.optab;
+  s.vt = s.tab + L.vt;
+  s.minv = s.tab + L.minv;
+  s.up = s.tab + L.up;
+  s.inv_int_up = s.tab + L.inv_int_up;
+  s.alpha = s.tab + L.alpha;
+  s.beta = s.tab + L.beta;
+  s.twz = (const cplx*)(s.tab + L.twz);
+  s.twx = (const cplx*)(s.tab + L.twx);
+  s.twnx = (const cplx*)(s.tab + L.twnx);
+  s.twnz = (const cplx*)(s.tab + L.twnz);
+  s.kfwd = s.tab + L.kfwd;
+  s.kinv = s.tab + L.kinv;
+  s.rc_pm = s.tab + L.rc_pm;
+  s.intw_pm = s.tab + L.intw_pm;
+  s.op_pm = s.tab + L.op_pm;
+  s.vt_pm = s.tab + L.vt_pm;
+  s.up_pm = s.tab + L.up_pm;
+  s.pt_pm = s.tab + L.pt_pm;
+  s.ptinv = s.tab + L.ptinv;
+  s.pt = s.tab + L.pt;
+  s.pk_pm = s.tab + L.pk_pm;
+  s.pkinv = s.tab + L.pkinv;
+  s.pk = s.tab + L.pk;
+}
+
 thread_local std::string g_last_error;
 
 int fail(int code, const char* what, hipError_t err = hipSuccess) {
@@ -218,6 +276,75 @@ int fail(int code, const char* what, hipError_t err = hipSuccess) {
     hipError_t err_ = (x);                                 \
     if (err_ != hipSuccess) return fail(CHAN_EDEVICE, #x, err_); \
   } while (0)
+
+// Validates grid and options and fills every field of *e that does not depend on its device
+// buffers (the flow is absent, the device unset).
+int setup_env(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_stream, chan_env* e) {
+  if (!valid_grid(grid)) return fail(CHAN_EINVAL, "grid");
+  chan_opts_t o;
+  if (opts) o = *opts; else chan_opts_default(&o);
+  if (!valid_opts(&o)) return fail(CHAN_EINVAL, "options");
+  const Dims d = make_dims(grid);
+  const PhysParams ph = make_phys(grid, &o);
+  if (!(ph.nu > 0) || !(ph.dt > 0)) return fail(CHAN_EINVAL, "viscosity or time step");
+  double ypn = 0.0;
+  const int js = sensing_node(d, ph, grid->obs_y_plus, &ypn);
+  if (js < 0 || js >= d.N) return fail(CHAN_EINVAL, "sensing plane not inside the channel");
+  int js_planes[MAX_PLANES];
+  double yp_planes[MAX_PLANES];
+  js_planes[0] = js;
+  yp_planes[0] = ypn;
+  for (int k = 0; k < o.n_extra_planes; ++k) {
+    js_planes[1 + k] = sensing_node(d, ph, o.extra_obs_y_plus[k], &yp_planes[1 + k]);
+    if (js_planes[1 + k] < 0 || js_planes[1 + k] >= d.N)
+      return fail(CHAN_EINVAL, "extra observation plane not inside the channel");
+  }
+  std::memset(&e->s, 0, sizeof(e->s));
+  e->grid = *grid;
+  e->opts = o;
+  e->d = d;
+  e->ph = ph;
+  e->js = js;
+  e->y_plus_node = ypn;
+  e->n_planes = 1 + o.n_extra_planes;
+  for (int k = 0; k < MAX_PLANES; ++k) {
+    e->js_planes[k] = k < e->n_planes ? js_planes[k] : -1;
+    e->y_plus_planes[k] = k < e->n_planes ? yp_planes[k] : 0.0;
+  }
+  e->stream = (hipStream_t)hip_stream;
+  e->device = -1;
+  e->dev_block = nullptr;
+  e->dev_bytes = 0;
+  e->host_status = nullptr;
+  e->have_flow = false;
+  e->poisoned = false;
+  e->self = nullptr;
+  e->force_generic = generic_forced();
+  e->t = 0.0;
+  e->nstep = 0;
+  for (int r = 0; r < 3; ++r) {
+    // in the Chebyshev variable: nu' = nu ys^2 (closed channel: nu)
+    const double nux = ph.nu_xi();
+    e->sc[r].lam0 = 1.0 / (RK_BETA[r] * nux * ph.dt);
+    e->sc[r].ab = RK_ALPHA[r] / RK_BETA[r];
+    e->sc[r].gb = RK_GAMMA[r] / (RK_BETA[r] * nux);
+    e->sc[r].zb = RK_ZETA[r] / (RK_BETA[r] * nux);
+  }
+  return CHAN_OK;
+}
+
+// Host precompute of the operator tables (FP64), checked for the expected size and finiteness.
+int host_tables(const Dims& d, const PhysParams& ph, HostTables* ht) {
+  try {
+    precompute_tables(d, ph, ht);
+  } catch (const std::bad_alloc&) {
+    return fail(CHAN_ENOMEM, "host tables");
+  }
+  if (ht->L.total != table_doubles(d, ph.open)) return fail(CHAN_EINVAL, "table layout");
+  for (double v : ht->data)
+    if (!std::isfinite(v)) return fail(CHAN_EINVAL, "non-finite operator table (singular influence matrix)");
+  return CHAN_OK;
+}
 
 ColChan make_col_chan(const chan_env* e) {
   ColChan c;
@@ -313,10 +440,9 @@ void batch_free(chan_batch* b) {
 StepChan* stage_step(const chan_batch* b) { return (StepChan*)b->h_stage; }
 StepChan* dev_step(const chan_batch* b) { return (StepChan*)b->dev; }
 
-// The per-call launch arguments of env i (k: its position among this call's active envs).
-StepChan make_step_chan(const chan_batch* b, int i, int k, const double* action, int n_sub, double* obs,
-                        double* tau_w, double* drag) {
-  const chan_env* e = b->envs[i];
+// The per-call launch arguments of env e; status_out: the device word that receives its status.
+StepChan make_step_chan_env(const chan_env* e, int* status_out, const double* action, int n_sub, double* obs,
+                            double* tau_w, double* drag) {
   const Dims& d = e->d;
   const bool ext = e->opts.controller == CHAN_CTRL_EXTERNAL;
   StepChan c;
@@ -367,8 +493,14 @@ StepChan make_step_chan(const chan_batch* b, int i, int k, const double* action,
   c.twnz = (decltype(c.twnz))(e->s.twnz);
   c.drag_acc = (decltype(c.drag_acc))(e->s.drag_acc);
   c.status = (decltype(c.status))(e->s.status);
-  c.status_out = (decltype(c.status_out))(b->d_status + k);
+  c.status_out = (decltype(c.status_out))(status_out);
   return c;
+}
+
+// The per-call launch arguments of env i of a batch (k: its position among this call's active envs).
+StepChan make_step_chan(const chan_batch* b, int i, int k, const double* action, int n_sub, double* obs,
+                        double* tau_w, double* drag) {
+  return make_step_chan_env(b->envs[i], b->d_status + k, action, n_sub, obs, tau_w, drag);
 }
 
 // Stages the arguments of the active envs (b->active) and uploads them; StepChan entries
@@ -859,64 +991,18 @@ size_t chan_env_footprint_bytes(const chan_grid_t* grid, const chan_opts_t* opts
 
 int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_stream, chan_env** out) {
   g_last_error.clear();
-  if (!out || !valid_grid(grid)) return fail(CHAN_EINVAL, "grid");
-  chan_opts_t o;
-  if (opts) o = *opts; else chan_opts_default(&o);
-  if (!valid_opts(&o)) return fail(CHAN_EINVAL, "options");
-  const Dims d = make_dims(grid);
-  const PhysParams ph = make_phys(grid, &o);
-  if (!(ph.nu > 0) || !(ph.dt > 0)) return fail(CHAN_EINVAL, "viscosity or time step");
-  double ypn = 0.0;
-  const int js = sensing_node(d, ph, grid->obs_y_plus, &ypn);
-  if (js < 0 || js >= d.N) return fail(CHAN_EINVAL, "sensing plane not inside the channel");
-  int js_planes[MAX_PLANES];
-  double yp_planes[MAX_PLANES];
-  js_planes[0] = js;
-  yp_planes[0] = ypn;
-  for (int k = 0; k < o.n_extra_planes; ++k) {
-    js_planes[1 + k] = sensing_node(d, ph, o.extra_obs_y_plus[k], &yp_planes[1 + k]);
-    if (js_planes[1 + k] < 0 || js_planes[1 + k] >= d.N)
-      return fail(CHAN_EINVAL, "extra observation plane not inside the channel");
-  }
-
+  if (!out) return fail(CHAN_EINVAL, "out");
+  chan_env setup;
+  int rc = setup_env(grid, opts, hip_stream, &setup);
+  if (rc != CHAN_OK) return rc;
+  const Dims d = setup.d;
+  const PhysParams ph = setup.ph;
   HostTables ht;
-  try {
-    precompute_tables(d, ph, &ht);
-  } catch (const std::bad_alloc&) {
-    return CHAN_ENOMEM;
-  }
-  if (ht.L.total != table_doubles(d, ph.open)) return CHAN_EINVAL;
-  for (double v : ht.data)
-    if (!std::isfinite(v)) return CHAN_EINVAL;  // e.g. a singular influence matrix
+  rc = host_tables(d, ph, &ht);
+  if (rc != CHAN_OK) return rc;
 
-  chan_env* e = new (std::nothrow) chan_env();
+  chan_env* e = new (std::nothrow) chan_env(setup);
   if (!e) return CHAN_ENOMEM;
-  e->grid = *grid;
-  e->opts = o;
-  e->d = d;
-  e->ph = ph;
-  e->js = js;
-  e->y_plus_node = ypn;
-  e->n_planes = 1 + o.n_extra_planes;
-  for (int k = 0; k < MAX_PLANES; ++k) {
-    e->js_planes[k] = k < e->n_planes ? js_planes[k] : -1;
-    e->y_plus_planes[k] = k < e->n_planes ? yp_planes[k] : 0.0;
-  }
-  e->stream = (hipStream_t)hip_stream;
-  e->have_flow = false;
-  e->poisoned = false;
-  e->self = nullptr;
-  e->force_generic = generic_forced();
-  e->t = 0.0;
-  e->nstep = 0;
-  for (int r = 0; r < 3; ++r) {
-    // in the Chebyshev variable: nu' = nu ys^2 (closed channel: nu)
-    const double nux = ph.nu_xi();
-    e->sc[r].lam0 = 1.0 / (RK_BETA[r] * nux * ph.dt);
-    e->sc[r].ab = RK_ALPHA[r] / RK_BETA[r];
-    e->sc[r].gb = RK_GAMMA[r] / (RK_BETA[r] * nux);
-    e->sc[r].zb = RK_ZETA[r] / (RK_BETA[r] * nux);
-  }
   {
     const hipError_t err = hipGetDevice(&e->device);
     if (err != hipSuccess) {
@@ -938,59 +1024,8 @@ int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_
     delete e;
     return CHAN_ENOMEM;
   }
-  char* b = (char*)e->dev_block;
-  auto take = [&](size_t n) {
-    char* r = b;
-    b += n;
-    return r;
-  };
   DeviceState& s = e->s;
-  s.vS = (cplx*)take(z.spec);
-  s.oS = (cplx*)take(z.spec);
-  s.hist = (cplx*)take(2 * z.spec);
-  s.meanS = (double*)take(align256((size_t)2 * d.ny * sizeof(double)));
-  s.meanH = (double*)take(align256((size_t)2 * d.ny * sizeof(double)));
-  s.F6 = (cplx*)take(z.plane6);
-  s.Z6 = (cplx*)take(z.z6);
-  s.W3 = (cplx*)take(z.w3);
-  s.H3 = (cplx*)take(z.h3);
-  s.vw_old = (cplx*)take(z.wall);
-  s.vw_new = (cplx*)take(z.wall);
-  s.vw_opp = (cplx*)take(z.wall);
-  s.tauw = (cplx*)take(z.wall);
-  s.tmp2d = (cplx*)take(z.tmp2d);
-  s.tab = (double*)take(z.tab);
-  s.pbuf = (cplx*)take(z.pbuf);
-  s.pscr = (double*)take(z.pscr);
-  s.drag_acc = (double*)take(256);
-  s.status = (int*)take(256);
-  const TableLayout& L = ht.L;
-  s.cosk = s.tab + L.cosk;
-  s.rc = s.tab + L.rc;
-  s.optab = s.tab + L.optab;
-  s.vt = s.tab + L.vt;
-  s.minv = s.tab + L.minv;
-  s.up = s.tab + L.up;
-  s.inv_int_up = s.tab + L.inv_int_up;
-  s.alpha = s.tab + L.alpha;
-  s.beta = s.tab + L.beta;
-  s.twz = (const cplx*)(s.tab + L.twz);
-  s.twx = (const cplx*)(s.tab + L.twx);
-  s.twnx = (const cplx*)(s.tab + L.twnx);
-  s.twnz = (const cplx*)(s.tab + L.twnz);
-  s.kfwd = s.tab + L.kfwd;
-  s.kinv = s.tab + L.kinv;
-  s.rc_pm = s.tab + L.rc_pm;
-  s.intw_pm = s.tab + L.intw_pm;
-  s.op_pm = s.tab + L.op_pm;
-  s.vt_pm = s.tab + L.vt_pm;
-  s.up_pm = s.tab + L.up_pm;
-  s.pt_pm = s.tab + L.pt_pm;
-  s.ptinv = s.tab + L.ptinv;
-  s.pt = s.tab + L.pt;
-  s.pk_pm = s.tab + L.pk_pm;
-  s.pkinv = s.tab + L.pkinv;
-  s.pk = s.tab + L.pk;
+  carve_state(d, z, ht.L, (char*)e->dev_block, &s);
   {
     hipError_t err = hipMemsetAsync(e->dev_block, 0, z.total, e->stream);
     const char* what = "hipMemsetAsync";
@@ -1168,3 +1203,338 @@ int chan_env_timing_read(chan_env* e, int32_t nclass, int64_t* launches, double*
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// chan_step_static: one env step of a caller-owned flow state without any allocation.  The
+// operator tables, every work buffer and the launch arguments live in `scratch`, a file-scope
+// device array (one copy per device, held until the process ends).  Host code never passes the
+// array's name to a kernel or a copy: it uses the address from hipGetSymbolAddress, taken once
+// per device on that device's first call and kept in static_slot[device].
+// ---------------------------------------------------------------------------------------------
+namespace {
+
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)32 << 20;
+constexpr size_t STATIC_ARGS_BYTES = 4096;   // front of the scratch: launch arguments, status words
+constexpr size_t ARG_PRIME = 0, ARG_STEP = 1024, ARG_COL = 2048, ARG_PLANE = 3072, ARG_STATUS = 3840, ARG_INSTATUS = 3844;
+static_assert(sizeof(StepChan) <= 1024 && sizeof(ColChan) <= 1024 && sizeof(PlaneChan) <= 768, "argument slots");
+constexpr int MAX_STATIC_DEVICES = 64;
+
+}  // namespace
+
+static __device__ __align__(256) char scratch[STATIC_SCRATCH_BYTES];
+
+namespace {
+
+// What the scratch of one device holds: its address, and which configuration's tables.
+struct StaticSlot {
+  std::mutex lock;              // calls on one device are serialised
+  char* ptr = nullptr;          // hipGetSymbolAddress(scratch) on this device
+  bool have_tables = false;
+  int nx = 0, ny = 0, nz = 0;
+  PhysParams ph;
+  TableLayout L;
+  PlaneTiles tiles = {0, 0};
+};
+StaticSlot static_slot[MAX_STATIC_DEVICES];
+
+bool same_tables(const StaticSlot& s, const Dims& d, const PhysParams& p) {
+  const PhysParams& q = s.ph;
+  return s.have_tables && s.nx == d.nx && s.ny == d.ny && s.nz == d.nz && q.nu == p.nu && q.dt == p.dt &&
+         q.ub == p.ub && q.forcing == p.forcing && q.px == p.px && q.lx == p.lx && q.lz == p.lz && q.open == p.open &&
+         q.ys == p.ys;
+}
+
+// Launch arguments into the scratch (by value through the kernel arguments: no host copy).
+__global__ void k_static_args(StepChan prime, StepChan step, ColChan col, PlaneChan plane, StepChan* d_prime,
+                              StepChan* d_step, ColChan* d_col, PlaneChan* d_plane, int* in_status) {
+  if (threadIdx.x == 0) {
+    *d_prime = prime;
+    *d_step = step;
+    *d_col = col;
+    *d_plane = plane;
+    *in_status = 0;
+  }
+}
+
+__global__ void k_static_zero(double* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0.0;
+}
+
+// The caller's state, exchange layout [q][p][n] (v, omega_y) | U | W | v_w,old [q][p] | t | step,
+// into the device layout [p][q][n], with the canonical form chan_env_set_state gives it: zero
+// (0, 0) pair of v and omega_y, zero Nyquist row, p = 0 column Hermitian (the q > 0 half kept).
+// Any non-finite entry sets *in_status.
+struct StaticIO {
+  int nz, nkx, ny;
+  gptr<double> flat;
+  gptr<cplx> vS, oS, vw_old, vw_new;
+  gptr<double> meanS;
+  gptr<int> in_status;
+  gptr<const int> status;
+  double t_inc, n_inc;
+};
+
+__device__ __forceinline__ int canon_src_q(int p, int q, int nz) {
+  // -1: the entry is zero; otherwise the source row (a negative value marks a conjugate)
+  if (q == nz / 2 || (p == 0 && q == 0)) return -1;
+  if (p == 0 && q > nz / 2) return -(nz - q) - 2;
+  return q;
+}
+
+__global__ void k_state_in(StaticIO A) {
+  const int nz = A.nz, nkx = A.nkx, NY = A.ny;
+  const size_t nspec = (size_t)nz * nkx * NY;  // complex entries per field
+  const size_t nvw = (size_t)nz * nkx;
+  const size_t total = 2 * nspec + NY + nvw;
+  bool bad = false;
+  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x, nthr = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = tid; i < total; i += nthr) {
+    if (i < 2 * nspec) {
+      const int f = i >= nspec;
+      const size_t j = i - f * nspec;        // destination [p][q][n]
+      const int n = (int)(j % NY);
+      const int pq = (int)(j / NY), p = pq / nz, q = pq - p * nz;
+      const gptr<const double> src = A.flat + (size_t)f * 2 * nspec;
+      const double sr = src[2 * (((size_t)q * nkx + p) * NY + n)], si = src[2 * (((size_t)q * nkx + p) * NY + n) + 1];
+      bad = bad || !isfinite(sr) || !isfinite(si);
+      const int s = canon_src_q(p, q, nz);
+      cplx v = make_double2(0.0, 0.0);
+      if (s >= 0) {
+        v = make_double2(sr, si);
+      } else if (s < -1) {
+        const int qs = -s - 2;
+        const size_t o = 2 * (((size_t)qs * nkx + p) * NY + n);
+        v = make_double2(src[o], -src[o + 1]);
+      }
+      (f ? A.oS : A.vS)[j] = v;
+    } else if (i < 2 * nspec + NY) {
+      const int k = (int)(i - 2 * nspec);    // U[k] and W[k]
+      const double u = A.flat[4 * nspec + k], w = A.flat[4 * nspec + NY + k];
+      bad = bad || !isfinite(u) || !isfinite(w);
+      A.meanS[k] = u;
+      A.meanS[NY + k] = w;
+    } else {
+      const size_t j = i - 2 * nspec - NY;   // destination [p][q]
+      const int p = (int)(j / nz), q = (int)(j - (size_t)p * nz);
+      const gptr<const double> src = A.flat + 4 * nspec + 2 * NY;
+      const double sr = src[2 * ((size_t)q * nkx + p)], si = src[2 * ((size_t)q * nkx + p) + 1];
+      bad = bad || !isfinite(sr) || !isfinite(si);
+      const int s = canon_src_q(p, q, nz);
+      cplx v = make_double2(0.0, 0.0);
+      if (s >= 0) {
+        v = make_double2(sr, si);
+      } else if (s < -1) {
+        const size_t o = 2 * ((size_t)(-s - 2) * nkx + p);
+        v = make_double2(src[o], -src[o + 1]);
+      }
+      A.vw_old[j] = v;
+      A.vw_new[j] = v;
+    }
+  }
+  if (tid == 0) {
+    const double t = A.flat[4 * nspec + 2 * NY + 2 * nvw], ns = A.flat[4 * nspec + 2 * NY + 2 * nvw + 1];
+    bad = bad || !isfinite(t) || !isfinite(ns);
+  }
+  if (bad) *A.in_status = 1;
+}
+
+// The advanced state back into the caller's buffer, unless the input or the action was rejected
+// (then the buffer is left as it was).
+__global__ void k_state_out(StaticIO A) {
+  if (*A.in_status != 0 || (*A.status & STATUS_BAD_ACTION)) return;
+  const int nz = A.nz, nkx = A.nkx, NY = A.ny;
+  const size_t nspec = (size_t)nz * nkx * NY;
+  const size_t nvw = (size_t)nz * nkx;
+  const size_t total = 2 * nspec + NY + nvw;
+  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x, nthr = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = tid; i < total; i += nthr) {
+    if (i < 2 * nspec) {
+      const int f = i >= nspec;
+      const size_t j = i - f * nspec;        // destination [q][p][n]
+      const int n = (int)(j % NY);
+      const int qp = (int)(j / NY), q = qp / nkx, p = qp - q * nkx;
+      const cplx v = (f ? A.oS : A.vS)[((size_t)p * nz + q) * NY + n];
+      A.flat[(size_t)f * 2 * nspec + 2 * j] = v.x;
+      A.flat[(size_t)f * 2 * nspec + 2 * j + 1] = v.y;
+    } else if (i < 2 * nspec + NY) {
+      const int k = (int)(i - 2 * nspec);
+      A.flat[4 * nspec + k] = A.meanS[k];
+      A.flat[4 * nspec + NY + k] = A.meanS[NY + k];
+    } else {
+      const size_t j = i - 2 * nspec - NY;   // destination [q][p]
+      const int q = (int)(j / nkx), p = (int)(j - (size_t)q * nkx);
+      const cplx v = A.vw_old[(size_t)p * nz + q];
+      A.flat[4 * nspec + 2 * NY + 2 * j] = v.x;
+      A.flat[4 * nspec + 2 * NY + 2 * j + 1] = v.y;
+    }
+  }
+  if (tid == 0) {
+    const size_t o = 4 * nspec + 2 * NY + 2 * nvw;
+    A.flat[o] = A.flat[o] + A.t_inc;
+    A.flat[o + 1] = A.flat[o + 1] + A.n_inc;
+  }
+}
+
+// Column pass of the single channel e (the general kernel for N > 64 or when forced).
+int static_column(chan_env* e, const ColChan& h, const ColStage& S, bool solve, bool recon, hipStream_t st) {
+  if (uses_pm(e)) return launch_column_pm(e->d, nullptr, &h, 1, S, solve, recon, st, nullptr);
+  const int r = S.stage;
+  int mode = WALL_OPP;
+  double s = 0.0;
+  if (e->opts.controller == CHAN_CTRL_EXTERNAL) {
+    mode = WALL_RAMP;
+    if (r >= 0) s = (e->opts.action_mode == CHAN_HOLD) ? 1.0 : (S.m + RK_C_END[r]) / (double)S.n_sub;
+  }
+  return launch_column_pass(e->d, e->s, e->ph, r, e->sc[r < 0 ? 0 : r], mode, s, e->js, e->opts.opp_alpha, r == 2,
+                            recon, st, nullptr);
+}
+
+// A fixed plane-pass tiling (tilings change no result): three pairs of rows per x-row block
+// where that is valid, pencil blocks of 16.
+PlaneTiles static_tiles(const Dims& d) {
+  std::vector<PlaneTiles> c;
+  if (plane_tile_candidates(d, &c) != 0 || c.empty()) return PlaneTiles{0, 0};
+  for (const PlaneTiles& t : c)
+    if (t.P >= 3 && t.PB >= 16) return t;
+  return c.back();
+}
+
+int static_step(chan_env* e, char* base, const PlaneTiles& tiles, double* state, const double* action,
+                int32_t n_substeps, double* obs, double* tau_w, double* drag, hipStream_t st) {
+  const Dims& d = e->d;
+  StepChan* d_prime = (StepChan*)(base + ARG_PRIME);
+  StepChan* d_step = (StepChan*)(base + ARG_STEP);
+  ColChan* d_col = (ColChan*)(base + ARG_COL);
+  PlaneChan* d_plane = (PlaneChan*)(base + ARG_PLANE);
+  int* d_status = (int*)(base + ARG_STATUS);
+  int* d_in = (int*)(base + ARG_INSTATUS);
+  const bool ext = e->opts.controller == CHAN_CTRL_EXTERNAL;
+  StepChan prime = make_step_chan_env(e, d_status, nullptr, 1, nullptr, nullptr, nullptr);
+  prime.skip = 0;
+  prime.zero_vw = 0;
+  StepChan step = make_step_chan_env(e, d_status, action, n_substeps, obs, tau_w, drag);
+  step.skip = 0;
+  const ColChan h = make_col_chan(e);
+  const PlaneChan pc = make_plane_chan(e);
+  StaticIO io;
+  std::memset(&io, 0, sizeof(io));
+  io.nz = d.nz;
+  io.nkx = d.nkx;
+  io.ny = d.ny;
+  io.flat = (decltype(io.flat))state;
+  io.vS = (decltype(io.vS))e->s.vS;
+  io.oS = (decltype(io.oS))e->s.oS;
+  io.vw_old = (decltype(io.vw_old))e->s.vw_old;
+  io.vw_new = (decltype(io.vw_new))e->s.vw_new;
+  io.meanS = (decltype(io.meanS))e->s.meanS;
+  io.in_status = (decltype(io.in_status))d_in;
+  io.status = (decltype(io.status))e->s.status;
+  io.t_inc = n_substeps * e->ph.dt;       // as chan_env_step advances its clock
+  io.n_inc = (double)n_substeps;
+  const size_t total = (size_t)2 * d.nz * d.nkx * d.ny + d.ny + (size_t)d.nz * d.nkx;
+  const unsigned io_blocks = (unsigned)std::min<size_t>((total + 255) / 256, 1024);
+
+  hipLaunchKernelGGL(k_static_args, dim3(1), dim3(64), 0, st, prime, step, h, pc, d_prime, d_step, d_col, d_plane,
+                     d_in);
+  // prime: the state, then the plane-pass input, opposition target and wall shear from it
+  // (chan_env_set_state's sequence)
+  if (launch_begin_step(d_prime, 1, st, nullptr)) return fail(CHAN_EDEVICE, "launch begin_step", hipGetLastError());
+  hipLaunchKernelGGL(k_state_in, dim3(io_blocks), dim3(256), 0, st, io);
+  if (static_column(e, h, ColStage{-1, 0, 1}, false, true, st))
+    return fail(CHAN_EDEVICE, "launch column pass", hipGetLastError());
+  // the env step (chan_env_step's sequence for one channel)
+  if (launch_begin_step(d_step, 1, st, nullptr)) return fail(CHAN_EDEVICE, "launch begin_step", hipGetLastError());
+  if (ext && action && launch_ingest(d_step, 1, d.nx, d.nz, d.nkx, st, nullptr))
+    return fail(CHAN_EDEVICE, "launch ingest", hipGetLastError());
+  for (int m = 0; m < n_substeps; ++m)
+    for (int r = 0; r < 3; ++r) {
+      const bool last = (m == n_substeps - 1) && (r == 2);
+      if (launch_plane_pass(d, d_plane, 1, tiles, st, nullptr))
+        return fail(CHAN_EDEVICE, "launch plane pass", hipGetLastError());
+      if (static_column(e, h, ColStage{r, m, n_substeps}, true, !last, st))
+        return fail(CHAN_EDEVICE, "launch column pass", hipGetLastError());
+    }
+  const ColStage S_end = {-1, 0, n_substeps};
+  if (static_column(e, h, S_end, false, true, st)) return fail(CHAN_EDEVICE, "launch column pass", hipGetLastError());
+  const bool pressure = obs != nullptr && (e->opts.obs_mask & CHAN_OBS_P);
+  if (pressure) {
+    if (launch_plane_pass(d, d_plane, 1, tiles, st, nullptr))
+      return fail(CHAN_EDEVICE, "launch plane pass (pressure)", hipGetLastError());
+    int rc = 0;
+    if (uses_pm(e)) {
+      rc = launch_pressure_pm(d, d_col, 1, S_end, st, nullptr);
+    } else {
+      const bool ramp = ext && e->opts.action_mode == CHAN_RAMP;
+      rc = launch_pressure_generic(d, e->s, e->ph, e->n_planes, e->js_planes, ramp, n_substeps, st, nullptr);
+    }
+    if (rc) return fail(CHAN_EDEVICE, "launch pressure", hipGetLastError());
+  }
+  if (launch_finish_step(d_step, 1, st, nullptr)) return fail(CHAN_EDEVICE, "launch finish_step", hipGetLastError());
+  const int nslots = pressure ? 1 + SLOTS_PER_PLANE * e->n_planes : SLOTS_PER_PLANE * e->n_planes - 3;
+  if (launch_outputs(d_step, 1, d.nx, d.nz, d.nkx, nslots, st, nullptr))
+    return fail(CHAN_EDEVICE, "launch outputs", hipGetLastError());
+  if (pressure && launch_pressure_finish(d_step, 1, st, nullptr))
+    return fail(CHAN_EDEVICE, "launch pressure finish", hipGetLastError());
+  hipLaunchKernelGGL(k_state_out, dim3(io_blocks), dim3(256), 0, st, io);
+  HIPCHECK(hipGetLastError());
+  int words[2] = {0, 0};
+  HIPCHECK(hipMemcpyAsync(words, d_status, sizeof(words), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  if (words[1]) return fail(CHAN_ENONFINITE, "non-finite value in the state given (state unchanged)");
+  if (words[0] & STATUS_BAD_ACTION) return fail(CHAN_ENONFINITE, "non-finite action (state unchanged)");
+  if (words[0] & STATUS_NONFINITE) return fail(CHAN_ENONFINITE, "non-finite state after the step");
+  return CHAN_OK;
+}
+
+}  // namespace
+
+extern "C" int chan_step_static(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_stream, double* state,
+                                const double* action, int32_t n_substeps, double* obs, double* tau_w, double* drag) {
+  g_last_error.clear();
+  if (!state) return fail(CHAN_EINVAL, "state");
+  if (n_substeps < 1) return fail(CHAN_EINVAL, "n_substeps < 1");
+  chan_env e;
+  int rc = setup_env(grid, opts, hip_stream, &e);
+  if (rc != CHAN_OK) return rc;
+  const Dims& d = e.d;
+  const size_t tabd = table_doubles(d, e.ph.open);
+  const Sizes z = buffer_sizes(d, tabd);
+  if (STATIC_ARGS_BYTES + z.total > STATIC_SCRATCH_BYTES)
+    return fail(CHAN_EINVAL, "grid too large for chan_step_static (its scratch holds 32 MiB; "
+                             "chan_env_footprint_bytes must be at most 32 MiB - 4 KiB)");
+  int dev = -1;
+  HIPCHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_STATIC_DEVICES) return fail(CHAN_EDEVICE, "device index beyond the static slots");
+  e.device = dev;
+  StaticSlot& slot = static_slot[dev];
+  std::lock_guard<std::mutex> guard(slot.lock);
+  if (!slot.ptr) {
+    void* p = nullptr;
+    HIPCHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    slot.ptr = (char*)p;
+  }
+  char* base = slot.ptr + STATIC_ARGS_BYTES;
+  hipStream_t st = e.stream;
+  if (!same_tables(slot, d, e.ph)) {
+    HostTables ht;
+    rc = host_tables(d, e.ph, &ht);
+    if (rc != CHAN_OK) return rc;
+    slot.have_tables = false;
+    carve_state(d, z, ht.L, base, &e.s);
+    // clear every buffer (the Nyquist rows are never written by the kernels), then the tables
+    hipLaunchKernelGGL(k_static_zero, dim3(1024), dim3(256), 0, st, (double*)base, z.total / sizeof(double));
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipMemcpyAsync(e.s.tab, ht.data.data(), ht.data.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    slot.nx = d.nx;
+    slot.ny = d.ny;
+    slot.nz = d.nz;
+    slot.ph = e.ph;
+    slot.L = ht.L;
+    slot.tiles = static_tiles(d);
+    slot.have_tables = true;
+  } else {
+    carve_state(d, z, slot.L, base, &e.s);
+  }
+  return static_step(&e, slot.ptr, slot.tiles, state, action, n_substeps, obs, tau_w, drag, st);
+}
