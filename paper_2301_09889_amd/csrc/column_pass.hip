@@ -340,6 +340,15 @@ __device__ __forceinline__ void tau_solve_pm(const Lane<N>& L, const cplx* R, co
     const cplx ge = cscale(cadd(gt[k], gb[k]), 0.5);
     const cplx x0e = cscale(csub(ge, cadd(sum_even, Et)), isf_even);
     Xt[k] = caxpy(Et, Ft, x0e);
+    // The boundary rows to rounding.  x0 comes from 1/sum F and sum E, which cancel heavily
+    // when lam is large (the wall layer lives in the top coefficients), so X(+-1) = g holds
+    // only to eps sum |E|.  The rows fix the top coefficient of each parity given the others:
+    // a_N = (g_t + g_b)/2 - sum_{even n < N} a_n, a_{N-1} = (g_t - g_b)/2 - sum_{odd n < N-1} a_n.
+    const bool top_odd = L.odd && L.i == H - 1;
+    const cplx s = half_sum(top_odd ? cz() : X[k]);
+    const cplx go = cscale(csub(gt[k], gb[k]), 0.5);
+    Xt[k] = csub(ge, readlane_c(s, 0));
+    if (top_odd) X[k] = csub(go, s);
   }
 }
 

@@ -390,6 +390,33 @@ __device__ __forceinline__ cplx tau_value(const cplx* E, const double* TAB, cons
   return caxpy(base, TAB[s * OPSZ + 3 * ML + i], x0[s]);
 }
 
+// The Dirichlet rows x(+1) = g_t, x(-1) = g_b of a tau solution held in registers (element
+// e = lane + 64 slot), to rounding.  x0 = (g - sum E) / sum F cancels heavily when lam is large
+// (the wall layer lives in the top coefficients), so the rows hold only to eps sum |E|; given
+// the lower coefficients they fix the top one of each parity:
+// a_N = ge - sum_{even n < N} a_n, a_{N-1} = go - sum_{odd n < N-1} a_n, ge, go = (g_t +- g_b)/2.
+template <int N>
+__device__ __forceinline__ void dirichlet_rows(cplx* xs, cplx ge, cplx go, int lane) {
+  constexpr int NS = CP<N>::NS;
+  cplx se = cz(), so = cz();
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int e = lane + 64 * s;
+    if (e < N - 1) {
+      if (e & 1) so = cadd(so, xs[s]);
+      else se = cadd(se, xs[s]);
+    }
+  }
+  se = wave_sum(se);
+  so = wave_sum(so);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int e = lane + 64 * s;
+    if (e == N) xs[s] = csub(ge, se);
+    if (e == N - 1) xs[s] = csub(go, so);
+  }
+}
+
 template <int N>
 __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
   constexpr int WPB = wpb<N>();
@@ -559,11 +586,27 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
           for (int t = 0; t < 4; ++t) SC[t] = x0[t];
       }
       wave_sync();
-      for (int e = lane; e <= N; e += 64) {
-        const cplx phip = tau_value<N>(B[4], TAB, SC, e);
-        const cplx om = tau_value<N>(B[5], TAB, SC + 2, e);
-        B[6][e] = phip;
-        B[7][e] = om;
+      {
+        cplx xp[NS], xw[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const int e = lane + 64 * s;
+          xp[s] = xw[s] = cz();
+          if (e <= N) {
+            xp[s] = tau_value<N>(B[4], TAB, SC, e);
+            xw[s] = tau_value<N>(B[5], TAB, SC + 2, e);
+          }
+        }
+        dirichlet_rows<N>(xp, cz(), cz(), lane);
+        dirichlet_rows<N>(xw, cz(), cz(), lane);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const int e = lane + 64 * s;
+          if (e <= N) {
+            B[6][e] = xp[s];
+            B[7][e] = xw[s];
+          }
+        }
       }
       wave_sync();
       // (f) v_p: (D^2 - k^2) v_p = phi_p, v_p(+1) = 0, v_p(-1) = v_w
@@ -599,9 +642,13 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         const int e = lane + 64 * s;
-        vp[s] = cz();
+        vp[s] = (e <= N) ? tau_value<N>(B[3], TAB, SC + 4, e) : cz();
+      }
+      dirichlet_rows<N>(vp, cscale(vw, 0.5), cscale(vw, -0.5), lane);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int e = lane + 64 * s;
         if (e <= N) {
-          vp[s] = tau_value<N>(B[3], TAB, SC + 4, e);
           const double n2 = (double)e * (double)e;
           // top row: dv/dxi(+1) (wall) or d^2v/dxi^2(+1) = sum n^2 (n^2 - 1)/3 v_n (surface)
           dtop = caxpy(dtop, A.open ? n2 * (n2 - 1.0) / 3.0 : n2, vp[s]);
@@ -709,6 +756,7 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
         xs[s] = cz();
         if (e <= N) xs[s] = tau_value<N>(B[3], TAB, SC, e);
       }
+      dirichlet_rows<N>(xs, cz(), cz(), lane);
       if (A.open) {  // dU/dxi(+1) = dW/dxi(+1) = 0: add c phi_+ (k = 0)
         cplx ds = cz();
 #pragma unroll
