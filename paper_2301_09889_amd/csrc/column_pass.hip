@@ -342,13 +342,14 @@ __device__ __forceinline__ void tau_solve_pm(const Lane<N>& L, const cplx* R, co
     Xt[k] = caxpy(Et, Ft, x0e);
     // The boundary rows to rounding.  x0 comes from 1/sum F and sum E, which cancel heavily
     // when lam is large (the wall layer lives in the top coefficients), so X(+-1) = g holds
-    // only to eps sum |E|.  The rows fix the top coefficient of each parity given the others:
-    // a_N = (g_t + g_b)/2 - sum_{even n < N} a_n, a_{N-1} = (g_t - g_b)/2 - sum_{odd n < N-1} a_n.
-    const bool top_odd = L.odd && L.i == H - 1;
-    const cplx s = half_sum(top_odd ? cz() : X[k]);
-    const cplx go = cscale(csub(gt[k], gb[k]), 0.5);
-    Xt[k] = csub(ge, readlane_c(s, 0));
-    if (top_odd) X[k] = csub(go, s);
+    // only to eps sum |E|.  One refinement of x0 per parity removes the row residual
+    // r = sum_i X_{2i+s} - g_s along the homogeneous solution F (dx0 = -r / sum F), which
+    // leaves the other tau rows as they were and every coefficient to rounding.
+    cplx rs = half_sum(X[k]);
+    rs = caxpy(rs, L.evenf(), Xt[k]);                           // even lanes: + X_N
+    const cplx dx0 = cscale(csub(rs, g), -isf);
+    X[k] = L.ok ? caxpy(X[k], F, dx0) : cz();
+    Xt[k] = caxpy(Xt[k], Ft, readlane_c(dx0, 0));
   }
 }
 

@@ -392,28 +392,33 @@ __device__ __forceinline__ cplx tau_value(const cplx* E, const double* TAB, cons
 
 // The Dirichlet rows x(+1) = g_t, x(-1) = g_b of a tau solution held in registers (element
 // e = lane + 64 slot), to rounding.  x0 = (g - sum E) / sum F cancels heavily when lam is large
-// (the wall layer lives in the top coefficients), so the rows hold only to eps sum |E|; given
-// the lower coefficients they fix the top one of each parity:
-// a_N = ge - sum_{even n < N} a_n, a_{N-1} = go - sum_{odd n < N-1} a_n, ge, go = (g_t +- g_b)/2.
+// (the wall layer lives in the top coefficients), so the rows hold only to eps sum |E|.  One
+// refinement of x0 per parity removes the row residual r_s = sum_i x_{2i+s} - g_s along the
+// homogeneous solution F_i of that parity (x_{2i+s} -= F_i r_s / sum F), which leaves the other
+// tau rows as they were and every coefficient to rounding; g_e, g_o = (g_t +- g_b)/2.  TAB holds
+// the operator record the solution was computed with.
 template <int N>
-__device__ __forceinline__ void dirichlet_rows(cplx* xs, cplx ge, cplx go, int lane) {
+__device__ __forceinline__ void refine_rows(cplx* xs, const double* TAB, cplx ge, cplx go, int lane) {
   constexpr int NS = CP<N>::NS;
+  constexpr int ML = N / 2 + 1;
+  constexpr int OPSZ = 4 * ML + 2;
   cplx se = cz(), so = cz();
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int e = lane + 64 * s;
-    if (e < N - 1) {
+    if (e <= N) {
       if (e & 1) so = cadd(so, xs[s]);
       else se = cadd(se, xs[s]);
     }
   }
   se = wave_sum(se);
   so = wave_sum(so);
+  const cplx de = cscale(csub(se, ge), -TAB[4 * ML]);
+  const cplx dodd = cscale(csub(so, go), -TAB[OPSZ + 4 * ML]);
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int e = lane + 64 * s;
-    if (e == N) xs[s] = csub(ge, se);
-    if (e == N - 1) xs[s] = csub(go, so);
+    if (e <= N) xs[s] = caxpy(xs[s], TAB[(e & 1) * OPSZ + 3 * ML + (e >> 1)], (e & 1) ? dodd : de);
   }
 }
 
@@ -597,8 +602,8 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
             xw[s] = tau_value<N>(B[5], TAB, SC + 2, e);
           }
         }
-        dirichlet_rows<N>(xp, cz(), cz(), lane);
-        dirichlet_rows<N>(xw, cz(), cz(), lane);
+        refine_rows<N>(xp, TAB, cz(), cz(), lane);
+        refine_rows<N>(xw, TAB, cz(), cz(), lane);
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
           const int e = lane + 64 * s;
@@ -644,7 +649,7 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
         const int e = lane + 64 * s;
         vp[s] = (e <= N) ? tau_value<N>(B[3], TAB, SC + 4, e) : cz();
       }
-      dirichlet_rows<N>(vp, cscale(vw, 0.5), cscale(vw, -0.5), lane);
+      refine_rows<N>(vp, TAB, cscale(vw, 0.5), cscale(vw, -0.5), lane);
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         const int e = lane + 64 * s;
@@ -756,7 +761,7 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
         xs[s] = cz();
         if (e <= N) xs[s] = tau_value<N>(B[3], TAB, SC, e);
       }
-      dirichlet_rows<N>(xs, cz(), cz(), lane);
+      refine_rows<N>(xs, TAB, cz(), cz(), lane);
       if (A.open) {  // dU/dxi(+1) = dW/dxi(+1) = 0: add c phi_+ (k = 0)
         cplx ds = cz();
 #pragma unroll

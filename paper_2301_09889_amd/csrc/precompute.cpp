@@ -65,6 +65,11 @@ void host_tau_solve(const Dims& d, const double* rec, const double* rc, const do
     }
     const double x0 = (g - sum) * t[4 * ML];
     for (int i = 0; i <= m; ++i) x[2 * i + s] = (i == 0 ? 0.0 : E[2 * i + s]) + F[i] * x0;
+    // one refinement of x0: the boundary-row residual removed along the homogeneous solution
+    double r = -g;
+    for (int i = 0; i <= m; ++i) r += x[2 * i + s];
+    const double dx0 = -r * t[4 * ML];
+    for (int i = 0; i <= m; ++i) x[2 * i + s] += F[i] * dx0;
   }
 }
 
