@@ -49,3 +49,29 @@ def rel_field_diff(a, b):
 
 def gpu_state(S, genv):
     return ch.state_from_flat(S, genv.get_state())
+
+
+def field_errors(a, b, pair_floor=1e-3):
+    """Element-wise comparison of two states field by field.
+
+    Returns a dict: for v, om, U, W the relative max-norm error max|a - b| / max|b| of that
+    field alone; for v and om also 'v_pair', 'om_pair': the worst pair (one Chebyshev column)
+    measured against that pair's own coefficient norm, with pairs whose norm is below
+    pair_floor x the field's largest pair norm measured against that floor instead."""
+    out = {}
+    for name, x, y in (("v", a.v, b.v), ("om", a.om, b.om), ("U", a.ubar, b.ubar), ("W", a.wbar, b.wbar)):
+        scale = np.abs(y).max()
+        out[name] = float(np.abs(x - y).max() / scale) if scale > 0 else float(np.abs(x).max())
+    for name, x, y in (("v", a.v, b.v), ("om", a.om, b.om)):
+        cn = np.linalg.norm(y, axis=-1)
+        den = np.maximum(cn, pair_floor * cn.max())
+        out[name + "_pair"] = float((np.linalg.norm(x - y, axis=-1) / den).max())
+    return out
+
+
+def assert_fields(a, b, tol, what=""):
+    e = field_errors(a, b)
+    print(f"  {what} " + " ".join(f"{k} {v:.1e}" for k, v in e.items()), flush=True)
+    bad = {k: v for k, v in e.items() if not v <= tol}
+    assert not bad, (what, bad, tol)
+    return e
