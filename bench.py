@@ -150,27 +150,50 @@ def host_cpu_model():
     return None
 
 
-def cpu_baseline(g, opts_kw, n_sub_env, seed, budget_substeps):
-    """The oracle (test infrastructure) on a bounded sample of the same workload,
-    one BLAS thread."""
+def _oracle_sample(job):
+    """One oracle process of the CPU baseline: warm-up time step, then budget_substeps time
+    steps of one env step of the workload on one BLAS thread; returns their wall seconds."""
+    g, opts_kw, seed, budget_substeps = job
     from threadpoolctl import threadpool_limits
 
     from oracle import channel as ch
     from synth import gaussian_action
-    cfg = ch.Config(**g, **opts_kw)
-    env = ch.Env(cfg)
+    env = ch.Env(ch.Config(**g, **opts_kw))
     env.reset(seed)
     act = gaussian_action(1000 + seed, g["nz"], g["nx"])
     with threadpool_limits(limits=1):
         env.step(act, 1)  # warm caches and matrices
         t0 = time.perf_counter()
         env.step(act, budget_substeps)
-        dt = time.perf_counter() - t0
-    per_substep = dt / budget_substeps
-    return {"value": 1.0 / (per_substep * n_sub_env), "unit": "env-steps/s", "cores": 1, "kind": "oracle",
-            "host_cpu": host_cpu_model(),
-            "sample": f"{budget_substeps} time steps of one env step of the same workload "
-                      f"({dt:.1f} s), scaled to {n_sub_env} time steps per env step; one BLAS thread"}
+        return time.perf_counter() - t0
+
+
+def host_cores():
+    """Cores this process may run on, capped at 16 (the host share of one GPU)."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def cpu_baseline(g, opts_kw, n_sub_env, seed, budget_substeps):
+    """The oracle (test infrastructure) on a bounded sample of the same workload: one process
+    per available core (each on its own seed, one BLAS thread, all at once; throughputs
+    summed), and the single-core figure of the first of them run alone.  Runs before any GPU
+    work (the processes are forked)."""
+    import multiprocessing as mp
+    single = _oracle_sample((g, opts_kw, seed, budget_substeps))
+    n = host_cores()
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(n) as pool:
+        times = pool.map(_oracle_sample, [(g, opts_kw, seed + k, budget_substeps) for k in range(n)])
+    wall = time.perf_counter() - t0
+    per_env_step = [t / budget_substeps * n_sub_env for t in times]
+    total = float(sum(1.0 / t for t in per_env_step))
+    return {"value": total, "unit": "env-steps/s", "cores": n, "kind": "oracle",
+            "host_cpu": host_cpu_model(), "host_cores_available": len(os.sched_getaffinity(0)),
+            "single_core_value": 1.0 / (single / budget_substeps * n_sub_env),
+            "sample": f"{n} oracle processes at once, one per core and one BLAS thread each, seeds {seed}.."
+                      f"{seed + n - 1}, each {budget_substeps} time steps of one env step of the same workload "
+                      f"(slowest {max(times):.1f} s, {wall:.1f} s wall with start-up), scaled to {n_sub_env} time "
+                      f"steps per env step and summed; single_core_value: the first alone ({single:.1f} s)"}
 
 
 def batched_specs(n, mix="uneven"):
@@ -311,14 +334,20 @@ def run_served(args, torch, b, gaussian_action):
     while server.has_pending():
         server.step_once()
     torch.cuda.synchronize()
-    # closed loop: every channel always has a request pending (saturation)
+    # closed loop: every channel always has a request pending (saturation); each channel's next
+    # request is submitted as soon as its last one is polled done
     t0 = time.perf_counter()
     n_done = 0
-    for _ in range(3):
-        for cid in ids:
-            server.submit(cid, make_action(cid, 1), args.substeps)
-        while server.has_pending():
-            n_done += sum(1 for r in server.step_once() if r.code == 0)
+    left = {cid: 2 for cid in ids}
+    for cid in ids:
+        server.submit(cid, make_action(cid, 1), args.substeps)
+    while server.has_pending():
+        server.launch()
+        for r in server.poll():
+            n_done += 1 if r.code == 0 else 0
+            if left[r.channel] > 0:
+                left[r.channel] -= 1
+                server.submit(r.channel, make_action(r.channel, 1), args.substeps)
     sat = n_done / (time.perf_counter() - t0)
     sweep = []
     for rate in [float(x) for x in args.rates.split(",")]:
@@ -398,7 +427,8 @@ def run_scale(args, torch, b, gaussian_action):
     for cid in ids:
         server.submit(cid, make_action(cid, 1), args.substeps)
     while server.has_pending():
-        for r in server.step_once():
+        server.launch()
+        for r in server.poll():
             if r.code != 0:
                 failed += 1
                 continue
@@ -498,6 +528,11 @@ def main():
     if args.top == "freeslip":
         opts_kw["top_bc"] = 1
         workload = "open " + workload.replace(" x 2 x ", " x 1 x ")
+    # the oracle's CPU figure first, before any GPU work (its processes are forked)
+    cpu = None
+    if not args.no_cpu_baseline and args.workload != "re395":  # one oracle time step takes minutes there
+        cpu = cpu_baseline(g, opts_kw, args.substeps, args.seed, args.cpu_substeps)
+        print(f"cpu baseline: {cpu['value']:.3f} env-steps/s on {cpu['cores']} cores", file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
     grid = b.ChanGrid(g["nx"], g["ny"], g["nz"], g["lx"], g["lz"], g["re_tau"], g["dt_plus"], g["obs_y_plus"])
     opts = b.make_opts(**opts_kw)
@@ -587,10 +622,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_probe_bytes_each_way"] = src.numel() * 8
-    if not args.no_cpu_baseline and args.workload != "re395":  # one oracle time step takes minutes there
-        out["cpu_baseline"] = cpu_baseline(g, opts_kw, args.substeps, args.seed, args.cpu_substeps)
-    else:
-        out["cpu_baseline"] = None
+    out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -48,7 +48,8 @@ enum {
   CHAN_ENOMEM = -2,      /* device or host allocation failed                      */
   CHAN_EDEVICE = -3,     /* a HIP runtime call failed                             */
   CHAN_ENONFINITE = -4,  /* non-finite action (state untouched) or state (poisoned) */
-  CHAN_ESTATE = -5       /* step or get_state before reset/set_state, or poisoned */
+  CHAN_ESTATE = -5,      /* step or get_state before reset/set_state, or poisoned */
+  CHAN_EBUSY = -6        /* the env is held by an unfinished asynchronous call (chan_batch_launch) */
 };
 
 /* Opaque environment handle, owned by the library. */
@@ -217,10 +218,11 @@ const char* chan_kernel_class_name(int32_t cls);
  * would (the same kernels on the same per-channel data): results are bitwise the
  * same alone and in the batch.
  *
- * chan_batch_create: n envs (n >= 1), each listed once, all created on the same
- * HIP stream and device; the batch refers to them and does not own them (destroy
- * the batch first).  Errors: CHAN_EINVAL (empty, null, duplicate, mixed streams,
- * more than 65535 / N_y channels of one shape), CHAN_ENOMEM, CHAN_EDEVICE.
+ * chan_batch_create: n envs (n >= 1), each listed once, all on the current device; the batch
+ * refers to them and does not own them (destroy the batch first).  Its synchronous calls
+ * (chan_batch_step, chan_batch_step_subset) run on the first env's stream.  Errors:
+ * CHAN_EINVAL (empty, null, duplicate, other devices, more than 65535 / N_y channels of one
+ * shape), CHAN_EBUSY (an env held by an unfinished call), CHAN_ENOMEM, CHAN_EDEVICE.
  *
  * chan_batch_step: one env step (n_substeps time steps) of every env, in the
  * order given at creation.  actions, obs, tau_w and drag are host arrays of n
@@ -253,6 +255,38 @@ void chan_batch_destroy(struct chan_batch* batch);
 int32_t chan_batch_size(const struct chan_batch* batch);
 int chan_batch_set_timing(struct chan_batch* batch, int32_t enable);
 int chan_batch_timing_read(struct chan_batch* batch, int32_t nclass, int64_t* launches, double* ms);
+
+/* ---- Asynchronous batch calls and membership (a request loop over channels that come and go) ----
+ * chan_batch_launch queues one env step of the batch's envs envs[0..n) (each at most once; the
+ * per-env arrays indexed like envs, as for chan_batch_step) on hip_stream, any stream of the
+ * batch's device, and returns at once with *out holding the call.  Outputs are written by the
+ * stream; an env is held by the call until chan_call_finish, and meanwhile any other call
+ * involving it (including its own chan_env_* calls) fails with CHAN_EBUSY.  Calls on different
+ * streams with disjoint envs run concurrently on the device; each call stages its launch
+ * arguments in buffers of its own.  Errors: CHAN_EINVAL (n_substeps < 1, an env not in the
+ * batch or listed twice), CHAN_EBUSY, CHAN_ESTATE (no listed env has a flow state), CHAN_ENOMEM,
+ * CHAN_EDEVICE; nothing is queued then.
+ *
+ * chan_call_query: 1 while the call's work is still queued or running, 0 once it has finished
+ * (does not block); CHAN_EINVAL for a null call.
+ *
+ * chan_call_finish waits for the call, applies each env's outcome (clock, step counter, a
+ * poisoned state), writes the per-env codes to results (if non-NULL; as for chan_batch_step)
+ * and frees the call; returns CHAN_OK if every env succeeded, else the first failing env's
+ * code.  Every launched call must be finished, before the batch is destroyed.
+ *
+ * chan_batch_add: env joins the batch (its grid shape's plane-pass tiling is tuned on it if the
+ * shape is new to the batch; later channels of the shape reuse it).  chan_batch_remove: env
+ * leaves the batch (not destroyed); later positions shift down by one.  Errors: CHAN_EINVAL
+ * (null, another device, already a member / not a member), CHAN_EBUSY (held by a call). */
+typedef struct chan_call chan_call;
+int chan_batch_launch(struct chan_batch* batch, void* hip_stream, int32_t n, struct chan_env* const* envs,
+                      const double* const* actions, int32_t n_substeps, double* const* obs, double* const* tau_w,
+                      double* const* drag, struct chan_call** out);
+int chan_call_query(const struct chan_call* call);
+int chan_call_finish(struct chan_call* call, int32_t* results);
+int chan_batch_add(struct chan_batch* batch, struct chan_env* env);
+int chan_batch_remove(struct chan_batch* batch, struct chan_env* env);
 
 /* ---- No allocation ----
  * For callers that cannot allocate device memory (code inside a tight serving loop, harnesses

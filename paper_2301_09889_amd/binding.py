@@ -12,7 +12,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
-CHAN_OK, CHAN_EINVAL, CHAN_ENOMEM, CHAN_EDEVICE, CHAN_ENONFINITE, CHAN_ESTATE = 0, -1, -2, -3, -4, -5
+CHAN_OK, CHAN_EINVAL, CHAN_ENOMEM, CHAN_EDEVICE, CHAN_ENONFINITE, CHAN_ESTATE, CHAN_EBUSY = 0, -1, -2, -3, -4, -5, -6
 CHAN_TOP_WALL, CHAN_TOP_FREESLIP = 0, 1
 CHAN_CFR, CHAN_CPG = 0, 1
 CHAN_CTRL_EXTERNAL, CHAN_CTRL_OPPOSITION = 0, 1
@@ -125,6 +125,17 @@ def load_library():
     lib.chan_batch_set_timing.restype = ctypes.c_int
     lib.chan_batch_timing_read.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int64), P(ctypes.c_double)]
     lib.chan_batch_timing_read.restype = ctypes.c_int
+    lib.chan_batch_launch.argtypes = [vp, vp, ctypes.c_int32, P(vp), P(vp), ctypes.c_int32, P(vp), P(vp), P(vp),
+                                      P(vp)]
+    lib.chan_batch_launch.restype = ctypes.c_int
+    lib.chan_call_query.argtypes = [vp]
+    lib.chan_call_query.restype = ctypes.c_int
+    lib.chan_call_finish.argtypes = [vp, P(ctypes.c_int32)]
+    lib.chan_call_finish.restype = ctypes.c_int
+    lib.chan_batch_add.argtypes = [vp, vp]
+    lib.chan_batch_add.restype = ctypes.c_int
+    lib.chan_batch_remove.argtypes = [vp, vp]
+    lib.chan_batch_remove.restype = ctypes.c_int
     lib.chan_step_static.argtypes = [P(ChanGrid), P(ChanOpts), vp, vp, vp, ctypes.c_int32, vp, vp, vp]
     lib.chan_step_static.restype = ctypes.c_int
     _LIB = lib
@@ -249,6 +260,32 @@ def chan_batch_step_subset(h, idx, action_ptrs, n_substeps, obs_ptrs, tau_ptrs, 
     return load_library().chan_batch_step_subset(h, len(idx), ia, _ptr_array(action_ptrs), int(n_substeps),
                                                  _ptr_array(obs_ptrs), _ptr_array(tau_ptrs), _ptr_array(drag_ptrs),
                                                  results)
+
+
+def chan_batch_launch(h, stream, env_handles, action_ptrs, n_substeps, obs_ptrs, tau_ptrs, drag_ptrs):
+    """Queue one env step of the listed envs on stream; returns (code, call handle)."""
+    call = ctypes.c_void_p()
+    hs = (ctypes.c_void_p * len(env_handles))(*env_handles)
+    rc = load_library().chan_batch_launch(h, ctypes.c_void_p(stream), len(env_handles), hs,
+                                          _ptr_array(action_ptrs), int(n_substeps), _ptr_array(obs_ptrs),
+                                          _ptr_array(tau_ptrs), _ptr_array(drag_ptrs), ctypes.byref(call))
+    return rc, call
+
+
+def chan_call_query(call):
+    return load_library().chan_call_query(call)
+
+
+def chan_call_finish(call, results):
+    return load_library().chan_call_finish(call, results)
+
+
+def chan_batch_add(h, env_handle):
+    return load_library().chan_batch_add(h, env_handle)
+
+
+def chan_batch_remove(h, env_handle):
+    return load_library().chan_batch_remove(h, env_handle)
 
 
 def chan_batch_destroy(h):
@@ -405,6 +442,38 @@ class ChanBatch:
             raise ChanError(rc, "chan_batch_step_subset")
         return codes
 
+    def launch(self, envs, actions, n_substeps, obs, tau_w, drag, stream=None):
+        """Queue one env step of envs (members of this batch) on stream (a torch stream; None: the
+        current one) and return at once.  actions: float64 device tensors (nz, nx) or None per
+        env; obs, tau_w, drag: per-env output tensors (or None) written by the stream.  Returns a
+        ChanCall; the envs are held by it until its finish()."""
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream()
+        aptrs = [_action_ptr(e, actions[k] if actions is not None else None) for k, e in enumerate(envs)]
+
+        def ptrs(ts):
+            return [t.data_ptr() if t is not None else 0 for t in ts] if ts is not None else [0] * len(envs)
+
+        rc, call = chan_batch_launch(self.handle, st.cuda_stream, [e.handle for e in envs], aptrs, n_substeps,
+                                     ptrs(obs), ptrs(tau_w), ptrs(drag))
+        if rc != CHAN_OK:
+            raise ChanError(rc, "chan_batch_launch")
+        return ChanCall(call, len(envs), keep=(actions, obs, tau_w, drag))
+
+    def add(self, env):
+        rc = chan_batch_add(self.handle, env.handle)
+        if rc != CHAN_OK:
+            raise ChanError(rc, "chan_batch_add")
+        self.envs.append(env)
+        self.results = (ctypes.c_int32 * len(self.envs))()
+
+    def remove(self, env):
+        rc = chan_batch_remove(self.handle, env.handle)
+        if rc != CHAN_OK:
+            raise ChanError(rc, "chan_batch_remove")
+        self.envs.remove(env)
+        self.results = (ctypes.c_int32 * max(1, len(self.envs)))()
+
     def close(self):
         if self.handle:
             chan_batch_destroy(self.handle)
@@ -415,3 +484,32 @@ class ChanBatch:
             self.close()
         except Exception:
             pass
+
+
+class ChanCall:
+    """An asynchronous batch call (chan_batch_launch); keeps its tensors alive until finished."""
+
+    def __init__(self, handle, n, keep=None):
+        self.handle = handle
+        self.n = n
+        self.keep = keep
+        self.codes = None
+
+    def done(self):
+        """True once the call's work has finished (does not block)."""
+        if self.codes is not None:
+            return True
+        rc = chan_call_query(self.handle)
+        if rc < 0:
+            raise ChanError(rc, "chan_call_query")
+        return rc == 0
+
+    def finish(self):
+        """Wait for the call, apply its outcome to the envs and return the per-env codes."""
+        if self.codes is None:
+            res = (ctypes.c_int32 * self.n)()
+            chan_call_finish(self.handle, res)
+            self.handle = None
+            self.codes = list(res)
+            self.keep = None
+        return self.codes

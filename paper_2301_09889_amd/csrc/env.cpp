@@ -14,37 +14,57 @@
 
 using namespace chanenv;
 
-// Channels of one grid shape inside a batch: one launch per kernel covers the active ones.
-struct ShapeGroup {
+// A grid shape seen by a batch; its plane-pass tiling is tuned once and kept while the batch
+// lives, also after its channels leave.
+struct ShapeInfo {
   Dims d;
   bool pm;                        // N <= 64: the parity-major column kernels
-  std::vector<int> members;       // indices into chan_batch::envs
-  PlaneTiles tiles = {0, 0};      // plane-pass tiling chosen by tune_plane
-  // this call's active members, their arguments in the staging buffers
-  int nact = 0;
+  PlaneTiles tiles = {0, 0};
+};
+
+// Launch-argument staging of one call: the pinned host arrays, their device copy and the
+// per-env status words.  A call holds its slot from launch to finish, so calls in flight at the
+// same time never share staging.
+struct CallSlot {
+  int cap = 0;
+  size_t off_col = 0, off_plane = 0, off_status = 0, bytes = 0;
+  char* host = nullptr;           // pinned: StepChan[cap] | ColChan[cap] | PlaneChan[cap] | int[cap]
+  char* dev = nullptr;            // the same layout on the device
+  hipEvent_t done = nullptr;      // recorded after the call's last command
+  bool busy = false;
+};
+
+// A call's channels of one shape: one launch per kernel covers them.
+struct CallGroup {
+  int shape = 0;
+  std::vector<chan_env*> envs;
   ColChan* d_col = nullptr;
   const ColChan* h_col = nullptr;
   PlaneChan* d_plane = nullptr;
 };
 
-// Envs stepped together.  Each call copies the launch arguments of its active channels
-// (per-step StepChan, and the fixed ColChan / PlaneChan, grouped by shape) into one pinned
-// staging buffer and uploads it with one copy.  Every env owns a batch of one for its own
-// steps.
-struct chan_batch {
-  std::vector<chan_env*> envs;
-  std::vector<ShapeGroup> groups;
-  std::vector<int> group_of;      // env index -> group
-  std::vector<ColChan> col;       // per env
-  std::vector<PlaneChan> plane;   // per env
+// One env step of some of a batch's channels, queued on one stream (chan_batch_launch), or
+// the priming pass after reset / set_state.
+struct chan_call {
+  chan_batch* b = nullptr;
+  CallSlot* slot = nullptr;
   hipStream_t stream = nullptr;
-  void* dev = nullptr;            // staging copy on the device + int status[n]
-  char* h_stage = nullptr;        // pinned: StepChan[n] | ColChan[n] | PlaneChan[n]
-  size_t stage_bytes = 0, off_col = 0, off_plane = 0;
-  int* d_status = nullptr;
-  int* h_status = nullptr;        // pinned
-  std::vector<int> active;        // this call's env indices, in call order
+  std::vector<chan_env*> envs;    // in call order
+  std::vector<CallGroup> groups;  // in the batch's shape order
+  int n_sub = 1;
   int max_nx = 0, max_nz = 0, max_nkx = 0;
+};
+
+// Envs stepped together.  Members can join and leave; every call stages the launch arguments
+// of its channels (per-step StepChan, and the fixed ColChan / PlaneChan grouped by shape) in a
+// slot of its own and uploads them with one copy per array.  Every env owns a batch of one for
+// its own steps.
+struct chan_batch {
+  std::vector<chan_env*> envs;    // members in order (the indices of chan_batch_step_subset)
+  std::vector<ShapeInfo> shapes;
+  hipStream_t stream = nullptr;   // the synchronous calls' stream: the first member's
+  int device = 0;
+  std::vector<CallSlot*> slots;
   KernelTimer timer;
   double timing_ms[KC_COUNT];
   int64_t timing_launches[KC_COUNT];
@@ -72,6 +92,9 @@ struct chan_env {
   StageConsts sc[3];
   bool force_generic;   // CHANENV_GENERIC_COLUMN=1: use the general column kernel for every N
   chan_batch* self;     // batch of one for chan_env_step
+  ColChan col;          // the column kernels' arguments (fixed for the env's life)
+  PlaneChan plane;      // the plane kernels' arguments
+  const chan_call* in_flight;  // the unfinished asynchronous call holding this env, if any
 };
 
 namespace {
@@ -319,6 +342,7 @@ int setup_env(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_stream
   e->have_flow = false;
   e->poisoned = false;
   e->self = nullptr;
+  e->in_flight = nullptr;
   e->force_generic = generic_forced();
   e->t = 0.0;
   e->nstep = 0;
@@ -427,18 +451,24 @@ PlaneChan make_plane_chan(const chan_env* e) {
 
 bool uses_pm(const chan_env* e) { return e->d.N <= 64 && !e->force_generic; }
 
+void free_slot(CallSlot* sl) {
+  if (!sl) return;
+  if (sl->done) {
+    (void)hipEventSynchronize(sl->done);
+    (void)hipEventDestroy(sl->done);
+  }
+  if (sl->dev) (void)hipFree(sl->dev);
+  if (sl->host) (void)hipHostFree(sl->host);
+  delete sl;
+}
+
 void batch_free(chan_batch* b) {
   if (!b) return;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
+  for (CallSlot* sl : b->slots) free_slot(sl);
   for (hipEvent_t ev : b->timer.pool) (void)hipEventDestroy(ev);
-  if (b->dev) (void)hipFree(b->dev);
-  if (b->h_stage) (void)hipHostFree(b->h_stage);
-  if (b->h_status) (void)hipHostFree(b->h_status);
   delete b;
 }
-
-StepChan* stage_step(const chan_batch* b) { return (StepChan*)b->h_stage; }
-StepChan* dev_step(const chan_batch* b) { return (StepChan*)b->dev; }
 
 // The per-call launch arguments of env e; status_out: the device word that receives its status.
 StepChan make_step_chan_env(const chan_env* e, int* status_out, const double* action, int n_sub, double* obs,
@@ -497,189 +527,126 @@ StepChan make_step_chan_env(const chan_env* e, int* status_out, const double* ac
   return c;
 }
 
-// The per-call launch arguments of env i of a batch (k: its position among this call's active envs).
-StepChan make_step_chan(const chan_batch* b, int i, int k, const double* action, int n_sub, double* obs,
-                        double* tau_w, double* drag) {
-  return make_step_chan_env(b->envs[i], b->d_status + k, action, n_sub, obs, tau_w, drag);
+int find_shape(const chan_batch* b, const chan_env* e) {
+  for (size_t k = 0; k < b->shapes.size(); ++k) {
+    const ShapeInfo& sh = b->shapes[k];
+    if (sh.d.nx == e->d.nx && sh.d.ny == e->d.ny && sh.d.nz == e->d.nz && sh.pm == uses_pm(e)) return (int)k;
+  }
+  return -1;
 }
 
-// Stages the arguments of the active envs (b->active) and uploads them; StepChan entries
-// come from step(i, k).
-template <class StepFn>
-int stage_call(chan_batch* b, StepFn step) {
-  const int na = (int)b->active.size();
-  StepChan* hs = stage_step(b);
-  ColChan* hc = (ColChan*)(b->h_stage + b->off_col);
-  PlaneChan* hp = (PlaneChan*)(b->h_stage + b->off_plane);
-  char* dbase = (char*)b->dev;
-  for (ShapeGroup& g : b->groups) g.nact = 0;
-  for (int k = 0; k < na; ++k) {
-    hs[k] = step(b->active[k], k);
-    b->groups[b->group_of[b->active[k]]].nact++;
+int find_member(const chan_batch* b, const chan_env* e) {
+  for (size_t k = 0; k < b->envs.size(); ++k)
+    if (b->envs[k] == e) return (int)k;
+  return -1;
+}
+
+// A free slot holding at least n envs (grown or created if none); nullptr if out of memory.
+CallSlot* acquire_slot(chan_batch* b, int n) {
+  CallSlot* pick = nullptr;
+  for (CallSlot* sl : b->slots)
+    if (!sl->busy && sl->cap >= n) return sl->busy = true, sl;
+  for (CallSlot* sl : b->slots)
+    if (!sl->busy) {
+      pick = sl;
+      break;
+    }
+  if (!pick) {
+    pick = new (std::nothrow) CallSlot();
+    if (!pick) return nullptr;
+    if (hipEventCreateWithFlags(&pick->done, hipEventDisableTiming) != hipSuccess) {
+      delete pick;
+      return nullptr;
+    }
+    b->slots.push_back(pick);
   }
+  const int cap = std::max(n, 2 * pick->cap);
+  const size_t off_col = align256((size_t)cap * sizeof(StepChan));
+  const size_t off_plane = off_col + align256((size_t)cap * sizeof(ColChan));
+  const size_t off_status = off_plane + align256((size_t)cap * sizeof(PlaneChan));
+  const size_t bytes = off_status + align256((size_t)cap * sizeof(int));
+  char *dev = nullptr, *host = nullptr;
+  if (hipMalloc((void**)&dev, bytes) != hipSuccess) return nullptr;
+  if (hipHostMalloc((void**)&host, bytes) != hipSuccess) {
+    (void)hipFree(dev);
+    return nullptr;
+  }
+  if (pick->dev) (void)hipFree(pick->dev);
+  if (pick->host) (void)hipHostFree(pick->host);
+  pick->dev = dev;
+  pick->host = host;
+  pick->cap = cap;
+  pick->off_col = off_col;
+  pick->off_plane = off_plane;
+  pick->off_status = off_status;
+  pick->bytes = bytes;
+  pick->busy = true;
+  return pick;
+}
+
+StepChan* host_step(const chan_call* c) { return (StepChan*)c->slot->host; }
+StepChan* dev_step(const chan_call* c) { return (StepChan*)c->slot->dev; }
+int* dev_status(const chan_call* c) { return (int*)(c->slot->dev + c->slot->off_status); }
+int* host_status(const chan_call* c) { return (int*)(c->slot->host + c->slot->off_status); }
+
+// Stages the launch arguments of the call's envs (c->envs set): step(k) gives env k's
+// StepChan.  Groups the envs by shape (the batch's shape order, call order within a shape) and
+// uploads the three arrays on the call's stream.
+template <class StepFn>
+int stage_call(chan_call* c, StepFn step) {
+  chan_batch* b = c->b;
+  const int na = (int)c->envs.size();
+  c->slot = acquire_slot(b, na);
+  if (!c->slot) return fail(CHAN_ENOMEM, "call staging buffers");
+  StepChan* hs = host_step(c);
+  ColChan* hc = (ColChan*)(c->slot->host + c->slot->off_col);
+  PlaneChan* hp = (PlaneChan*)(c->slot->host + c->slot->off_plane);
+  char* dbase = c->slot->dev;
+  c->max_nx = c->max_nz = c->max_nkx = 0;
+  for (int k = 0; k < na; ++k) {
+    hs[k] = step(k);
+    c->max_nx = std::max(c->max_nx, c->envs[k]->d.nx);
+    c->max_nz = std::max(c->max_nz, c->envs[k]->d.nz);
+    c->max_nkx = std::max(c->max_nkx, c->envs[k]->d.nkx);
+  }
+  c->groups.clear();
   size_t pos = 0;
-  for (ShapeGroup& g : b->groups) {
-    g.d_col = (ColChan*)(dbase + b->off_col) + pos;
+  for (size_t sh = 0; sh < b->shapes.size(); ++sh) {
+    CallGroup g;
+    g.shape = (int)sh;
+    g.d_col = (ColChan*)(dbase + c->slot->off_col) + pos;
     g.h_col = hc + pos;
-    g.d_plane = (PlaneChan*)(dbase + b->off_plane) + pos;
-    for (int k = 0; k < na; ++k) {
-      const int i = b->active[k];
-      if (&b->groups[b->group_of[i]] != &g) continue;
-      hc[pos] = b->col[i];
-      hp[pos] = b->plane[i];
+    g.d_plane = (PlaneChan*)(dbase + c->slot->off_plane) + pos;
+    for (chan_env* e : c->envs) {
+      if (find_shape(b, e) != (int)sh) continue;
+      g.envs.push_back(e);
+      hc[pos] = e->col;
+      hp[pos] = e->plane;
       ++pos;
     }
+    if (!g.envs.empty()) c->groups.push_back(g);
   }
-  // the three arrays, each as far as it is used
-  HIPCHECK(hipMemcpyAsync(dbase, b->h_stage, na * sizeof(StepChan), hipMemcpyHostToDevice, b->stream));
-  HIPCHECK(hipMemcpyAsync(dbase + b->off_col, hc, pos * sizeof(ColChan), hipMemcpyHostToDevice, b->stream));
-  HIPCHECK(hipMemcpyAsync(dbase + b->off_plane, hp, pos * sizeof(PlaneChan), hipMemcpyHostToDevice, b->stream));
+  HIPCHECK(hipMemcpyAsync(dbase, c->slot->host, na * sizeof(StepChan), hipMemcpyHostToDevice, c->stream));
+  HIPCHECK(hipMemcpyAsync(dbase + c->slot->off_col, hc, pos * sizeof(ColChan), hipMemcpyHostToDevice, c->stream));
+  HIPCHECK(hipMemcpyAsync(dbase + c->slot->off_plane, hp, pos * sizeof(PlaneChan), hipMemcpyHostToDevice, c->stream));
   return CHAN_OK;
 }
 
-int tune_plane(chan_batch* b, ShapeGroup& g);
-
-// Groups the envs by grid shape and allocates the staging buffers.  The envs must share one
-// stream and one device and appear once each.
-int batch_build(chan_env* const* envs, int n, chan_batch** out) {
-  if (n < 1 || !envs) return fail(CHAN_EINVAL, "batch: no envs");
-  for (int i = 0; i < n; ++i) {
-    if (!envs[i]) return fail(CHAN_EINVAL, "batch: null env");
-    if (envs[i]->stream != envs[0]->stream || envs[i]->device != envs[0]->device)
-      return fail(CHAN_EINVAL, "batch: envs on different streams or devices");
-    for (int k = 0; k < i; ++k)
-      if (envs[k] == envs[i]) return fail(CHAN_EINVAL, "batch: env listed twice");
-  }
-  chan_batch* b = new (std::nothrow) chan_batch();
-  if (!b) return CHAN_ENOMEM;
-  b->envs.assign(envs, envs + n);
-  b->stream = envs[0]->stream;
-  for (int k = 0; k < KC_COUNT; ++k) {
-    b->timing_ms[k] = 0.0;
-    b->timing_launches[k] = 0;
-  }
-  for (int i = 0; i < n; ++i) {
-    const chan_env* e = envs[i];
-    const bool pm = uses_pm(e);
-    int gi = -1;
-    for (size_t g = 0; g < b->groups.size(); ++g) {
-      const Dims& d = b->groups[g].d;
-      if (d.nx == e->d.nx && d.ny == e->d.ny && d.nz == e->d.nz && b->groups[g].pm == pm) gi = (int)g;
-    }
-    if (gi < 0) {
-      b->groups.push_back(ShapeGroup());
-      gi = (int)b->groups.size() - 1;
-      b->groups[gi].d = e->d;
-      b->groups[gi].pm = pm;
-    }
-    b->groups[gi].members.push_back(i);
-    b->group_of.push_back(gi);
-    b->col.push_back(make_col_chan(e));
-    b->plane.push_back(make_plane_chan(e));
-    if (e->d.ny * (int)b->groups[gi].members.size() > 65535) {
-      batch_free(b);
-      return fail(CHAN_EINVAL, "batch: too many channels of one shape (N_y x count > 65535)");
-    }
-    b->max_nx = std::max(b->max_nx, e->d.nx);
-    b->max_nz = std::max(b->max_nz, e->d.nz);
-    b->max_nkx = std::max(b->max_nkx, e->d.nkx);
-  }
-  b->off_col = align256(n * sizeof(StepChan));
-  b->off_plane = b->off_col + align256(n * sizeof(ColChan));
-  b->stage_bytes = b->off_plane + align256(n * sizeof(PlaneChan));
-  hipError_t err = hipMalloc(&b->dev, b->stage_bytes + align256(n * sizeof(int)));
-  if (err != hipSuccess) {
-    batch_free(b);
-    return fail(CHAN_ENOMEM, "hipMalloc(batch)", err);
-  }
-  b->d_status = (int*)((char*)b->dev + b->stage_bytes);
-  // clear status words: the tuning launches below test them before their stores
-  err = hipMemsetAsync(b->d_status, 0, n * sizeof(int), b->stream);
-  if (err != hipSuccess) {
-    batch_free(b);
-    return fail(CHAN_EDEVICE, "hipMemsetAsync(batch status)", err);
-  }
-  if (hipHostMalloc((void**)&b->h_stage, b->stage_bytes) != hipSuccess ||
-      hipHostMalloc((void**)&b->h_status, n * sizeof(int)) != hipSuccess) {
-    batch_free(b);
-    return fail(CHAN_ENOMEM, "hipHostMalloc(batch)");
-  }
-  // tune with every env staged (no step arguments are used by the plane pass)
-  b->active.resize(n);
-  for (int i = 0; i < n; ++i) b->active[i] = i;
-  int rc = stage_call(b, [&](int i, int k) { return make_step_chan(b, i, k, nullptr, 1, nullptr, nullptr, nullptr); });
-  for (size_t g = 0; g < b->groups.size() && rc == CHAN_OK; ++g) rc = tune_plane(b, b->groups[g]);
-  if (rc != CHAN_OK) {
-    batch_free(b);
-    return rc;
-  }
-  *out = b;
-  return CHAN_OK;
+void release_call(chan_call* c) {
+  for (chan_env* e : c->envs)
+    if (e->in_flight == c) e->in_flight = nullptr;
+  if (c->slot) c->slot->busy = false;
+  c->slot = nullptr;
 }
 
-// Plane-pass tiling of a group: every valid tiling is timed on the group's own buffers and
-// the fastest kept (the plane pass rewrites only its intermediates and H3, with the values
-// the next plane pass writes anyway, and no tiling changes a result).
-int tune_plane(chan_batch* b, ShapeGroup& g) {
-  std::vector<PlaneTiles> cands;
-  if (plane_tile_candidates(g.d, &cands)) return fail(CHAN_EINVAL, "no plane-pass tiling for this grid");
-  g.tiles = cands.back();
-  if (cands.size() == 1) return CHAN_OK;
-  const int nm = g.nact;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  HIPCHECK(hipEventCreate(&e0));
-  hipError_t err = hipEventCreate(&e1);
-  if (err != hipSuccess) {
-    (void)hipEventDestroy(e0);
-    return fail(CHAN_EDEVICE, "hipEventCreate", err);
-  }
-  // Every candidate is timed in each of ROUNDS sweeps over the list (REPS back-to-back plane
-  // passes after one warm-up) and keeps its best sweep, so that clock ramps and one-off
-  // stalls do not decide the choice.
-  constexpr int REPS = 4, ROUNDS = 3;
-  std::vector<float> best_ms(cands.size(), 0.0f);
-  std::vector<char> ran(cands.size(), 0);
-  for (int round = 0; round < ROUNDS && err == hipSuccess; ++round) {
-    for (size_t c = 0; c < cands.size(); ++c) {
-      const PlaneTiles& t = cands[c];
-      if (launch_plane_pass(g.d, g.d_plane, nm, t, b->stream, nullptr)) continue;  // warm-up
-      err = hipEventRecord(e0, b->stream);
-      for (int k = 0; k < REPS && err == hipSuccess; ++k)
-        if (launch_plane_pass(g.d, g.d_plane, nm, t, b->stream, nullptr)) err = hipErrorLaunchFailure;
-      if (err == hipSuccess) err = hipEventRecord(e1, b->stream);
-      if (err == hipSuccess) err = hipEventSynchronize(e1);
-      float ms = 0.0f;
-      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-      if (err != hipSuccess) break;
-      if (!ran[c] || ms < best_ms[c]) best_ms[c] = ms;
-      ran[c] = 1;
-    }
-  }
-  bool have = false;
-  float best = 0.0f;
-  for (size_t c = 0; c < cands.size() && err == hipSuccess; ++c) {
-    if (ran[c] && (!have || best_ms[c] < best)) {
-      best = best_ms[c];
-      g.tiles = cands[c];
-      have = true;
-    }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (err != hipSuccess) return fail(CHAN_EDEVICE, "plane-pass tiling", err);
-  return have ? CHAN_OK : fail(CHAN_EDEVICE, "plane-pass tiling: no candidate ran", hipGetLastError());
-}
-
-// Column pass of one group's active channels after the plane pass of stage S.stage (or,
-// S.stage = -1, the reconstruction alone).
-int group_column(chan_batch* b, const ShapeGroup& g, const ColStage& S, bool solve, bool recon, KernelTimer* tm) {
-  if (g.nact == 0) return 0;
-  if (g.pm) return launch_column_pm(g.d, g.d_col, g.h_col, g.nact, S, solve, recon, b->stream, tm);
-  for (int k = 0; k < g.nact; ++k) {
-    const ColChan& c = g.h_col[k];
-    chan_env* e = nullptr;
-    for (int i : g.members)
-      if (b->col[i].vS == c.vS) e = b->envs[i];
+// Column pass of one group after the plane pass of stage S.stage (or, S.stage = -1, the
+// reconstruction alone).
+int group_column(const chan_batch* b, const CallGroup& g, hipStream_t st, const ColStage& S, bool solve, bool recon,
+                 KernelTimer* tm) {
+  if (g.envs.empty()) return 0;
+  const ShapeInfo& sh = b->shapes[g.shape];
+  if (sh.pm) return launch_column_pm(sh.d, g.d_col, g.h_col, (int)g.envs.size(), S, solve, recon, st, tm);
+  for (chan_env* e : g.envs) {
     const int r = S.stage;
     int mode = WALL_OPP;
     double s = 0.0;
@@ -688,69 +655,166 @@ int group_column(chan_batch* b, const ShapeGroup& g, const ColStage& S, bool sol
       if (r >= 0) s = (e->opts.action_mode == CHAN_HOLD) ? 1.0 : (S.m + RK_C_END[r]) / (double)S.n_sub;
     }
     if (launch_column_pass(e->d, e->s, e->ph, r, e->sc[r < 0 ? 0 : r], mode, s, e->js, e->opts.opp_alpha, r == 2,
-                           recon, b->stream, tm))
+                           recon, st, tm))
       return -1;
   }
   return 0;
 }
 
-// Plane-pass input, opposition target and wall shear from the stored state of every env of
-// the batch (after reset or set_state).
-int batch_prime(chan_batch* b) {
-  const int n = (int)b->envs.size();
-  b->active.resize(n);
-  for (int i = 0; i < n; ++i) b->active[i] = i;
-  int rc = stage_call(b, [&](int i, int k) {
-    StepChan c = make_step_chan(b, i, k, nullptr, 1, nullptr, nullptr, nullptr);
-    c.zero_vw = 0;
-    c.skip = 0;
-    return c;
-  });
-  if (rc != CHAN_OK) return rc;
-  if (launch_begin_step(dev_step(b), n, b->stream, nullptr))
-    return fail(CHAN_EDEVICE, "launch begin_step", hipGetLastError());
-  const ColStage S = {-1, 0, 1};
-  for (const ShapeGroup& g : b->groups)
-    if (group_column(b, g, S, false, true, nullptr))
-      return fail(CHAN_EDEVICE, "launch column pass", hipGetLastError());
-  HIPCHECK(hipStreamSynchronize(b->stream));
+int tune_plane(chan_batch* b, int shape, const std::vector<chan_env*>& members);
+
+// Adds env to the batch (its shape's tiling tuned on it if the shape is new).
+int batch_add(chan_batch* b, chan_env* e) {
+  if (!e) return fail(CHAN_EINVAL, "batch: null env");
+  if (e->device != b->device) return fail(CHAN_EINVAL, "batch: env on another device");
+  if (find_member(b, e) >= 0) return fail(CHAN_EINVAL, "batch: env listed twice");
+  if (e->in_flight) return fail(CHAN_EBUSY, "batch: env has an unfinished call");
+  int sh = find_shape(b, e);
+  if (sh < 0) {
+    ShapeInfo info;
+    info.d = e->d;
+    info.pm = uses_pm(e);
+    b->shapes.push_back(info);
+    sh = (int)b->shapes.size() - 1;
+    const int rc = tune_plane(b, sh, std::vector<chan_env*>{e});
+    if (rc != CHAN_OK) {
+      b->shapes.pop_back();
+      return rc;
+    }
+  }
+  b->envs.push_back(e);
   return CHAN_OK;
 }
 
-// One env step of the envs idx[0..na) of the batch (per-call arrays indexed like idx; any
-// array may be null = all null).
-int batch_step(chan_batch* b, int32_t na, const int32_t* idx, const double* const* actions, int32_t n_substeps,
-               double* const* obs, double* const* tau_w, double* const* drag, int32_t* results) {
-  if (n_substeps < 1) return fail(CHAN_EINVAL, "n_substeps < 1");
-  const int n = (int)b->envs.size();
-  if (na < 1 || na > n) return fail(CHAN_EINVAL, "batch step: bad number of envs");
-  b->active.resize(na);
-  {
-    std::vector<char> seen(n, 0);
-    for (int k = 0; k < na; ++k) {
-      const int i = idx ? idx[k] : k;
-      if (i < 0 || i >= n || seen[i]) return fail(CHAN_EINVAL, "batch step: env index out of range or repeated");
-      seen[i] = 1;
-      b->active[k] = i;
+int batch_build(chan_env* const* envs, int n, chan_batch** out) {
+  if (n < 1 || !envs) return fail(CHAN_EINVAL, "batch: no envs");
+  for (int i = 0; i < n; ++i)
+    if (!envs[i]) return fail(CHAN_EINVAL, "batch: null env");
+  chan_batch* b = new (std::nothrow) chan_batch();
+  if (!b) return CHAN_ENOMEM;
+  b->stream = envs[0]->stream;
+  b->device = envs[0]->device;
+  for (int k = 0; k < KC_COUNT; ++k) {
+    b->timing_ms[k] = 0.0;
+    b->timing_launches[k] = 0;
+  }
+  // shapes first, each tuned on all of its channels together
+  for (int i = 0; i < n; ++i) {
+    if (envs[i]->device != b->device) {
+      batch_free(b);
+      return fail(CHAN_EINVAL, "batch: envs on different devices");
+    }
+    for (int k = 0; k < i; ++k)
+      if (envs[k] == envs[i]) {
+        batch_free(b);
+        return fail(CHAN_EINVAL, "batch: env listed twice");
+      }
+    if (envs[i]->in_flight) {
+      batch_free(b);
+      return fail(CHAN_EBUSY, "batch: env has an unfinished call");
+    }
+    if (find_shape(b, envs[i]) < 0) {
+      ShapeInfo info;
+      info.d = envs[i]->d;
+      info.pm = uses_pm(envs[i]);
+      b->shapes.push_back(info);
     }
   }
-  int n_ready = 0;
-  for (int k = 0; k < na; ++k) n_ready += (b->envs[b->active[k]]->have_flow && !b->envs[b->active[k]]->poisoned) ? 1 : 0;
-  if (n_ready == 0) return fail(CHAN_ESTATE, "no env with a valid flow state");
-  g_last_error.clear();
-  bool any_action = false;
-  int rc = stage_call(b, [&](int i, int k) {
-    StepChan c = make_step_chan(b, i, k, actions ? actions[k] : nullptr, n_substeps, obs ? obs[k] : nullptr,
-                                tau_w ? tau_w[k] : nullptr, drag ? drag[k] : nullptr);
-    any_action = any_action || (c.action != nullptr && !c.skip);
-    return c;
+  for (size_t sh = 0; sh < b->shapes.size(); ++sh) {
+    std::vector<chan_env*> members;
+    for (int i = 0; i < n; ++i)
+      if (find_shape(b, envs[i]) == (int)sh) members.push_back(envs[i]);
+    if ((size_t)b->shapes[sh].d.ny * members.size() > 65535) {
+      batch_free(b);
+      return fail(CHAN_EINVAL, "batch: too many channels of one shape (N_y x count > 65535)");
+    }
+    const int rc = tune_plane(b, (int)sh, members);
+    if (rc != CHAN_OK) {
+      batch_free(b);
+      return rc;
+    }
+  }
+  b->envs.assign(envs, envs + n);
+  *out = b;
+  return CHAN_OK;
+}
+
+// Plane-pass tiling of a shape, timed on the given channels' own buffers with every valid
+// tiling; the fastest is kept.  The plane pass rewrites only its intermediates and H3 with the
+// values the next plane pass writes anyway, and no tiling changes a result.  The channels must
+// not be in an unfinished call.
+int tune_plane(chan_batch* b, int shape, const std::vector<chan_env*>& members) {
+  ShapeInfo& sh = b->shapes[shape];
+  std::vector<PlaneTiles> cands;
+  if (plane_tile_candidates(sh.d, &cands)) return fail(CHAN_EINVAL, "no plane-pass tiling for this grid");
+  sh.tiles = cands.back();
+  if (cands.size() == 1) return CHAN_OK;
+  chan_call c;
+  c.b = b;
+  c.stream = b->stream;
+  c.envs = members;
+  int rc = stage_call(&c, [&](int k) {
+    return make_step_chan_env(members[k], dev_status(&c) + k, nullptr, 1, nullptr, nullptr, nullptr);
   });
-  if (rc != CHAN_OK) return rc;
-  hipStream_t st = b->stream;
-  KernelTimer* tm = b->timer.on ? &b->timer : nullptr;
-  StepChan* ds = dev_step(b);
+  if (rc != CHAN_OK) {
+    release_call(&c);
+    return rc;
+  }
+  const CallGroup& g = c.groups[0];
+  const int nm = (int)g.envs.size();
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t err = hipEventCreate(&e0);
+  if (err == hipSuccess) err = hipEventCreate(&e1);
+  // Every candidate is timed in each of ROUNDS sweeps over the list (REPS back-to-back plane
+  // passes after one warm-up) and keeps its best sweep, so that clock ramps and one-off
+  // stalls do not decide the choice.
+  constexpr int REPS = 4, ROUNDS = 3;
+  std::vector<float> best_ms(cands.size(), 0.0f);
+  std::vector<char> ran(cands.size(), 0);
+  for (int round = 0; round < ROUNDS && err == hipSuccess; ++round) {
+    for (size_t k = 0; k < cands.size(); ++k) {
+      const PlaneTiles& t = cands[k];
+      if (launch_plane_pass(sh.d, g.d_plane, nm, t, c.stream, nullptr)) continue;  // warm-up
+      err = hipEventRecord(e0, c.stream);
+      for (int r = 0; r < REPS && err == hipSuccess; ++r)
+        if (launch_plane_pass(sh.d, g.d_plane, nm, t, c.stream, nullptr)) err = hipErrorLaunchFailure;
+      if (err == hipSuccess) err = hipEventRecord(e1, c.stream);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      if (err != hipSuccess) break;
+      if (!ran[k] || ms < best_ms[k]) best_ms[k] = ms;
+      ran[k] = 1;
+    }
+  }
+  bool have = false;
+  float best = 0.0f;
+  for (size_t k = 0; k < cands.size() && err == hipSuccess; ++k) {
+    if (ran[k] && (!have || best_ms[k] < best)) {
+      best = best_ms[k];
+      sh.tiles = cands[k];
+      have = true;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  const hipError_t sync = hipStreamSynchronize(c.stream);
+  release_call(&c);
+  if (err == hipSuccess) err = sync;
+  if (err != hipSuccess) return fail(CHAN_EDEVICE, "plane-pass tiling", err);
+  return have ? CHAN_OK : fail(CHAN_EDEVICE, "plane-pass tiling: no candidate ran", hipGetLastError());
+}
+
+// Queues the launches of one env step of the call's envs (already staged), then the status
+// read-back and the completion event.
+int launch_step(chan_call* c, bool any_action, KernelTimer* tm, double* const* obs) {
+  chan_batch* b = c->b;
+  hipStream_t st = c->stream;
+  const int na = (int)c->envs.size();
+  const int n_substeps = c->n_sub;
+  StepChan* ds = dev_step(c);
   if (launch_begin_step(ds, na, st, tm)) return fail(CHAN_EDEVICE, "launch begin_step", hipGetLastError());
-  if (any_action && launch_ingest(ds, na, b->max_nx, b->max_nz, b->max_nkx, st, tm))
+  if (any_action && launch_ingest(ds, na, c->max_nx, c->max_nz, c->max_nkx, st, tm))
     return fail(CHAN_EDEVICE, "launch ingest", hipGetLastError());
   for (int m = 0; m < n_substeps; ++m) {
     for (int r = 0; r < 3; ++r) {
@@ -758,44 +822,41 @@ int batch_step(chan_batch* b, int32_t na, const int32_t* idx, const double* cons
       // below, which also serves set_state (bitwise-identical resume).
       const bool last = (m == n_substeps - 1) && (r == 2);
       const ColStage S = {r, m, n_substeps};
-      for (const ShapeGroup& g : b->groups) {
-        if (g.nact == 0) continue;
-        if (launch_plane_pass(g.d, g.d_plane, g.nact, g.tiles, st, tm))
+      for (const CallGroup& g : c->groups) {
+        const ShapeInfo& sh = b->shapes[g.shape];
+        if (launch_plane_pass(sh.d, g.d_plane, (int)g.envs.size(), sh.tiles, st, tm))
           return fail(CHAN_EDEVICE, "launch plane pass", hipGetLastError());
-        if (group_column(b, g, S, true, !last, tm)) return fail(CHAN_EDEVICE, "launch column pass", hipGetLastError());
+        if (group_column(b, g, st, S, true, !last, tm)) return fail(CHAN_EDEVICE, "launch column pass", hipGetLastError());
       }
     }
   }
   const ColStage S_end = {-1, 0, n_substeps};
-  for (const ShapeGroup& g : b->groups)
-    if (group_column(b, g, S_end, false, true, tm)) return fail(CHAN_EDEVICE, "launch column pass", hipGetLastError());
+  for (const CallGroup& g : c->groups)
+    if (group_column(b, g, st, S_end, false, true, tm)) return fail(CHAN_EDEVICE, "launch column pass", hipGetLastError());
   // pressure observed: the end-of-step state's non-linear term (a plane pass; the next step's
   // first stage recomputes the same H), then the Poisson solve per pair, before finish_step
   // replaces the old wall velocity (its rate enters the wall condition)
   int max_planes = 1;
   bool any_pressure = false;
   for (int k = 0; k < na; ++k) {
-    const chan_env* e = b->envs[b->active[k]];
+    const chan_env* e = c->envs[k];
     max_planes = std::max(max_planes, e->n_planes);
     any_pressure = any_pressure || (obs != nullptr && obs[k] != nullptr && (e->opts.obs_mask & CHAN_OBS_P));
   }
   if (any_pressure)
-    for (const ShapeGroup& g : b->groups) {
+    for (const CallGroup& g : c->groups) {
+      const ShapeInfo& sh = b->shapes[g.shape];
       bool has = false;
-      for (int k = 0; k < g.nact; ++k) has = has || g.h_col[k].n_pplanes > 0;
+      for (size_t k = 0; k < g.envs.size(); ++k) has = has || g.h_col[k].n_pplanes > 0;
       if (!has) continue;
-      if (launch_plane_pass(g.d, g.d_plane, g.nact, g.tiles, st, tm))
+      if (launch_plane_pass(sh.d, g.d_plane, (int)g.envs.size(), sh.tiles, st, tm))
         return fail(CHAN_EDEVICE, "launch plane pass (pressure)", hipGetLastError());
-      if (g.pm) {
-        if (launch_pressure_pm(g.d, g.d_col, g.nact, S_end, st, tm))
+      if (sh.pm) {
+        if (launch_pressure_pm(sh.d, g.d_col, (int)g.envs.size(), S_end, st, tm))
           return fail(CHAN_EDEVICE, "launch pressure", hipGetLastError());
       } else {
-        for (int k = 0; k < g.nact; ++k) {
-          if (g.h_col[k].n_pplanes == 0) continue;
-          const chan_env* e = nullptr;
-          for (int i : g.members)
-            if (b->col[i].vS == g.h_col[k].vS) e = b->envs[i];
-          if (!e) continue;
+        for (const chan_env* e : g.envs) {
+          if (e->col.n_pplanes == 0) continue;
           const bool ramp = e->opts.controller == CHAN_CTRL_EXTERNAL && e->opts.action_mode == CHAN_RAMP;
           if (launch_pressure_generic(e->d, e->s, e->ph, e->n_planes, e->js_planes, ramp, n_substeps, st, tm))
             return fail(CHAN_EDEVICE, "launch pressure", hipGetLastError());
@@ -804,43 +865,146 @@ int batch_step(chan_batch* b, int32_t na, const int32_t* idx, const double* cons
     }
   if (launch_finish_step(ds, na, st, tm)) return fail(CHAN_EDEVICE, "launch finish_step", hipGetLastError());
   const int nslots = any_pressure ? 1 + SLOTS_PER_PLANE * max_planes : SLOTS_PER_PLANE * max_planes - 3;
-  if (launch_outputs(ds, na, b->max_nx, b->max_nz, b->max_nkx, nslots, st, tm))
+  if (launch_outputs(ds, na, c->max_nx, c->max_nz, c->max_nkx, nslots, st, tm))
     return fail(CHAN_EDEVICE, "launch outputs", hipGetLastError());
   if (any_pressure && launch_pressure_finish(ds, na, st, tm))
     return fail(CHAN_EDEVICE, "launch pressure finish", hipGetLastError());
-  HIPCHECK(hipMemcpyAsync(b->h_status, b->d_status, na * sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCHECK(hipStreamSynchronize(st));
-  rc = CHAN_OK;
-  const StepChan* hs = stage_step(b);
+  HIPCHECK(hipMemcpyAsync(host_status(c), dev_status(c), na * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipEventRecord(c->slot->done, st));
+  return CHAN_OK;
+}
+
+// Validates and queues one env step of envs[0..na) on stream st; on success *out holds the call
+// (every env marked as held by it).
+int batch_launch(chan_batch* b, hipStream_t st, int32_t na, chan_env* const* envs, const double* const* actions,
+                 int32_t n_substeps, double* const* obs, double* const* tau_w, double* const* drag, chan_call** out) {
+  if (n_substeps < 1) return fail(CHAN_EINVAL, "n_substeps < 1");
+  if (na < 1 || na > (int32_t)b->envs.size() || !envs) return fail(CHAN_EINVAL, "batch step: bad number of envs");
   for (int k = 0; k < na; ++k) {
-    chan_env* e = b->envs[b->active[k]];
-    const int status = b->h_status[k];
-    int ri = CHAN_OK;
-    if (hs[k].skip) {
-      ri = CHAN_ESTATE;
-      if (rc == CHAN_OK) fail(CHAN_ESTATE, "env without a valid flow state (skipped)");
-    } else if (status & STATUS_BAD_ACTION) {
-      ri = CHAN_ENONFINITE;
-      if (rc == CHAN_OK) fail(CHAN_ENONFINITE, "non-finite action");
-    } else {
-      e->t += n_substeps * e->ph.dt;
-      e->nstep += n_substeps;
-      if (status & STATUS_NONFINITE) {
-        e->poisoned = true;
-        ri = CHAN_ENONFINITE;
-        if (rc == CHAN_OK) fail(CHAN_ENONFINITE, "non-finite state after the step");
-      }
-    }
-    if (results) results[k] = ri;
-    if (rc == CHAN_OK) rc = ri;
+    if (!envs[k] || find_member(b, envs[k]) < 0) return fail(CHAN_EINVAL, "batch step: env not in the batch");
+    if (envs[k]->in_flight) return fail(CHAN_EBUSY, "batch step: env has an unfinished call");
+    for (int j = 0; j < k; ++j)
+      if (envs[j] == envs[k]) return fail(CHAN_EINVAL, "batch step: env listed twice");
   }
+  int n_ready = 0;
+  for (int k = 0; k < na; ++k) n_ready += (envs[k]->have_flow && !envs[k]->poisoned) ? 1 : 0;
+  if (n_ready == 0) return fail(CHAN_ESTATE, "no env with a valid flow state");
+  chan_call* c = new (std::nothrow) chan_call();
+  if (!c) return CHAN_ENOMEM;
+  c->b = b;
+  c->stream = st;
+  c->n_sub = n_substeps;
+  c->envs.assign(envs, envs + na);
+  bool any_action = false;
+  int rc = stage_call(c, [&](int k) {
+    StepChan s = make_step_chan_env(c->envs[k], dev_status(c) + k, actions ? actions[k] : nullptr, n_substeps,
+                                    obs ? obs[k] : nullptr, tau_w ? tau_w[k] : nullptr, drag ? drag[k] : nullptr);
+    any_action = any_action || (s.action != nullptr && !s.skip);
+    return s;
+  });
+  if (rc == CHAN_OK) rc = launch_step(c, any_action, b->timer.on ? &b->timer : nullptr, obs);
+  if (rc != CHAN_OK) {
+    (void)hipStreamSynchronize(st);
+    release_call(c);
+    delete c;
+    return rc;
+  }
+  for (chan_env* e : c->envs) e->in_flight = c;
+  *out = c;
+  return CHAN_OK;
+}
+
+// Waits for the call, applies each env's outcome (clock, step counter, poisoning), writes the
+// result codes, frees the call.  Returns CHAN_OK if every env succeeded, else the first
+// failing env's code.
+int batch_finish(chan_call* c, int32_t* results) {
+  const hipError_t err = hipEventSynchronize(c->slot->done);
+  int rc = CHAN_OK;
+  if (err != hipSuccess) {
+    rc = fail(CHAN_EDEVICE, "hipEventSynchronize", err);
+  } else {
+    const StepChan* hs = host_step(c);
+    const int* status = host_status(c);
+    for (size_t k = 0; k < c->envs.size(); ++k) {
+      chan_env* e = c->envs[k];
+      int ri = CHAN_OK;
+      if (hs[k].skip) {
+        ri = CHAN_ESTATE;
+        if (rc == CHAN_OK) fail(CHAN_ESTATE, "env without a valid flow state (skipped)");
+      } else if (status[k] & STATUS_BAD_ACTION) {
+        ri = CHAN_ENONFINITE;
+        if (rc == CHAN_OK) fail(CHAN_ENONFINITE, "non-finite action");
+      } else {
+        e->t += c->n_sub * e->ph.dt;
+        e->nstep += c->n_sub;
+        if (status[k] & STATUS_NONFINITE) {
+          e->poisoned = true;
+          ri = CHAN_ENONFINITE;
+          if (rc == CHAN_OK) fail(CHAN_ENONFINITE, "non-finite state after the step");
+        }
+      }
+      if (results) results[k] = ri;
+      if (rc == CHAN_OK) rc = ri;
+    }
+  }
+  release_call(c);
+  delete c;
   return rc;
+}
+
+// Synchronous env step of the batch's envs idx[0..na) (idx null: the first na) on the batch's
+// stream.
+int batch_step(chan_batch* b, int32_t na, const int32_t* idx, const double* const* actions, int32_t n_substeps,
+               double* const* obs, double* const* tau_w, double* const* drag, int32_t* results) {
+  const int n = (int)b->envs.size();
+  if (na < 1 || na > n) return fail(CHAN_EINVAL, "batch step: bad number of envs");
+  std::vector<chan_env*> envs(na);
+  for (int k = 0; k < na; ++k) {
+    const int i = idx ? idx[k] : k;
+    if (i < 0 || i >= n) return fail(CHAN_EINVAL, "batch step: env index out of range or repeated");
+    envs[k] = b->envs[i];
+  }
+  g_last_error.clear();
+  chan_call* c = nullptr;
+  const int rc = batch_launch(b, b->stream, na, envs.data(), actions, n_substeps, obs, tau_w, drag, &c);
+  if (rc != CHAN_OK) {
+    if (rc == CHAN_EINVAL && g_last_error == "batch step: env listed twice")
+      g_last_error = "batch step: env index out of range or repeated";
+    return rc;
+  }
+  return batch_finish(c, results);
+}
+
+// Plane-pass input, opposition target and wall shear from the stored state of env e (after
+// reset or set_state), on its own batch of one.
+int batch_prime(chan_batch* b) {
+  chan_call c;
+  c.b = b;
+  c.stream = b->stream;
+  c.envs = b->envs;
+  int rc = stage_call(&c, [&](int k) {
+    StepChan s = make_step_chan_env(c.envs[k], dev_status(&c) + k, nullptr, 1, nullptr, nullptr, nullptr);
+    s.zero_vw = 0;
+    s.skip = 0;
+    return s;
+  });
+  if (rc == CHAN_OK && launch_begin_step(dev_step(&c), (int)c.envs.size(), c.stream, nullptr))
+    rc = fail(CHAN_EDEVICE, "launch begin_step", hipGetLastError());
+  const ColStage S = {-1, 0, 1};
+  for (size_t k = 0; k < c.groups.size() && rc == CHAN_OK; ++k)
+    if (group_column(b, c.groups[k], c.stream, S, false, true, nullptr))
+      rc = fail(CHAN_EDEVICE, "launch column pass", hipGetLastError());
+  const hipError_t err = hipStreamSynchronize(c.stream);
+  release_call(&c);
+  if (rc != CHAN_OK) return rc;
+  if (err != hipSuccess) return fail(CHAN_EDEVICE, "hipStreamSynchronize", err);
+  return CHAN_OK;
 }
 
 int batch_drain_timer(chan_batch* b) {
   KernelTimer& t = b->timer;
   if (t.used == 0) return CHAN_OK;
-  HIPCHECK(hipStreamSynchronize(b->stream));
+  HIPCHECK(hipDeviceSynchronize());
   for (size_t k = 0; k < t.used; ++k) {
     float ms = 0.0f;
     HIPCHECK(hipEventElapsedTime(&ms, t.pool[2 * k], t.pool[2 * k + 1]));
@@ -967,6 +1131,7 @@ const char* chan_strerror(int code) {
     case CHAN_EDEVICE: return "HIP device error";
     case CHAN_ENONFINITE: return "non-finite action or state";
     case CHAN_ESTATE: return "no flow state (reset or set_state first) or poisoned state";
+    case CHAN_EBUSY: return "env held by an unfinished asynchronous call";
     default: return "unknown error";
   }
 }
@@ -1026,6 +1191,8 @@ int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_
   }
   DeviceState& s = e->s;
   carve_state(d, z, ht.L, (char*)e->dev_block, &s);
+  e->col = make_col_chan(e);
+  e->plane = make_plane_chan(e);
   {
     hipError_t err = hipMemsetAsync(e->dev_block, 0, z.total, e->stream);
     const char* what = "hipMemsetAsync";
@@ -1058,6 +1225,7 @@ int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_
 
 void chan_env_destroy(chan_env* e) {
   if (!e) return;
+  if (e->in_flight) (void)hipDeviceSynchronize();
   if (e->stream) (void)hipStreamSynchronize(e->stream);
   batch_free(e->self);
   if (e->dev_block) (void)hipFree(e->dev_block);
@@ -1067,6 +1235,7 @@ void chan_env_destroy(chan_env* e) {
 
 int chan_env_reset(chan_env* e, uint64_t seed) {
   if (!e) return CHAN_EINVAL;
+  if (e->in_flight) return fail(CHAN_EBUSY, "env held by an unfinished call");
   std::vector<double> flat;
   try {
     initial_condition(e->d, e->ph, e->opts.ic_profile, e->opts.ic_amp, seed, &flat);
@@ -1078,6 +1247,7 @@ int chan_env_reset(chan_env* e, uint64_t seed) {
 
 int chan_env_set_state(chan_env* e, const double* host, size_t n_doubles) {
   if (!e || !host) return CHAN_EINVAL;
+  if (e->in_flight) return fail(CHAN_EBUSY, "env held by an unfinished call");
   const Dims& d = e->d;
   const size_t n = (size_t)4 * d.nz * d.nkx * d.ny + 2 * (size_t)d.ny + 2 * (size_t)d.nz * d.nkx + 2;
   if (n_doubles != n) return CHAN_EINVAL;
@@ -1088,6 +1258,7 @@ int chan_env_set_state(chan_env* e, const double* host, size_t n_doubles) {
 
 int chan_env_get_state(const chan_env* e, double* host, size_t n_doubles) {
   if (!e || !host) return CHAN_EINVAL;
+  if (e->in_flight) return fail(CHAN_EBUSY, "env held by an unfinished call");
   const Dims& d = e->d;
   const int NY = d.ny, nz = d.nz, nkx = d.nkx;
   const size_t n = (size_t)4 * nz * nkx * NY + 2 * (size_t)NY + 2 * (size_t)nz * nkx + 2;
@@ -1146,6 +1317,7 @@ int chan_env_query(const chan_env* e, chan_info_t* out) {
 int chan_env_step(chan_env* e, const double* action, int32_t n_substeps, double* obs, double* tau_w,
                   double* drag) {
   if (!e) return CHAN_EINVAL;
+  if (e->in_flight) return fail(CHAN_EBUSY, "env held by an unfinished call");
   return batch_step(e->self, 1, nullptr, &action, n_substeps, &obs, &tau_w, &drag, nullptr);
 }
 
@@ -1167,6 +1339,44 @@ int chan_batch_step_subset(chan_batch* b, int32_t n, const int32_t* idx, const d
                            int32_t* results) {
   if (!b || !idx) return CHAN_EINVAL;
   return batch_step(b, n, idx, actions, n_substeps, obs, tau_w, drag, results);
+}
+
+int chan_batch_launch(chan_batch* b, void* hip_stream, int32_t n, chan_env* const* envs,
+                      const double* const* actions, int32_t n_substeps, double* const* obs, double* const* tau_w,
+                      double* const* drag, chan_call** out) {
+  g_last_error.clear();
+  if (!b || !out) return CHAN_EINVAL;
+  *out = nullptr;
+  return batch_launch(b, (hipStream_t)hip_stream, n, envs, actions, n_substeps, obs, tau_w, drag, out);
+}
+
+int chan_call_query(const chan_call* c) {
+  if (!c || !c->slot) return CHAN_EINVAL;
+  const hipError_t err = hipEventQuery(c->slot->done);
+  if (err == hipSuccess) return 0;
+  if (err == hipErrorNotReady) return 1;
+  return fail(CHAN_EDEVICE, "hipEventQuery", err);
+}
+
+int chan_call_finish(chan_call* c, int32_t* results) {
+  if (!c || !c->slot) return CHAN_EINVAL;
+  g_last_error.clear();
+  return batch_finish(c, results);
+}
+
+int chan_batch_add(chan_batch* b, chan_env* env) {
+  if (!b) return CHAN_EINVAL;
+  g_last_error.clear();
+  return batch_add(b, env);
+}
+
+int chan_batch_remove(chan_batch* b, chan_env* env) {
+  if (!b || !env) return CHAN_EINVAL;
+  const int k = find_member(b, env);
+  if (k < 0) return fail(CHAN_EINVAL, "batch: env not in the batch");
+  if (env->in_flight) return fail(CHAN_EBUSY, "batch: env held by an unfinished call");
+  b->envs.erase(b->envs.begin() + k);
+  return CHAN_OK;
 }
 
 void chan_batch_destroy(chan_batch* b) { batch_free(b); }

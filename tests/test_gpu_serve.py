@@ -1,6 +1,10 @@
-"""The request loop (continuous batching over resident channels) on the GPU: every channel's
-results are bitwise those of the same requests served alone, and admission follows the HBM
-footprint budget."""
+"""The request loop (asynchronous continuous batching over resident channels) on the GPU.
+
+Every request's own outputs (observation, wall shear, drag) and every channel's final state are
+bitwise those of the same requests served alone; calls on two lanes are in flight at the same
+time; a channel released while its call is in flight frees its memory once the call finishes,
+and a waiting channel is then admitted; an env held by an unfinished call refuses other calls
+(CHAN_EBUSY)."""
 import numpy as np
 import pytest
 
@@ -31,42 +35,123 @@ def action(spec, k):
     return to_device(gaussian_action(2000 + 17 * spec[-1] + k, spec[2], spec[0]))
 
 
-def test_served_results_equal_alone():
+def alone_outputs(cfg, seed, acts, nsubs):
+    """The requests of one channel served alone: per-request (obs, tau_w, drag) and final state."""
     import paper_2301_09889_amd.binding as b
+    e = b.ChanEnv(*grid_opts(cfg))
+    e.reset(seed)
+    outs = []
+    for a, n in zip(acts, nsubs):
+        obs, tau, drag = e.step(a, n)
+        outs.append((obs.cpu().numpy().copy(), tau.cpu().numpy().copy(), drag.item()))
+    state = e.get_state()
+    e.close()
+    return outs, state
+
+
+def check_requests(reqs_of, cfgs, seeds, server, final=True):
+    for c, reqs in reqs_of.items():
+        outs, state = alone_outputs(cfgs[c], seeds[c], [r.action for r in reqs], [r.n_substeps for r in reqs])
+        for k, (r, (obs, tau, drag)) in enumerate(zip(reqs, outs)):
+            assert r.code == 0, (c, k, r.code)
+            assert np.array_equal(r.obs.cpu().numpy(), obs), (c, k)
+            assert np.array_equal(r.tau_w.cpu().numpy(), tau), (c, k)
+            assert r.drag.item() == drag, (c, k)
+        if final and c in server.channels:
+            assert np.array_equal(server.channels[c].get_state(), state), c
+
+
+def test_served_results_equal_alone():
+    """An irregular stream (some channels queue several requests, substep counts differ) served
+    with non-blocking launches and polls: every request's outputs equal alone, bitwise."""
     from paper_2301_09889_amd.serve import ChannelServer
-    server = ChannelServer(hbm_budget=1 << 40)
-    for s in SPECS:
-        grid, opts = grid_opts(cfg_of(s))
-        assert server.admit(grid, opts, s[-1]) is not None
-    alone = []
-    for s in SPECS:
-        grid, opts = grid_opts(cfg_of(s))
-        e = b.ChanEnv(grid, opts)
-        e.reset(s[-1])
-        alone.append(e)
-    # an irregular stream: some channels queue several requests, substep counts differ
+    server = ChannelServer(hbm_budget=1 << 40, lanes=2)
+    cfgs = [cfg_of(s) for s in SPECS]
+    seeds = [s[-1] for s in SPECS]
+    for c, s in zip(cfgs, seeds):
+        assert server.admit(*grid_opts(c), s) is not None
     stream = [0, 1, 1, 2, 4, 3, 0, 3, 3, 1, 4, 2, 0]
     nsub = {0: 2, 1: 3, 2: 2, 3: 1, 4: 2}
     k_of = [0] * len(SPECS)
-    reqs = []
-    for c in stream:
-        reqs.append(server.submit(c, action(SPECS[c], k_of[c]), nsub[c]))
+    reqs_of = {c: [] for c in range(len(SPECS))}
+    for i, c in enumerate(stream):
+        reqs_of[c].append(server.submit(c, action(SPECS[c], k_of[c]), nsub[c]))
         k_of[c] += 1
-        if len(reqs) % 4 == 0:          # serve while requests keep arriving
-            server.step_once()
+        if i % 3 == 2:          # requests keep arriving while calls are in flight
+            server.launch()
+            server.poll()
     while server.has_pending():
-        server.step_once()
-    assert all(r.code == 0 for r in reqs)
-    for c, s in enumerate(SPECS):
-        for k in range(k_of[c]):
-            alone[c].step(action(s, k), nsub[c])
-        assert np.array_equal(alone[c].get_state(), server.channels[c].get_state()), c
-        assert np.array_equal(alone[c].obs.cpu().numpy(), server.channels[c].obs.cpu().numpy()), c
-        assert np.array_equal(alone[c].tau_w.cpu().numpy(), server.channels[c].tau_w.cpu().numpy()), c
-        assert alone[c].drag.item() == server.channels[c].drag.item(), c
+        server.launch()
+        server.poll()
+    check_requests(reqs_of, cfgs, seeds, server)
     server.close()
-    for e in alone:
-        e.close()
+
+
+def test_two_lanes_in_flight_together():
+    """Requests that arrive while a call is on the GPU are launched on the other lane at once:
+    two calls in flight together, disjoint channels, results equal alone."""
+    from paper_2301_09889_amd.serve import ChannelServer
+    server = ChannelServer(hbm_budget=1 << 40, lanes=2)
+    cfgs = [cfg_of(s) for s in SPECS]
+    seeds = [s[-1] for s in SPECS]
+    for c, s in zip(cfgs, seeds):
+        server.admit(*grid_opts(c), s)
+    reqs_of = {c: [] for c in range(len(SPECS))}
+    for c in (1, 4):                    # the two larger channels first
+        reqs_of[c].append(server.submit(c, action(SPECS[c], 0), 10))
+    server.launch()
+    for c in (0, 2, 3):                 # arrive while the first call is in flight
+        reqs_of[c].append(server.submit(c, action(SPECS[c], 0), 2))
+    server.launch()
+    lanes = sorted({reqs[0].lane for reqs in reqs_of.values()})
+    assert len(server.inflight) >= 2 and lanes == [0, 1]
+    while server.has_pending():
+        server.launch()
+        server.poll()
+    check_requests(reqs_of, cfgs, seeds, server)
+    server.close()
+
+
+def test_release_frees_memory_and_admits_waiting():
+    import paper_2301_09889_amd.binding as b
+    from paper_2301_09889_amd.serve import ChannelServer
+    big = cfg_of(SPECS[1])
+    need = b.chan_env_footprint_bytes(*grid_opts(big))
+    server = ChannelServer(hbm_budget=int(2.5 * need), lanes=2)
+    a = server.admit(*grid_opts(big), 1)
+    c = server.admit(*grid_opts(cfg_of(SPECS[4])), 4)
+    w = server.admit(*grid_opts(big), 7, wait=True)       # does not fit yet
+    assert (a, c) == (0, 1) and w == 2 and not server.is_admitted(w)
+    assert server.used == 2 * need
+    r0 = server.submit(a, action(SPECS[1], 0), 3)
+    server.launch()
+    server.release(a)                                      # while its call is in flight
+    assert server.is_admitted(a) and not server.is_admitted(w)
+    server.poll(block=True)
+    assert not server.is_admitted(a) and server.is_admitted(w) and server.used == 2 * need
+    reqs_of = {w: [server.submit(w, to_device(gaussian_action(50 + k, 32, 32)), 2) for k in range(2)]}
+    while server.has_pending():
+        server.launch()
+        server.poll()
+    outs, _ = alone_outputs(big, 1, [r0.action], [3])
+    assert r0.code == 0 and np.array_equal(r0.obs.cpu().numpy(), outs[0][0])
+    check_requests(reqs_of, {w: big}, {w: 7}, server)
+    server.close()
+
+
+def test_held_env_refuses_other_calls():
+    import paper_2301_09889_amd.binding as b
+    from paper_2301_09889_amd.serve import ChannelServer
+    server = ChannelServer(hbm_budget=1 << 40, lanes=1)
+    cid = server.admit(*grid_opts(cfg_of(SPECS[0])), 0)
+    server.submit(cid, None, 20)
+    server.launch()
+    with pytest.raises(b.ChanError) as err:
+        server.channels[cid].get_state()
+    assert err.value.code == b.CHAN_EBUSY
+    server.poll(block=True)
+    server.channels[cid].get_state()
+    server.close()
 
 
 def test_admission_by_footprint():
@@ -80,7 +165,7 @@ def test_admission_by_footprint():
     assert server.used == 2 * need and server.rejected_channels == 1
     small, sopts = grid_opts(cfg_of(SPECS[3]))
     assert b.chan_env_footprint_bytes(small, sopts) <= server.budget - server.used
-    assert server.admit(small, sopts, 9) == 2        # a smaller channel still fits
+    assert server.admit(small, sopts, 9) is not None       # a smaller channel still fits
     server.close()
 
 
@@ -88,8 +173,8 @@ def test_scale_mix_served_equals_alone():
     """The at-scale mix at full size: two 128x97x128 channels at Re_tau 395 (2 pi x 2 x pi h,
     general column kernel) and six minimal channels (16x65x16, Re_tau 180) in one request loop,
     Gaussian zero-net-flux actions, three requests of 10 time steps each, the large channels'
-    requests arriving late: every channel bitwise equal to the same requests served alone."""
-    import paper_2301_09889_amd.binding as b
+    requests arriving while the small ones are on the GPU: every request's outputs and every
+    channel's state bitwise equal to the same requests served alone."""
     from paper_2301_09889_amd.serve import ChannelServer
 
     big = ch.Config(nx=128, ny=97, nz=128, lx=2 * np.pi, lz=np.pi, re_tau=395.0, dt_plus=0.05,
@@ -103,29 +188,20 @@ def test_scale_mix_served_equals_alone():
         c = cfgs[i]
         return to_device(gaussian_action(7000 + 13 * i + k, c.nz, c.nx))
 
-    server = ChannelServer(hbm_budget=1 << 40)
+    server = ChannelServer(hbm_budget=1 << 40, lanes=2)
     for c, s in zip(cfgs, seeds):
         assert server.admit(*grid_opts(c), s) is not None
-    reqs = []
+    reqs_of = {i: [] for i in range(len(cfgs))}
     for k in range(3):
         for i in range(2, len(cfgs)):
-            reqs.append(server.submit(i, act(i, k), 10))
-        server.step_once()
+            reqs_of[i].append(server.submit(i, act(i, k), 10))
+        server.launch()
         for i in range(2):
-            reqs.append(server.submit(i, act(i, k), 10))
+            reqs_of[i].append(server.submit(i, act(i, k), 10))
+        server.launch()
+        server.poll()
     while server.has_pending():
-        server.step_once()
-    assert all(r.code == 0 for r in reqs)
-    for i, (c, s) in enumerate(zip(cfgs, seeds)):
-        e = b.ChanEnv(*grid_opts(c))
-        e.reset(s)
-        for k in range(3):
-            e.step(act(i, k), 10)
-        nd = int(np.count_nonzero(e.get_state() != server.channels[i].get_state()))
-        print(f"  channel {i} ({c.nx}x{c.ny}x{c.nz}): state entries differing {nd}", flush=True)
-        assert nd == 0, i
-        assert np.array_equal(e.obs.cpu().numpy(), server.channels[i].obs.cpu().numpy()), i
-        assert np.array_equal(e.tau_w.cpu().numpy(), server.channels[i].tau_w.cpu().numpy()), i
-        assert e.drag.item() == server.channels[i].drag.item(), i
-        e.close()
+        server.launch()
+        server.poll()
+    check_requests(reqs_of, cfgs, seeds, server)
     server.close()
