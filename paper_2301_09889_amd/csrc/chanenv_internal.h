@@ -38,7 +38,7 @@ struct TableLayout {
   size_t cosk, rc, optab, vt, minv, up, inv_int_up, twz, twx, twnx, twnz, alpha, beta;
   // parity-major copies for the column kernel with N <= 64 (one lane per coefficient:
   // even n = 2l in lanes l < 32, odd n = 2i + 1 in lanes 32 + i, n = N as a 65th "tail" entry)
-  size_t kfwd, kinv, rc_pm, intw_pm, op_pm, vt_pm, up_pm;
+  size_t kfwd, ccos, rc_pm, intw_pm, op_pm, vt_pm, up_pm;
   // open channel only: phi_+ of every pair and stage (parity-major for N <= 64, natural order
   // above) and 1/(dphi_+/dxi)(+1)
   size_t pt_pm, ptinv, pt;
@@ -94,7 +94,7 @@ struct DeviceState {
   int *status;                  // [1]
   // views into tab
   const double *cosk, *rc, *optab, *vt, *minv, *up, *inv_int_up, *alpha, *beta;
-  const double *kfwd, *kinv, *rc_pm, *intw_pm, *op_pm, *vt_pm, *up_pm, *pt_pm, *ptinv, *pt, *pk_pm, *pkinv, *pk;
+  const double *kfwd, *ccos, *rc_pm, *intw_pm, *op_pm, *vt_pm, *up_pm, *pt_pm, *ptinv, *pt, *pk_pm, *pkinv, *pk;
   cplx *pbuf;                   // [MAX_PLANES][nkx][nz] pressure spectra on the observation planes
   double *pscr;                 // [MAX_PLANES][3][nz][nx] u, v, w on the pressure planes
   const cplx *twz, *twx, *twnx, *twnz;
@@ -141,7 +141,7 @@ struct ColChan {
   gptr<cplx> F6;
   gptr<const cplx> vw_old, vw_new;
   gptr<cplx> vw_opp, tauw;
-  gptr<const double> kfwd, kinv, rc_pm, intw_pm, op_pm, vt_pm, up_pm, minv, inv_int_up, alpha, beta;
+  gptr<const double> kfwd, ccos, rc_pm, intw_pm, op_pm, vt_pm, up_pm, minv, inv_int_up, alpha, beta;
   gptr<const double> pt_pm, ptinv, pk_pm, pkinv;
   gptr<cplx> pbuf;
   gptr<double> drag_acc;

@@ -401,9 +401,8 @@ __device__ __forceinline__ void fmac_row(double (&acc)[G], const double (&q)[G],
 // parity-major coefficients a (this lane) and the tail a_N.
 // CHUNK: request the cosines of each group of 16 terms just before its FMA blocks instead of
 // all at once (fewer live registers; the same arithmetic in the same order).
-template <int N, int F, bool CHUNK, class Load>
-__device__ __forceinline__ void dct_fwd_pm(const Lane<N>& L, Load load, const double* __restrict__ kfwd, cplx* a,
-                                           cplx* at) {
+template <int N, int F, bool CHUNK, class Load, class Cos>
+__device__ __forceinline__ void dct_fwd_pm(const Lane<N>& L, Load load, Cos cosv, cplx* a, cplx* at) {
   constexpr int H = N / 2;
   constexpr int NQ = (H + 15) / 16;
   const int lane = L.l;
@@ -413,7 +412,7 @@ __device__ __forceinline__ void dct_fwd_pm(const Lane<N>& L, Load load, const do
   double cf[H + 1];
   if constexpr (!CHUNK) {
 #pragma unroll
-    for (int j = 0; j <= H; ++j) cf[j] = kfwd[j * 64 + lane];
+    for (int j = 0; j <= H; ++j) cf[j] = cosv(j);
   }
   double Q[NQ][2 * F];  // (re, im) of each field
   cplx gh[F];
@@ -450,12 +449,12 @@ __device__ __forceinline__ void dct_fwd_pm(const Lane<N>& L, Load load, const do
         if constexpr (CHUNK) {
 #pragma unroll
           for (int kk = 0; kk < 16; ++kk)
-            if (16 * m + kk < H) cf[16 * m + kk] = kfwd[(16 * m + kk) * 64 + lane];
+            if (16 * m + kk < H) cf[16 * m + kk] = cosv(16 * m + kk);
         }
         for_16([&](auto kk_c) { term(kk_c, m_c); });
       },
       std::make_integer_sequence<int, NQ>{});
-  if constexpr (CHUNK) cf[H] = kfwd[H * 64 + lane];
+  if constexpr (CHUNK) cf[H] = cosv(H);
   const double ch = cf[H];
   const double sc = (L.n == 0) ? (1.0 / N) : (2.0 / N);
 #pragma unroll
@@ -476,9 +475,9 @@ __device__ __forceinline__ void dct_fwd_pm(const Lane<N>& L, Load load, const do
 // f_j = sum_n a_n cos(pi n j / N), folded with P_n = a_n + a_{N-n}, M_n = a_n - a_{N-n}
 // (n < N/2; even nodes need P, odd nodes M) and a_{N/2} in both; the node-N tail is
 // sum_n (-1)^n a_n.
-template <int N, int F, bool CHUNK>
-__device__ __forceinline__ void dct_inv_pm(const Lane<N>& L, const cplx* a, const cplx* at,
-                                           const double* __restrict__ kinv, cplx* f, cplx* ft) {
+template <int N, int F, bool CHUNK, class Cos>
+__device__ __forceinline__ void dct_inv_pm(const Lane<N>& L, const cplx* a, const cplx* at, Cos cosv, cplx* f,
+                                           cplx* ft) {
   constexpr int H = N / 2;
   constexpr int NQ = (H + 15) / 16;
   constexpr int SH = (H & 1) ? 32 + (H >> 1) : (H >> 1);  // lane of a_{N/2}
@@ -486,7 +485,7 @@ __device__ __forceinline__ void dct_inv_pm(const Lane<N>& L, const cplx* a, cons
   double cf[H + 1];  // this lane's cosines, requested up front (or per group of 16, CHUNK)
   if constexpr (!CHUNK) {
 #pragma unroll
-    for (int n = 0; n <= H; ++n) cf[n] = kinv[n * 64 + lane];
+    for (int n = 0; n <= H; ++n) cf[n] = cosv(n);
   }
   double Q[NQ][2 * F];  // (re, im) of each field
   cplx ah[F];
@@ -522,12 +521,12 @@ __device__ __forceinline__ void dct_inv_pm(const Lane<N>& L, const cplx* a, cons
         if constexpr (CHUNK) {
 #pragma unroll
           for (int kk = 0; kk < 16; ++kk)
-            if (16 * m + kk < H) cf[16 * m + kk] = kinv[(16 * m + kk) * 64 + lane];
+            if (16 * m + kk < H) cf[16 * m + kk] = cosv(16 * m + kk);
         }
         for_16([&](auto kk_c) { term(kk_c, m_c); });
       },
       std::make_integer_sequence<int, NQ>{});
-  if constexpr (CHUNK) cf[H] = kinv[H * 64 + lane];
+  if constexpr (CHUNK) cf[H] = cosv(H);
   const double ch = cf[H];
 #pragma unroll
   for (int g = 0; g < F; ++g) {
@@ -553,21 +552,20 @@ constexpr int PART_SOLVE = 0, PART_RECON = 1, PART_BOTH = 2;
 // Time fraction at the end of RK stage r (c_end of the stage).
 __device__ __forceinline__ double stage_end(int r) { return r == 0 ? 8.0 / 15.0 : (r == 1 ? 2.0 / 3.0 : 1.0); }
 
-// One block of CW columns (block cb of the channel's columns).
-template <int N, int PART, bool CHUNK, int CW>
-__device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S, int cb) {
+// One column of a block: wave `wave` of the block takes column c = (p, q).  H at the nodes is
+// read from the block's LDS tile Hin ([g][column][node]), and the six reconstructed fields are
+// written into its tile Fout ([f][column][node]) for the block's coalesced store.  ctab: the
+// block's LDS copy of cos(pi k / N), k < 2N (LDS_COS); the DCTs' cosine cos(pi j n / N) of this
+// lane's index n is entry (j n) mod 2N of it, or entry j of the lane's column of the 64-lane table
+// in memory (the same double).
+template <int N, int PART, bool CHUNK, int CW, bool LDS_COS>
+__device__ __forceinline__ void column_body(const ColChan& A, const ColStage& S, int c, int p, int q, int wave,
+                                            int status0, const cplx* Hin, cplx* Fout, const double* ctab) {
   constexpr int NY = N + 1;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // wave-uniform column
-  const int c = __builtin_amdgcn_readfirstlane(cb * CW + wave);
-  if (c >= A.ncol) return;
-  // a rejected action skips the step: tested before the first store, loaded here so that
-  // its latency overlaps the loads below
-  const int status0 = *A.status;
+  const int lane = threadIdx.x & 63;
   const int nz = A.nz;
-  const int p = c / nz, q = c - p * nz;
-  if (q == nz / 2) return;            // Nyquist: never stored
-  if (p == 0 && q > nz / 2) return;   // written by its Hermitian partner (0, -q)
+  const int ln = Lane<N>(lane).n;
+  auto cosv = [&](int j) { return LDS_COS ? ctab[(j * ln) & (2 * N - 1)] : A.kfwd[j * 64 + lane]; };
   const bool mean = (c == 0);
   const int partner = (p == 0 && q > 0) ? (nz - q) : -1;
   const Lane<N> L(lane);
@@ -583,15 +581,13 @@ __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S
     const int r = S.stage;
     const double lam0 = A.lam0[r], ab = A.ab[r], gb = A.gb[r], zb = A.zb[r];
     // H1, H2, H3 at node j of this column; the mean flow sees the real parts of H1, H3 only
-    const cplx* h3 = A.H3 + (size_t)p * nz + q;
-    const size_t jstride = (size_t)A.nkx * nz;
     auto loadH = [&](int g, int j) {
-      cplx x = h3[g * A.plane + (size_t)j * jstride];
+      cplx x = Hin[(g * CW + wave) * NY + j];
       if (mean && g != 1) x.y = 0.0;
       return x;
     };
     cplx hc[3], hct[3];
-    dct_fwd_pm<N, 3, false>(L, loadH, A.kfwd, hc, hct);
+    dct_fwd_pm<N, 3, true>(L, loadH, cosv, hc, hct);
     if (status0 & STATUS_BAD_ACTION) return;
     // state (v, omega_y; mean: X = U + i W) and the previous stage's explicit terms
     // (h_v, h_g; mean: h_u + i h_w)
@@ -849,14 +845,9 @@ __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S
     tau_hat = make_double2(A.nu_wall * slope, 0.0);
   }
   cplx ph[6], pht[6];
-  dct_inv_pm<N, 6, CHUNK>(L, fld, fldt, A.kinv, ph, pht);
+  dct_inv_pm<N, 6, CHUNK>(L, fld, fldt, cosv, ph, pht);
   if (status0 & STATUS_BAD_ACTION) return;
-  // write the six fields at the nodes (this lane: node n; lane 0 also node N) and the
-  // Hermitian partner column
-  const size_t o = ((size_t)nl * A.nkx + p) * nz + q;
-  const size_t ot = ((size_t)N * A.nkx + p) * nz + q;
-  const size_t o2 = ((size_t)nl * A.nkx + p) * nz + (partner >= 0 ? partner : 0);
-  const size_t ot2 = ((size_t)N * A.nkx + p) * nz + (partner >= 0 ? partner : 0);
+  // the six fields at the nodes (this lane: node n; lane 0 also node N) into the block's tile
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
     cplx val = ph[f], valt = pht[f];
@@ -864,14 +855,9 @@ __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S
       val.y = 0.0;
       valt.y = 0.0;
     }
-    if (L.ok) {
-      A.F6[(size_t)f * A.plane + o] = val;
-      if (partner >= 0) A.F6[(size_t)f * A.plane + o2] = cconj(val);
-    }
-    if (lane == 0) {
-      A.F6[(size_t)f * A.plane + ot] = valt;
-      if (partner >= 0) A.F6[(size_t)f * A.plane + ot2] = cconj(valt);
-    }
+    cplx* dst = Fout + (f * CW + wave) * NY;
+    if (L.ok) dst[nl] = val;
+    if (lane == 0) dst[N] = valt;
   }
   if (want_end) {
     // opposition target from v at the sensing node (js < N), Hermitian partner too
@@ -887,6 +873,61 @@ __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S
   }
 }
 
+// One block of CW columns (block cb of the channel's columns): one p, CW consecutive q (CW
+// divides N_z), one wavefront per column.  H of the block's columns is loaded into LDS and the
+// reconstructed fields stored from LDS by the whole block with q fastest, so that a load or
+// store instruction covers CW consecutive q of 64 / CW nodes instead of 64 nodes of one column
+// (every node of a column lies in its own cache line of the node-major planes).  Every wave
+// reaches the block's barriers: a Nyquist or partner-written column, or a rejected action,
+// only skips its work and its stores.
+template <int N, int PART, bool CHUNK, int CW, bool LDS_COS>
+__device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S, int cb, cplx* tile) {
+  constexpr int NY = N + 1;
+  const int wave = threadIdx.x >> 6;
+  const int nz = A.nz;
+  const int c0 = cb * CW;
+  if (c0 >= A.ncol) return;  // whole block (N_x/2 N_z is a multiple of CW)
+  const int p = c0 / nz, q0 = c0 - p * nz;
+  const size_t jstride = (size_t)A.nkx * nz;
+  // a rejected action skips the step: tested before every store
+  const int status0 = *A.status;
+  cplx* Hin = tile;                 // [g][column][node]
+  cplx* Fout = tile + 3 * CW * NY;  // [f][column][node]
+  double* ctab = reinterpret_cast<double*>(tile + 9 * CW * NY);  // cos(pi k / N), k < 2N
+  if constexpr (LDS_COS)
+    for (int t = threadIdx.x; t < 2 * N; t += 64 * CW) ctab[t] = A.ccos[t];
+  if constexpr (PART != PART_RECON) {
+    const cplx* src = A.H3 + (size_t)p * nz + q0;
+#pragma unroll 1
+    for (int t = threadIdx.x; t < 3 * NY * CW; t += 64 * CW) {
+      const int qq = t % CW, gj = t / CW;
+      const int g = gj / NY, j = gj - g * NY;
+      Hin[(g * CW + qq) * NY + j] = src[g * A.plane + (size_t)j * jstride + qq];
+    }
+  }
+  __syncthreads();
+  const int q = q0 + wave;
+  const int c = __builtin_amdgcn_readfirstlane(c0 + wave);
+  // Nyquist columns are never stored; (0, q > N_z/2) is written by its Hermitian partner (0, -q)
+  if (q != nz / 2 && !(p == 0 && q > nz / 2))
+    column_body<N, PART, CHUNK, CW, LDS_COS>(A, S, c, p, q, wave, status0, Hin, Fout, ctab);
+  if constexpr (PART == PART_SOLVE) return;
+  __syncthreads();
+  if (status0 & STATUS_BAD_ACTION) return;
+  cplx* dst = A.F6 + (size_t)p * nz + q0;
+#pragma unroll 1
+  for (int t = threadIdx.x; t < 6 * NY * CW; t += 64 * CW) {
+    const int qq = t % CW, fj = t / CW;
+    const int f = fj / NY, j = fj - f * NY;
+    const int qc = q0 + qq;
+    if (qc == nz / 2 || (p == 0 && qc > nz / 2)) continue;
+    const cplx val = Fout[(f * CW + qq) * NY + j];
+    const size_t o = f * A.plane + (size_t)j * jstride;
+    dst[o + qq] = val;
+    if (p == 0 && qc > 0) A.F6[o + (nz - qc)] = cconj(val);  // Hermitian partner (0, -q)
+  }
+}
+
 // Many channels: channel blockIdx.x / bpc of the device array.  With many columns resident,
 // occupancy hides load latency: the reconstruction requests its cosines per group of 16
 // terms, which keeps the reconstruction and the fused launch within three waves per SIMD
@@ -897,9 +938,10 @@ __global__ __launch_bounds__(64 * CWAVES, 3) void k_column_pm(const ColChan* __r
   // contiguous block ranges per XCD: 23.8 -> 20.6 ms of column launches per env step of the
   // 256-channel batch (the one-channel launch below, all blocks resident at once, is 2 % slower
   // with the same mapping)
+  __shared__ double tile[9 * CWAVES * (N + 1) * 2 + 2 * N];
   const int b = xcd_block(blockIdx.x, gridDim.x);
   const int ch = b / bpc;
-  column_block<N, PART, PART != PART_SOLVE, CWAVES>(chans[ch], S, b - ch * bpc);
+  column_block<N, PART, PART != PART_SOLVE, CWAVES, false>(chans[ch], S, b - ch * bpc, reinterpret_cast<cplx*>(tile));
 }
 
 // One channel, its arguments by value (preloaded with the kernel arguments instead of read
@@ -909,7 +951,8 @@ __global__ __launch_bounds__(64 * CWAVES, 3) void k_column_pm(const ColChan* __r
 // channel, 1984 columns, 8 % slower with one per block).
 template <int N, int PART, int CW>
 __global__ __launch_bounds__(64 * CW, 2) void k_column_pm1(ColChan A, ColStage S) {
-  column_block<N, PART, false, CW>(A, S, blockIdx.x);
+  __shared__ double tile[9 * CW * (N + 1) * 2 + 2 * N];
+  column_block<N, PART, false, CW, true>(A, S, blockIdx.x, reinterpret_cast<cplx*>(tile));
 }
 
 // Columns per block of the single-channel launch for ncol columns.
@@ -999,7 +1042,7 @@ __device__ __forceinline__ void pressure_block(const ColChan& A, const ColStage&
   const size_t jstride = (size_t)A.nkx * nz;
   auto loadH = [&](int g, int j) { return h3[g * A.plane + (size_t)j * jstride]; };
   cplx hc[3], hct[3];
-  dct_fwd_pm<N, 3, false>(L, loadH, A.kfwd, hc, hct);
+  dct_fwd_pm<N, 3, false>(L, loadH, [&](int j) { return A.kfwd[j * 64 + lane]; }, hc, hct);
   const int nl = (L.ok ? L.n : 0);
   const size_t col = (size_t)c * NY;
   const cplx v = L.ok ? A.vS[col + nl] : cz();

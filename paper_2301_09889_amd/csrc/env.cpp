@@ -219,7 +219,7 @@ size_t table_doubles(const Dims& d, bool open) {
              r2((size_t)d.ncol * 3 * NY) + r2((size_t)d.ncol * 12) + r2((size_t)3 * NY) + r2(4) + r2(2 * d.mz) +
              r2(2 * d.mx) + r2(2 * d.nx) + r2(2 * d.nz) + r2(d.nkx) + r2(d.nz);
   if (pm)
-    t += 2 * r2((size_t)(H + 1) * 64) + r2((size_t)3 * PM_ENTRIES) + r2(PM_ENTRIES) +
+    t += r2((size_t)(H + 1) * 64) + r2((size_t)2 * d.N) + r2((size_t)3 * PM_ENTRIES) + r2(PM_ENTRIES) +
          r2((size_t)d.ncol * NOPS * PM_OPSZ) + r2((size_t)d.ncol * 3 * PM_ENTRIES) + r2((size_t)3 * PM_ENTRIES);
   if (open) t += r2((size_t)d.ncol * 3) + r2((size_t)d.ncol * 3 * NY) + (pm ? r2((size_t)d.ncol * 3 * PM_ENTRIES) : 0);
   t += r2((size_t)d.ncol * 4) + r2((size_t)d.ncol * NY) + (pm ? r2((size_t)d.ncol * PM_ENTRIES) : 0);
@@ -269,7 +269,7 @@ void carve_state(const Dims& d, const Sizes& z, const TableLayout& L, char* base
   s.twnx = (const cplx*)(s.tab + L.twnx);
   s.twnz = (const cplx*)(s.tab + L.twnz);
   s.kfwd = s.tab + L.kfwd;
-  s.kinv = s.tab + L.kinv;
+  s.ccos = s.tab + L.ccos;
   s.rc_pm = s.tab + L.rc_pm;
   s.intw_pm = s.tab + L.intw_pm;
   s.op_pm = s.tab + L.op_pm;
@@ -411,7 +411,7 @@ ColChan make_col_chan(const chan_env* e) {
   c.vw_opp = (decltype(c.vw_opp))(s.vw_opp);
   c.tauw = (decltype(c.tauw))(s.tauw);
   c.kfwd = (decltype(c.kfwd))(s.kfwd);
-  c.kinv = (decltype(c.kinv))(s.kinv);
+  c.ccos = (decltype(c.ccos))(s.ccos);
   c.rc_pm = (decltype(c.rc_pm))(s.rc_pm);
   c.intw_pm = (decltype(c.intw_pm))(s.intw_pm);
   c.op_pm = (decltype(c.op_pm))(s.op_pm);

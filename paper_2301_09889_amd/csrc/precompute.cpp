@@ -127,8 +127,10 @@ static void fill_parity_major(const Dims& d, std::vector<double>& T, const Table
     for (int l = 0; l < 64; ++l) {
       const int n = lane_n(l);
       T[L.kfwd + (size_t)jj * 64 + l] = lane_ok(l) ? (double)cosl(PI * (long double)((jj * n) % (2 * N)) / N) : 0.0;
-      T[L.kinv + (size_t)jj * 64 + l] = lane_ok(l) ? (double)cosl(PI * (long double)((jj * n) % (2 * N)) / N) : 0.0;
     }
+  // the distinct entries of that table: cos(pi k / N), k < 2N (the same expression, so a lookup
+  // at k = (jj n) mod 2N gives the same double)
+  for (int k = 0; k < 2 * N; ++k) T[L.ccos + k] = (double)cosl(PI * (long double)k / N);
   for (int n = 0; n <= N; ++n) {
     const int sl = pm_slot(N, n);
     for (int k = 0; k < 3; ++k) T[L.rc_pm + (size_t)k * PM_ENTRIES + sl] = T[L.rc + (size_t)k * NY + n];
@@ -179,7 +181,7 @@ void precompute_tables(const Dims& d, const PhysParams& ph, HostTables* out) {
   L.beta = take(d.nz);
   const bool pm = d.N <= 64;
   L.kfwd = take(pm ? (size_t)(H + 1) * 64 : 0);
-  L.kinv = take(pm ? (size_t)(H + 1) * 64 : 0);
+  L.ccos = take(pm ? (size_t)2 * N : 0);
   L.rc_pm = take(pm ? (size_t)3 * PM_ENTRIES : 0);
   L.intw_pm = take(pm ? (size_t)PM_ENTRIES : 0);
   L.op_pm = take(pm ? (size_t)d.ncol * NOPS * PM_OPSZ : 0);
