@@ -568,6 +568,8 @@ __device__ __forceinline__ void column_body(const ColChan& A, const ColStage& S,
   auto cosv = [&](int j) { return LDS_COS ? ctab[(j * ln) & (2 * N - 1)] : A.kfwd[j * 64 + lane]; };
   const bool mean = (c == 0);
   const int partner = (p == 0 && q > 0) ? (nz - q) : -1;
+  // the per-column operator tables depend on k^2 only: (p, q) and (p, N_z - q) share them
+  const int crec = p * nz + (q > nz / 2 ? nz - q : q);
   const Lane<N> L(lane);
   const double al = A.alpha[p], be = A.beta[q];
   const double k2 = al * al + be * be;
@@ -615,13 +617,13 @@ __device__ __forceinline__ void column_body(const ColChan& A, const ColStage& S,
       }
     }
     const RowCoef rcf = load_rc<N>(L, A.rc_pm);
-    const TauRec rs = load_rec<N>(L, A.op_pm + ((size_t)c * NOPS + r) * PM_OPSZ);
+    const TauRec rs = load_rec<N>(L, A.op_pm + ((size_t)crec * NOPS + r) * PM_OPSZ);
     TauRec rv = rs;
     cplx vw = cz();
     double mi0 = 0.0, mi1 = 0.0, mi2 = 0.0, mi3 = 0.0, tv = 0.0, tvt = 0.0;
     double iw = 0.0, iwt = 0.0, upl = 0.0, upt = 0.0, iiu = 0.0;
     if (!mean) {
-      rv = load_rec<N>(L, A.op_pm + ((size_t)c * NOPS + 3) * PM_OPSZ);
+      rv = load_rec<N>(L, A.op_pm + ((size_t)crec * NOPS + 3) * PM_OPSZ);
       if (!A.ext) {
         vw = A.vw_opp[c];
       } else {  // wall velocity ramped from the old to the new action (or the new one held)
@@ -629,12 +631,12 @@ __device__ __forceinline__ void column_body(const ColChan& A, const ColStage& S,
         const cplx o = A.vw_old[c], nn = A.vw_new[c];
         vw = caxpy(o, s_ramp, csub(nn, o));
       }
-      const double* mi = A.minv + ((size_t)c * 3 + r) * 4;
+      const double* mi = A.minv + ((size_t)crec * 3 + r) * 4;
       mi0 = mi[0];
       mi1 = mi[1];
       mi2 = mi[2];
       mi3 = mi[3];
-      const double* vtab = A.vt_pm + ((size_t)c * 3 + r) * PM_ENTRIES;
+      const double* vtab = A.vt_pm + ((size_t)crec * 3 + r) * PM_ENTRIES;
       tv = vtab[lane];
       tvt = vtab[64];
     } else {
@@ -704,10 +706,10 @@ __device__ __forceinline__ void column_body(const ColChan& A, const ColStage& S,
       om = X[1];
       omt = Xt[1];
       if (A.open) {  // d omega_y/dxi (+1) = 0: add c phi_+
-        const double* ptab = A.pt_pm + ((size_t)c * 3 + r) * PM_ENTRIES;
+        const double* ptab = A.pt_pm + ((size_t)crec * 3 + r) * PM_ENTRIES;
         const double pl = ptab[lane], plt = ptab[64];
         const cplx dw = coef_sum<N>(L, om, omt, n2, N2);
-        const double pinv = A.ptinv[(size_t)c * 3 + r];
+        const double pinv = A.ptinv[(size_t)crec * 3 + r];
         const cplx cw = make_double2(-dw.x * pinv, -dw.y * pinv);
         om = caxpy(om, pl, cw);
         omt = caxpy(omt, plt, cw);
@@ -1055,7 +1057,8 @@ __device__ __forceinline__ void pressure_block(const ColChan& A, const ColStage&
   const cplx f = cscale(cadd(dH2, ab), A.ysi);
   const cplx ft = cscale(abt, A.ysi);
   const RowCoef rcf = load_rc<N>(L, A.rc_pm);
-  const TauRec rk = load_rec<N>(L, A.op_pm + ((size_t)c * NOPS + 3) * PM_OPSZ);
+  const int crec = p * nz + (q > nz / 2 ? nz - q : q);  // tables shared by (p, +-q)
+  const TauRec rk = load_rec<N>(L, A.op_pm + ((size_t)crec * NOPS + 3) * PM_OPSZ);
   cplx R[1], Rt[1];
   R[0] = tau_rows_pm<N>(L, f, ft, rcf, 0.0, cz(), cz(), Rt[0]);
   const cplx z1[1] = {cz()};
@@ -1081,10 +1084,10 @@ __device__ __forceinline__ void pressure_block(const ColChan& A, const ColStage&
   const cplx dP_top = coef_sum<N>(L, P[0], Pt[0], n2, N2);
   const cplx dP_bot = coef_sum<N>(L, P[0], Pt[0], -L.sgn() * n2, -N2);
   const cplx r_top = csub(g_top, dP_top), r_bot = csub(g_bot, dP_bot);
-  const double* mi = A.pkinv + (size_t)c * 4;
+  const double* mi = A.pkinv + (size_t)crec * 4;
   const cplx c0 = make_double2(mi[0] * r_top.x + mi[1] * r_bot.x, mi[0] * r_top.y + mi[1] * r_bot.y);
   const cplx c1 = make_double2(mi[2] * r_top.x + mi[3] * r_bot.x, mi[2] * r_top.y + mi[3] * r_bot.y);
-  const double* ptab = A.pk_pm + (size_t)c * PM_ENTRIES;
+  const double* ptab = A.pk_pm + (size_t)crec * PM_ENTRIES;
   const double pl = ptab[lane], plt = ptab[64];
   cplx Pc = caxpy(caxpy(P[0], pl, c0), L.sgn() * pl, c1);
   const cplx Pct = caxpy(caxpy(Pt[0], plt, c0), plt, c1);

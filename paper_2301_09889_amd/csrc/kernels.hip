@@ -442,6 +442,8 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
   if (p == 0 && q > nz / 2) return;   // written by its Hermitian partner (0, -q)
   const bool mean = (c == 0);
   const int partner = (p == 0 && q > 0) ? (nz - q) : -1;
+  // the per-column operator tables depend on k^2 only: (p, q) and (p, N_z - q) share them
+  const int crec = p * nz + (q > nz / 2 ? nz - q : q);
 
   double* wb = smem + (size_t)wave * P::WAVE_DOUBLES;
   cplx* B[P::NB];
@@ -571,7 +573,7 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
       }
       // operator record of D^2 - lam for this column and stage -> LDS
       {
-        const double* src = A.optab + ((size_t)c * NOPS + r) * 2 * P::OPSZ;
+        const double* src = A.optab + ((size_t)crec * NOPS + r) * 2 * P::OPSZ;
         for (int t = lane; t < 2 * P::OPSZ; t += 64) TAB[t] = src[t];
       }
       wave_sync();
@@ -623,7 +625,7 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
         vw = caxpy(o, A.s_ramp, csub(nn, o));
       }
       {
-        const double* src = A.optab + ((size_t)c * NOPS + 3) * 2 * P::OPSZ;
+        const double* src = A.optab + ((size_t)crec * NOPS + 3) * 2 * P::OPSZ;
         for (int t = lane; t < 2 * P::OPSZ; t += 64) TAB[t] = src[t];
       }
       for (int e = lane; e <= N; e += 64) B[2][e] = tau_rows<N>(B[6], A.rc, e);
@@ -662,18 +664,18 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
       }
       dtop = wave_sum(dtop);
       dbot = wave_sum(dbot);
-      const double* mi = A.minv + ((size_t)c * 3 + r) * 4;
+      const double* mi = A.minv + ((size_t)crec * 3 + r) * 4;
       const cplx c0 = make_double2(-(mi[0] * dtop.x + mi[1] * dbot.x), -(mi[0] * dtop.y + mi[1] * dbot.y));
       const cplx c1 = make_double2(-(mi[2] * dtop.x + mi[3] * dbot.x), -(mi[2] * dtop.y + mi[3] * dbot.y));
-      const double* vt = A.vt + ((size_t)c * 3 + r) * NY;
+      const double* vt = A.vt + ((size_t)crec * 3 + r) * NY;
       // free-slip top: omega_y += c phi_+ with c = -(domega/dxi)(+1) / (dphi_+/dxi)(+1)
       cplx cw = cz();
-      const double* ptc = A.open ? A.pt + ((size_t)c * 3 + r) * NY : nullptr;
+      const double* ptc = A.open ? A.pt + ((size_t)crec * 3 + r) * NY : nullptr;
       if (A.open) {
         cplx dw = cz();
         for (int e = lane; e <= N; e += 64) dw = caxpy(dw, (double)e * (double)e, B[7][e]);
         dw = wave_sum(dw);
-        const double pinv = A.ptinv[(size_t)c * 3 + r];
+        const double pinv = A.ptinv[(size_t)crec * 3 + r];
         cw = make_double2(-dw.x * pinv, -dw.y * pinv);
       }
       bool ok = true;
@@ -714,7 +716,7 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
       }
       for (int e = lane; e <= N; e += 64) B[4][e] = make_double2(A.meanS[e], A.meanS[NY + e]);
       {
-        const double* src = A.optab + ((size_t)c * NOPS + r) * 2 * P::OPSZ;
+        const double* src = A.optab + ((size_t)crec * NOPS + r) * 2 * P::OPSZ;
         for (int t = lane; t < 2 * P::OPSZ; t += 64) TAB[t] = src[t];
       }
       wave_sync();
@@ -976,6 +978,7 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_pressure_gen(PressGenArgs A) 
   if (q == nz / 2) return;
   if (p == 0 && q > nz / 2) return;
   const int partner = (p == 0 && q > 0) ? (nz - q) : -1;
+  const int crec = p * nz + (q > nz / 2 ? nz - q : q);  // tables shared by (p, +-q)
   const size_t pstride = (size_t)A.nkx * nz;
   if (c == 0) {
     if (lane < A.n_pplanes) A.pbuf[(size_t)lane * pstride] = cz();
@@ -1024,7 +1027,7 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_pressure_gen(PressGenArgs A) 
     }
   }
   {
-    const double* src = A.optab + ((size_t)c * NOPS + 3) * 2 * P::OPSZ;
+    const double* src = A.optab + ((size_t)crec * NOPS + 3) * 2 * P::OPSZ;
     for (int t = lane; t < 2 * P::OPSZ; t += 64) TAB[t] = src[t];
   }
   wave_sync();
@@ -1073,10 +1076,10 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_pressure_gen(PressGenArgs A) 
   const cplx g_top = cscale(caxpy(H2_top, A.nu_xi, caxpy(d2vt, -k2s, vt0)), A.ysi);
   const cplx g_bot = cscale(csub(caxpy(H2_bot, A.nu_xi, caxpy(d2vb, -k2s, vb0)), rate), A.ysi);
   const cplx r_top = csub(g_top, dPt), r_bot = csub(g_bot, dPb);
-  const double* mi = A.pkinv + (size_t)c * 4;
+  const double* mi = A.pkinv + (size_t)crec * 4;
   const cplx c0 = make_double2(mi[0] * r_top.x + mi[1] * r_bot.x, mi[0] * r_top.y + mi[1] * r_bot.y);
   const cplx c1 = make_double2(mi[2] * r_top.x + mi[3] * r_bot.x, mi[2] * r_top.y + mi[3] * r_bot.y);
-  const double* pk = A.pk + (size_t)c * NY;
+  const double* pk = A.pk + (size_t)crec * NY;
   for (int k = 0; k < A.n_pplanes; ++k) {
     const int j = A.pjs[k];
     const bool flip = j > H;

@@ -231,10 +231,11 @@ void precompute_tables(const Dims& d, const PhysParams& ph, HostTables* out) {
   };
 
   std::vector<double> phi(NY), v(NY), zero(NY, 0.0);
+  // Columns (p, q) and (p, N_z - q) have the same k^2 and so the same tables: only q < N_z/2
+  // is filled, and the kernels read the tables of (p, N_z - q) for q > N_z/2.
   for (int c = 0; c < d.ncol; ++c) {
     const int p = c / d.nz, q = c % d.nz;
-    if (q == d.nz / 2) continue;
-    if (p == 0 && q > d.nz / 2) continue;
+    if (q >= d.nz / 2) continue;
     const double k2 = (alpha[p] * alpha[p] + beta[q] * beta[q]) * iys2;
     double* base = &T[L.optab + (size_t)c * NOPS * 2 * d.opsz];
     for (int r = 0; r < 3; ++r) fill_record(d, k2 + lam0[r], base + (size_t)r * 2 * d.opsz);
