@@ -954,7 +954,8 @@ __global__ __launch_bounds__(64 * CWAVES, 3) void k_column_pm(const ColChan* __r
 template <int N, int PART, int CW>
 __global__ __launch_bounds__(64 * CW, 2) void k_column_pm1(ColChan A, ColStage S) {
   __shared__ double tile[9 * CW * (N + 1) * 2 + 2 * N];
-  column_block<N, PART, false, CW, true>(A, S, blockIdx.x, reinterpret_cast<cplx*>(tile));
+  // contiguous block ranges per XCD: neighbouring blocks share the cache lines of their tiles
+  column_block<N, PART, false, CW, true>(A, S, xcd_block(blockIdx.x, gridDim.x), reinterpret_cast<cplx*>(tile));
 }
 
 // Columns per block of the single-channel launch for ncol columns.
