@@ -187,7 +187,10 @@ int chan_env_query(const struct chan_env* env, chan_info_t* out);
  * 0 if the grid is invalid. */
 size_t chan_env_footprint_bytes(const chan_grid_t* grid, const chan_opts_t* opts);
 
-/* Free the env and its device memory.  NULL is a no-op. */
+/* Free the env and its device memory.  NULL is a no-op.  An env held by an unfinished call
+ * (chan_batch_launch) is first waited for and detached from the call, which then reports
+ * CHAN_EINVAL for it when finished; the env leaves every batch that lists it (later positions
+ * shift down by one). */
 void chan_env_destroy(struct chan_env* env);
 
 /* Kernel timing (instrumentation for benchmarks).  chan_env_set_timing(env, 1)
@@ -273,7 +276,8 @@ int chan_batch_timing_read(struct chan_batch* batch, int32_t nclass, int64_t* la
  * chan_call_finish waits for the call, applies each env's outcome (clock, step counter, a
  * poisoned state), writes the per-env codes to results (if non-NULL; as for chan_batch_step)
  * and frees the call; returns CHAN_OK if every env succeeded, else the first failing env's
- * code.  Every launched call must be finished, before the batch is destroyed.
+ * code.  chan_batch_destroy finishes the batch's unfinished calls itself (each env's outcome
+ * applied as by chan_call_finish) and frees them: their handles are invalid afterwards.
  *
  * chan_batch_add: env joins the batch (its grid shape's plane-pass tiling is tuned on it if the
  * shape is new to the batch; later channels of the shape reuse it).  chan_batch_remove: env

@@ -6,6 +6,7 @@ was created with; PyTorch serves only as the allocator of device memory and the
 owner of the stream.
 """
 import ctypes
+import weakref
 import os
 
 import numpy as np
@@ -393,7 +394,11 @@ class ChanEnv:
         return chan_env_query(self.handle)
 
     def close(self):
+        """Destroy the env: the library waits for a call that holds it and removes it from every
+        batch; the Python batches that list it drop it too."""
         if self.handle:
+            for b in list(getattr(self, "_batches", ())):
+                b._drop(self)
             chan_env_destroy(self.handle)
             self.handle = None
 
@@ -412,6 +417,15 @@ class ChanBatch:
         self.envs = list(envs)
         self.handle = chan_batch_create([e.handle for e in self.envs])
         self.results = (ctypes.c_int32 * len(self.envs))()
+        self._calls = weakref.WeakSet()
+        for e in self.envs:
+            _member_of(e).add(self)
+
+    def _drop(self, env):
+        """env is being destroyed (the library removes it from the batch itself)."""
+        if env in self.envs:
+            self.envs.remove(env)
+            self.results = (ctypes.c_int32 * max(1, len(self.envs)))()
 
     def step(self, actions, n_substeps):
         """actions: list of float64 device tensors (nz, nx) or None per env (or None for all).
@@ -458,13 +472,16 @@ class ChanBatch:
                                      ptrs(obs), ptrs(tau_w), ptrs(drag))
         if rc != CHAN_OK:
             raise ChanError(rc, "chan_batch_launch")
-        return ChanCall(call, len(envs), keep=(actions, obs, tau_w, drag))
+        c = ChanCall(call, len(envs), keep=(actions, obs, tau_w, drag))
+        self._calls.add(c)
+        return c
 
     def add(self, env):
         rc = chan_batch_add(self.handle, env.handle)
         if rc != CHAN_OK:
             raise ChanError(rc, "chan_batch_add")
         self.envs.append(env)
+        _member_of(env).add(self)
         self.results = (ctypes.c_int32 * len(self.envs))()
 
     def remove(self, env):
@@ -472,10 +489,17 @@ class ChanBatch:
         if rc != CHAN_OK:
             raise ChanError(rc, "chan_batch_remove")
         self.envs.remove(env)
+        _member_of(env).discard(self)
         self.results = (ctypes.c_int32 * max(1, len(self.envs)))()
 
     def close(self):
+        """Destroy the batch: the library finishes its unfinished calls itself (the envs'
+        outcomes applied; finish() then reports CHAN_EINVAL for every env of such a call)."""
         if self.handle:
+            for c in list(self._calls):
+                c._abandon()
+            for e in self.envs:
+                _member_of(e).discard(self)
             chan_batch_destroy(self.handle)
             self.handle = None
 
@@ -484,6 +508,12 @@ class ChanBatch:
             self.close()
         except Exception:
             pass
+
+
+def _member_of(env):
+    if not hasattr(env, "_batches"):
+        env._batches = weakref.WeakSet()
+    return env._batches
 
 
 class ChanCall:
@@ -503,6 +533,13 @@ class ChanCall:
         if rc < 0:
             raise ChanError(rc, "chan_call_query")
         return rc == 0
+
+    def _abandon(self):
+        """Its batch is being destroyed (the library finishes the call and frees it)."""
+        if self.codes is None:
+            self.handle = None
+            self.codes = [CHAN_EINVAL] * self.n
+            self.keep = None
 
     def finish(self):
         """Wait for the call, apply its outcome to the envs and return the per-env codes."""

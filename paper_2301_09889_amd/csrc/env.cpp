@@ -65,6 +65,7 @@ struct chan_batch {
   hipStream_t stream = nullptr;   // the synchronous calls' stream: the first member's
   int device = 0;
   std::vector<CallSlot*> slots;
+  std::vector<chan_call*> calls;  // launched and not yet finished
   KernelTimer timer;
   double timing_ms[KC_COUNT];
   int64_t timing_launches[KC_COUNT];
@@ -94,7 +95,8 @@ struct chan_env {
   chan_batch* self;     // batch of one for chan_env_step
   ColChan col;          // the column kernels' arguments (fixed for the env's life)
   PlaneChan plane;      // the plane kernels' arguments
-  const chan_call* in_flight;  // the unfinished asynchronous call holding this env, if any
+  chan_call* in_flight;  // the unfinished asynchronous call holding this env, if any
+  std::vector<chan_batch*> member_of;  // the caller's batches that list this env
 };
 
 namespace {
@@ -462,8 +464,18 @@ void free_slot(CallSlot* sl) {
   delete sl;
 }
 
+template <class T>
+void erase_value(std::vector<T>& v, const T& x) {
+  v.erase(std::remove(v.begin(), v.end(), x), v.end());
+}
+
+int batch_finish(chan_call* c, int32_t* results);
+
 void batch_free(chan_batch* b) {
   if (!b) return;
+  // calls never finished: finish them (wait, apply each env's outcome, release, free)
+  for (chan_call* c : std::vector<chan_call*>(b->calls)) (void)batch_finish(c, nullptr);
+  for (chan_env* e : b->envs) erase_value(e->member_of, b);
   if (b->stream) (void)hipStreamSynchronize(b->stream);
   for (CallSlot* sl : b->slots) free_slot(sl);
   for (hipEvent_t ev : b->timer.pool) (void)hipEventDestroy(ev);
@@ -634,10 +646,11 @@ int stage_call(chan_call* c, StepFn step) {
 
 void release_call(chan_call* c) {
   for (chan_env* e : c->envs)
-    if (e->in_flight == c) e->in_flight = nullptr;
+    if (e && e->in_flight == c) e->in_flight = nullptr;
   if (c->slot) c->slot->busy = false;
   c->slot = nullptr;
 }
+
 
 // Column pass of one group after the plane pass of stage S.stage (or, S.stage = -1, the
 // reconstruction alone).
@@ -910,6 +923,7 @@ int batch_launch(chan_batch* b, hipStream_t st, int32_t na, chan_env* const* env
     return rc;
   }
   for (chan_env* e : c->envs) e->in_flight = c;
+  b->calls.push_back(c);
   *out = c;
   return CHAN_OK;
 }
@@ -928,7 +942,10 @@ int batch_finish(chan_call* c, int32_t* results) {
     for (size_t k = 0; k < c->envs.size(); ++k) {
       chan_env* e = c->envs[k];
       int ri = CHAN_OK;
-      if (hs[k].skip) {
+      if (!e) {  // destroyed while the call was in flight
+        ri = CHAN_EINVAL;
+        if (rc == CHAN_OK) fail(CHAN_EINVAL, "env destroyed before its call was finished");
+      } else if (hs[k].skip) {
         ri = CHAN_ESTATE;
         if (rc == CHAN_OK) fail(CHAN_ESTATE, "env without a valid flow state (skipped)");
       } else if (status[k] & STATUS_BAD_ACTION) {
@@ -947,6 +964,7 @@ int batch_finish(chan_call* c, int32_t* results) {
       if (rc == CHAN_OK) rc = ri;
     }
   }
+  erase_value(c->b->calls, c);
   release_call(c);
   delete c;
   return rc;
@@ -1225,7 +1243,14 @@ int chan_env_create(const chan_grid_t* grid, const chan_opts_t* opts, void* hip_
 
 void chan_env_destroy(chan_env* e) {
   if (!e) return;
-  if (e->in_flight) (void)hipDeviceSynchronize();
+  if (chan_call* c = e->in_flight) {  // wait for its call, then leave it (finishing it reports CHAN_EINVAL here)
+    if (c->slot) (void)hipEventSynchronize(c->slot->done);
+    for (chan_env*& x : c->envs)
+      if (x == e) x = nullptr;
+    e->in_flight = nullptr;
+  }
+  for (chan_batch* b : e->member_of) erase_value(b->envs, e);
+  e->member_of.clear();
   if (e->stream) (void)hipStreamSynchronize(e->stream);
   batch_free(e->self);
   if (e->dev_block) (void)hipFree(e->dev_block);
@@ -1325,7 +1350,10 @@ int chan_batch_create(int32_t n, chan_env* const* envs, chan_batch** out) {
   g_last_error.clear();
   if (!out) return CHAN_EINVAL;
   *out = nullptr;
-  return batch_build(envs, n, out);
+  const int rc = batch_build(envs, n, out);
+  if (rc == CHAN_OK)
+    for (chan_env* e : (*out)->envs) e->member_of.push_back(*out);
+  return rc;
 }
 
 int chan_batch_step(chan_batch* b, const double* const* actions, int32_t n_substeps, double* const* obs,
@@ -1367,7 +1395,9 @@ int chan_call_finish(chan_call* c, int32_t* results) {
 int chan_batch_add(chan_batch* b, chan_env* env) {
   if (!b) return CHAN_EINVAL;
   g_last_error.clear();
-  return batch_add(b, env);
+  const int rc = batch_add(b, env);
+  if (rc == CHAN_OK) env->member_of.push_back(b);
+  return rc;
 }
 
 int chan_batch_remove(chan_batch* b, chan_env* env) {
@@ -1376,6 +1406,7 @@ int chan_batch_remove(chan_batch* b, chan_env* env) {
   if (k < 0) return fail(CHAN_EINVAL, "batch: env not in the batch");
   if (env->in_flight) return fail(CHAN_EBUSY, "batch: env held by an unfinished call");
   b->envs.erase(b->envs.begin() + k);
+  erase_value(env->member_of, b);
   return CHAN_OK;
 }
 

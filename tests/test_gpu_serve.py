@@ -205,3 +205,58 @@ def test_scale_mix_served_equals_alone():
         server.poll()
     check_requests(reqs_of, cfgs, seeds, server)
     server.close()
+
+
+def _minimal_envs(n, seeds):
+    import paper_2301_09889_amd.binding as b
+    envs = []
+    for s in seeds[:n]:
+        e = b.ChanEnv(*grid_opts(cfg_of(SPECS[0])))
+        e.reset(s)
+        envs.append(e)
+    return envs
+
+
+def test_batch_destroyed_with_a_call_in_flight():
+    """Destroying a batch finishes its unfinished call itself: the envs are released with the
+    step applied (clock, step counter, state as alone), and the call's handle reports
+    CHAN_EINVAL instead of touching freed memory."""
+    import torch
+    import paper_2301_09889_amd.binding as b
+    envs = _minimal_envs(2, [0, 1])
+    batch = b.ChanBatch(envs)
+    outs = [(torch.empty_like(e.obs), torch.empty_like(e.tau_w), torch.empty_like(e.drag)) for e in envs]
+    call = batch.launch(envs, None, 5, [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs])
+    batch.close()
+    assert call.finish() == [b.CHAN_EINVAL, b.CHAN_EINVAL]
+    for e, s in zip(envs, [0, 1]):
+        alone_obs, alone_state = alone_outputs(cfg_of(SPECS[0]), s, [None], [5])
+        assert e.query().nstep == 5
+        assert np.array_equal(e.get_state(), alone_state)
+        e.close()
+
+
+def test_env_destroyed_while_held_and_while_a_member():
+    """An env destroyed while a call holds it is waited for and detached (its slot of the call
+    reports CHAN_EINVAL, the others finish normally and equal alone); an env destroyed while a
+    batch lists it leaves the batch, which keeps stepping the others."""
+    import torch
+    import paper_2301_09889_amd.binding as b
+    envs = _minimal_envs(3, [0, 1, 2])
+    batch = b.ChanBatch(envs)
+    outs = [(torch.empty_like(e.obs), torch.empty_like(e.tau_w), torch.empty_like(e.drag)) for e in envs]
+    call = batch.launch(envs, None, 5, [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs])
+    envs[1].close()
+    assert len(batch.envs) == 2
+    assert call.finish() == [b.CHAN_OK, b.CHAN_EINVAL, b.CHAN_OK]
+    for k, s in ((0, 0), (2, 2)):
+        alone, state = alone_outputs(cfg_of(SPECS[0]), s, [None], [5])
+        assert np.array_equal(outs[k][0].cpu().numpy(), alone[0][0])
+        assert np.array_equal(envs[k].get_state(), state)
+    envs[0].close()
+    assert batch.envs == [envs[2]]
+    assert batch.step(None, 3) == [b.CHAN_OK]
+    _, state = alone_outputs(cfg_of(SPECS[0]), 2, [None, None], [5, 3])
+    assert np.array_equal(envs[2].get_state(), state)
+    batch.close()
+    envs[2].close()
