@@ -244,6 +244,18 @@ def run_batched(args, torch, b, gaussian_action):
     batch.step(acts, args.substeps)
     kt = b.chan_batch_timing_read(batch.handle)
     b.chan_batch_set_timing(batch.handle, 0)
+    # host time to enqueue one batch step (asynchronous launch, returns once every launch is
+    # queued) against the whole step: what capturing the launches in a graph could save at most
+    enq, whole = [], []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        call = batch.launch(envs, acts, args.substeps, [e.obs for e in envs], [e.tau_w for e in envs],
+                            [e.drag for e in envs], stream=torch.cuda.current_stream())
+        s1 = time.perf_counter()
+        call.finish()
+        whole.append(time.perf_counter() - s0)
+        enq.append(s1 - s0)
     # the plain form: the same kind of channels, one channel per launch
     sub = list(range(min(16, len(envs))))
     for i in sub:
@@ -286,6 +298,8 @@ def run_batched(args, torch, b, gaussian_action):
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "plain_one_channel_per_launch": {"value": plain, "unit": "env-steps/s",
                                          "sample": f"channels 0-{len(sub) - 1} of the mix, each stepped alone"},
+        "host_enqueue_ms": {"enqueue_p50": 1e3 * float(np.median(enq)), "step_p50": 1e3 * float(np.median(whole)),
+                            "note": "host time to queue one batch step's launches vs the whole step (5 steps)"},
         "batched_over_plain": value / plain,
         "roofline": None,
         "path_roofline": {"alg_bytes_per_substep": path_bytes, "achieved_GBs": path_bytes / sub_s / 1e9,
@@ -565,6 +579,20 @@ def main():
     elapsed_timed = time.perf_counter() - t1
     kt = b.chan_env_timing_read(env.handle)
     b.chan_env_set_timing(env.handle, 0)
+    # host time to enqueue one env step (asynchronous launch through a batch of one) against
+    # the whole step: what capturing the launches in a graph could save at most
+    one = b.ChanBatch([env])
+    enq, whole = [], []
+    for k in range(5):
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        call = one.launch([env], [acts[k]] if use_action else None, args.substeps, [env.obs], [env.tau_w], [env.drag],
+                          stream=torch.cuda.current_stream())
+        s1 = time.perf_counter()
+        call.finish()
+        whole.append(time.perf_counter() - s0)
+        enq.append(s1 - s0)
+    one.close()
     env.close()
 
     dom = max((k for k in kt if kt[k][0] > 0), key=lambda k: kt[k][1])
@@ -614,6 +642,8 @@ def main():
         "copy_bandwidth_GBs": copy_gbs,
         "kernels": kernels,
         "timing_pass_ms_per_step": 1e3 * elapsed_timed / args.steps,
+        "host_enqueue_ms": {"enqueue_p50": 1e3 * float(np.median(enq)), "step_p50": 1e3 * float(np.median(whole)),
+                            "note": "host time to queue one env step's launches vs the whole step (5 steps)"},
     }
     if args.copy_probe:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
