@@ -146,8 +146,40 @@ static void invalid_inputs() {
   CHECK(chan_last_error() != nullptr, "last error");
 }
 
+// The homogeneous solutions of the influence-matrix method meet their Dirichlet rows to rounding
+// (the tau solve's x0 refinement): v_+(+1) = v_+(-1) = 0 for every pair and stage, and in the
+// open channel phi_+(+1) = 1, phi_+(-1) = 0.  Residuals relative to sum |x_n|; the scan alone
+// (without the refinement) leaves them at eps times its much larger intermediate sums.
+static void boundary_rows(const Dims& d, const HostTables& t, bool open, double* worst) {
+  const int N = d.N, NY = d.ny;
+  for (int c = 1; c < d.ncol; ++c) {
+    const int q = c % d.nz;
+    if (q >= d.nz / 2) continue;
+    for (int r = 0; r < 3; ++r) {
+      const double* v = &t.data[t.L.vt + ((size_t)c * 3 + r) * NY];
+      double top = 0.0, bot = 0.0, mag = 0.0;
+      for (int n = 0; n <= N; ++n) {
+        top += v[n];
+        bot += (n & 1) ? -v[n] : v[n];
+        mag += std::fabs(v[n]);
+      }
+      *worst = std::fmax(*worst, std::fmax(std::fabs(top), std::fabs(bot)) / mag);
+      if (open) {
+        const double* ph = &t.data[t.L.pt + ((size_t)c * 3 + r) * NY];
+        double pt = -1.0, pb = 0.0, pm = 0.0;
+        for (int n = 0; n <= N; ++n) {
+          pt += ph[n];
+          pb += (n & 1) ? -ph[n] : ph[n];
+          pm += std::fabs(ph[n]);
+        }
+        *worst = std::fmax(*worst, std::fmax(std::fabs(pt), std::fabs(pb)) / pm);
+      }
+    }
+  }
+}
+
 // The operator tables of every supported N, closed and open, at two Reynolds numbers: every
-// entry finite.
+// entry finite, and the homogeneous solutions on their boundary rows.
 static void tables() {
   const int nys[] = {17, 33, 65, 97, 129};
   for (int ny : nys)
@@ -160,6 +192,10 @@ static void tables() {
         size_t bad = 0;
         for (double v : t.data) bad += std::isfinite(v) ? 0 : 1;
         CHECK(bad == 0, "%zu non-finite table entries N=%d open=%d re=%g", bad, ny - 1, open, re);
+        double worst = 0.0;
+        boundary_rows(d, t, open != 0, &worst);
+        CHECK(worst <= 1e-14, "boundary rows of v_+ / phi_+ off by %.2e (N=%d open=%d re=%g)", worst, ny - 1, open, re);
+        std::printf("boundary rows N=%d open=%d re=%g: %.2e\n", ny - 1, open, re, worst);
       }
 }
 

@@ -2,7 +2,9 @@
 
 tests/host_sanitize/driver.cpp drives validation (every supported grid, and invalid grids and
 options, which must be refused with CHAN_EINVAL and leave *out untouched), the FP64 operator
-precompute of every supported N (closed and open channel, two Reynolds numbers), the seeded
+precompute of every supported N (closed and open channel, two Reynolds numbers: every entry
+finite, and the influence-matrix homogeneous solutions on their Dirichlet rows to 1e-14 of their
+coefficient magnitude, which pins the tau solve's boundary-row refinement), the seeded
 initial condition and the plane-pass tiling candidates.  The library sources are compiled as
 usual for gfx950, with the sanitizers on the host side only; no device code runs (there is no
 GPU here, and every device path stops at its first HIP call)."""
