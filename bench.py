@@ -256,6 +256,22 @@ def run_batched(args, torch, b, gaussian_action):
         call.finish()
         whole.append(time.perf_counter() - s0)
         enq.append(s1 - s0)
+    # the same batch step captured once as a HIP graph and replayed (same buffers each time)
+    graph_value = None
+    try:
+        gr = batch.capture(envs, acts, args.substeps, [e.obs for e in envs], [e.tau_w for e in envs],
+                           [e.drag for e in envs])
+        gr.launch().finish()
+        torch.cuda.synchronize()
+        n_rep, gdone = max(5, args.steps // 4), 0
+        t2 = time.perf_counter()
+        for _ in range(n_rep):
+            gdone += sum(1 for c in gr.launch().finish() if c == 0)
+        torch.cuda.synchronize()
+        graph_value = gdone / (time.perf_counter() - t2)
+        gr.close()
+    except b.ChanError as err:                # a diverged channel has no valid state to capture
+        print(f"graph replay skipped: {err}", file=sys.stderr, flush=True)
     # the plain form: the same kind of channels, one channel per launch
     sub = list(range(min(16, len(envs))))
     for i in sub:
@@ -268,6 +284,23 @@ def run_batched(args, torch, b, gaussian_action):
             envs[i].step(acts[i], args.substeps)
     torch.cuda.synchronize()
     plain = len(sub) * reps / (time.perf_counter() - t1)
+    # and one captured graph per channel, replayed one channel at a time
+    plain_graph = None
+    try:
+        graphs = [envs[i].capture(acts[i], args.substeps) for i in sub]
+        for gi in graphs:
+            gi.launch().finish()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            for gi in graphs:
+                gi.launch().finish()
+        torch.cuda.synchronize()
+        plain_graph = len(sub) * reps / (time.perf_counter() - t1)
+        for gi in graphs:
+            gi.close()
+    except b.ChanError as err:
+        print(f"plain graph replay skipped: {err}", file=sys.stderr, flush=True)
     batch.close()
     path_bytes = sum(path_bytes_per_substep(sp) for k, sp in enumerate(specs) if codes[k] == 0)
     sub_s = elapsed / (args.steps * args.substeps)
@@ -297,7 +330,10 @@ def run_batched(args, torch, b, gaussian_action):
         "env_steps_completed": done,
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "plain_one_channel_per_launch": {"value": plain, "unit": "env-steps/s",
-                                         "sample": f"channels 0-{len(sub) - 1} of the mix, each stepped alone"},
+                                         "sample": f"channels 0-{len(sub) - 1} of the mix, each stepped alone",
+                                         "graph_replay_value": plain_graph},
+        "graph_replay": {"value": graph_value, "unit": "env-steps/s",
+                         "note": "the batch step captured once as a HIP graph (chan_batch_capture) and replayed"},
         "host_enqueue_ms": {"enqueue_p50": 1e3 * float(np.median(enq)), "step_p50": 1e3 * float(np.median(whole)),
                             "note": "host time to queue one batch step's launches vs the whole step (5 steps)"},
         "batched_over_plain": value / plain,
@@ -593,6 +629,21 @@ def main():
         whole.append(time.perf_counter() - s0)
         enq.append(s1 - s0)
     one.close()
+    # the same env step captured once as a HIP graph (chan_env_capture) and replayed, the action
+    # copied into the captured buffer on the stream before each replay
+    abuf = torch.zeros_like(acts[0])
+    gr = env.capture(abuf if use_action else None, args.substeps)
+    for k in range(2):
+        abuf.copy_(acts[k])
+        gr.launch().finish()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for k in range(args.steps):
+        abuf.copy_(acts[args.warmup + k])
+        gr.launch().finish()
+    torch.cuda.synchronize()
+    elapsed_graph = time.perf_counter() - t2
+    gr.close()
     env.close()
 
     dom = max((k for k in kt if kt[k][0] > 0), key=lambda k: kt[k][1])
@@ -644,6 +695,9 @@ def main():
         "timing_pass_ms_per_step": 1e3 * elapsed_timed / args.steps,
         "host_enqueue_ms": {"enqueue_p50": 1e3 * float(np.median(enq)), "step_p50": 1e3 * float(np.median(whole)),
                             "note": "host time to queue one env step's launches vs the whole step (5 steps)"},
+        "graph_replay": {"value": args.steps / elapsed_graph, "unit": "env-steps/s",
+                         "ms_per_step": 1e3 * elapsed_graph / args.steps,
+                         "note": "the same env steps captured once as a HIP graph (chan_env_capture) and replayed"},
     }
     if args.copy_probe:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")

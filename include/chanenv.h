@@ -292,6 +292,38 @@ int chan_call_finish(struct chan_call* call, int32_t* results);
 int chan_batch_add(struct chan_batch* batch, struct chan_env* env);
 int chan_batch_remove(struct chan_batch* batch, struct chan_env* env);
 
+/* ---- Captured env steps (HIP graphs) ----
+ * A worker repeats the same EVOLVE request every env step (§3.3): the same channels, the same
+ * action and output buffers, the same number of time steps.  chan_batch_capture records one such
+ * env step of the batch's envs envs[0..n) (arguments as for chan_batch_launch) as a HIP graph of
+ * its kernel launches and status read-back; the launch arguments are staged once, in buffers the
+ * graph owns.  Nothing runs at capture time.  chan_env_capture does the same for one env on its
+ * own (its action, outputs and n_substeps as for chan_env_step).
+ * chan_graph_launch replays the step on hip_stream (any stream of the batch's device) and returns
+ * a call like chan_batch_launch: the envs are held by it, and chan_call_query / chan_call_finish
+ * complete it (clock, step counter, per-env codes).  The replay reads the actions the buffers
+ * hold when the stream reaches it, so a worker refills its action buffer on that stream and
+ * replays again; its results are bitwise those of chan_batch_launch with the same arguments.
+ * reset, set_state and get_state of the envs between replays are allowed (the replay steps the
+ * state the env holds then).  A graph has one replay in flight at a time.
+ * Errors of capture: CHAN_EINVAL (as for chan_batch_launch), CHAN_EBUSY, CHAN_ESTATE (an env
+ * without a valid flow state: every env must have one), CHAN_ENOMEM, CHAN_EDEVICE.  Errors of
+ * launch: CHAN_ESTATE (an env now without a valid flow state or poisoned; an env has left the
+ * batch or been destroyed since the capture; the batch has been destroyed: capture again),
+ * CHAN_EBUSY (an env held by another call, or the graph's previous replay unfinished),
+ * CHAN_ENOMEM, CHAN_EDEVICE; nothing is queued then.
+ * chan_graph_destroy finishes the graph's replay in flight, if any (its call handle is invalid
+ * afterwards), and frees the graph; NULL is a no-op.  Destroying the batch (or, for
+ * chan_env_capture, the env) leaves its graphs to be destroyed by the caller. */
+typedef struct chan_graph chan_graph;
+int chan_batch_capture(struct chan_batch* batch, int32_t n, struct chan_env* const* envs,
+                       const double* const* actions, int32_t n_substeps, double* const* obs, double* const* tau_w,
+                       double* const* drag, struct chan_graph** out);
+int chan_env_capture(struct chan_env* env, const double* action, int32_t n_substeps, double* obs, double* tau_w,
+                     double* drag, struct chan_graph** out);
+int chan_graph_launch(struct chan_graph* graph, void* hip_stream, struct chan_call** out);
+void chan_graph_destroy(struct chan_graph* graph);
+
 /* ---- No allocation ----
  * For callers that cannot allocate device memory (code inside a tight serving loop, harnesses
  * that forbid hipMalloc): one env step of a flow state the caller owns, with no env object and

@@ -137,6 +137,14 @@ def load_library():
     lib.chan_batch_add.restype = ctypes.c_int
     lib.chan_batch_remove.argtypes = [vp, vp]
     lib.chan_batch_remove.restype = ctypes.c_int
+    lib.chan_batch_capture.argtypes = [vp, ctypes.c_int32, P(vp), P(vp), ctypes.c_int32, P(vp), P(vp), P(vp), P(vp)]
+    lib.chan_batch_capture.restype = ctypes.c_int
+    lib.chan_env_capture.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp, P(vp)]
+    lib.chan_env_capture.restype = ctypes.c_int
+    lib.chan_graph_launch.argtypes = [vp, vp, P(vp)]
+    lib.chan_graph_launch.restype = ctypes.c_int
+    lib.chan_graph_destroy.argtypes = [vp]
+    lib.chan_graph_destroy.restype = None
     lib.chan_step_static.argtypes = [P(ChanGrid), P(ChanOpts), vp, vp, vp, ctypes.c_int32, vp, vp, vp]
     lib.chan_step_static.restype = ctypes.c_int
     _LIB = lib
@@ -273,6 +281,33 @@ def chan_batch_launch(h, stream, env_handles, action_ptrs, n_substeps, obs_ptrs,
     return rc, call
 
 
+def chan_batch_capture(h, env_handles, action_ptrs, n_substeps, obs_ptrs, tau_ptrs, drag_ptrs):
+    """Capture one env step of the listed envs as a graph; returns (code, graph handle)."""
+    graph = ctypes.c_void_p()
+    hs = (ctypes.c_void_p * len(env_handles))(*env_handles)
+    rc = load_library().chan_batch_capture(h, len(env_handles), hs, _ptr_array(action_ptrs), int(n_substeps),
+                                           _ptr_array(obs_ptrs), _ptr_array(tau_ptrs), _ptr_array(drag_ptrs),
+                                           ctypes.byref(graph))
+    return rc, graph
+
+
+def chan_env_capture(h, action_ptr, n_substeps, obs_ptr, tau_ptr, drag_ptr):
+    graph = ctypes.c_void_p()
+    rc = load_library().chan_env_capture(h, ctypes.c_void_p(action_ptr), int(n_substeps), ctypes.c_void_p(obs_ptr),
+                                         ctypes.c_void_p(tau_ptr), ctypes.c_void_p(drag_ptr), ctypes.byref(graph))
+    return rc, graph
+
+
+def chan_graph_launch(graph, stream):
+    call = ctypes.c_void_p()
+    rc = load_library().chan_graph_launch(graph, ctypes.c_void_p(stream), ctypes.byref(call))
+    return rc, call
+
+
+def chan_graph_destroy(graph):
+    load_library().chan_graph_destroy(graph)
+
+
 def chan_call_query(call):
     return load_library().chan_call_query(call)
 
@@ -393,12 +428,27 @@ class ChanEnv:
     def query(self):
         return chan_env_query(self.handle)
 
+    def capture(self, action, n_substeps):
+        """Capture one env step with this action tensor (or None) and the env's own output tensors
+        as a graph; ChanGraph.launch replays it (refill the action tensor between replays)."""
+        rc, g = chan_env_capture(self.handle, _action_ptr(self, action), n_substeps, self.obs.data_ptr(),
+                                 self.tau_w.data_ptr(), self.drag.data_ptr())
+        self._check(rc, "chan_env_capture")
+        graph = ChanGraph(g, 1, keep=(action,))
+        if not hasattr(self, "_graphs"):
+            self._graphs = weakref.WeakSet()
+        self._graphs.add(graph)
+        return graph
+
     def close(self):
         """Destroy the env: the library waits for a call that holds it and removes it from every
-        batch; the Python batches that list it drop it too."""
+        batch; the Python batches that list it drop it too.  Replays of the env's own graphs
+        (capture) are finished by the library."""
         if self.handle:
             for b in list(getattr(self, "_batches", ())):
                 b._drop(self)
+            for g in list(getattr(self, "_graphs", ())):
+                g._abandon_calls()
             chan_env_destroy(self.handle)
             self.handle = None
 
@@ -418,6 +468,7 @@ class ChanBatch:
         self.handle = chan_batch_create([e.handle for e in self.envs])
         self.results = (ctypes.c_int32 * len(self.envs))()
         self._calls = weakref.WeakSet()
+        self._graphs = weakref.WeakSet()
         for e in self.envs:
             _member_of(e).add(self)
 
@@ -476,6 +527,22 @@ class ChanBatch:
         self._calls.add(c)
         return c
 
+    def capture(self, envs, actions, n_substeps, obs, tau_w, drag):
+        """Capture one env step of envs with these tensors (as for launch) as a graph;
+        ChanGraph.launch replays it."""
+        aptrs = [_action_ptr(e, actions[k] if actions is not None else None) for k, e in enumerate(envs)]
+
+        def ptrs(ts):
+            return [t.data_ptr() if t is not None else 0 for t in ts] if ts is not None else [0] * len(envs)
+
+        rc, g = chan_batch_capture(self.handle, [e.handle for e in envs], aptrs, n_substeps, ptrs(obs), ptrs(tau_w),
+                                   ptrs(drag))
+        if rc != CHAN_OK:
+            raise ChanError(rc, "chan_batch_capture")
+        graph = ChanGraph(g, len(envs), keep=(actions, obs, tau_w, drag))
+        self._graphs.add(graph)
+        return graph
+
     def add(self, env):
         rc = chan_batch_add(self.handle, env.handle)
         if rc != CHAN_OK:
@@ -498,6 +565,8 @@ class ChanBatch:
         if self.handle:
             for c in list(self._calls):
                 c._abandon()
+            for g in list(self._graphs):
+                g._abandon_calls()
             for e in self.envs:
                 _member_of(e).discard(self)
             chan_batch_destroy(self.handle)
@@ -550,3 +619,41 @@ class ChanCall:
             self.codes = list(res)
             self.keep = None
         return self.codes
+
+
+class ChanGraph:
+    """A captured env step (ChanBatch.capture / ChanEnv.capture): launch() replays it and returns a
+    ChanCall; keeps the captured tensors alive."""
+
+    def __init__(self, handle, n, keep=None):
+        self.handle = handle
+        self.n = n
+        self.keep = keep
+        self._calls = weakref.WeakSet()
+
+    def launch(self, stream=None):
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream()
+        rc, call = chan_graph_launch(self.handle, st.cuda_stream)
+        if rc != CHAN_OK:
+            raise ChanError(rc, "chan_graph_launch")
+        c = ChanCall(call, self.n, keep=self.keep)
+        self._calls.add(c)
+        return c
+
+    def _abandon_calls(self):
+        """The library is about to finish this graph's replay in flight itself."""
+        for c in list(self._calls):
+            c._abandon()
+
+    def close(self):
+        if self.handle:
+            self._abandon_calls()
+            chan_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

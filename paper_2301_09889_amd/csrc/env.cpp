@@ -55,6 +55,21 @@ struct chan_call {
   int max_nx = 0, max_nz = 0, max_nkx = 0;
 };
 
+// One env step of some of a batch's channels captured as a HIP graph (chan_batch_capture).  The
+// launch arguments never change between replays, so they are staged once, before the capture,
+// into a slot the graph owns (outside the batch's pool); the graph holds the kernels, the status
+// read-back into that slot's pinned words, and nothing else.  A replay is an ordinary call on
+// that slot (busy while it is in flight), finished by batch_finish like any other.
+struct chan_graph {
+  chan_batch* b = nullptr;        // null once the batch is destroyed
+  std::vector<chan_env*> envs;    // in call order
+  int n_sub = 1;
+  CallSlot* slot = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool stale = false;             // an env left the batch or was destroyed after the capture
+};
+
 // Envs stepped together.  Members can join and leave; every call stages the launch arguments
 // of its channels (per-step StepChan, and the fixed ColChan / PlaneChan grouped by shape) in a
 // slot of its own and uploads them with one copy per array.  Every env owns a batch of one for
@@ -66,6 +81,7 @@ struct chan_batch {
   int device = 0;
   std::vector<CallSlot*> slots;
   std::vector<chan_call*> calls;  // launched and not yet finished
+  std::vector<chan_graph*> graphs;  // captured steps of this batch's envs (chan_batch_capture)
   KernelTimer timer;
   double timing_ms[KC_COUNT];
   int64_t timing_launches[KC_COUNT];
@@ -475,6 +491,7 @@ void batch_free(chan_batch* b) {
   if (!b) return;
   // calls never finished: finish them (wait, apply each env's outcome, release, free)
   for (chan_call* c : std::vector<chan_call*>(b->calls)) (void)batch_finish(c, nullptr);
+  for (chan_graph* g : b->graphs) g->b = nullptr;  // the caller still destroys them
   for (chan_env* e : b->envs) erase_value(e->member_of, b);
   if (b->stream) (void)hipStreamSynchronize(b->stream);
   for (CallSlot* sl : b->slots) free_slot(sl);
@@ -553,7 +570,10 @@ int find_member(const chan_batch* b, const chan_env* e) {
   return -1;
 }
 
-// A free slot holding at least n envs (grown or created if none); nullptr if out of memory.
+bool size_slot(CallSlot* pick, int cap);
+
+// A free slot of the batch's pool with room for n envs (grown or created if none), marked busy;
+// nullptr if out of memory.
 CallSlot* acquire_slot(chan_batch* b, int n) {
   CallSlot* pick = nullptr;
   for (CallSlot* sl : b->slots)
@@ -572,16 +592,22 @@ CallSlot* acquire_slot(chan_batch* b, int n) {
     }
     b->slots.push_back(pick);
   }
-  const int cap = std::max(n, 2 * pick->cap);
+  if (!size_slot(pick, std::max(n, 2 * pick->cap))) return nullptr;
+  pick->busy = true;
+  return pick;
+}
+
+// (Re)allocates the slot's buffers for cap envs; false (slot unchanged) if an allocation fails.
+bool size_slot(CallSlot* pick, int cap) {
   const size_t off_col = align256((size_t)cap * sizeof(StepChan));
   const size_t off_plane = off_col + align256((size_t)cap * sizeof(ColChan));
   const size_t off_status = off_plane + align256((size_t)cap * sizeof(PlaneChan));
   const size_t bytes = off_status + align256((size_t)cap * sizeof(int));
   char *dev = nullptr, *host = nullptr;
-  if (hipMalloc((void**)&dev, bytes) != hipSuccess) return nullptr;
+  if (hipMalloc((void**)&dev, bytes) != hipSuccess) return false;
   if (hipHostMalloc((void**)&host, bytes) != hipSuccess) {
     (void)hipFree(dev);
-    return nullptr;
+    return false;
   }
   if (pick->dev) (void)hipFree(pick->dev);
   if (pick->host) (void)hipHostFree(pick->host);
@@ -592,8 +618,7 @@ CallSlot* acquire_slot(chan_batch* b, int n) {
   pick->off_plane = off_plane;
   pick->off_status = off_status;
   pick->bytes = bytes;
-  pick->busy = true;
-  return pick;
+  return true;
 }
 
 StepChan* host_step(const chan_call* c) { return (StepChan*)c->slot->host; }
@@ -608,7 +633,7 @@ template <class StepFn>
 int stage_call(chan_call* c, StepFn step) {
   chan_batch* b = c->b;
   const int na = (int)c->envs.size();
-  c->slot = acquire_slot(b, na);
+  if (!c->slot) c->slot = acquire_slot(b, na);  // a captured step brings its own
   if (!c->slot) return fail(CHAN_ENOMEM, "call staging buffers");
   StepChan* hs = host_step(c);
   ColChan* hc = (ColChan*)(c->slot->host + c->slot->off_col);
@@ -819,8 +844,8 @@ int tune_plane(chan_batch* b, int shape, const std::vector<chan_env*>& members) 
 }
 
 // Queues the launches of one env step of the call's envs (already staged), then the status
-// read-back and the completion event.
-int launch_step(chan_call* c, bool any_action, KernelTimer* tm, double* const* obs) {
+// read-back and (record_done) the completion event.
+int launch_step(chan_call* c, bool any_action, KernelTimer* tm, double* const* obs, bool record_done = true) {
   chan_batch* b = c->b;
   hipStream_t st = c->stream;
   const int na = (int)c->envs.size();
@@ -883,7 +908,19 @@ int launch_step(chan_call* c, bool any_action, KernelTimer* tm, double* const* o
   if (any_pressure && launch_pressure_finish(ds, na, st, tm))
     return fail(CHAN_EDEVICE, "launch pressure finish", hipGetLastError());
   HIPCHECK(hipMemcpyAsync(host_status(c), dev_status(c), na * sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCHECK(hipEventRecord(c->slot->done, st));
+  if (record_done) HIPCHECK(hipEventRecord(c->slot->done, st));
+  return CHAN_OK;
+}
+
+// The envs of a call: members of b, each listed once, none held by an unfinished call.
+int check_call_envs(const chan_batch* b, int32_t na, chan_env* const* envs) {
+  if (na < 1 || na > (int32_t)b->envs.size() || !envs) return fail(CHAN_EINVAL, "batch step: bad number of envs");
+  for (int k = 0; k < na; ++k) {
+    if (!envs[k] || find_member(b, envs[k]) < 0) return fail(CHAN_EINVAL, "batch step: env not in the batch");
+    if (envs[k]->in_flight) return fail(CHAN_EBUSY, "batch step: env has an unfinished call");
+    for (int j = 0; j < k; ++j)
+      if (envs[j] == envs[k]) return fail(CHAN_EINVAL, "batch step: env listed twice");
+  }
   return CHAN_OK;
 }
 
@@ -892,13 +929,8 @@ int launch_step(chan_call* c, bool any_action, KernelTimer* tm, double* const* o
 int batch_launch(chan_batch* b, hipStream_t st, int32_t na, chan_env* const* envs, const double* const* actions,
                  int32_t n_substeps, double* const* obs, double* const* tau_w, double* const* drag, chan_call** out) {
   if (n_substeps < 1) return fail(CHAN_EINVAL, "n_substeps < 1");
-  if (na < 1 || na > (int32_t)b->envs.size() || !envs) return fail(CHAN_EINVAL, "batch step: bad number of envs");
-  for (int k = 0; k < na; ++k) {
-    if (!envs[k] || find_member(b, envs[k]) < 0) return fail(CHAN_EINVAL, "batch step: env not in the batch");
-    if (envs[k]->in_flight) return fail(CHAN_EBUSY, "batch step: env has an unfinished call");
-    for (int j = 0; j < k; ++j)
-      if (envs[j] == envs[k]) return fail(CHAN_EINVAL, "batch step: env listed twice");
-  }
+  const int rc0 = check_call_envs(b, na, envs);
+  if (rc0 != CHAN_OK) return rc0;
   int n_ready = 0;
   for (int k = 0; k < na; ++k) n_ready += (envs[k]->have_flow && !envs[k]->poisoned) ? 1 : 0;
   if (n_ready == 0) return fail(CHAN_ESTATE, "no env with a valid flow state");
@@ -968,6 +1000,134 @@ int batch_finish(chan_call* c, int32_t* results) {
   release_call(c);
   delete c;
   return rc;
+}
+
+void graph_free(chan_graph* g) {
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  free_slot(g->slot);
+  delete g;
+}
+
+// Captures one env step of envs[0..na) with these buffers: stages the launch arguments into the
+// graph's own slot on a private stream, waits for them, then records the step's launches on that
+// stream.  Every env must have a valid flow state (a replay steps all of them).
+int batch_capture(chan_batch* b, int32_t na, chan_env* const* envs, const double* const* actions,
+                  int32_t n_substeps, double* const* obs, double* const* tau_w, double* const* drag,
+                  chan_graph** out) {
+  if (n_substeps < 1) return fail(CHAN_EINVAL, "n_substeps < 1");
+  const int rc0 = check_call_envs(b, na, envs);
+  if (rc0 != CHAN_OK) return rc0;
+  for (int k = 0; k < na; ++k)
+    if (!envs[k]->have_flow || envs[k]->poisoned) return fail(CHAN_ESTATE, "capture: env without a valid flow state");
+  chan_graph* g = new (std::nothrow) chan_graph();
+  if (!g) return CHAN_ENOMEM;
+  g->b = b;
+  g->envs.assign(envs, envs + na);
+  g->n_sub = n_substeps;
+  g->slot = new (std::nothrow) CallSlot();
+  if (!g->slot) {
+    delete g;
+    return CHAN_ENOMEM;
+  }
+  if (hipEventCreateWithFlags(&g->slot->done, hipEventDisableTiming) != hipSuccess) {
+    g->slot->done = nullptr;
+    graph_free(g);
+    return fail(CHAN_EDEVICE, "hipEventCreateWithFlags");
+  }
+  if (!size_slot(g->slot, na)) {
+    graph_free(g);
+    return fail(CHAN_ENOMEM, "capture staging buffers");
+  }
+  hipStream_t cs = nullptr;
+  hipError_t err = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (err != hipSuccess) {
+    graph_free(g);
+    return fail(CHAN_EDEVICE, "hipStreamCreateWithFlags", err);
+  }
+  chan_call c;
+  c.b = b;
+  c.stream = cs;
+  c.slot = g->slot;
+  c.envs = g->envs;
+  c.n_sub = n_substeps;
+  bool any_action = false;
+  int rc = stage_call(&c, [&](int k) {
+    StepChan s = make_step_chan_env(c.envs[k], dev_status(&c) + k, actions ? actions[k] : nullptr, n_substeps,
+                                    obs ? obs[k] : nullptr, tau_w ? tau_w[k] : nullptr, drag ? drag[k] : nullptr);
+    any_action = any_action || (s.action != nullptr && !s.skip);
+    return s;
+  });
+  if (rc == CHAN_OK && (err = hipStreamSynchronize(cs)) != hipSuccess) rc = fail(CHAN_EDEVICE, "hipStreamSynchronize", err);
+  if (rc == CHAN_OK) {
+    err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (err != hipSuccess) {
+      rc = fail(CHAN_EDEVICE, "hipStreamBeginCapture", err);
+    } else {
+      rc = launch_step(&c, any_action, nullptr, obs, false);
+      hipGraph_t graph = nullptr;
+      err = hipStreamEndCapture(cs, &graph);
+      g->graph = graph;
+      if (rc == CHAN_OK && err != hipSuccess) rc = fail(CHAN_EDEVICE, "hipStreamEndCapture", err);
+      if (rc == CHAN_OK && (err = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0)) != hipSuccess)
+        rc = fail(CHAN_EDEVICE, "hipGraphInstantiate", err);
+    }
+  }
+  (void)hipStreamDestroy(cs);
+  if (rc != CHAN_OK) {
+    graph_free(g);
+    return rc;
+  }
+  b->graphs.push_back(g);
+  *out = g;
+  return CHAN_OK;
+}
+
+// Replays a captured step on stream st; *out: the call (finished by batch_finish).
+int graph_launch(chan_graph* g, hipStream_t st, chan_call** out) {
+  if (!g->b) return fail(CHAN_ESTATE, "graph: its batch was destroyed");
+  if (g->stale) return fail(CHAN_ESTATE, "graph: an env left the batch or was destroyed after the capture");
+  if (g->slot->busy) return fail(CHAN_EBUSY, "graph: its previous replay is unfinished");
+  for (chan_env* e : g->envs) {
+    if (e->in_flight) return fail(CHAN_EBUSY, "graph: env has an unfinished call");
+    if (!e->have_flow || e->poisoned) return fail(CHAN_ESTATE, "graph: env without a valid flow state");
+  }
+  chan_call* c = new (std::nothrow) chan_call();
+  if (!c) return CHAN_ENOMEM;
+  c->b = g->b;
+  c->slot = g->slot;
+  c->stream = st;
+  c->envs = g->envs;
+  c->n_sub = g->n_sub;
+  hipError_t err = hipGraphLaunch(g->exec, st);
+  if (err == hipSuccess) err = hipEventRecord(g->slot->done, st);
+  if (err != hipSuccess) {
+    (void)hipStreamSynchronize(st);
+    delete c;
+    return fail(CHAN_EDEVICE, "hipGraphLaunch", err);
+  }
+  g->slot->busy = true;
+  for (chan_env* e : c->envs) e->in_flight = c;
+  g->b->calls.push_back(c);
+  *out = c;
+  return CHAN_OK;
+}
+
+// Finishes the graph's replay in flight (if any), then frees it.
+void graph_destroy(chan_graph* g) {
+  if (g->b) {
+    for (chan_call* c : std::vector<chan_call*>(g->b->calls))
+      if (c->slot == g->slot) (void)batch_finish(c, nullptr);
+    erase_value(g->b->graphs, g);
+  }
+  graph_free(g);
+}
+
+// Graphs of b that step env e can no longer be replayed (e left b or is being destroyed).
+void stale_graphs(chan_batch* b, const chan_env* e) {
+  for (chan_graph* g : b->graphs)
+    for (const chan_env* x : g->envs)
+      if (x == e) g->stale = true;
 }
 
 // Synchronous env step of the batch's envs idx[0..na) (idx null: the first na) on the batch's
@@ -1249,7 +1409,10 @@ void chan_env_destroy(chan_env* e) {
       if (x == e) x = nullptr;
     e->in_flight = nullptr;
   }
-  for (chan_batch* b : e->member_of) erase_value(b->envs, e);
+  for (chan_batch* b : e->member_of) {
+    erase_value(b->envs, e);
+    stale_graphs(b, e);
+  }
   e->member_of.clear();
   if (e->stream) (void)hipStreamSynchronize(e->stream);
   batch_free(e->self);
@@ -1407,7 +1570,36 @@ int chan_batch_remove(chan_batch* b, chan_env* env) {
   if (env->in_flight) return fail(CHAN_EBUSY, "batch: env held by an unfinished call");
   b->envs.erase(b->envs.begin() + k);
   erase_value(env->member_of, b);
+  stale_graphs(b, env);
   return CHAN_OK;
+}
+
+int chan_batch_capture(chan_batch* b, int32_t n, chan_env* const* envs, const double* const* actions,
+                       int32_t n_substeps, double* const* obs, double* const* tau_w, double* const* drag,
+                       chan_graph** out) {
+  g_last_error.clear();
+  if (!b || !out) return CHAN_EINVAL;
+  *out = nullptr;
+  return batch_capture(b, n, envs, actions, n_substeps, obs, tau_w, drag, out);
+}
+
+int chan_env_capture(chan_env* e, const double* action, int32_t n_substeps, double* obs, double* tau_w,
+                     double* drag, chan_graph** out) {
+  g_last_error.clear();
+  if (!e || !out) return CHAN_EINVAL;
+  *out = nullptr;
+  return batch_capture(e->self, 1, &e, &action, n_substeps, &obs, &tau_w, &drag, out);
+}
+
+int chan_graph_launch(chan_graph* g, void* hip_stream, chan_call** out) {
+  g_last_error.clear();
+  if (!g || !out) return CHAN_EINVAL;
+  *out = nullptr;
+  return graph_launch(g, (hipStream_t)hip_stream, out);
+}
+
+void chan_graph_destroy(chan_graph* g) {
+  if (g) graph_destroy(g);
 }
 
 void chan_batch_destroy(chan_batch* b) { batch_free(b); }
