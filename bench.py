@@ -225,6 +225,7 @@ def run_batched(args, torch, b, gaussian_action):
         acts.append(torch.tensor(gaussian_action(1000 + sp["seed"], sp["nz"], sp["nx"]), dtype=torch.float64,
                                  device="cuda") if sp["external"] else None)
     batch = b.ChanBatch(envs)
+    tuning = b.chan_batch_tuning(batch.handle)
     for _ in range(args.warmup):
         batch.step(acts, args.substeps)
     torch.cuda.synchronize()
@@ -332,6 +333,7 @@ def run_batched(args, torch, b, gaussian_action):
         "plain_one_channel_per_launch": {"value": plain, "unit": "env-steps/s",
                                          "sample": f"channels 0-{len(sub) - 1} of the mix, each stepped alone",
                                          "graph_replay_value": plain_graph},
+        "tuning": tuning,
         "graph_replay": {"value": graph_value, "unit": "env-steps/s",
                          "note": "the batch step captured once as a HIP graph (chan_batch_capture) and replayed"},
         "host_enqueue_ms": {"enqueue_p50": 1e3 * float(np.median(enq)), "step_p50": 1e3 * float(np.median(whole)),

@@ -259,6 +259,17 @@ int32_t chan_batch_size(const struct chan_batch* batch);
 int chan_batch_set_timing(struct chan_batch* batch, int32_t enable);
 int chan_batch_timing_read(struct chan_batch* batch, int32_t nclass, int64_t* launches, double* ms);
 
+/* The tuned launch shapes of the batch's grid shapes (instrumentation).  A batch times, when it is
+ * created, every valid tiling of the plane pass for each grid shape on that shape's channels, and
+ * for a shape with several channels on the parity-major column kernels (N_y <= 65) the columns per
+ * block of the batched column launch (2 or 4); the fastest of each is kept.  No result depends on
+ * either choice.  A shape that first arrives through chan_batch_add is tuned on that one channel's
+ * plane pass and keeps 4 columns per block.  Writes up to max_shapes records of 6 int32
+ * {nx, ny, nz, z pencils per block, x-row pairs per block, columns per block} (columns per block
+ * 0 for a shape on the general column kernel) and returns the number of shapes; CHAN_EINVAL for
+ * NULL arguments. */
+int chan_batch_tuning(const struct chan_batch* batch, int32_t max_shapes, int32_t* out);
+
 /* ---- Asynchronous batch calls and membership (a request loop over channels that come and go) ----
  * chan_batch_launch queues one env step of the batch's envs envs[0..n) (each at most once; the
  * per-env arrays indexed like envs, as for chan_batch_step) on hip_stream, any stream of the

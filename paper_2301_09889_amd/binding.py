@@ -137,6 +137,8 @@ def load_library():
     lib.chan_batch_add.restype = ctypes.c_int
     lib.chan_batch_remove.argtypes = [vp, vp]
     lib.chan_batch_remove.restype = ctypes.c_int
+    lib.chan_batch_tuning.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int32)]
+    lib.chan_batch_tuning.restype = ctypes.c_int
     lib.chan_batch_capture.argtypes = [vp, ctypes.c_int32, P(vp), P(vp), ctypes.c_int32, P(vp), P(vp), P(vp), P(vp)]
     lib.chan_batch_capture.restype = ctypes.c_int
     lib.chan_env_capture.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp, P(vp)]
@@ -279,6 +281,18 @@ def chan_batch_launch(h, stream, env_handles, action_ptrs, n_substeps, obs_ptrs,
                                           _ptr_array(action_ptrs), int(n_substeps), _ptr_array(obs_ptrs),
                                           _ptr_array(tau_ptrs), _ptr_array(drag_ptrs), ctypes.byref(call))
     return rc, call
+
+
+def chan_batch_tuning(h):
+    """The batch's tuned launch shapes: a list of dicts per grid shape."""
+    lib = load_library()
+    n = lib.chan_batch_tuning(h, 0, None)
+    if n < 0:
+        raise ChanError(n, "chan_batch_tuning")
+    buf = (ctypes.c_int32 * (6 * max(n, 1)))()
+    lib.chan_batch_tuning(h, n, buf)
+    keys = ("nx", "ny", "nz", "z_pencils_per_block", "x_pairs_per_block", "columns_per_block")
+    return [dict(zip(keys, buf[6 * k:6 * k + 6])) for k in range(n)]
 
 
 def chan_batch_capture(h, env_handles, action_ptrs, n_substeps, obs_ptrs, tau_ptrs, drag_ptrs):

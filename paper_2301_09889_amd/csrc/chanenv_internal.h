@@ -252,9 +252,10 @@ int plane_tile_candidates(const Dims& d, std::vector<PlaneTiles>* out);
 // N <= 64 column pass over nch channels of one shape: the solve of stage S.stage (if solve)
 // and/or the reconstruction that follows it (if recon; S.stage -1: reconstruction only).
 // d_col: the channels' arguments on the device; h_col (optional): the same on the host, used
-// to pass a single channel's arguments by value.
+// to pass a single channel's arguments by value.  batch_cw: columns per block when nch > 1
+// (2 or 4; no result depends on it).
 int launch_column_pm(const Dims& d, const ColChan* d_col, const ColChan* h_col, int nch, const ColStage& S,
-                     bool solve, bool recon, hipStream_t st, KernelTimer* tm);
+                     bool solve, bool recon, hipStream_t st, KernelTimer* tm, int batch_cw);
 // General column pass (any N, one channel per launch); stage -1 only reconstructs the
 // plane-pass input from the state; with recon false the pass stops after the solve.
 int launch_column_pass(const Dims& d, DeviceState& s, const PhysParams& ph, int stage,

@@ -42,7 +42,7 @@ namespace chanenv {
 
 namespace {
 
-constexpr int CWAVES = 4;  // columns (wavefronts) per block of the batched kernel
+constexpr int CWAVES = 4;  // columns (wavefronts) per block of the pressure kernel
 
 
 // ---- cross-lane moves without LDS (gfx950 DPP and permlane swaps) ----
@@ -934,16 +934,17 @@ __device__ __forceinline__ void column_block(const ColChan& A, const ColStage& S
 // occupancy hides load latency: the reconstruction requests its cosines per group of 16
 // terms, which keeps the reconstruction and the fused launch within three waves per SIMD
 // (138 and 164 VGPRs at N = 64; all cosines up front needs more than 170).
-template <int N, int PART>
-__global__ __launch_bounds__(64 * CWAVES, 3) void k_column_pm(const ColChan* __restrict__ chans, ColStage S,
-                                                               int bpc) {
+// CW columns per block, chosen per grid shape by the batch's tuner (2 or 4: the 16x65x16 channels
+// of a large batch run about 3 % faster two per block, the 32x65x32 ones as fast four per block).
+template <int N, int PART, int CW>
+__global__ __launch_bounds__(64 * CW, 3) void k_column_pm(const ColChan* __restrict__ chans, ColStage S, int bpc) {
   // contiguous block ranges per XCD: 23.8 -> 20.6 ms of column launches per env step of the
   // 256-channel batch (the one-channel launch below, all blocks resident at once, is 2 % slower
   // with the same mapping)
-  __shared__ double tile[9 * CWAVES * (N + 1) * 2 + 2 * N];
+  __shared__ double tile[9 * CW * (N + 1) * 2];
   const int b = xcd_block(blockIdx.x, gridDim.x);
   const int ch = b / bpc;
-  column_block<N, PART, PART != PART_SOLVE, CWAVES, false>(chans[ch], S, b - ch * bpc, reinterpret_cast<cplx*>(tile));
+  column_block<N, PART, PART != PART_SOLVE, CW, false>(chans[ch], S, b - ch * bpc, reinterpret_cast<cplx*>(tile));
 }
 
 // One channel, its arguments by value (preloaded with the kernel arguments instead of read
@@ -980,9 +981,29 @@ int launch_pm1(const ColChan& A, int ncol, const ColStage& S, bool solve, bool r
   return 0;
 }
 
+template <int N, int CW>
+int launch_pmb(const ColChan* d_col, int nch, int ncol, const ColStage& S, bool solve, bool recon, hipStream_t st,
+               KernelTimer* tm) {
+  const int bpc = (ncol + CW - 1) / CW;
+  const dim3 grid(bpc * nch), block(64 * CW);
+  if (solve && recon) {
+    timed_launch(tm, KC_FUSED, k_column_pm<N, PART_BOTH, CW>, grid, block, 0, st, d_col, S, bpc);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+  }
+  if (solve) {
+    timed_launch(tm, KC_COLUMN, k_column_pm<N, PART_SOLVE, CW>, grid, block, 0, st, d_col, S, bpc);
+    if (hipGetLastError() != hipSuccess) return -1;
+  }
+  if (recon) {
+    timed_launch(tm, KC_RECON, k_column_pm<N, PART_RECON, CW>, grid, block, 0, st, d_col, S, bpc);
+    if (hipGetLastError() != hipSuccess) return -1;
+  }
+  return 0;
+}
+
 template <int N>
 int launch_pm(const ColChan* d_col, const ColChan* h_col, int nch, int ncol, const ColStage& S, bool solve,
-              bool recon, hipStream_t st, KernelTimer* tm) {
+              bool recon, hipStream_t st, KernelTimer* tm, int batch_cw) {
   // Both parts in one launch: the solved state stays in registers for the reconstruction,
   // which saves a kernel boundary and the state's reload.  (Every stage of every batch takes
   // this path, so a channel's arithmetic does not depend on the batch it is in; neither does
@@ -994,21 +1015,11 @@ int launch_pm(const ColChan* d_col, const ColChan* h_col, int nch, int ncol, con
       default: return launch_pm1<N, 4>(h_col[0], ncol, S, solve, recon, st, tm);
     }
   }
-  const int bpc = (ncol + CWAVES - 1) / CWAVES;
-  const dim3 grid(bpc * nch), block(64 * CWAVES);
-  if (solve && recon) {
-    timed_launch(tm, KC_FUSED, k_column_pm<N, PART_BOTH>, grid, block, 0, st, d_col, S, bpc);
-    return hipGetLastError() == hipSuccess ? 0 : -1;
+  switch (batch_cw) {
+    case 2: return launch_pmb<N, 2>(d_col, nch, ncol, S, solve, recon, st, tm);
+    case 4: return launch_pmb<N, 4>(d_col, nch, ncol, S, solve, recon, st, tm);
+    default: return -1;
   }
-  if (solve) {
-    timed_launch(tm, KC_COLUMN, k_column_pm<N, PART_SOLVE>, grid, block, 0, st, d_col, S, bpc);
-    if (hipGetLastError() != hipSuccess) return -1;
-  }
-  if (recon) {
-    timed_launch(tm, KC_RECON, k_column_pm<N, PART_RECON>, grid, block, 0, st, d_col, S, bpc);
-    if (hipGetLastError() != hipSuccess) return -1;
-  }
-  return 0;
 }
 
 // Pressure on the observation planes (the observable p - <p>_plane; end of an env step, after a
@@ -1117,12 +1128,12 @@ __global__ __launch_bounds__(64 * CWAVES, 2) void k_pressure_pm(const ColChan* _
 }  // namespace
 
 int launch_column_pm(const Dims& d, const ColChan* d_col, const ColChan* h_col, int nch, const ColStage& S,
-                     bool solve, bool recon, hipStream_t st, KernelTimer* tm) {
+                     bool solve, bool recon, hipStream_t st, KernelTimer* tm, int batch_cw) {
   if (nch < 1) return 0;
   switch (d.N) {
-    case 16: return launch_pm<16>(d_col, h_col, nch, d.ncol, S, solve, recon, st, tm);
-    case 32: return launch_pm<32>(d_col, h_col, nch, d.ncol, S, solve, recon, st, tm);
-    case 64: return launch_pm<64>(d_col, h_col, nch, d.ncol, S, solve, recon, st, tm);
+    case 16: return launch_pm<16>(d_col, h_col, nch, d.ncol, S, solve, recon, st, tm, batch_cw);
+    case 32: return launch_pm<32>(d_col, h_col, nch, d.ncol, S, solve, recon, st, tm, batch_cw);
+    case 64: return launch_pm<64>(d_col, h_col, nch, d.ncol, S, solve, recon, st, tm, batch_cw);
     default: return -1;
   }
 }

@@ -20,6 +20,7 @@ struct ShapeInfo {
   Dims d;
   bool pm;                        // N <= 64: the parity-major column kernels
   PlaneTiles tiles = {0, 0};
+  int col_cw = 4;                 // columns per block of the batched column launch (tuned)
 };
 
 // Launch-argument staging of one call: the pinned host arrays, their device copy and the
@@ -683,7 +684,7 @@ int group_column(const chan_batch* b, const CallGroup& g, hipStream_t st, const 
                  KernelTimer* tm) {
   if (g.envs.empty()) return 0;
   const ShapeInfo& sh = b->shapes[g.shape];
-  if (sh.pm) return launch_column_pm(sh.d, g.d_col, g.h_col, (int)g.envs.size(), S, solve, recon, st, tm);
+  if (sh.pm) return launch_column_pm(sh.d, g.d_col, g.h_col, (int)g.envs.size(), S, solve, recon, st, tm, sh.col_cw);
   for (chan_env* e : g.envs) {
     const int r = S.stage;
     int mode = WALL_OPP;
@@ -700,6 +701,7 @@ int group_column(const chan_batch* b, const CallGroup& g, hipStream_t st, const 
 }
 
 int tune_plane(chan_batch* b, int shape, const std::vector<chan_env*>& members);
+int tune_column(chan_batch* b, int shape, const std::vector<chan_env*>& members);
 
 // Adds env to the batch (its shape's tiling tuned on it if the shape is new).
 int batch_add(chan_batch* b, chan_env* e) {
@@ -766,7 +768,8 @@ int batch_build(chan_env* const* envs, int n, chan_batch** out) {
       batch_free(b);
       return fail(CHAN_EINVAL, "batch: too many channels of one shape (N_y x count > 65535)");
     }
-    const int rc = tune_plane(b, (int)sh, members);
+    int rc = tune_plane(b, (int)sh, members);
+    if (rc == CHAN_OK) rc = tune_column(b, (int)sh, members);
     if (rc != CHAN_OK) {
       batch_free(b);
       return rc;
@@ -841,6 +844,87 @@ int tune_plane(chan_batch* b, int shape, const std::vector<chan_env*>& members) 
   if (err == hipSuccess) err = sync;
   if (err != hipSuccess) return fail(CHAN_EDEVICE, "plane-pass tiling", err);
   return have ? CHAN_OK : fail(CHAN_EDEVICE, "plane-pass tiling: no candidate ran", hipGetLastError());
+}
+
+// Columns per block of the batched column launch for a shape with several channels, timed with
+// the launch the steps use most (solve and reconstruction of stage 0 in one launch) on shadow
+// arguments: the channels' own H3 and tables, but a scratch copy of the state it writes at that
+// stage (v, omega_y, the RK history, the mean profiles and the plane-pass input: the leading
+// region of every env's block, up to Z6), so that no real buffer is written.  No block shape
+// changes a result (each column's arithmetic is the same).  At most 1 GiB of scratch: a larger
+// group is timed on its first channels.  A single channel keeps its own launch; without scratch
+// memory the shape keeps 4.
+int tune_column(chan_batch* b, int shape, const std::vector<chan_env*>& members) {
+  ShapeInfo& sh = b->shapes[shape];
+  if (!sh.pm || members.size() < 2) return CHAN_OK;
+  static const int kCands[] = {4, 2};
+  const size_t lead = (size_t)((char*)members[0]->s.Z6 - (char*)members[0]->s.vS);
+  const int nm = (int)std::min(members.size(), std::max<size_t>(2, ((size_t)1 << 30) / lead));
+  char* scratch = nullptr;
+  ColChan* d_shadow = nullptr;
+  if (hipMalloc((void**)&scratch, lead * nm) != hipSuccess) {
+    (void)hipGetLastError();
+    return CHAN_OK;
+  }
+  if (hipMalloc((void**)&d_shadow, nm * sizeof(ColChan)) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(scratch);
+    return CHAN_OK;
+  }
+  std::vector<ColChan> h(nm);
+  const hipStream_t st = b->stream;
+  hipError_t err = hipSuccess;
+  for (int k = 0; k < nm && err == hipSuccess; ++k) {
+    const chan_env* e = members[k];
+    char* base = scratch + (size_t)k * lead;
+    auto relo = [&](const void* ptr) { return base + ((const char*)ptr - (const char*)e->s.vS); };
+    h[k] = e->col;
+    h[k].vS = (decltype(h[k].vS))(relo(e->s.vS));
+    h[k].oS = (decltype(h[k].oS))(relo(e->s.oS));
+    h[k].hist = (decltype(h[k].hist))(relo(e->s.hist));
+    h[k].meanS = (decltype(h[k].meanS))(relo(e->s.meanS));
+    h[k].meanH = (decltype(h[k].meanH))(relo(e->s.meanH));
+    h[k].F6 = (decltype(h[k].F6))(relo(e->s.F6));
+    err = hipMemcpyAsync(base, e->s.vS, lead, hipMemcpyDeviceToDevice, st);
+  }
+  if (err == hipSuccess) err = hipMemcpyAsync(d_shadow, h.data(), nm * sizeof(ColChan), hipMemcpyHostToDevice, st);
+  if (err == hipSuccess) err = hipStreamSynchronize(st);
+  const ColStage S = {0, 0, 1};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (err == hipSuccess) err = hipEventCreate(&e0);
+  if (err == hipSuccess) err = hipEventCreate(&e1);
+  // as for the plane tiling: ROUNDS sweeps of REPS launches after a warm-up, best sweep kept
+  constexpr int REPS = 4, ROUNDS = 3;
+  float best_ms[2] = {0.0f, 0.0f};
+  bool ran[2] = {false, false};
+  for (int round = 0; round < ROUNDS && err == hipSuccess; ++round) {
+    for (int k = 0; k < 2 && err == hipSuccess; ++k) {
+      if (launch_column_pm(sh.d, d_shadow, nullptr, nm, S, true, true, st, nullptr, kCands[k])) {
+        err = hipErrorLaunchFailure;
+        break;
+      }
+      err = hipEventRecord(e0, st);
+      for (int r = 0; r < REPS && err == hipSuccess; ++r)
+        if (launch_column_pm(sh.d, d_shadow, nullptr, nm, S, true, true, st, nullptr, kCands[k]))
+          err = hipErrorLaunchFailure;
+      if (err == hipSuccess) err = hipEventRecord(e1, st);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      if (err != hipSuccess) break;
+      if (!ran[k] || ms < best_ms[k]) best_ms[k] = ms;
+      ran[k] = true;
+    }
+  }
+  if (err == hipSuccess && ran[0] && ran[1]) sh.col_cw = best_ms[1] < best_ms[0] ? kCands[1] : kCands[0];
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  const hipError_t sync = hipStreamSynchronize(st);
+  (void)hipFree(d_shadow);
+  (void)hipFree(scratch);
+  if (err == hipSuccess) err = sync;
+  if (err != hipSuccess) return fail(CHAN_EDEVICE, "column block tuning", err);
+  return CHAN_OK;
 }
 
 // Queues the launches of one env step of the call's envs (already staged), then the status
@@ -1606,6 +1690,22 @@ void chan_batch_destroy(chan_batch* b) { batch_free(b); }
 
 int32_t chan_batch_size(const chan_batch* b) { return b ? (int32_t)b->envs.size() : 0; }
 
+int chan_batch_tuning(const chan_batch* b, int32_t max_shapes, int32_t* out) {
+  if (!b || (max_shapes > 0 && !out)) return CHAN_EINVAL;
+  const int n = (int)b->shapes.size();
+  for (int k = 0; k < n && k < max_shapes; ++k) {
+    const ShapeInfo& sh = b->shapes[k];
+    int32_t* r = out + 6 * k;
+    r[0] = sh.d.nx;
+    r[1] = sh.d.ny;
+    r[2] = sh.d.nz;
+    r[3] = sh.tiles.PB;
+    r[4] = sh.tiles.P;
+    r[5] = sh.pm ? sh.col_cw : 0;
+  }
+  return n;
+}
+
 int chan_batch_set_timing(chan_batch* b, int32_t enable) {
   if (!b) return CHAN_EINVAL;
   return batch_set_timing(b, enable);
@@ -1810,7 +1910,7 @@ __global__ void k_state_out(StaticIO A) {
 
 // Column pass of the single channel e (the general kernel for N > 64 or when forced).
 int static_column(chan_env* e, const ColChan& h, const ColStage& S, bool solve, bool recon, hipStream_t st) {
-  if (uses_pm(e)) return launch_column_pm(e->d, nullptr, &h, 1, S, solve, recon, st, nullptr);
+  if (uses_pm(e)) return launch_column_pm(e->d, nullptr, &h, 1, S, solve, recon, st, nullptr, 4);
   const int r = S.stage;
   int mode = WALL_OPP;
   double s = 0.0;

@@ -252,3 +252,21 @@ def test_bench_batch_members_match_oracle():
     batch.close()
     for e in envs:
         e.close()
+
+
+def test_batch_tuning_reported():
+    """The tuned launch shapes of the mix: one record per grid shape in first-seen order; the
+    parity-major shapes with several channels get 2 or 4 columns per block, the general kernel 0;
+    the mix's bitwise equality with the channels alone (above) holds whichever was picked."""
+    import paper_2301_09889_amd.binding as b
+    envs = make_envs(MIX)
+    batch = b.ChanBatch(envs)
+    t = b.chan_batch_tuning(batch.handle)
+    print("  tuning:", t, flush=True)
+    assert [(r["nx"], r["ny"], r["nz"]) for r in t] == [(16, 65, 16), (32, 65, 32), (8, 33, 8), (8, 97, 8)]
+    assert t[0]["columns_per_block"] in (2, 4) and t[1]["columns_per_block"] in (2, 4)
+    assert t[2]["columns_per_block"] == 4 and t[3]["columns_per_block"] == 0
+    assert all(r["z_pencils_per_block"] > 0 and r["x_pairs_per_block"] > 0 for r in t)
+    batch.close()
+    for e in envs:
+        e.close()
