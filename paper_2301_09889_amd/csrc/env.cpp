@@ -1,6 +1,8 @@
 // C ABI of the channel-flow environment: validation, device allocation, the stage
 // loop and the state exchange.  All numerical work of a step is queued as HIP
 // kernels (kernels.hip); the host only sequences launches.
+#include <dlfcn.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -927,6 +929,38 @@ int tune_column(chan_batch* b, int shape, const std::vector<chan_env*>& members)
   return CHAN_OK;
 }
 
+// Named host ranges (roctx) around the launches of each env step and RK3 stage, so that a marker
+// trace (rocprofv3 --marker-trace) shows where the host queued them.  The roctx library is
+// opened at first use; without it the ranges are no-ops.
+struct Roctx {
+  int (*push)(const char*) = nullptr;
+  int (*pop)() = nullptr;
+  Roctx() {
+    void* h = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_LOCAL);
+    if (!h) return;
+    push = reinterpret_cast<int (*)(const char*)>(dlsym(h, "roctxRangePushA"));
+    pop = reinterpret_cast<int (*)()>(dlsym(h, "roctxRangePop"));
+    if (!push || !pop) push = nullptr, pop = nullptr;
+  }
+};
+
+const Roctx& roctx() {
+  static const Roctx r;
+  return r;
+}
+
+struct RoctxRange {
+  const bool on;
+  explicit RoctxRange(const char* msg) : on(roctx().push != nullptr) {
+    if (on) roctx().push(msg);
+  }
+  ~RoctxRange() {
+    if (on) roctx().pop();
+  }
+  RoctxRange(const RoctxRange&) = delete;
+  RoctxRange& operator=(const RoctxRange&) = delete;
+};
+
 // Queues the launches of one env step of the call's envs (already staged), then the status
 // read-back and (record_done) the completion event.
 int launch_step(chan_call* c, bool any_action, KernelTimer* tm, double* const* obs, bool record_done = true) {
@@ -935,6 +969,7 @@ int launch_step(chan_call* c, bool any_action, KernelTimer* tm, double* const* o
   const int na = (int)c->envs.size();
   const int n_substeps = c->n_sub;
   StepChan* ds = dev_step(c);
+  const RoctxRange step_range(record_done ? "chan env step" : "chan env step (captured)");
   if (launch_begin_step(ds, na, st, tm)) return fail(CHAN_EDEVICE, "launch begin_step", hipGetLastError());
   if (any_action && launch_ingest(ds, na, c->max_nx, c->max_nz, c->max_nkx, st, tm))
     return fail(CHAN_EDEVICE, "launch ingest", hipGetLastError());
@@ -944,6 +979,8 @@ int launch_step(chan_call* c, bool any_action, KernelTimer* tm, double* const* o
       // below, which also serves set_state (bitwise-identical resume).
       const bool last = (m == n_substeps - 1) && (r == 2);
       const ColStage S = {r, m, n_substeps};
+      static const char* const kStageName[3] = {"RK3 stage 1", "RK3 stage 2", "RK3 stage 3"};
+      const RoctxRange stage_range(kStageName[r]);
       for (const CallGroup& g : c->groups) {
         const ShapeInfo& sh = b->shapes[g.shape];
         if (launch_plane_pass(sh.d, g.d_plane, (int)g.envs.size(), sh.tiles, st, tm))
