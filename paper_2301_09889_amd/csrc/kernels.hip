@@ -206,6 +206,76 @@ __device__ __forceinline__ void cheb_d1_reg(const cplx* x, cplx* out, int lane) 
   }
 }
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// DCT-I matvecs of F folded vectors on the matrix cores (N/2 a multiple of 16).  After the
+// even/odd fold, even outputs 2i take the S values X[f][0..N/2] and odd outputs 2i+1 the D
+// values X[f][N-k], k < N/2 (the middle term's cosine vanishes for odd outputs), with the
+// cosines cosk[k (N+1) + e] of both transforms.  Each is a product of a (N/2 x terms) cosine
+// matrix and a (terms x 2F) matrix of the fields' real and imaginary parts, done as 16 x 16
+// output tiles of v_mfma_f64_16x16x4_f64 (A: 16 outputs x 4 terms, B: 4 terms x 16 columns):
+// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds D[4r + l / 16][l % 16],
+// r < 4.  The 2F <= 16 columns are (field, re/im) pairs; lanes of unused columns supply zeros.
+// The results are written back over X (after every lane's reads) and returned in the lanes'
+// element order, as the loops below do; top: the last output (a_N or the node N value).
+template <int N, int F>
+__device__ __forceinline__ void dct_mfma(cplx* const* X, const double* __restrict__ cosk, int lane,
+                                         cplx (*out)[CP<N>::NS], const cplx* top, double sc0, double sc) {
+  static_assert((N / 2) % 16 == 0 && 2 * F <= 16, "matrix-core DCT shape");
+  constexpr int H = N / 2, T = H / 16, KE = (H + 4) / 4, KO = H / 4;
+  const int col = lane & 15, kq = lane >> 4;
+  const int f = col >> 1, part = col & 1;
+  double* xf = nullptr;
+#pragma unroll
+  for (int g = 0; g < F; ++g)
+    if (g == f) xf = reinterpret_cast<double*>(X[g]);
+  dbl4 de[T], dd[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) de[t] = dd[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+  for (int ks = 0; ks < KE; ++ks) {
+    const int k = 4 * ks + kq;
+    const bool in = k <= H;
+    const double b = (xf && in) ? xf[2 * k + part] : 0.0;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const double a = in ? cosk[k * (N + 1) + 2 * (16 * t + col)] : 0.0;
+      de[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, de[t], 0, 0, 0);
+    }
+  }
+#pragma unroll 2
+  for (int ks = 0; ks < KO; ++ks) {
+    const int k = 4 * ks + kq;
+    const double b = xf ? xf[2 * (N - k) + part] : 0.0;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const double a = cosk[k * (N + 1) + 2 * (16 * t + col) + 1];
+      dd[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, dd[t], 0, 0, 0);
+    }
+  }
+  wave_sync();
+  if (xf) {
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * t + 4 * r + kq;
+        xf[2 * (2 * i) + part] = de[t][r];
+        xf[2 * (2 * i + 1) + part] = dd[t][r];
+      }
+  }
+  wave_sync();
+#pragma unroll
+  for (int s = 0; s < CP<N>::NS; ++s) {
+    const int e = lane + 64 * s;
+#pragma unroll
+    for (int g = 0; g < F; ++g) out[g][s] = (e < N) ? cscale(X[g][e], e == 0 ? sc0 : sc) : cz();
+  }
+#pragma unroll
+  for (int g = 0; g < F; ++g)
+    if (lane == (N % 64)) out[g][N / 64] = top[g];
+}
+
 // Forward DCT-I of F nodal vectors X[f][0..N] (overwritten by the even/odd fold):
 // a_n = 2/(N cb_n) sum_j f_j cos(pi n j/N)/cb_j.  Result in out[f][slot].
 template <int N, int F>
@@ -225,6 +295,18 @@ __device__ __forceinline__ void dct_forward(cplx* const* X, const double* __rest
     }
   }
   wave_sync();
+  if constexpr (H % 16 == 0 && 2 * F <= 16) {
+    // a_N = (1/N) sum_{j <= N/2} (-1)^j S_j, from the folded values before they are replaced
+    cplx top[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      cplx part = cz();
+      for (int j = lane; j <= H; j += 64) part = caxpy(part, (j & 1) ? -1.0 : 1.0, X[f][j]);
+      top[f] = cscale(wave_sum(part), 1.0 / N);
+    }
+    dct_mfma<N, F>(X, cosk, lane, out, top, 1.0 / N, 2.0 / N);
+    return;
+  }
 #pragma unroll
   for (int s = 0; s < CP<N>::NS; ++s) {
     const int e = lane + 64 * s;
@@ -270,6 +352,18 @@ __device__ __forceinline__ void dct_inverse(cplx* const* X, const double* __rest
     }
   }
   wave_sync();
+  if constexpr (H % 16 == 0 && 2 * F <= 16) {
+    // f_N = sum_{n <= N/2} (-1)^n S_n, from the folded values before they are replaced
+    cplx top[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      cplx part = cz();
+      for (int n = lane; n <= H; n += 64) part = caxpy(part, (n & 1) ? -1.0 : 1.0, X[f][n]);
+      top[f] = wave_sum(part);
+    }
+    dct_mfma<N, F>(X, cosk, lane, out, top, 1.0, 1.0);
+    return;
+  }
 #pragma unroll
   for (int s = 0; s < CP<N>::NS; ++s) {
     const int e = lane + 64 * s;
