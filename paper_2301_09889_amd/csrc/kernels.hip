@@ -136,7 +136,11 @@ struct CP {
   static constexpr int OPSZ = 4 * ML + 2;
   static constexpr int NB = 8;               // complex work vectors per wave
   static constexpr int NYP = NY + 1;
-  static constexpr int WAVE_DOUBLES = NB * NYP * 2 + 2 * OPSZ + 32;
+  // LDS per wave: the work vectors and 32 doubles of small scalars.  The operator records are
+  // read from the table in global memory where they are used: staged in LDS as well, a wave took
+  // 16 KB at N = 96 and five two-wave blocks filled a CU (2.5 waves per SIMD); without them six
+  // fit (three per SIMD, the register limit).
+  static constexpr int WAVE_DOUBLES = NB * NYP * 2 + 32;
 };
 
 // wavefronts (columns) per block: four for N <= 64, two above (LDS per block < 64 KiB)
@@ -543,8 +547,8 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
   cplx* B[P::NB];
 #pragma unroll
   for (int k = 0; k < P::NB; ++k) B[k] = reinterpret_cast<cplx*>(wb + (size_t)k * P::NYP * 2);
-  double* TAB = wb + (size_t)P::NB * P::NYP * 2;
-  cplx* SC = reinterpret_cast<cplx*>(TAB + 2 * P::OPSZ);  // small scalars
+  const double* TAB = nullptr;                                            // operator record
+  cplx* SC = reinterpret_cast<cplx*>(wb + (size_t)P::NB * P::NYP * 2);  // small scalars
 
   const double al = A.alpha[p], be = A.beta[q];
   const double k2 = al * al + be * be;
@@ -665,11 +669,8 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
           B[1][e] = ro;
         }
       }
-      // operator record of D^2 - lam for this column and stage -> LDS
-      {
-        const double* src = A.optab + ((size_t)crec * NOPS + r) * 2 * P::OPSZ;
-        for (int t = lane; t < 2 * P::OPSZ; t += 64) TAB[t] = src[t];
-      }
+      // operator record of D^2 - lam for this column and stage (read where used)
+      TAB = A.optab + ((size_t)crec * NOPS + r) * 2 * P::OPSZ;
       wave_sync();
       for (int e = lane; e <= N; e += 64) {
         B[2][e] = tau_rows<N>(B[0], A.rc, e);
@@ -718,10 +719,7 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
         const cplx o = A.vw_old[c], nn = A.vw_new[c];
         vw = caxpy(o, A.s_ramp, csub(nn, o));
       }
-      {
-        const double* src = A.optab + ((size_t)crec * NOPS + 3) * 2 * P::OPSZ;
-        for (int t = lane; t < 2 * P::OPSZ; t += 64) TAB[t] = src[t];
-      }
+      TAB = A.optab + ((size_t)crec * NOPS + 3) * 2 * P::OPSZ;
       for (int e = lane; e <= N; e += 64) B[2][e] = tau_rows<N>(B[6], A.rc, e);
       wave_sync();
       {
@@ -809,10 +807,7 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
         }
       }
       for (int e = lane; e <= N; e += 64) B[4][e] = make_double2(A.meanS[e], A.meanS[NY + e]);
-      {
-        const double* src = A.optab + ((size_t)crec * NOPS + r) * 2 * P::OPSZ;
-        for (int t = lane; t < 2 * P::OPSZ; t += 64) TAB[t] = src[t];
-      }
+      TAB = A.optab + ((size_t)crec * NOPS + r) * 2 * P::OPSZ;
       wave_sync();
       cplx xm[NS], dm1[NS], dm2[NS];
 #pragma unroll
@@ -1082,8 +1077,8 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_pressure_gen(PressGenArgs A) 
   cplx* B[P::NB];
 #pragma unroll
   for (int k = 0; k < P::NB; ++k) B[k] = reinterpret_cast<cplx*>(wb + (size_t)k * P::NYP * 2);
-  double* TAB = wb + (size_t)P::NB * P::NYP * 2;
-  cplx* SC = reinterpret_cast<cplx*>(TAB + 2 * P::OPSZ);
+  const double* TAB = nullptr;                                            // operator record
+  cplx* SC = reinterpret_cast<cplx*>(wb + (size_t)P::NB * P::NYP * 2);  // small scalars
   const double al = A.alpha[p], be = A.beta[q];
   const double als = al * A.ysi, bes = be * A.ysi;
   const double k2s = als * als + bes * bes;
@@ -1120,10 +1115,7 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_pressure_gen(PressGenArgs A) 
       B[3][e] = cscale(cadd(dH2s[s], ab), A.ysi);
     }
   }
-  {
-    const double* src = A.optab + ((size_t)crec * NOPS + 3) * 2 * P::OPSZ;
-    for (int t = lane; t < 2 * P::OPSZ; t += 64) TAB[t] = src[t];
-  }
+  TAB = A.optab + ((size_t)crec * NOPS + 3) * 2 * P::OPSZ;
   wave_sync();
   for (int e = lane; e <= N; e += 64) B[4][e] = tau_rows<N>(B[3], A.rc, e);
   wave_sync();
