@@ -171,40 +171,64 @@ struct ColArgs {
   int* status;
 };
 
+// A cross-lane result used only under a per-lane condition: the empty volatile asm keeps the
+// permlane or DPP move that made it out of the conditional code, where lanes switched off by
+// EXEC would not supply their values (the compiler otherwise sinks it into one arm of a select).
+__device__ __forceinline__ double pin(double x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
 // D on coefficients held in registers, element e = lane + 64 s in slot s (zero above N):
 //   b_e = (2/c_e) sum_{p > e, p + e odd} p a_p = (2/c_e) W(e + 1),  W(e) = sum_{k >= 0} y_{e+2k},
-// y_p = p a_p.  W is a stride-2 suffix sum: a five-step scan within each slot (offsets 2 .. 32
-// keep the parity), plus the same-parity totals of the higher slots; b_N = 0.  Wave-uniform.
+// y_p = p a_p.  W is a stride-2 suffix sum, done without LDS: within each row of 16 lanes by DPP
+// row shifts of 2, 4 and 8 (each lane keeps its parity); then the same-parity totals of the rows
+// above in the slot (each row's total broadcast in its row and exchanged by permlane swaps: row 0
+// adds T1 + (T2 + T3), row 1 T2 + T3, row 2 T3); then those of the higher slots (lanes 0 and 1
+// of a slot hold its totals); b_e takes W of lane e + 1 by the wave-wide one-lane shift.
+// b_N = 0.  Wave-uniform.
 template <int N>
 __device__ __forceinline__ void cheb_d1_reg(const cplx* x, cplx* out, int lane) {
   constexpr int NS = CP<N>::NS;
+  const bool odd = lane & 1;
+  const bool even_row = ((lane >> 4) & 1) == 0, low = lane < 32;
   cplx w[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int e = lane + 64 * s;
-    w[s] = (e <= N) ? cscale(x[s], (double)e) : cz();
+    cplx v = (e <= N) ? cscale(x[s], (double)e) : cz();
+    v = cadd(v, cmov<DPP_ROW_SHL + 2>(v));
+    v = cadd(v, cmov<DPP_ROW_SHL + 4>(v));
+    v = cadd(v, cmov<DPP_ROW_SHL + 8>(v));
+    const double t0x = pin(dmov<DPP_ROW_BCAST + 0>(v.x)), t0y = pin(dmov<DPP_ROW_BCAST + 0>(v.y));
+    const double t1x = pin(dmov<DPP_ROW_BCAST + 1>(v.x)), t1y = pin(dmov<DPP_ROW_BCAST + 1>(v.y));
+    const cplx T = make_double2(odd ? t1x : t0x, odd ? t1y : t0y);  // this parity's total of the row
+    const Pair rx = row_swap(T.x, T.x), ry = row_swap(T.y, T.y);  // a: T0 T0 T2 T2, b: T1 T1 T3 T3
+    const double px = rx.a + rx.b, py = ry.a + ry.b;   // T0 + T1 (rows 0, 1), T2 + T3 (rows 2, 3)
+    const double nx = pin(rx.b), ny = pin(ry.b);
+    const double hx = pin(half_swap(px, px).b), hy = pin(half_swap(py, py).b);  // T2 + T3 everywhere
+    const cplx carry = make_double2((even_row ? nx : 0.0) + (low ? hx : 0.0), (even_row ? ny : 0.0) + (low ? hy : 0.0));
+    w[s] = cadd(v, carry);
   }
-#pragma unroll
-  for (int d = 2; d < 64; d <<= 1) {
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      const double nx = __shfl_down(w[s].x, d, 64), ny = __shfl_down(w[s].y, d, 64);
-      if (lane + d < 64) w[s] = make_double2(w[s].x + nx, w[s].y + ny);
-    }
-  }
-  cplx carry = cz();
+  // every cross-lane value below is read by all lanes before any per-lane choice
+  cplx up = cz();
 #pragma unroll
   for (int s = NS - 1; s >= 0; --s) {
-    const cplx tot = make_double2(__shfl(w[s].x, lane & 1, 64), __shfl(w[s].y, lane & 1, 64));
-    w[s] = cadd(w[s], carry);
-    carry = cadd(carry, tot);
+    const double ex = pin(readlane_d(w[s].x, 0)), ey = pin(readlane_d(w[s].y, 0));
+    const double ox = pin(readlane_d(w[s].x, 1)), oy = pin(readlane_d(w[s].y, 1));
+    const cplx tot = make_double2(odd ? ox : ex, odd ? oy : ey);
+    w[s] = cadd(w[s], up);
+    up = cadd(up, tot);
   }
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    const double zx = __shfl_down(w[s].x, 1, 64), zy = __shfl_down(w[s].y, 1, 64);
-    cplx next = cz();
-    if (s + 1 < NS) next = make_double2(__shfl(w[s + 1 < NS ? s + 1 : s].x, 0, 64), __shfl(w[s + 1 < NS ? s + 1 : s].y, 0, 64));
-    const cplx z = (lane < 63) ? make_double2(zx, zy) : next;
+    const double zx = pin(dmov<DPP_WAVE_SHL1>(w[s].x)), zy = pin(dmov<DPP_WAVE_SHL1>(w[s].y));
+    double nx = 0.0, ny = 0.0;
+    if (s + 1 < NS) {
+      nx = pin(readlane_d(w[s + 1 < NS ? s + 1 : s].x, 0));
+      ny = pin(readlane_d(w[s + 1 < NS ? s + 1 : s].y, 0));
+    }
+    const cplx z = make_double2(lane == 63 ? nx : zx, lane == 63 ? ny : zy);
     const int e = lane + 64 * s;
     out[s] = (e < N) ? cscale(z, e == 0 ? 1.0 : 2.0) : cz();
   }
@@ -408,12 +432,96 @@ __device__ __forceinline__ cplx tau_rows(const cplx* f, const double* __restrict
   return r;
 }
 
+// x moved by the DPP pattern CTRL; a lane whose source lies outside its row keeps id (the
+// identity of the composition being scanned).
+template <int CTRL>
+__device__ __forceinline__ double dmov_id(double x, double id) {
+  return __builtin_amdgcn_update_dpp(id, x, CTRL, 0xF, 0xF, false);
+}
+
+// Affine compositions over the 64 lanes, without LDS.  Suffix: lane l holds (a_l, b_l) with
+// e_l = a_l + b_l e_{l+1} (e_64 = 0); returns e_l for every a[k] (one multiplier chain b shared
+// by the K right-hand sides).  Prefix: E_l = c_l + g_l E_{l-1} (E_{-1} = 0).  Each takes four
+// DPP steps within the rows of 16 lanes (a source outside the row reads the identity (0, 1)),
+// then the composition with the rows further along in the scan's direction: each row's
+// composite is broadcast in its row and exchanged by permlane swaps (suffix: row 2 takes row
+// 3's, row 1 the composite of rows 2-3, row 0 that of rows 1-3; prefix mirrored).
+template <int K>
+__device__ __forceinline__ void affine_suffix(cplx* a, double b, int lane) {
+  const int row = lane >> 4;
+  const bool even_row = (row & 1) == 0, low = lane < 32;
+  auto step = [&](auto dc) {
+    constexpr int D = decltype(dc)::value;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      a[k] = caxpy(a[k], b, make_double2(dmov_id<DPP_ROW_SHL + D>(a[k].x, 0.0), dmov_id<DPP_ROW_SHL + D>(a[k].y, 0.0)));
+    b *= dmov_id<DPP_ROW_SHL + D>(b, 1.0);
+  };
+  step(std::integral_constant<int, 1>{});
+  step(std::integral_constant<int, 2>{});
+  step(std::integral_constant<int, 4>{});
+  step(std::integral_constant<int, 8>{});
+  const double RB = dmov<DPP_ROW_BCAST + 0>(b);
+  const double foB = pin(row_swap(RB, RB).b);  // rows 0, 2: the next row's multiplier
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    cplx carry;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const double x = c ? a[k].y : a[k].x;
+      const double RA = dmov<DPP_ROW_BCAST + 0>(x);
+      const double foA = pin(row_swap(RA, RA).b);    // rows 0, 2: the next row's composite
+      const double V = fma(RB, foA, RA);              // row 2: e at the first lane of row 2
+      const double W = row_swap(V, V).a;              // rows 2, 3: row 2's V
+      const double X = pin(cross_halves(W, W, low));  // rows 0, 1 take it from rows 2, 3
+      const double cv = row == 3 ? 0.0 : row == 2 ? foA : row == 1 ? X : fma(foB, X, foA);
+      if (c) carry.y = cv; else carry.x = cv;
+    }
+    a[k] = caxpy(a[k], b, carry);
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void affine_prefix(cplx* c, double g, int lane) {
+  const int row = lane >> 4;
+  const bool even_row = (row & 1) == 0, low = lane < 32;
+  auto step = [&](auto dc) {
+    constexpr int D = decltype(dc)::value;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      c[k] = caxpy(c[k], g, make_double2(dmov_id<DPP_ROW_SHR + D>(c[k].x, 0.0), dmov_id<DPP_ROW_SHR + D>(c[k].y, 0.0)));
+    g *= dmov_id<DPP_ROW_SHR + D>(g, 1.0);
+  };
+  step(std::integral_constant<int, 1>{});
+  step(std::integral_constant<int, 2>{});
+  step(std::integral_constant<int, 4>{});
+  step(std::integral_constant<int, 8>{});
+  const double RG = dmov<DPP_ROW_BCAST + 15>(g);
+  const double feG = pin(row_swap(RG, RG).a);  // rows 1, 3: the previous row's multiplier
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    cplx carry;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const double x = q ? c[k].y : c[k].x;
+      const double RC = dmov<DPP_ROW_BCAST + 15>(x);
+      const double feC = pin(row_swap(RC, RC).a);    // rows 1, 3: the previous row's composite
+      const double V = fma(RG, feC, RC);              // row 1: E at the last lane of row 1
+      const double W = row_swap(V, V).b;              // rows 0, 1: row 1's V
+      const double X = pin(cross_halves(W, W, low));  // rows 2, 3 take it from rows 0, 1
+      const double cv = row == 0 ? 0.0 : row == 1 ? feC : row == 2 ? X : fma(feG, X, feC);
+      if (q) carry.y = cv; else carry.x = cv;
+    }
+    c[k] = caxpy(c[k], g, carry);
+  }
+}
+
 // Even/odd elimination of both parities of K tau systems that share one operator record
 // {w, u, f, F, 1/sum F} per parity, on the whole wavefront: lane l takes index i = l + 1
-// (i <= m = (N - s)/2 <= 64).  The bottom-up
-// recurrence e_i = w_i R_{2i+s} - u_i e_{i+1} (e_{m+1} = 0) is the affine suffix composition of
-// (a_i, b_i) = (w_i R_{2i+s}, -u_i), the top-down one E_i = e_i + f_i E_{i-1} (E_0 = 0) the
-// affine prefix composition of (e_i, f_i); each is a six-step Hillis-Steele scan over lanes.
+// (i <= m = (N - s)/2 <= 64).  The bottom-up recurrence e_i = w_i R_{2i+s} - u_i e_{i+1}
+// (e_{m+1} = 0) is the affine suffix composition of (w_i R_{2i+s}, -u_i), the top-down one
+// E_i = e_i + f_i E_{i-1} (E_0 = 0) the affine prefix composition of (e_i, f_i); lanes past m
+// hold (0, 0), which ends the chains there.
 // Writes E_i to E[k][2i+s] and x0[2k+s] = (g[2k+s] - sum_i E_i) / sum F_i.
 template <int N, int K>
 __device__ __forceinline__ void tau_chain_wave(cplx* const* R, const double* TAB, const cplx* g, cplx* const* E,
@@ -429,46 +537,10 @@ __device__ __forceinline__ void tau_chain_wave(cplx* const* R, const double* TAB
     const bool act = i <= m;
     const double w = act ? tab[i] : 0.0, u = act ? tab[ML + i] : 0.0, f = act ? tab[2 * ML + i] : 0.0;
     cplx a[K];
-    double b[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      a[k] = act ? cscale(R[k][2 * i + s], w) : cz();
-      b[k] = act ? -u : 0.0;
-    }
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const bool in = i + d <= m;
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const double ax = __shfl_down(a[k].x, d, 64), ay = __shfl_down(a[k].y, d, 64);
-        const double bn = __shfl_down(b[k], d, 64);
-        if (in) {
-          a[k] = make_double2(fma(b[k], ax, a[k].x), fma(b[k], ay, a[k].y));
-          b[k] *= bn;
-        } else {
-          b[k] = 0.0;
-        }
-      }
-    }
-    // a[k] = e_i; now the prefix scan E_i = e_i + f_i E_{i-1}
-    double gg[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) gg[k] = act ? f : 0.0;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const bool in = i - d >= 1;
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const double cx = __shfl_up(a[k].x, d, 64), cy = __shfl_up(a[k].y, d, 64);
-        const double gn = __shfl_up(gg[k], d, 64);
-        if (in) {
-          a[k] = make_double2(fma(gg[k], cx, a[k].x), fma(gg[k], cy, a[k].y));
-          gg[k] *= gn;
-        } else {
-          gg[k] = 0.0;
-        }
-      }
-    }
+    for (int k = 0; k < K; ++k) a[k] = act ? cscale(R[k][2 * i + s], w) : cz();
+    affine_suffix<K>(a, act ? -u : 0.0, lane);   // a[k] = e_i
+    affine_prefix<K>(a, act ? f : 0.0, lane);    // a[k] = E_i
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       if (act) E[k][2 * i + s] = a[k];
@@ -478,7 +550,6 @@ __device__ __forceinline__ void tau_chain_wave(cplx* const* R, const double* TAB
   }
 }
 
-// Value of element e of a tau solution: x_e = E_e + F_{e/2} x0_{parity(e)}.
 template <int N>
 __device__ __forceinline__ cplx tau_value(const cplx* E, const double* TAB, const cplx* x0, int e) {
   constexpr int ML = N / 2 + 1;
