@@ -63,27 +63,6 @@ __device__ __forceinline__ void for_16(Fn&& fn) {
   for_each_k(fn, std::make_integer_sequence<int, 16>{});
 }
 
-// Sums whose every step adds two values that are already identical within their groups, so
-// that every lane of the group receives the bitwise-same result.
-__device__ __forceinline__ double row_sum(double x) {
-  x += dmov<DPP_QUAD_XOR1>(x);
-  x += dmov<DPP_QUAD_XOR2>(x);
-  x += dmov<DPP_ROW_HALF_MIRROR>(x);
-  x += dmov<DPP_ROW_MIRROR>(x);
-  return x;
-}
-__device__ __forceinline__ double half_sum(double x) {
-  const Pair r = row_swap(row_sum(x), row_sum(x));
-  return r.a + r.b;  // (row 0 + row 1) or (row 2 + row 3), in that order on every lane
-}
-__device__ __forceinline__ cplx half_sum(cplx v) { return make_double2(half_sum(v.x), half_sum(v.y)); }
-__device__ __forceinline__ double lane_sum(double x) {
-  const double h = half_sum(x);
-  const Pair r = half_swap(h, h);
-  return r.a + r.b;  // low half + high half on every lane
-}
-__device__ __forceinline__ cplx lane_sum(cplx v) { return make_double2(lane_sum(v.x), lane_sum(v.y)); }
-
 // Parity-major bookkeeping of one lane.
 template <int N>
 struct Lane {

@@ -91,6 +91,40 @@ __device__ __forceinline__ cplx readlane_c(cplx v, int l) { return make_double2(
 __device__ __forceinline__ cplx shfl_c(cplx v, int src) {
   return make_double2(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
 }
+// A cross-lane result used only under a per-lane condition: the empty volatile asm keeps the
+// permlane or DPP move that made it out of the conditional code, where lanes switched off by
+// EXEC would not supply their values (the compiler otherwise sinks it into one arm of a select).
+__device__ __forceinline__ double pin(double x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+// Sums whose every step adds two values that are already identical within their groups, so
+// that every lane of the group receives the bitwise-same result.
+__device__ __forceinline__ double row_sum(double x) {
+  x += dmov<DPP_QUAD_XOR1>(x);
+  x += dmov<DPP_QUAD_XOR2>(x);
+  x += dmov<DPP_ROW_HALF_MIRROR>(x);
+  x += dmov<DPP_ROW_MIRROR>(x);
+  return x;
+}
+__device__ __forceinline__ double half_sum(double x) {
+  const Pair r = row_swap(row_sum(x), row_sum(x));
+  return r.a + r.b;  // (row 0 + row 1) or (row 2 + row 3), in that order on every lane
+}
+__device__ __forceinline__ cplx half_sum(cplx v) { return make_double2(half_sum(v.x), half_sum(v.y)); }
+__device__ __forceinline__ double lane_sum(double x) {
+  const double h = half_sum(x);
+  const Pair r = half_swap(h, h);
+  return r.a + r.b;  // low half + high half on every lane
+}
+__device__ __forceinline__ cplx lane_sum(cplx v) { return make_double2(lane_sum(v.x), lane_sum(v.y)); }
+
+// Sum over the 64 lanes (all active); every lane receives the bitwise-same total.  Pinned, so
+// that a total used by one lane only is still formed with every lane taking part.
+__device__ __forceinline__ double wave_sum(double v) { return pin(lane_sum(v)); }
+__device__ __forceinline__ cplx wave_sum(cplx v) { return make_double2(wave_sum(v.x), wave_sum(v.y)); }
+
 // Workgroups go to the eight XCDs in turn (workgroup b to XCD b mod 8), each XCD with its own
 // L2.  Logical block of workgroup b of G: every XCD takes one contiguous range, so neighbouring
 // columns, which share the cache lines of the node-major fields, meet in one L2.  A bijection
@@ -107,13 +141,6 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Butterfly sum over the 64 lanes; every lane receives the bitwise-same total.
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-HD cplx wave_sum(cplx v) { return make_double2(wave_sum(v.x), wave_sum(v.y)); }
 
 // cos and sin of 2 pi m / 48, m = 0..47: every root of unity the small DFTs below use
 // (orders 2, 3, 4, 6, 8, 12, 16, 24, 48) is one of these.

@@ -171,14 +171,6 @@ struct ColArgs {
   int* status;
 };
 
-// A cross-lane result used only under a per-lane condition: the empty volatile asm keeps the
-// permlane or DPP move that made it out of the conditional code, where lanes switched off by
-// EXEC would not supply their values (the compiler otherwise sinks it into one arm of a select).
-__device__ __forceinline__ double pin(double x) {
-  asm volatile("" : "+v"(x));
-  return x;
-}
-
 // D on coefficients held in registers, element e = lane + 64 s in slot s (zero above N):
 //   b_e = (2/c_e) sum_{p > e, p + e odd} p a_p = (2/c_e) W(e + 1),  W(e) = sum_{k >= 0} y_{e+2k},
 // y_p = p a_p.  W is a stride-2 suffix sum, done without LDS: within each row of 16 lanes by DPP
