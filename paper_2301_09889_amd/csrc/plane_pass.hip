@@ -49,11 +49,17 @@ __device__ __forceinline__ cplx twiddle(cplx a, const cplx* tw, int m) {
 }
 
 
+// Threads of a z-kernel block: PB pencils (at most 32) times the first pass's length A.  The
+// launch bound states that maximum, so that the compiler may give the long transforms more than
+// the 128 registers a 1024-thread bound allows (k_zinv2<192> spilled 52 of them under it).
+template <int L>
+constexpr int zkernel_threads() { return ((32 * FftPlan<L>::A + 63) / 64) * 64; }
+
 // ---------------------------------------------------------------------------
 // z inverse: block (p chunk, field, node); F6 -> Z6.
 // ---------------------------------------------------------------------------
 template <int L>
-__global__ __launch_bounds__(1024) void k_zinv2(const PlaneChan* __restrict__ chans, int ny, int PB) {
+__global__ __launch_bounds__(zkernel_threads<L>()) void k_zinv2(const PlaneChan* __restrict__ chans, int ny, int PB) {
   constexpr int FA = FftPlan<L>::A, FB = FftPlan<L>::B;
   constexpr int LP = FftLds<L>::LS, AP = FftLds<L>::AP;
   extern __shared__ double dyn_lds[];
@@ -102,7 +108,7 @@ __global__ __launch_bounds__(1024) void k_zinv2(const PlaneChan* __restrict__ ch
 // z forward: block (p chunk, product, node); W3 -> H3.
 // ---------------------------------------------------------------------------
 template <int L>
-__global__ __launch_bounds__(1024) void k_zfwd2(const PlaneChan* __restrict__ chans, int ny, int PB) {
+__global__ __launch_bounds__(zkernel_threads<L>()) void k_zfwd2(const PlaneChan* __restrict__ chans, int ny, int PB) {
   constexpr int FA = FftPlan<L>::A, FB = FftPlan<L>::B;
   constexpr int LP = FftLds<L>::LS, AP = FftLds<L>::AP;
   extern __shared__ double dyn_lds[];
@@ -585,6 +591,7 @@ static int launch_plane2(const Dims& d, const PlaneChan* chans, int nch, const P
   const int PB = t.PB, P = t.P;
   const int pairs = MZ / 2;
   if (PB < 1 || PB > d.nkx || P < 1 || pairs % P != 0 || xrow_threads<MX>(P) > 1024) return -1;
+  if (((PB * FftPlan<MZ>::A + 63) / 64) * 64 > zkernel_threads<MZ>()) return -1;  // the z kernels' bound
   const int nblk = (d.nkx + PB - 1) / PB;
   const size_t shz = (size_t)(MZ + (size_t)PB * FftLds<MZ>::LS) * sizeof(cplx);
   const size_t shf = (size_t)(2 * MZ + (size_t)PB * FftLds<MZ>::LS) * sizeof(cplx);
