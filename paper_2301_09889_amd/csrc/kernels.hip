@@ -1460,7 +1460,7 @@ int launch_ingest(const StepChan* d_step, int nch, int max_nx, int max_nz, int m
 // Source spectra are [p][q].  Columns: inverse FFT along z.
 __global__ void k_out_cols(const StepChan* __restrict__ chans) {
   extern __shared__ double dyn_lds[];
-  const StepChan C = chans[blockIdx.y];
+  const StepChan& C = chans[blockIdx.y];  // read in place: a copy indexed by slot lives in scratch
   const int p = blockIdx.x, f = blockIdx.z;
   const cplx* src = C.out_src[f];
   if (src == nullptr || C.out_dst[f] == nullptr || C.skip || p >= C.nkx) return;
@@ -1478,7 +1478,7 @@ __global__ void k_out_cols(const StepChan* __restrict__ chans) {
 // Rows: Hermitian extension along x (real part of p = 0), inverse FFT, real part out.
 __global__ void k_out_rows(const StepChan* __restrict__ chans) {
   extern __shared__ double dyn_lds[];
-  const StepChan C = chans[blockIdx.y];
+  const StepChan& C = chans[blockIdx.y];
   const int k = blockIdx.x, f = blockIdx.z;
   double* out = C.out_dst[f];
   if (C.out_src[f] == nullptr || out == nullptr || C.skip || k >= C.nz) return;
@@ -1507,7 +1507,7 @@ __global__ void k_out_rows(const StepChan* __restrict__ chans) {
 // its plane mean), pointwise on the N_z x N_x grid, in place.  Fixed-order block reduction.
 __global__ __launch_bounds__(256) void k_pressure_finish(const StepChan* __restrict__ chans) {
   __shared__ double red[256];
-  const StepChan C = chans[blockIdx.x];
+  const StepChan& C = chans[blockIdx.x];
   const int base = 1 + SLOTS_PER_PLANE * (int)blockIdx.y;
   auto pr = C.out_dst[base + 3];
   if (C.skip || pr == nullptr || C.out_src[base + 3] == nullptr) return;  // uniform per block
