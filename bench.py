@@ -42,11 +42,11 @@ RE395 = dict(nx=128, ny=97, nz=128, lx=2 * np.pi, lz=np.pi, re_tau=395.0, dt_plu
 # and is reported as null for any other source.
 TRAFFIC = {
     "column_solve_reconstruct": (3.8932e+07, "column_pass.hip", "d9c39fcd5336c91daa763a605300bc19ab60214ffbb05590762bcbdc319b2779"),
-    "x_rows_fft_product": (2.8928e+07, "plane_pass.hip", "568603a192e34b53e8317047b4929f10b9886cf4214356d0c7d1c83a21547e90"),
-    "z_inverse_fft": (3.2061e+07, "plane_pass.hip", "568603a192e34b53e8317047b4929f10b9886cf4214356d0c7d1c83a21547e90"),
-    "z_forward_fft": (1.6094e+07, "plane_pass.hip", "568603a192e34b53e8317047b4929f10b9886cf4214356d0c7d1c83a21547e90"),
+    "x_rows_fft_product": (2.8930e+07, "plane_pass.hip", "26b0d8c0508981163fce8e53bd5b1d249137085fbae50dc7aac0110d63f16773"),
+    "z_inverse_fft": (3.2062e+07, "plane_pass.hip", "26b0d8c0508981163fce8e53bd5b1d249137085fbae50dc7aac0110d63f16773"),
+    "z_forward_fft": (1.6095e+07, "plane_pass.hip", "26b0d8c0508981163fce8e53bd5b1d249137085fbae50dc7aac0110d63f16773"),
     "column_pass": (2.4452e+07, "column_pass.hip", "d9c39fcd5336c91daa763a605300bc19ab60214ffbb05590762bcbdc319b2779"),
-    "column_reconstruct": (1.7562e+07, "column_pass.hip", "d9c39fcd5336c91daa763a605300bc19ab60214ffbb05590762bcbdc319b2779"),
+    "column_reconstruct": (1.7564e+07, "column_pass.hip", "d9c39fcd5336c91daa763a605300bc19ab60214ffbb05590762bcbdc319b2779"),
 }
 
 
