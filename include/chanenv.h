@@ -279,7 +279,7 @@ int chan_batch_tuning(const struct chan_batch* batch, int32_t max_shapes, int32_
  * streams with disjoint envs run concurrently on the device; each call stages its launch
  * arguments in buffers of its own.  Errors: CHAN_EINVAL (n_substeps < 1, an env not in the
  * batch or listed twice), CHAN_EBUSY, CHAN_ESTATE (no listed env has a flow state), CHAN_ENOMEM,
- * CHAN_EDEVICE; nothing is queued then.
+ * CHAN_EDEVICE; nothing is queued then, and *out (if given) is NULL.
  *
  * chan_call_query: 1 while the call's work is still queued or running, 0 once it has finished
  * (does not block); CHAN_EINVAL for a null call.
@@ -322,7 +322,8 @@ int chan_batch_remove(struct chan_batch* batch, struct chan_env* env);
  * launch: CHAN_ESTATE (an env now without a valid flow state or poisoned; an env has left the
  * batch or been destroyed since the capture; the batch has been destroyed: capture again),
  * CHAN_EBUSY (an env held by another call, or the graph's previous replay unfinished),
- * CHAN_ENOMEM, CHAN_EDEVICE; nothing is queued then.
+ * CHAN_ENOMEM, CHAN_EDEVICE; nothing is queued then.  On every failure of capture or launch
+ * *out (if given) is NULL.
  * chan_graph_destroy finishes the graph's replay in flight, if any (its call handle is invalid
  * afterwards), and frees the graph; NULL is a no-op.  Destroying the batch (or, for
  * chan_env_capture, the env) leaves its graphs to be destroyed by the caller. */

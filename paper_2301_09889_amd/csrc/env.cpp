@@ -1657,8 +1657,8 @@ int chan_batch_launch(chan_batch* b, void* hip_stream, int32_t n, chan_env* cons
                       const double* const* actions, int32_t n_substeps, double* const* obs, double* const* tau_w,
                       double* const* drag, chan_call** out) {
   g_last_error.clear();
+  if (out) *out = nullptr;
   if (!b || !out) return CHAN_EINVAL;
-  *out = nullptr;
   return batch_launch(b, (hipStream_t)hip_stream, n, envs, actions, n_substeps, obs, tau_w, drag, out);
 }
 
@@ -1699,23 +1699,23 @@ int chan_batch_capture(chan_batch* b, int32_t n, chan_env* const* envs, const do
                        int32_t n_substeps, double* const* obs, double* const* tau_w, double* const* drag,
                        chan_graph** out) {
   g_last_error.clear();
+  if (out) *out = nullptr;
   if (!b || !out) return CHAN_EINVAL;
-  *out = nullptr;
   return batch_capture(b, n, envs, actions, n_substeps, obs, tau_w, drag, out);
 }
 
 int chan_env_capture(chan_env* e, const double* action, int32_t n_substeps, double* obs, double* tau_w,
                      double* drag, chan_graph** out) {
   g_last_error.clear();
+  if (out) *out = nullptr;
   if (!e || !out) return CHAN_EINVAL;
-  *out = nullptr;
   return batch_capture(e->self, 1, &e, &action, n_substeps, &obs, &tau_w, &drag, out);
 }
 
 int chan_graph_launch(chan_graph* g, void* hip_stream, chan_call** out) {
   g_last_error.clear();
+  if (out) *out = nullptr;
   if (!g || !out) return CHAN_EINVAL;
-  *out = nullptr;
   return graph_launch(g, (hipStream_t)hip_stream, out);
 }
 

@@ -142,6 +142,18 @@ static void invalid_inputs() {
   CHECK(chan_step_static(&bad[0], nullptr, nullptr, state, nullptr, 1, nullptr, nullptr, nullptr) == CHAN_EINVAL,
         "static step accepted an invalid grid");
   CHECK(chan_batch_create(0, nullptr, nullptr) == CHAN_EINVAL, "empty batch");
+  // captured steps and the tuning query refuse missing arguments without touching a device
+  chan_graph* gr = reinterpret_cast<chan_graph*>(0x1);
+  CHECK(chan_batch_capture(nullptr, 1, nullptr, nullptr, 1, nullptr, nullptr, nullptr, &gr) == CHAN_EINVAL,
+        "capture without a batch");
+  CHECK(gr == nullptr, "capture without a batch leaves *out null");
+  CHECK(chan_env_capture(nullptr, nullptr, 1, nullptr, nullptr, nullptr, nullptr) == CHAN_EINVAL, "env capture");
+  chan_call* call = reinterpret_cast<chan_call*>(0x1);
+  CHECK(chan_graph_launch(nullptr, nullptr, &call) == CHAN_EINVAL, "launch without a graph");
+  CHECK(call == nullptr, "launch without a graph leaves *out null");
+  chan_graph_destroy(nullptr);
+  int32_t rec[6];
+  CHECK(chan_batch_tuning(nullptr, 1, rec) == CHAN_EINVAL, "tuning of no batch");
   for (int code = -8; code <= 0; ++code) CHECK(chan_strerror(code) != nullptr, "strerror(%d)", code);
   CHECK(chan_last_error() != nullptr, "last error");
 }
