@@ -264,10 +264,13 @@ int chan_batch_timing_read(struct chan_batch* batch, int32_t nclass, int64_t* la
  * for a shape with several channels on the parity-major column kernels (N_y <= 65) the columns per
  * block of the batched column launch (2 or 4); the fastest of each is kept.  No result depends on
  * either choice.  A shape that first arrives through chan_batch_add is tuned on that one channel's
- * plane pass and keeps 4 columns per block.  Writes up to max_shapes records of 6 int32
- * {nx, ny, nz, z pencils per block, x-row pairs per block, columns per block} (columns per block
- * 0 for a shape on the general column kernel) and returns the number of shapes; CHAN_EINVAL for
- * NULL arguments. */
+ * plane pass and keeps 4 columns per block.  Writes up to max_shapes records of 7 int32
+ * {nx, ny, nz, z pencils per block, x-row pairs per block, columns per block, plane fused}
+ * (columns per block 0 for a shape on the general column kernel; plane fused 1 where the z
+ * inverse and the x rows run as one launch, possible for padded lengths M_x, M_z of 48 or 96,
+ * else 0) and returns the number of shapes; CHAN_EINVAL for NULL arguments.  The environment
+ * variable CHANENV_PLANE_FORM, read when a shape is tuned, limits the plane-pass choice to
+ * "split" (three launches) or "fused" forms (where the shape has one). */
 int chan_batch_tuning(const struct chan_batch* batch, int32_t max_shapes, int32_t* out);
 
 /* ---- Asynchronous batch calls and membership (a request loop over channels that come and go) ----

@@ -289,10 +289,10 @@ def chan_batch_tuning(h):
     n = lib.chan_batch_tuning(h, 0, None)
     if n < 0:
         raise ChanError(n, "chan_batch_tuning")
-    buf = (ctypes.c_int32 * (6 * max(n, 1)))()
+    buf = (ctypes.c_int32 * (7 * max(n, 1)))()
     lib.chan_batch_tuning(h, n, buf)
-    keys = ("nx", "ny", "nz", "z_pencils_per_block", "x_pairs_per_block", "columns_per_block")
-    return [dict(zip(keys, buf[6 * k:6 * k + 6])) for k in range(n)]
+    keys = ("nx", "ny", "nz", "z_pencils_per_block", "x_pairs_per_block", "columns_per_block", "plane_fused")
+    return [dict(zip(keys, buf[7 * k:7 * k + 7])) for k in range(n)]
 
 
 def chan_batch_capture(h, env_handles, action_ptrs, n_substeps, obs_ptrs, tau_ptrs, drag_ptrs):

@@ -240,15 +240,16 @@ int launch_pressure_finish(const StepChan* d_step, int nch, hipStream_t st, Kern
 int launch_outputs(const StepChan* d_step, int nch, int max_nx, int max_nz, int max_nkx, int nslots, hipStream_t st,
                    KernelTimer* tm);
 // Plane pass over nch channels of one shape (M_x, M_z from nx, nz), with a tiling: PB pencils
-// per z-kernel block, P pairs of padded z rows per x-row block.  The tiling distributes
+// per z-kernel block, P pairs of padded z rows per x-row block, and fused = 1 for the z inverse
+// and the x rows in one launch (k_zxrow, P = its pairs per block).  The tiling distributes
 // independent transforms over blocks and does not change any result.
 struct PlaneTiles {
-  int PB, P;
+  int PB, P, fused;
 };
 int launch_plane_pass(const Dims& d, const PlaneChan* d_plane, int nch, const PlaneTiles& t, hipStream_t st,
                       KernelTimer* tm);
 // Every valid tiling for the shape (for the tuner); -1 if the shape has none.
-int plane_tile_candidates(const Dims& d, std::vector<PlaneTiles>* out);
+int plane_tile_candidates(const Dims& d, std::vector<PlaneTiles>* out, int form = 0);
 // N <= 64 column pass over nch channels of one shape: the solve of stage S.stage (if solve)
 // and/or the reconstruction that follows it (if recon; S.stage -1: reconstruction only).
 // d_col: the channels' arguments on the device; h_col (optional): the same on the host, used

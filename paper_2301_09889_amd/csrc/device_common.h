@@ -1,5 +1,5 @@
 // Device helpers shared by the HIP sources: FP64 complex arithmetic on double2,
-// wavefront-scope synchronisation and reductions, and small in-register DFTs.
+// wavefront-scope synchronisation and reductions.
 #pragma once
 
 #include "chanenv_internal.h"
@@ -140,105 +140,5 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
-
-
-// cos and sin of 2 pi m / 48, m = 0..47: every root of unity the small DFTs below use
-// (orders 2, 3, 4, 6, 8, 12, 16, 24, 48) is one of these.
-constexpr double C48[48] = {1.0, 0.9914448613738104111446, 0.9659258262890682867497, 0.9238795325112867561282, 0.8660254037844386467637, 0.7933533402912351645798, 0.7071067811865475244008, 0.6087614290087206394161, 0.5, 0.3826834323650897717285, 0.2588190451025207623489, 0.1305261922200515915484, 2.06703210982639882365e-43, -0.1305261922200515915484, -0.2588190451025207623489, -0.3826834323650897717285, -0.5, -0.6087614290087206394161, -0.7071067811865475244008, -0.7933533402912351645798, -0.8660254037844386467637, -0.9238795325112867561282, -0.9659258262890682867497, -0.9914448613738104111446, -1.0, -0.9914448613738104111446, -0.9659258262890682867497, -0.9238795325112867561282, -0.8660254037844386467637, -0.7933533402912351645798, -0.7071067811865475244008, -0.6087614290087206394161, -0.5, -0.3826834323650897717285, -0.2588190451025207623489, -0.1305261922200515915484, 2.233876440654988324292e-41, 0.1305261922200515915484, 0.2588190451025207623489, 0.3826834323650897717285, 0.5, 0.6087614290087206394161, 0.7071067811865475244008, 0.7933533402912351645798, 0.8660254037844386467637, 0.9238795325112867561282, 0.9659258262890682867497, 0.9914448613738104111446};
-constexpr double S48[48] = {0.0, 0.1305261922200515915484, 0.2588190451025207623489, 0.3826834323650897717285, 0.5, 0.6087614290087206394161, 0.7071067811865475244008, 0.7933533402912351645798, 0.8660254037844386467637, 0.9238795325112867561282, 0.9659258262890682867497, 0.9914448613738104111446, 1.0, 0.9914448613738104111446, 0.9659258262890682867497, 0.9238795325112867561282, 0.8660254037844386467637, 0.7933533402912351645798, 0.7071067811865475244008, 0.6087614290087206394161, 0.5, 0.3826834323650897717285, 0.2588190451025207623489, 0.1305261922200515915484, 4.134064219652797647299e-43, -0.1305261922200515915484, -0.2588190451025207623489, -0.3826834323650897717285, -0.5, -0.6087614290087206394161, -0.7071067811865475244008, -0.7933533402912351645798, -0.8660254037844386467637, -0.9238795325112867561282, -0.9659258262890682867497, -0.9914448613738104111446, -1.0, -0.9914448613738104111446, -0.9659258262890682867497, -0.9238795325112867561282, -0.8660254037844386467637, -0.7933533402912351645798, -0.7071067811865475244008, -0.6087614290087206394161, -0.5, -0.3826834323650897717285, -0.2588190451025207623489, -0.1305261922200515915484};
-
-// exp(SG * 2 pi i m / R) for a root of order R dividing 48 (SG = -1 forward, +1 inverse).
-template <int R, int SG>
-HD cplx root(int m) {
-  const int k = ((48 / R) * m) % 48;
-  return make_double2(C48[k], SG * S48[k]);
-}
-
-// a * exp(SG * 2 pi i m / R), with the multiplications by 1 and +-i written out.
-template <int R, int SG>
-HD cplx rotate(cplx a, int m) {
-  const int k = ((48 / R) * m) % 48;
-  if (k == 0) return a;
-  if (k == 12) return SG > 0 ? cmuli(a) : make_double2(a.y, -a.x);
-  if (k == 24) return make_double2(-a.x, -a.y);
-  if (k == 36) return SG > 0 ? make_double2(a.y, -a.x) : cmuli(a);
-  return cmul(a, root<R, SG>(m));
-}
-
-// Small DFTs in registers: X[k] = sum_n x[n] exp(SG 2 pi i n k / R), in place.
-template <int R, int SG>
-struct Dft;
-
-template <int SG>
-struct Dft<1, SG> {
-  static HD void run(cplx* x) {}
-};
-
-template <int SG>
-struct Dft<2, SG> {
-  static HD void run(cplx* x) {
-    const cplx a = x[0], b = x[1];
-    x[0] = cadd(a, b);
-    x[1] = csub(a, b);
-  }
-};
-
-template <int SG>
-struct Dft<3, SG> {
-  static HD void run(cplx* x) {
-    const double h = 0.8660254037844386467637232;  // sqrt(3)/2
-    const cplx t1 = cadd(x[1], x[2]), t2 = csub(x[1], x[2]);
-    const cplx m = make_double2(x[0].x - 0.5 * t1.x, x[0].y - 0.5 * t1.y);
-    const cplx r = make_double2(-SG * h * t2.y, SG * h * t2.x);  // SG i h t2
-    x[0] = cadd(x[0], t1);
-    x[1] = cadd(m, r);
-    x[2] = csub(m, r);
-  }
-};
-
-template <int SG>
-struct Dft<4, SG> {
-  static HD void run(cplx* x) {
-    const cplx a = cadd(x[0], x[2]), b = csub(x[0], x[2]);
-    const cplx c = cadd(x[1], x[3]), d = csub(x[1], x[3]);
-    const cplx id = make_double2(-SG * d.y, SG * d.x);  // SG i d
-    x[0] = cadd(a, c);
-    x[2] = csub(a, c);
-    x[1] = cadd(b, id);
-    x[3] = csub(b, id);
-  }
-};
-
-// R = R1 R2 by one Cooley--Tukey split (n = R2 n1 + n2, k = k1 + R1 k2).
-template <int R1, int R2, int SG>
-struct DftSplit {
-  static HD void run(cplx* x) {
-    constexpr int R = R1 * R2;
-    cplx y[R];
-#pragma unroll
-    for (int n2 = 0; n2 < R2; ++n2) {
-      cplx t[R1];
-#pragma unroll
-      for (int n1 = 0; n1 < R1; ++n1) t[n1] = x[R2 * n1 + n2];
-      Dft<R1, SG>::run(t);
-#pragma unroll
-      for (int k1 = 0; k1 < R1; ++k1) y[n2 * R1 + k1] = rotate<R, SG>(t[k1], n2 * k1);
-    }
-#pragma unroll
-    for (int k1 = 0; k1 < R1; ++k1) {
-      cplx t[R2];
-#pragma unroll
-      for (int n2 = 0; n2 < R2; ++n2) t[n2] = y[n2 * R1 + k1];
-      Dft<R2, SG>::run(t);
-#pragma unroll
-      for (int k2 = 0; k2 < R2; ++k2) x[k1 + R1 * k2] = t[k2];
-    }
-  }
-};
-
-template <int SG> struct Dft<6, SG> : DftSplit<3, 2, SG> {};
-template <int SG> struct Dft<8, SG> : DftSplit<4, 2, SG> {};
-template <int SG> struct Dft<12, SG> : DftSplit<3, 4, SG> {};
-template <int SG> struct Dft<16, SG> : DftSplit<4, 4, SG> {};
 
 }  // namespace chanenv

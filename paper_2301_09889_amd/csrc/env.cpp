@@ -21,7 +21,7 @@ using namespace chanenv;
 struct ShapeInfo {
   Dims d;
   bool pm;                        // N <= 64: the parity-major column kernels
-  PlaneTiles tiles = {0, 0};
+  PlaneTiles tiles = {0, 0, 0};
   int col_cw = 4;                 // columns per block of the batched column launch (tuned)
 };
 
@@ -205,6 +205,16 @@ int sensing_node(const Dims& d, const PhysParams& ph, double yplus, double* node
 bool generic_forced() {
   const char* g = std::getenv("CHANENV_GENERIC_COLUMN");
   return g && g[0] == '1';
+}
+
+// Plane-pass forms the tuner may pick from (CHANENV_PLANE_FORM, read when a shape is tuned):
+// "split" only the three-launch tilings, "fused" only the fused z inverse and x rows (where the
+// shape has them), anything else every tiling.  The forms give bitwise the same results.
+int plane_form() {
+  const char* f = std::getenv("CHANENV_PLANE_FORM");
+  if (f && std::strcmp(f, "split") == 0) return 1;
+  if (f && std::strcmp(f, "fused") == 0) return 2;
+  return 0;
 }
 
 struct Sizes {
@@ -789,7 +799,10 @@ int batch_build(chan_env* const* envs, int n, chan_batch** out) {
 int tune_plane(chan_batch* b, int shape, const std::vector<chan_env*>& members) {
   ShapeInfo& sh = b->shapes[shape];
   std::vector<PlaneTiles> cands;
-  if (plane_tile_candidates(sh.d, &cands)) return fail(CHAN_EINVAL, "no plane-pass tiling for this grid");
+  const int form = plane_form();
+  if (form && (plane_tile_candidates(sh.d, &cands, form) || cands.empty())) cands.clear();
+  if (cands.empty() && plane_tile_candidates(sh.d, &cands))
+    return fail(CHAN_EINVAL, "no plane-pass tiling for this grid");
   sh.tiles = cands.back();
   if (cands.size() == 1) return CHAN_OK;
   chan_call c;
@@ -1732,13 +1745,14 @@ int chan_batch_tuning(const chan_batch* b, int32_t max_shapes, int32_t* out) {
   const int n = (int)b->shapes.size();
   for (int k = 0; k < n && k < max_shapes; ++k) {
     const ShapeInfo& sh = b->shapes[k];
-    int32_t* r = out + 6 * k;
+    int32_t* r = out + 7 * k;
     r[0] = sh.d.nx;
     r[1] = sh.d.ny;
     r[2] = sh.d.nz;
     r[3] = sh.tiles.PB;
     r[4] = sh.tiles.P;
     r[5] = sh.pm ? sh.col_cw : 0;
+    r[6] = sh.tiles.fused;
   }
   return n;
 }
@@ -1803,7 +1817,7 @@ struct StaticSlot {
   int nx = 0, ny = 0, nz = 0;
   PhysParams ph;
   TableLayout L;
-  PlaneTiles tiles = {0, 0};
+  PlaneTiles tiles = {0, 0, 0};
 };
 StaticSlot static_slot[MAX_STATIC_DEVICES];
 
@@ -1963,7 +1977,7 @@ int static_column(chan_env* e, const ColChan& h, const ColStage& S, bool solve, 
 // where that is valid, pencil blocks of 16.
 PlaneTiles static_tiles(const Dims& d) {
   std::vector<PlaneTiles> c;
-  if (plane_tile_candidates(d, &c) != 0 || c.empty()) return PlaneTiles{0, 0};
+  if (plane_tile_candidates(d, &c, 1) != 0 || c.empty()) return PlaneTiles{0, 0, 0};
   for (const PlaneTiles& t : c)
     if (t.P >= 3 && t.PB >= 16) return t;
   return c.back();

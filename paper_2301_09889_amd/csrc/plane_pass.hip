@@ -15,9 +15,22 @@
 //
 // Layouts (complex):  F6[f][j][p][q], Z6[f][j][zz][p], W3[g][j][zz][p], H3[g][j][p][q].
 // A launch covers nch channels of one shape: blockIdx.z = channel * N_y + node.
+//
+// The z inverse exists in two kernels (k_zinv2, and k_zxrow, which redoes its first pass and
+// keeps two outputs) that must give bitwise the same values.  Which multiplies the compiler
+// fuses into adds depends on how a transform's outputs are used next, so both take their DFTs
+// and twiddles from chanenv::strict, a copy compiled without multiply-add contraction (every
+// operation rounds on its own); the other transforms, each in one code path, contract.
 #include "device_common.h"
 
 namespace chanenv {
+namespace strict {
+#pragma clang fp contract(off)
+#include "small_dft.inc"
+#pragma clang fp contract(fast)
+}  // namespace strict
+
+#include "small_dft.inc"
 
 template <int L>
 struct FftPlan;
@@ -38,15 +51,6 @@ struct FftLds {
   static constexpr int LS = ((L + 1 > B * AP) ? L + 1 : B * AP) | 1;
 };
 
-
-// a * w_L^(SG m) from a table tw[k] = exp(-2 pi i k / L) held in LDS.
-template <int L, int SG>
-__device__ __forceinline__ cplx twiddle(cplx a, const cplx* tw, int m) {
-  if (m == 0) return a;
-  cplx w = tw[m % L];
-  if (SG > 0) w.y = -w.y;
-  return cmul(a, w);
-}
 
 
 // Threads of a z-kernel block: PB pencils (at most 32) times the first pass's length A.  The
@@ -85,10 +89,10 @@ __global__ __launch_bounds__(zkernel_threads<L>()) void k_zinv2(const PlaneChan*
       const int q = (zz < h) ? zz : ((zz > L - h) ? zz - L + nz : -1);
       t[n1] = (q >= 0) ? src[(size_t)p * nz + q] : cz();
     }
-    Dft<FA, 1>::run(t);
+    strict::Dft<FA, 1>::run(t);
     cplx* y = Y + p * LP + n2 * AP;
 #pragma unroll
-    for (int k1 = 0; k1 < FA; ++k1) y[k1] = twiddle<L, 1>(t[k1], tw, n2 * k1);
+    for (int k1 = 0; k1 < FA; ++k1) y[k1] = strict::twiddle<L, 1>(t[k1], tw, n2 * k1);
   }
   __syncthreads();
   cplx* dst = A.Z6 + fj * L * A.nkx + p0;
@@ -97,7 +101,7 @@ __global__ __launch_bounds__(zkernel_threads<L>()) void k_zinv2(const PlaneChan*
     cplx u[FB];
 #pragma unroll
     for (int n2 = 0; n2 < FB; ++n2) u[n2] = Y[p * LP + n2 * AP + k1];
-    Dft<FB, 1>::run(u);
+    strict::Dft<FB, 1>::run(u);
     if (skip) continue;
 #pragma unroll
     for (int k2 = 0; k2 < FB; ++k2) dst[(size_t)(k1 + FA * k2) * A.nkx + p] = u[k2];
@@ -174,15 +178,142 @@ __global__ __launch_bounds__(zkernel_threads<L>()) void k_zfwd2(const PlaneChan*
 }
 
 // ---------------------------------------------------------------------------
+// x rows on a block's staged sequences S[field * P + pair][LS] (the packed spectra of P pairs
+// of padded z rows of node j, see k_xrow2): six inverse real FFTs, the products, three
+// forward FFTs and the unpacking, one task per thread in every phase (the block has 6 P A
+// threads).  Pair pr holds rows z = row0 + rstep pr and z + 1; the products go to W3 unless
+// skip.  Pass 1 writes each task's A outputs at stride AP, sequences lie LS apart.
+// ---------------------------------------------------------------------------
+template <int L, int LS, int AP>
+__device__ __forceinline__ void xrow_body(const PlaneChan& A, cplx* S, const cplx* tw, int P, int j, int row0,
+                                          int rstep, bool skip) {
+  constexpr int FA = FftPlan<L>::A, FB = FftPlan<L>::B;
+  static_assert(FA >= FB, "pass 1 has at most one task per thread");
+  static_assert(LS > L && LS >= (FB - 1) * AP + FA, "LDS sequence stride too small");
+  const int nkx = A.nkx, ny = A.ny;
+  const int mz = 3 * A.nz / 2;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  // 1. inverse pass 1, one task (f, pair, n2) per thread: the packed spectrum k = B n1 + n2 is
+  // read into registers, then (after every task has read its inputs) transformed and written
+  // back over the staged rows
+  {
+    const int task = tid;
+    const bool have = task < 6 * P * FB;
+    const int seq = task / FB, n2 = task - seq * FB;
+    cplx t[FA];
+    if (have) {
+      const cplx* z = S + seq * LS;
+#pragma unroll
+      for (int n1 = 0; n1 < FA; ++n1) {
+        const int k = FB * n1 + n2;
+        t[n1] = (k < nkx) ? z[k] : ((k > L - nkx) ? z[nkx + (L - k)] : cz());
+      }
+    }
+    __syncthreads();
+    if (have) {
+      Dft<FA, 1>::run(t);
+      cplx* y = S + seq * LS + n2 * AP;
+#pragma unroll
+      for (int k1 = 0; k1 < FA; ++k1) y[k1] = twiddle<L, 1>(t[k1], tw, n2 * k1);
+    }
+  }
+  __syncthreads();
+  // 2. inverse pass 2, tasks (f, pair, k1): values at x = k1 + A k2, back into S in order
+  {
+    const int ntask = 6 * P * FA;
+    cplx X[FB];
+    int base = 0, k1 = 0;
+    const bool have = tid < ntask;
+    if (have) {
+      const int seq = tid / FA;
+      k1 = tid - seq * FA;
+      base = seq * LS;
+#pragma unroll
+      for (int n2 = 0; n2 < FB; ++n2) X[n2] = S[base + n2 * AP + k1];
+      Dft<FB, 1>::run(X);
+    }
+    __syncthreads();
+    if (have) {
+#pragma unroll
+      for (int k2 = 0; k2 < FB; ++k2) S[base + k1 + FA * k2] = X[k2];
+    }
+  }
+  __syncthreads();
+  // 3. products at every (pair, x); re = the pair's first row, im = its second
+  for (int task = tid; task < P * L; task += nthr) {
+    const int pr = task / L, x = task - pr * L;
+    const cplx U = S[(0 * P + pr) * LS + x], V = S[(1 * P + pr) * LS + x], W = S[(2 * P + pr) * LS + x];
+    const cplx OX = S[(3 * P + pr) * LS + x], OY = S[(4 * P + pr) * LS + x], OZ = S[(5 * P + pr) * LS + x];
+    S[(0 * P + pr) * LS + x] = make_double2(V.x * OZ.x - W.x * OY.x, V.y * OZ.y - W.y * OY.y);
+    S[(1 * P + pr) * LS + x] = make_double2(W.x * OX.x - U.x * OZ.x, W.y * OX.y - U.y * OZ.y);
+    S[(2 * P + pr) * LS + x] = make_double2(U.x * OY.x - V.x * OX.x, U.y * OY.y - V.y * OX.y);
+  }
+  __syncthreads();
+  // 4. forward pass 1, tasks (g, pair, n2)
+  {
+    const int ntask = 3 * P * FB;
+    cplx t[FA];
+    int base = 0, n2 = 0;
+    const bool have = tid < ntask;
+    if (have) {
+      const int seq = tid / FB;
+      n2 = tid - seq * FB;
+      base = seq * LS;
+#pragma unroll
+      for (int n1 = 0; n1 < FA; ++n1) t[n1] = S[base + FB * n1 + n2];
+      Dft<FA, -1>::run(t);
+    }
+    __syncthreads();
+    if (have) {
+#pragma unroll
+      for (int k1 = 0; k1 < FA; ++k1) S[base + n2 * AP + k1] = twiddle<L, -1>(t[k1], tw, n2 * k1);
+    }
+  }
+  __syncthreads();
+  // 5. forward pass 2, tasks (g, pair, k1): spectrum k = k1 + A k2 back into S in order
+  {
+    const int ntask = 3 * P * FA;
+    cplx X[FB];
+    int base = 0, k1 = 0;
+    const bool have = tid < ntask;
+    if (have) {
+      const int seq = tid / FA;
+      k1 = tid - seq * FA;
+      base = seq * LS;
+#pragma unroll
+      for (int n2 = 0; n2 < FB; ++n2) X[n2] = S[base + n2 * AP + k1];
+      Dft<FB, -1>::run(X);
+    }
+    __syncthreads();
+    if (have) {
+#pragma unroll
+      for (int k2 = 0; k2 < FB; ++k2) S[base + k1 + FA * k2] = X[k2];
+    }
+  }
+  __syncthreads();
+  // 6. unpack the two rows of each pair: a = (Y_k + conj Y_{L-k})/2, b = (Y_k - conj Y_{L-k})/(2i)
+  for (int task = tid; task < 3 * P * nkx && !skip; task += nthr) {
+    const int seq = task / nkx, k = task - seq * nkx;
+    const int g = seq / P, pr = seq - g * P;
+    const cplx Yk = S[seq * LS + k];
+    const cplx Ym = cconj(S[seq * LS + ((L - k) % L)]);
+    const cplx Xa = make_double2(0.5 * (Yk.x + Ym.x), 0.5 * (Yk.y + Ym.y));
+    const cplx Xb = make_double2(0.5 * (Yk.y - Ym.y), -0.5 * (Yk.x - Ym.x));
+    const int za = row0 + rstep * pr;
+    cplx* wa = A.W3 + (((size_t)g * ny + j) * mz + za) * nkx;
+    wa[k] = Xa;
+    wa[nkx + k] = Xb;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // x rows: block (pair chunk, node); Z6 -> W3.  Each phase gives one task per thread so
 // that the six inverse transforms, the products and the three forward transforms of a
 // block are all in flight together; S holds 6 sequences per pair, transformed in place.
 // ---------------------------------------------------------------------------
 template <int L>
 __global__ __launch_bounds__(1024) void k_xrow2(const PlaneChan* __restrict__ chans, int nyc, int P) {
-  constexpr int FA = FftPlan<L>::A, FB = FftPlan<L>::B;
-  constexpr int LP = FftLds<L>::LS, AP = FftLds<L>::AP;
-  static_assert(FA >= FB, "pass 1 has at most one task per thread");
+  constexpr int LP = FftLds<L>::LS;
   extern __shared__ double dyn_lds[];
   cplx* tw = reinterpret_cast<cplx*>(dyn_lds);
   cplx* S = tw + L;         // [field][pair][LP]
@@ -211,117 +342,122 @@ __global__ __launch_bounds__(1024) void k_xrow2(const PlaneChan* __restrict__ ch
     S[seq * LP + nkx + m] = make_double2(xa.x + xb.y, xb.x - xa.y);
   }
   __syncthreads();
-  // 1. inverse pass 1, one task (f, pair, n2) per thread (the block has 6 P A >= 6 P B
-  // threads): the packed spectrum k = B n1 + n2 is read into registers, then (after every
-  // task has read its inputs) transformed and written back over the staged rows
-  {
-    const int task = tid;
-    const bool have = task < 6 * P * FB;
-    const int seq = task / FB, n2 = task - seq * FB;
-    cplx t[FA];
-    if (have) {
-      const cplx* z = S + seq * LP;
+  xrow_body<L, LP, FftLds<L>::AP>(A, S, tw, P, j, 2 * pair0, 2, skip);
+}
+
+// ---------------------------------------------------------------------------
+// z inverse and x rows in one launch (M_z, M_x in {48, 96}): the padded z rows never leave
+// the block.  Block (node, k1 pair): the rows z = k1 + A_z k2 and z + 1 (k1 even, every k2)
+// of one node, which are the outputs k1, k1 + 1 of the z inverse's second pass for every
+// (field, p) pencil.  The first pass (the DFT over n1 of each task n2) is done in full and
+// its outputs k1, k1 + 1 kept, so every value is the one k_zinv2 writes to Z6, and the rows
+// are paired as in k_xrow2 (two rows 2m, 2m + 1 per complex sequence): W3 is bitwise that of
+// k_zinv2 + k_xrow2.  Each node's blocks run on one XCD (the hardware deals workgroup b to
+// XCD b mod 8), so that its input plane, read by A_z / 2 blocks, is fetched into one L2.
+// ---------------------------------------------------------------------------
+template <int MZ, int MX>
+constexpr bool zx_fusable() { return (MZ == 48 || MZ == 96) && (MX == 48 || MX == 96); }
+
+template <int MZ, int MX>
+struct ZxPlan {
+  static constexpr int ZA = FftPlan<MZ>::A, ZB = FftPlan<MZ>::B, XA = FftPlan<MX>::A, XB = FftPlan<MX>::B;
+  static constexpr int NKX = MX / 3;             // stored x modes: N_x / 2 with M_x = 3 N_x / 2
+  static constexpr int P = ZB;                   // pairs of rows per block, one per k2
+  static constexpr int NG = ZA / 2;              // blocks per node
+  static constexpr int AP = XA | 1;
+  static constexpr int LS = ((MX + 1 > (XB - 1) * AP + XA) ? MX + 1 : (XB - 1) * AP + XA) | 1;
+  static constexpr int YS = 2 * ZB + 1;          // first-pass outputs kept per pencil, padded odd
+  static constexpr int THREADS = ((6 * P * XA + 63) / 64) * 64;
+  static constexpr int TW = MZ + (MX == MZ ? 0 : MX);
+  static constexpr int LDS_CPLX = TW + 6 * P * LS;
+  static_assert(ZA % 2 == 0, "k1 pairs");
+  static_assert(NKX * YS <= P * LS, "first-pass outputs fit in the row buffer");
+  static_assert(12 * NKX <= THREADS, "one second-pass task per thread");
+};
+
+template <int MZ, int MX>
+__global__ __launch_bounds__((ZxPlan<MZ, MX>::THREADS)) void k_zxrow(const PlaneChan* __restrict__ chans, int ny,
+                                                                   int nnodes) {
+  using ZP = ZxPlan<MZ, MX>;
+  constexpr int ZA = ZP::ZA, ZB = ZP::ZB, P = ZP::P, LS = ZP::LS, YS = ZP::YS, NKX = ZP::NKX;
+  extern __shared__ double dyn_lds[];
+  cplx* twz = reinterpret_cast<cplx*>(dyn_lds);
+  cplx* twx = (MX == MZ) ? twz : twz + MZ;       // the same table when the lengths agree
+  cplx* S = twz + ZP::TW;                        // [field][pair][LS]
+  cplx* Y = S;                                   // first-pass outputs [field][p][YS], read before S is written
+  const int b = blockIdx.x, xcd = b & 7, sl = b >> 3;
+  const int grp = sl % ZP::NG, node = (sl / ZP::NG) * 8 + xcd;
+  if (node >= nnodes) return;                    // the whole block: before any barrier
+  const PlaneChan A = chans[node / ny];
+  const int j = node % ny;
+  const bool skip = (*A.status & STATUS_BAD_ACTION) != 0;  // tested at the stores
+  const int kb = 2 * grp;                        // this block's k1 pair: kb, kb + 1
+  const int nz = A.nz, h = nz / 2;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  for (int t = tid; t < MZ; t += nthr) twz[t] = A.twz[t];
+  if (MX != MZ)
+    for (int t = tid; t < MX; t += nthr) twx[t] = A.twx[t];
+  __syncthreads();
+  // z pass 1, tasks (f, p, n2): the full DFT over n1 of x[B n1 + n2] (zero padding as in
+  // k_zinv2), outputs kb and kb + 1 twiddled and kept
+  for (int task = tid; task < 6 * NKX * ZB; task += nthr) {
+    const int fp = task / ZB, n2 = task - fp * ZB;
+    const int f = fp / NKX, p = fp - f * NKX;
+    const cplx* src = A.F6 + (((size_t)f * A.ny + j) * NKX + p) * nz;
+    cplx t[ZA];
 #pragma unroll
-      for (int n1 = 0; n1 < FA; ++n1) {
-        const int k = FB * n1 + n2;
-        t[n1] = (k < nkx) ? z[k] : ((k > L - nkx) ? z[nkx + (L - k)] : cz());
+    for (int n1 = 0; n1 < ZA; ++n1) {
+      const int zz = ZB * n1 + n2;
+      const int q = (zz < h) ? zz : ((zz > MZ - h) ? zz - MZ + nz : -1);
+      t[n1] = (q >= 0) ? src[q] : cz();
+    }
+    strict::Dft<ZA, 1>::run(t);
+    cplx y0 = t[0], y1 = t[1];
+#pragma unroll
+    for (int k1 = 2; k1 < ZA; k1 += 2) {
+      if (k1 == kb) {
+        y0 = t[k1];
+        y1 = t[k1 + 1];
       }
     }
-    __syncthreads();
-    if (have) {
-      Dft<FA, 1>::run(t);
-      cplx* y = S + seq * LP + n2 * AP;
-#pragma unroll
-      for (int k1 = 0; k1 < FA; ++k1) y[k1] = twiddle<L, 1>(t[k1], tw, n2 * k1);
-    }
+    Y[fp * YS + 2 * n2] = strict::twiddle<MZ, 1>(y0, twz, n2 * kb);
+    Y[fp * YS + 2 * n2 + 1] = strict::twiddle<MZ, 1>(y1, twz, n2 * (kb + 1));
   }
   __syncthreads();
-  // 2. inverse pass 2, tasks (f, pair, k1): values at x = k1 + A k2, back into S in order
+  // z pass 2, tasks (f, p, s): the DFT over n2 gives rows kb + s + A_z k2 of pencil (f, p);
+  // lane pairs (s = 0, 1) exchange their values and write the packed sequences of k_xrow2's
+  // staging: the s = 0 lane P_p = a_p + i b_p at S[f P + k2][p], the s = 1 lane
+  // Q_p = conj(a_p) + i conj(b_p) at S[f P + k2][N_x/2 + p] (a, b: rows kb, kb + 1).  Every
+  // lane takes part in the exchange (out-of-range tasks on a clamped pencil, not stored).
   {
-    const int ntask = 6 * P * FA;
-    cplx X[FB];
-    int base = 0, k1 = 0;
-    const bool have = tid < ntask;
-    if (have) {
-      const int seq = tid / FA;
-      k1 = tid - seq * FA;
-      base = seq * LP;
+    const int task = tid;
+    const bool have = task < 12 * NKX;
+    const int fp = have ? (task >> 1) : 0, sidx = task & 1;
+    cplx u[ZB];
 #pragma unroll
-      for (int n2 = 0; n2 < FB; ++n2) X[n2] = S[base + n2 * AP + k1];
-      Dft<FB, 1>::run(X);
-    }
-    __syncthreads();
-    if (have) {
+    for (int n2 = 0; n2 < ZB; ++n2) u[n2] = Y[fp * YS + 2 * n2 + sidx];
+    strict::Dft<ZB, 1>::run(u);
+    __syncthreads();                             // every Y read before S is written
+    const int f = fp / NKX, p = fp - f * NKX;
 #pragma unroll
-      for (int k2 = 0; k2 < FB; ++k2) S[base + k1 + FA * k2] = X[k2];
-    }
-  }
-  __syncthreads();
-  // 3. products at every (pair, x); re = row 2 pair, im = row 2 pair + 1
-  for (int task = tid; task < P * L; task += nthr) {
-    const int pr = task / L, x = task - pr * L;
-    const cplx U = S[(0 * P + pr) * LP + x], V = S[(1 * P + pr) * LP + x], W = S[(2 * P + pr) * LP + x];
-    const cplx OX = S[(3 * P + pr) * LP + x], OY = S[(4 * P + pr) * LP + x], OZ = S[(5 * P + pr) * LP + x];
-    S[(0 * P + pr) * LP + x] = make_double2(V.x * OZ.x - W.x * OY.x, V.y * OZ.y - W.y * OY.y);
-    S[(1 * P + pr) * LP + x] = make_double2(W.x * OX.x - U.x * OZ.x, W.y * OX.y - U.y * OZ.y);
-    S[(2 * P + pr) * LP + x] = make_double2(U.x * OY.x - V.x * OX.x, U.y * OY.y - V.y * OX.y);
-  }
-  __syncthreads();
-  // 4. forward pass 1, tasks (g, pair, n2)
-  {
-    const int ntask = 3 * P * FB;
-    cplx t[FA];
-    int base = 0, n2 = 0;
-    const bool have = tid < ntask;
-    if (have) {
-      const int seq = tid / FB;
-      n2 = tid - seq * FB;
-      base = seq * LP;
-#pragma unroll
-      for (int n1 = 0; n1 < FA; ++n1) t[n1] = S[base + FB * n1 + n2];
-      Dft<FA, -1>::run(t);
-    }
-    __syncthreads();
-    if (have) {
-#pragma unroll
-      for (int k1 = 0; k1 < FA; ++k1) S[base + n2 * AP + k1] = twiddle<L, -1>(t[k1], tw, n2 * k1);
+    for (int k2 = 0; k2 < ZB; ++k2) {
+      const cplx o = cmov<DPP_QUAD_XOR1>(u[k2]);  // the partner row's value
+      cplx xa = sidx ? o : u[k2], xb = sidx ? u[k2] : o;
+      if (p == 0) {
+        xa.y = 0.0;
+        xb.y = 0.0;
+      }
+      if (have) {
+        cplx* seq = S + (f * P + k2) * LS;
+        if (sidx == 0)
+          seq[p] = make_double2(xa.x - xb.y, xa.y + xb.x);
+        else
+          seq[NKX + p] = make_double2(xa.x + xb.y, xb.x - xa.y);
+      }
     }
   }
   __syncthreads();
-  // 5. forward pass 2, tasks (g, pair, k1): spectrum k = k1 + A k2 back into S in order
-  {
-    const int ntask = 3 * P * FA;
-    cplx X[FB];
-    int base = 0, k1 = 0;
-    const bool have = tid < ntask;
-    if (have) {
-      const int seq = tid / FA;
-      k1 = tid - seq * FA;
-      base = seq * LP;
-#pragma unroll
-      for (int n2 = 0; n2 < FB; ++n2) X[n2] = S[base + n2 * AP + k1];
-      Dft<FB, -1>::run(X);
-    }
-    __syncthreads();
-    if (have) {
-#pragma unroll
-      for (int k2 = 0; k2 < FB; ++k2) S[base + k1 + FA * k2] = X[k2];
-    }
-  }
-  __syncthreads();
-  // 6. unpack the two rows of each pair: a = (Y_k + conj Y_{L-k})/2, b = (Y_k - conj Y_{L-k})/(2i)
-  for (int task = tid; task < 3 * P * nkx && !skip; task += nthr) {
-    const int seq = task / nkx, k = task - seq * nkx;
-    const int g = seq / P, pr = seq - g * P;
-    const cplx Yk = S[seq * LP + k];
-    const cplx Ym = cconj(S[seq * LP + ((L - k) % L)]);
-    const cplx Xa = make_double2(0.5 * (Yk.x + Ym.x), 0.5 * (Yk.y + Ym.y));
-    const cplx Xb = make_double2(0.5 * (Yk.y - Ym.y), -0.5 * (Yk.x - Ym.x));
-    const int za = 2 * (pair0 + pr);
-    cplx* wa = A.W3 + (((size_t)g * ny + j) * mz + za) * nkx;
-    wa[k] = Xa;
-    wa[nkx + k] = Xb;
-  }
+  xrow_body<MX, LS, ZP::AP>(A, S, twx, P, j, kb, ZA, skip);
 }
 
 // ---------------------------------------------------------------------------
@@ -590,7 +726,7 @@ static int launch_plane2(const Dims& d, const PlaneChan* chans, int nch, const P
   }
   const int PB = t.PB, P = t.P;
   const int pairs = MZ / 2;
-  if (PB < 1 || PB > d.nkx || P < 1 || pairs % P != 0 || xrow_threads<MX>(P) > 1024) return -1;
+  if (PB < 1 || PB > d.nkx) return -1;
   if (((PB * FftPlan<MZ>::A + 63) / 64) * 64 > zkernel_threads<MZ>()) return -1;  // the z kernels' bound
   const int nblk = (d.nkx + PB - 1) / PB;
   const size_t shz = (size_t)(MZ + (size_t)PB * FftLds<MZ>::LS) * sizeof(cplx);
@@ -598,36 +734,59 @@ static int launch_plane2(const Dims& d, const PlaneChan* chans, int nch, const P
   constexpr int ZA = FftPlan<MZ>::A;
   const int zthr = ((PB * ZA + 63) / 64) * 64;
   const unsigned nyz = (unsigned)(d.ny * nch);
-  timed_launch(tm, KC_ZINV, k_zinv2<MZ>, dim3(nblk, 6, nyz), dim3(zthr), shz, st, chans, d.ny, PB);
-  timed_launch(tm, KC_XROW, k_xrow2<MX>, dim3(pairs / P, nyz), dim3(xrow_threads<MX>(P)), xrow_lds<MX>(P), st,
-               chans, d.ny, P);
+  if (t.fused) {
+    if constexpr (zx_fusable<MZ, MX>()) {
+      using ZP = ZxPlan<MZ, MX>;
+      if (d.nkx != ZP::NKX || P != ZP::P) return -1;
+      const long nodes = (long)d.ny * nch;
+      const long nblocks = (nodes + 7) / 8 * 8 * ZP::NG;
+      if (nblocks > 0x7fffffffL) return -1;
+      timed_launch(tm, KC_XROW, k_zxrow<MZ, MX>, dim3((unsigned)nblocks), dim3(ZP::THREADS),
+                   (size_t)ZP::LDS_CPLX * sizeof(cplx), st, chans, d.ny, (int)nodes);
+    } else {
+      return -1;
+    }
+  } else {
+    if (P < 1 || pairs % P != 0 || xrow_threads<MX>(P) > 1024) return -1;
+    timed_launch(tm, KC_ZINV, k_zinv2<MZ>, dim3(nblk, 6, nyz), dim3(zthr), shz, st, chans, d.ny, PB);
+    timed_launch(tm, KC_XROW, k_xrow2<MX>, dim3(pairs / P, nyz), dim3(xrow_threads<MX>(P)), xrow_lds<MX>(P), st,
+                 chans, d.ny, P);
+  }
   timed_launch(tm, KC_ZFWD, k_zfwd2<MZ>, dim3(nblk, 3, nyz), dim3(zthr), shf, st, chans, d.ny, PB);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 // Valid tilings: z-kernel blocks of 8, 16 or 32 pencils (at most N_x/2); x-row blocks of P
-// pairs of rows with P dividing M_z/2, at most 1024 threads and 80 KiB of LDS.
+// pairs of rows with P dividing M_z/2, at most 1024 threads and 80 KiB of LDS; where M_z and
+// M_x are 48 or 96, also the fused z inverse and x rows with each of those z-forward blocks.
+// form: 0 every tiling, 1 only the three-launch ones, 2 only the fused ones.
 template <int MZ, int MX>
-static void tiles2(const Dims& d, std::vector<PlaneTiles>* out) {
+static void tiles2(const Dims& d, std::vector<PlaneTiles>* out, int form) {
   const int pairs = MZ / 2;
   std::vector<int> pbs;
   for (int pb : {8, 16, 32})
     if (pb <= d.nkx) pbs.push_back(pb);
   if (pbs.empty()) pbs.push_back(d.nkx);
-  for (int P = 1; P <= pairs; ++P) {
-    if (pairs % P != 0 || xrow_threads<MX>(P) > 1024 || xrow_lds<MX>(P) > 80 * 1024) continue;
-    for (int pb : pbs) out->push_back(PlaneTiles{pb, P});
+  if (form != 2) {
+    for (int P = 1; P <= pairs; ++P) {
+      if (pairs % P != 0 || xrow_threads<MX>(P) > 1024 || xrow_lds<MX>(P) > 80 * 1024) continue;
+      for (int pb : pbs) out->push_back(PlaneTiles{pb, P, 0});
+    }
+  }
+  if constexpr (zx_fusable<MZ, MX>()) {
+    if (form != 1 && d.nkx == ZxPlan<MZ, MX>::NKX)
+      for (int pb : pbs) out->push_back(PlaneTiles{pb, ZxPlan<MZ, MX>::P, 1});
   }
 }
 
 template <int MZ>
 static int dispatch_mx(const Dims& d, const PlaneChan* chans, int nch, const PlaneTiles& t, hipStream_t st,
-                       KernelTimer* tm, std::vector<PlaneTiles>* tiles) {
+                       KernelTimer* tm, std::vector<PlaneTiles>* tiles, int form) {
   switch (d.mx) {
 #define CHANENV_MX(M)                                              \
     case M:                                                       \
       if (tiles) {                                                \
-        tiles2<MZ, M>(d, tiles);                                  \
+        tiles2<MZ, M>(d, tiles, form);                            \
         return 0;                                                 \
       }                                                           \
       return launch_plane2<MZ, M>(d, chans, nch, t, st, tm);
@@ -643,14 +802,14 @@ static int dispatch_mx(const Dims& d, const PlaneChan* chans, int nch, const Pla
 }
 
 static int dispatch_mz(const Dims& d, const PlaneChan* chans, int nch, const PlaneTiles& t, hipStream_t st,
-                       KernelTimer* tm, std::vector<PlaneTiles>* tiles) {
+                       KernelTimer* tm, std::vector<PlaneTiles>* tiles, int form) {
   switch (d.mz) {
-    case 6: return dispatch_mx<6>(d, chans, nch, t, st, tm, tiles);
-    case 12: return dispatch_mx<12>(d, chans, nch, t, st, tm, tiles);
-    case 24: return dispatch_mx<24>(d, chans, nch, t, st, tm, tiles);
-    case 48: return dispatch_mx<48>(d, chans, nch, t, st, tm, tiles);
-    case 96: return dispatch_mx<96>(d, chans, nch, t, st, tm, tiles);
-    case 192: return dispatch_mx<192>(d, chans, nch, t, st, tm, tiles);
+    case 6: return dispatch_mx<6>(d, chans, nch, t, st, tm, tiles, form);
+    case 12: return dispatch_mx<12>(d, chans, nch, t, st, tm, tiles, form);
+    case 24: return dispatch_mx<24>(d, chans, nch, t, st, tm, tiles, form);
+    case 48: return dispatch_mx<48>(d, chans, nch, t, st, tm, tiles, form);
+    case 96: return dispatch_mx<96>(d, chans, nch, t, st, tm, tiles, form);
+    case 192: return dispatch_mx<192>(d, chans, nch, t, st, tm, tiles, form);
     default: return -1;
   }
 }
@@ -659,12 +818,12 @@ int launch_plane_pass(const Dims& d, const PlaneChan* chans, int nch, const Plan
                       KernelTimer* tm) {
   if (nch < 1) return 0;
   if ((size_t)d.ny * nch > 65535) return -1;   // grid z limit
-  return dispatch_mz(d, chans, nch, t, st, tm, nullptr);
+  return dispatch_mz(d, chans, nch, t, st, tm, nullptr, 0);
 }
 
-int plane_tile_candidates(const Dims& d, std::vector<PlaneTiles>* out) {
+int plane_tile_candidates(const Dims& d, std::vector<PlaneTiles>* out, int form) {
   out->clear();
-  const int rc = dispatch_mz(d, nullptr, 0, PlaneTiles{0, 0}, nullptr, nullptr, out);
+  const int rc = dispatch_mz(d, nullptr, 0, PlaneTiles{0, 0, 0}, nullptr, nullptr, out, form);
   return (rc == 0 && !out->empty()) ? 0 : -1;
 }
 

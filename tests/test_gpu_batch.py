@@ -267,6 +267,8 @@ def test_batch_tuning_reported():
     assert t[0]["columns_per_block"] in (2, 4) and t[1]["columns_per_block"] in (2, 4)
     assert t[2]["columns_per_block"] == 4 and t[3]["columns_per_block"] == 0
     assert all(r["z_pencils_per_block"] > 0 and r["x_pairs_per_block"] > 0 for r in t)
+    # the fused plane form exists for M_z, M_x in {48, 96} only (here the 32x65x32 channels)
+    assert t[1]["plane_fused"] in (0, 1) and all(r["plane_fused"] == 0 for k, r in enumerate(t) if k != 1)
     batch.close()
     for e in envs:
         e.close()
