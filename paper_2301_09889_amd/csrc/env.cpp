@@ -821,10 +821,23 @@ int tune_plane(chan_batch* b, int shape, const std::vector<chan_env*>& members) 
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t err = hipEventCreate(&e0);
   if (err == hipSuccess) err = hipEventCreate(&e1);
-  // Every candidate is timed in each of ROUNDS sweeps over the list (REPS back-to-back plane
+  // Every candidate is timed in each of ROUNDS sweeps over the list (reps back-to-back plane
   // passes after one warm-up) and keeps its best sweep, so that clock ramps and one-off
-  // stalls do not decide the choice.
-  constexpr int REPS = 4, ROUNDS = 3;
+  // stalls do not decide the choice.  reps (4 to 64) makes a sweep last about 1 ms, from the
+  // time of one pass with the last tiling: tilings a few per cent apart are not ranked on a
+  // window of a hundred microseconds.
+  constexpr int ROUNDS = 3;
+  int reps = 4;
+  if (err == hipSuccess && !launch_plane_pass(sh.d, g.d_plane, nm, cands.back(), c.stream, nullptr)) {
+    float ms = 0.0f;
+    err = hipEventRecord(e0, c.stream);
+    if (err == hipSuccess && launch_plane_pass(sh.d, g.d_plane, nm, cands.back(), c.stream, nullptr))
+      err = hipErrorLaunchFailure;
+    if (err == hipSuccess) err = hipEventRecord(e1, c.stream);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err == hipSuccess && ms > 0.0f) reps = std::min(64, std::max(4, (int)std::ceil(1.0f / ms)));
+  }
   std::vector<float> best_ms(cands.size(), 0.0f);
   std::vector<char> ran(cands.size(), 0);
   for (int round = 0; round < ROUNDS && err == hipSuccess; ++round) {
@@ -832,7 +845,7 @@ int tune_plane(chan_batch* b, int shape, const std::vector<chan_env*>& members) 
       const PlaneTiles& t = cands[k];
       if (launch_plane_pass(sh.d, g.d_plane, nm, t, c.stream, nullptr)) continue;  // warm-up
       err = hipEventRecord(e0, c.stream);
-      for (int r = 0; r < REPS && err == hipSuccess; ++r)
+      for (int r = 0; r < reps && err == hipSuccess; ++r)
         if (launch_plane_pass(sh.d, g.d_plane, nm, t, c.stream, nullptr)) err = hipErrorLaunchFailure;
       if (err == hipSuccess) err = hipEventRecord(e1, c.stream);
       if (err == hipSuccess) err = hipEventSynchronize(e1);
