@@ -39,12 +39,13 @@ RE395 = dict(nx=128, ny=97, nz=128, lx=2 * np.pi, lz=np.pi, re_tau=395.0, dt_plu
 # KiB per dispatch; profiles/hbm_traffic_larger_channel.md).  FETCH_SIZE is scaled by 2.0 and
 # WRITE_SIZE by 1.0: what the two counters read for the 256 MiB device copy of --copy-probe
 # (131084 and 262144 KiB).  Each figure holds for the kernel source with the listed SHA-256
-# and is reported as null for any other source.
+# (plane_pass.hip includes small_dft.inc, unchanged since) and is reported as null for any
+# other source.  The plane figures are the three-launch form the tuner keeps for one channel.
 TRAFFIC = {
     "column_solve_reconstruct": (3.8932e+07, "column_pass.hip", "d9c39fcd5336c91daa763a605300bc19ab60214ffbb05590762bcbdc319b2779"),
-    "x_rows_fft_product": (2.8930e+07, "plane_pass.hip", "26b0d8c0508981163fce8e53bd5b1d249137085fbae50dc7aac0110d63f16773"),
-    "z_inverse_fft": (3.2062e+07, "plane_pass.hip", "26b0d8c0508981163fce8e53bd5b1d249137085fbae50dc7aac0110d63f16773"),
-    "z_forward_fft": (1.6095e+07, "plane_pass.hip", "26b0d8c0508981163fce8e53bd5b1d249137085fbae50dc7aac0110d63f16773"),
+    "x_rows_fft_product": (2.8924e+07, "plane_pass.hip", "083a2fe67463dfc67c26aca3bb569914d5e0bfa6a8d1a106a5cadb88df8d38c7"),
+    "z_inverse_fft": (3.2070e+07, "plane_pass.hip", "083a2fe67463dfc67c26aca3bb569914d5e0bfa6a8d1a106a5cadb88df8d38c7"),
+    "z_forward_fft": (1.6094e+07, "plane_pass.hip", "083a2fe67463dfc67c26aca3bb569914d5e0bfa6a8d1a106a5cadb88df8d38c7"),
     "column_pass": (2.4452e+07, "column_pass.hip", "d9c39fcd5336c91daa763a605300bc19ab60214ffbb05590762bcbdc319b2779"),
     "column_reconstruct": (1.7564e+07, "column_pass.hip", "d9c39fcd5336c91daa763a605300bc19ab60214ffbb05590762bcbdc319b2779"),
 }
