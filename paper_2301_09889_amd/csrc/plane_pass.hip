@@ -179,7 +179,7 @@ __global__ __launch_bounds__(zkernel_threads<L>()) void k_zfwd2(const PlaneChan*
 
 // ---------------------------------------------------------------------------
 // x rows on a block's staged sequences S[field * P + pair][LS] (the packed spectra of P pairs
-// of padded z rows of node j, see k_xrow2): six inverse real FFTs, the products, three
+// of padded z rows of node j, see k_xrow2, and a zero at S[.][2 N_x/2]): six inverse real FFTs, the products, three
 // forward FFTs and the unpacking, one task per thread in every phase (the block has 6 P A
 // threads).  Pair pr holds rows z = row0 + rstep pr and z + 1; the products go to W3 unless
 // skip.  Pass 1 writes each task's A outputs at stride AP, sequences lie LS apart.
@@ -190,12 +190,15 @@ __device__ __forceinline__ void xrow_body(const PlaneChan& A, cplx* S, const cpl
   constexpr int FA = FftPlan<L>::A, FB = FftPlan<L>::B;
   static_assert(FA >= FB, "pass 1 has at most one task per thread");
   static_assert(LS > L && LS >= (FB - 1) * AP + FA, "LDS sequence stride too small");
-  const int nkx = A.nkx, ny = A.ny;
+  static_assert(2 * (L / 3) < LS, "room for the zero slot after the packed spectrum");
+  constexpr int nkx = L / 3;  // stored x modes N_x/2 (M_x = 3 N_x/2; checked at launch)
+  const int ny = A.ny;
   const int mz = 3 * A.nz / 2;
   const int tid = threadIdx.x, nthr = blockDim.x;
   // 1. inverse pass 1, one task (f, pair, n2) per thread: the packed spectrum k = B n1 + n2 is
-  // read into registers, then (after every task has read its inputs) transformed and written
-  // back over the staged rows
+  // read into registers (the unstored modes from the sequence's zero slot S[seq][2 nkx], so that
+  // every read is unconditional), then (after every task has read its inputs) transformed and
+  // written back over the staged rows
   {
     const int task = tid;
     const bool have = task < 6 * P * FB;
@@ -206,7 +209,7 @@ __device__ __forceinline__ void xrow_body(const PlaneChan& A, cplx* S, const cpl
 #pragma unroll
       for (int n1 = 0; n1 < FA; ++n1) {
         const int k = FB * n1 + n2;
-        t[n1] = (k < nkx) ? z[k] : ((k > L - nkx) ? z[nkx + (L - k)] : cz());
+        t[n1] = z[(k < nkx) ? k : ((k > L - nkx) ? nkx + (L - k) : 2 * nkx)];
       }
     }
     __syncthreads();
@@ -320,26 +323,45 @@ __global__ __launch_bounds__(1024) void k_xrow2(const PlaneChan* __restrict__ ch
   const PlaneChan A = chans[blockIdx.y / nyc];
   const bool skip = (*A.status & STATUS_BAD_ACTION) != 0;  // tested at the stores
   const int pair0 = blockIdx.x * P, j = blockIdx.y % nyc;
-  const int nkx = A.nkx, ny = A.ny;
+  constexpr int nkx = L / 3;  // stored x modes N_x/2 (checked at launch)
+  const int ny = A.ny;
   const int mz = 3 * A.nz / 2;
   const int tid = threadIdx.x, nthr = blockDim.x;
   for (int t = tid; t < L; t += nthr) tw[t] = A.twx[t];
   // 0. stage the rows: for every (field, pair) sequence and stored mode m < N_x/2, the packed
   // spectrum P_m = a_m + i b_m of the two rows (a_0, b_0 real) at S[seq][m] and the packed
   // conjugates Q_m = conj(a_m) + i conj(b_m), which give modes L - m, at S[seq][nkx + m]
-  // (2 nkx <= L + 1 slots).  Each stored mode is loaded once, coalesced.
-  for (int it = tid; it < 6 * P * nkx; it += nthr) {
-    const int seq = it / nkx, m = it - seq * nkx;
-    const int f = seq / P, pr = seq - f * P;
-    const int za = 2 * (pair0 + pr);
-    const cplx* ra = A.Z6 + (((size_t)f * ny + j) * mz + za) * nkx;
-    cplx xa = ra[m], xb = ra[nkx + m];
-    if (m == 0) {
-      xa.y = 0.0;
-      xb.y = 0.0;
+  // (2 nkx <= L + 1 slots), and a zero at S[seq][2 nkx].  Each stored mode is loaded once,
+  // coalesced; a thread issues the loads of all its items (at most IT: the block has 6 P A
+  // threads and N_x/2 = L/3 modes per sequence) before it waits for any.
+  constexpr int IT = (nkx + FftPlan<L>::A - 1) / FftPlan<L>::A;
+  cplx xa[IT], xb[IT];
+#pragma unroll
+  for (int r = 0; r < IT; ++r) {
+    const int it = tid + r * nthr;
+    if (it < 6 * P * nkx) {
+      const int seq = it / nkx, m = it - seq * nkx;
+      const int f = seq / P, pr = seq - f * P;
+      const int za = 2 * (pair0 + pr);
+      const cplx* ra = A.Z6 + (((size_t)f * ny + j) * mz + za) * nkx;
+      xa[r] = ra[m];
+      xb[r] = ra[nkx + m];
     }
-    S[seq * LP + m] = make_double2(xa.x - xb.y, xa.y + xb.x);
-    S[seq * LP + nkx + m] = make_double2(xa.x + xb.y, xb.x - xa.y);
+  }
+#pragma unroll
+  for (int r = 0; r < IT; ++r) {
+    const int it = tid + r * nthr;
+    if (it < 6 * P * nkx) {
+      const int seq = it / nkx, m = it - seq * nkx;
+      cplx a = xa[r], b = xb[r];
+      if (m == 0) {
+        a.y = 0.0;
+        b.y = 0.0;
+        S[seq * LP + 2 * nkx] = cz();
+      }
+      S[seq * LP + m] = make_double2(a.x - b.y, a.y + b.x);
+      S[seq * LP + nkx + m] = make_double2(a.x + b.y, b.x - a.y);
+    }
   }
   __syncthreads();
   xrow_body<L, LP, FftLds<L>::AP>(A, S, tw, P, j, 2 * pair0, 2, skip);
@@ -449,10 +471,12 @@ __global__ __launch_bounds__((ZxPlan<MZ, MX>::THREADS)) void k_zxrow(const Plane
       }
       if (have) {
         cplx* seq = S + (f * P + k2) * LS;
-        if (sidx == 0)
+        if (sidx == 0) {
           seq[p] = make_double2(xa.x - xb.y, xa.y + xb.x);
-        else
+        } else {
           seq[NKX + p] = make_double2(xa.x + xb.y, xb.x - xa.y);
+          if (p == 0) seq[2 * NKX] = cz();       // the zero slot the x rows' first pass reads
+        }
       }
     }
   }
@@ -726,7 +750,7 @@ static int launch_plane2(const Dims& d, const PlaneChan* chans, int nch, const P
   }
   const int PB = t.PB, P = t.P;
   const int pairs = MZ / 2;
-  if (PB < 1 || PB > d.nkx) return -1;
+  if (PB < 1 || PB > d.nkx || d.nkx != MX / 3) return -1;
   if (((PB * FftPlan<MZ>::A + 63) / 64) * 64 > zkernel_threads<MZ>()) return -1;  // the z kernels' bound
   const int nblk = (d.nkx + PB - 1) / PB;
   const size_t shz = (size_t)(MZ + (size_t)PB * FftLds<MZ>::LS) * sizeof(cplx);
