@@ -75,13 +75,15 @@ __global__ __launch_bounds__(zkernel_threads<L>()) void k_zinv2(const PlaneChan*
   const bool skip = (*A.status & STATUS_BAD_ACTION) != 0;
   const int p0 = blockIdx.x * PB, f = blockIdx.y, j = blockIdx.z % ny;
   const int np = min(PB, A.nkx - p0);
-  const int nz = A.nz, h = nz / 2;
+  constexpr int nz = 2 * L / 3, h = nz / 2;  // N_z (M_z = 3 N_z/2; checked at launch)
   for (int t = threadIdx.x; t < L; t += blockDim.x) tw[t] = A.twz[t];
   __syncthreads();
   const size_t fj = (size_t)f * A.ny + j;
   const cplx* src = A.F6 + (fj * A.nkx + p0) * nz;
   for (int task = threadIdx.x; task < np * FB; task += blockDim.x) {
-    const int p = task / FB, n2 = task - p * FB;
+    // unsigned, so that n2 < B is known and the padding test of each term n1 folds where all
+    // of its B rows lie on one side
+    const int p = (int)((unsigned)task / FB), n2 = (int)((unsigned)task % FB);
     cplx t[FA];
 #pragma unroll
     for (int n1 = 0; n1 < FA; ++n1) {
@@ -123,7 +125,7 @@ __global__ __launch_bounds__(zkernel_threads<L>()) void k_zfwd2(const PlaneChan*
   const bool skip = (*A.status & STATUS_BAD_ACTION) != 0;  // tested at the stores
   const int p0 = blockIdx.x * PB, g = blockIdx.y, j = blockIdx.z % ny;
   const int np = min(PB, A.nkx - p0);
-  const int nz = A.nz, h = nz / 2;
+  constexpr int nz = 2 * L / 3, h = nz / 2;  // N_z (checked at launch)
   for (int t = threadIdx.x; t < L; t += blockDim.x) tw[t] = A.twz[t];
   __syncthreads();
   const size_t gj = (size_t)g * A.ny + j;
@@ -142,7 +144,7 @@ __global__ __launch_bounds__(zkernel_threads<L>()) void k_zfwd2(const PlaneChan*
   cplx* dst = A.H3 + (gj * A.nkx + p0) * nz;
   const double sc = A.scale;
   for (int task = threadIdx.x; task < np * FA; task += blockDim.x) {
-    const int p = task / FA, k1 = task - p * FA;
+    const int p = (int)((unsigned)task / FA), k1 = (int)((unsigned)task % FA);  // k1 < A known
     cplx u[FB];
 #pragma unroll
     for (int n2 = 0; n2 < FB; ++n2) u[n2] = Y[p * LP + n2 * AP + k1];
@@ -414,7 +416,7 @@ __global__ __launch_bounds__((ZxPlan<MZ, MX>::THREADS)) void k_zxrow(const Plane
   const int j = node % ny;
   const bool skip = (*A.status & STATUS_BAD_ACTION) != 0;  // tested at the stores
   const int kb = 2 * grp;                        // this block's k1 pair: kb, kb + 1
-  const int nz = A.nz, h = nz / 2;
+  constexpr int nz = 2 * MZ / 3, h = nz / 2;  // N_z (checked at launch)
   const int tid = threadIdx.x, nthr = blockDim.x;
   for (int t = tid; t < MZ; t += nthr) twz[t] = A.twz[t];
   if (MX != MZ)
@@ -423,7 +425,7 @@ __global__ __launch_bounds__((ZxPlan<MZ, MX>::THREADS)) void k_zxrow(const Plane
   // z pass 1, tasks (f, p, n2): the full DFT over n1 of x[B n1 + n2] (zero padding as in
   // k_zinv2), outputs kb and kb + 1 twiddled and kept
   for (int task = tid; task < 6 * NKX * ZB; task += nthr) {
-    const int fp = task / ZB, n2 = task - fp * ZB;
+    const int fp = (int)((unsigned)task / ZB), n2 = (int)((unsigned)task % ZB);  // n2 < B known
     const int f = fp / NKX, p = fp - f * NKX;
     const cplx* src = A.F6 + (((size_t)f * A.ny + j) * NKX + p) * nz;
     cplx t[ZA];
@@ -522,7 +524,7 @@ __global__ __launch_bounds__((SmallPlane<MZ, MX>::THREADS)) void k_plane_small(c
   const PlaneChan A = chans[blockIdx.x / ny];
   const bool skip = (*A.status & STATUS_BAD_ACTION) != 0;  // tested at the stores
   const int j = blockIdx.x % ny;
-  const int nz = A.nz, h = nz / 2;
+  constexpr int nz = 2 * MZ / 3, h = nz / 2;  // N_z (checked at launch)
   const int tid = threadIdx.x, nthr = blockDim.x;
   for (int t = tid; t < MZ; t += nthr) twz[t] = A.twz[t];
   for (int t = tid; t < MX; t += nthr) twx[t] = A.twx[t];
@@ -531,7 +533,7 @@ __global__ __launch_bounds__((SmallPlane<MZ, MX>::THREADS)) void k_plane_small(c
   // A. z inverse of every (field, p) pencil (k_zinv2)
   for (int task = tid; task < 6 * NKX * ZB; task += nthr) {
     const int f = task / (NKX * ZB), rem = task - f * NKX * ZB;
-    const int p = rem / ZB, n2 = rem - p * ZB;
+    const int p = (int)((unsigned)rem / ZB), n2 = (int)((unsigned)rem % ZB);  // n2 < B known
     const cplx* src = A.F6 + (((size_t)f * A.ny + j) * NKX + p) * nz;
     cplx t[ZA];
 #pragma unroll
@@ -740,6 +742,7 @@ static int xrow_threads(int P) { return ((6 * P * FftPlan<MX>::A + 63) / 64) * 6
 template <int MZ, int MX>
 static int launch_plane2(const Dims& d, const PlaneChan* chans, int nch, const PlaneTiles& t, hipStream_t st,
                          KernelTimer* tm) {
+  if (d.nz != 2 * MZ / 3) return -1;       // the kernels take N_z from M_z
   if constexpr (MZ == 24 && MX == 24) {  // one launch per stage for the small planes
     using SP = SmallPlane<MZ, MX>;
     if (d.nkx != SP::NKX) return -1;
