@@ -311,14 +311,22 @@ __device__ __forceinline__ void xrow_body(const PlaneChan& A, cplx* S, const cpl
   }
 }
 
+// Threads of an x-row block of P pairs of rows: one per task of the second pass, 6 P A.
+template <int L>
+constexpr int xrow_threads_c(int P) { return ((6 * P * FftPlan<L>::A + 63) / 64) * 64; }
+
 // ---------------------------------------------------------------------------
 // x rows: block (pair chunk, node); Z6 -> W3.  Each phase gives one task per thread so
 // that the six inverse transforms, the products and the three forward transforms of a
 // block are all in flight together; S holds 6 sequences per pair, transformed in place.
+// PC: the pairs per block as a compile-time constant (the tuner's usual picks, so that the
+// index arithmetic has no division by a run-time P), or 0 for P taken from the argument.
 // ---------------------------------------------------------------------------
-template <int L>
-__global__ __launch_bounds__(1024) void k_xrow2(const PlaneChan* __restrict__ chans, int nyc, int P) {
+template <int L, int PC>
+__global__ __launch_bounds__(PC > 0 ? xrow_threads_c<L>(PC) : 1024) void k_xrow2(const PlaneChan* __restrict__ chans,
+                                                                                  int nyc, int Parg) {
   constexpr int LP = FftLds<L>::LS;
+  const int P = PC > 0 ? PC : Parg;
   extern __shared__ double dyn_lds[];
   cplx* tw = reinterpret_cast<cplx*>(dyn_lds);
   cplx* S = tw + L;         // [field][pair][LP]
@@ -737,7 +745,30 @@ __global__ __launch_bounds__((SmallPlane<MZ, MX>::THREADS)) void k_plane_small(c
 template <int MX>
 static size_t xrow_lds(int P) { return (size_t)(MX + (size_t)6 * P * FftLds<MX>::LS) * sizeof(cplx); }
 template <int MX>
-static int xrow_threads(int P) { return ((6 * P * FftPlan<MX>::A + 63) / 64) * 64; }
+static int xrow_threads(int P) { return xrow_threads_c<MX>(P); }
+
+// k_xrow2 with P pairs per block: the compile-time instance for the usual P, else the generic one.
+template <int MX, int PC>
+static void launch_xrow_pc(KernelTimer* tm, dim3 grid, int P, hipStream_t st, const PlaneChan* chans, int ny) {
+  if constexpr (PC > 0 && xrow_threads_c<MX>(PC) <= 1024) {
+    timed_launch(tm, KC_XROW, k_xrow2<MX, PC>, grid, dim3(xrow_threads<MX>(P)), xrow_lds<MX>(P), st, chans, ny, P);
+  } else {
+    timed_launch(tm, KC_XROW, k_xrow2<MX, 0>, grid, dim3(xrow_threads<MX>(P)), xrow_lds<MX>(P), st, chans, ny, P);
+  }
+}
+template <int MX>
+static void launch_xrow(KernelTimer* tm, dim3 grid, int P, hipStream_t st, const PlaneChan* chans, int ny) {
+  switch (P) {
+    case 1: launch_xrow_pc<MX, 1>(tm, grid, P, st, chans, ny); break;
+    case 2: launch_xrow_pc<MX, 2>(tm, grid, P, st, chans, ny); break;
+    case 3: launch_xrow_pc<MX, 3>(tm, grid, P, st, chans, ny); break;
+    case 4: launch_xrow_pc<MX, 4>(tm, grid, P, st, chans, ny); break;
+    case 6: launch_xrow_pc<MX, 6>(tm, grid, P, st, chans, ny); break;
+    case 8: launch_xrow_pc<MX, 8>(tm, grid, P, st, chans, ny); break;
+    case 12: launch_xrow_pc<MX, 12>(tm, grid, P, st, chans, ny); break;
+    default: launch_xrow_pc<MX, 0>(tm, grid, P, st, chans, ny); break;
+  }
+}
 
 template <int MZ, int MX>
 static int launch_plane2(const Dims& d, const PlaneChan* chans, int nch, const PlaneTiles& t, hipStream_t st,
@@ -776,8 +807,7 @@ static int launch_plane2(const Dims& d, const PlaneChan* chans, int nch, const P
   } else {
     if (P < 1 || pairs % P != 0 || xrow_threads<MX>(P) > 1024) return -1;
     timed_launch(tm, KC_ZINV, k_zinv2<MZ>, dim3(nblk, 6, nyz), dim3(zthr), shz, st, chans, d.ny, PB);
-    timed_launch(tm, KC_XROW, k_xrow2<MX>, dim3(pairs / P, nyz), dim3(xrow_threads<MX>(P)), xrow_lds<MX>(P), st,
-                 chans, d.ny, P);
+    launch_xrow<MX>(tm, dim3(pairs / P, nyz), P, st, chans, d.ny);
   }
   timed_launch(tm, KC_ZFWD, k_zfwd2<MZ>, dim3(nblk, 3, nyz), dim3(zthr), shf, st, chans, d.ny, PB);
   return hipGetLastError() == hipSuccess ? 0 : -1;
