@@ -252,9 +252,30 @@ __device__ __forceinline__ void dct_mfma(cplx* const* X, const double* __restric
   dbl4 de[T], dd[T];
 #pragma unroll
   for (int t = 0; t < T; ++t) de[t] = dd[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+  // The cosines of step ks + 1 are requested before the products of step ks, so that their
+  // load overlaps the matrix instructions instead of stalling each step (the same operands in
+  // the same order).  Steps ks < H/4 have every term k = 4 ks + kq below H; the one after it
+  // (k = H for kq = 0 only) is done last on its own.
+  constexpr int KEF = H / 4;
+  static_assert(KE == KEF + 1 && KO == KEF, "step counts");
+  double an[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) an[t] = cosk[kq * (N + 1) + 2 * (16 * t + col)];
 #pragma unroll 2
-  for (int ks = 0; ks < KE; ++ks) {
+  for (int ks = 0; ks < KEF; ++ks) {
     const int k = 4 * ks + kq;
+    double a[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) a[t] = an[t];
+    const int kn = (ks + 1 < KEF) ? k + 4 : k;  // the last step reloads its own (unused)
+#pragma unroll
+    for (int t = 0; t < T; ++t) an[t] = cosk[kn * (N + 1) + 2 * (16 * t + col)];
+    const double b = xf ? xf[2 * k + part] : 0.0;
+#pragma unroll
+    for (int t = 0; t < T; ++t) de[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b, de[t], 0, 0, 0);
+  }
+  {
+    const int k = 4 * KEF + kq;
     const bool in = k <= H;
     const double b = (xf && in) ? xf[2 * k + part] : 0.0;
 #pragma unroll
@@ -263,15 +284,20 @@ __device__ __forceinline__ void dct_mfma(cplx* const* X, const double* __restric
       de[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, de[t], 0, 0, 0);
     }
   }
+#pragma unroll
+  for (int t = 0; t < T; ++t) an[t] = cosk[kq * (N + 1) + 2 * (16 * t + col) + 1];
 #pragma unroll 2
   for (int ks = 0; ks < KO; ++ks) {
     const int k = 4 * ks + kq;
+    double a[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) a[t] = an[t];
+    const int kn = (ks + 1 < KO) ? k + 4 : k;
+#pragma unroll
+    for (int t = 0; t < T; ++t) an[t] = cosk[kn * (N + 1) + 2 * (16 * t + col) + 1];
     const double b = xf ? xf[2 * (N - k) + part] : 0.0;
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-      const double a = cosk[k * (N + 1) + 2 * (16 * t + col) + 1];
-      dd[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, dd[t], 0, 0, 0);
-    }
+    for (int t = 0; t < T; ++t) dd[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b, dd[t], 0, 0, 0);
   }
   wave_sync();
   if (xf) {
