@@ -548,12 +548,23 @@ __device__ __forceinline__ void tau_chain_wave(cplx* const* R, const double* TAB
   constexpr int OPSZ = 4 * ML + 2;
   static_assert(N / 2 <= 64, "one lane per elimination index");
   const int i = lane + 1;
+  // both parities' coefficients requested up front (lanes past m read row m and discard it), so
+  // that their loads overlap instead of following each parity's scans
+  double tw[2], tu[2], tf[2], tsc[2];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const double* tab = TAB + s * OPSZ;
+    const int ic = min(i, (N - s) / 2);
+    tw[s] = tab[ic];
+    tu[s] = tab[ML + ic];
+    tf[s] = tab[2 * ML + ic];
+    tsc[s] = tab[4 * ML];
+  }
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
     const int m = (N - s) / 2;
     const bool act = i <= m;
-    const double w = act ? tab[i] : 0.0, u = act ? tab[ML + i] : 0.0, f = act ? tab[2 * ML + i] : 0.0;
+    const double w = act ? tw[s] : 0.0, u = act ? tu[s] : 0.0, f = act ? tf[s] : 0.0;
     cplx a[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) a[k] = act ? cscale(R[k][2 * i + s], w) : cz();
@@ -563,7 +574,7 @@ __device__ __forceinline__ void tau_chain_wave(cplx* const* R, const double* TAB
     for (int k = 0; k < K; ++k) {
       if (act) E[k][2 * i + s] = a[k];
       const cplx sum = wave_sum(act ? a[k] : cz());
-      x0[2 * k + s] = cscale(csub(g[2 * k + s], sum), tab[4 * ML]);
+      x0[2 * k + s] = cscale(csub(g[2 * k + s], sum), tsc[s]);
     }
   }
 }
@@ -589,6 +600,14 @@ __device__ __forceinline__ void refine_rows(cplx* xs, const double* TAB, cplx ge
   constexpr int NS = CP<N>::NS;
   constexpr int ML = N / 2 + 1;
   constexpr int OPSZ = 4 * ML + 2;
+  // the record's values requested before the sums they follow (elements past N read element N)
+  const double re = TAB[4 * ML], ro = TAB[OPSZ + 4 * ML];
+  double fw[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int ec = min(lane + 64 * s, N);
+    fw[s] = TAB[(ec & 1) * OPSZ + 3 * ML + (ec >> 1)];
+  }
   cplx se = cz(), so = cz();
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
@@ -600,12 +619,12 @@ __device__ __forceinline__ void refine_rows(cplx* xs, const double* TAB, cplx ge
   }
   se = wave_sum(se);
   so = wave_sum(so);
-  const cplx de = cscale(csub(se, ge), -TAB[4 * ML]);
-  const cplx dodd = cscale(csub(so, go), -TAB[OPSZ + 4 * ML]);
+  const cplx de = cscale(csub(se, ge), -re);
+  const cplx dodd = cscale(csub(so, go), -ro);
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int e = lane + 64 * s;
-    if (e <= N) xs[s] = caxpy(xs[s], TAB[(e & 1) * OPSZ + 3 * ML + (e >> 1)], (e & 1) ? dodd : de);
+    if (e <= N) xs[s] = caxpy(xs[s], fw[s], (e & 1) ? dodd : de);
   }
 }
 
