@@ -450,6 +450,32 @@ __device__ __forceinline__ cplx tau_rows(const cplx* f, const double* __restrict
   return r;
 }
 
+// The tau-row coefficients of the lane's elements e = lane + 64 s, requested together (an
+// element past N reads row N and does not use it), so that a loop over the lane's elements
+// waits for memory once.
+template <int N>
+struct RcLane {
+  double c0[CP<N>::NS], c1[CP<N>::NS], c2[CP<N>::NS];
+  __device__ __forceinline__ RcLane(const double* __restrict__ rc, int lane) {
+    constexpr int NY = N + 1;
+#pragma unroll
+    for (int s = 0; s < CP<N>::NS; ++s) {
+      const int n = min(lane + 64 * s, N);
+      c0[s] = rc[n];
+      c1[s] = rc[NY + n];
+      c2[s] = rc[2 * NY + n];
+    }
+  }
+  // tau_rows of element n = lane + 64 s (n <= N) with these coefficients
+  __device__ __forceinline__ cplx rows(const cplx* f, int s, int n) const {
+    if (n < 2) return cz();
+    cplx r = cscale(f[n - 2], c0[s]);
+    r = caxpy(r, -c1[s], f[n]);
+    if (n + 2 <= N) r = caxpy(r, c2[s], f[n + 2]);
+    return r;
+  }
+};
+
 // x moved by the DPP pattern CTRL; a lane whose source lies outside its row keeps id (the
 // identity of the composition being scanned).
 template <int CTRL>
@@ -587,6 +613,26 @@ __device__ __forceinline__ cplx tau_value(const cplx* E, const double* TAB, cons
   const cplx base = (i == 0) ? cz() : E[e];
   return caxpy(base, TAB[s * OPSZ + 3 * ML + i], x0[s]);
 }
+
+// The homogeneous solutions F of the lane's elements e = lane + 64 s in an operator record,
+// requested together (an element past N reads element N); tau_value with them.
+template <int N>
+struct TauF {
+  double f[CP<N>::NS];
+  __device__ __forceinline__ TauF(const double* TAB, int lane) {
+    constexpr int ML = N / 2 + 1;
+    constexpr int OPSZ = 4 * ML + 2;
+#pragma unroll
+    for (int s = 0; s < CP<N>::NS; ++s) {
+      const int e = min(lane + 64 * s, N);
+      f[s] = TAB[(e & 1) * OPSZ + 3 * ML + (e >> 1)];
+    }
+  }
+  __device__ __forceinline__ cplx value(const cplx* E, const cplx* x0, int s, int e) const {
+    const cplx base = ((e >> 1) == 0) ? cz() : E[e];
+    return caxpy(base, f[s], x0[e & 1]);
+  }
+};
 
 // The Dirichlet rows x(+1) = g_t, x(-1) = g_b of a tau solution held in registers (element
 // e = lane + 64 slot), to rounding.  x0 = (g - sum E) / sum F cancels heavily when lam is large
@@ -779,10 +825,18 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
       }
       // operator record of D^2 - lam for this column and stage (read where used)
       TAB = A.optab + ((size_t)crec * NOPS + r) * 2 * P::OPSZ;
-      wave_sync();
-      for (int e = lane; e <= N; e += 64) {
-        B[2][e] = tau_rows<N>(B[0], A.rc, e);
-        B[3][e] = tau_rows<N>(B[1], A.rc, e);
+      const TauF<N> tf1(TAB, lane);
+      {
+        const RcLane<N> rq(A.rc, lane);
+        wave_sync();
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const int e = lane + 64 * s;
+          if (e <= N) {
+            B[2][e] = rq.rows(B[0], s, e);
+            B[3][e] = rq.rows(B[1], s, e);
+          }
+        }
       }
       wave_sync();
       // (e) phi_p and omega_y: both parities of both systems as wave-wide scans
@@ -803,8 +857,8 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
           const int e = lane + 64 * s;
           xp[s] = xw[s] = cz();
           if (e <= N) {
-            xp[s] = tau_value<N>(B[4], TAB, SC, e);
-            xw[s] = tau_value<N>(B[5], TAB, SC + 2, e);
+            xp[s] = tf1.value(B[4], SC, s, e);
+            xw[s] = tf1.value(B[5], SC + 2, s, e);
           }
         }
         refine_rows<N>(xp, TAB, cz(), cz(), lane);
@@ -828,7 +882,15 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
         vw = caxpy(o, A.s_ramp, csub(nn, o));
       }
       TAB = A.optab + ((size_t)crec * NOPS + 3) * 2 * P::OPSZ;
-      for (int e = lane; e <= N; e += 64) B[2][e] = tau_rows<N>(B[6], A.rc, e);
+      const TauF<N> tf3(TAB, lane);
+      {
+        const RcLane<N> rq(A.rc, lane);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const int e = lane + 64 * s;
+          if (e <= N) B[2][e] = rq.rows(B[6], s, e);
+        }
+      }
       wave_sync();
       {
         // even part (g_top + g_bot)/2, odd part (g_top - g_bot)/2 with g_top = 0, g_bot = v_w
@@ -849,7 +911,7 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         const int e = lane + 64 * s;
-        vp[s] = (e <= N) ? tau_value<N>(B[3], TAB, SC + 4, e) : cz();
+        vp[s] = (e <= N) ? tf3.value(B[3], SC + 4, s, e) : cz();
       }
       refine_rows<N>(vp, TAB, cscale(vw, 0.5), cscale(vw, -0.5), lane);
 #pragma unroll
@@ -937,8 +999,16 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
           B[0][e] = rr;
         }
       }
-      wave_sync();
-      for (int e = lane; e <= N; e += 64) B[2][e] = tau_rows<N>(B[0], A.rc, e);
+      const TauF<N> tfm(TAB, lane);
+      {
+        const RcLane<N> rq(A.rc, lane);
+        wave_sync();
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const int e = lane + 64 * s;
+          if (e <= N) B[2][e] = rq.rows(B[0], s, e);
+        }
+      }
       wave_sync();
       {
         cplx* const Rs[1] = {B[2]};
@@ -958,7 +1028,7 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
       for (int s = 0; s < NS; ++s) {
         const int e = lane + 64 * s;
         xs[s] = cz();
-        if (e <= N) xs[s] = tau_value<N>(B[3], TAB, SC, e);
+        if (e <= N) xs[s] = tfm.value(B[3], SC, s, e);
       }
       refine_rows<N>(xs, TAB, cz(), cz(), lane);
       if (A.open) {  // dU/dxi(+1) = dW/dxi(+1) = 0: add c phi_+ (k = 0)
