@@ -152,7 +152,7 @@ static void invalid_inputs() {
   CHECK(chan_graph_launch(nullptr, nullptr, &call) == CHAN_EINVAL, "launch without a graph");
   CHECK(call == nullptr, "launch without a graph leaves *out null");
   chan_graph_destroy(nullptr);
-  int32_t rec[6];
+  int32_t rec[7];  // one tuning record
   CHECK(chan_batch_tuning(nullptr, 1, rec) == CHAN_EINVAL, "tuning of no batch");
   for (int code = -8; code <= 0; ++code) CHECK(chan_strerror(code) != nullptr, "strerror(%d)", code);
   CHECK(chan_last_error() != nullptr, "last error");
