@@ -134,18 +134,24 @@ struct CP {
   static constexpr int NS = (NY + 63) / 64;  // element slots per lane
   static constexpr int ML = N / 2 + 1;
   static constexpr int OPSZ = 4 * ML + 2;
-  static constexpr int NB = 8;               // complex work vectors per wave
+  static constexpr int NB = 6;               // complex work vectors per wave
   static constexpr int NYP = NY + 1;
   // LDS per wave: the work vectors and 32 doubles of small scalars.  The operator records are
   // read from the table in global memory where they are used: staged in LDS as well, a wave took
-  // 16 KB at N = 96 and five two-wave blocks filled a CU (2.5 waves per SIMD); without them six
-  // fit (three per SIMD, the register limit).
+  // 16 KB at N = 96 and five two-wave blocks filled a CU (2.5 waves per SIMD).  Six work vectors
+  // (no phase needs more) take 9.4 KB at N = 96, so that 16 waves (four per SIMD) fit a CU.
   static constexpr int WAVE_DOUBLES = NB * NYP * 2 + 32;
 };
 
 // wavefronts (columns) per block: four for N <= 64, two above (LDS per block < 64 KiB)
 template <int N>
 constexpr int wpb() { return N <= 64 ? 4 : 2; }
+
+// Waves per SIMD the general column kernel asks the compiler for: four at N = 96, which its
+// registers allow without spilling (116), the LDS of six work vectors too; the compiler's own
+// choice otherwise (at N = 128 four would spill 63 registers).
+template <int N>
+constexpr int col_waves() { return N == 96 ? 4 : 1; }
 
 struct ColArgs {
   int nkx, nz, ncol;
@@ -675,7 +681,8 @@ __device__ __forceinline__ void refine_rows(cplx* xs, const double* TAB, cplx ge
 }
 
 template <int N>
-__global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
+__global__ __launch_bounds__(64 * wpb<N>()) __attribute__((amdgpu_waves_per_eu(col_waves<N>())))
+void k_column(ColArgs A) {
   constexpr int WPB = wpb<N>();
   using P = CP<N>;
   constexpr int NY = P::NY;
@@ -864,11 +871,11 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
         refine_rows<N>(xp, TAB, cz(), cz(), lane);
         refine_rows<N>(xw, TAB, cz(), cz(), lane);
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
+        for (int s = 0; s < NS; ++s) {  // over the chain's inputs, no longer needed
           const int e = lane + 64 * s;
           if (e <= N) {
-            B[6][e] = xp[s];
-            B[7][e] = xw[s];
+            B[2][e] = xp[s];  // phi_p
+            B[3][e] = xw[s];  // omega_y
           }
         }
       }
@@ -888,14 +895,14 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
           const int e = lane + 64 * s;
-          if (e <= N) B[2][e] = rq.rows(B[6], s, e);
+          if (e <= N) B[0][e] = rq.rows(B[2], s, e);
         }
       }
       wave_sync();
       {
         // even part (g_top + g_bot)/2, odd part (g_top - g_bot)/2 with g_top = 0, g_bot = v_w
-        cplx* const Rs[1] = {B[2]};
-        cplx* const Es[1] = {B[3]};
+        cplx* const Rs[1] = {B[0]};
+        cplx* const Es[1] = {B[1]};
         const cplx gv[2] = {cscale(vw, 0.5), cscale(vw, -0.5)};
         cplx x0[2];
         tau_chain_wave<N, 1>(Rs, TAB, gv, Es, x0, lane);
@@ -911,7 +918,7 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         const int e = lane + 64 * s;
-        vp[s] = (e <= N) ? tf3.value(B[3], SC + 4, s, e) : cz();
+        vp[s] = (e <= N) ? tf3.value(B[1], SC + 4, s, e) : cz();
       }
       refine_rows<N>(vp, TAB, cscale(vw, 0.5), cscale(vw, -0.5), lane);
 #pragma unroll
@@ -935,7 +942,7 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
       const double* ptc = A.open ? A.pt + ((size_t)crec * 3 + r) * NY : nullptr;
       if (A.open) {
         cplx dw = cz();
-        for (int e = lane; e <= N; e += 64) dw = caxpy(dw, (double)e * (double)e, B[7][e]);
+        for (int e = lane; e <= N; e += 64) dw = caxpy(dw, (double)e * (double)e, B[3][e]);
         dw = wave_sum(dw);
         const double pinv = A.ptinv[(size_t)crec * 3 + r];
         cw = make_double2(-dw.x * pinv, -dw.y * pinv);
@@ -949,7 +956,7 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
           const double t = vt[e];
           const double b = (e & 1) ? -t : t;
           vv[s] = caxpy(caxpy(vp[s], t, c0), b, c1);
-          oo[s] = A.open ? caxpy(B[7][e], ptc[e], cw) : B[7][e];
+          oo[s] = A.open ? caxpy(B[3][e], ptc[e], cw) : B[3][e];
           A.vS[col + e] = vv[s];
           A.oS[col + e] = oo[s];
           if (partner >= 0) {
@@ -1146,7 +1153,7 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
         const cplx v = vv[s];
         B[4][e] = csub(cscale(dw, A.ys), cmuli(cscale(v, be)));
         B[5][e] = csub(cmuli(cscale(v, al)), cscale(du, A.ys));
-        B[6][e] = oo[s];
+        B[1][e] = oo[s];
       }
     }
     wave_sync();
@@ -1173,7 +1180,7 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
         B[3][e] = make_double2(X.y, 0.0);
         B[4][e] = make_double2(A.ys * dX.y, 0.0);
         B[5][e] = make_double2(-(A.ys * dX.x), 0.0);
-        B[6][e] = cz();
+        B[1][e] = cz();
       }
     }
     tau_hat = make_double2(A.nu * wave_sum(slope), 0.0);
@@ -1182,7 +1189,7 @@ __global__ __launch_bounds__(64 * wpb<N>()) void k_column(ColArgs A) {
     wave_sync();
   }
   // fields in order (u, v, w, omega_x, omega_y, omega_z)
-  cplx* X6[6] = {B[2], B[0], B[3], B[4], B[6], B[5]};
+  cplx* X6[6] = {B[2], B[0], B[3], B[4], B[1], B[5]};
   cplx ph[6][NS];
   dct_inverse<N, 6>(X6, A.cosk, lane, ph);
 #pragma unroll
