@@ -147,11 +147,11 @@ struct CP {
 template <int N>
 constexpr int wpb() { return N <= 64 ? 4 : 2; }
 
-// Waves per SIMD the general column kernel asks the compiler for: four at N = 96, which its
-// registers allow without spilling (116), the LDS of six work vectors too; the compiler's own
-// choice otherwise (at N = 128 four would spill 63 registers).
+// Waves per SIMD the general column kernel asks the compiler for: four at N = 96 and three at
+// N = 128, which their registers allow without spilling (116, 161) and the LDS of six work
+// vectors too (at N = 128 four would spill 63 registers); the compiler's own choice otherwise.
 template <int N>
-constexpr int col_waves() { return N == 96 ? 4 : 1; }
+constexpr int col_waves() { return N == 96 ? 4 : (N == 128 ? 3 : 1); }
 
 struct ColArgs {
   int nkx, nz, ncol;
