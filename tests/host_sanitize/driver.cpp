@@ -243,6 +243,18 @@ static void tilings() {
       std::vector<PlaneTiles> c;
       const int rc = plane_tile_candidates(dims(nx, 33, nz), &c);
       CHECK(rc == 0 && !c.empty(), "no plane tiling for %d x %d", nx, nz);
+      // the fused z inverse and x rows exist exactly for padded lengths 48 and 96 (N = 32, 64)
+      const bool fusable = (nx == 32 || nx == 64) && (nz == 32 || nz == 64);
+      int nfused = 0;
+      for (const PlaneTiles& t : c) nfused += t.fused ? 1 : 0;
+      CHECK((nfused > 0) == fusable, "fused candidates for %d x %d: %d", nx, nz, nfused);
+      std::vector<PlaneTiles> split, fused;
+      CHECK(plane_tile_candidates(dims(nx, 33, nz), &split, 1) == 0, "split tilings %d x %d", nx, nz);
+      for (const PlaneTiles& t : split) CHECK(!t.fused, "split form lists a fused tiling");
+      const int rf = plane_tile_candidates(dims(nx, 33, nz), &fused, 2);
+      CHECK((rf == 0 && !fused.empty()) == fusable, "fused-only tilings %d x %d", nx, nz);
+      for (const PlaneTiles& t : fused) CHECK(t.fused == 1, "fused form lists a split tiling");
+      CHECK(split.size() + fused.size() == c.size(), "forms do not partition the tilings");
     }
 }
 
