@@ -43,9 +43,9 @@ RE395 = dict(nx=128, ny=97, nz=128, lx=2 * np.pi, lz=np.pi, re_tau=395.0, dt_plu
 # other source.  The plane figures are the three-launch form the tuner keeps for one channel.
 TRAFFIC = {
     "column_solve_reconstruct": (3.8932e+07, "column_pass.hip", "d9c39fcd5336c91daa763a605300bc19ab60214ffbb05590762bcbdc319b2779"),
-    "x_rows_fft_product": (2.8902e+07, "plane_pass.hip", "e5eec9c6c96efbfb969f1c549d2ca4b10086aaebbd755fc526cc64dc91fe5708"),
-    "z_inverse_fft": (3.2047e+07, "plane_pass.hip", "e5eec9c6c96efbfb969f1c549d2ca4b10086aaebbd755fc526cc64dc91fe5708"),
-    "z_forward_fft": (1.6087e+07, "plane_pass.hip", "e5eec9c6c96efbfb969f1c549d2ca4b10086aaebbd755fc526cc64dc91fe5708"),
+    "x_rows_fft_product": (2.8902e+07, "plane_pass.hip", "8a08bd7f959abeedfc6fc9893ee51a5a8ae72b7da0de4e745d7d1def2938cc33"),
+    "z_inverse_fft": (3.2047e+07, "plane_pass.hip", "8a08bd7f959abeedfc6fc9893ee51a5a8ae72b7da0de4e745d7d1def2938cc33"),
+    "z_forward_fft": (1.6087e+07, "plane_pass.hip", "8a08bd7f959abeedfc6fc9893ee51a5a8ae72b7da0de4e745d7d1def2938cc33"),
     "column_pass": (2.4452e+07, "column_pass.hip", "d9c39fcd5336c91daa763a605300bc19ab60214ffbb05590762bcbdc319b2779"),
     "column_reconstruct": (1.7564e+07, "column_pass.hip", "d9c39fcd5336c91daa763a605300bc19ab60214ffbb05590762bcbdc319b2779"),
 }

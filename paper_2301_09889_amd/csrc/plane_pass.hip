@@ -12,6 +12,8 @@
 //                packed as real and imaginary part), the products, three forward FFTs,
 //                all on one block's LDS with one task per thread in every phase;
 //   k_zfwd<M_z>  forward FFT along z, truncation to |q| < N_z/2, 1/(M_x M_z), Hermitian fix.
+// For padded lengths 48 and 96 the first two may run as one launch (k_zxrow, the padded rows
+// kept in LDS), and for 24 x 24 all three (k_plane_small); the tuner picks per batch.
 //
 // Layouts (complex):  F6[f][j][p][q], Z6[f][j][zz][p], W3[g][j][zz][p], H3[g][j][p][q].
 // A launch covers nch channels of one shape: blockIdx.z = channel * N_y + node.
